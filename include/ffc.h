@@ -1,0 +1,205 @@
+/*
+ * ffc.h - C ABI of the far-field compression library (HIP, gfx950).
+ *
+ * The library computes kernel sums u_i = sum_j K(y_i, x_j) q_j (March & Biros,
+ * "Far-Field Compression for Fast Kernel Summation Methods in High
+ * Dimensions", Section 1, eq. e:sum) with the paper's sampled-row
+ * interpolative decomposition as the far-field representation (Section 2.2):
+ * for every node of a tree over the points, sample target rows, form the
+ * sampled kernel block K' (Section 2.2), take its interpolative decomposition
+ * by column-pivoted QR (Section 2.1.3; Appendix 6.1) and apply the skeletons
+ * in the sum (eq. e:id).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers (HIP global memory), *_host are
+ *    host pointers. Coordinates are float64, row-major (point-major), N x d.
+ *  - stream is a hipStream_t passed as void*; NULL means the null stream.
+ *    Calls that launch work are asynchronous and stream ordered; the caller
+ *    keeps device buffers alive until the stream has reached the call.
+ *  - Every call returns ffc_status; nothing throws across the ABI. On error
+ *    ffc_last_error() returns a thread-local message. Arguments are validated
+ *    before anything is launched.
+ *  - Handles (ffc_tree, ffc_skel) are opaque, owned by the library and released
+ *    with ffc_free_tree / ffc_free_skel.
+ *  - Kernel evaluations that are not finite (for instance the Laplace kernel
+ *    overflowing at tiny distances) raise a device flag that ffc_check_device
+ *    reports as FFC_ERR_NONFINITE.
+ */
+#ifndef FFC_H
+#define FFC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FFC_OK = 0,
+  FFC_ERR_INVALID_ARG = 1,
+  FFC_ERR_HIP = 2,
+  FFC_ERR_OOM = 3,
+  FFC_ERR_NONFINITE = 4,
+  FFC_ERR_STATE = 5
+} ffc_status;
+
+/* Kernel functions (Section 4.2-4.4):
+ *  FFC_GAUSSIAN    exp(-||x - y||^2 / (2 h^2))                 (eq. eqn_gaussian_kernel)
+ *  FFC_LAPLACE     ||x - y||^(2 - d), d >= 3; pairs at zero distance give 0
+ *  FFC_POLYNOMIAL  (x^T y / h + c)^p, integer p >= 1 (the paper sets c = 1)  */
+typedef enum { FFC_GAUSSIAN = 0, FFC_LAPLACE = 1, FFC_POLYNOMIAL = 2 } ffc_kernel_kind;
+
+typedef struct {
+  int32_t kind;   /* ffc_kernel_kind */
+  int32_t p;      /* polynomial degree */
+  double h;       /* bandwidth (Gaussian, polynomial), > 0 */
+  double c;       /* polynomial constant */
+} ffc_kernel;
+
+/* Arithmetic of the kernel evaluations (distances / inner products and the
+ * kernel function). The QR, the interpolation solve and the charges are always
+ * float64. FFC_MIXED_BF16X3 splits coordinates into bfloat16 hi + lo parts and
+ * forms the Gram products hi*hi + hi*lo + lo*hi on matrix cores with float32
+ * accumulation (Gaussian and polynomial kernels; the Laplace kernel is always
+ * evaluated from explicit float32 differences in that mode). */
+typedef enum { FFC_FP64 = 0, FFC_FP32 = 1, FFC_MIXED_BF16X3 = 2 } ffc_precision;
+
+typedef enum { FFC_SAMPLE_UNIFORM = 0, FFC_SAMPLE_LEARNED = 1 } ffc_sampler;
+
+typedef struct ffc_tree ffc_tree;
+typedef struct ffc_skel ffc_skel;
+typedef struct ffc_proposal ffc_proposal;
+
+/* Skeletonization options.
+ *  tol          relative rank tolerance: the QR stops at the first pivot whose
+ *               column norm is below tol times the first pivot's (> 0 or 0 for
+ *               full rank)
+ *  max_rank     rank cap, >= 1
+ *  num_samples  sampled target rows per node; 0 means 2 * max_rank. Capped at
+ *               the number of points outside the node.
+ *  precision    ffc_precision of the sampled kernel block
+ *  sampler      ffc_sampler; FFC_SAMPLE_LEARNED needs `proposal`
+ *  seed         seed of the counter-based row sampler
+ *  fallback_tol learned sampler only: a node whose held-out error estimate
+ *               exceeds it is redone with uniform rows (<= 0 disables) */
+typedef struct {
+  double tol;
+  int32_t max_rank;
+  int32_t num_samples;
+  int32_t precision;
+  int32_t sampler;
+  uint64_t seed;
+  const ffc_proposal* proposal;
+  double fallback_tol;
+} ffc_skel_opts;
+
+/* Build a binary ball tree over X (Section 2: hierarchical groupings of the
+ * points). Depth D is the least D with ceil(N / 2^D) <= leaf_size; all leaves
+ * sit at level D. Each node is split at the median of the projections onto
+ * (p2 - p1), p1 the point farthest from the node centroid, p2 the point
+ * farthest from p1; points are ordered by (projection, caller index) and the
+ * left child takes the first ceil(n/2). Node ids are breadth first (root 0,
+ * children 2a+1, 2a+2). The points are copied, so X_dev may be freed after
+ * the stream passes the call. Errors: N < 1, d < 1, leaf_size < 1, NULL
+ * pointers -> FFC_ERR_INVALID_ARG. */
+ffc_status ffc_build_tree(const double* X_dev, int64_t N, int32_t d, int32_t leaf_size,
+                          void* stream, ffc_tree** out);
+
+/* Two-part "tree": root plus leaves [0, n_left) and [n_left, N) in caller order
+ * (one source node against the remaining targets, Section 4.1 set-up).
+ * Errors: n_left < 1 or n_left >= N -> FFC_ERR_INVALID_ARG. */
+ffc_status ffc_build_partition(const double* X_dev, int64_t N, int32_t d, int64_t n_left,
+                               void* stream, ffc_tree** out);
+
+/* Tree shape: depth, number of nodes (2^(depth+1) - 1), N and d. */
+ffc_status ffc_tree_info(const ffc_tree* t, int32_t* depth, int32_t* num_nodes,
+                         int64_t* N, int32_t* d);
+
+/* Copies to host: perm_host[pos] = caller index of the point at tree position
+ * pos (N entries); begin/end of every node (num_nodes entries each); centroid
+ * (num_nodes x d) and radius (num_nodes). Any output may be NULL. Synchronizes
+ * with the stream of the last call on the tree. */
+ffc_status ffc_tree_arrays(const ffc_tree* t, int32_t* perm_host, int64_t* begin_host,
+                           int64_t* end_host, double* centroid_host, double* radius_host);
+
+/* Skeletonize every non-root node (Section 2.2), deepest level first. A leaf's
+ * columns are its points; an internal node's columns are the skeleton of its
+ * left child followed by that of its right child. Target rows are sampled from
+ * the points outside the node. Per node: sampled block K' (s x n), column-
+ * pivoted QR to tolerance (Appendix 6.1), R11 T = R12, P = [I T] Pi^T, skeleton
+ * = first r pivots (Section 2.1.3). All nodes of a level run in one launch per
+ * stage. *out must be NULL (a new handle is returned) or a handle from an
+ * earlier call on the same tree with the same sample count and rank cap,
+ * whose storage is then reused and overwritten (FFC_ERR_STATE otherwise).
+ * Errors: invalid kernel (h <= 0, p < 1, Laplace with d = 2), tol < 0,
+ * max_rank < 1, num_samples < 0, learned sampler without proposal. */
+ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const ffc_skel_opts* o,
+                                 void* stream, ffc_skel** out);
+
+/* u = K q with the compressed far field (eq. e:id): equivalent charges
+ * q~ = P q upward through the tree, then for every target the skeletons of
+ * the siblings of its leaf's ancestors (far field) plus its own leaf directly
+ * (near field). q_dev and u_dev are N-vectors in caller order; u_far_dev
+ * (nullable) receives the far-field part only. precision: ffc_precision of the
+ * kernel evaluations. The skeleton must come from the same tree. */
+ffc_status ffc_evaluate_sum(const ffc_tree* t, const ffc_skel* sk, const ffc_kernel* k,
+                            const double* q_dev, double* u_dev, double* u_far_dev,
+                            int32_t precision, void* stream);
+
+/* Direct summation u_i = sum_j K(y_i, x_j) q_j (Section 1, eq. e:sum) for m
+ * targets Y (m x d) and n sources X (n x d). Laplace pairs at zero distance
+ * contribute 0. Errors: m, n < 0, d < 1, NULL pointers with nonzero sizes. */
+ffc_status ffc_direct_sum(const double* Y_dev, int64_t m, const double* X_dev, int64_t n,
+                          int32_t d, const ffc_kernel* k, const double* q_dev, double* u_dev,
+                          int32_t precision, void* stream);
+
+/* Sampled kernel block of a tree: out[j * s + i] = K(x_rows[i], x_cols[j]) for
+ * tree positions rows_dev (s) and cols_dev (n), column-major s x n (the block
+ * K' of Section 2.2, computed by the same kernels the skeletonization uses). */
+ffc_status ffc_sampled_block(const ffc_tree* t, const ffc_kernel* k, int32_t precision,
+                             const int32_t* rows_dev, int32_t s, const int32_t* cols_dev,
+                             int32_t n, double* out_dev, void* stream);
+
+/* Interpolative decompositions of `batch` column-major s x n blocks A_dev
+ * (block b at A_dev + b * s * n; overwritten by the factorization). Outputs:
+ * rank_dev[b]; piv_dev[b * n + k] = column of the k-th pivot; P_dev[b *
+ * max_rank * n + i * n + j] = P (rank x n, row-major, original column order);
+ * rows i >= rank are left untouched. Same QR and solve as the skeletonization
+ * (Appendix 6.1; Theorem thm_compute_id). Errors: s, n < 1, max_rank < 1. */
+ffc_status ffc_interp_decomp(double* A_dev, int32_t batch, int32_t s, int32_t n, double tol,
+                             int32_t max_rank, int32_t* rank_dev, int32_t* piv_dev,
+                             double* P_dev, void* stream);
+
+/* Per-node results copied to host (synchronizes). node in [1, num_nodes).
+ * rank, n_cols, n_rows are required; cols/rows/skel (tree positions) and P
+ * (rank x n_cols, row-major) may be NULL; buffers must hold n_cols, n_rows,
+ * rank and rank * n_cols entries. */
+ffc_status ffc_skel_node(const ffc_skel* sk, int32_t node, int32_t* rank, int32_t* n_cols,
+                         int32_t* n_rows, int32_t* cols_host, int32_t* rows_host,
+                         int32_t* skel_host, double* P_host);
+
+typedef struct {
+  int32_t num_nodes;        /* skeletonized nodes (all non-root nodes) */
+  int32_t rank_min, rank_max;
+  double rank_mean;
+  int32_t rank_cap_hits;    /* nodes whose rank equals max_rank */
+  int32_t fallbacks;        /* learned sampler: nodes redone with uniform rows */
+  double kernel_evals;      /* sum over nodes of s * n_cols */
+} ffc_stats;
+
+/* Rank statistics of a skeleton set (synchronizes). */
+ffc_status ffc_skel_stats(const ffc_skel* sk, ffc_stats* out);
+
+/* Synchronizes `stream` and reports (then clears) the device error flag:
+ * FFC_ERR_NONFINITE if a kernel value was not finite since the last check. */
+ffc_status ffc_check_device(void* stream);
+
+void ffc_free_tree(ffc_tree* t);
+void ffc_free_skel(ffc_skel* sk);
+const char* ffc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFC_H */

@@ -12,7 +12,9 @@ Readings where the paper is silent:
   are recomputed from scratch at every step (no downdating).
 * The rank is chosen adaptively: with rho_k the norm of the k-th pivot column
   (= |R_kk|), stop at the first k with rho_k < tol * rho_0, else at
-  min(s, n, max_rank). A zero matrix gives r = 0. This is the QR analogue of
+  min(s, n, max_rank); a pivot column of norm exactly zero also stops it (so
+  tol = 0 gives the numerical full rank and R11 stays nonsingular). A zero
+  matrix gives r = 0. This is the QR analogue of
   the paper's epsilon-rank rule sigma_{r+1} / sigma_1 < eps (Section 4.1.3).
 * Householder reflectors use alpha = -sign(x_1) ||x|| with sign(0) = +1; the
   sign choice does not change P.
@@ -35,6 +37,7 @@ class ID:
     T: np.ndarray         # r x (n - r), R11^{-1} R12
     P: np.ndarray         # r x n in original column order
     rho: np.ndarray       # pivot norms rho_0, ..., rho_{r-1} (|R_kk|)
+    gap: np.ndarray       # relative gap (best - runner-up) / best of squared norms at each pivot
 
     @property
     def skel(self) -> np.ndarray:
@@ -44,13 +47,16 @@ class ID:
 def cpqr(A: np.ndarray, tol: float, max_rank: int):
     """Householder QR with column pivoting, stopped by the rank rule.
 
-    Returns (r, piv, R_full, rho) where R_full is the overwritten s x n array
-    whose first r rows hold R (pivoted order) and rows r.. hold R22.
+    Returns (r, piv, R_full, rho, gap) where R_full is the overwritten s x n array
+    whose first r rows hold R (pivoted order) and rows r.. hold R22, and gap
+    records, for every pivot examined (including the one that stopped the
+    loop), the relative gap between the two largest trailing squared norms.
     """
     A = np.array(A, dtype=np.float64, copy=True)
     s, n = A.shape
     piv = np.arange(n)
     rho = []
+    gap = []
     kmax = min(s, n, max_rank)
     rho0 = 0.0
     r = 0
@@ -60,9 +66,11 @@ def cpqr(A: np.ndarray, tol: float, max_rank: int):
         cand = np.flatnonzero(norms2 == best) + k
         p = int(cand[np.argmin(piv[cand])])
         rho_k = math.sqrt(norms2[p - k])
+        others = np.delete(norms2, p - k)
+        gap.append((best - others.max()) / best if others.size and best > 0 else 1.0)
         if k == 0:
             rho0 = rho_k
-        if rho0 == 0.0 or rho_k < tol * rho0:
+        if rho_k == 0.0 or rho_k < tol * rho0:
             break
         if p != k:
             A[:, [k, p]] = A[:, [p, k]]
@@ -79,7 +87,7 @@ def cpqr(A: np.ndarray, tol: float, max_rank: int):
         A[k + 1:, k] = 0.0
         rho.append(rho_k)
         r = k + 1
-    return r, piv, A, np.array(rho)
+    return r, piv, A, np.array(rho), np.array(gap)
 
 
 def back_substitute(R11: np.ndarray, B: np.ndarray) -> np.ndarray:
@@ -97,16 +105,16 @@ def interpolative_decomposition(A: np.ndarray, tol: float, max_rank: int) -> ID:
     """Rank-r ID of A: A ~ A[:, skel] @ P (Appendix 6.1)."""
     A = np.asarray(A, dtype=np.float64)
     n = A.shape[1]
-    r, piv, RA, rho = cpqr(A, tol, max_rank)
+    r, piv, RA, rho, gap = cpqr(A, tol, max_rank)
     R = RA[:r, :].copy()
     T = back_substitute(R[:, :r], R[:, r:]) if r > 0 else np.zeros((0, n))
     P = np.zeros((r, n))
     P[np.arange(r), piv[:r]] = 1.0
     P[:, piv[r:]] = T
-    return ID(rank=r, piv=piv, R=R, T=T, P=P, rho=rho)
+    return ID(rank=r, piv=piv, R=R, T=T, P=P, rho=rho, gap=gap)
 
 
 def r22_frobenius(A: np.ndarray, tol: float, max_rank: int) -> float:
     """||R22||_F of the stopped factorization (equals ||A - A[:, J] P||_F)."""
-    r, _, RA, _ = cpqr(A, tol, max_rank)
+    r, _, RA, _, _ = cpqr(A, tol, max_rank)
     return float(np.linalg.norm(RA[r:, r:]))

@@ -35,6 +35,7 @@ class NodeSkeleton:
     skel: np.ndarray      # tree positions of the skeleton points (pivot order)
     P: np.ndarray         # rank x len(cols)
     rho: np.ndarray
+    gap: np.ndarray
 
 
 @dataclass
@@ -56,10 +57,11 @@ def skeletonize_node(Xt: np.ndarray, tree: Tree, a: int, cols: np.ndarray, k: Ke
     Kp = kernel_matrix(Xt[rows], Xt[cols], k)
     if len(cols) == 0 or len(rows) == 0:
         return NodeSkeleton(cols=cols, rows=rows, rank=0, piv=np.arange(len(cols)),
-                            skel=cols[:0], P=np.zeros((0, len(cols))), rho=np.zeros(0))
+                            skel=cols[:0], P=np.zeros((0, len(cols))), rho=np.zeros(0),
+                            gap=np.ones(0))
     idd = interpolative_decomposition(Kp, tol, max_rank)
     return NodeSkeleton(cols=cols, rows=rows, rank=idd.rank, piv=idd.piv,
-                        skel=cols[idd.skel], P=idd.P, rho=idd.rho)
+                        skel=cols[idd.skel], P=idd.P, rho=idd.rho, gap=idd.gap)
 
 
 def skeletonize(X: np.ndarray, tree: Tree, k: Kernel, tol: float, max_rank: int,

@@ -1,0 +1,353 @@
+// Kernel-function tiles: sampled blocks K', far/near-field evaluation and the
+// direct sum.
+//
+// Every stage that evaluates the kernel shares one tile engine: a 256-thread
+// workgroup computes a 64 x 64 tile of squared distances (Gaussian, Laplace)
+// or inner products (polynomial) between a row set and a column set of
+// points. Coordinates are staged through LDS in chunks of 32 dimensions,
+// transposed so that each thread reads 4 row values and 4 column values per
+// dimension and owns a 4 x 4 block of the tile. Squared distances are formed
+// from explicit coordinate differences, so they carry no cancellation.
+//
+// Epilogues:
+//   * sampled block K'_{ij} = K(y_rows[i], x_cols[j]) stored column major
+//     (Section 2.2, the s x n matrix whose ID is taken);
+//   * kernel sums u_i = sum_j K(y_i, x_j) q_j (Section 1, eq. e:sum; eq. e:id
+//     with the skeleton points and equivalent charges), reduced across the
+//     16 threads sharing a row in a fixed order, so results are deterministic.
+#include "ffc_internal.h"
+
+namespace ffc {
+namespace {
+
+constexpr int BM = 64, BN = 64, KC = 32, NT = 256;
+constexpr int LDSP = BM + 1;   // padded LDS row (bank spread)
+
+template <typename T>
+struct TileSmem {
+  T ys[KC][LDSP];
+  T xs[KC][LDSP];
+};
+
+// Row / column index maps: an explicit index list or a contiguous range.
+struct IdxMap {
+  const int32_t* idx;
+  int64_t base;
+  __device__ inline int64_t operator()(int i) const { return idx ? (int64_t)idx[i] : base + i; }
+};
+
+// acc[i][j] for rows r0 + tr + 16 i and columns c0 + tc + 16 j.
+template <typename T, bool DOT>
+__device__ inline void tile_accumulate(const double* __restrict__ Y, IdxMap rows, int nrows, const double* __restrict__ X,
+                                       IdxMap cols, int ncols, int d, TileSmem<T>& sm, T (&acc)[4][4]) {
+  const int tid = threadIdx.x;
+  const int tr = tid & 15, tc = tid >> 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+  for (int k0 = 0; k0 < d; k0 += KC) {
+#pragma unroll
+    for (int e = tid; e < BM * KC; e += NT) {
+      const int r = e / KC, kk = e % KC;
+      const int k = k0 + kk;
+      T yv = T(0), xv = T(0);
+      if (k < d) {
+        if (r < nrows) yv = (T)Y[rows(r) * d + k];
+        if (r < ncols) xv = (T)X[cols(r) * d + k];
+      }
+      sm.ys[kk][r] = yv;
+      sm.xs[kk][r] = xv;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < KC; ++kk) {
+      T a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sm.ys[kk][tr + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = sm.xs[kk][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (DOT) {
+            acc[i][j] = fma(a[i], b[j], acc[i][j]);
+          } else {
+            const T df = a[i] - b[j];
+            acc[i][j] = fma(df, df, acc[i][j]);
+          }
+        }
+    }
+    __syncthreads();
+  }
+}
+
+// Kernel function of an accumulated distance^2 (or inner product when DOT).
+template <bool DOT>
+__device__ inline double kfun(double acc, const KParams& kp) {
+  if (DOT) {
+    const double base = fma(acc, kp.inv_h, kp.c);
+    double r = 1.0;
+    for (int i = 0; i < kp.p; ++i) r *= base;
+    return r;
+  }
+  if (kp.kind == FFC_GAUSSIAN) return exp(acc * kp.neg_inv_2h2);
+  return acc > 0.0 ? pow(acc, kp.lap_expo) : 0.0;   // Laplace
+}
+
+template <bool DOT>
+__device__ inline double kfun(float acc, const KParams& kp) {
+  if (DOT) {
+    const float base = fmaf(acc, (float)kp.inv_h, (float)kp.c);
+    float r = 1.0f;
+    for (int i = 0; i < kp.p; ++i) r *= base;
+    return (double)r;
+  }
+  if (kp.kind == FFC_GAUSSIAN) return (double)expf(acc * (float)kp.neg_inv_2h2);
+  return acc > 0.0f ? pow((double)acc, kp.lap_expo) : 0.0;   // Laplace: power in FP64 (range)
+}
+
+__device__ inline void flag_nonfinite(unsigned int* flag) { atomicOr(flag, 1u); }
+
+// ---------------------------------------------------------------------------
+// Sampled blocks for all nodes of a level.
+// ---------------------------------------------------------------------------
+template <typename T, bool DOT>
+__global__ void __launch_bounds__(NT) k_level_kblock(const double* __restrict__ Xt, int d, KParams kp, int first,
+                                                     int tiles_m, int tiles_n, const int32_t* __restrict__ rows,
+                                                     const int32_t* __restrict__ nrows, int s_cap,
+                                                     const int32_t* __restrict__ cols,
+                                                     const int32_t* __restrict__ ncols, int n_cap,
+                                                     double* __restrict__ A, unsigned int* flag) {
+  __shared__ TileSmem<T> sm;
+  const int tiles = tiles_m * tiles_n;
+  const int ln = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  const int node = first + ln;
+  const int s = nrows[node], n = ncols[node];
+  const int r0 = (tile % tiles_m) * BM, c0 = (tile / tiles_m) * BN;
+  if (r0 >= s || c0 >= n) return;
+  const IdxMap rmap{rows + (int64_t)node * s_cap + r0, 0};
+  const IdxMap cmap{cols + (int64_t)node * n_cap + c0, 0};
+  T acc[4][4];
+  tile_accumulate<T, DOT>(Xt, rmap, s - r0, Xt, cmap, n - c0, d, sm, acc);
+  double* out = A + (int64_t)ln * s_cap * n_cap;
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = c0 + tc + 16 * j;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + tr + 16 * i;
+      if (r < s && c < n) {
+        const double v = kfun<DOT>(acc[i][j], kp);
+        bad |= !isfinite(v);
+        out[(int64_t)c * s_cap + r] = v;
+      }
+    }
+  }
+  if (bad) flag_nonfinite(flag);
+}
+
+// Standalone sampled block: rows/cols are explicit lists of tree positions.
+template <typename T, bool DOT>
+__global__ void __launch_bounds__(NT) k_sampled_block(const double* __restrict__ Xt, int d, KParams kp,
+                                                      const int32_t* __restrict__ rows, int s,
+                                                      const int32_t* __restrict__ cols, int n, int tiles_m,
+                                                      double* __restrict__ out, unsigned int* flag) {
+  __shared__ TileSmem<T> sm;
+  const int r0 = (blockIdx.x % tiles_m) * BM, c0 = (blockIdx.x / tiles_m) * BN;
+  T acc[4][4];
+  tile_accumulate<T, DOT>(Xt, IdxMap{rows + r0, 0}, s - r0, Xt, IdxMap{cols + c0, 0}, n - c0, d, sm, acc);
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = r0 + tr + 16 * i, c = c0 + tc + 16 * j;
+      if (r < s && c < n) {
+        const double v = kfun<DOT>(acc[i][j], kp);
+        bad |= !isfinite(v);
+        out[(int64_t)c * s + r] = v;
+      }
+    }
+  if (bad) flag_nonfinite(flag);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel sums: accumulate sum_j K(y_i, x_j) q_j over one source set into
+// per-thread partial sums part[i] (rows tr + 16 i of the tile).
+// ---------------------------------------------------------------------------
+template <typename T, bool DOT>
+__device__ inline void sum_over_sources(const double* __restrict__ Y, IdxMap rows, int nrows,
+                                        const double* __restrict__ X, IdxMap cols, int ncols,
+                                        const double* __restrict__ q, int d, const KParams& kp, TileSmem<T>& sm,
+                                        double (&part)[4], bool& bad) {
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  for (int c0 = 0; c0 < ncols; c0 += BN) {
+    IdxMap cm{cols.idx ? cols.idx + c0 : nullptr, cols.base + c0};
+    T acc[4][4];
+    tile_accumulate<T, DOT>(Y, rows, nrows, X, cm, ncols - c0, d, sm, acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + tc + 16 * j;
+      if (c < ncols) {
+        const double qj = q[c];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double v = kfun<DOT>(acc[i][j], kp);
+          bad |= !isfinite(v);
+          part[i] = fma(v, qj, part[i]);
+        }
+      }
+    }
+  }
+}
+
+// Fixed-order reduction of part[] across the 16 column threads of each row.
+__device__ inline void reduce_rows(double (&part)[4], double* red /* 16 x 64 */, double* rowsum /* 64 */) {
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) red[tc * BM + tr + 16 * i] = part[i];
+  __syncthreads();
+  if (threadIdx.x < BM) {
+    double s = 0.0;
+    for (int c = 0; c < 16; ++c) s += red[c * BM + threadIdx.x];
+    rowsum[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// Far field (sibling cover) + near field (own leaf) for a tile of targets.
+template <typename T, bool DOT>
+__global__ void __launch_bounds__(NT) k_evaluate(const double* __restrict__ Xt, int d, KParams kp, int depth,
+                                                 const int32_t* __restrict__ tile_leaf,
+                                                 const int32_t* __restrict__ tile_start,
+                                                 const int32_t* __restrict__ nb, const int32_t* __restrict__ ne,
+                                                 const double* __restrict__ q_tree,
+                                                 const int32_t* __restrict__ rank, const int32_t* __restrict__ skel,
+                                                 int r_cap, const double* __restrict__ qt,
+                                                 const int32_t* __restrict__ perm, double* __restrict__ u,
+                                                 double* __restrict__ u_far, unsigned int* flag) {
+  __shared__ TileSmem<T> sm;
+  __shared__ double red[16 * BM];
+  __shared__ double far_sum[BM], near_sum[BM];
+  const int leaf = tile_leaf[blockIdx.x];
+  const int start = tile_start[blockIdx.x];
+  const int nrows = min(BM, ne[leaf] - start);
+  const IdxMap rmap{nullptr, start};
+  bool bad = false;
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+  // Far field: one cover node per level (the sibling of each ancestor).
+  int a = leaf;
+  for (int lev = depth; lev >= 1; --lev) {
+    const int sib = (a & 1) ? a + 1 : a - 1;
+    const int r = rank[sib];
+    if (r > 0)
+      sum_over_sources<T, DOT>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)sib * r_cap, 0}, r,
+                               qt + (int64_t)sib * r_cap, d, kp, sm, part, bad);
+    a = (a - 1) >> 1;
+  }
+  reduce_rows(part, red, far_sum);
+  double npart[4] = {0.0, 0.0, 0.0, 0.0};
+  const int lb = nb[leaf];
+  sum_over_sources<T, DOT>(Xt, rmap, nrows, Xt, IdxMap{nullptr, lb}, ne[leaf] - lb, q_tree + lb, d, kp, sm, npart,
+                           bad);
+  reduce_rows(npart, red, near_sum);
+  if (threadIdx.x < nrows) {
+    const int pos = start + threadIdx.x;
+    const int ci = perm[pos];
+    const double f = far_sum[threadIdx.x];
+    u[ci] = f + near_sum[threadIdx.x];
+    if (u_far) u_far[ci] = f;
+  }
+  if (bad) flag_nonfinite(flag);
+}
+
+// Direct sum over all sources for a tile of 64 targets.
+template <typename T, bool DOT>
+__global__ void __launch_bounds__(NT) k_direct(const double* __restrict__ Y, int64_t m, const double* __restrict__ X,
+                                               int64_t n, int d, KParams kp, const double* __restrict__ q,
+                                               double* __restrict__ u, unsigned int* flag) {
+  __shared__ TileSmem<T> sm;
+  __shared__ double red[16 * BM];
+  __shared__ double rowsum[BM];
+  const int64_t r0 = (int64_t)blockIdx.x * BM;
+  const int nrows = (int)min<int64_t>(BM, m - r0);
+  bool bad = false;
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+  sum_over_sources<T, DOT>(Y, IdxMap{nullptr, r0}, nrows, X, IdxMap{nullptr, 0}, (int)n, q, d, kp, sm, part, bad);
+  reduce_rows(part, red, rowsum);
+  if (threadIdx.x < nrows) u[r0 + threadIdx.x] = rowsum[threadIdx.x];
+  if (bad) flag_nonfinite(flag);
+}
+
+template <typename F>
+ffc_status dispatch(int precision, bool dot, F&& f) {
+  if (precision == FFC_FP64) return dot ? f(double(), std::true_type()) : f(double(), std::false_type());
+  return dot ? f(float(), std::true_type()) : f(float(), std::false_type());
+}
+
+}  // namespace
+
+ffc_status launch_level_kblock(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, int first,
+                               int count, double* A, hipStream_t st) {
+  const int tiles_m = (sk->s_cap + BM - 1) / BM, tiles_n = (sk->n_cap + BN - 1) / BN;
+  const int64_t blocks = (int64_t)count * tiles_m * tiles_n;
+  const bool dot = kp.kind == FFC_POLYNOMIAL;
+  return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
+    using T = decltype(tv);
+    constexpr bool D = decltype(dv)::value;
+    hipLaunchKernelGGL((k_level_kblock<T, D>), dim3((unsigned)blocks), dim3(NT), 0, st, t->Xt.ptr, t->d, kp, first,
+                       tiles_m, tiles_n, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, sk->cols.ptr, sk->ncols.ptr,
+                       sk->n_cap, A, device_flag());
+    FFC_LAUNCH_CHECK("k_level_kblock");
+    return FFC_OK;
+  });
+}
+
+ffc_status launch_sampled_block(const ffc_tree* t, const KParams& kp, int precision, const int32_t* rows, int s,
+                                const int32_t* cols, int n, double* out, hipStream_t st) {
+  const int tiles_m = (s + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
+  const bool dot = kp.kind == FFC_POLYNOMIAL;
+  return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
+    using T = decltype(tv);
+    constexpr bool D = decltype(dv)::value;
+    hipLaunchKernelGGL((k_sampled_block<T, D>), dim3((unsigned)(tiles_m * tiles_n)), dim3(NT), 0, st, t->Xt.ptr,
+                       t->d, kp, rows, s, cols, n, tiles_m, out, device_flag());
+    FFC_LAUNCH_CHECK("k_sampled_block");
+    return FFC_OK;
+  });
+}
+
+ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, double* u,
+                           double* u_far, hipStream_t st) {
+  const bool dot = kp.kind == FFC_POLYNOMIAL;
+  return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
+    using T = decltype(tv);
+    constexpr bool D = decltype(dv)::value;
+    hipLaunchKernelGGL((k_evaluate<T, D>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
+                       t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
+                       sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->perm.ptr, u, u_far, device_flag());
+    FFC_LAUNCH_CHECK("k_evaluate");
+    return FFC_OK;
+  });
+}
+
+ffc_status launch_direct_sum(const double* Y, int64_t m, const double* X, int64_t n, int d, const KParams& kp,
+                             int precision, const double* q, double* u, hipStream_t st) {
+  if (m == 0) return FFC_OK;
+  const bool dot = kp.kind == FFC_POLYNOMIAL;
+  return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
+    using T = decltype(tv);
+    constexpr bool D = decltype(dv)::value;
+    hipLaunchKernelGGL((k_direct<T, D>), dim3((unsigned)((m + BM - 1) / BM)), dim3(NT), 0, st, Y, m, X, n, d, kp, q,
+                       u, device_flag());
+    FFC_LAUNCH_CHECK("k_direct");
+    return FFC_OK;
+  });
+}
+
+}  // namespace ffc

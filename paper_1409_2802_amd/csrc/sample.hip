@@ -1,0 +1,115 @@
+// Uniform target-row sampling and per-level column lists.
+//
+// Rows are drawn uniformly without replacement from the points outside the
+// node (Section 4.1.3, uniform sampling; Theorem thm_column_sampling_approx2).
+// The draw is Floyd's algorithm (Bentley & Floyd, CACM 1987) fed by a
+// counter-based SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the value for
+// counter j is the first SplitMix64 output from state seed ^ (node << 32) ^ j,
+// and a uniform integer in [0, j] is the high 64 bits of u64 * (j + 1).
+// Candidate t maps to tree position t (t < begin) or t + node size.
+//
+// One wavefront per node: each Floyd step is computed redundantly by all 64
+// lanes (no broadcast needed), set membership is a ballot over the set held
+// in LDS, and the chosen set is sorted with an LDS bitonic network.
+#include <climits>
+
+#include "ffc_internal.h"
+
+namespace ffc {
+namespace {
+
+__device__ inline uint64_t splitmix_first(uint64_t state) {
+  uint64_t z = state + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_sample_rows(const int32_t* __restrict__ nb, const int32_t* __restrict__ ne, int64_t N, int first,
+                              int s, int s_cap, int sort_n, uint64_t seed, int32_t* __restrict__ rows,
+                              int32_t* __restrict__ nrows) {
+  extern __shared__ int set[];   // sort_n ints (power of two >= s)
+  const int node = first + blockIdx.x;
+  const int lane = threadIdx.x;
+  const int b = nb[node], e = ne[node];
+  const int64_t M = N - (e - b);
+  int32_t* out = rows + (int64_t)node * s_cap;
+  if (s >= M) {
+    for (int64_t i = lane; i < M; i += 64) out[i] = (int32_t)(i < b ? i : i + (e - b));
+    if (lane == 0) nrows[node] = (int32_t)M;
+    return;
+  }
+  const uint64_t stream = (uint64_t)(uint32_t)node << 32;
+  int cnt = 0;
+  for (int64_t j = M - s; j < M; ++j) {
+    const uint64_t u = splitmix_first(seed ^ stream ^ (uint64_t)j);
+    const int t = (int)__umul64hi(u, (uint64_t)(j + 1));
+    bool hit = false;
+    for (int i = lane; i < cnt; i += 64) hit |= (set[i] == t);
+    const bool any = __ballot(hit) != 0ull;
+    if (lane == 0) set[cnt] = any ? (int)j : t;
+    ++cnt;
+    __syncthreads();
+  }
+  for (int i = cnt + lane; i < sort_n; i += 64) set[i] = INT_MAX;
+  __syncthreads();
+  for (int k = 2; k <= sort_n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = lane; t < sort_n / 2; t += 64) {
+        const int i = (t / j) * 2 * j + (t % j);
+        const bool asc = (i & k) == 0;
+        const int x = set[i], y = set[i + j];
+        if ((y < x) == asc) { set[i] = y; set[i + j] = x; }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = lane; i < s; i += 64) {
+    const int t = set[i];
+    out[i] = t < b ? t : t + (e - b);
+  }
+  if (lane == 0) nrows[node] = s;
+}
+
+__global__ void k_level_columns(const int32_t* __restrict__ nb, const int32_t* __restrict__ ne, int first,
+                                int leaves, int n_cap, int r_cap, const int32_t* __restrict__ rank,
+                                const int32_t* __restrict__ skel, int32_t* __restrict__ cols,
+                                int32_t* __restrict__ ncols) {
+  const int node = first + blockIdx.x;
+  int32_t* out = cols + (int64_t)node * n_cap;
+  if (leaves) {
+    const int b = nb[node], n = ne[node] - b;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = b + i;
+    if (threadIdx.x == 0) ncols[node] = n;
+    return;
+  }
+  const int l = 2 * node + 1, r = 2 * node + 2;
+  const int rl = rank[l], rr = rank[r];
+  for (int i = threadIdx.x; i < rl; i += blockDim.x) out[i] = skel[(int64_t)l * r_cap + i];
+  for (int i = threadIdx.x; i < rr; i += blockDim.x) out[rl + i] = skel[(int64_t)r * r_cap + i];
+  if (threadIdx.x == 0) ncols[node] = rl + rr;
+}
+
+}  // namespace
+
+ffc_status launch_sample_rows(const ffc_tree* t, ffc_skel* sk, int first, int count, int s, uint64_t seed,
+                              hipStream_t st) {
+  int sort_n = 1;
+  while (sort_n < s) sort_n <<= 1;
+  const size_t lds = (size_t)sort_n * sizeof(int);
+  hipLaunchKernelGGL(k_sample_rows, dim3(count), dim3(64), lds, st, t->begin.ptr, t->end.ptr, t->N, first, s,
+                     sk->s_cap, sort_n, seed, sk->rows.ptr, sk->nrows.ptr);
+  FFC_LAUNCH_CHECK("k_sample_rows");
+  return FFC_OK;
+}
+
+ffc_status launch_level_columns(const ffc_tree* t, ffc_skel* sk, int first, int count, bool leaves,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_level_columns, dim3(count), dim3(256), 0, st, t->begin.ptr, t->end.ptr, first,
+                     leaves ? 1 : 0, sk->n_cap, sk->r_cap, sk->rank.ptr, sk->skel.ptr, sk->cols.ptr,
+                     sk->ncols.ptr);
+  FFC_LAUNCH_CHECK("k_level_columns");
+  return FFC_OK;
+}
+
+}  // namespace ffc

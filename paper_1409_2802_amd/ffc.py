@@ -1,0 +1,290 @@
+"""Python binding of libffc.so (argument marshalling only).
+
+Every call goes straight to the C ABI declared in include/ffc.h; all
+computation happens in the library's HIP kernels. torch tensors supply device
+memory and the current HIP stream. There is no fallback: if the library is
+missing or the GPU is absent, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libffc.so")
+
+FFC_OK, FFC_ERR_INVALID_ARG, FFC_ERR_HIP, FFC_ERR_OOM, FFC_ERR_NONFINITE, FFC_ERR_STATE = range(6)
+GAUSSIAN, LAPLACE, POLYNOMIAL = 0, 1, 2
+FP64, FP32, MIXED_BF16X3 = 0, 1, 2
+SAMPLE_UNIFORM, SAMPLE_LEARNED = 0, 1
+
+# Every exported entry point of include/ffc.h.
+EXPORTS = [
+    "ffc_build_tree", "ffc_build_partition", "ffc_tree_info", "ffc_tree_arrays",
+    "ffc_skeletonize_nodes", "ffc_evaluate_sum", "ffc_direct_sum", "ffc_sampled_block",
+    "ffc_interp_decomp", "ffc_skel_node", "ffc_skel_stats", "ffc_check_device",
+    "ffc_free_tree", "ffc_free_skel", "ffc_last_error",
+]
+
+
+class FfcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ffc error {code}: {msg}")
+        self.code = code
+
+
+class KernelC(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_int32), ("h", ctypes.c_double), ("c", ctypes.c_double)]
+
+
+class SkelOptsC(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_rank", ctypes.c_int32), ("num_samples", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("sampler", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("proposal", ctypes.c_void_p), ("fallback_tol", ctypes.c_double)]
+
+
+class StatsC(ctypes.Structure):
+    _fields_ = [("num_nodes", ctypes.c_int32), ("rank_min", ctypes.c_int32), ("rank_max", ctypes.c_int32),
+                ("rank_mean", ctypes.c_double), ("rank_cap_hits", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("kernel_evals", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libffc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with `python -m paper_1409_2802_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "ffc_build_tree": [P, I64, I32, I32, P, PP],
+        "ffc_build_partition": [P, I64, I32, I64, P, PP],
+        "ffc_tree_info": [P, P, P, P, P],
+        "ffc_tree_arrays": [P, P, P, P, P, P],
+        "ffc_skeletonize_nodes": [P, ctypes.POINTER(KernelC), ctypes.POINTER(SkelOptsC), P, PP],
+        "ffc_evaluate_sum": [P, P, ctypes.POINTER(KernelC), P, P, P, I32, P],
+        "ffc_direct_sum": [P, I64, P, I64, I32, ctypes.POINTER(KernelC), P, P, I32, P],
+        "ffc_sampled_block": [P, ctypes.POINTER(KernelC), I32, P, I32, P, I32, P, P],
+        "ffc_interp_decomp": [P, I32, I32, I32, D, I32, P, P, P, P],
+        "ffc_skel_node": [P, I32, P, P, P, P, P, P, P],
+        "ffc_skel_stats": [P, ctypes.POINTER(StatsC)],
+        "ffc_check_device": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.ffc_free_tree.argtypes = [P]
+    lib.ffc_free_tree.restype = None
+    lib.ffc_free_skel.argtypes = [P]
+    lib.ffc_free_skel.restype = None
+    lib.ffc_last_error.argtypes = []
+    lib.ffc_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code: int) -> None:
+    if code != FFC_OK:
+        raise FfcError(code, load_library().ffc_last_error().decode())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dev_f64(x, name: str) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64))
+    if not x.is_cuda:
+        x = x.to("cuda")
+    if x.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    return x.contiguous()
+
+
+def _dev_i32(x) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(np.ascontiguousarray(x, dtype=np.int32))
+    return x.to(device="cuda", dtype=torch.int32).contiguous()
+
+
+@dataclass(frozen=True)
+class Kernel:
+    kind: int
+    h: float = 1.0
+    c: float = 1.0
+    p: int = 1
+
+    def c_struct(self) -> KernelC:
+        return KernelC(kind=self.kind, p=self.p, h=self.h, c=self.c)
+
+
+class Tree:
+    """Handle to a ball tree (or two-part partition) built on the GPU."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        depth, nn, N, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        _check(load_library().ffc_tree_info(handle, ctypes.byref(depth), ctypes.byref(nn), ctypes.byref(N),
+                                            ctypes.byref(d)))
+        self.depth, self.num_nodes, self.N, self.d = depth.value, nn.value, N.value, d.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def arrays(self) -> dict:
+        perm = np.empty(self.N, dtype=np.int32)
+        b = np.empty(self.num_nodes, dtype=np.int64)
+        e = np.empty(self.num_nodes, dtype=np.int64)
+        cen = np.empty((self.num_nodes, self.d), dtype=np.float64)
+        rad = np.empty(self.num_nodes, dtype=np.float64)
+        _check(load_library().ffc_tree_arrays(self._h, perm.ctypes.data, b.ctypes.data, e.ctypes.data,
+                                              cen.ctypes.data, rad.ctypes.data))
+        return {"perm": perm, "begin": b, "end": e, "centroid": cen, "radius": rad}
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ffc_free_tree(self._h)
+            self._h = None
+
+
+def build_tree(X, leaf_size: int, stream=None) -> Tree:
+    Xd = _dev_f64(X, "X")
+    h = ctypes.c_void_p()
+    _check(load_library().ffc_build_tree(_ptr(Xd), Xd.shape[0], Xd.shape[1], leaf_size, _stream(stream),
+                                         ctypes.byref(h)))
+    return Tree(h)
+
+
+def build_partition(X, n_left: int, stream=None) -> Tree:
+    Xd = _dev_f64(X, "X")
+    h = ctypes.c_void_p()
+    _check(load_library().ffc_build_partition(_ptr(Xd), Xd.shape[0], Xd.shape[1], n_left, _stream(stream),
+                                              ctypes.byref(h)))
+    return Tree(h)
+
+
+class Skeletons:
+    """Handle to the per-node skeletons of a tree."""
+
+    def __init__(self, handle: ctypes.c_void_p, tree: Tree):
+        self._h = handle
+        self.tree = tree
+
+    @property
+    def handle(self):
+        return self._h
+
+    def node(self, a: int) -> dict:
+        lib = load_library()
+        r, nc, nr = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.ffc_skel_node(self._h, a, ctypes.byref(r), ctypes.byref(nc), ctypes.byref(nr), None, None, None,
+                                 None))
+        cols = np.empty(max(nc.value, 1), dtype=np.int32)
+        rows = np.empty(max(nr.value, 1), dtype=np.int32)
+        skel = np.empty(max(r.value, 1), dtype=np.int32)
+        P = np.empty((max(r.value, 1), max(nc.value, 1)), dtype=np.float64)
+        _check(lib.ffc_skel_node(self._h, a, ctypes.byref(r), ctypes.byref(nc), ctypes.byref(nr), cols.ctypes.data,
+                                 rows.ctypes.data, skel.ctypes.data, P.ctypes.data))
+        return {"rank": r.value, "cols": cols[:nc.value], "rows": rows[:nr.value], "skel": skel[:r.value],
+                "P": P[:r.value, :nc.value]}
+
+    def stats(self) -> dict:
+        st = StatsC()
+        _check(load_library().ffc_skel_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in StatsC._fields_}
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ffc_free_skel(self._h)
+            self._h = None
+
+
+def skeletonize(tree: Tree, kernel: Kernel, tol: float, max_rank: int, num_samples: int = 0,
+                precision: int = FP64, seed: int = 0, reuse: Skeletons | None = None,
+                stream=None) -> Skeletons:
+    opts = SkelOptsC(tol=tol, max_rank=max_rank, num_samples=num_samples, precision=precision,
+                     sampler=SAMPLE_UNIFORM, seed=seed, proposal=None, fallback_tol=0.0)
+    h = ctypes.c_void_p(reuse.handle.value if reuse is not None else None)
+    k = kernel.c_struct()
+    _check(load_library().ffc_skeletonize_nodes(tree.handle, ctypes.byref(k), ctypes.byref(opts), _stream(stream),
+                                                ctypes.byref(h)))
+    if reuse is not None:
+        return reuse
+    return Skeletons(h, tree)
+
+
+def evaluate_sum(tree: Tree, sk: Skeletons, kernel: Kernel, q, precision: int = FP64, stream=None):
+    qd = _dev_f64(q, "q")
+    u = torch.empty(tree.N, dtype=torch.float64, device="cuda")
+    uf = torch.empty(tree.N, dtype=torch.float64, device="cuda")
+    k = kernel.c_struct()
+    _check(load_library().ffc_evaluate_sum(tree.handle, sk.handle, ctypes.byref(k), _ptr(qd), _ptr(u), _ptr(uf),
+                                           precision, _stream(stream)))
+    return u, uf
+
+
+def evaluate_sum_into(tree: Tree, sk: Skeletons, kernel: Kernel, q: torch.Tensor, u: torch.Tensor,
+                      u_far: torch.Tensor | None, precision: int = FP64, stream=None) -> None:
+    k = kernel.c_struct()
+    _check(load_library().ffc_evaluate_sum(tree.handle, sk.handle, ctypes.byref(k), _ptr(q), _ptr(u), _ptr(u_far),
+                                           precision, _stream(stream)))
+
+
+def direct_sum(Y, X, q, kernel: Kernel, precision: int = FP64, out: torch.Tensor | None = None, stream=None):
+    Yd, Xd, qd = _dev_f64(Y, "Y"), _dev_f64(X, "X"), _dev_f64(q, "q")
+    if Yd.shape[1] != Xd.shape[1] or qd.shape[0] != Xd.shape[0]:
+        raise ValueError("shape mismatch")
+    u = out if out is not None else torch.empty(Yd.shape[0], dtype=torch.float64, device="cuda")
+    k = kernel.c_struct()
+    _check(load_library().ffc_direct_sum(_ptr(Yd), Yd.shape[0], _ptr(Xd), Xd.shape[0], Xd.shape[1], ctypes.byref(k),
+                                         _ptr(qd), _ptr(u), precision, _stream(stream)))
+    return u
+
+
+def sampled_block(tree: Tree, kernel: Kernel, rows, cols, precision: int = FP64, stream=None) -> torch.Tensor:
+    """K(x_rows, x_cols) for tree positions; returned as an (s, n) view."""
+    rd, cd = _dev_i32(rows), _dev_i32(cols)
+    s, n = rd.numel(), cd.numel()
+    out = torch.empty((n, s), dtype=torch.float64, device="cuda")
+    k = kernel.c_struct()
+    _check(load_library().ffc_sampled_block(tree.handle, ctypes.byref(k), precision, _ptr(rd), s, _ptr(cd), n,
+                                            _ptr(out), _stream(stream)))
+    return out.T
+
+
+def interp_decomp(A, tol: float, max_rank: int, stream=None):
+    """Batched ID of A (batch, s, n). Returns (rank[b], piv[b, n], P[b, max_rank, n])."""
+    Ad = _dev_f64(A, "A")
+    if Ad.dim() == 2:
+        Ad = Ad[None]
+    b, s, n = Ad.shape
+    work = Ad.transpose(1, 2).contiguous()          # column-major s x n blocks
+    rank = torch.zeros(b, dtype=torch.int32, device="cuda")
+    piv = torch.zeros((b, n), dtype=torch.int32, device="cuda")
+    P = torch.zeros((b, max_rank, n), dtype=torch.float64, device="cuda")
+    _check(load_library().ffc_interp_decomp(_ptr(work), b, s, n, tol, max_rank, _ptr(rank), _ptr(piv), _ptr(P),
+                                            _stream(stream)))
+    return rank, piv, P
+
+
+def check_device(stream=None) -> None:
+    """Raise FfcError(FFC_ERR_NONFINITE) if a kernel value was not finite."""
+    _check(load_library().ffc_check_device(_stream(stream)))

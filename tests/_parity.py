@@ -1,0 +1,76 @@
+"""Shared parity helpers for the GPU tests (GPU path vs the CPU oracle)."""
+import numpy as np
+
+from oracle.kernels import GAUSSIAN, LAPLACE, POLYNOMIAL
+from oracle.kernels import Kernel as OKernel
+
+# Parity bar for FP64 results (relative 2-norm), from the rounding of the
+# method's arithmetic: sums of a few thousand kernel values times
+# interpolation coefficients bounded by the condition of R11.
+FP64_REL = 1e-10
+# A pivot is "unambiguous" when the two largest trailing squared norms differ
+# by more than this relative gap; only then must both sides pick the same one.
+GAP_MIN = 1e-10
+
+
+def okernel(kind, h=1.0, c=1.0, p=1):
+    return OKernel(kind, h=h, c=c, p=p)
+
+
+def gkernel(kind, h=1.0, c=1.0, p=1):
+    from paper_1409_2802_amd.ffc import Kernel
+    return Kernel(kind, h=h, c=c, p=p)
+
+
+KERNELS = {
+    "gaussian": (GAUSSIAN, dict(h=1.0)),
+    "laplace": (LAPLACE, dict()),
+    "polynomial": (POLYNOMIAL, dict(h=4.0, p=3)),
+}
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a))
+
+
+def unambiguous(node, tol):
+    """Pivots and the stopping decision of an oracle node are well separated."""
+    if node.gap.size and node.gap.min() <= GAP_MIN:
+        return False
+    if node.rho.size and tol > 0:
+        # rho_k / rho_0 for every accepted pivot stays clear of tol.
+        ratios = node.rho / node.rho[0]
+        if np.any(np.abs(ratios - tol) <= 1e-9 * tol):
+            return False
+    return True
+
+
+U64 = 2.0 ** -53
+
+
+def direct_bound(Y, X, q, kind, kw):
+    """Per-target bound on |u_gpu - u_oracle| for a kernel sum in FP64.
+
+    Both sides form r^2 (or x.y) from d products with relative error up to
+    about (d + 2) u each; the kernel turns a relative error e of its argument
+    into amp * e, amp = |d ln K / d ln r^2| (Gaussian r^2 / 2h^2, Laplace
+    (d - 2) / 2, polynomial p |a / (a + c)| with a = x.y / h); summing n terms
+    adds n u. The bound is that budget times sum_j |K_ij q_j|.
+    """
+    import numpy as np
+    from oracle.direct import direct_abs_sum
+    from oracle.kernels import kernel_matrix, sqdist
+    d = Y.shape[1]
+    ok = okernel(kind, **kw)
+    if kind == GAUSSIAN:
+        amp = float(sqdist(Y, X).max()) / (2 * kw.get("h", 1.0) ** 2)
+    elif kind == LAPLACE:
+        amp = (d - 2) / 2.0
+    else:
+        a = (Y @ X.T) / kw.get("h", 1.0)
+        c = kw.get("c", 1.0)
+        amp = kw.get("p", 1) * float(np.max(np.abs(a) / np.maximum(np.abs(a + c), 1e-300)))
+    budget = (2 * (d + 2) * (amp + 1) + 4 + 2 * X.shape[0]) * U64
+    return budget * direct_abs_sum(Y, X, q, ok)

@@ -1,0 +1,68 @@
+"""GPU direct sum and sampled kernel blocks against the oracle (Section 1,
+eq. e:sum; Section 2.2, the sampled block K')."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.direct import direct_abs_sum, direct_sum as o_direct
+from oracle.kernels import kernel_matrix
+from oracle.tree import build_tree as o_build_tree
+from paper_1409_2802_amd import workloads as W
+from tests._parity import KERNELS, direct_bound, gkernel, okernel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ffc():
+    from paper_1409_2802_amd import ffc as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.load_library()
+    return m
+
+
+@pytest.mark.parametrize("name", list(KERNELS))
+@pytest.mark.parametrize("m,n,d", [(1, 1, 3), (65, 130, 4), (333, 1000, 16), (200, 257, 64), (70, 90, 1000)])
+def test_direct_sum_fp64(ffc, name, m, n, d):
+    kind, kw = KERNELS[name]
+    if kind == 1 and d < 3:
+        pytest.skip("Laplace needs d >= 3")
+    Y = W.normal(m, d, seed=1) / np.sqrt(d)
+    X = W.normal(n, d, seed=2) / np.sqrt(d)
+    if m >= 3 and n >= 3:
+        X[:3] = Y[:3]          # coincident pairs: the Laplace kernel must give 0 there
+    q = W.charges(n, seed=3)
+    u = ffc.direct_sum(Y, X, q, gkernel(kind, **kw)).cpu().numpy()
+    ref = o_direct(Y, X, q, okernel(kind, **kw))
+    assert np.all(np.abs(u - ref) <= direct_bound(Y, X, q, kind, kw))
+    ffc.check_device()
+
+
+@pytest.mark.parametrize("name", list(KERNELS))
+def test_direct_sum_fp32(ffc, name):
+    kind, kw = KERNELS[name]
+    Y = W.uniform_cube(300, 8, seed=4)
+    X = W.uniform_cube(500, 8, seed=5) + 0.05
+    q = W.charges(500, seed=6)
+    u = ffc.direct_sum(Y, X, q, gkernel(kind, **kw), precision=ffc.FP32).cpu().numpy()
+    ref = o_direct(Y, X, q, okernel(kind, **kw))
+    scale = direct_abs_sum(Y, X, q, okernel(kind, **kw))
+    # FP32 distances: relative error of each kernel value ~ (d + |log K|) * 2^-23 times the power for Laplace.
+    bound = {0: 5e-5, 1: 5e-5, 2: 5e-5}[kind]
+    assert np.all(np.abs(u - ref) <= bound * scale)
+
+
+@pytest.mark.parametrize("name", list(KERNELS))
+@pytest.mark.parametrize("N,d,s,n", [(600, 4, 37, 129), (3000, 16, 128, 200), (900, 100, 70, 65)])
+def test_sampled_block_fp64(ffc, name, N, d, s, n):
+    kind, kw = KERNELS[name]
+    X = W.gaussian_mixture(N, d, k=5, box=3.0, std=0.5, seed=7)
+    t = ffc.build_tree(X, 64)
+    perm = t.arrays()["perm"]
+    g = np.random.default_rng(8)
+    rows = g.choice(N, size=s, replace=False).astype(np.int32)
+    cols = g.choice(N, size=n, replace=False).astype(np.int32)
+    Kg = ffc.sampled_block(t, gkernel(kind, **kw), rows, cols).cpu().numpy()
+    Xt = X[perm]
+    Ko = kernel_matrix(Xt[rows], Xt[cols], okernel(kind, **kw))
+    np.testing.assert_allclose(Kg, Ko, rtol=1e-12, atol=0)

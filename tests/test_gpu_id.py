@@ -1,0 +1,86 @@
+"""GPU batched interpolative decomposition against the oracle (Section 2.1.3,
+Definition of the ID, Theorem thm_compute_id; Appendix 6.1)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.cpqr_id import interpolative_decomposition
+from oracle.kernels import POLYNOMIAL, kernel_matrix
+from oracle.sampling import floyd_sample
+from tests._parity import GAP_MIN, gkernel, okernel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ffc():
+    from paper_1409_2802_amd import ffc as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.load_library()
+    return m
+
+
+def decaying(s, n, seed, decay=8.0):
+    g = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(g.standard_normal((s, min(s, n))))
+    V, _ = np.linalg.qr(g.standard_normal((n, min(s, n))))
+    sv = 10.0 ** -np.linspace(0, decay, min(s, n))
+    return U @ np.diag(sv) @ V.T
+
+
+def check_against_oracle(A, rank, piv, P, tol, max_rank):
+    o = interpolative_decomposition(A, tol, max_rank)
+    if o.gap.size == 0 or o.gap.min() > GAP_MIN:
+        assert rank == o.rank
+        np.testing.assert_array_equal(piv[:rank], o.piv[:rank])
+        # P agrees to the conditioning of R11 (Appendix 6.1 solve).
+        R11 = o.R[:, :o.rank]
+        kappa = np.linalg.cond(R11) if o.rank else 1.0
+        np.testing.assert_allclose(P[:rank], o.P, atol=max(1e-13, 1e-15 * kappa) * max(1.0, np.abs(o.P).max()))
+    # Reconstruction through the GPU skeleton is as good as the oracle's.
+    err_g = np.linalg.norm(A - A[:, piv[:rank]] @ P[:rank])
+    err_o = np.linalg.norm(A - A[:, o.skel] @ o.P)
+    assert err_g <= err_o * (1 + 1e-6) + 1e-12 * np.linalg.norm(A)
+    # P contains the identity on the skeleton columns.
+    np.testing.assert_array_equal(P[:rank][:, piv[:rank]], np.eye(rank))
+
+
+@pytest.mark.parametrize("s,n,tol,max_rank", [(40, 30, 1e-6, 30), (128, 256, 1e-6, 64), (512, 512, 1e-5, 256),
+                                              (100, 7, 0.0, 7), (33, 65, 1e-3, 5), (1, 9, 1e-3, 3), (9, 1, 1e-3, 3)])
+def test_batched_id_matches_oracle(ffc, s, n, tol, max_rank):
+    mats = [decaying(s, n, seed) for seed in range(3)]
+    rank, piv, P = ffc.interp_decomp(np.stack(mats), tol, max_rank)
+    rank, piv, P = rank.cpu().numpy(), piv.cpu().numpy(), P.cpu().numpy()
+    for b, A in enumerate(mats):
+        check_against_oracle(A, int(rank[b]), piv[b], P[b], tol, max_rank)
+
+
+def test_zero_and_full_rank_blocks(ffc):
+    A = np.zeros((16, 12))
+    rank, _, _ = ffc.interp_decomp(A, 1e-6, 12)
+    assert int(rank[0]) == 0
+    B = np.random.default_rng(0).standard_normal((20, 12))
+    rank, piv, P = ffc.interp_decomp(B, 0.0, 12)
+    r = int(rank[0])
+    assert r == 12
+    p = piv[0].cpu().numpy()
+    np.testing.assert_allclose(B[:, p[:r]] @ P[0].cpu().numpy()[:r], B, atol=1e-13)
+
+
+@pytest.mark.parametrize("p,expected", [(2, 15), (3, 35)])
+def test_polynomial_exact_rank(ffc, p, expected):
+    """(x.y/h + 1)^p in d = 4 has rank C(4 + p, p): the GPU ID finds it and the
+    sampled rows reconstruct the whole block."""
+    assert math.comb(4 + p, p) == expected
+    g = np.random.default_rng(6)
+    X, Y = g.standard_normal((80, 4)), g.standard_normal((600, 4))
+    k = okernel(POLYNOMIAL, h=2.0, p=p)
+    rows = np.array(floyd_sample(600, 2 * expected, seed=1, stream=0))
+    rank, piv, P = ffc.interp_decomp(kernel_matrix(Y[rows], X, k), 1e-11, 80)
+    r = int(rank[0])
+    assert r == expected
+    K = kernel_matrix(Y, X, k)
+    pv = piv[0].cpu().numpy()[:r]
+    assert np.linalg.norm(K - K[:, pv] @ P[0].cpu().numpy()[:r]) / np.linalg.norm(K) < 1e-9

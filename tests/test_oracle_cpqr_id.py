@@ -40,7 +40,7 @@ def test_pivots_and_diagonal_match_lapack_dgeqp3():
     g = _rng(2)
     A = g.standard_normal((20, 12)) * (2.0 ** -np.arange(12))[None, :]
     A = A[:, g.permutation(12)]
-    r, piv, RA, _ = cpqr(A, tol=0.0, max_rank=12)
+    r, piv, RA, _, _ = cpqr(A, tol=0.0, max_rank=12)
     _, R_ref, piv_ref = scipy.linalg.qr(A, pivoting=True, mode="economic")
     np.testing.assert_array_equal(piv, piv_ref)
     np.testing.assert_allclose(np.abs(np.diag(RA[:12, :12])), np.abs(np.diag(R_ref)), rtol=1e-12)
@@ -79,7 +79,7 @@ def test_tie_break_goes_to_smallest_original_column():
     A = np.zeros((4, 4))
     A[0, 3] = A[1, 1] = 2.0
     A[2, 0] = 1.0
-    r, piv, _, _ = cpqr(A, tol=0.0, max_rank=4)
+    r, piv, _, _, _ = cpqr(A, tol=0.0, max_rank=4)
     assert piv[0] == 1 and piv[1] == 3
 
 
