@@ -1,0 +1,232 @@
+"""Throughput of the far-field compression hot path on one MI355X.
+
+A step is one pass of the whole hot path over the resident input: every
+non-root node skeletonized (row sampling, sampled kernel block, pivoted-QR
+ID, interpolation solve, skeleton ids) and the kernel sum evaluated with the
+compressed far field (equivalent charges upward, far + near field sums).
+The tree is built once, outside the timed region.
+
+Workload (default): N = 65536 points in d = 16 from a mixture of 32 Gaussian
+clusters (centres uniform in [0, 10]^16, std 0.5), Gaussian kernel h = 1,
+ball tree with leaf size 512, rank cap 256 and 2 x 256 sampled rows per
+node, ID tolerance 1e-5, q ~ N(0, 1), FP64.
+
+Prints one JSON line: value = skeletonized nodes per second of step time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "skeletonized nodes/s + kernel evals/s at far-field rel err 1e-4 vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+WORKLOADS = {
+    "mixture16": dict(N=65536, d=16, data="gaussian_mixture", clusters=32, box=10.0, std=0.5, kernel="gaussian",
+                      h=1.0, leaf=512, max_rank=256, num_samples=512, tol=1e-5),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mixture16", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def make_inputs(w):
+    from paper_1409_2802_amd import workloads as W
+    X = W.gaussian_mixture(w["N"], w["d"], k=w["clusters"], box=w["box"], std=w["std"], seed=0)
+    q = W.charges(w["N"], seed=1)
+    return X, q
+
+
+def cpqr_flops(s, n, r):
+    """Householder QR to rank r of an s x n block plus the r x r triangular solve."""
+    return 4.0 * s * n * r - 2.0 * r * r * (s + n) + 4.0 * r ** 3 / 3.0 + r * r * max(n - r, 0)
+
+
+def cpqr_bytes(s, n, r):
+    """One read + write of the trailing block per pivot step (block larger than on-chip storage)."""
+    k = np.arange(r, dtype=np.float64)
+    return float(np.sum(16.0 * (s - k) * (n - k))) + 8.0 * s * n
+
+
+def cpu_baseline(w, X, q, budget_s):
+    """The oracle, single-threaded, on a bounded sample of the workload's nodes."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.kernels import GAUSSIAN
+    from oracle.kernels import Kernel as OKernel
+    from oracle.skeleton import skeletonize_node
+    from oracle.tree import build_tree as o_build_tree
+    ok = OKernel(GAUSSIAN, h=w["h"])
+    with threadpool_limits(limits=1):
+        ot = o_build_tree(X, w["leaf"])
+        Xt = X[ot.perm]
+        t0 = time.perf_counter()
+        done = 0
+        for a in ot.level_nodes(ot.depth):          # leaves: their columns need no children
+            cols = np.arange(ot.begin[a], ot.end[a], dtype=np.int64)
+            skeletonize_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], 0)
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} leaf nodes of the same tree (512 points, {w['num_samples']} sampled rows each), "
+                      f"single thread, {dt:.1f} s"}
+
+
+def oracle_far_check(w, X, q, u_far_gpu, count=256):
+    """Far-field relative error of the GPU result against the oracle's exact sum on sampled targets."""
+    from oracle.evaluate import exact_far_field, relative_error
+    from oracle.kernels import GAUSSIAN
+    from oracle.kernels import Kernel as OKernel
+    from oracle.tree import build_tree as o_build_tree
+    from paper_1409_2802_amd import workloads as W
+    ot = o_build_tree(X, w["leaf"])
+    tg = W.subset(w["N"], count, seed=2)
+    ex = exact_far_field(X, ot, OKernel(GAUSSIAN, h=w["h"]), q, tg)
+    return relative_error(u_far_gpu[tg], ex)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the method's kernels are measured on a single MI355X "
+              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1409_2802_amd import ffc
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ffc.load_library()
+    w = WORKLOADS[args.workload]
+    prec = ffc.FP64 if args.precision == "fp64" else ffc.FP32
+    X, q = make_inputs(w)
+    Xd = torch.as_tensor(X, device="cuda")
+    qd = torch.as_tensor(q, device="cuda")
+    k = ffc.Kernel(ffc.GAUSSIAN, h=w["h"])
+    tree = ffc.build_tree(Xd, w["leaf"])
+    u = torch.empty(w["N"], dtype=torch.float64, device="cuda")
+    uf = torch.empty(w["N"], dtype=torch.float64, device="cuda")
+
+    def step(sk):
+        sk = ffc.skeletonize(tree, k, tol=w["tol"], max_rank=w["max_rank"], num_samples=w["num_samples"],
+                             precision=prec, seed=0, reuse=sk)
+        ffc.evaluate_sum_into(tree, sk, k, qd, u, uf, precision=prec)
+        return sk
+
+    sk = None
+    for _ in range(max(1, args.warmup)):
+        sk = step(sk)
+    torch.cuda.synchronize()
+    ffc.check_device()
+    ffc.profile_read(reset=True)
+    ffc.profile_enable(True)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        sk = step(sk)
+    stop.record()
+    torch.cuda.synchronize()
+    ffc.profile_enable(False)
+    prof = ffc.profile_read(reset=True)
+    ms_total = start.elapsed_time(stop)
+    ms_step = ms_total / args.steps
+    ffc.check_device()
+
+    # Work counts of one step.
+    st = sk.stats()
+    arr = tree.arrays()
+    ranks = np.zeros(tree.num_nodes, dtype=np.int64)
+    nodes = {}
+    for a in range(1, tree.num_nodes):
+        nodes[a] = sk.node(a)
+        ranks[a] = nodes[a]["rank"]
+    sizes = arr["end"] - arr["begin"]
+    leaves = range((1 << tree.depth) - 1, tree.num_nodes)
+    eval_evals = float(sum(sizes[a] ** 2 for a in leaves))
+    eval_evals += float(sum(sizes[a + 1 if a % 2 else a - 1] * ranks[a] for a in range(1, tree.num_nodes)))
+    skel_evals = st["kernel_evals"]
+    nodes_per_s = st["num_nodes"] / (ms_step * 1e-3)
+    evals_per_s = (skel_evals + eval_evals) / (ms_step * 1e-3)
+
+    # Accuracy against the plain FP64 path: exact far field = direct sum minus the (exact) near field.
+    ud = ffc.direct_sum(Xd, Xd, qd, k, precision=ffc.FP64)
+    torch.cuda.synchronize()
+    u_h, uf_h, ud_h = u.cpu().numpy(), uf.cpu().numpy(), ud.cpu().numpy()
+    far_exact = ud_h - (u_h - uf_h)
+    e_far_gpu = float(np.linalg.norm(uf_h - far_exact) / np.linalg.norm(far_exact))
+    e_tot_gpu = float(np.linalg.norm(u_h - ud_h) / np.linalg.norm(ud_h))
+
+    # Roofline of the dominant stage (average launch duration from the in-region events).
+    dom = max((s for s in prof if s not in ("tree", "direct")), key=lambda s: prof[s]["ms"])
+    launches_per_step = prof[dom]["launches"] / args.steps
+    ms_per_launch = prof[dom]["ms"] / max(1, prof[dom]["launches"])
+    roof = None
+    if dom == "cpqr":
+        byts = sum(cpqr_bytes(len(nodes[a]["rows"]), len(nodes[a]["cols"]), nodes[a]["rank"])
+                   for a in nodes) / launches_per_step
+        roof = {"bound": "hbm", "achieved": byts / (ms_per_launch * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "traffic": None}
+    elif dom in ("kblock", "evaluate"):
+        ev = skel_evals if dom == "kblock" else eval_evals
+        flops = ev * 3.0 * w["d"] / launches_per_step
+        peak = FP64_PEAK_TFLOPS if prec == ffc.FP64 else FP32_PEAK_TFLOPS
+        roof = {"bound": "alu", "achieved": flops / (ms_per_launch * 1e-3) / 1e12, "peak": peak,
+                "unit": "TFLOP/s", "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None}
+    if roof["achieved"] is not None:
+        roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = dom
+    roof["ms_per_launch"] = ms_per_launch
+    roof["launches_per_step"] = launches_per_step
+
+    out = {
+        "metric": METRIC, "value": nodes_per_s, "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == ffc.FP64 else "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: N={w['N']} d={w['d']} {w['clusters']}-cluster Gaussian mixture, "
+                               f"Gaussian h={w['h']}, leaf {w['leaf']}, s={w['num_samples']}, "
+                               f"max_rank={w['max_rank']}, tol={w['tol']}",
+                   "N": w["N"], "d": w["d"], "leaf_size": w["leaf"], "num_samples": w["num_samples"],
+                   "max_rank": w["max_rank"], "tol": w["tol"], "precision": args.precision},
+        "kernel_evals_per_s": evals_per_s,
+        "skeleton_kernel_evals": skel_evals, "evaluate_kernel_evals": eval_evals,
+        "ranks": {"min": st["rank_min"], "mean": st["rank_mean"], "max": st["rank_max"],
+                  "cap_hits": st["rank_cap_hits"]},
+        "e_far_vs_gpu_fp64_direct": e_far_gpu, "e_total_vs_gpu_fp64_direct": e_tot_gpu,
+        "meets_1e-4": e_far_gpu <= 1e-4,
+        "stage_ms_per_step": {s: prof[s]["ms"] / args.steps for s in prof},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(w, X, q, args.cpu_budget_s)
+        cb["e_far_vs_oracle_256_targets"] = oracle_far_check(w, X, q, uf_h)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

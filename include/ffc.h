@@ -194,6 +194,25 @@ ffc_status ffc_skel_stats(const ffc_skel* sk, ffc_stats* out);
  * FFC_ERR_NONFINITE if a kernel value was not finite since the last check. */
 ffc_status ffc_check_device(void* stream);
 
+/* Stage profiler (tracing). When enabled, every stage launch is bracketed by
+ * two HIP events recorded on the stream the stage runs on; ffc_profile_read
+ * waits for them and returns the accumulated milliseconds and launch counts
+ * per stage (index = ffc_stage), optionally resetting the totals. */
+typedef enum {
+  FFC_STAGE_TREE = 0,      /* tree construction */
+  FFC_STAGE_SAMPLE = 1,    /* target-row sampling */
+  FFC_STAGE_COLUMNS = 2,   /* per-level column lists */
+  FFC_STAGE_KBLOCK = 3,    /* sampled kernel blocks K' */
+  FFC_STAGE_CPQR = 4,      /* pivoted QR + interpolation solve */
+  FFC_STAGE_SKEL = 5,      /* skeleton ids */
+  FFC_STAGE_UPWARD = 6,    /* equivalent charges */
+  FFC_STAGE_EVALUATE = 7,  /* far + near field sums */
+  FFC_STAGE_DIRECT = 8,    /* direct sums */
+  FFC_NUM_STAGES = 9
+} ffc_stage;
+ffc_status ffc_profile_enable(int32_t on);
+ffc_status ffc_profile_read(double* ms_host, int64_t* launches_host, int32_t num_stages, int32_t reset);
+
 void ffc_free_tree(ffc_tree* t);
 void ffc_free_skel(ffc_skel* sk);
 const char* ffc_last_error(void);

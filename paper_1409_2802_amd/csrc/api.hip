@@ -139,7 +139,10 @@ ffc_status ffc_build_tree(const double* X_dev, int64_t N, int32_t d, int32_t lea
     if (e != hipSuccess) s = fail(FFC_ERR_HIP, std::string("copy of X: ") + hipGetErrorString(e));
   }
   if (s == FFC_OK) s = finish_tree_common(t, st);
-  if (s == FFC_OK) s = launch_build_tree(t, leaf_size, st);
+  if (s == FFC_OK) {
+    StageTimer timer(FFC_STAGE_TREE, st);
+    s = launch_build_tree(t, leaf_size, st);
+  }
   if (s != FFC_OK) {
     delete t;
     return s;
@@ -289,9 +292,18 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
   auto run = [&]() -> ffc_status {
     for (int lev = t->depth; lev >= 1; --lev) {
       const int first = (1 << lev) - 1, count = 1 << lev;
-      FFC_TRY(launch_sample_rows(t, sk, first, count, s_cap, o->seed, st));
-      FFC_TRY(launch_level_columns(t, sk, first, count, lev == t->depth, st));
-      FFC_TRY(launch_level_kblock(t, sk, kp, o->precision, first, count, sk->work.ptr, st));
+      {
+        StageTimer tm(FFC_STAGE_SAMPLE, st);
+        FFC_TRY(launch_sample_rows(t, sk, first, count, s_cap, o->seed, st));
+      }
+      {
+        StageTimer tm(FFC_STAGE_COLUMNS, st);
+        FFC_TRY(launch_level_columns(t, sk, first, count, lev == t->depth, st));
+      }
+      {
+        StageTimer tm(FFC_STAGE_KBLOCK, st);
+        FFC_TRY(launch_level_kblock(t, sk, kp, o->precision, first, count, sk->work.ptr, st));
+      }
       IdBatch bt{};
       bt.A = sk->work.ptr;
       bt.a_stride = (int64_t)s_cap * n_cap;
@@ -308,8 +320,14 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
       bt.P = sk->P.ptr + (int64_t)first * r_cap * n_cap;
       bt.p_stride = (int64_t)r_cap * n_cap;
       bt.p_ld = n_cap;
-      FFC_TRY(launch_interp_decomp(bt, count, st));
-      FFC_TRY(launch_skeleton_ids(sk, first, count, st));
+      {
+        StageTimer tm(FFC_STAGE_CPQR, st);
+        FFC_TRY(launch_interp_decomp(bt, count, st));
+      }
+      {
+        StageTimer tm(FFC_STAGE_SKEL, st);
+        FFC_TRY(launch_skeleton_ids(sk, first, count, st));
+      }
     }
     return FFC_OK;
   };
@@ -336,10 +354,16 @@ ffc_status ffc_evaluate_sum(const ffc_tree* t, const ffc_skel* sk, const ffc_ker
   hipStream_t st = (hipStream_t)stream;
   ffc_tree* tm = const_cast<ffc_tree*>(t);
   ffc_skel* sm = const_cast<ffc_skel*>(sk);
-  FFC_TRY(launch_charges_to_tree(tm, q_dev, st));
-  for (int lev = t->depth; lev >= 1; --lev)
-    FFC_TRY(launch_upward(t, sm, (1 << lev) - 1, 1 << lev, lev == t->depth, st));
-  FFC_TRY(launch_evaluate(t, sk, make_kparams(*k, t->d), precision, u_dev, u_far_dev, st));
+  {
+    StageTimer timer(FFC_STAGE_UPWARD, st);
+    FFC_TRY(launch_charges_to_tree(tm, q_dev, st));
+    for (int lev = t->depth; lev >= 1; --lev)
+      FFC_TRY(launch_upward(t, sm, (1 << lev) - 1, 1 << lev, lev == t->depth, st));
+  }
+  {
+    StageTimer timer(FFC_STAGE_EVALUATE, st);
+    FFC_TRY(launch_evaluate(t, sk, make_kparams(*k, t->d), precision, u_dev, u_far_dev, st));
+  }
   tm->last_stream = st;
   return FFC_OK;
 }
@@ -355,6 +379,7 @@ ffc_status ffc_direct_sum(const double* Y_dev, int64_t m, const double* X_dev, i
   if (precision == FFC_MIXED_BF16X3)
     return fail(FFC_ERR_INVALID_ARG, "mixed bf16x3 precision is not available in this build");
   if (!device_flag()) return fail(FFC_ERR_HIP, "cannot allocate the device flag");
+  StageTimer timer(FFC_STAGE_DIRECT, (hipStream_t)stream);
   return launch_direct_sum(Y_dev, m, X_dev, n, d, make_kparams(*k, d), precision, q_dev, u_dev, (hipStream_t)stream);
 }
 

@@ -21,8 +21,11 @@
 namespace ffc {
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 1024;
 constexpr int NW = NT / 64;
+// Columns a wavefront updates at once: CPW * MAXR doubles stay in registers.
+template <int MAXR>
+struct ColsPerWave { static constexpr int value = MAXR <= 8 ? 4 : 2; };
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -61,6 +64,76 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// Apply the reflector (v, beta) to CPW columns starting at j0 (a wavefront's
+// share) and recompute their norms over rows k+1..s-1. Rows per lane are
+// cached in registers when s - k <= 64 * MAXR.
+template <int MAXR, int CPW>
+__device__ inline void update_columns(double* __restrict__ A, int lda, int s, int k, int j0, int ncol,
+                                      const double* __restrict__ v, double beta, double* __restrict__ norms,
+                                      int lane) {
+  double a[CPW][MAXR];
+  double dot[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) dot[c] = 0.0;
+#pragma unroll
+  for (int m = 0; m < MAXR; ++m) {
+    const int i = k + lane + 64 * m;
+    const bool in = i < s;
+    const double vi = in ? v[i] : 0.0;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      a[c][m] = (in && c < ncol) ? A[(int64_t)(j0 + c) * lda + i] : 0.0;
+      dot[c] = fma(vi, a[c][m], dot[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) dot[c] = wave_sum(dot[c]) * beta;
+  double nrm[CPW];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) nrm[c] = 0.0;
+#pragma unroll
+  for (int m = 0; m < MAXR; ++m) {
+    const int i = k + lane + 64 * m;
+    if (i < s) {
+      const double vi = v[i];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        if (c < ncol) {
+          const double x = fma(-vi, dot[c], a[c][m]);
+          A[(int64_t)(j0 + c) * lda + i] = x;
+          if (i > k) nrm[c] = fma(x, x, nrm[c]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    nrm[c] = wave_sum(nrm[c]);
+    if (lane == 0 && c < ncol) norms[j0 + c] = nrm[c];
+  }
+}
+
+// Same without the register cache (any s): two passes over the column.
+__device__ inline void update_columns_any(double* __restrict__ A, int lda, int s, int k, int j0, int ncol,
+                                          const double* __restrict__ v, double beta, double* __restrict__ norms,
+                                          int lane) {
+  for (int c = 0; c < ncol; ++c) {
+    double* cj = A + (int64_t)(j0 + c) * lda;
+    double dot = 0.0;
+    for (int i = k + lane; i < s; i += 64) dot = fma(v[i], cj[i], dot);
+    dot = wave_sum(dot) * beta;
+    double nrm = 0.0;
+    for (int i = k + lane; i < s; i += 64) {
+      const double x = fma(-v[i], dot, cj[i]);
+      cj[i] = x;
+      if (i > k) nrm = fma(x, x, nrm);
+    }
+    nrm = wave_sum(nrm);
+    if (lane == 0) norms[j0 + c] = nrm;
+  }
+}
+
+template <int MAXR>
 __global__ void __launch_bounds__(NT) k_cpqr_id(IdBatch bt) {
   extern __shared__ double smem[];
   const int b = blockIdx.x;
@@ -137,20 +210,14 @@ __global__ void __launch_bounds__(NT) k_cpqr_id(IdBatch bt) {
     const double beta = vv > 0.0 ? 2.0 / vv : 0.0;
     __syncthreads();
     for (int i = k + tid; i < s; i += NT) ck[i] = i == k ? alpha : 0.0;
-    // Apply to the trailing columns and recompute their norms over rows k+1..s-1.
-    for (int j = k + 1 + w; j < n; j += NW) {
-      double* cj = A + (int64_t)j * lda;
-      double dot = 0.0;
-      for (int i = k + lane; i < s; i += 64) dot = fma(v[i], cj[i], dot);
-      dot = wave_sum(dot) * beta;
-      double nrm = 0.0;
-      for (int i = k + lane; i < s; i += 64) {
-        const double a = fma(-v[i], dot, cj[i]);
-        cj[i] = a;
-        if (i > k) nrm = fma(a, a, nrm);
-      }
-      nrm = wave_sum(nrm);
-      if (lane == 0) norms[j] = nrm;
+    // Apply to the trailing columns; each wavefront takes CPW columns at a time.
+    const int first = k + 1;
+    constexpr int CPW = ColsPerWave<MAXR>::value;
+    const bool cached = MAXR > 0 && (s - k) <= 64 * MAXR;
+    for (int j0 = first + w * CPW; j0 < n; j0 += NW * CPW) {
+      const int ncol = min(CPW, n - j0);
+      if (cached) update_columns<(MAXR > 0 ? MAXR : 1), CPW>(A, lda, s, k, j0, ncol, v, beta, norms, lane);
+      else update_columns_any(A, lda, s, k, j0, ncol, v, beta, norms, lane);
     }
     __syncthreads();
   }
@@ -231,7 +298,16 @@ ffc_status launch_interp_decomp(const IdBatch& bt, int batch, hipStream_t st) {
     set_error("interpolative decomposition: block too large for LDS (s + n too big)");
     return FFC_ERR_INVALID_ARG;
   }
-  hipLaunchKernelGGL(k_cpqr_id, dim3(batch), dim3(NT), lds, st, bt);
+  auto launch = [&](auto kern) -> ffc_status {
+    if (lds > 64 * 1024)
+      FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3(batch), dim3(NT), lds, st, bt);
+    return FFC_OK;
+  };
+  if (bt.s_max <= 64 * 8) FFC_TRY(launch(k_cpqr_id<8>));
+  else if (bt.s_max <= 64 * 16) FFC_TRY(launch(k_cpqr_id<16>));
+  else FFC_TRY(launch(k_cpqr_id<0>));
   FFC_LAUNCH_CHECK("k_cpqr_id");
   return FFC_OK;
 }

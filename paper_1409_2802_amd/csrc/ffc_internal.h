@@ -60,6 +60,23 @@ struct KParams {
 
 KParams make_kparams(const ffc_kernel& k, int d);
 
+// Stage profiler: a StageTimer brackets the launches of one stage with events
+// on the stage's stream while profiling is enabled.
+bool profiling();
+class StageTimer {
+ public:
+  StageTimer(int stage, hipStream_t st);
+  ~StageTimer();
+  StageTimer(const StageTimer&) = delete;
+  StageTimer& operator=(const StageTimer&) = delete;
+
+ private:
+  int stage_;
+  hipStream_t st_;
+  hipEvent_t start_{}, stop_{};
+  bool active_ = false;
+};
+
 // Device flag word (bit 0: a kernel value was not finite). One per process.
 unsigned int* device_flag();
 

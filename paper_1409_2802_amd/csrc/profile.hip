@@ -1,0 +1,96 @@
+// Stage profiler: optional HIP events around every stage launch, recorded on
+// the stream the stage runs on, accumulated per stage on read.
+#include <mutex>
+
+#include "ffc_internal.h"
+
+namespace ffc {
+namespace {
+
+struct Pending {
+  int stage;
+  hipEvent_t start, stop;
+};
+
+std::mutex g_mu;
+bool g_on = false;
+std::vector<hipEvent_t> g_free;   // recycled events
+
+hipEvent_t get_event() {
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (!g_free.empty()) {
+      hipEvent_t e = g_free.back();
+      g_free.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e{};
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+std::vector<Pending> g_pending;
+double g_ms[FFC_NUM_STAGES] = {};
+int64_t g_launches[FFC_NUM_STAGES] = {};
+
+}  // namespace
+
+bool profiling() { return g_on; }
+
+StageTimer::StageTimer(int stage, hipStream_t st) : stage_(stage), st_(st) {
+  if (!g_on) return;
+  start_ = get_event();
+  stop_ = get_event();
+  if (!start_ || !stop_) return;
+  active_ = hipEventRecord(start_, st_) == hipSuccess;
+}
+
+StageTimer::~StageTimer() {
+  if (!active_) return;
+  (void)hipEventRecord(stop_, st_);
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_pending.push_back(Pending{stage_, start_, stop_});
+}
+
+}  // namespace ffc
+
+using namespace ffc;
+
+extern "C" {
+
+ffc_status ffc_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_on = on != 0;
+  return FFC_OK;
+}
+
+ffc_status ffc_profile_read(double* ms_host, int64_t* launches_host, int32_t num_stages, int32_t reset) {
+  if (num_stages < 0) {
+    set_error("num_stages must be >= 0");
+    return FFC_ERR_INVALID_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_mu);
+  for (const Pending& p : g_pending) {
+    FFC_HIP_TRY(hipEventSynchronize(p.stop));
+    float ms = 0.f;
+    FFC_HIP_TRY(hipEventElapsedTime(&ms, p.start, p.stop));
+    g_ms[p.stage] += ms;
+    g_launches[p.stage] += 1;
+    g_free.push_back(p.start);
+    g_free.push_back(p.stop);
+  }
+  g_pending.clear();
+  for (int i = 0; i < num_stages && i < FFC_NUM_STAGES; ++i) {
+    if (ms_host) ms_host[i] = g_ms[i];
+    if (launches_host) launches_host[i] = g_launches[i];
+  }
+  if (reset) {
+    for (int i = 0; i < FFC_NUM_STAGES; ++i) {
+      g_ms[i] = 0.0;
+      g_launches[i] = 0;
+    }
+  }
+  return FFC_OK;
+}
+
+}  // extern "C"

@@ -8,9 +8,10 @@
 // and a uniform integer in [0, j] is the high 64 bits of u64 * (j + 1).
 // Candidate t maps to tree position t (t < begin) or t + node size.
 //
-// One wavefront per node: each Floyd step is computed redundantly by all 64
-// lanes (no broadcast needed), set membership is a ballot over the set held
-// in LDS, and the chosen set is sorted with an LDS bitonic network.
+// Two kernels implement the same draw. The bitmap kernel (used whenever the
+// bitmap of the complement fits the LDS budget) keeps the chosen set as bits;
+// the general kernel keeps it as a list scanned by one wavefront with a
+// ballot, then sorts it with an LDS bitonic network.
 #include <climits>
 
 #include "ffc_internal.h"
@@ -71,6 +72,77 @@ __global__ void k_sample_rows(const int32_t* __restrict__ nb, const int32_t* __r
   if (lane == 0) nrows[node] = s;
 }
 
+// Bitmap variant (complement size M up to 32 * kMaxBitmapWords): the chosen
+// set lives as a bitmap of {0..M-1} in LDS, so membership is one bit test and
+// the ascending order falls out of a prefix count over the words. The Floyd
+// values t_j are produced in parallel, then one lane applies the sequential
+// insert rule (j replaces t_j when t_j is already taken).
+constexpr int kMaxBitmapWords = 12288;   // 48 KB of LDS -> M <= 393216
+constexpr int kBitmapThreads = 256;
+
+__global__ void __launch_bounds__(kBitmapThreads)
+k_sample_rows_bitmap(const int32_t* __restrict__ nb, const int32_t* __restrict__ ne, int64_t N, int first, int s,
+                     int s_cap, uint64_t seed, int32_t* __restrict__ rows, int32_t* __restrict__ nrows) {
+  extern __shared__ unsigned int bits[];            // nwords bitmap words, then s ints of t values
+  __shared__ int wsum[kBitmapThreads];
+  const int node = first + blockIdx.x;
+  const int tid = threadIdx.x;
+  const int b = nb[node], e = ne[node];
+  const int M = (int)(N - (e - b));
+  int32_t* out = rows + (int64_t)node * s_cap;
+  if (s >= M) {
+    for (int i = tid; i < M; i += kBitmapThreads) out[i] = i < b ? i : i + (e - b);
+    if (tid == 0) nrows[node] = M;
+    return;
+  }
+  const int nwords = (M + 31) / 32;
+  int* tv = reinterpret_cast<int*>(bits + nwords);
+  for (int w = tid; w < nwords; w += kBitmapThreads) bits[w] = 0u;
+  const uint64_t stream = (uint64_t)(uint32_t)node << 32;
+  for (int q = tid; q < s; q += kBitmapThreads) {
+    const int64_t j = (int64_t)(M - s) + q;
+    const uint64_t u = splitmix_first(seed ^ stream ^ (uint64_t)j);
+    tv[q] = (int)__umul64hi(u, (uint64_t)(j + 1));
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int q = 0; q < s; ++q) {
+      int t = tv[q];
+      const unsigned int m = 1u << (t & 31);
+      if (bits[t >> 5] & m) t = M - s + q;
+      bits[t >> 5] |= 1u << (t & 31);
+    }
+  }
+  __syncthreads();
+  // Ascending extraction: each thread owns a contiguous range of words.
+  const int per = (nwords + kBitmapThreads - 1) / kBitmapThreads;
+  const int w0 = tid * per, w1 = min(nwords, w0 + per);
+  int cnt = 0;
+  for (int w = w0; w < w1; ++w) cnt += __popc(bits[w]);
+  wsum[tid] = cnt;
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int i = 0; i < kBitmapThreads; ++i) {
+      const int c = wsum[i];
+      wsum[i] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+  int pos = wsum[tid];
+  for (int w = w0; w < w1; ++w) {
+    unsigned int word = bits[w];
+    while (word) {
+      const int bit = __ffs(word) - 1;
+      word &= word - 1;
+      const int t = w * 32 + bit;
+      out[pos++] = t < b ? t : t + (e - b);
+    }
+  }
+  if (tid == 0) nrows[node] = s;
+}
+
 __global__ void k_level_columns(const int32_t* __restrict__ nb, const int32_t* __restrict__ ne, int first,
                                 int leaves, int n_cap, int r_cap, const int32_t* __restrict__ rank,
                                 const int32_t* __restrict__ skel, int32_t* __restrict__ cols,
@@ -94,10 +166,17 @@ __global__ void k_level_columns(const int32_t* __restrict__ nb, const int32_t* _
 
 ffc_status launch_sample_rows(const ffc_tree* t, ffc_skel* sk, int first, int count, int s, uint64_t seed,
                               hipStream_t st) {
+  const int64_t nwords = (t->N + 31) / 32;
+  const size_t lds = (size_t)nwords * sizeof(unsigned int) + (size_t)s * sizeof(int);
+  if (nwords <= kMaxBitmapWords && lds <= 64 * 1024) {
+    hipLaunchKernelGGL(k_sample_rows_bitmap, dim3(count), dim3(kBitmapThreads), lds, st, t->begin.ptr, t->end.ptr,
+                       t->N, first, s, sk->s_cap, seed, sk->rows.ptr, sk->nrows.ptr);
+    FFC_LAUNCH_CHECK("k_sample_rows_bitmap");
+    return FFC_OK;
+  }
   int sort_n = 1;
   while (sort_n < s) sort_n <<= 1;
-  const size_t lds = (size_t)sort_n * sizeof(int);
-  hipLaunchKernelGGL(k_sample_rows, dim3(count), dim3(64), lds, st, t->begin.ptr, t->end.ptr, t->N, first, s,
+  hipLaunchKernelGGL(k_sample_rows, dim3(count), dim3(64), (size_t)sort_n * sizeof(int), st, t->begin.ptr, t->end.ptr, t->N, first, s,
                      sk->s_cap, sort_n, seed, sk->rows.ptr, sk->nrows.ptr);
   FFC_LAUNCH_CHECK("k_sample_rows");
   return FFC_OK;

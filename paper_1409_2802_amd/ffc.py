@@ -27,8 +27,10 @@ EXPORTS = [
     "ffc_build_tree", "ffc_build_partition", "ffc_tree_info", "ffc_tree_arrays",
     "ffc_skeletonize_nodes", "ffc_evaluate_sum", "ffc_direct_sum", "ffc_sampled_block",
     "ffc_interp_decomp", "ffc_skel_node", "ffc_skel_stats", "ffc_check_device",
-    "ffc_free_tree", "ffc_free_skel", "ffc_last_error",
+    "ffc_free_tree", "ffc_free_skel", "ffc_last_error", "ffc_profile_enable", "ffc_profile_read",
 ]
+
+STAGES = ["tree", "sample", "columns", "kblock", "cpqr", "skel", "upward", "evaluate", "direct"]
 
 
 class FfcError(RuntimeError):
@@ -79,6 +81,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ffc_skel_node": [P, I32, P, P, P, P, P, P, P],
         "ffc_skel_stats": [P, ctypes.POINTER(StatsC)],
         "ffc_check_device": [P],
+        "ffc_profile_enable": [I32],
+        "ffc_profile_read": [P, P, I32, I32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -288,3 +292,16 @@ def interp_decomp(A, tol: float, max_rank: int, stream=None):
 def check_device(stream=None) -> None:
     """Raise FfcError(FFC_ERR_NONFINITE) if a kernel value was not finite."""
     _check(load_library().ffc_check_device(_stream(stream)))
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(load_library().ffc_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True) -> dict:
+    """Accumulated milliseconds and launch counts per stage since the last reset."""
+    n = len(STAGES)
+    ms = np.zeros(n, dtype=np.float64)
+    cnt = np.zeros(n, dtype=np.int64)
+    _check(load_library().ffc_profile_read(ms.ctypes.data, cnt.ctypes.data, n, 1 if reset else 0))
+    return {name: {"ms": float(ms[i]), "launches": int(cnt[i])} for i, name in enumerate(STAGES)}
