@@ -165,7 +165,9 @@ ffc_status ffc_sampled_block(const ffc_tree* t, const ffc_kernel* k, int32_t pre
  * rank_dev[b]; piv_dev[b * n + k] = column of the k-th pivot; P_dev[b *
  * max_rank * n + i * n + j] = P (rank x n, row-major, original column order);
  * rows i >= rank are left untouched. Same QR and solve as the skeletonization
- * (Appendix 6.1; Theorem thm_compute_id). Errors: s, n < 1, max_rank < 1. */
+ * (Appendix 6.1; Theorem thm_compute_id). piv_dev entries k >= rank list the
+ * remaining columns. Returns after the stream has finished the work (the call
+ * owns temporary device scratch). Errors: s, n < 1, max_rank < 1. */
 ffc_status ffc_interp_decomp(double* A_dev, int32_t batch, int32_t s, int32_t n, double tol,
                              int32_t max_rank, int32_t* rank_dev, int32_t* piv_dev,
                              double* P_dev, void* stream);
@@ -191,7 +193,9 @@ typedef struct {
 ffc_status ffc_skel_stats(const ffc_skel* sk, ffc_stats* out);
 
 /* Synchronizes `stream` and reports (then clears) the device error flag:
- * FFC_ERR_NONFINITE if a kernel value was not finite since the last check. */
+ * FFC_ERR_NONFINITE if a kernel value was not finite since the last check,
+ * FFC_ERR_HIP if a bounded wait inside the QR kernel gave up (its results
+ * are then invalid). */
 ffc_status ffc_check_device(void* stream);
 
 /* Stage profiler (tracing). When enabled, every stage launch is bracketed by

@@ -322,7 +322,9 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
       bt.p_ld = n_cap;
       {
         StageTimer tm(FFC_STAGE_CPQR, st);
-        FFC_TRY(launch_interp_decomp(bt, count, st));
+        bool used = false;
+        FFC_TRY(launch_interp_decomp_coop(bt, count, sk->qr_scratch, st, used));
+        if (!used) FFC_TRY(launch_interp_decomp(bt, count, st));
       }
       {
         StageTimer tm(FFC_STAGE_SKEL, st);
@@ -421,7 +423,13 @@ ffc_status ffc_interp_decomp(double* A_dev, int32_t batch, int32_t s, int32_t n,
   bt.P = P_dev;
   bt.p_stride = (int64_t)max_rank * n;
   bt.p_ld = n;
-  return launch_interp_decomp(bt, batch, (hipStream_t)stream);
+  hipStream_t st = (hipStream_t)stream;
+  DevBuf<unsigned char> scratch;
+  bool used = false;
+  FFC_TRY(launch_interp_decomp_coop(bt, batch, scratch, st, used));
+  if (!used) FFC_TRY(launch_interp_decomp(bt, batch, st));
+  FFC_HIP_TRY(hipStreamSynchronize(st));   // the scratch is released on return
+  return FFC_OK;
 }
 
 ffc_status ffc_skel_node(const ffc_skel* sk, int32_t node, int32_t* rank, int32_t* n_cols, int32_t* n_rows,
@@ -482,6 +490,7 @@ ffc_status ffc_check_device(void* stream) {
   FFC_HIP_TRY(hipMemcpy(&h, f, sizeof(h), hipMemcpyDeviceToHost));
   if (h) {
     FFC_HIP_TRY(hipMemset(f, 0, sizeof(unsigned int)));
+    if (h & 2u) return fail(FFC_ERR_HIP, "a QR workgroup group barrier timed out (results are invalid)");
     return fail(FFC_ERR_NONFINITE, "a kernel evaluation was not finite");
   }
   return FFC_OK;

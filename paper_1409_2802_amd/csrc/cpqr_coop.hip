@@ -1,0 +1,524 @@
+// Register-resident batched column-pivoted QR (the ID of Section 2.1.3 /
+// Appendix 6.1), distributed over a group of workgroups per block.
+//
+// Right-looking Householder QR with column pivoting re-reads the whole
+// trailing block at every pivot step, so with the block in HBM it is bound by
+// memory traffic. Here each block (s <= 512 rows) is spread over G
+// workgroups: a workgroup owns 8 wavefronts x 8 columns, each column held by
+// 16 lanes with up to 32 rows per lane in VGPRs for the whole factorization.
+// One pivot step then needs no block traffic at all:
+//   1. every workgroup reads the winning candidate column (published at the
+//      end of the previous step) and forms the reflector v, beta = 2 / v^T v;
+//   2. it applies the reflector to its own non-pivot columns in registers and
+//      recomputes their trailing norms exactly (rows k+1..s-1);
+//   3. it publishes its best column (norm, original index, values) to a
+//      double-buffered slot and arrives at the group barrier;
+//   4. after the barrier all workgroups pick the same global best (largest
+//      norm, ties to the smaller original column) and apply the same stop rule.
+// The pivot column is frozen in place (its rows 0..k-1 are R(0:k, k), row k
+// gets alpha), so no columns are swapped; the pivot order is recorded.
+//
+// Scheduling: the groups of a level form a flat task list; a persistent grid
+// of co-resident workgroups takes tasks w, w + grid, ... in order. A group's
+// tasks are consecutive, so the smallest unfinished task always has all its
+// members able to reach it: no deadlock as long as G <= grid and the whole
+// grid is resident (guaranteed by the cooperative launch). Barrier waits are
+// bounded; a timeout raises bit 1 of the device flag and the workgroup
+// abandons its remaining work, so every wave exits.
+#include <climits>
+
+#include "ffc_internal.h"
+
+namespace ffc {
+namespace {
+
+constexpr int NT = 512;
+constexpr int NWV = NT / 64;
+constexpr unsigned int kSpinLimit = 1u << 21;   // ~1 us per poll -> about 2 s
+constexpr int kCtrStride = 64;   // one 256-byte line per group counter (no false sharing)
+
+struct CoopArgs {
+  double* A;
+  int64_t a_stride;
+  int lda;
+  const int32_t* s_arr;
+  const int32_t* n_arr;
+  int s_uniform, n_uniform;
+  int count;
+  double tol;
+  int max_rank;
+  int32_t* rank;
+  int32_t* piv;
+  int64_t piv_stride;
+  int32_t* task_start;       // [count + 1]
+  unsigned int* counters;    // [count]
+  double* slots;             // [count][2][gmax][s_max + 2]
+  int gmax;
+  int s_max;
+  int cols_per_wg;
+  unsigned int* flag;
+};
+
+struct Best {
+  double v;
+  int orig;
+};
+
+__device__ inline bool better(double v, int o, double bv, int bo) { return v > bv || (v == bv && o < bo); }
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Group tasks per block: G_b = ceil(n_b / cols_per_wg) (at least 1); prefix
+// sums into task_start; counters cleared. One workgroup.
+__global__ void k_coop_tasks(CoopArgs ca) {
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int b = 0; b < ca.count; ++b) {
+      ca.task_start[b] = acc;
+      const int n = ca.n_arr ? ca.n_arr[b] : ca.n_uniform;
+      acc += max(1, (n + ca.cols_per_wg - 1) / ca.cols_per_wg);
+    }
+    ca.task_start[ca.count] = acc;
+  }
+  for (int b = threadIdx.x; b < ca.count; b += blockDim.x) ca.counters[(int64_t)b * kCtrStride] = 0u;
+}
+
+__device__ inline double* slot_ptr(const CoopArgs& ca, int b, int buf, int g) {
+  return ca.slots + (((int64_t)b * 2 + buf) * ca.gmax + g) * (int64_t)(ca.s_max + 2);
+}
+
+// Slot traffic uses relaxed agent-scope atomic loads and stores: they are
+// performed coherently across the chiplets' L2 caches, so no cache-wide
+// fence (L2 write-back / invalidate) is needed around the barrier.
+__device__ inline void slot_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double slot_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Arrive and wait until `target` arrivals; false on timeout. Every wave first
+// waits for its own slot stores to complete, so they precede the arrival.
+__device__ inline bool group_barrier(unsigned int* ctr, unsigned int target, unsigned int* flag, int* s_ok) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned int spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kSpinLimit) {
+        atomicOr(flag, 2u);
+        ok = 0;
+        break;
+      }
+    }
+    *s_ok = ok;
+  }
+  __syncthreads();
+  return *s_ok != 0;
+}
+
+// All-reduce of a double within each row of 16 lanes by DPP moves (quad
+// swaps, half-row mirror, row mirror). Every step adds two values in the same
+// order on both partners, so all 16 lanes end with bitwise-identical sums.
+template <int CTRL>
+__device__ inline double dpp_mov(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double row16_sum(double x) {
+  x += dpp_mov<0xB1>(x);    // quad_perm [1,0,3,2]
+  x += dpp_mov<0x4E>(x);    // quad_perm [2,3,0,1]
+  x += dpp_mov<0x141>(x);   // row_half_mirror
+  x += dpp_mov<0x140>(x);   // row_mirror
+  return x;
+}
+
+// Register layout: a wavefront is 4 lane groups of 16 lanes; a lane group owns
+// CS columns and each of its lanes keeps RL rows (i = lane16 + 16 m) of them,
+// so a column's dot products and norms are 16-lane DPP reductions.
+template <int RL>
+__global__ void __launch_bounds__(NT) k_cpqr_coop(CoopArgs ca) {
+  constexpr int CS = 64 / RL;          // columns per lane group
+  constexpr int CPW = 4 * CS;          // columns per wavefront
+  __shared__ Best wb[NWV];
+  __shared__ int s_ok;
+  extern __shared__ double cand[];     // gmax x (s_max + 2): staged candidates of the group
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int grp = lane >> 4, l16 = lane & 15;
+  const int T = ca.task_start[ca.count];
+  for (int task = blockIdx.x; task < T; task += gridDim.x) {
+    // Block of this task: largest b with task_start[b] <= task.
+    int lo = 0, hi = ca.count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (ca.task_start[mid] <= task) lo = mid; else hi = mid - 1;
+    }
+    const int b = lo;
+    const int g = task - ca.task_start[b];
+    const int G = ca.task_start[b + 1] - ca.task_start[b];
+    const int s = ca.s_arr ? ca.s_arr[b] : ca.s_uniform;
+    const int n = ca.n_arr ? ca.n_arr[b] : ca.n_uniform;
+    double* A = ca.A + (int64_t)b * ca.a_stride;
+    unsigned int* ctr = ca.counters + (int64_t)b * kCtrStride;
+    const int col0 = g * ca.cols_per_wg + w * CPW + grp * CS;   // this lane group's first column
+
+    double a[CS][RL];
+#pragma unroll
+    for (int c = 0; c < CS; ++c)
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        const int i = l16 + 16 * m, j = col0 + c;
+        a[c][m] = (i < s && j < n) ? A[(int64_t)j * ca.lda + i] : 0.0;
+      }
+    unsigned int done = 0u;   // bit c: column col0 + c is a frozen pivot
+
+    // Publish this workgroup's best column (trailing norm over rows >= k) into buffer buf.
+    auto publish = [&](int k, int buf) {
+      Best best{-1.0, INT_MAX};
+      int bestc = -1;
+#pragma unroll
+      for (int c = 0; c < CS; ++c) {
+        double nrm = 0.0;
+#pragma unroll
+        for (int m = 0; m < RL; ++m) {
+          const int i = l16 + 16 * m;
+          const double x = (i >= k) ? a[c][m] : 0.0;
+          nrm = fma(x, x, nrm);
+        }
+        nrm = row16_sum(nrm);
+        const int j = col0 + c;
+        if (j < n && !(done & (1u << c)) && better(nrm, j, best.v, best.orig)) {
+          best = Best{nrm, j};
+          bestc = c;
+        }
+      }
+      // Best of the 4 lane groups of the wavefront (same result in every lane).
+      Best wbst{__shfl(best.v, 0, 64), __shfl(best.orig, 0, 64)};
+      int wg_owner = 0;
+#pragma unroll
+      for (int q = 1; q < 4; ++q) {
+        const Best o{__shfl(best.v, q * 16, 64), __shfl(best.orig, q * 16, 64)};
+        if (better(o.v, o.orig, wbst.v, wbst.orig)) { wbst = o; wg_owner = q; }
+      }
+      if (lane == 0) wb[w] = wbst;
+      __syncthreads();
+      Best gb = wb[0];
+      int gw = 0;
+      for (int i = 1; i < NWV; ++i)
+        if (better(wb[i].v, wb[i].orig, gb.v, gb.orig)) { gb = wb[i]; gw = i; }
+      double* sl = slot_ptr(ca, b, buf, g);
+      if (w == gw && grp == wg_owner && gb.orig != INT_MAX) {
+#pragma unroll
+        for (int c = 0; c < CS; ++c)
+          if (c == bestc)
+#pragma unroll
+            for (int m = 0; m < RL; ++m) {
+              const int i = l16 + 16 * m;
+              if (i < s) slot_store(sl + 2 + i, a[c][m]);
+            }
+      }
+      if (threadIdx.x == 0) {
+        slot_store(sl, gb.orig == INT_MAX ? -1.0 : gb.v);
+        slot_store(sl + 1, (double)(gb.orig == INT_MAX ? -1 : gb.orig));
+      }
+    };
+    // Stage the G candidates of buffer buf (headers and columns) into LDS with
+    // batched loads, then pick the global best (norm, column, owner).
+    auto select = [&](int buf, double& nv, int& orig, int& owner) {
+      const int stride = ca.s_max + 2;
+      const int total = G * stride;
+      const double* base = slot_ptr(ca, b, buf, 0);
+      constexpr int BATCH = 8;
+      for (int e0 = 0; e0 < total; e0 += NT * BATCH) {
+        double tmp[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+          const int e = e0 + u * NT + (int)threadIdx.x;
+          const int off = e % stride;
+          tmp[u] = (e < total && off < s + 2) ? slot_load(base + e) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+          const int e = e0 + u * NT + (int)threadIdx.x;
+          if (e < total) cand[e] = tmp[u];
+        }
+      }
+      __syncthreads();
+      nv = -1.0; orig = INT_MAX; owner = -1;
+      for (int q = 0; q < G; ++q) {
+        const double v = cand[q * stride];
+        const int o = (int)cand[q * stride + 1];
+        if (o >= 0 && better(v, o, nv, orig)) { nv = v; orig = o; owner = q; }
+      }
+    };
+
+    publish(0, 0);
+    bool alive = group_barrier(ctr, (unsigned)G, ca.flag, &s_ok);
+    double nv;
+    int porig, powner;
+    if (alive) select(0, nv, porig, powner);
+    const int kmax = min(min(s, n), ca.max_rank);
+    const double rho0 = (alive && porig != INT_MAX) ? sqrt(nv) : 0.0;
+    int k = 0;
+    for (; alive && k < kmax; ++k) {
+      if (porig == INT_MAX) break;
+      const double rho = sqrt(nv);
+      if (rho == 0.0 || rho < ca.tol * rho0) break;
+      const double* x = cand + powner * (ca.s_max + 2) + 2;   // staged winner
+      const double xk = x[k];
+      const double alpha = xk != 0.0 ? -copysign(rho, xk) : -rho;
+      double v[RL];
+      double part = 0.0;
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        const int i = l16 + 16 * m;
+        v[m] = (i >= k && i < s) ? (i == k ? xk - alpha : x[i]) : 0.0;
+        part = fma(v[m], v[m], part);
+      }
+      // Every lane group holds all rows, so the reflector norm is a 16-lane sum.
+      const double vv = row16_sum(part);
+      const double beta = vv > 0.0 ? 2.0 / vv : 0.0;
+      // Freeze the pivot column: row k becomes alpha.
+      if (g == powner) {
+#pragma unroll
+        for (int c = 0; c < CS; ++c)
+          if (col0 + c == porig) {
+            done |= 1u << c;
+#pragma unroll
+            for (int m = 0; m < RL; ++m)
+              if (l16 + 16 * m == k) a[c][m] = alpha;
+          }
+        if (threadIdx.x == 0) ca.piv[(int64_t)b * ca.piv_stride + k] = porig;
+      }
+      // Apply the reflector to the non-pivot columns (a frozen or absent
+      // column gets a zero coefficient, which leaves it unchanged).
+#pragma unroll
+      for (int c = 0; c < CS; ++c) {
+        double dot = 0.0;
+#pragma unroll
+        for (int m = 0; m < RL; ++m) dot = fma(v[m], a[c][m], dot);
+        dot = row16_sum(dot);
+        const double coef = (col0 + c < n && !(done & (1u << c))) ? dot * beta : 0.0;
+#pragma unroll
+        for (int m = 0; m < RL; ++m) a[c][m] = fma(-v[m], coef, a[c][m]);
+      }
+      publish(k + 1, (k + 1) & 1);
+      alive = group_barrier(ctr, (unsigned)(G * (k + 2)), ca.flag, &s_ok);
+      if (alive) select((k + 1) & 1, nv, porig, powner);
+    }
+    if (!alive) return;   // timed out: the device flag reports it
+    // Write the columns back in place: rows 0..k-1 of every column hold R.
+#pragma unroll
+    for (int c = 0; c < CS; ++c)
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {
+        const int i = l16 + 16 * m, j = col0 + c;
+        if (i < s && j < n) A[(int64_t)j * ca.lda + i] = a[c][m];
+      }
+    if (g == 0 && threadIdx.x == 0) ca.rank[b] = k;
+  }
+}
+
+// T = R11^{-1} R12 and P for blocks factored in place without swaps: column
+// piv[l] holds R(0:l+1, l); every other column j holds R(0:r, j) in rows 0..r-1.
+struct SolveArgs {
+  int r_max;
+  double* A;
+  int64_t a_stride;
+  int lda;
+  const int32_t* n_arr;
+  int n_uniform;
+  int n_max;
+  const int32_t* rank;
+  int32_t* piv;
+  int64_t piv_stride;
+  double* P;
+  int64_t p_stride;
+  int p_ld;
+};
+
+constexpr int SB = 32;   // rows per solve block
+
+// One workgroup per block. T = R11^{-1} R12 by blocked back substitution:
+// R11 rows [kb, kb + SB) are staged in LDS, each thread owns one right-hand
+// column and keeps that block of its solution in registers, first removing
+// the contribution of the already solved rows below, then solving the SB x SB
+// triangle.
+__global__ void __launch_bounds__(NT) k_id_solve(SolveArgs sa) {
+  extern __shared__ double smd[];
+  const int b = blockIdx.x;
+  const int n = sa.n_arr ? sa.n_arr[b] : sa.n_uniform;
+  const int r = sa.rank[b];
+  double* Rb = smd;                                             // SB x r_max
+  int* pos = reinterpret_cast<int*>(Rb + (size_t)SB * sa.r_max);  // n_max: pivot position or -1
+  int* pv = pos + sa.n_max;                                     // n_max: pivot columns in order
+  int* np = pv + sa.n_max;                                      // n_max: non-pivot columns
+  double* A = sa.A + (int64_t)b * sa.a_stride;
+  int32_t* piv = sa.piv + (int64_t)b * sa.piv_stride;
+  for (int j = threadIdx.x; j < n; j += NT) pos[j] = -1;
+  __syncthreads();
+  for (int l = threadIdx.x; l < r; l += NT) {
+    const int j = piv[l];
+    pv[l] = j;
+    pos[j] = l;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {   // remaining columns, ascending, after the pivots
+    int q = 0;
+    for (int j = 0; j < n; ++j)
+      if (pos[j] < 0) {
+        np[q] = j;
+        piv[r + q] = j;
+        ++q;
+      }
+  }
+  __syncthreads();
+  const int nnp = n - r;
+  const int rs = sa.r_max;
+  for (int c0 = 0; c0 < nnp; c0 += NT) {
+    const int cidx = c0 + (int)threadIdx.x;
+    double* col = cidx < nnp ? A + (int64_t)np[cidx] * sa.lda : nullptr;
+    for (int kb = ((r - 1) / SB) * SB; kb >= 0 && r > 0; kb -= SB) {
+      __syncthreads();
+      // Stage R(kb + ii, l) for l in [kb, r): column pv[l] of A, row kb + ii.
+      const int width = r - kb;
+      for (int e = threadIdx.x; e < SB * width; e += NT) {
+        const int l = kb + e / SB, ii = e % SB;
+        Rb[ii * rs + (l - kb)] = (kb + ii < r) ? A[(int64_t)pv[l] * sa.lda + kb + ii] : 0.0;
+      }
+      __syncthreads();
+      if (col) {
+        double t[SB];
+#pragma unroll
+        for (int ii = 0; ii < SB; ++ii) t[ii] = (kb + ii < r) ? col[kb + ii] : 0.0;
+        for (int l = kb + SB; l < r; ++l) {
+          const double tl = col[l];
+#pragma unroll
+          for (int ii = 0; ii < SB; ++ii) t[ii] = fma(-Rb[ii * rs + (l - kb)], tl, t[ii]);
+        }
+#pragma unroll
+        for (int ii = SB - 1; ii >= 0; --ii) {
+          if (kb + ii < r) {
+#pragma unroll
+            for (int jj = ii + 1; jj < SB; ++jj)
+              if (kb + jj < r) t[ii] = fma(-Rb[ii * rs + jj], t[jj], t[ii]);
+            t[ii] /= Rb[ii * rs + ii];
+          }
+        }
+#pragma unroll
+        for (int ii = 0; ii < SB; ++ii)
+          if (kb + ii < r) col[kb + ii] = t[ii];
+      }
+    }
+  }
+  __syncthreads();
+  double* P = sa.P + (int64_t)b * sa.p_stride;
+  for (int e = threadIdx.x; e < r * n; e += NT) {
+    const int i = e / n, j = e % n;
+    const int pj = pos[j];
+    P[(int64_t)i * sa.p_ld + j] = pj >= 0 ? (pj == i ? 1.0 : 0.0) : A[(int64_t)j * sa.lda + i];
+  }
+}
+
+int resident_grid(const void* kern, size_t lds) {
+  int dev = 0, nb = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, lds) != hipSuccess) return 0;
+  return nb * cus;
+}
+
+template <int R>
+ffc_status launch_r(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hipStream_t st, bool& used) {
+  constexpr int CPW = 4 * (64 / R);   // columns per wavefront
+  const int cols_per_wg = CPW * NWV;
+  const int gmax = std::max(1, (bt.n_max + cols_per_wg - 1) / cols_per_wg);
+  const void* kern = reinterpret_cast<const void*>(&k_cpqr_coop<R>);
+  const size_t lds = (size_t)gmax * (bt.s_max + 2) * sizeof(double);
+  if (lds > 150 * 1024) return FFC_OK;   // candidates do not fit in LDS: caller falls back
+  if (lds > 64 * 1024)
+    FFC_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const int grid_cap = resident_grid(kern, lds);
+  if (grid_cap < gmax) return FFC_OK;   // a group would not fit: caller falls back
+  const size_t slot_doubles = (size_t)batch * 2 * gmax * (bt.s_max + 2);
+  const size_t bytes = slot_doubles * sizeof(double) + ((size_t)batch + 1) * sizeof(int32_t) + 256 +
+                       (size_t)batch * kCtrStride * sizeof(unsigned int);
+  if (scratch.count < bytes) FFC_TRY(scratch.alloc(bytes));
+  CoopArgs ca{};
+  ca.A = bt.A;
+  ca.a_stride = bt.a_stride;
+  ca.lda = bt.lda;
+  ca.s_arr = bt.s_arr;
+  ca.n_arr = bt.n_arr;
+  ca.s_uniform = bt.s_uniform;
+  ca.n_uniform = bt.n_uniform;
+  ca.count = batch;
+  ca.tol = bt.tol;
+  ca.max_rank = bt.max_rank;
+  ca.rank = bt.rank;
+  ca.piv = bt.piv;
+  ca.piv_stride = bt.piv_stride;
+  ca.slots = reinterpret_cast<double*>(scratch.ptr);
+  ca.task_start = reinterpret_cast<int32_t*>(ca.slots + slot_doubles);
+  {
+    // Counters start on a 256-byte boundary after the task table.
+    const uintptr_t p = reinterpret_cast<uintptr_t>(ca.task_start + batch + 1);
+    ca.counters = reinterpret_cast<unsigned int*>((p + 255) & ~uintptr_t(255));
+  }
+  ca.gmax = gmax;
+  ca.s_max = bt.s_max;
+  ca.cols_per_wg = cols_per_wg;
+  ca.flag = device_flag();
+  hipLaunchKernelGGL(k_coop_tasks, dim3(1), dim3(256), 0, st, ca);
+  FFC_LAUNCH_CHECK("k_coop_tasks");
+  const int upper_tasks = batch * gmax;
+  const int grid = std::min(grid_cap, upper_tasks);
+  void* args[] = {&ca};
+  FFC_HIP_TRY(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(NT), args, (unsigned int)lds, st));
+  SolveArgs sa{};
+  sa.A = bt.A;
+  sa.a_stride = bt.a_stride;
+  sa.lda = bt.lda;
+  sa.n_arr = bt.n_arr;
+  sa.n_uniform = bt.n_uniform;
+  sa.n_max = bt.n_max;
+  sa.rank = bt.rank;
+  sa.piv = bt.piv;
+  sa.piv_stride = bt.piv_stride;
+  sa.P = bt.P;
+  sa.p_stride = bt.p_stride;
+  sa.p_ld = bt.p_ld;
+  sa.r_max = std::max(1, std::min(bt.max_rank, std::min(bt.s_max, bt.n_max)));
+  const size_t slds = (size_t)SB * sa.r_max * sizeof(double) + 3 * (size_t)bt.n_max * sizeof(int);
+  if (slds > 64 * 1024)
+    FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_id_solve),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds));
+  hipLaunchKernelGGL(k_id_solve, dim3(batch), dim3(NT), slds, st, sa);
+  FFC_LAUNCH_CHECK("k_id_solve");
+  used = true;
+  return FFC_OK;
+}
+
+}  // namespace
+
+ffc_status launch_interp_decomp_coop(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hipStream_t st,
+                                     bool& used) {
+  used = false;
+  if (batch <= 0) return FFC_OK;
+  {
+    const int rmax = std::max(1, std::min(bt.max_rank, std::min(bt.s_max, bt.n_max)));
+    if ((size_t)SB * rmax * sizeof(double) + 3 * (size_t)bt.n_max * sizeof(int) > 150 * 1024) return FFC_OK;
+  }
+  if (bt.s_max <= 256) return launch_r<16>(bt, batch, scratch, st, used);
+  if (bt.s_max <= 512) return launch_r<32>(bt, batch, scratch, st, used);
+  return FFC_OK;
+}
+
+}  // namespace ffc

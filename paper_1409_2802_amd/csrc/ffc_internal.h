@@ -148,6 +148,7 @@ struct ffc_skel {
   ffc::DevBuf<double> P;                    // num_nodes x r_cap x n_cap
   ffc::DevBuf<double> qt;                   // num_nodes x r_cap (equivalent charges)
   ffc::DevBuf<double> work;                 // sampled blocks of the widest level
+  ffc::DevBuf<unsigned char> qr_scratch;    // group slots / counters of the QR kernel
   int32_t fallbacks = 0;
   hipStream_t last_stream = nullptr;
 };
@@ -201,6 +202,13 @@ struct IdBatch {
   int p_ld;               // leading dimension of P rows
 };
 ffc_status launch_interp_decomp(const IdBatch& b, int batch, hipStream_t st);
+
+// Register-resident variant (cpqr_coop.hip) for s <= 512: sets used = false
+// (and launches nothing) when a block does not fit, so the caller can fall
+// back to launch_interp_decomp. scratch grows as needed and must stay alive
+// until the stream has passed the call.
+ffc_status launch_interp_decomp_coop(const IdBatch& b, int batch, DevBuf<unsigned char>& scratch, hipStream_t st,
+                                     bool& used);
 
 // Skeleton ids from pivots: skel[node][i] = cols[node][piv[node][i]] (cpqr.hip).
 ffc_status launch_skeleton_ids(ffc_skel* sk, int first, int count, hipStream_t st);
