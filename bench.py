@@ -58,15 +58,27 @@ def make_inputs(w):
     return X, q
 
 
-def cpqr_flops(s, n, r):
-    """Householder QR to rank r of an s x n block plus the r x r triangular solve."""
-    return 4.0 * s * n * r - 2.0 * r * r * (s + n) + 4.0 * r ** 3 / 3.0 + r * r * max(n - r, 0)
+def qr_flops(s, n, r):
+    """Householder QR of an s x n block stopped at rank r (pivoting is free)."""
+    return max(0.0, 4.0 * s * n * r - 2.0 * r * r * (s + n) + 4.0 * r ** 3 / 3.0)
 
 
-def cpqr_bytes(s, n, r):
-    """One read + write of the trailing block per pivot step (block larger than on-chip storage)."""
-    k = np.arange(r, dtype=np.float64)
-    return float(np.sum(16.0 * (s - k) * (n - k))) + 8.0 * s * n
+def solve_flops(n, r):
+    """R11 T = R12 with R11 r x r upper triangular and n - r right-hand sides."""
+    return float(r) * r * max(n - r, 0)
+
+
+def stage_work(stage, nodes, tree_sizes, d, skel_evals, eval_evals):
+    """Algorithmic FP64 flops of one launch-sum of a stage over one step."""
+    if stage == "cpqr":
+        return sum(qr_flops(len(v["rows"]), len(v["cols"]), v["rank"]) for v in nodes.values())
+    if stage == "solve":
+        return sum(solve_flops(len(v["cols"]), v["rank"]) for v in nodes.values())
+    if stage == "kblock":
+        return skel_evals * 3.0 * d
+    if stage == "evaluate":
+        return eval_evals * 3.0 * d
+    return None
 
 
 def cpu_baseline(w, X, q, budget_s):
@@ -183,25 +195,18 @@ def main():
     dom = max((s for s in prof if s not in ("tree", "direct")), key=lambda s: prof[s]["ms"])
     launches_per_step = prof[dom]["launches"] / args.steps
     ms_per_launch = prof[dom]["ms"] / max(1, prof[dom]["launches"])
-    roof = None
-    if dom == "cpqr":
-        byts = sum(cpqr_bytes(len(nodes[a]["rows"]), len(nodes[a]["cols"]), nodes[a]["rank"])
-                   for a in nodes) / launches_per_step
-        roof = {"bound": "hbm", "achieved": byts / (ms_per_launch * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "traffic": None}
-    elif dom in ("kblock", "evaluate"):
-        ev = skel_evals if dom == "kblock" else eval_evals
-        flops = ev * 3.0 * w["d"] / launches_per_step
-        peak = FP64_PEAK_TFLOPS if prec == ffc.FP64 else FP32_PEAK_TFLOPS
-        roof = {"bound": "alu", "achieved": flops / (ms_per_launch * 1e-3) / 1e12, "peak": peak,
-                "unit": "TFLOP/s", "traffic": None}
-    else:
-        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": None}
-    if roof["achieved"] is not None:
+    flops = stage_work(dom, nodes, sizes, w["d"], skel_evals, eval_evals)
+    peak = FP64_PEAK_TFLOPS if prec == ffc.FP64 or dom in ("cpqr", "solve") else FP32_PEAK_TFLOPS
+    roof = {"bound": "alu", "achieved": None, "peak": peak, "unit": "TFLOP/s", "traffic": None}
+    if flops is not None and launches_per_step > 0:
+        roof["achieved"] = flops / launches_per_step / (ms_per_launch * 1e-3) / 1e12
         roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = dom
+    roof["kernel"] = {"cpqr": "k_cpqr_coop", "solve": "k_coop_tasks + k_id_solve", "kblock": "k_level_kblock",
+                      "evaluate": "k_evaluate", "sample": "k_sample_rows_bitmap", "upward": "k_upward"}.get(dom, dom)
+    roof["stage"] = dom
     roof["ms_per_launch"] = ms_per_launch
     roof["launches_per_step"] = launches_per_step
+    roof["flop_per_step"] = flops
 
     out = {
         "metric": METRIC, "value": nodes_per_s, "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,

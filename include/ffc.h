@@ -207,12 +207,13 @@ typedef enum {
   FFC_STAGE_SAMPLE = 1,    /* target-row sampling */
   FFC_STAGE_COLUMNS = 2,   /* per-level column lists */
   FFC_STAGE_KBLOCK = 3,    /* sampled kernel blocks K' */
-  FFC_STAGE_CPQR = 4,      /* pivoted QR + interpolation solve */
+  FFC_STAGE_CPQR = 4,      /* column-pivoted QR factorization kernel */
   FFC_STAGE_SKEL = 5,      /* skeleton ids */
   FFC_STAGE_UPWARD = 6,    /* equivalent charges */
   FFC_STAGE_EVALUATE = 7,  /* far + near field sums */
   FFC_STAGE_DIRECT = 8,    /* direct sums */
-  FFC_NUM_STAGES = 9
+  FFC_STAGE_SOLVE = 9,     /* QR set-up and interpolation solve R11 T = R12, P */
+  FFC_NUM_STAGES = 10
 } ffc_stage;
 ffc_status ffc_profile_enable(int32_t on);
 ffc_status ffc_profile_read(double* ms_host, int64_t* launches_host, int32_t num_stages, int32_t reset);

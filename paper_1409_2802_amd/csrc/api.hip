@@ -321,10 +321,12 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
       bt.p_stride = (int64_t)r_cap * n_cap;
       bt.p_ld = n_cap;
       {
-        StageTimer tm(FFC_STAGE_CPQR, st);
         bool used = false;
         FFC_TRY(launch_interp_decomp_coop(bt, count, sk->qr_scratch, st, used));
-        if (!used) FFC_TRY(launch_interp_decomp(bt, count, st));
+        if (!used) {
+          StageTimer tm(FFC_STAGE_CPQR, st);
+          FFC_TRY(launch_interp_decomp(bt, count, st));
+        }
       }
       {
         StageTimer tm(FFC_STAGE_SKEL, st);

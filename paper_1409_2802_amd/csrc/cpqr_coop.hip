@@ -476,12 +476,18 @@ ffc_status launch_r(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch
   ca.s_max = bt.s_max;
   ca.cols_per_wg = cols_per_wg;
   ca.flag = device_flag();
-  hipLaunchKernelGGL(k_coop_tasks, dim3(1), dim3(256), 0, st, ca);
-  FFC_LAUNCH_CHECK("k_coop_tasks");
+  {
+    StageTimer tm(FFC_STAGE_SOLVE, st);
+    hipLaunchKernelGGL(k_coop_tasks, dim3(1), dim3(256), 0, st, ca);
+    FFC_LAUNCH_CHECK("k_coop_tasks");
+  }
   const int upper_tasks = batch * gmax;
   const int grid = std::min(grid_cap, upper_tasks);
   void* args[] = {&ca};
-  FFC_HIP_TRY(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(NT), args, (unsigned int)lds, st));
+  {
+    StageTimer tm(FFC_STAGE_CPQR, st);
+    FFC_HIP_TRY(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(NT), args, (unsigned int)lds, st));
+  }
   SolveArgs sa{};
   sa.A = bt.A;
   sa.a_stride = bt.a_stride;
@@ -500,8 +506,11 @@ ffc_status launch_r(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch
   if (slds > 64 * 1024)
     FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_id_solve),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds));
-  hipLaunchKernelGGL(k_id_solve, dim3(batch), dim3(NT), slds, st, sa);
-  FFC_LAUNCH_CHECK("k_id_solve");
+  {
+    StageTimer tm(FFC_STAGE_SOLVE, st);
+    hipLaunchKernelGGL(k_id_solve, dim3(batch), dim3(NT), slds, st, sa);
+    FFC_LAUNCH_CHECK("k_id_solve");
+  }
   used = true;
   return FFC_OK;
 }

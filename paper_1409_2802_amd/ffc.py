@@ -30,7 +30,7 @@ EXPORTS = [
     "ffc_free_tree", "ffc_free_skel", "ffc_last_error", "ffc_profile_enable", "ffc_profile_read",
 ]
 
-STAGES = ["tree", "sample", "columns", "kblock", "cpqr", "skel", "upward", "evaluate", "direct"]
+STAGES = ["tree", "sample", "columns", "kblock", "cpqr", "skel", "upward", "evaluate", "direct", "solve"]
 
 
 class FfcError(RuntimeError):
