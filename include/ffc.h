@@ -155,7 +155,8 @@ ffc_status ffc_direct_sum(const double* Y_dev, int64_t m, const double* X_dev, i
 
 /* Sampled kernel block of a tree: out[j * s + i] = K(x_rows[i], x_cols[j]) for
  * tree positions rows_dev (s) and cols_dev (n), column-major s x n (the block
- * K' of Section 2.2, computed by the same kernels the skeletonization uses). */
+ * K' of Section 2.2, computed by the same kernels the skeletonization uses).
+ * precision: FFC_FP64 or FFC_FP32. */
 ffc_status ffc_sampled_block(const ffc_tree* t, const ffc_kernel* k, int32_t precision,
                              const int32_t* rows_dev, int32_t s, const int32_t* cols_dev,
                              int32_t n, double* out_dev, void* stream);

@@ -233,8 +233,6 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
     return fail(FFC_ERR_INVALID_ARG, "unknown sampler");
   if (o->sampler == FFC_SAMPLE_LEARNED)
     return fail(FFC_ERR_INVALID_ARG, "the learned sampler needs a proposal (not available in this build)");
-  if (o->precision == FFC_MIXED_BF16X3)
-    return fail(FFC_ERR_INVALID_ARG, "mixed bf16x3 precision is not available in this build");
   hipStream_t st = (hipStream_t)stream;
 
   const int64_t s_req = o->num_samples > 0 ? o->num_samples : 2 * (int64_t)o->max_rank;
@@ -353,8 +351,6 @@ ffc_status ffc_evaluate_sum(const ffc_tree* t, const ffc_skel* sk, const ffc_ker
     return fail(FFC_ERR_STATE, "skeleton set does not belong to this tree");
   FFC_TRY(check_kernel(k, t->d));
   FFC_TRY(check_precision(precision));
-  if (precision == FFC_MIXED_BF16X3)
-    return fail(FFC_ERR_INVALID_ARG, "mixed bf16x3 precision is not available in this build");
   hipStream_t st = (hipStream_t)stream;
   ffc_tree* tm = const_cast<ffc_tree*>(t);
   ffc_skel* sm = const_cast<ffc_skel*>(sk);
@@ -380,8 +376,6 @@ ffc_status ffc_direct_sum(const double* Y_dev, int64_t m, const double* X_dev, i
     return fail(FFC_ERR_INVALID_ARG, "NULL pointer with nonzero size");
   FFC_TRY(check_kernel(k, d));
   FFC_TRY(check_precision(precision));
-  if (precision == FFC_MIXED_BF16X3)
-    return fail(FFC_ERR_INVALID_ARG, "mixed bf16x3 precision is not available in this build");
   if (!device_flag()) return fail(FFC_ERR_HIP, "cannot allocate the device flag");
   StageTimer timer(FFC_STAGE_DIRECT, (hipStream_t)stream);
   return launch_direct_sum(Y_dev, m, X_dev, n, d, make_kparams(*k, d), precision, q_dev, u_dev, (hipStream_t)stream);
@@ -396,7 +390,7 @@ ffc_status ffc_sampled_block(const ffc_tree* t, const ffc_kernel* k, int32_t pre
   FFC_TRY(check_kernel(k, t->d));
   FFC_TRY(check_precision(precision));
   if (precision == FFC_MIXED_BF16X3)
-    return fail(FFC_ERR_INVALID_ARG, "mixed bf16x3 precision is not available in this build");
+    return fail(FFC_ERR_INVALID_ARG, "ffc_sampled_block supports FFC_FP64 and FFC_FP32 only");
   if (s == 0 || n == 0) return FFC_OK;
   return launch_sampled_block(t, make_kparams(*k, t->d), precision, rows_dev, s, cols_dev, n, out_dev,
                               (hipStream_t)stream);

@@ -221,6 +221,16 @@ ffc_status launch_charges_to_tree(ffc_tree* t, const double* q, hipStream_t st);
 ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision,
                            double* u, double* u_far, hipStream_t st);
 
+// Mixed-precision (bf16 hi/lo Gram on matrix cores) variants of the sampled
+// blocks, the evaluation and the direct sum for the Gaussian and polynomial
+// kernels (gram_mfma.hip).
+ffc_status launch_level_kblock_mixed(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int first, int count,
+                                     double* A, hipStream_t st);
+ffc_status launch_evaluate_mixed(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, double* u, double* u_far,
+                                 hipStream_t st);
+ffc_status launch_direct_mixed(const double* Y, int64_t m, const double* X, int64_t n, int d, const KParams& kp,
+                               const double* q, double* u, hipStream_t st);
+
 // Direct sum (kblock.hip).
 ffc_status launch_direct_sum(const double* Y, int64_t m, const double* X, int64_t n, int d, const KParams& kp,
                              int precision, const double* q, double* u, hipStream_t st);

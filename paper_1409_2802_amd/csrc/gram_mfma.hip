@@ -1,0 +1,345 @@
+// Mixed-precision kernel tiles on matrix cores (FFC_MIXED_BF16X3).
+//
+// Distances in high dimension are Gram contractions: ||y - x||^2 =
+// ||y||^2 + ||x||^2 - 2 y.x. Coordinates are first centred on a common point
+// (the node centroid) so the norms stay small, then each centred coordinate
+// z is split into bfloat16 parts hi = bf16(z), lo = bf16(z - hi), which carry
+// z to about 2^-17 relative. The Gram product is hi.hi + hi.lo + lo.hi (the
+// lo.lo term is below that error) on v_mfma_f32_16x16x32_bf16 with float32
+// accumulation; the norms are float32 sums of squares. The kernel function
+// (Gaussian exp, or the polynomial power of the uncentred inner product) runs
+// in float32 in the epilogue and the block is stored in float64 for the QR.
+//
+// A 256-thread workgroup computes a 64 x 64 tile; coordinates go through LDS
+// 32 dimensions at a time. The MFMA A operand holds the column points and B
+// the row points, so each output lane owns one sampled row of a column and
+// the column-major stores coalesce. Operand layout of the instruction (lane
+// l, element i): A[l % 16][(l / 16) * 8 + i], B[(l / 16) * 8 + i][l % 16],
+// D[(l / 16) * 4 + i][l % 16].
+#include "ffc_internal.h"
+
+namespace ffc {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int TM = 64, TN = 64, KCH = 32, NTH = 256;
+constexpr int LROW = KCH + 8;   // bf16 per LDS row (16-byte aligned, spread over banks)
+
+struct __attribute__((aligned(16))) MixSmem {
+  __bf16 xh[TN][LROW], xl[TN][LROW];   // column points (A operand)
+  __bf16 yh[TM][LROW], yl[TM][LROW];   // row points (B operand)
+  float xn[TN], yn[TM];                // squared norms of the centred points
+};
+
+struct Idx {
+  const int32_t* idx;
+  int64_t base;
+  __device__ inline int64_t operator()(int i) const { return idx ? (int64_t)idx[i] : base + i; }
+};
+
+// acc[bi][bj][e] = Gram entry (column point cb + bi*16 + (l/16)*4 + e, row point rb + bj*16 + l%16)
+// with cb = (wave >> 1) * 32 and rb = (wave & 1) * 32 inside the tile. When CENTRED, norms of the
+// centred points are left in sm.xn / sm.yn.
+template <bool CENTRED>
+__device__ void mixed_tile(const double* __restrict__ Y, Idx rows, int nrows, const double* __restrict__ X, Idx cols,
+                           int ncols, int d, const double* __restrict__ center, MixSmem& sm, f32x4 (&acc)[2][2]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // Staging map: thread t handles dimension kk = t % 32 of points t / 32 + 8 j, j < 8.
+  const int kk = tid & 31, p0 = tid >> 5;
+  float yacc[8], xacc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) yacc[j] = xacc[j] = 0.f;
+  int64_t yrow[8], xrow[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int p = p0 + 8 * j;
+    yrow[j] = p < nrows ? rows(p) : -1;
+    xrow[j] = p < ncols ? cols(p) : -1;
+  }
+  for (int k0 = 0; k0 < d; k0 += KCH) {
+    const int k = k0 + kk;
+    const double c = (CENTRED && k < d) ? center[k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int p = p0 + 8 * j;
+      const double yv = (yrow[j] >= 0 && k < d) ? Y[yrow[j] * d + k] - c : 0.0;
+      const double xv = (xrow[j] >= 0 && k < d) ? X[xrow[j] * d + k] - c : 0.0;
+      const __bf16 yh = (__bf16)(float)yv, xh = (__bf16)(float)xv;
+      sm.yh[p][kk] = yh;
+      sm.yl[p][kk] = (__bf16)(float)(yv - (double)(float)yh);
+      sm.xh[p][kk] = xh;
+      sm.xl[p][kk] = (__bf16)(float)(xv - (double)(float)xh);
+      const float yf = (float)yv, xf = (float)xv;
+      yacc[j] = fmaf(yf, yf, yacc[j]);
+      xacc[j] = fmaf(xf, xf, xacc[j]);
+    }
+    __syncthreads();
+    const int kofs = (lane >> 4) * 8;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const int xr = (w >> 1) * 32 + bi * 16 + (lane & 15);
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sm.xh[xr][kofs]);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(&sm.xl[xr][kofs]);
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&sm.yh[yr][kofs]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&sm.yl[yr][kofs]);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[bi][bj], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  if (CENTRED) {
+    // Sum the 32 per-dimension partials of each point (lanes sharing p0 form a half wave).
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      float yv = yacc[j], xv = xacc[j];
+#pragma unroll
+      for (int off = 16; off > 0; off >>= 1) {
+        yv += __shfl_xor(yv, off, 64);
+        xv += __shfl_xor(xv, off, 64);
+      }
+      if (kk == 0) {
+        sm.yn[p0 + 8 * j] = yv;
+        sm.xn[p0 + 8 * j] = xv;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <bool DOT>
+__device__ inline float kfun_mixed(float g, float yn, float xn, const KParams& kp) {
+  if (DOT) {
+    const float base = fmaf(g, (float)kp.inv_h, (float)kp.c);
+    float r = 1.f;
+    for (int i = 0; i < kp.p; ++i) r *= base;
+    return r;
+  }
+  const float r2 = fmaxf(yn + xn - 2.f * g, 0.f);
+  return expf(r2 * (float)kp.neg_inv_2h2);   // Gaussian (the Laplace kernel never comes here)
+}
+
+// Sampled blocks of a level in mixed precision (Gaussian: centred on the node
+// centroid; polynomial: raw inner products).
+template <bool DOT>
+__global__ void __launch_bounds__(NTH) k_level_kblock_mixed(const double* __restrict__ Xt, int d, KParams kp,
+                                                            int first, int tiles_m, int tiles_n,
+                                                            const int32_t* __restrict__ rows,
+                                                            const int32_t* __restrict__ nrows_a, int s_cap,
+                                                            const int32_t* __restrict__ cols,
+                                                            const int32_t* __restrict__ ncols_a, int n_cap,
+                                                            const double* __restrict__ centroid,
+                                                            double* __restrict__ A, unsigned int* flag) {
+  __shared__ MixSmem sm;
+  const int tiles = tiles_m * tiles_n;
+  const int ln = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  const int node = first + ln;
+  const int s = nrows_a[node], n = ncols_a[node];
+  const int r0 = (tile % tiles_m) * TM, c0 = (tile / tiles_m) * TN;
+  if (r0 >= s || c0 >= n) return;
+  f32x4 acc[2][2];
+  mixed_tile<!DOT>(Xt, Idx{rows + (int64_t)node * s_cap + r0, 0}, min(TM, s - r0), Xt,
+                   Idx{cols + (int64_t)node * n_cap + c0, 0}, min(TN, n - c0), d, centroid + (int64_t)node * d, sm,
+                   acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* out = A + (int64_t)ln * s_cap * n_cap;
+  bool bad = false;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int xc = (w >> 1) * 32 + bi * 16 + (lane >> 4) * 4 + e;
+        if (r0 + yr < s && c0 + xc < n) {
+          const float v = kfun_mixed<DOT>(acc[bi][bj][e], DOT ? 0.f : sm.yn[yr], DOT ? 0.f : sm.xn[xc], kp);
+          bad |= !isfinite(v);
+          out[(int64_t)(c0 + xc) * s_cap + (r0 + yr)] = (double)v;
+        }
+      }
+    }
+  if (bad) atomicOr(flag, 1u);
+}
+
+// Kernel sums in mixed precision: part[bj] accumulates sum_x K(y, x) q_x for
+// the row point (w & 1) * 32 + bj * 16 + l % 16 of the tile.
+template <bool DOT>
+__device__ inline void mixed_sum(const double* __restrict__ Y, Idx rows, int nrows, const double* __restrict__ X,
+                                 Idx cols, int ncols, const double* __restrict__ q, int d,
+                                 const double* __restrict__ center, const KParams& kp, MixSmem& sm, double (&part)[2],
+                                 bool& bad) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < ncols; c0 += TN) {
+    Idx cm{cols.idx ? cols.idx + c0 : nullptr, cols.base + c0};
+    f32x4 acc[2][2];
+    mixed_tile<!DOT>(Y, rows, nrows, X, cm, min(TN, ncols - c0), d, center, sm, acc);
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+      double s = 0.0;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int xc = (w >> 1) * 32 + bi * 16 + (lane >> 4) * 4 + e;
+          if (c0 + xc < ncols) {
+            const float v = kfun_mixed<DOT>(acc[bi][bj][e], DOT ? 0.f : sm.yn[yr], DOT ? 0.f : sm.xn[xc], kp);
+            bad |= !isfinite(v);
+            s = fma((double)v, q[c0 + xc], s);
+          }
+        }
+      part[bj] += s;
+    }
+    __syncthreads();   // norms in LDS are rewritten by the next tile
+  }
+}
+
+// Fixed-order reduction of part[] to one value per row point of the tile.
+__device__ inline void mixed_reduce(double (&part)[2], double* red /* 4 waves x 2 x 64 */, double* rowsum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int bj = 0; bj < 2; ++bj) red[(w * 2 + bj) * 64 + lane] = part[bj];
+  __syncthreads();
+  if (threadIdx.x < TM) {
+    const int yr = threadIdx.x;
+    const int wy = yr / 32, bj = (yr % 32) / 16, l16 = yr % 16;
+    double s = 0.0;
+    for (int wx = 0; wx < 2; ++wx) {
+      const int wv = wx * 2 + wy;
+      for (int g = 0; g < 4; ++g) s += red[(wv * 2 + bj) * 64 + g * 16 + l16];
+    }
+    rowsum[yr] = s;
+  }
+  __syncthreads();
+}
+
+template <bool DOT>
+__global__ void __launch_bounds__(NTH) k_evaluate_mixed(const double* __restrict__ Xt, int d, KParams kp, int depth,
+                                                        const int32_t* __restrict__ tile_leaf,
+                                                        const int32_t* __restrict__ tile_start,
+                                                        const int32_t* __restrict__ nb, const int32_t* __restrict__ ne,
+                                                        const double* __restrict__ q_tree,
+                                                        const int32_t* __restrict__ rank,
+                                                        const int32_t* __restrict__ skel, int r_cap,
+                                                        const double* __restrict__ qt,
+                                                        const double* __restrict__ centroid,
+                                                        const int32_t* __restrict__ perm, double* __restrict__ u,
+                                                        double* __restrict__ u_far, unsigned int* flag) {
+  __shared__ MixSmem sm;
+  __shared__ double red[8 * 64];
+  __shared__ double far_sum[TM], near_sum[TM];
+  const int leaf = tile_leaf[blockIdx.x];
+  const int start = tile_start[blockIdx.x];
+  const int nrows = min(TM, ne[leaf] - start);
+  const Idx rmap{nullptr, start};
+  const double* cen = centroid + (int64_t)leaf * d;
+  bool bad = false;
+  double part[2] = {0.0, 0.0};
+  int a = leaf;
+  for (int lev = depth; lev >= 1; --lev) {
+    const int sib = (a & 1) ? a + 1 : a - 1;
+    const int r = rank[sib];
+    if (r > 0)
+      mixed_sum<DOT>(Xt, rmap, nrows, Xt, Idx{skel + (int64_t)sib * r_cap, 0}, r, qt + (int64_t)sib * r_cap, d, cen,
+                     kp, sm, part, bad);
+    a = (a - 1) >> 1;
+  }
+  mixed_reduce(part, red, far_sum);
+  double npart[2] = {0.0, 0.0};
+  const int lb = nb[leaf];
+  mixed_sum<DOT>(Xt, rmap, nrows, Xt, Idx{nullptr, lb}, ne[leaf] - lb, q_tree + lb, d, cen, kp, sm, npart, bad);
+  mixed_reduce(npart, red, near_sum);
+  if (threadIdx.x < nrows) {
+    const int ci = perm[start + threadIdx.x];
+    const double f = far_sum[threadIdx.x];
+    u[ci] = f + near_sum[threadIdx.x];
+    if (u_far) u_far[ci] = f;
+  }
+  if (bad) atomicOr(flag, 1u);
+}
+
+template <bool DOT>
+__global__ void __launch_bounds__(NTH) k_direct_mixed(const double* __restrict__ Y, int64_t m,
+                                                      const double* __restrict__ X, int64_t n, int d, KParams kp,
+                                                      const double* __restrict__ q, double* __restrict__ u,
+                                                      unsigned int* flag) {
+  __shared__ MixSmem sm;
+  __shared__ double red[8 * 64];
+  __shared__ double rowsum[TM];
+  __shared__ double cen[1024];
+  const int64_t r0 = (int64_t)blockIdx.x * TM;
+  const int nrows = (int)min<int64_t>(TM, m - r0);
+  // Centre on the first target of the tile (any common point works for distances).
+  const int dc = min(d, 1024);
+  for (int k = threadIdx.x; k < dc; k += NTH) cen[k] = Y[r0 * d + k];
+  __syncthreads();
+  bool bad = false;
+  double part[2] = {0.0, 0.0};
+  mixed_sum<DOT>(Y, Idx{nullptr, r0}, nrows, X, Idx{nullptr, 0}, (int)n, q, d, cen, kp, sm, part, bad);
+  mixed_reduce(part, red, rowsum);
+  if (threadIdx.x < nrows) u[r0 + threadIdx.x] = rowsum[threadIdx.x];
+  if (bad) atomicOr(flag, 1u);
+}
+
+}  // namespace
+
+ffc_status launch_level_kblock_mixed(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int first, int count,
+                                     double* A, hipStream_t st) {
+  const int tiles_m = (sk->s_cap + TM - 1) / TM, tiles_n = (sk->n_cap + TN - 1) / TN;
+  const int64_t blocks = (int64_t)count * tiles_m * tiles_n;
+  if (kp.kind == FFC_POLYNOMIAL)
+    hipLaunchKernelGGL(k_level_kblock_mixed<true>, dim3((unsigned)blocks), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
+                       first, tiles_m, tiles_n, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, sk->cols.ptr, sk->ncols.ptr,
+                       sk->n_cap, t->centroid.ptr, A, device_flag());
+  else
+    hipLaunchKernelGGL(k_level_kblock_mixed<false>, dim3((unsigned)blocks), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
+                       first, tiles_m, tiles_n, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, sk->cols.ptr, sk->ncols.ptr,
+                       sk->n_cap, t->centroid.ptr, A, device_flag());
+  FFC_LAUNCH_CHECK("k_level_kblock_mixed");
+  return FFC_OK;
+}
+
+ffc_status launch_evaluate_mixed(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, double* u, double* u_far,
+                                 hipStream_t st) {
+  if (kp.kind == FFC_POLYNOMIAL)
+    hipLaunchKernelGGL(k_evaluate_mixed<true>, dim3((unsigned)t->num_tiles), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
+                       t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
+                       sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->centroid.ptr, t->perm.ptr, u, u_far,
+                       device_flag());
+  else
+    hipLaunchKernelGGL(k_evaluate_mixed<false>, dim3((unsigned)t->num_tiles), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
+                       t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
+                       sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->centroid.ptr, t->perm.ptr, u, u_far,
+                       device_flag());
+  FFC_LAUNCH_CHECK("k_evaluate_mixed");
+  return FFC_OK;
+}
+
+ffc_status launch_direct_mixed(const double* Y, int64_t m, const double* X, int64_t n, int d, const KParams& kp,
+                               const double* q, double* u, hipStream_t st) {
+  if (m == 0) return FFC_OK;
+  if (kp.kind != FFC_POLYNOMIAL && d > 1024) {
+    set_error("mixed-precision direct sum supports d <= 1024");
+    return FFC_ERR_INVALID_ARG;
+  }
+  const unsigned blocks = (unsigned)((m + TM - 1) / TM);
+  if (kp.kind == FFC_POLYNOMIAL)
+    hipLaunchKernelGGL(k_direct_mixed<true>, dim3(blocks), dim3(NTH), 0, st, Y, m, X, n, d, kp, q, u, device_flag());
+  else
+    hipLaunchKernelGGL(k_direct_mixed<false>, dim3(blocks), dim3(NTH), 0, st, Y, m, X, n, d, kp, q, u, device_flag());
+  FFC_LAUNCH_CHECK("k_direct_mixed");
+  return FFC_OK;
+}
+
+}  // namespace ffc

@@ -15,6 +15,9 @@
 //   * kernel sums u_i = sum_j K(y_i, x_j) q_j (Section 1, eq. e:sum; eq. e:id
 //     with the skeleton points and equivalent charges), reduced across the
 //     16 threads sharing a row in a fixed order, so results are deterministic.
+// Precision: FP64 tiles in double; FP32 tiles (and the Laplace kernel in the
+// mixed mode) in float with the Laplace power taken in double; the mixed mode
+// of the Gaussian and polynomial kernels runs on matrix cores (gram_mfma.hip).
 #include "ffc_internal.h"
 
 namespace ffc {
@@ -294,6 +297,8 @@ ffc_status dispatch(int precision, bool dot, F&& f) {
 
 ffc_status launch_level_kblock(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, int first,
                                int count, double* A, hipStream_t st) {
+  if (precision == FFC_MIXED_BF16X3 && kp.kind != FFC_LAPLACE)
+    return launch_level_kblock_mixed(t, sk, kp, first, count, A, st);
   const int tiles_m = (sk->s_cap + BM - 1) / BM, tiles_n = (sk->n_cap + BN - 1) / BN;
   const int64_t blocks = (int64_t)count * tiles_m * tiles_n;
   const bool dot = kp.kind == FFC_POLYNOMIAL;
@@ -324,6 +329,7 @@ ffc_status launch_sampled_block(const ffc_tree* t, const KParams& kp, int precis
 
 ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, double* u,
                            double* u_far, hipStream_t st) {
+  if (precision == FFC_MIXED_BF16X3 && kp.kind != FFC_LAPLACE) return launch_evaluate_mixed(t, sk, kp, u, u_far, st);
   const bool dot = kp.kind == FFC_POLYNOMIAL;
   return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
     using T = decltype(tv);
@@ -339,6 +345,7 @@ ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams&
 ffc_status launch_direct_sum(const double* Y, int64_t m, const double* X, int64_t n, int d, const KParams& kp,
                              int precision, const double* q, double* u, hipStream_t st) {
   if (m == 0) return FFC_OK;
+  if (precision == FFC_MIXED_BF16X3 && kp.kind != FFC_LAPLACE) return launch_direct_mixed(Y, m, X, n, d, kp, q, u, st);
   const bool dot = kp.kind == FFC_POLYNOMIAL;
   return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
     using T = decltype(tv);

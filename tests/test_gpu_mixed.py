@@ -1,0 +1,90 @@
+"""Mixed precision (bf16 hi/lo Gram on matrix cores, float32 accumulation):
+direct sums within the bound of the representation, and the compressed far
+field within 1e-4 of the FP64 oracle where the method itself is accurate."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.direct import direct_abs_sum, direct_sum as o_direct
+from oracle.evaluate import exact_far_field
+from oracle.kernels import GAUSSIAN, LAPLACE, POLYNOMIAL
+from oracle.tree import build_tree as o_build_tree
+from paper_1409_2802_amd import workloads as W
+from tests._parity import gkernel, okernel, rel
+
+pytestmark = pytest.mark.gpu
+
+# bf16 hi + lo carries a coordinate to 2^-17 relative; the dropped lo*lo term and
+# float32 accumulation stay below 2^-16 of |y||x| for these sizes.
+GRAM_REL = 2.0 ** -15
+
+
+@pytest.fixture(scope="module")
+def ffc():
+    from paper_1409_2802_amd import ffc as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.load_library()
+    return m
+
+
+@pytest.mark.parametrize("d", [3, 16, 64, 200, 1000])
+def test_direct_sum_mixed_gaussian(ffc, d):
+    h = 0.6 * np.sqrt(d) ** 0.5
+    Y = W.normal(130, d, seed=1) * 0.3
+    X = W.normal(257, d, seed=2) * 0.3
+    q = W.charges(257, seed=3)
+    u = ffc.direct_sum(Y, X, q, gkernel(GAUSSIAN, h=h), precision=ffc.MIXED_BF16X3).cpu().numpy()
+    ok = okernel(GAUSSIAN, h=h)
+    ref = o_direct(Y, X, q, ok)
+    # |d K| <= K * |d r^2| / (2 h^2); |d r^2| <= GRAM_REL * (|y'| + |x'|)^2 with y', x' centred on a target.
+    span = (np.linalg.norm(Y - Y[0], axis=1).max() + np.linalg.norm(X - Y[0], axis=1).max()) ** 2
+    bound = (GRAM_REL * span / (2 * h * h) + 2.0 ** -20) * direct_abs_sum(Y, X, q, ok)
+    assert np.all(np.abs(u - ref) <= bound)
+
+
+@pytest.mark.parametrize("d,p", [(4, 3), (64, 2), (1000, 3)])
+def test_direct_sum_mixed_polynomial(ffc, d, p):
+    Y = W.normal(100, d, seed=4) / np.sqrt(d)
+    X = W.normal(300, d, seed=5) / np.sqrt(d)
+    q = W.charges(300, seed=6)
+    k = dict(h=1.0, p=p)
+    u = ffc.direct_sum(Y, X, q, gkernel(POLYNOMIAL, **k), precision=ffc.MIXED_BF16X3).cpu().numpy()
+    ok = okernel(POLYNOMIAL, **k)
+    ref = o_direct(Y, X, q, ok)
+    dot = np.abs(Y) @ np.abs(X).T
+    base = np.abs(Y @ X.T + 1.0)
+    amp = p * (GRAM_REL * dot / np.maximum(base, 1e-300)).max() + 2.0 ** -20 * p
+    assert np.all(np.abs(u - ref) <= amp * direct_abs_sum(Y, X, q, ok))
+
+
+def test_direct_sum_mixed_laplace_uses_float_differences(ffc):
+    Y = W.uniform_cube(90, 6, seed=7)
+    X = W.uniform_cube(140, 6, seed=8) + 0.05
+    q = W.charges(140, seed=9)
+    u = ffc.direct_sum(Y, X, q, gkernel(LAPLACE), precision=ffc.MIXED_BF16X3).cpu().numpy()
+    ok = okernel(LAPLACE)
+    assert np.all(np.abs(u - o_direct(Y, X, q, ok)) <= 5e-5 * direct_abs_sum(Y, X, q, ok))
+
+
+@pytest.mark.parametrize("name,make,kind,kw,leaf,tol,mr", [
+    ("poly-d4-p3", lambda: W.uniform_cube(4096, 4, seed=0), POLYNOMIAL, dict(h=1.0, p=3), 256, 1e-9, 128),
+    ("gauss-d8-h3", lambda: W.uniform_cube(4096, 8, seed=0), GAUSSIAN, dict(h=3.0), 256, 1e-8, 128),
+])
+def test_mixed_far_field_within_1e4_of_fp64_oracle(ffc, name, make, kind, kw, leaf, tol, mr):
+    X = make()
+    q = W.charges(X.shape[0], seed=1)
+    gk, ok = gkernel(kind, **kw), okernel(kind, **kw)
+    t = ffc.build_tree(X, leaf)
+    ex = exact_far_field(X, o_build_tree(X, leaf), ok, q)
+    errs, far = {}, {}
+    for prec in (ffc.FP64, ffc.MIXED_BF16X3):
+        sk = ffc.skeletonize(t, gk, tol=tol, max_rank=mr, seed=0, precision=prec)
+        _, uf = ffc.evaluate_sum(t, sk, gk, q, precision=prec)
+        far[prec] = uf.cpu().numpy()
+        errs[prec] = rel(far[prec], ex)
+    ffc.check_device()
+    gap = rel(far[ffc.MIXED_BF16X3], far[ffc.FP64])
+    print(name, "e_far fp64", errs[ffc.FP64], "mixed", errs[ffc.MIXED_BF16X3], "mixed vs fp64", gap)
+    assert errs[ffc.FP64] < 1e-5        # the method is accurate on this configuration
+    assert errs[ffc.MIXED_BF16X3] < 1e-4
+    assert gap < 1e-4
