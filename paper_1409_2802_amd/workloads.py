@@ -81,3 +81,16 @@ def subset(n_total: int, count: int, seed: int = 2) -> np.ndarray:
     """A sorted seeded subset of `count` distinct indices of range(n_total)."""
     g = _rng(seed)
     return np.sort(g.choice(n_total, size=min(count, n_total), replace=False))
+
+
+def mlp_init(seed: int = 5) -> np.ndarray:
+    """Initial parameters of the 16 -> 64 -> 64 -> 1 proposal network, float64.
+
+    He-normal weights, zero biases, flat in the order W1 (16 x 64, row-major),
+    b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3 (1): 5313 values.
+    """
+    g = _rng(seed)
+    W1 = g.standard_normal((16, 64)) * np.sqrt(2.0 / 16)
+    W2 = g.standard_normal((64, 64)) * np.sqrt(2.0 / 64)
+    w3 = g.standard_normal(64) * np.sqrt(1.0 / 64)
+    return np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), w3, [0.0]])
