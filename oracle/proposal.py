@@ -37,6 +37,20 @@ sigma_k^2 / (sigma_k^2 + lambda); a smoothed form of the rank-r leverage of
 Section 3 (Definition of statistical leverage) that needs no rank choice.
 Target t_i = ln(max(l_i, 1e-12) * m / sum(l)).
 
+Training set: block g (g < 2^28) picks leaf first_leaf + uniform_below(
+counter(seed, 7 * 2^29, g), number of leaves); its columns are a Floyd draw
+of n = min(block_cols, smallest leaf) positions inside the leaf (stream
+5 * 2^29 | g), its targets a Floyd draw of m = min(block_rows, N - largest
+leaf) positions outside it (stream 5 * 2^29 | 2^28 | g). Its rows' features
+are taken against the geometry of its columns with stream id = the leaf, and
+its labels are the targets of the ridge leverage of K(targets, columns).
+Samples are numbered block-major (g m + i). Standardization: mean and
+population standard deviation over all samples. Training: per epoch e, the
+position p of the epoch visits sample (p * k_e) mod C (C samples), k_e = 1 +
+uniform_below(counter(seed, 7 * 2^29 | 2^28, e), C - 1) raised to the next
+value coprime with C; consecutive positions form mini-batches of `batch`
+samples (the last one short), each followed by one Adam step.
+
 Selection: pool of min(M, 8 s) uniform candidates (`floyd_sample` stream
 node | 2^31); weights w = 0.9 softmax(score) + 0.1 / pool; Efraimidis-Spirakis
 keys -ln(U_i) / w_i with U_i = ((u64 >> 11) + 0.5) 2^-53 from the counter
@@ -53,7 +67,7 @@ import numpy as np
 
 from .cpqr_id import interpolative_decomposition
 from .kernels import Kernel, kernel_matrix
-from .sampling import counter_u64, floyd_sample, sample_far_rows
+from .sampling import counter_u64, floyd_sample, sample_far_rows, uniform_below
 
 NF = 16
 H = 64
@@ -62,6 +76,10 @@ STREAM_SUBSAMPLE = 1 << 30
 STREAM_POOL = 1 << 31
 STREAM_KEYS = 3 << 30
 STREAM_HELDOUT = 1 << 29
+STREAM_TRAIN_COLS = 5 << 29
+STREAM_TRAIN_ROWS = (5 << 29) | (1 << 28)
+STREAM_TRAIN_LEAF = 7 << 29
+STREAM_TRAIN_SHUFFLE = (7 << 29) | (1 << 28)
 
 
 # ----------------------------------------------------------------------------
@@ -181,6 +199,55 @@ def adam_step(theta, m1, m2, grad, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     return theta - lr * mhat / (np.sqrt(vhat) + eps), m1, m2
 
 
+def fit_standardization(F: np.ndarray):
+    """Per-feature mean and population std (floored at 1e-6); f15 keeps mu 0, sd 1."""
+    F = np.asarray(F, dtype=np.float64)
+    mu = F.mean(axis=0)
+    sd = np.maximum(F.std(axis=0), 1e-6)
+    mu[NF - 1] = 0.0
+    sd[NF - 1] = 1.0
+    return mu, sd
+
+
+def epoch_stride(C: int, seed: int, epoch: int) -> int:
+    """Multiplier k_e of the epoch's visiting order p -> (p k_e) mod C."""
+    if C <= 1:
+        return 1
+    k = 1 + uniform_below(counter_u64(seed, STREAM_TRAIN_SHUFFLE, epoch), C - 1)
+    while math.gcd(k, C) != 1:
+        k = k + 1 if k + 1 < C else 1
+    return k
+
+
+def train(F: np.ndarray, t: np.ndarray, theta0: np.ndarray, epochs: int, batch: int, lr: float, seed: int,
+          mu: np.ndarray, sd: np.ndarray):
+    """Mini-batch Adam on the mean squared error; returns (theta, per-epoch loss, per-step loss).
+
+    The epoch loss is the sample-weighted mean of its mini-batch losses.
+    """
+    Z = standardize(F, mu, sd)
+    t = np.asarray(t, dtype=np.float64)
+    C = len(t)
+    theta = np.array(theta0, dtype=np.float64)
+    m1 = np.zeros_like(theta)
+    m2 = np.zeros_like(theta)
+    step = 0
+    hist, steps = [], []
+    for e in range(epochs):
+        k = epoch_stride(C, seed, e)
+        order = (np.arange(C, dtype=object) * k % C).astype(np.int64)
+        tot = 0.0
+        for p0 in range(0, C, batch):
+            idx = order[p0:p0 + batch]
+            loss, g = mlp_loss_grad(theta, Z[idx], t[idx])
+            step += 1
+            theta, m1, m2 = adam_step(theta, m1, m2, g, step, lr=lr)
+            tot += loss * len(idx)
+            steps.append(loss)
+        hist.append(tot / C)
+    return theta, np.array(hist), np.array(steps)
+
+
 # ----------------------------------------------------------------------------
 # Labels
 # ----------------------------------------------------------------------------
@@ -237,6 +304,52 @@ def heldout_error(Kh: np.ndarray, skel_local: np.ndarray, P: np.ndarray) -> floa
     if den == 0.0:
         return 0.0
     return float(np.linalg.norm(Kh - Kh[:, skel_local] @ P) / den)
+
+
+# ----------------------------------------------------------------------------
+# Training set
+# ----------------------------------------------------------------------------
+@dataclass
+class TrainingBlock:
+    leaf: int
+    cols: np.ndarray       # tree positions inside the leaf
+    rows: np.ndarray       # tree positions outside it
+
+
+def training_blocks(tree, num_blocks: int, block_cols: int, block_rows: int, seed: int):
+    """The training blocks of the proposal (definitions in the module docstring)."""
+    first = (1 << tree.depth) - 1
+    leaves = list(tree.level_nodes(tree.depth))
+    sizes = [int(tree.end[a] - tree.begin[a]) for a in leaves]
+    n = min(block_cols, min(sizes))
+    m = min(block_rows, tree.N - max(sizes))
+    out = []
+    for g in range(num_blocks):
+        leaf = first + uniform_below(counter_u64(seed, STREAM_TRAIN_LEAF, g), len(leaves))
+        b, e = int(tree.begin[leaf]), int(tree.end[leaf])
+        cols = np.array(floyd_sample(e - b, n, seed, STREAM_TRAIN_COLS | g), dtype=np.int64) + b
+        M = tree.N - (e - b)
+        picks = floyd_sample(M, m, seed, STREAM_TRAIN_ROWS | g)
+        rows = np.array([x if x < b else x + (e - b) for x in picks], dtype=np.int64)
+        out.append(TrainingBlock(leaf=leaf, cols=cols, rows=rows))
+    return out, n, m
+
+
+def training_set(X, tree, k: Kernel, num_blocks: int, block_cols: int, block_rows: int, eps: float, seed: int):
+    """Features F (C x 16), ridge leverages and targets of all training samples, block-major."""
+    Xt = np.asarray(X, dtype=np.float64)[tree.perm]
+    blocks, n, m = training_blocks(tree, num_blocks, block_cols, block_rows, seed)
+    F, lev, tgt = [], [], []
+    for blk in blocks:
+        geo = column_geometry(Xt[blk.cols], seed, blk.leaf)
+        F.append(features(Xt[blk.rows], geo))
+        B = kernel_matrix(Xt[blk.rows], Xt[blk.cols], k)
+        l = ridge_leverage(B, eps)
+        lev.append(l)
+        tgt.append(leverage_targets(l))
+    if not blocks:
+        return np.zeros((0, NF)), np.zeros(0), np.zeros(0), blocks
+    return np.concatenate(F), np.concatenate(lev), np.concatenate(tgt), blocks
 
 
 # ----------------------------------------------------------------------------
