@@ -11,8 +11,8 @@ Definitions (both sides implement these; parity unpinned for the feature set
 itself, which is a design choice — its pins are invariants below):
 
 Column set X_c (n points) of a node: centroid c = mean, radius rho = largest
-distance to c (1 if zero). Subsample S: `floyd_sample(n, 64, seed, stream =
-node | 2^30)` indices into the columns (all of them if n <= 64). Anchors:
+distance to c (1 if zero). Subsample S: `floyd_sample(n, 256, seed, stream =
+node | 2^30)` indices into the columns (all of them if n <= 256). Anchors:
 a_1 = the point of S farthest from c; a_{k+1} = the point of S farthest from
 {a_1..a_k} (largest minimum distance), up to 7 anchors (ties: first in S
 order); u_k = (a_k - c) / |a_k - c| (0 if zero).
@@ -51,7 +51,7 @@ uniform_below(counter(seed, 7 * 2^29 | 2^28, e), C - 1) raised to the next
 value coprime with C; consecutive positions form mini-batches of `batch`
 samples (the last one short), each followed by one Adam step.
 
-Selection: pool of min(M, 8 s) uniform candidates (`floyd_sample` stream
+Selection: pool of min(M, c s) uniform candidates (c = pool factor, 8 by default) (`floyd_sample` stream
 node | 2^31); weights w = 0.9 softmax(score) + 0.1 / pool; Efraimidis-Spirakis
 keys -ln(U_i) / w_i with U_i = ((u64 >> 11) + 0.5) 2^-53 from the counter
 generator (stream node | 3 * 2^30); the s smallest keys are taken. Fallback:
@@ -71,6 +71,8 @@ from .sampling import counter_u64, floyd_sample, sample_far_rows, uniform_below
 
 NF = 16
 H = 64
+SUB = 256          # column subsample of the geometry
+POOL_FACTOR = 8    # default candidate pool: min(M, POOL_FACTOR * s)
 NPARAM = NF * H + H + H * H + H + H + 1      # 5313
 STREAM_SUBSAMPLE = 1 << 30
 STREAM_POOL = 1 << 31
@@ -100,7 +102,7 @@ def column_geometry(Xc: np.ndarray, seed: int, node: int) -> ColumnGeometry:
     rho = float(np.sqrt(((Xc - c) ** 2).sum(axis=1).max())) if n else 0.0
     if rho == 0.0:
         rho = 1.0
-    idx = floyd_sample(n, 64, seed, node | STREAM_SUBSAMPLE)
+    idx = floyd_sample(n, SUB, seed, node | STREAM_SUBSAMPLE)
     S = Xc[idx]
     U = np.zeros((7, d))
     if len(S):
@@ -287,9 +289,9 @@ def select_rows(scores: np.ndarray, pool: np.ndarray, s: int, seed: int, node: i
     return np.sort(pool[order[:s]])
 
 
-def candidate_pool(b: int, e: int, N: int, s: int, seed: int, node: int) -> np.ndarray:
+def candidate_pool(b: int, e: int, N: int, s: int, seed: int, node: int, factor: int = POOL_FACTOR) -> np.ndarray:
     M = N - (e - b)
-    picks = floyd_sample(M, min(M, 8 * s), seed, node | STREAM_POOL)
+    picks = floyd_sample(M, min(M, factor * s), seed, node | STREAM_POOL)
     return np.array([t if t < b else t + (e - b) for t in picks], dtype=np.int64)
 
 
@@ -356,7 +358,8 @@ def training_set(X, tree, k: Kernel, num_blocks: int, block_cols: int, block_row
 # Learned skeletonization (Section 2.2 with importance-sampled rows)
 # ----------------------------------------------------------------------------
 def skeletonize_learned(X, tree, k: Kernel, tol: float, max_rank: int, num_samples: int, seed: int,
-                        theta: np.ndarray, mu: np.ndarray, sd: np.ndarray, fallback_tol: float):
+                        theta: np.ndarray, mu: np.ndarray, sd: np.ndarray, fallback_tol: float,
+                        pool_factor: int = POOL_FACTOR):
     """Like skeleton.skeletonize, with rows drawn from the learned proposal.
 
     Returns (Skeletons, fallback flags per node).
@@ -376,7 +379,7 @@ def skeletonize_learned(X, tree, k: Kernel, tol: float, max_rank: int, num_sampl
             node = None
             fell[a] = False
             if len(cols) > 0:
-                pool = candidate_pool(b, e, tree.N, s, seed, a)
+                pool = candidate_pool(b, e, tree.N, s, seed, a, pool_factor)
                 geo = column_geometry(Xt[cols], seed, a)
                 scores, _ = mlp_forward(theta, standardize(features(Xt[pool], geo), mu, sd))
                 rows = select_rows(scores, pool, s, seed, a)
