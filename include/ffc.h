@@ -78,10 +78,15 @@ typedef struct ffc_proposal ffc_proposal;
  *  num_samples  sampled target rows per node; 0 means 2 * max_rank. Capped at
  *               the number of points outside the node.
  *  precision    ffc_precision of the sampled kernel block
- *  sampler      ffc_sampler; FFC_SAMPLE_LEARNED needs `proposal`
+ *  sampler      ffc_sampler; FFC_SAMPLE_LEARNED needs `proposal` (kept by
+ *               reference: it must outlive the call)
  *  seed         seed of the counter-based row sampler
  *  fallback_tol learned sampler only: a node whose held-out error estimate
- *               exceeds it is redone with uniform rows (<= 0 disables) */
+ *               exceeds it is redone with uniform rows (<= 0 disables; the
+ *               check synchronizes the stream once per level)
+ *  pool_factor  learned sampler only: the candidate pool of a node is
+ *               min(M, pool_factor * samples) uniform far points (0 means 8;
+ *               the pool is limited to 8192) */
 typedef struct {
   double tol;
   int32_t max_rank;
@@ -91,6 +96,7 @@ typedef struct {
   uint64_t seed;
   const ffc_proposal* proposal;
   double fallback_tol;
+  int32_t pool_factor;
 } ffc_skel_opts;
 
 /* Build a binary ball tree over X (Section 2: hierarchical groupings of the
@@ -192,6 +198,104 @@ typedef struct {
 
 /* Rank statistics of a skeleton set (synchronizes). */
 ffc_status ffc_skel_stats(const ffc_skel* sk, ffc_stats* out);
+
+/* ---------------------------------------------------------------------------
+ * Learned row proposal.
+ *
+ * Leverage-score sampling of target rows (Section 3, importance sampling) is
+ * the most reliable choice of rows but needs the whole block; the paper's
+ * cheap alternatives are geometric heuristics (Section 3.2). The proposal
+ * learns the map from 16 cheap geometric features of a target (against the
+ * node's column set: distances to its centroid, to a 256-point subsample and
+ * projections on 7 far anchors) to the log of its ridge leverage, with a
+ * 16 -> 64 -> 64 -> 1 ReLU network in float32. Skeletonization then draws s
+ * rows from a uniform pool of min(M, c s) candidates (c = pool_factor) with weights 0.9
+ * softmax(score) + 0.1 / pool, without replacement (Efraimidis-Spirakis keys),
+ * and redoes a node with uniform rows when the error on 32 held-out rows
+ * exceeds fallback_tol.
+ *
+ * Parameters theta (FFC_PROPOSAL_NPARAM float32): W1 (16 x 64, row-major), b1
+ * (64), W2 (64 x 64), b2 (64), w3 (64), b3. Standardization mu, sd (16 each):
+ * the network sees (f - mu) / sd, with the constant feature 15 left at 1.
+ * A proposal handle owns device copies of theta, mu, sd and the Adam moments.
+ * ------------------------------------------------------------------------- */
+#define FFC_PROPOSAL_NPARAM 5313
+#define FFC_PROPOSAL_NFEAT 16
+
+/* theta_host required; mu_host / sd_host may be NULL (0 and 1). Synchronous.
+ * Errors: NULL theta or out, non-finite values -> FFC_ERR_INVALID_ARG. */
+ffc_status ffc_proposal_create(const float* theta_host, const float* mu_host, const float* sd_host,
+                               ffc_proposal** out);
+/* Copies the current theta / mu / sd to the host (any may be NULL); synchronizes
+ * the device. */
+ffc_status ffc_proposal_get(const ffc_proposal* p, float* theta_host, float* mu_host, float* sd_host);
+void ffc_proposal_free(ffc_proposal* p);
+
+/* Features of target rows against column sets, for `count` blocks: block g
+ * has columns cols_dev[g * col_stride + j], j < ncols_dev[g] (tree positions,
+ * at least 1), stream id ids_dev[g] (the node id in skeletonization) and
+ * targets tgt_dev[g * tgt_stride + i], i < ntgt_dev[g] (tree positions); the
+ * features go to feat_dev[(g * tgt_stride + i) * 16 + f] (other slots are not
+ * written). All arrays are device arrays. Synchronizes (geometry scratch). */
+ffc_status ffc_proposal_features(const ffc_tree* t, const int32_t* cols_dev, int32_t col_stride,
+                                 const int32_t* ncols_dev, const int32_t* ids_dev, const int32_t* tgt_dev,
+                                 int32_t tgt_stride, const int32_t* ntgt_dev, int32_t count, uint64_t seed,
+                                 float* feat_dev, void* stream);
+/* Sets mu, sd from `count` feature rows (population std floored at 1e-6). */
+ffc_status ffc_proposal_fit_standardization(ffc_proposal* p, const float* feat_dev, int64_t count, void* stream);
+/* score_dev[i] = network output for feature row i. */
+ffc_status ffc_proposal_score(const ffc_proposal* p, const float* feat_dev, int64_t count, float* score_dev,
+                              void* stream);
+/* Mean squared error of the scores against target_dev over `count` rows and
+ * its gradient (grad_dev: FFC_PROPOSAL_NPARAM floats, loss_dev: 1 float, both
+ * device). Synchronizes (partial sums scratch). */
+ffc_status ffc_proposal_gradient(const ffc_proposal* p, const float* feat_dev, const float* target_dev,
+                                 int64_t count, float* grad_dev, float* loss_dev, void* stream);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, bias-corrected; the handle counts
+ * its steps) with the gradient grad_dev. */
+ffc_status ffc_proposal_adam(ffc_proposal* p, const float* grad_dev, float lr, void* stream);
+
+/* Ridge leverage of the rows of `count` row-major m x n blocks (B_dev, back
+ * to back, not modified): l_i = b_i^T (B^T B + eps^2 ||B||_F^2 I)^{-1} b_i,
+ * the smoothed form of the leverage of Section 3 that needs no rank choice;
+ * target_dev (may be NULL) gets ln(max(l_i, 1e-12) m / sum(l)). A zero block
+ * gives zeros. Errors: a factorization that fails (not positive definite)
+ * -> FFC_ERR_NONFINITE. Synchronizes (scratch). */
+ffc_status ffc_leverage_labels(const double* B_dev, int64_t m, int32_t n, int32_t count, double eps,
+                               double* lev_dev, float* target_dev, void* stream);
+
+/* Proposal training. Block g of the training set takes a random leaf of the
+ * tree, n = min(block_cols, smallest leaf) of its points as columns and m =
+ * min(block_rows, N - largest leaf) points outside it as targets (counter-based
+ * draws from `seed`); its samples are the targets' features and the targets
+ * of the ridge leverage of K(targets, columns) in float64. Training fits the
+ * standardization on all samples, then runs `epochs` passes of mini-batch Adam
+ * (`batch` samples per step, learning rate lr) on the mean squared error, the
+ * epoch's order a seeded stride permutation. loss_host (epochs floats, may be
+ * NULL) receives each epoch's mean loss. Synchronizes.
+ * Errors: num_blocks < 1, block sizes < 1, batch < 1, epochs < 0 ->
+ * FFC_ERR_INVALID_ARG. */
+typedef struct {
+  int32_t num_blocks;
+  int32_t block_cols;
+  int32_t block_rows;
+  int32_t epochs;
+  int32_t batch;
+  float lr;
+  double eps;
+  uint64_t seed;
+} ffc_train_opts;
+ffc_status ffc_proposal_train(ffc_proposal* p, const ffc_tree* t, const ffc_kernel* k, const ffc_train_opts* o,
+                              float* loss_host, void* stream);
+/* The training set of ffc_proposal_train without the training: block leaves,
+ * columns (num_blocks x n), targets (num_blocks x m), features
+ * (num_blocks * m x 16) and label targets (num_blocks * m) into device arrays
+ * sized by the caller from n_out / m_out, which a first call with all arrays
+ * NULL returns. Synchronizes. */
+ffc_status ffc_proposal_training_set(const ffc_tree* t, const ffc_kernel* k, const ffc_train_opts* o,
+                                     int32_t* n_out, int32_t* m_out, int32_t* leaves_dev, int32_t* cols_dev,
+                                     int32_t* rows_dev, float* feat_dev, float* target_dev, double* lev_dev,
+                                     void* stream);
 
 /* Synchronizes `stream` and reports (then clears) the device error flag:
  * FFC_ERR_NONFINITE if a kernel value was not finite since the last check,

@@ -74,6 +74,8 @@ ffc_status finish_tree_common(ffc_tree* t, hipStream_t st) {
 
 void set_error(const std::string& msg) { g_error = msg; }
 
+ffc_status validate_kernel(const ffc_kernel* k, int d) { return check_kernel(k, d); }
+
 KParams make_kparams(const ffc_kernel& k, int d) {
   KParams p{};
   p.kind = k.kind;
@@ -231,8 +233,10 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
   if (o->num_samples < 0) return fail(FFC_ERR_INVALID_ARG, "num_samples must be >= 0");
   if (o->sampler != FFC_SAMPLE_UNIFORM && o->sampler != FFC_SAMPLE_LEARNED)
     return fail(FFC_ERR_INVALID_ARG, "unknown sampler");
-  if (o->sampler == FFC_SAMPLE_LEARNED)
-    return fail(FFC_ERR_INVALID_ARG, "the learned sampler needs a proposal (not available in this build)");
+  const bool learned = o->sampler == FFC_SAMPLE_LEARNED;
+  if (learned && !o->proposal) return fail(FFC_ERR_INVALID_ARG, "the learned sampler needs a proposal");
+  if (learned && !std::isfinite(o->fallback_tol)) return fail(FFC_ERR_INVALID_ARG, "fallback_tol must be finite");
+  if (learned && o->pool_factor < 0) return fail(FFC_ERR_INVALID_ARG, "pool_factor must be >= 0");
   hipStream_t st = (hipStream_t)stream;
 
   const int64_t s_req = o->num_samples > 0 ? o->num_samples : 2 * (int64_t)o->max_rank;
@@ -287,48 +291,67 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
   sk->fallbacks = 0;
   const KParams kp = make_kparams(*k, t->d);
   const int max_rank = std::min(o->max_rank, r_cap);
+  // Sampled blocks, interpolative decompositions and skeleton ids of one level
+  // (rows and columns already in place).
+  auto skeletonize_level = [&](int first, int count) -> ffc_status {
+    {
+      StageTimer tm(FFC_STAGE_KBLOCK, st);
+      FFC_TRY(launch_level_kblock(t, sk, kp, o->precision, first, count, sk->work.ptr, st));
+    }
+    IdBatch bt{};
+    bt.A = sk->work.ptr;
+    bt.a_stride = (int64_t)s_cap * n_cap;
+    bt.lda = s_cap;
+    bt.s_arr = sk->nrows.ptr + first;
+    bt.n_arr = sk->ncols.ptr + first;
+    bt.s_max = s_cap;
+    bt.n_max = n_cap;
+    bt.tol = o->tol;
+    bt.max_rank = max_rank;
+    bt.rank = sk->rank.ptr + first;
+    bt.piv = sk->piv.ptr + (int64_t)first * n_cap;
+    bt.piv_stride = n_cap;
+    bt.P = sk->P.ptr + (int64_t)first * r_cap * n_cap;
+    bt.p_stride = (int64_t)r_cap * n_cap;
+    bt.p_ld = n_cap;
+    {
+      bool used = false;
+      FFC_TRY(launch_interp_decomp_coop(bt, count, sk->qr_scratch, st, used));
+      if (!used) {
+        StageTimer tm(FFC_STAGE_CPQR, st);
+        FFC_TRY(launch_interp_decomp(bt, count, st));
+      }
+    }
+    {
+      StageTimer tm(FFC_STAGE_SKEL, st);
+      FFC_TRY(launch_skeleton_ids(sk, first, count, st));
+    }
+    return FFC_OK;
+  };
   auto run = [&]() -> ffc_status {
+    if (learned) FFC_TRY(learned_alloc(t, sk, o->pool_factor > 0 ? o->pool_factor : 8));
     for (int lev = t->depth; lev >= 1; --lev) {
       const int first = (1 << lev) - 1, count = 1 << lev;
-      {
-        StageTimer tm(FFC_STAGE_SAMPLE, st);
-        FFC_TRY(launch_sample_rows(t, sk, first, count, s_cap, o->seed, st));
-      }
       {
         StageTimer tm(FFC_STAGE_COLUMNS, st);
         FFC_TRY(launch_level_columns(t, sk, first, count, lev == t->depth, st));
       }
       {
-        StageTimer tm(FFC_STAGE_KBLOCK, st);
-        FFC_TRY(launch_level_kblock(t, sk, kp, o->precision, first, count, sk->work.ptr, st));
+        StageTimer tm(FFC_STAGE_SAMPLE, st);
+        if (learned)
+          FFC_TRY(learned_rows_level(t, sk, o->proposal, first, count, s_cap, o->seed, st));
+        else
+          FFC_TRY(launch_sample_rows(t, sk, first, count, s_cap, o->seed, st));
       }
-      IdBatch bt{};
-      bt.A = sk->work.ptr;
-      bt.a_stride = (int64_t)s_cap * n_cap;
-      bt.lda = s_cap;
-      bt.s_arr = sk->nrows.ptr + first;
-      bt.n_arr = sk->ncols.ptr + first;
-      bt.s_max = s_cap;
-      bt.n_max = n_cap;
-      bt.tol = o->tol;
-      bt.max_rank = max_rank;
-      bt.rank = sk->rank.ptr + first;
-      bt.piv = sk->piv.ptr + (int64_t)first * n_cap;
-      bt.piv_stride = n_cap;
-      bt.P = sk->P.ptr + (int64_t)first * r_cap * n_cap;
-      bt.p_stride = (int64_t)r_cap * n_cap;
-      bt.p_ld = n_cap;
-      {
-        bool used = false;
-        FFC_TRY(launch_interp_decomp_coop(bt, count, sk->qr_scratch, st, used));
-        if (!used) {
-          StageTimer tm(FFC_STAGE_CPQR, st);
-          FFC_TRY(launch_interp_decomp(bt, count, st));
+      FFC_TRY(skeletonize_level(first, count));
+      if (learned && o->fallback_tol > 0.0) {
+        int redo = 0;
+        FFC_TRY(learned_heldout_level(t, sk, kp, o->precision, first, count, s_cap, o->seed, o->fallback_tol, redo,
+                                      st));
+        if (redo) {   // failed nodes now hold uniform rows; the others recompute identically
+          sk->fallbacks += redo;
+          FFC_TRY(skeletonize_level(first, count));
         }
-      }
-      {
-        StageTimer tm(FFC_STAGE_SKEL, st);
-        FFC_TRY(launch_skeleton_ids(sk, first, count, st));
       }
     }
     return FFC_OK;

@@ -59,6 +59,8 @@ struct KParams {
 };
 
 KParams make_kparams(const ffc_kernel& k, int d);
+// Validates a kernel description for dimension d (sets the error message).
+ffc_status validate_kernel(const ffc_kernel* k, int d);
 
 // Stage profiler: a StageTimer brackets the launches of one stage with events
 // on the stage's stream while profiling is enabled.
@@ -110,6 +112,20 @@ struct DevBuf {
   }
 };
 
+// Column geometry of node blocks for the learned proposal (proposal.hip).
+struct GeomArgs {
+  const int32_t* cols;      // block b's columns at cols + b * col_stride (tree positions)
+  int64_t col_stride;
+  const int32_t* ncols;     // [count]
+  const int32_t* node_ids;  // [count] stream ids of the blocks
+  uint64_t seed;
+  double* cen;              // [count][d]
+  double* rho;              // [count]
+  int32_t* sub;             // [count][256] subsample (tree positions)
+  int32_t* nsub;            // [count]
+  double* U;                // [count][7][d] anchor directions
+};
+
 }  // namespace ffc
 
 struct ffc_tree {
@@ -132,6 +148,28 @@ struct ffc_tree {
   hipStream_t last_stream = nullptr;
 };
 
+struct ffc_proposal {
+  ffc::DevBuf<float> theta, mu, sd;   // parameters and standardization
+  ffc::DevBuf<float> m1, m2;          // Adam moments
+  int32_t step = 0;                   // Adam steps taken
+};
+
+namespace ffc {
+// Scratch of the learned sampler, sized for the widest level of one tree.
+struct LearnedScratch {
+  int32_t p_cap = 0;                  // candidate pool capacity per node
+  DevBuf<int32_t> ids;                // node ids 0..num_nodes-1
+  DevBuf<int32_t> pool, npool;        // num_nodes x p_cap
+  DevBuf<double> cen, rho, U;         // geometry of one level
+  DevBuf<int32_t> sub, nsub;          // 256-point column subsamples
+  DevBuf<float> feat, score;          // level x p_cap (x 16)
+  DevBuf<int32_t> hrows, nheld;       // num_nodes x 32 held-out rows
+  DevBuf<double> Kh;                  // level x 32 x n_cap
+  DevBuf<unsigned char> mask;         // num_nodes
+  DevBuf<unsigned int> counter;       // fallbacks of the current level
+};
+}  // namespace ffc
+
 struct ffc_skel {
   int32_t num_nodes = 0;
   int32_t depth = 0;
@@ -149,6 +187,7 @@ struct ffc_skel {
   ffc::DevBuf<double> qt;                   // num_nodes x r_cap (equivalent charges)
   ffc::DevBuf<double> work;                 // sampled blocks of the widest level
   ffc::DevBuf<unsigned char> qr_scratch;    // group slots / counters of the QR kernel
+  ffc::LearnedScratch learned;              // learned sampler (allocated on first use)
   int32_t fallbacks = 0;
   hipStream_t last_stream = nullptr;
 };
@@ -167,6 +206,17 @@ ffc_status launch_gather_tree_points(ffc_tree* t, hipStream_t st);
 // Uniform row sampling (sample.hip): rows[node] for nodes [first, first+count).
 ffc_status launch_sample_rows(const ffc_tree* t, ffc_skel* sk, int first, int count, int s,
                               uint64_t seed, hipStream_t st);
+// General form: draws into rows + node * cap (counts in nrows[node]) with the
+// Floyd stream node | stream_or; nodes with mask[node] == 0 are skipped when
+// mask is non-null.
+ffc_status launch_sample_rows_into(const ffc_tree* t, int32_t* rows, int32_t* nrows, int cap, int first, int count,
+                                   int s, uint64_t seed, uint32_t stream_or, const unsigned char* mask,
+                                   hipStream_t st);
+// Raw form: range g = [nb[g], ne[g]) of tree positions; draws s of the M
+// positions inside it (inside) or outside it in [0, N), Floyd stream g | stream_or.
+ffc_status launch_draw(const int32_t* nb, const int32_t* ne, int64_t N, bool inside, int32_t* rows, int32_t* nrows,
+                       int cap, int first, int count, int s, uint64_t seed, uint32_t stream_or,
+                       const unsigned char* mask, hipStream_t st);
 
 // Column lists of a level (sample.hip).
 ffc_status launch_level_columns(const ffc_tree* t, ffc_skel* sk, int first, int count, bool leaves,
@@ -176,6 +226,16 @@ ffc_status launch_level_columns(const ffc_tree* t, ffc_skel* sk, int first, int 
 // each s_cap x n_cap column-major with leading dimension s_cap) (kblock.hip).
 ffc_status launch_level_kblock(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision,
                                int first, int count, double* A, hipStream_t st);
+
+// Sampled blocks for nodes [first, first+count) given raw row/column lists
+// (node b: rows + b * s_cap, nrows[b], cols + b * n_cap, ncols[b]; the mixed
+// mode centres block b on centroid + (first + b) * d) (kblock.hip).
+ffc_status launch_kblock_batch(const ffc_tree* t, const KParams& kp, int precision, const int32_t* rows,
+                               const int32_t* nrows, int s_cap, const int32_t* cols, const int32_t* ncols, int n_cap,
+                               int first, int count, const double* centroid, double* A, hipStream_t st);
+
+// Gram matrices of column-major m x n blocks, n x n row-major each (kblock.hip).
+ffc_status launch_gram(const double* B, int m, int n, int count, double* G, hipStream_t st);
 
 // Standalone sampled block (kblock.hip).
 ffc_status launch_sampled_block(const ffc_tree* t, const KParams& kp, int precision, const int32_t* rows,
@@ -217,6 +277,45 @@ ffc_status launch_skeleton_ids(ffc_skel* sk, int first, int count, hipStream_t s
 ffc_status launch_upward(const ffc_tree* t, ffc_skel* sk, int first, int count, bool leaves, hipStream_t st);
 ffc_status launch_charges_to_tree(ffc_tree* t, const double* q, hipStream_t st);
 
+// Learned sampler for one level (api_proposal.hip): candidate pool, geometry,
+// features, scores and selection into sk->rows / sk->nrows.
+ffc_status learned_rows_level(const ffc_tree* t, ffc_skel* sk, const ffc_proposal* p, int first, int count, int s,
+                              uint64_t seed, hipStream_t st);
+// Held-out check of a skeletonized level; returns in `redo` the number of nodes
+// that failed (their mask is set and their rows redrawn uniformly). Synchronizes.
+ffc_status learned_heldout_level(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int precision, int first,
+                                 int count, int s, uint64_t seed, double tol, int& redo, hipStream_t st);
+ffc_status learned_alloc(const ffc_tree* t, ffc_skel* sk, int pool_factor);
+
+// Learned proposal (proposal.hip).
+ffc_status launch_geometry(const double* Xt, int d, const GeomArgs& ga, int count, hipStream_t st);
+ffc_status launch_features(const double* Xt, int d, const GeomArgs& ga, const int32_t* tgt, int tgt_stride,
+                           const int32_t* ntgt, int count, float* feat, int64_t feat_stride, hipStream_t st);
+ffc_status launch_mlp_score(const float* theta, const float* mu, const float* sdv, const float* feat, int64_t count,
+                            float* score, hipStream_t st);
+ffc_status launch_mlp_grad(const float* theta, const float* mu, const float* sdv, const float* feat,
+                           const float* target, int64_t count, int64_t p0, int64_t stride_mul, int64_t total,
+                           float* grads, hipStream_t st);
+ffc_status launch_grad_reduce_adam(const float* grads, int nwg, float* theta, float* m1, float* m2, float* gsum,
+                                   float* loss_out, bool adam, float lr, int step, int64_t total, hipStream_t st);
+ffc_status launch_feature_stats(const float* feat, int64_t count, float* mu, float* sdv, hipStream_t st);
+// Selection for nodes [first, first+count): pool / npool / score indexed by
+// b = node - first, rows / nrows / ncols / mask by node; nodes with an empty
+// column set get nrows = 0.
+ffc_status launch_select_rows(const float* score, int64_t score_stride, const int32_t* pool, int pool_stride,
+                              const int32_t* npool, int first, int count, int s, uint64_t seed, const int32_t* ncols,
+                              const unsigned char* mask, int32_t* rows, int s_cap, int32_t* nrows, hipStream_t st);
+ffc_status launch_heldout_check(const double* Kh, const int32_t* nh, int h_cap, const ffc_skel* sk, int first,
+                                int count, double tol, unsigned char* mask, unsigned int* fallbacks, hipStream_t st);
+
+// Ridge leverage labels (leverage.hip) of row-major m x n blocks B_b: G_b =
+// B_b^T B_b, its Cholesky factor with eps^2 tr(G_b) added to the diagonal,
+// lev[b][i] = |B_b(i, :) L^{-T}|^2 (B overwritten by B L^{-T}) and, when target
+// is non-null, target[b][i] = ln(max(lev, 1e-12) m / sum(lev)).
+// status[b]: 0 factorized, 1 zero block (leverages 0), 2 not positive definite.
+ffc_status launch_ridge_leverage(double* B, int64_t m, int n, int count, double* G, double eps, double* lev,
+                                 float* target, int* status, hipStream_t st);
+
 // Far + near field evaluation (kblock.hip).
 ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision,
                            double* u, double* u_far, hipStream_t st);
@@ -224,8 +323,9 @@ ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams&
 // Mixed-precision (bf16 hi/lo Gram on matrix cores) variants of the sampled
 // blocks, the evaluation and the direct sum for the Gaussian and polynomial
 // kernels (gram_mfma.hip).
-ffc_status launch_level_kblock_mixed(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int first, int count,
-                                     double* A, hipStream_t st);
+ffc_status launch_kblock_batch_mixed(const ffc_tree* t, const KParams& kp, const int32_t* rows, const int32_t* nrows,
+                                     int s_cap, const int32_t* cols, const int32_t* ncols, int n_cap, int first,
+                                     int count, const double* centroid, double* A, hipStream_t st);
 ffc_status launch_evaluate_mixed(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, double* u, double* u_far,
                                  hipStream_t st);
 ffc_status launch_direct_mixed(const double* Y, int64_t m, const double* X, int64_t n, int d, const KParams& kp,

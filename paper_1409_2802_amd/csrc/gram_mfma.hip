@@ -294,18 +294,18 @@ __global__ void __launch_bounds__(NTH) k_direct_mixed(const double* __restrict__
 
 }  // namespace
 
-ffc_status launch_level_kblock_mixed(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int first, int count,
-                                     double* A, hipStream_t st) {
-  const int tiles_m = (sk->s_cap + TM - 1) / TM, tiles_n = (sk->n_cap + TN - 1) / TN;
+ffc_status launch_kblock_batch_mixed(const ffc_tree* t, const KParams& kp, const int32_t* rows, const int32_t* nrows,
+                                     int s_cap, const int32_t* cols, const int32_t* ncols, int n_cap, int first,
+                                     int count, const double* centroid, double* A, hipStream_t st) {
+  const int tiles_m = (s_cap + TM - 1) / TM, tiles_n = (n_cap + TN - 1) / TN;
   const int64_t blocks = (int64_t)count * tiles_m * tiles_n;
+  if (blocks == 0) return FFC_OK;
   if (kp.kind == FFC_POLYNOMIAL)
     hipLaunchKernelGGL(k_level_kblock_mixed<true>, dim3((unsigned)blocks), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
-                       first, tiles_m, tiles_n, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, sk->cols.ptr, sk->ncols.ptr,
-                       sk->n_cap, t->centroid.ptr, A, device_flag());
+                       first, tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, centroid, A, device_flag());
   else
     hipLaunchKernelGGL(k_level_kblock_mixed<false>, dim3((unsigned)blocks), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
-                       first, tiles_m, tiles_n, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, sk->cols.ptr, sk->ncols.ptr,
-                       sk->n_cap, t->centroid.ptr, A, device_flag());
+                       first, tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, centroid, A, device_flag());
   FFC_LAUNCH_CHECK("k_level_kblock_mixed");
   return FFC_OK;
 }

@@ -295,22 +295,59 @@ ffc_status dispatch(int precision, bool dot, F&& f) {
 
 }  // namespace
 
-ffc_status launch_level_kblock(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, int first,
-                               int count, double* A, hipStream_t st) {
+ffc_status launch_kblock_batch(const ffc_tree* t, const KParams& kp, int precision, const int32_t* rows,
+                               const int32_t* nrows, int s_cap, const int32_t* cols, const int32_t* ncols, int n_cap,
+                               int first, int count, const double* centroid, double* A, hipStream_t st) {
   if (precision == FFC_MIXED_BF16X3 && kp.kind != FFC_LAPLACE)
-    return launch_level_kblock_mixed(t, sk, kp, first, count, A, st);
-  const int tiles_m = (sk->s_cap + BM - 1) / BM, tiles_n = (sk->n_cap + BN - 1) / BN;
+    return launch_kblock_batch_mixed(t, kp, rows, nrows, s_cap, cols, ncols, n_cap, first, count, centroid, A, st);
+  const int tiles_m = (s_cap + BM - 1) / BM, tiles_n = (n_cap + BN - 1) / BN;
   const int64_t blocks = (int64_t)count * tiles_m * tiles_n;
+  if (blocks == 0) return FFC_OK;
   const bool dot = kp.kind == FFC_POLYNOMIAL;
   return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
     using T = decltype(tv);
     constexpr bool D = decltype(dv)::value;
     hipLaunchKernelGGL((k_level_kblock<T, D>), dim3((unsigned)blocks), dim3(NT), 0, st, t->Xt.ptr, t->d, kp, first,
-                       tiles_m, tiles_n, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, sk->cols.ptr, sk->ncols.ptr,
-                       sk->n_cap, A, device_flag());
+                       tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, A, device_flag());
     FFC_LAUNCH_CHECK("k_level_kblock");
     return FFC_OK;
   });
+}
+
+ffc_status launch_level_kblock(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, int first,
+                               int count, double* A, hipStream_t st) {
+  return launch_kblock_batch(t, kp, precision, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, sk->cols.ptr, sk->ncols.ptr,
+                             sk->n_cap, first, count, t->centroid.ptr, A, st);
+}
+
+// Gram matrices G_b = B_b^T B_b of column-major m x n blocks (B_b at B + b * m * n):
+// column i of B_b is an m-dimensional point, so the inner-product tile engine applies.
+__global__ void __launch_bounds__(NT) k_gram(const double* __restrict__ B, int m, int n, int tiles,
+                                             double* __restrict__ G) {
+  __shared__ TileSmem<double> sm;
+  const int b = blockIdx.x / (tiles * tiles), tile = blockIdx.x % (tiles * tiles);
+  const int r0 = (tile % tiles) * BM, c0 = (tile / tiles) * BN;
+  const double* Bb = B + (int64_t)b * m * n;
+  double acc[4][4];
+  tile_accumulate<double, true>(Bb, IdxMap{nullptr, r0}, n - r0, Bb, IdxMap{nullptr, c0}, n - c0, m, sm, acc);
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  double* Gb = G + (int64_t)b * n * n;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = r0 + tr + 16 * i, c = c0 + tc + 16 * j;
+      if (r < n && c < n) Gb[(int64_t)r * n + c] = acc[i][j];
+    }
+}
+
+ffc_status launch_gram(const double* B, int m, int n, int count, double* G, hipStream_t st) {
+  const int tiles = (n + BM - 1) / BM;
+  const int64_t blocks = (int64_t)count * tiles * tiles;
+  if (blocks == 0) return FFC_OK;
+  hipLaunchKernelGGL(k_gram, dim3((unsigned)blocks), dim3(NT), 0, st, B, m, n, tiles, G);
+  FFC_LAUNCH_CHECK("k_gram");
+  return FFC_OK;
 }
 
 ffc_status launch_sampled_block(const ffc_tree* t, const KParams& kp, int precision, const int32_t* rows, int s,

@@ -1,0 +1,632 @@
+// Learned row proposal: features, the 16-64-64-1 network (inference,
+// gradients, Adam) and importance selection of target rows.
+//
+// Leverage-score sampling is the paper's gold standard for choosing rows but
+// needs the whole block (Section 3, importance sampling); the cheap geometric
+// heuristics of Section 3.2 motivate learning the map from per-target
+// geometry to leverage. Definitions (shared with the CPU reference):
+//  * column geometry of a node: centroid c and radius rho of its column
+//    points, a 256-point subsample S (Floyd draw, stream node | 2^30, ascending)
+//    and up to 7 anchors of S by farthest-point selection from c;
+//  * 16 features of a target: |y-c|/rho, its log, the 4 smallest |y-x|/rho
+//    over S, their mean over S, log of the smallest, the projections of y - c
+//    on the 7 anchor directions over rho, and a constant 1;
+//  * scores from the network on standardized features; weights 0.9 softmax
+//    + 0.1 uniform over a pool of c s uniform candidates; Efraimidis-Spirakis
+//    keys -ln(U)/w select s rows without replacement.
+#include <climits>
+
+#include "ffc_internal.h"
+
+namespace ffc {
+namespace {
+
+constexpr int NF = 16, NH = 64;
+constexpr int NPARAM = NF * NH + NH + NH * NH + NH + NH + 1;   // 5313
+constexpr int OFF_W1 = 0, OFF_B1 = NF * NH, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH,
+              OFF_B3 = OFF_W3 + NH;
+constexpr int SUB = 256;         // column subsample size
+constexpr int kMaxGeomCols = 16384;   // column-set bitmap capacity (512 words of LDS)
+constexpr int NANCH = 7;
+constexpr uint64_t STREAM_SUBSAMPLE = 1ull << 30, STREAM_KEYS = 3ull << 30;
+
+__device__ inline uint64_t splitmix_first(uint64_t state) {
+  uint64_t z = state + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ inline uint64_t counter_u64(uint64_t seed, uint64_t stream, uint64_t j) {
+  return splitmix_first(seed ^ (stream << 32) ^ j);
+}
+
+// ---------------------------------------------------------------------------
+// Column geometry: one workgroup per node.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt, int d, GeomArgs ga) {
+  __shared__ int sidx[SUB];
+  __shared__ double sd2[SUB], mind[SUB];
+  __shared__ double red[256];
+  __shared__ unsigned int bits[kMaxGeomCols / 32];
+  __shared__ int s_k, anchors[NANCH];
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int n = ga.ncols[b];
+  const int32_t* cols = ga.cols + (int64_t)b * ga.col_stride;
+  double* cen = ga.cen + (int64_t)b * d;
+  const uint64_t node = (uint64_t)ga.node_ids[b];
+  // Centroid (each thread owns dimensions; fixed summation order).
+  for (int k = tid; k < d; k += 256) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += Xt[(int64_t)cols[j] * d + k];
+    cen[k] = n > 0 ? s / n : 0.0;
+  }
+  __syncthreads();
+  // Radius.
+  double mx = 0.0;
+  for (int j = tid; j < n; j += 256) {
+    const double* x = Xt + (int64_t)cols[j] * d;
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) { const double df = x[k] - cen[k]; s = fma(df, df, s); }
+    mx = fmax(mx, s);
+  }
+  red[tid] = mx;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+    __syncthreads();
+  }
+  // Subsample: Floyd's algorithm over {0..n-1} (values t_j drawn in parallel,
+  // the insert rule applied in order against an LDS bitmap), then ascending.
+  const int nwords = (min(n, kMaxGeomCols) + 31) / 32;
+  for (int w = tid; w < nwords; w += 256) bits[w] = 0u;
+  if (n > SUB)
+    for (int q = tid; q < SUB; q += 256) {
+      const int j = n - SUB + q;
+      sidx[q] = (int)__umul64hi(counter_u64(ga.seed, node | STREAM_SUBSAMPLE, (uint64_t)j), (uint64_t)(j + 1));
+    }
+  __syncthreads();
+  if (tid == 0) {
+    const double r = sqrt(red[0]);
+    ga.rho[b] = r > 0.0 ? r : 1.0;
+    int cnt = 0;
+    if (n <= SUB) {
+      for (int j = 0; j < n; ++j) sidx[cnt++] = j;
+    } else {
+      for (int q = 0; q < SUB; ++q) {
+        int t = sidx[q];
+        if (bits[t >> 5] & (1u << (t & 31))) t = n - SUB + q;
+        bits[t >> 5] |= 1u << (t & 31);
+      }
+      for (int w = 0; w < nwords; ++w)
+        for (unsigned int word = bits[w]; word; word &= word - 1) sidx[cnt++] = w * 32 + __ffs(word) - 1;
+    }
+    s_k = cnt;
+  }
+  __syncthreads();
+  const int ns = s_k;
+  int32_t* S_out = ga.sub + (int64_t)b * SUB;
+  for (int q = tid; q < SUB; q += 256) S_out[q] = q < ns ? cols[sidx[q]] : -1;
+  if (tid == 0) ga.nsub[b] = ns;
+  // Anchors: farthest-point selection, starting from the point farthest from c.
+  if (tid < SUB) {
+    double s = -1.0;
+    if (tid < ns) {
+      const double* x = Xt + (int64_t)cols[sidx[tid]] * d;
+      s = 0.0;
+      for (int k = 0; k < d; ++k) { const double df = x[k] - cen[k]; s = fma(df, df, s); }
+    }
+    sd2[tid] = s;
+  }
+  __syncthreads();
+  const int na = min(NANCH, ns);
+  for (int a = 0; a < na; ++a) {
+    if (tid == 0) {
+      const double* key = a == 0 ? sd2 : mind;
+      int best = 0;
+      for (int q = 1; q < ns; ++q)
+        if (key[q] > key[best]) best = q;
+      anchors[a] = best;
+    }
+    __syncthreads();
+    if (tid < ns) {
+      const double* x = Xt + (int64_t)cols[sidx[tid]] * d;
+      const double* y = Xt + (int64_t)cols[sidx[anchors[a]]] * d;
+      double s = 0.0;
+      for (int k = 0; k < d; ++k) { const double df = x[k] - y[k]; s = fma(df, df, s); }
+      mind[tid] = a == 0 ? s : fmin(mind[tid], s);
+    }
+    __syncthreads();
+  }
+  // Anchor directions.
+  double* U = ga.U + (int64_t)b * NANCH * d;
+  for (int a = 0; a < NANCH; ++a) {
+    double nrm2 = 0.0;
+    if (a < na) {
+      const double* y = Xt + (int64_t)cols[sidx[anchors[a]]] * d;
+      for (int k = 0; k < d; ++k) { const double df = y[k] - cen[k]; nrm2 = fma(df, df, nrm2); }
+    }
+    const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+    for (int k = tid; k < d; k += 256)
+      U[(int64_t)a * d + k] = a < na ? (Xt[(int64_t)cols[sidx[anchors[a]]] * d + k] - cen[k]) * inv : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Features: one thread per (node, target).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt, int d, GeomArgs ga,
+                                                  const int32_t* __restrict__ tgt, int tgt_stride,
+                                                  const int32_t* __restrict__ ntgt, int count_nodes,
+                                                  float* __restrict__ feat, int64_t feat_stride) {
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int b = (int)(gid / tgt_stride), i = (int)(gid % tgt_stride);
+  if (b >= count_nodes || i >= ntgt[b]) return;
+  const double* y = Xt + (int64_t)tgt[(int64_t)b * tgt_stride + i] * d;
+  const double* c = ga.cen + (int64_t)b * d;
+  const double rho = ga.rho[b];
+  const int ns = ga.nsub[b];
+  const int32_t* S = ga.sub + (int64_t)b * SUB;
+  double dc = 0.0;
+  for (int k = 0; k < d; ++k) { const double df = y[k] - c[k]; dc = fma(df, df, dc); }
+  dc = sqrt(dc) / rho;
+  double best[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+  double sum = 0.0;
+  for (int q = 0; q < ns; ++q) {
+    const double* x = Xt + (int64_t)S[q] * d;
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) { const double df = y[k] - x[k]; s = fma(df, df, s); }
+    const double v = sqrt(s) / rho;
+    sum += v;
+    if (v < best[3]) {   // keep the 4 smallest, ascending
+      best[3] = v;
+      for (int a = 3; a > 0 && best[a] < best[a - 1]; --a) { const double tt = best[a]; best[a] = best[a - 1]; best[a - 1] = tt; }
+    }
+  }
+  float* f = feat + (int64_t)b * feat_stride + (int64_t)i * NF;
+  f[0] = (float)dc;
+  f[1] = (float)log(dc + 1e-12);
+  for (int q = 0; q < 4; ++q) f[2 + q] = (float)(q < ns ? best[q] : best[max(ns - 1, 0)]);
+  f[6] = (float)(ns > 0 ? sum / ns : 0.0);
+  f[7] = (float)log(best[0] + 1e-12);
+  const double* U = ga.U + (int64_t)b * NANCH * d;
+  for (int a = 0; a < NANCH; ++a) {
+    double p = 0.0;
+    for (int k = 0; k < d; ++k) p = fma(y[k] - c[k], U[(int64_t)a * d + k], p);
+    f[8 + a] = (float)(p / rho);
+  }
+  f[15] = 1.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Network inference: one thread per sample, parameters in LDS.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_mlp_score(const float* __restrict__ theta, const float* __restrict__ mu,
+                                                   const float* __restrict__ sdv, const float* __restrict__ feat,
+                                                   int64_t count, float* __restrict__ score) {
+  __shared__ float w[NPARAM];
+  __shared__ float smu[NF], ssd[NF];
+  for (int p = threadIdx.x; p < NPARAM; p += blockDim.x) w[p] = theta[p];
+  for (int p = threadIdx.x; p < NF; p += blockDim.x) { smu[p] = mu[p]; ssd[p] = sdv[p]; }
+  __syncthreads();
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float z[NF];
+#pragma unroll
+  for (int q = 0; q < NF; ++q) z[q] = (feat[i * NF + q] - smu[q]) / ssd[q];
+  z[NF - 1] = 1.f;
+  float h1[NH];
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    float a = w[OFF_B1 + j];
+#pragma unroll
+    for (int q = 0; q < NF; ++q) a = fmaf(z[q], w[OFF_W1 + q * NH + j], a);
+    h1[j] = fmaxf(a, 0.f);
+  }
+  float y = w[OFF_B3];
+  for (int j = 0; j < NH; ++j) {
+    float a = w[OFF_B2 + j];
+#pragma unroll
+    for (int q = 0; q < NH; ++q) a = fmaf(h1[q], w[OFF_W2 + q * NH + j], a);
+    y = fmaf(fmaxf(a, 0.f), w[OFF_W3 + j], y);
+  }
+  score[i] = y;
+}
+
+// ---------------------------------------------------------------------------
+// Gradients of the mean squared error over sub-batches of 64 samples; one
+// workgroup writes the sum of its samples' contributions (scaled by 1/total).
+// Sample positions p map to rows (p * stride_mul) mod count (a fixed shuffle).
+// ---------------------------------------------------------------------------
+constexpr int GB = 64;
+
+struct GradSmem {
+  float w[NPARAM];
+  float smu[NF], ssd[NF];
+  float Z[GB][NF];
+  float A1[GB][NH];   // pre-activations, later dA1
+  float A2[GB][NH];   // pre-activations, later dA2
+  float dy[GB];
+  float loss[GB];
+};
+
+__global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ theta, const float* __restrict__ mu,
+                                                  const float* __restrict__ sdv, const float* __restrict__ feat,
+                                                  const float* __restrict__ target, int64_t count, int64_t p0,
+                                                  int64_t stride_mul, int64_t total, float* __restrict__ grads) {
+  extern __shared__ float gsm_raw[];
+  GradSmem& sm = *reinterpret_cast<GradSmem*>(gsm_raw);
+  const int tid = threadIdx.x;
+  for (int p = tid; p < NPARAM; p += 256) sm.w[p] = theta[p];
+  for (int p = tid; p < NF; p += 256) { sm.smu[p] = mu[p]; sm.ssd[p] = sdv[p]; }
+  const int64_t base = p0 + (int64_t)blockIdx.x * GB;
+  __syncthreads();
+  const int s = tid >> 2, qd = tid & 3;   // sample, quarter of the hidden units
+  const int64_t pos = base + s;
+  const bool valid = pos < p0 + total;
+  const int64_t row = valid ? (int64_t)(((unsigned __int128)pos * (unsigned __int128)stride_mul) % (unsigned __int128)count) : 0;
+  if (qd == 0) {
+    for (int q = 0; q < NF; ++q) sm.Z[s][q] = valid ? (feat[row * NF + q] - sm.smu[q]) / sm.ssd[q] : 0.f;
+    sm.Z[s][NF - 1] = valid ? 1.f : 0.f;
+  }
+  __syncthreads();
+  for (int j = qd * 16; j < qd * 16 + 16; ++j) {
+    float a = sm.w[OFF_B1 + j];
+    for (int q = 0; q < NF; ++q) a = fmaf(sm.Z[s][q], sm.w[OFF_W1 + q * NH + j], a);
+    sm.A1[s][j] = a;
+  }
+  __syncthreads();
+  float ypart = 0.f;
+  for (int j = qd * 16; j < qd * 16 + 16; ++j) {
+    float a = sm.w[OFF_B2 + j];
+    for (int q = 0; q < NH; ++q) a = fmaf(fmaxf(sm.A1[s][q], 0.f), sm.w[OFF_W2 + q * NH + j], a);
+    sm.A2[s][j] = a;
+    ypart = fmaf(fmaxf(a, 0.f), sm.w[OFF_W3 + j], ypart);
+  }
+  // y = b3 + sum over the four quarters (lanes 4s..4s+3 are adjacent).
+  ypart += __shfl_xor(ypart, 1, 64);
+  ypart += __shfl_xor(ypart, 2, 64);
+  if (qd == 0) {
+    const float y = ypart + sm.w[OFF_B3];
+    const float r = valid ? y - target[row] : 0.f;
+    sm.dy[s] = 2.f * r / (float)total;
+    sm.loss[s] = r * r;
+  }
+  __syncthreads();
+  float* g = grads + (int64_t)blockIdx.x * (NPARAM + 1);
+  // Output layer.
+  if (tid < NH) {
+    float a = 0.f;
+    for (int q = 0; q < GB; ++q) a = fmaf(sm.dy[q], fmaxf(sm.A2[q][tid], 0.f), a);
+    g[OFF_W3 + tid] = a;
+  }
+  if (tid == NH) {
+    float a = 0.f, l = 0.f;
+    for (int q = 0; q < GB; ++q) { a += sm.dy[q]; l += sm.loss[q]; }
+    g[OFF_B3] = a;
+    g[NPARAM] = l;
+  }
+  __syncthreads();
+  // dA2 = dy w3 (A2 > 0), in place.
+  for (int j = qd * 16; j < qd * 16 + 16; ++j) sm.A2[s][j] = sm.A2[s][j] > 0.f ? sm.dy[s] * sm.w[OFF_W3 + j] : 0.f;
+  __syncthreads();
+  // dW2 = H1^T dA2, db2 = sum dA2 (fixed sample order).
+  for (int e = tid; e < NH * NH; e += 256) {
+    const int i = e / NH, j = e % NH;
+    float a = 0.f;
+    for (int q = 0; q < GB; ++q) a = fmaf(fmaxf(sm.A1[q][i], 0.f), sm.A2[q][j], a);
+    g[OFF_W2 + e] = a;
+  }
+  if (tid < NH) {
+    float a = 0.f;
+    for (int q = 0; q < GB; ++q) a += sm.A2[q][tid];
+    g[OFF_B2 + tid] = a;
+  }
+  // dA1 = (dA2 W2^T) (A1 > 0): computed into registers, then stored over A1.
+  float da1[16];
+  for (int jj = 0; jj < 16; ++jj) {
+    const int j = qd * 16 + jj;
+    float a = 0.f;
+    for (int q = 0; q < NH; ++q) a = fmaf(sm.A2[s][q], sm.w[OFF_W2 + j * NH + q], a);
+    da1[jj] = sm.A1[s][j] > 0.f ? a : 0.f;
+  }
+  __syncthreads();
+  for (int jj = 0; jj < 16; ++jj) sm.A1[s][qd * 16 + jj] = da1[jj];
+  __syncthreads();
+  for (int e = tid; e < NF * NH; e += 256) {
+    const int i = e / NH, j = e % NH;
+    float a = 0.f;
+    for (int q = 0; q < GB; ++q) a = fmaf(sm.Z[q][i], sm.A1[q][j], a);
+    g[OFF_W1 + e] = a;
+  }
+  if (tid < NH) {
+    float a = 0.f;
+    for (int q = 0; q < GB; ++q) a += sm.A1[q][tid];
+    g[OFF_B1 + tid] = a;
+  }
+}
+
+// Sum of the workgroup gradients (fixed order; rows of NPARAM + 1 floats, the
+// last one the loss, read only when loss_out is set); optionally one Adam step.
+__global__ void k_grad_reduce_adam(const float* __restrict__ grads, int nwg, float* __restrict__ theta,
+                                   float* __restrict__ m1, float* __restrict__ m2, float* __restrict__ gsum,
+                                   float* __restrict__ loss_out, int adam, float lr, float c1, float c2, int64_t total) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > NPARAM || (p == NPARAM && !loss_out)) return;
+  float a = 0.f;
+  for (int w = 0; w < nwg; ++w) a += grads[(int64_t)w * (NPARAM + 1) + p];
+  if (p == NPARAM) {
+    *loss_out = a / (float)total;
+    return;
+  }
+  if (gsum) gsum[p] = a;
+  if (adam) {
+    const float mm = 0.9f * m1[p] + 0.1f * a;
+    const float vv = 0.999f * m2[p] + 0.001f * a * a;
+    m1[p] = mm;
+    m2[p] = vv;
+    theta[p] -= lr * (mm * c1) / (sqrtf(vv * c2) + 1e-8f);
+  }
+}
+
+// Feature standardization statistics (mean and population std per feature),
+// one workgroup per feature, fixed-order reduction in double.
+__global__ void __launch_bounds__(256) k_feature_stats(const float* __restrict__ feat, int64_t count,
+                                                       float* __restrict__ mu, float* __restrict__ sdv) {
+  __shared__ double r1[256], r2[256];
+  const int f = blockIdx.x;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += 256) {
+    const double v = feat[i * NF + f];
+    s1 += v;
+    s2 += v * v;
+  }
+  r1[threadIdx.x] = s1;
+  r2[threadIdx.x] = s2;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) { r1[threadIdx.x] += r1[threadIdx.x + off]; r2[threadIdx.x] += r2[threadIdx.x + off]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double m = count ? r1[0] / count : 0.0;
+    const double var = count ? fmax(r2[0] / count - m * m, 0.0) : 0.0;
+    mu[f] = f == NF - 1 ? 0.f : (float)m;
+    sdv[f] = f == NF - 1 ? 1.f : (float)fmax(sqrt(var), 1e-6);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Importance selection: one workgroup per node; pool <= 8192 candidates.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(512) k_select_rows(const float* __restrict__ score, int64_t score_stride,
+                                                     const int32_t* __restrict__ pool, int pool_stride,
+                                                     const int32_t* __restrict__ npool, int first, int s_req,
+                                                     uint64_t seed, const int32_t* __restrict__ ncols,
+                                                     const unsigned char* __restrict__ mask,
+                                                     int32_t* __restrict__ rows, int s_cap, int32_t* __restrict__ nrows,
+                                                     int sort_n) {
+  extern __shared__ unsigned char sel_raw[];
+  double* key = reinterpret_cast<double*>(sel_raw);      // sort_n
+  int* idx = reinterpret_cast<int*>(key + sort_n);      // sort_n
+  __shared__ double red[512];
+  const int b = blockIdx.x, node = first + b, tid = threadIdx.x;
+  if (mask && !mask[node]) return;
+  if (ncols[node] == 0) {   // empty column set: nothing to sample for
+    if (tid == 0) nrows[node] = 0;
+    return;
+  }
+  const int P = npool[b];
+  const float* sc = score + (int64_t)b * score_stride;
+  const int32_t* pl = pool + (int64_t)b * pool_stride;
+  int32_t* out = rows + (int64_t)node * s_cap;
+  if (s_req >= P) {   // every candidate is taken
+    for (int i = tid; i < P; i += 512) out[i] = pl[i];
+    if (tid == 0) nrows[node] = P;
+    return;
+  }
+  // softmax: max, then sum of exponentials (double, fixed order per thread + tree).
+  double mx = -INFINITY;
+  for (int i = tid; i < P; i += 512) mx = fmax(mx, (double)sc[i]);
+  red[tid] = mx;
+  __syncthreads();
+  for (int off = 256; off > 0; off >>= 1) {
+    if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+    __syncthreads();
+  }
+  mx = red[0];
+  __syncthreads();
+  double se = 0.0;
+  for (int i = tid; i < P; i += 512) se += exp((double)sc[i] - mx);
+  red[tid] = se;
+  __syncthreads();
+  for (int off = 256; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  se = red[0];
+  for (int i = tid; i < sort_n; i += 512) {
+    if (i < P) {
+      const double wgt = 0.9 * exp((double)sc[i] - mx) / se + 0.1 / P;
+      const double u = ((double)(counter_u64(seed, (uint64_t)node | STREAM_KEYS, (uint64_t)i) >> 11) + 0.5) * 0x1.0p-53;
+      const double kv = -log(u) / wgt;
+      key[i] = isfinite(kv) ? kv : INFINITY;   // a non-finite score is drawn last (by index)
+      idx[i] = i;
+    } else {
+      key[i] = INFINITY;
+      idx[i] = INT_MAX;
+    }
+  }
+  __syncthreads();
+  // Bitonic sort by (key, index).
+  for (int k = 2; k <= sort_n; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = tid; t < sort_n / 2; t += 512) {
+        const int i = (t / j) * 2 * j + (t % j);
+        const bool asc = (i & k) == 0;
+        const double ka = key[i], kb = key[i + j];
+        const int ia = idx[i], ib = idx[i + j];
+        const bool less = kb < ka || (kb == ka && ib < ia);
+        if (less == asc) { key[i] = kb; key[i + j] = ka; idx[i] = ib; idx[i + j] = ia; }
+      }
+      __syncthreads();
+    }
+  // The s smallest keys; then their rows in ascending order (sort the positions,
+  // held exactly as doubles in the key array).
+  // (every real candidate sorts before the padding, so idx[i] < P for i < s_req < P)
+  for (int i = tid; i < sort_n; i += 512) key[i] = i < s_req ? (double)pl[idx[i]] : INFINITY;
+  __syncthreads();
+  for (int k = 2; k <= sort_n; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = tid; t < sort_n / 2; t += 512) {
+        const int i = (t / j) * 2 * j + (t % j);
+        const bool asc = (i & k) == 0;
+        const double ka = key[i], kb = key[i + j];
+        if ((kb < ka) == asc) { key[i] = kb; key[i + j] = ka; }
+      }
+      __syncthreads();
+    }
+  for (int i = tid; i < s_req; i += 512) out[i] = (int32_t)key[i];
+  if (tid == 0) nrows[node] = s_req;
+}
+
+// Held-out residual: err = ||K_h - K_h(:, piv[:r]) P|| / ||K_h|| per node, over
+// the node's nh_arr[node] held-out rows (K_h column-major, leading dimension
+// h_cap); sets the node's fallback mask when err > tol. One workgroup per node.
+__global__ void __launch_bounds__(256) k_heldout_check(const double* __restrict__ Kh, const int32_t* __restrict__ nh_arr,
+                                                       int h_cap, int n_cap,
+                                                       int r_cap, int first, const int32_t* __restrict__ rank,
+                                                       const int32_t* __restrict__ ncols,
+                                                       const int32_t* __restrict__ piv, const double* __restrict__ P,
+                                                       double tol, unsigned char* __restrict__ mask,
+                                                       unsigned int* __restrict__ fallbacks) {
+  __shared__ double r1[256], r2[256];
+  const int b = blockIdx.x, node = first + b, tid = threadIdx.x;
+  const int n = ncols[node], r = rank[node], nh = nh_arr[node];
+  const double* K = Kh + (int64_t)b * h_cap * n_cap;   // column-major h_cap x n
+  const int32_t* pv = piv + (int64_t)node * n_cap;
+  const double* Pn = P + (int64_t)node * r_cap * n_cap;
+  double num = 0.0, den = 0.0;
+  for (int e = tid; e < nh * n; e += 256) {
+    const int h = e % nh, j = e / nh;
+    const double kv = K[(int64_t)j * h_cap + h];
+    double approx = 0.0;
+    for (int i = 0; i < r; ++i) approx = fma(K[(int64_t)pv[i] * h_cap + h], Pn[(int64_t)i * n_cap + j], approx);
+    const double res = kv - approx;
+    num = fma(res, res, num);
+    den = fma(kv, kv, den);
+  }
+  r1[tid] = num;
+  r2[tid] = den;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (tid < off) { r1[tid] += r1[tid + off]; r2[tid] += r2[tid + off]; }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double err = r2[0] > 0.0 ? sqrt(r1[0] / r2[0]) : 0.0;
+    const bool fall = err > tol;
+    mask[node] = fall ? 1 : 0;
+    if (fall) atomicAdd(fallbacks, 1u);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+ffc_status launch_geometry(const double* Xt, int d, const GeomArgs& ga, int count, hipStream_t st) {
+  if (count <= 0) return FFC_OK;
+  if (ga.col_stride > kMaxGeomCols) {
+    set_error("column sets above 16384 points are not supported by the proposal features");
+    return FFC_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(k_geometry, dim3(count), dim3(256), 0, st, Xt, d, ga);
+  FFC_LAUNCH_CHECK("k_geometry");
+  return FFC_OK;
+}
+
+ffc_status launch_features(const double* Xt, int d, const GeomArgs& ga, const int32_t* tgt, int tgt_stride,
+                           const int32_t* ntgt, int count, float* feat, int64_t feat_stride, hipStream_t st) {
+  const int64_t threads = (int64_t)count * tgt_stride;
+  if (threads <= 0) return FFC_OK;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, Xt, d, ga, tgt, tgt_stride,
+                     ntgt, count, feat, feat_stride);
+  FFC_LAUNCH_CHECK("k_features");
+  return FFC_OK;
+}
+
+ffc_status launch_mlp_score(const float* theta, const float* mu, const float* sdv, const float* feat, int64_t count,
+                            float* score, hipStream_t st) {
+  if (count <= 0) return FFC_OK;
+  hipLaunchKernelGGL(k_mlp_score, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, theta, mu, sdv, feat, count,
+                     score);
+  FFC_LAUNCH_CHECK("k_mlp_score");
+  return FFC_OK;
+}
+
+ffc_status launch_mlp_grad(const float* theta, const float* mu, const float* sdv, const float* feat,
+                           const float* target, int64_t count, int64_t p0, int64_t stride_mul, int64_t total,
+                           float* grads, hipStream_t st) {
+  const int nwg = (int)((total + GB - 1) / GB);
+  const size_t lds = sizeof(GradSmem);
+  static bool attr = false;
+  if (!attr) {
+    FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_grad),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nwg), dim3(256), lds, st, theta, mu, sdv, feat, target, count, p0, stride_mul,
+                     total, grads);
+  FFC_LAUNCH_CHECK("k_mlp_grad");
+  return FFC_OK;
+}
+
+ffc_status launch_grad_reduce_adam(const float* grads, int nwg, float* theta, float* m1, float* m2, float* gsum,
+                                   float* loss_out, bool adam, float lr, int step, int64_t total, hipStream_t st) {
+  // Bias corrections 1 / (1 - beta^t), formed in double (1 - 0.999f alone is
+  // off by 1.3e-5 relative).
+  const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, step))), c2 = (float)(1.0 / (1.0 - std::pow(0.999, step)));
+  hipLaunchKernelGGL(k_grad_reduce_adam, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, st, grads, nwg, theta, m1, m2,
+                     gsum, loss_out, adam ? 1 : 0, lr, c1, c2, total);
+  FFC_LAUNCH_CHECK("k_grad_reduce_adam");
+  return FFC_OK;
+}
+
+ffc_status launch_feature_stats(const float* feat, int64_t count, float* mu, float* sdv, hipStream_t st) {
+  hipLaunchKernelGGL(k_feature_stats, dim3(NF), dim3(256), 0, st, feat, count, mu, sdv);
+  FFC_LAUNCH_CHECK("k_feature_stats");
+  return FFC_OK;
+}
+
+ffc_status launch_select_rows(const float* score, int64_t score_stride, const int32_t* pool, int pool_stride,
+                              const int32_t* npool, int first, int count, int s, uint64_t seed, const int32_t* ncols,
+                              const unsigned char* mask, int32_t* rows, int s_cap, int32_t* nrows, hipStream_t st) {
+  if (count <= 0) return FFC_OK;
+  int sort_n = 1;
+  while (sort_n < pool_stride) sort_n <<= 1;
+  const size_t lds = (size_t)sort_n * (sizeof(double) + sizeof(int));
+  if (lds > 150 * 1024) {
+    set_error("candidate pool too large for the selection kernel");
+    return FFC_ERR_INVALID_ARG;
+  }
+  if (lds > 64 * 1024)
+    FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select_rows),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_select_rows, dim3(count), dim3(512), lds, st, score, score_stride, pool, pool_stride, npool,
+                     first, s, seed, ncols, mask, rows, s_cap, nrows, sort_n);
+  FFC_LAUNCH_CHECK("k_select_rows");
+  return FFC_OK;
+}
+
+ffc_status launch_heldout_check(const double* Kh, const int32_t* nh, int h_cap, const ffc_skel* sk, int first,
+                                int count, double tol, unsigned char* mask, unsigned int* fallbacks, hipStream_t st) {
+  if (count <= 0) return FFC_OK;
+  hipLaunchKernelGGL(k_heldout_check, dim3(count), dim3(256), 0, st, Kh, nh, h_cap, sk->n_cap, sk->r_cap, first,
+                     sk->rank.ptr, sk->ncols.ptr, sk->piv.ptr, sk->P.ptr, tol, mask, fallbacks);
+  FFC_LAUNCH_CHECK("k_heldout_check");
+  return FFC_OK;
+}
+
+}  // namespace ffc

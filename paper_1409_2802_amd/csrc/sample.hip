@@ -27,20 +27,24 @@ __device__ inline uint64_t splitmix_first(uint64_t state) {
 }
 
 __global__ void k_sample_rows(const int32_t* __restrict__ nb, const int32_t* __restrict__ ne, int64_t N, int first,
-                              int s, int s_cap, int sort_n, uint64_t seed, int32_t* __restrict__ rows,
+                              int s, int s_cap, int sort_n, uint64_t seed, uint32_t stream_or, int inside,
+                              const unsigned char* __restrict__ mask, int32_t* __restrict__ rows,
                               int32_t* __restrict__ nrows) {
   extern __shared__ int set[];   // sort_n ints (power of two >= s)
   const int node = first + blockIdx.x;
   const int lane = threadIdx.x;
+  if (mask && !mask[node]) return;
   const int b = nb[node], e = ne[node];
-  const int64_t M = N - (e - b);
+  const int64_t M = inside ? (e - b) : N - (e - b);
+  // Candidate t -> tree position: inside the range, or around it.
+  const int lo = inside ? 0 : b, shift = inside ? b : e - b;
   int32_t* out = rows + (int64_t)node * s_cap;
   if (s >= M) {
-    for (int64_t i = lane; i < M; i += 64) out[i] = (int32_t)(i < b ? i : i + (e - b));
+    for (int64_t i = lane; i < M; i += 64) out[i] = (int32_t)(i < lo ? i : i + shift);
     if (lane == 0) nrows[node] = (int32_t)M;
     return;
   }
-  const uint64_t stream = (uint64_t)(uint32_t)node << 32;
+  const uint64_t stream = (uint64_t)((uint32_t)node | stream_or) << 32;
   int cnt = 0;
   for (int64_t j = M - s; j < M; ++j) {
     const uint64_t u = splitmix_first(seed ^ stream ^ (uint64_t)j);
@@ -67,7 +71,7 @@ __global__ void k_sample_rows(const int32_t* __restrict__ nb, const int32_t* __r
   }
   for (int i = lane; i < s; i += 64) {
     const int t = set[i];
-    out[i] = t < b ? t : t + (e - b);
+    out[i] = t < lo ? t : t + shift;
   }
   if (lane == 0) nrows[node] = s;
 }
@@ -82,23 +86,27 @@ constexpr int kBitmapThreads = 256;
 
 __global__ void __launch_bounds__(kBitmapThreads)
 k_sample_rows_bitmap(const int32_t* __restrict__ nb, const int32_t* __restrict__ ne, int64_t N, int first, int s,
-                     int s_cap, uint64_t seed, int32_t* __restrict__ rows, int32_t* __restrict__ nrows) {
+                     int s_cap, uint64_t seed, uint32_t stream_or, int inside,
+                     const unsigned char* __restrict__ mask, int32_t* __restrict__ rows,
+                     int32_t* __restrict__ nrows) {
   extern __shared__ unsigned int bits[];            // nwords bitmap words, then s ints of t values
   __shared__ int wsum[kBitmapThreads];
   const int node = first + blockIdx.x;
   const int tid = threadIdx.x;
+  if (mask && !mask[node]) return;
   const int b = nb[node], e = ne[node];
-  const int M = (int)(N - (e - b));
+  const int M = inside ? e - b : (int)(N - (e - b));
+  const int lo = inside ? 0 : b, shift = inside ? b : e - b;
   int32_t* out = rows + (int64_t)node * s_cap;
   if (s >= M) {
-    for (int i = tid; i < M; i += kBitmapThreads) out[i] = i < b ? i : i + (e - b);
+    for (int i = tid; i < M; i += kBitmapThreads) out[i] = i < lo ? i : i + shift;
     if (tid == 0) nrows[node] = M;
     return;
   }
   const int nwords = (M + 31) / 32;
   int* tv = reinterpret_cast<int*>(bits + nwords);
   for (int w = tid; w < nwords; w += kBitmapThreads) bits[w] = 0u;
-  const uint64_t stream = (uint64_t)(uint32_t)node << 32;
+  const uint64_t stream = (uint64_t)((uint32_t)node | stream_or) << 32;
   for (int q = tid; q < s; q += kBitmapThreads) {
     const int64_t j = (int64_t)(M - s) + q;
     const uint64_t u = splitmix_first(seed ^ stream ^ (uint64_t)j);
@@ -137,7 +145,7 @@ k_sample_rows_bitmap(const int32_t* __restrict__ nb, const int32_t* __restrict__
       const int bit = __ffs(word) - 1;
       word &= word - 1;
       const int t = w * 32 + bit;
-      out[pos++] = t < b ? t : t + (e - b);
+      out[pos++] = t < lo ? t : t + shift;
     }
   }
   if (tid == 0) nrows[node] = s;
@@ -164,22 +172,44 @@ __global__ void k_level_columns(const int32_t* __restrict__ nb, const int32_t* _
 
 }  // namespace
 
-ffc_status launch_sample_rows(const ffc_tree* t, ffc_skel* sk, int first, int count, int s, uint64_t seed,
-                              hipStream_t st) {
-  const int64_t nwords = (t->N + 31) / 32;
+ffc_status launch_draw(const int32_t* nb, const int32_t* ne, int64_t N, bool inside, int32_t* rows, int32_t* nrows,
+                       int cap, int first, int count, int s, uint64_t seed, uint32_t stream_or,
+                       const unsigned char* mask, hipStream_t st) {
+  if (count <= 0) return FFC_OK;
+  if (s > cap) {
+    set_error("row sample larger than its buffer");
+    return FFC_ERR_INVALID_ARG;
+  }
+  const int64_t nwords = (N + 31) / 32;
   const size_t lds = (size_t)nwords * sizeof(unsigned int) + (size_t)s * sizeof(int);
   if (nwords <= kMaxBitmapWords && lds <= 64 * 1024) {
-    hipLaunchKernelGGL(k_sample_rows_bitmap, dim3(count), dim3(kBitmapThreads), lds, st, t->begin.ptr, t->end.ptr,
-                       t->N, first, s, sk->s_cap, seed, sk->rows.ptr, sk->nrows.ptr);
+    hipLaunchKernelGGL(k_sample_rows_bitmap, dim3(count), dim3(kBitmapThreads), lds, st, nb, ne, N, first, s, cap,
+                       seed, stream_or, inside ? 1 : 0, mask, rows, nrows);
     FFC_LAUNCH_CHECK("k_sample_rows_bitmap");
     return FFC_OK;
   }
   int sort_n = 1;
   while (sort_n < s) sort_n <<= 1;
-  hipLaunchKernelGGL(k_sample_rows, dim3(count), dim3(64), (size_t)sort_n * sizeof(int), st, t->begin.ptr, t->end.ptr, t->N, first, s,
-                     sk->s_cap, sort_n, seed, sk->rows.ptr, sk->nrows.ptr);
+  if ((size_t)sort_n * sizeof(int) > 64 * 1024) {
+    set_error("row sample too large for the sampling kernel");
+    return FFC_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(k_sample_rows, dim3(count), dim3(64), (size_t)sort_n * sizeof(int), st, nb, ne, N, first, s, cap,
+                     sort_n, seed, stream_or, inside ? 1 : 0, mask, rows, nrows);
   FFC_LAUNCH_CHECK("k_sample_rows");
   return FFC_OK;
+}
+
+ffc_status launch_sample_rows_into(const ffc_tree* t, int32_t* rows, int32_t* nrows, int cap, int first, int count,
+                                   int s, uint64_t seed, uint32_t stream_or, const unsigned char* mask,
+                                   hipStream_t st) {
+  return launch_draw(t->begin.ptr, t->end.ptr, t->N, false, rows, nrows, cap, first, count, s, seed, stream_or, mask,
+                     st);
+}
+
+ffc_status launch_sample_rows(const ffc_tree* t, ffc_skel* sk, int first, int count, int s, uint64_t seed,
+                              hipStream_t st) {
+  return launch_sample_rows_into(t, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, first, count, s, seed, 0u, nullptr, st);
 }
 
 ffc_status launch_level_columns(const ffc_tree* t, ffc_skel* sk, int first, int count, bool leaves,

@@ -28,7 +28,13 @@ EXPORTS = [
     "ffc_skeletonize_nodes", "ffc_evaluate_sum", "ffc_direct_sum", "ffc_sampled_block",
     "ffc_interp_decomp", "ffc_skel_node", "ffc_skel_stats", "ffc_check_device",
     "ffc_free_tree", "ffc_free_skel", "ffc_last_error", "ffc_profile_enable", "ffc_profile_read",
+    "ffc_proposal_create", "ffc_proposal_get", "ffc_proposal_free", "ffc_proposal_features",
+    "ffc_proposal_fit_standardization", "ffc_proposal_score", "ffc_proposal_gradient", "ffc_proposal_adam",
+    "ffc_leverage_labels", "ffc_proposal_train", "ffc_proposal_training_set",
 ]
+
+NPARAM = 5313
+NFEAT = 16
 
 STAGES = ["tree", "sample", "columns", "kblock", "cpqr", "skel", "upward", "evaluate", "direct", "solve"]
 
@@ -46,13 +52,19 @@ class KernelC(ctypes.Structure):
 class SkelOptsC(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_rank", ctypes.c_int32), ("num_samples", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("sampler", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("proposal", ctypes.c_void_p), ("fallback_tol", ctypes.c_double)]
+                ("proposal", ctypes.c_void_p), ("fallback_tol", ctypes.c_double), ("pool_factor", ctypes.c_int32)]
 
 
 class StatsC(ctypes.Structure):
     _fields_ = [("num_nodes", ctypes.c_int32), ("rank_min", ctypes.c_int32), ("rank_max", ctypes.c_int32),
                 ("rank_mean", ctypes.c_double), ("rank_cap_hits", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
                 ("kernel_evals", ctypes.c_double)]
+
+
+class TrainOptsC(ctypes.Structure):
+    _fields_ = [("num_blocks", ctypes.c_int32), ("block_cols", ctypes.c_int32), ("block_rows", ctypes.c_int32),
+                ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("eps", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 _lib = None
@@ -83,6 +95,17 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ffc_check_device": [P],
         "ffc_profile_enable": [I32],
         "ffc_profile_read": [P, P, I32, I32],
+        "ffc_proposal_create": [P, P, P, PP],
+        "ffc_proposal_get": [P, P, P, P],
+        "ffc_proposal_features": [P, P, I32, P, P, P, I32, P, I32, U64, P, P],
+        "ffc_proposal_fit_standardization": [P, P, I64, P],
+        "ffc_proposal_score": [P, P, I64, P, P],
+        "ffc_proposal_gradient": [P, P, P, I64, P, P, P],
+        "ffc_proposal_adam": [P, P, ctypes.c_float, P],
+        "ffc_leverage_labels": [P, I64, I32, I32, D, P, P, P],
+        "ffc_proposal_train": [P, P, ctypes.POINTER(KernelC), ctypes.POINTER(TrainOptsC), P, P],
+        "ffc_proposal_training_set": [P, ctypes.POINTER(KernelC), ctypes.POINTER(TrainOptsC), P, P, P, P, P, P, P,
+                                      P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -92,6 +115,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ffc_free_tree.restype = None
     lib.ffc_free_skel.argtypes = [P]
     lib.ffc_free_skel.restype = None
+    lib.ffc_proposal_free.argtypes = [P]
+    lib.ffc_proposal_free.restype = None
     lib.ffc_last_error.argtypes = []
     lib.ffc_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -223,9 +248,13 @@ class Skeletons:
 
 def skeletonize(tree: Tree, kernel: Kernel, tol: float, max_rank: int, num_samples: int = 0,
                 precision: int = FP64, seed: int = 0, reuse: Skeletons | None = None,
+                proposal: "Proposal | None" = None, fallback_tol: float = 0.0, pool_factor: int = 0,
                 stream=None) -> Skeletons:
+    """Skeletonize every non-root node; with `proposal` the rows come from the learned sampler."""
     opts = SkelOptsC(tol=tol, max_rank=max_rank, num_samples=num_samples, precision=precision,
-                     sampler=SAMPLE_UNIFORM, seed=seed, proposal=None, fallback_tol=0.0)
+                     sampler=SAMPLE_LEARNED if proposal is not None else SAMPLE_UNIFORM, seed=seed,
+                     proposal=proposal.handle if proposal is not None else None, fallback_tol=fallback_tol,
+                     pool_factor=pool_factor)
     h = ctypes.c_void_p(reuse.handle.value if reuse is not None else None)
     k = kernel.c_struct()
     _check(load_library().ffc_skeletonize_nodes(tree.handle, ctypes.byref(k), ctypes.byref(opts), _stream(stream),
@@ -305,3 +334,126 @@ def profile_read(reset: bool = True) -> dict:
     cnt = np.zeros(n, dtype=np.int64)
     _check(load_library().ffc_profile_read(ms.ctypes.data, cnt.ctypes.data, n, 1 if reset else 0))
     return {name: {"ms": float(ms[i]), "launches": int(cnt[i])} for i, name in enumerate(STAGES)}
+
+
+# ---------------------------------------------------------------------------
+# Learned row proposal
+# ---------------------------------------------------------------------------
+def _dev_f32(x, name: str) -> torch.Tensor:
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32))
+    if not x.is_cuda:
+        x = x.to("cuda")
+    if x.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    return x.contiguous()
+
+
+class Proposal:
+    """Handle to the 16-64-64-1 proposal network (parameters, standardization, Adam state)."""
+
+    def __init__(self, theta, mu=None, sd=None):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        if th.shape != (NPARAM,):
+            raise ValueError(f"theta must have {NPARAM} entries")
+        m = None if mu is None else np.ascontiguousarray(mu, dtype=np.float32)
+        v = None if sd is None else np.ascontiguousarray(sd, dtype=np.float32)
+        h = ctypes.c_void_p()
+        _check(load_library().ffc_proposal_create(th.ctypes.data, None if m is None else m.ctypes.data,
+                                                  None if v is None else v.ctypes.data, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def get(self):
+        th = np.empty(NPARAM, dtype=np.float32)
+        mu = np.empty(NFEAT, dtype=np.float32)
+        sd = np.empty(NFEAT, dtype=np.float32)
+        _check(load_library().ffc_proposal_get(self._h, th.ctypes.data, mu.ctypes.data, sd.ctypes.data))
+        return th, mu, sd
+
+    def fit_standardization(self, feat: torch.Tensor, stream=None) -> None:
+        f = _dev_f32(feat, "feat")
+        _check(load_library().ffc_proposal_fit_standardization(self._h, _ptr(f), f.shape[0], _stream(stream)))
+
+    def score(self, feat: torch.Tensor, stream=None) -> torch.Tensor:
+        f = _dev_f32(feat, "feat")
+        out = torch.empty(f.shape[0], dtype=torch.float32, device="cuda")
+        _check(load_library().ffc_proposal_score(self._h, _ptr(f), f.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def gradient(self, feat: torch.Tensor, target: torch.Tensor, stream=None):
+        f, t = _dev_f32(feat, "feat"), _dev_f32(target, "target")
+        g = torch.empty(NPARAM, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(load_library().ffc_proposal_gradient(self._h, _ptr(f), _ptr(t), f.shape[0], _ptr(g), _ptr(loss),
+                                                    _stream(stream)))
+        return float(loss.item()), g
+
+    def adam(self, grad: torch.Tensor, lr: float, stream=None) -> None:
+        g = _dev_f32(grad, "grad")
+        _check(load_library().ffc_proposal_adam(self._h, _ptr(g), lr, _stream(stream)))
+
+    def train(self, tree: Tree, kernel: Kernel, num_blocks: int, block_cols: int, block_rows: int, epochs: int,
+              batch: int, lr: float, eps: float, seed: int = 0, stream=None) -> np.ndarray:
+        """Builds the training set on the GPU and trains; returns the per-epoch loss."""
+        o = TrainOptsC(num_blocks=num_blocks, block_cols=block_cols, block_rows=block_rows, epochs=epochs,
+                       batch=batch, lr=lr, eps=eps, seed=seed)
+        loss = np.zeros(max(epochs, 1), dtype=np.float32)
+        k = kernel.c_struct()
+        _check(load_library().ffc_proposal_train(self._h, tree.handle, ctypes.byref(k), ctypes.byref(o),
+                                                 loss.ctypes.data, _stream(stream)))
+        return loss[:epochs]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ffc_proposal_free(self._h)
+            self._h = None
+
+
+def proposal_features(tree: Tree, cols, ncols, ids, tgt, ntgt, seed: int, stream=None) -> torch.Tensor:
+    """Features (count, tgt_stride, 16) of targets tgt[g, :ntgt[g]] against columns cols[g, :ncols[g]]."""
+    cd, nc, idd, td, nt = _dev_i32(cols), _dev_i32(ncols), _dev_i32(ids), _dev_i32(tgt), _dev_i32(ntgt)
+    count, col_stride = cd.shape
+    tgt_stride = td.shape[1]
+    feat = torch.full((count, tgt_stride, NFEAT), float("nan"), dtype=torch.float32, device="cuda")
+    _check(load_library().ffc_proposal_features(tree.handle, _ptr(cd), col_stride, _ptr(nc), _ptr(idd), _ptr(td),
+                                                tgt_stride, _ptr(nt), count, seed, _ptr(feat), _stream(stream)))
+    return feat
+
+
+def leverage_labels(B, eps: float, stream=None):
+    """Ridge leverages and targets of the rows of blocks B (count, m, n)."""
+    Bd = _dev_f64(B, "B")
+    if Bd.dim() == 2:
+        Bd = Bd[None]
+    count, m, n = Bd.shape
+    lev = torch.empty((count, m), dtype=torch.float64, device="cuda")
+    tgt = torch.empty((count, m), dtype=torch.float32, device="cuda")
+    _check(load_library().ffc_leverage_labels(_ptr(Bd), m, n, count, eps, _ptr(lev), _ptr(tgt), _stream(stream)))
+    return lev, tgt
+
+
+def training_set(tree: Tree, kernel: Kernel, num_blocks: int, block_cols: int, block_rows: int, eps: float,
+                 seed: int = 0, stream=None) -> dict:
+    """The proposal's training set as built on the GPU (leaves, columns, targets, features, labels)."""
+    o = TrainOptsC(num_blocks=num_blocks, block_cols=block_cols, block_rows=block_rows, epochs=0, batch=1, lr=1e-3,
+                   eps=eps, seed=seed)
+    k = kernel.c_struct()
+    n, m = ctypes.c_int32(), ctypes.c_int32()
+    lib = load_library()
+    _check(lib.ffc_proposal_training_set(tree.handle, ctypes.byref(k), ctypes.byref(o), ctypes.byref(n),
+                                         ctypes.byref(m), None, None, None, None, None, None, _stream(stream)))
+    n, m = n.value, m.value
+    G = num_blocks
+    leaves = torch.empty(G, dtype=torch.int32, device="cuda")
+    cols = torch.empty((G, n), dtype=torch.int32, device="cuda")
+    rows = torch.empty((G, m), dtype=torch.int32, device="cuda")
+    feat = torch.empty((G * m, NFEAT), dtype=torch.float32, device="cuda")
+    tgt = torch.empty(G * m, dtype=torch.float32, device="cuda")
+    lev = torch.empty(G * m, dtype=torch.float64, device="cuda")
+    _check(lib.ffc_proposal_training_set(tree.handle, ctypes.byref(k), ctypes.byref(o), None, None, _ptr(leaves),
+                                         _ptr(cols), _ptr(rows), _ptr(feat), _ptr(tgt), _ptr(lev), _stream(stream)))
+    return {"n": n, "m": m, "leaves": leaves, "cols": cols, "rows": rows, "feat": feat, "target": tgt, "lev": lev}

@@ -1,0 +1,306 @@
+"""Learned row proposal on the GPU against the oracle: features, network
+scores, gradients, Adam, standardization, ridge leverage labels, the training
+set, training, learned skeletonization with its held-out fallback, and the
+gain over uniform sampling (Section 3 importance sampling; Section 3.2
+cheap heuristics; Section 4.1.3 sampling distributions)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import proposal as pr
+from oracle.evaluate import evaluate as o_evaluate
+from oracle.evaluate import exact_far_field
+from oracle.kernels import GAUSSIAN, LAPLACE, kernel_matrix
+from oracle.skeleton import skeletonize as o_skeletonize
+from oracle.tree import build_tree as o_build_tree
+from paper_1409_2802_amd import workloads as W
+from tests._parity import FP64_REL, gkernel, okernel, rel, unambiguous
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def ffc():
+    from paper_1409_2802_amd import ffc as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.load_library()
+    return m
+
+
+def trees(ffc, X, leaf):
+    t = ffc.build_tree(X, leaf)
+    ot = o_build_tree(X, leaf)
+    np.testing.assert_array_equal(t.arrays()["perm"], ot.perm)
+    return t, ot
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def test_features_match_oracle(ffc):
+    X = W.gaussian_mixture(3000, 6, k=8, box=6.0, std=0.5, seed=0)
+    t, ot = trees(ffc, X, 200)
+    Xt = X[ot.perm]
+    rng = np.random.default_rng(4)
+    ncols = [1, 3, 50, 256, 700]              # single point, fewer than 4, below / at / above the subsample
+    ntgt = [10, 77, 300, 64, 129]
+    ids = [3, 17, 100, 5, 1 << 20]
+    cs, ts = max(ncols), max(ntgt)
+    cols = np.zeros((5, cs), dtype=np.int32)
+    tgt = np.zeros((5, ts), dtype=np.int32)
+    for g in range(5):
+        cols[g, :ncols[g]] = np.sort(rng.choice(3000, ncols[g], replace=False))
+        tgt[g, :ntgt[g]] = rng.choice(3000, ntgt[g], replace=False)
+    feat = ffc.proposal_features(t, cols, ncols, ids, tgt, ntgt, seed=11).cpu().numpy()
+    for g in range(5):
+        geo = pr.column_geometry(Xt[cols[g, :ncols[g]]], 11, ids[g])
+        F = pr.features(Xt[tgt[g, :ntgt[g]]], geo)
+        np.testing.assert_allclose(feat[g, :ntgt[g]], F, rtol=1e-6, atol=1e-6, err_msg=f"block {g}")
+
+
+def _mlp_magnitude(theta, Z):
+    """S_i = |w3|^T (|W2|^T (|W1|^T |z_i| + |b1|) + |b2|) + |b3|: bounds every
+    partial sum of the forward pass, so float32 evaluation errs by <= 65 u S."""
+    W1, b1, W2, b2, w3, b3 = (np.abs(a) for a in pr.unpack(theta))
+    h1 = np.abs(Z) @ W1 + b1
+    h2 = h1 @ W2 + b2
+    return h2 @ w3 + b3
+
+
+def test_scores_match_oracle(ffc):
+    rng = np.random.default_rng(5)
+    theta = f32(W.mlp_init(5) + 0.05 * rng.standard_normal(pr.NPARAM))
+    mu = f32(rng.standard_normal(16))
+    sd = f32(0.5 + rng.random(16))
+    F = f32(2.0 * rng.standard_normal((1000, 16)))
+    F[:, 15] = 1.0
+    p = ffc.Proposal(theta, mu, sd)
+    y = p.score(torch.tensor(F, dtype=torch.float32, device="cuda")).cpu().numpy().astype(np.float64)
+    Z = pr.standardize(F, mu, sd)
+    yo, _ = pr.mlp_forward(theta, Z)
+    bound = 80 * U32 * _mlp_magnitude(theta, Z) + 1e-6
+    assert np.all(np.abs(y - yo) <= bound), float(np.max(np.abs(y - yo) / bound))
+
+
+def test_gradient_matches_oracle(ffc):
+    rng = np.random.default_rng(6)
+    theta = f32(W.mlp_init(5))
+    mu = f32(rng.standard_normal(16) * 0.1)
+    sd = f32(1.0 + rng.random(16))
+    F = f32(rng.standard_normal((1000, 16)))   # 15 full sub-batches of 64 and a tail of 40
+    F[:, 15] = 1.0
+    tg = f32(rng.standard_normal(1000) * 3.0)
+    p = ffc.Proposal(theta, mu, sd)
+    loss, g = p.gradient(torch.tensor(F, dtype=torch.float32, device="cuda"),
+                         torch.tensor(tg, dtype=torch.float32, device="cuda"))
+    lo, go = pr.mlp_loss_grad(theta, pr.standardize(F, mu, sd), tg)
+    assert abs(loss - lo) <= 1e-5 * lo
+    assert rel(g.cpu().numpy().astype(np.float64), go) <= 1e-4
+
+
+def test_adam_matches_oracle(ffc):
+    rng = np.random.default_rng(7)
+    theta0 = f32(W.mlp_init(5))
+    p = ffc.Proposal(theta0)
+    th, m1, m2 = theta0.copy(), np.zeros(pr.NPARAM), np.zeros(pr.NPARAM)
+    moved = 0.0
+    for step, lr in ((1, 1e-3), (2, 3e-3)):
+        g = f32(rng.standard_normal(pr.NPARAM) * 10.0 ** rng.uniform(-6, 0, pr.NPARAM))
+        p.adam(torch.tensor(g, dtype=torch.float32, device="cuda"), lr)
+        th, m1, m2 = pr.adam_step(th, m1, m2, g, step, lr=lr)
+        got = p.get()[0].astype(np.float64)
+        # Each update is at most a few lr in size and is formed in float32
+        # (about 10 roundings); theta itself is stored in float32.
+        moved += 3 * lr
+        np.testing.assert_allclose(got, th, rtol=2 * U32, atol=10 * U32 * moved)
+
+
+def test_fit_standardization_matches_oracle(ffc):
+    rng = np.random.default_rng(8)
+    F = f32(rng.standard_normal((5000, 16)) * rng.uniform(0.1, 10, 16) + rng.uniform(-5, 5, 16))
+    F[:, 3] = 2.5                                   # constant feature: floored sd
+    p = ffc.Proposal(W.mlp_init(5))
+    p.fit_standardization(torch.tensor(F, dtype=torch.float32, device="cuda"))
+    _, mu, sd = p.get()
+    muo, sdo = pr.fit_standardization(F)
+    np.testing.assert_allclose(mu, muo, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(sd, sdo, rtol=1e-5)
+    assert mu[15] == 0.0 and sd[15] == 1.0
+
+
+def _lev_tol(n, eps):
+    # Cholesky of G + lambda I in FP64: relative backward error ~ n u, amplified
+    # by cond(G + lambda I) <= 1 + 1 / eps^2; leverages lie in [0, 1].
+    return 10 * n * U64 * (1.0 + 1.0 / eps ** 2)
+
+
+@pytest.mark.parametrize("shape,kind", [((300, 100), "kernel"), ((130, 70), "gauss"), ((50, 120), "gauss"),
+                                        ((64, 32), "zero"), ((257, 97), "lowrank")])
+def test_leverage_labels_match_oracle(ffc, shape, kind):
+    m, n = shape
+    rng = np.random.default_rng(9)
+    if kind == "kernel":
+        X = W.low_intrinsic(m + n, 8, di=3, seed=1)
+        B = kernel_matrix(X[:m], X[m:], okernel(LAPLACE))
+    elif kind == "gauss":
+        B = rng.standard_normal((m, n))
+    elif kind == "lowrank":
+        B = rng.standard_normal((m, 5)) @ rng.standard_normal((5, n))
+    else:
+        B = np.zeros((m, n))
+    eps = 1e-3
+    Bs = np.stack([B, 0.5 * B[::-1]])                     # two blocks per call
+    lev, tgt = ffc.leverage_labels(Bs, eps)
+    lev, tgt = lev.cpu().numpy(), tgt.cpu().numpy()
+    for b in range(2):
+        lo = pr.ridge_leverage(Bs[b], eps)
+        to = pr.leverage_targets(lo)
+        assert np.max(np.abs(lev[b] - lo)) <= _lev_tol(n, eps)
+        big = lo > 1e-6
+        np.testing.assert_allclose(tgt[b][big], to[big], rtol=1e-6,
+                                   atol=1e-5 + float(np.max(_lev_tol(n, eps) / lo[big], initial=0.0)))
+
+
+def _learning_data():
+    return W.low_intrinsic(3000, 8, di=3, noise=1e-2, seed=5)
+
+
+def test_training_set_matches_oracle(ffc):
+    X = _learning_data()
+    t, ot = trees(ffc, X, 200)
+    ts = ffc.training_set(t, gkernel(GAUSSIAN, h=1.0), 6, 120, 500, eps=1e-3, seed=3)
+    F, lev, tgt, blocks = pr.training_set(X, ot, okernel(GAUSSIAN, h=1.0), 6, 120, 500, eps=1e-3, seed=3)
+    m = len(blocks[0].rows)
+    assert ts["n"] == len(blocks[0].cols) and ts["m"] == m
+    np.testing.assert_array_equal(ts["leaves"].cpu().numpy(), [b.leaf for b in blocks])
+    np.testing.assert_array_equal(ts["cols"].cpu().numpy(), np.stack([b.cols for b in blocks]))
+    np.testing.assert_array_equal(ts["rows"].cpu().numpy(), np.stack([b.rows for b in blocks]))
+    np.testing.assert_allclose(ts["feat"].cpu().numpy(), F, rtol=1e-6, atol=1e-6)
+    assert np.max(np.abs(ts["lev"].cpu().numpy() - lev)) <= _lev_tol(ts["n"], 1e-3)
+    big = lev > 1e-6
+    np.testing.assert_allclose(ts["target"].cpu().numpy()[big], tgt[big], rtol=1e-6, atol=1e-4)
+
+
+def test_training_matches_oracle(ffc):
+    X = _learning_data()
+    t, ot = trees(ffc, X, 200)
+    theta0 = f32(W.mlp_init(5))
+    p = ffc.Proposal(theta0)
+    epochs, batch, lr = 2, 256, 1e-3
+    hist = p.train(t, gkernel(GAUSSIAN, h=1.0), 6, 120, 500, epochs=epochs, batch=batch, lr=lr, eps=1e-3, seed=3)
+    th, mu, sd = p.get()
+    F, _, tgt, _ = pr.training_set(X, ot, okernel(GAUSSIAN, h=1.0), 6, 120, 500, eps=1e-3, seed=3)
+    muo, sdo = pr.fit_standardization(F)
+    np.testing.assert_allclose(mu, muo, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(sd, sdo, rtol=1e-5)
+    tho, ho, _ = pr.train(F, tgt, theta0, epochs=epochs, batch=batch, lr=lr, seed=3, mu=muo, sd=sdo)
+    np.testing.assert_allclose(hist, ho, rtol=1e-3)
+    steps = epochs * math.ceil(len(tgt) / batch)
+    d = np.abs(th.astype(np.float64) - tho)
+    # Adam moves each parameter by about lr per step whatever the gradient's
+    # size, so a gradient whose sign differs in the last bits can move one
+    # parameter the other way; nearly all must agree closely.
+    assert np.mean(d <= 1e-5) >= 0.99 and d.max() <= 2 * lr * steps
+
+
+def _selection_gap(scores, pool, s, seed, node):
+    """Relative gap between the s-th and (s+1)-th smallest oracle keys."""
+    P = len(pool)
+    if s >= P:
+        return math.inf
+    z = scores - scores.max()
+    w = 0.9 * np.exp(z) / np.exp(z).sum() + 0.1 / P
+    keys = np.sort([-math.log(pr.unit_uniform(seed, node | pr.STREAM_KEYS, i)) / w[i] for i in range(P)])
+    return (keys[s] - keys[s - 1]) / keys[s]
+
+
+def _learned_case(ffc, fallback_tol):
+    X = W.gaussian_mixture(2500, 5, k=8, box=6.0, std=0.5, seed=2)
+    t, ot = trees(ffc, X, 160)
+    rng = np.random.default_rng(10)
+    theta = f32(0.3 * W.mlp_init(5))
+    mu = f32(rng.uniform(0, 1, 16))
+    sd = f32(rng.uniform(0.5, 2, 16))
+    gk, ok = gkernel(GAUSSIAN, h=1.0), okernel(GAUSSIAN, h=1.0)
+    p = ffc.Proposal(theta, mu, sd)
+    sk = ffc.skeletonize(t, gk, tol=1e-6, max_rank=24, num_samples=48, seed=4, proposal=p, fallback_tol=fallback_tol)
+    osk, fell = pr.skeletonize_learned(X, ot, ok, 1e-6, 24, 48, 4, theta, mu, sd, fallback_tol)
+    return X, t, ot, sk, osk, fell, theta, mu, sd, gk, ok
+
+
+def test_learned_skeletonize_matches_oracle(ffc):
+    X, t, ot, sk, osk, fell, theta, mu, sd, gk, ok = _learned_case(ffc, 0.0)
+    Xt = X[ot.perm]
+    exact, checked = 0, 0
+    for level in range(ot.depth, 0, -1):
+        for a in ot.level_nodes(level):
+            g, o = sk.node(a), osk.nodes[a]
+            if not np.array_equal(g["cols"], o.cols):
+                continue                            # an ambiguous choice below changed the columns
+            checked += 1
+            b, e = int(ot.begin[a]), int(ot.end[a])
+            pool = pr.candidate_pool(b, e, ot.N, 48, 4, a)
+            sc, _ = pr.mlp_forward(theta, pr.standardize(pr.features(Xt[pool], pr.column_geometry(Xt[o.cols], 4, a)),
+                                                         mu, sd))
+            if len(o.cols) == 0 or _selection_gap(sc, pool, 48, 4, a) < 1e-4:
+                continue
+            np.testing.assert_array_equal(g["rows"], o.rows, err_msg=f"node {a}")
+            if not unambiguous(o, 1e-6):
+                continue
+            assert g["rank"] == o.rank, f"node {a}"
+            np.testing.assert_array_equal(g["skel"], o.skel)
+            np.testing.assert_allclose(g["P"], o.P, atol=1e-8 * max(1.0, np.abs(o.P).max()))
+            exact += 1
+    assert checked == ot.num_nodes - 1
+    assert exact >= 0.8 * checked, (exact, checked)
+    q = W.charges(ot.N, seed=1)
+    u, uf = ffc.evaluate_sum(t, sk, gk, q)
+    ou, ouf = o_evaluate(X, ot, osk, ok, q)
+    if exact == checked:
+        assert rel(uf.cpu().numpy(), ouf) < FP64_REL
+
+
+def test_learned_fallback_matches_oracle(ffc):
+    # A tiny tolerance: every node with a nonzero held-out residual (all but
+    # those whose ID reproduces every column) falls back to uniform rows,
+    # exactly as the oracle decides.
+    X, t, ot, sk, osk, fell, *_ = _learned_case(ffc, 1e-300)
+    nonempty = [a for a in range(1, ot.num_nodes) if len(osk.nodes[a].cols) > 0]
+    fallen = [a for a in nonempty if fell[a]]
+    assert sk.stats()["fallbacks"] == len(fallen) >= len(nonempty) // 2
+    uni = ffc.skeletonize(t, gkernel(GAUSSIAN, h=1.0), tol=1e-6, max_rank=24, num_samples=48, seed=4)
+    for a in fallen:
+        if a >= (1 << ot.depth) - 1:   # leaves: same columns as the uniform run
+            np.testing.assert_array_equal(sk.node(a)["rows"], uni.node(a)["rows"])
+    # A loose tolerance keeps every learned node.
+    _, _, _, sk2, _, fell2, *_ = _learned_case(ffc, 1e300)
+    assert sk2.stats()["fallbacks"] == 0 and not any(fell2.values())
+
+
+def test_learned_beats_uniform(ffc):
+    """Gain test: Laplace kernel on points near a 4-dimensional subspace of
+    R^16, where a few near targets carry the far field and uniform rows miss
+    them (the coherence problem of Section 3). The proposal is trained on the
+    GPU and sees every far point as a candidate (pool factor 64)."""
+    N, d = 4096, 16
+    X = W.low_intrinsic(N, d, di=4, noise=1e-2, seed=0)
+    q = W.charges(N, seed=1)
+    t, ot = trees(ffc, X, 256)
+    gk, ok = gkernel(LAPLACE), okernel(LAPLACE)
+    p = ffc.Proposal(W.mlp_init(5))
+    hist = p.train(t, gk, 48, 256, 2048, epochs=8, batch=512, lr=1e-3, eps=1e-4, seed=7)
+    assert hist[-1] < 0.2 * hist[0]
+    ex = exact_far_field(X, ot, ok, q)
+    uni = ffc.skeletonize(t, gk, tol=1e-6, max_rank=64, num_samples=64, seed=0)
+    lrn = ffc.skeletonize(t, gk, tol=1e-6, max_rank=64, num_samples=64, seed=0, proposal=p, pool_factor=64)
+    e_uni = rel(ffc.evaluate_sum(t, uni, gk, q)[1].cpu().numpy(), ex)
+    e_lrn = rel(ffc.evaluate_sum(t, lrn, gk, q)[1].cpu().numpy(), ex)
+    print(f"far-field error: uniform {e_uni:.3e}, learned {e_lrn:.3e}")
+    assert e_uni > 0.5
+    assert e_lrn < 0.25 * e_uni
