@@ -1,15 +1,26 @@
 """Throughput of the far-field compression hot path on one MI355X.
 
 A step is one pass of the whole hot path over the resident input: every
-non-root node skeletonized (row sampling, sampled kernel block, pivoted-QR
-ID, interpolation solve, skeleton ids) and the kernel sum evaluated with the
-compressed far field (equivalent charges upward, far + near field sums).
-The tree is built once, outside the timed region.
+non-root node skeletonized (row sampling or the learned proposal, sampled
+kernel block, pivoted-QR ID, interpolation solve, skeleton ids) and the
+kernel sum evaluated with the compressed far field (equivalent charges
+upward, far + near field sums). The tree is built once, outside the timed
+region; so is the proposal's training, which is timed on its own.
 
-Workload (default): N = 65536 points in d = 16 from a mixture of 32 Gaussian
-clusters (centres uniform in [0, 10]^16, std 0.5), Gaussian kernel h = 1,
-ball tree with leaf size 512, rank cap 256 and 2 x 256 sampled rows per
-node, ID tolerance 1e-5, q ~ N(0, 1), FP64.
+Workloads (synthetic, seeded):
+  mixture16   (default) N = 65536 points in d = 16 from a mixture of 32
+              Gaussian clusters (centres uniform in [0, 10]^16, std 0.5),
+              Gaussian kernel h = 1, leaf size 512, rank cap 256 and 2 x 256
+              sampled rows per node, ID tolerance 1e-5, q ~ N(0, 1), FP64
+  subspace64  N = 262144 points near a random 8-dim subspace of R^64 (noise
+              1e-2), Laplace kernel, leaf 1024, rank cap 256, 512 rows,
+              mixed precision
+  highdim1000 N = 65536, d = 1000, N(0, I)/sqrt(d) plus 64 offsets of norm 3,
+              polynomial kernel (x.y + 1)^3, leaf 512, tol 1e-4, mixed
+  highdim1000g  the same points with the Gaussian kernel h = 1.5
+  learned64   the subspace64 points with the Gaussian kernel h = 1 and the
+              learned proposal, trained on the GPU first (2000 blocks of 512
+              columns x 4096 targets by default)
 
 Prints one JSON line: value = skeletonized nodes per second of step time.
 """
@@ -32,10 +43,28 @@ METRIC = "skeletonized nodes/s + kernel evals/s at far-field rel err 1e-4 vs pla
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
 
+MIX = dict(data="gaussian_mixture", clusters=32, box=10.0, std=0.5)
+SUB = dict(data="low_intrinsic", di=8, noise=1e-2)
+HD = dict(data="highdim_clusters", clusters=64, offset=3.0)
 WORKLOADS = {
-    "mixture16": dict(N=65536, d=16, data="gaussian_mixture", clusters=32, box=10.0, std=0.5, kernel="gaussian",
-                      h=1.0, leaf=512, max_rank=256, num_samples=512, tol=1e-5),
+    "mixture16": dict(N=65536, d=16, **MIX, kernel="gaussian", h=1.0, leaf=512, max_rank=256, num_samples=512,
+                      tol=1e-5, precision="fp64",
+                      text="N=65536 d=16 32-cluster Gaussian mixture, Gaussian h=1.0"),
+    "subspace64": dict(N=262144, d=64, **SUB, kernel="laplace", h=1.0, leaf=1024, max_rank=256, num_samples=512,
+                       tol=1e-6, precision="mixed",
+                       text="N=262144 d=64 8-dim subspace + 1e-2 noise, Laplace |x-y|^-62"),
+    "highdim1000": dict(N=65536, d=1000, **HD, kernel="polynomial", h=1.0, p=3, c=1.0, leaf=512, max_rank=256,
+                        num_samples=512, tol=1e-4, precision="mixed",
+                        text="N=65536 d=1000 N(0,I)/sqrt(d) + 64 offsets of norm 3, polynomial (x.y+1)^3"),
+    "highdim1000g": dict(N=65536, d=1000, **HD, kernel="gaussian", h=1.5, leaf=512, max_rank=256,
+                         num_samples=512, tol=1e-4, precision="mixed",
+                         text="N=65536 d=1000 N(0,I)/sqrt(d) + 64 offsets of norm 3, Gaussian h=1.5"),
+    "learned64": dict(N=262144, d=64, **SUB, kernel="gaussian", h=1.0, leaf=1024, max_rank=256, num_samples=512,
+                      tol=1e-6, precision="mixed", learned=True, train_blocks=2000, block_cols=512,
+                      block_rows=4096, epochs=2, batch=4096, lr=1e-3, eps=1e-4, pool_factor=8,
+                      text="N=262144 d=64 8-dim subspace + 1e-2 noise, Gaussian h=1.0, learned proposal"),
 }
 
 
@@ -45,7 +74,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mixture16", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--train-blocks", type=int, default=None, help="learned64: training blocks")
+    ap.add_argument("--compare", action="store_true", help="learned64: uniform vs learned at 1x, 2x, 4x rows")
+    ap.add_argument("--variants", default="fp32,mixed",
+                    help="other precisions timed on the same workload, each judged against the FP64 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     return ap.parse_args()
@@ -53,9 +86,19 @@ def parse():
 
 def make_inputs(w):
     from paper_1409_2802_amd import workloads as W
-    X = W.gaussian_mixture(w["N"], w["d"], k=w["clusters"], box=w["box"], std=w["std"], seed=0)
+    if w["data"] == "gaussian_mixture":
+        X = W.gaussian_mixture(w["N"], w["d"], k=w["clusters"], box=w["box"], std=w["std"], seed=0)
+    elif w["data"] == "low_intrinsic":
+        X = W.low_intrinsic(w["N"], w["d"], di=w["di"], noise=w["noise"], seed=0)
+    else:
+        X = W.highdim_clusters(w["N"], w["d"], k=w["clusters"], offset_norm=w["offset"], seed=0)
     q = W.charges(w["N"], seed=1)
     return X, q
+
+
+def kernel_args(w):
+    kind = {"gaussian": 0, "laplace": 1, "polynomial": 2}[w["kernel"]]
+    return kind, dict(h=w.get("h", 1.0), c=w.get("c", 1.0), p=w.get("p", 1))
 
 
 def qr_flops(s, n, r):
@@ -68,28 +111,36 @@ def solve_flops(n, r):
     return float(r) * r * max(n - r, 0)
 
 
-def stage_work(stage, nodes, tree_sizes, d, skel_evals, eval_evals):
-    """Algorithmic FP64 flops of one launch-sum of a stage over one step."""
+def stage_roof(stage, nodes, d, skel_evals, eval_evals, mixed, kernel):
+    """(algorithmic flops of one step, bound, peak TFLOP/s) of a stage.
+
+    Kernel tiles count 3 d flops per evaluation (difference, multiply, add;
+    2 d for the inner product of the polynomial kernel); in the mixed mode the
+    Gaussian and polynomial Gram products run on matrix cores as three bf16
+    products (6 d flops per evaluation) against the bf16 peak."""
     if stage == "cpqr":
-        return sum(qr_flops(len(v["rows"]), len(v["cols"]), v["rank"]) for v in nodes.values())
+        return sum(qr_flops(len(v["rows"]), len(v["cols"]), v["rank"]) for v in nodes.values()), "alu", \
+            FP64_PEAK_TFLOPS
     if stage == "solve":
-        return sum(solve_flops(len(v["cols"]), v["rank"]) for v in nodes.values())
-    if stage == "kblock":
-        return skel_evals * 3.0 * d
-    if stage == "evaluate":
-        return eval_evals * 3.0 * d
-    return None
+        return sum(solve_flops(len(v["cols"]), v["rank"]) for v in nodes.values()), "alu", FP64_PEAK_TFLOPS
+    if stage in ("kblock", "evaluate"):
+        ev = skel_evals if stage == "kblock" else eval_evals
+        if mixed and kernel != "laplace":
+            return ev * 6.0 * d, "mfma", BF16_PEAK_TFLOPS
+        per = 2.0 * d if kernel == "polynomial" else 3.0 * d
+        return ev * per, "alu", (FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS)
+    return None, "alu", FP64_PEAK_TFLOPS
 
 
-def cpu_baseline(w, X, q, budget_s):
+def cpu_baseline(w, X, budget_s):
     """The oracle, single-threaded, on a bounded sample of the workload's nodes."""
     from threadpoolctl import threadpool_limits
 
-    from oracle.kernels import GAUSSIAN
     from oracle.kernels import Kernel as OKernel
     from oracle.skeleton import skeletonize_node
     from oracle.tree import build_tree as o_build_tree
-    ok = OKernel(GAUSSIAN, h=w["h"])
+    kind, kw = kernel_args(w)
+    ok = OKernel(kind, **kw)
     with threadpool_limits(limits=1):
         ot = o_build_tree(X, w["leaf"])
         Xt = X[ot.perm]
@@ -103,20 +154,20 @@ def cpu_baseline(w, X, q, budget_s):
                 break
         dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} leaf nodes of the same tree (512 points, {w['num_samples']} sampled rows each), "
-                      f"single thread, {dt:.1f} s"}
+            "sample": f"{done} leaf nodes of the same tree ({w['leaf']} points, {w['num_samples']} sampled rows "
+                      f"each, FP64), single thread, {dt:.1f} s"}
 
 
 def oracle_far_check(w, X, q, u_far_gpu, count=256):
     """Far-field relative error of the GPU result against the oracle's exact sum on sampled targets."""
     from oracle.evaluate import exact_far_field, relative_error
-    from oracle.kernels import GAUSSIAN
     from oracle.kernels import Kernel as OKernel
     from oracle.tree import build_tree as o_build_tree
     from paper_1409_2802_amd import workloads as W
+    kind, kw = kernel_args(w)
     ot = o_build_tree(X, w["leaf"])
     tg = W.subset(w["N"], count, seed=2)
-    ex = exact_far_field(X, ot, OKernel(GAUSSIAN, h=w["h"]), q, tg)
+    ex = exact_far_field(X, ot, OKernel(kind, **kw), q, tg)
     return relative_error(u_far_gpu[tg], ex)
 
 
@@ -129,29 +180,77 @@ def main():
     import torch
 
     from paper_1409_2802_amd import ffc
+    from paper_1409_2802_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ffc.load_library()
-    w = WORKLOADS[args.workload]
-    prec = ffc.FP64 if args.precision == "fp64" else ffc.FP32
+    w = dict(WORKLOADS[args.workload])
+    if args.train_blocks:
+        w["train_blocks"] = args.train_blocks
+    pname = args.precision or w["precision"]
+    prec = {"fp64": ffc.FP64, "fp32": ffc.FP32, "mixed": ffc.MIXED_BF16X3}[pname]
     X, q = make_inputs(w)
     Xd = torch.as_tensor(X, device="cuda")
     qd = torch.as_tensor(q, device="cuda")
-    k = ffc.Kernel(ffc.GAUSSIAN, h=w["h"])
+    kind, kw = kernel_args(w)
+    k = ffc.Kernel(kind, **kw)
     tree = ffc.build_tree(Xd, w["leaf"])
     u = torch.empty(w["N"], dtype=torch.float64, device="cuda")
     uf = torch.empty(w["N"], dtype=torch.float64, device="cuda")
+    print(f"[bench] {args.workload}: tree depth {tree.depth}, {tree.num_nodes} nodes", file=sys.stderr, flush=True)
 
-    def step(sk):
-        sk = ffc.skeletonize(tree, k, tol=w["tol"], max_rank=w["max_rank"], num_samples=w["num_samples"],
-                             precision=prec, seed=0, reuse=sk)
-        ffc.evaluate_sum_into(tree, sk, k, qd, u, uf, precision=prec)
+    training = None
+    proposal = None
+    if w.get("learned"):
+        proposal = ffc.Proposal(W.mlp_init(5))
+        ffc.profile_read(reset=True)
+        ffc.profile_enable(True)
+        t0 = time.perf_counter()
+        loss = proposal.train(tree, k, w["train_blocks"], w["block_cols"], w["block_rows"], epochs=w["epochs"],
+                              batch=w["batch"], lr=w["lr"], eps=w["eps"], seed=7)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ffc.profile_enable(False)
+        tp = ffc.profile_read(reset=True)
+        samples = w["train_blocks"] * w["block_rows"]
+        steps = w["epochs"] * math.ceil(samples / w["batch"])
+        lab_ms, tr_ms = tp["labels"]["ms"], tp["train"]["ms"]
+        # Labels: Gram (2 m n^2), Cholesky (n^3 / 3), solve (m n^2) per block, FP64.
+        m_, n_ = w["block_rows"], w["block_cols"]
+        lab_flops = w["train_blocks"] * (3.0 * m_ * n_ * n_ + n_ ** 3 / 3.0)
+        training = {"blocks": w["train_blocks"], "block": [m_, n_], "samples": samples, "epochs": w["epochs"],
+                    "batch": w["batch"], "steps": steps, "loss_per_epoch": [float(x) for x in loss],
+                    "labels_ms": lab_ms, "labels_per_s": samples / (lab_ms * 1e-3),
+                    "labels_fp64_tflops": lab_flops / (lab_ms * 1e-3) / 1e12,
+                    "train_ms": tr_ms, "train_samples_per_s": samples * w["epochs"] / (tr_ms * 1e-3),
+                    "train_ms_per_step": tr_ms / max(1, steps), "wall_s": wall}
+        print(f"[bench] trained: {json.dumps(training)}", file=sys.stderr, flush=True)
+
+    def step(sk, s=w["num_samples"], mr=w["max_rank"], prop=proposal, p=prec, out=(u, uf)):
+        sk = ffc.skeletonize(tree, k, tol=w["tol"], max_rank=mr, num_samples=s, precision=p, seed=0,
+                             reuse=sk, proposal=prop, pool_factor=w.get("pool_factor", 0))
+        ffc.evaluate_sum_into(tree, sk, k, qd, out[0], out[1], precision=p)
         return sk
+
+    def timed(p, steps, warmup, out):
+        sk = None
+        for _ in range(max(1, warmup)):
+            sk = step(sk, p=p, out=out)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            sk = step(sk, p=p, out=out)
+        ev1.record()
+        torch.cuda.synchronize()
+        ffc.check_device()
+        return sk, ev0.elapsed_time(ev1) / steps
 
     sk = None
     for _ in range(max(1, args.warmup)):
         sk = step(sk)
     torch.cuda.synchronize()
     ffc.check_device()
+    print("[bench] warm-up done", file=sys.stderr, flush=True)
     ffc.profile_read(reset=True)
     ffc.profile_enable(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -166,6 +265,7 @@ def main():
     ms_total = start.elapsed_time(stop)
     ms_step = ms_total / args.steps
     ffc.check_device()
+    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
 
     # Work counts of one step.
     st = sk.stats()
@@ -183,26 +283,60 @@ def main():
     nodes_per_s = st["num_nodes"] / (ms_step * 1e-3)
     evals_per_s = (skel_evals + eval_evals) / (ms_step * 1e-3)
 
-    # Accuracy against the plain FP64 path: exact far field = direct sum minus the (exact) near field.
+    # Accuracy against the plain FP64 path: exact far field = FP64 direct sum minus the exact near field
+    # (in the FP32 and mixed modes the near field is recomputed in FP64 by evaluating the same skeletons
+    # in FP64).
     ud = ffc.direct_sum(Xd, Xd, qd, k, precision=ffc.FP64)
     torch.cuda.synchronize()
     u_h, uf_h, ud_h = u.cpu().numpy(), uf.cpu().numpy(), ud.cpu().numpy()
-    far_exact = ud_h - (u_h - uf_h)
+    if prec == ffc.FP64:
+        near = u_h - uf_h
+    else:
+        u64 = torch.empty_like(u)
+        uf64 = torch.empty_like(uf)
+        ffc.evaluate_sum_into(tree, sk, k, qd, u64, uf64, precision=ffc.FP64)
+        torch.cuda.synchronize()
+        near = (u64 - uf64).cpu().numpy()
+    far_exact = ud_h - near
     e_far_gpu = float(np.linalg.norm(uf_h - far_exact) / np.linalg.norm(far_exact))
     e_tot_gpu = float(np.linalg.norm(u_h - ud_h) / np.linalg.norm(ud_h))
+    print(f"[bench] e_far {e_far_gpu:.3e}", file=sys.stderr, flush=True)
+
+    # The plain FP64 path on the same workload (same sampler and seeds): the reference the metric's
+    # 1e-4 far-field tolerance is read against, and the baseline of the speedups.
+    u64r, uf64r = torch.empty_like(u), torch.empty_like(uf)
+    if prec == ffc.FP64:
+        uf64_h, ms64 = uf_h, ms_step
+    else:
+        _, ms64 = timed(ffc.FP64, args.steps, args.warmup, (u64r, uf64r))
+        uf64_h = uf64r.cpu().numpy()
+    e_vs64 = float(np.linalg.norm(uf_h - uf64_h) / np.linalg.norm(uf64_h))
+    variants = {}
+    if prec == ffc.FP64 and proposal is None:
+        for vname in [v for v in args.variants.split(",") if v]:
+            vp = {"fp32": ffc.FP32, "mixed": ffc.MIXED_BF16X3}[vname]
+            uv, ufv = torch.empty_like(u), torch.empty_like(uf)
+            skv, msv = timed(vp, args.steps, args.warmup, (uv, ufv))
+            ufv_h = ufv.cpu().numpy()
+            variants[vname] = {"ms_per_step": msv, "nodes_per_s": skv.stats()["num_nodes"] / (msv * 1e-3),
+                               "speedup_vs_fp64": ms64 / msv,
+                               "e_far_vs_fp64_path": float(np.linalg.norm(ufv_h - uf64_h) / np.linalg.norm(uf64_h)),
+                               "e_far_vs_exact": float(np.linalg.norm(ufv_h - far_exact) / np.linalg.norm(far_exact))}
+            print(f"[bench] variant {vname}: {variants[vname]}", file=sys.stderr, flush=True)
 
     # Roofline of the dominant stage (average launch duration from the in-region events).
-    dom = max((s for s in prof if s not in ("tree", "direct")), key=lambda s: prof[s]["ms"])
+    dom = max((s for s in prof if s not in ("tree", "direct", "labels", "train")), key=lambda s: prof[s]["ms"])
     launches_per_step = prof[dom]["launches"] / args.steps
     ms_per_launch = prof[dom]["ms"] / max(1, prof[dom]["launches"])
-    flops = stage_work(dom, nodes, sizes, w["d"], skel_evals, eval_evals)
-    peak = FP64_PEAK_TFLOPS if prec == ffc.FP64 or dom in ("cpqr", "solve") else FP32_PEAK_TFLOPS
-    roof = {"bound": "alu", "achieved": None, "peak": peak, "unit": "TFLOP/s", "traffic": None}
+    flops, bound, peak = stage_roof(dom, nodes, w["d"], skel_evals, eval_evals, prec == ffc.MIXED_BF16X3,
+                                    w["kernel"])
+    roof = {"bound": bound, "achieved": None, "peak": peak, "unit": "TFLOP/s", "traffic": None}
     if flops is not None and launches_per_step > 0:
         roof["achieved"] = flops / launches_per_step / (ms_per_launch * 1e-3) / 1e12
         roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = {"cpqr": "k_cpqr_coop", "solve": "k_coop_tasks + k_id_solve", "kblock": "k_level_kblock",
-                      "evaluate": "k_evaluate", "sample": "k_sample_rows_bitmap", "upward": "k_upward"}.get(dom, dom)
+                      "evaluate": "k_evaluate", "sample": "k_sample_rows_bitmap", "upward": "k_upward",
+                      "proposal": "k_geometry + k_features + k_mlp_score + k_select_rows"}.get(dom, dom)
     roof["stage"] = dom
     roof["ms_per_launch"] = ms_per_launch
     roof["launches_per_step"] = launches_per_step
@@ -211,23 +345,41 @@ def main():
     out = {
         "metric": METRIC, "value": nodes_per_s, "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if prec == ffc.FP64 else "f32", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: N={w['N']} d={w['d']} {w['clusters']}-cluster Gaussian mixture, "
-                               f"Gaussian h={w['h']}, leaf {w['leaf']}, s={w['num_samples']}, "
+        "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "bf16x3+f32+f64"}[pname],
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {w['text']}, leaf {w['leaf']}, s={w['num_samples']}, "
                                f"max_rank={w['max_rank']}, tol={w['tol']}",
                    "N": w["N"], "d": w["d"], "leaf_size": w["leaf"], "num_samples": w["num_samples"],
-                   "max_rank": w["max_rank"], "tol": w["tol"], "precision": args.precision},
+                   "max_rank": w["max_rank"], "tol": w["tol"], "precision": pname,
+                   "sampler": "learned" if proposal is not None else "uniform"},
         "kernel_evals_per_s": evals_per_s,
         "skeleton_kernel_evals": skel_evals, "evaluate_kernel_evals": eval_evals,
         "ranks": {"min": st["rank_min"], "mean": st["rank_mean"], "max": st["rank_max"],
                   "cap_hits": st["rank_cap_hits"]},
-        "e_far_vs_gpu_fp64_direct": e_far_gpu, "e_total_vs_gpu_fp64_direct": e_tot_gpu,
-        "meets_1e-4": e_far_gpu <= 1e-4,
-        "stage_ms_per_step": {s: prof[s]["ms"] / args.steps for s in prof},
+        "e_far_vs_fp64_path": e_vs64, "meets_1e-4": e_vs64 <= 1e-4,
+        "speedup_vs_fp64_path": ms64 / ms_step,
+        "e_far_vs_exact": e_far_gpu, "e_total_vs_exact": e_tot_gpu,
+        "precision_variants": variants,
+        "stage_ms_per_step": {s: prof[s]["ms"] / args.steps for s in prof if prof[s]["launches"]},
         "roofline": roof,
     }
+    if training is not None:
+        out["training"] = training
+    if args.compare and proposal is not None:
+        cmp = []
+        for mult in (1, 2, 4):
+            s = min(mult * w["max_rank"], 1024)
+            row = {"num_samples": s}
+            for name, prop in (("uniform", None), ("learned", proposal)):
+                skc = step(None, s=s, prop=prop)
+                torch.cuda.synchronize()
+                row[name] = float(np.linalg.norm(uf.cpu().numpy() - far_exact) / np.linalg.norm(far_exact))
+                row[name + "_fallbacks"] = skc.stats()["fallbacks"]
+            cmp.append(row)
+            print(f"[bench] compare {row}", file=sys.stderr, flush=True)
+        out["uniform_vs_learned_e_far"] = cmp
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(w, X, q, args.cpu_budget_s)
+        cb = cpu_baseline(w, X, args.cpu_budget_s)
         cb["e_far_vs_oracle_256_targets"] = oracle_far_check(w, X, q, uf_h)
         out["cpu_baseline"] = cb
     print(json.dumps(out))

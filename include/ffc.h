@@ -318,7 +318,11 @@ typedef enum {
   FFC_STAGE_EVALUATE = 7,  /* far + near field sums */
   FFC_STAGE_DIRECT = 8,    /* direct sums */
   FFC_STAGE_SOLVE = 9,     /* QR set-up and interpolation solve R11 T = R12, P */
-  FFC_NUM_STAGES = 10
+  FFC_STAGE_PROPOSAL = 10, /* learned sampler: pool, geometry, features, scores, selection */
+  FFC_STAGE_HELDOUT = 11,  /* learned sampler: held-out rows, their block and the check */
+  FFC_STAGE_LABELS = 12,   /* training set: blocks, ridge leverage, geometry and features */
+  FFC_STAGE_TRAIN = 13,    /* proposal training: gradients and Adam steps */
+  FFC_NUM_STAGES = 14
 } ffc_stage;
 ffc_status ffc_profile_enable(int32_t on);
 ffc_status ffc_profile_read(double* ms_host, int64_t* launches_host, int32_t num_stages, int32_t reset);

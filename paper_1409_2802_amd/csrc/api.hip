@@ -336,18 +336,21 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
         StageTimer tm(FFC_STAGE_COLUMNS, st);
         FFC_TRY(launch_level_columns(t, sk, first, count, lev == t->depth, st));
       }
-      {
+      if (learned) {
+        StageTimer tm(FFC_STAGE_PROPOSAL, st);
+        FFC_TRY(learned_rows_level(t, sk, o->proposal, first, count, s_cap, o->seed, st));
+      } else {
         StageTimer tm(FFC_STAGE_SAMPLE, st);
-        if (learned)
-          FFC_TRY(learned_rows_level(t, sk, o->proposal, first, count, s_cap, o->seed, st));
-        else
-          FFC_TRY(launch_sample_rows(t, sk, first, count, s_cap, o->seed, st));
+        FFC_TRY(launch_sample_rows(t, sk, first, count, s_cap, o->seed, st));
       }
       FFC_TRY(skeletonize_level(first, count));
       if (learned && o->fallback_tol > 0.0) {
         int redo = 0;
-        FFC_TRY(learned_heldout_level(t, sk, kp, o->precision, first, count, s_cap, o->seed, o->fallback_tol, redo,
-                                      st));
+        {
+          StageTimer tm(FFC_STAGE_HELDOUT, st);
+          FFC_TRY(learned_heldout_level(t, sk, kp, o->precision, first, count, s_cap, o->seed, o->fallback_tol, redo,
+                                        st));
+        }
         if (redo) {   // failed nodes now hold uniform rows; the others recompute identically
           sk->fallbacks += redo;
           FFC_TRY(skeletonize_level(first, count));

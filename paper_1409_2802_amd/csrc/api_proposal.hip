@@ -163,21 +163,25 @@ ffc_status build_training_set(const ffc_tree* t, const ffc_kernel* k, const ffc_
   FFC_TRY(B.alloc((size_t)chunk * m * n));
   FFC_TRY(Gm.alloc((size_t)chunk * n * n));
   FFC_TRY(status.alloc(G));
-  for (int g0 = 0; g0 < G; g0 += chunk) {
-    const int c = std::min(chunk, G - g0);
-    // Row-major m x n blocks: the "rows" of the tile engine are the block's
-    // columns, its "columns" the targets (the kernels are symmetric).
-    FFC_TRY(launch_kblock_batch(t, kp, FFC_FP64, ts.cols.ptr + (int64_t)g0 * n, ts.ncols.ptr + g0, n,
-                                ts.rows.ptr + (int64_t)g0 * m, ts.nrows.ptr + g0, m, 0, c, nullptr, B.ptr, st));
-    FFC_TRY(launch_ridge_leverage(B.ptr, m, n, c, Gm.ptr, o->eps, ts.lev.ptr + (int64_t)g0 * m,
-                                  ts.target.ptr + (int64_t)g0 * m, status.ptr + g0, st));
-  }
-  // Features of every target against its block's columns.
-  GeomScratch gs;
+  GeomScratch gs;   // outlives the launches below (freed after the synchronization)
   FFC_TRY(gs.alloc(G, t->d));
-  const GeomArgs ga = gs.args(ts.cols.ptr, n, ts.ncols.ptr, ts.leaves.ptr, o->seed);
-  FFC_TRY(launch_geometry(t->Xt.ptr, t->d, ga, G, st));
-  FFC_TRY(launch_features(t->Xt.ptr, t->d, ga, ts.rows.ptr, m, ts.nrows.ptr, G, ts.feat.ptr, (int64_t)m * kNF, st));
+  {
+    StageTimer timer(FFC_STAGE_LABELS, st);
+    for (int g0 = 0; g0 < G; g0 += chunk) {
+      const int c = std::min(chunk, G - g0);
+      // Row-major m x n blocks: the "rows" of the tile engine are the block's
+      // columns, its "columns" the targets (the kernels are symmetric).
+      FFC_TRY(launch_kblock_batch(t, kp, FFC_FP64, ts.cols.ptr + (int64_t)g0 * n, ts.ncols.ptr + g0, n,
+                                  ts.rows.ptr + (int64_t)g0 * m, ts.nrows.ptr + g0, m, 0, c, nullptr, B.ptr, st));
+      FFC_TRY(launch_ridge_leverage(B.ptr, m, n, c, Gm.ptr, o->eps, ts.lev.ptr + (int64_t)g0 * m,
+                                    ts.target.ptr + (int64_t)g0 * m, status.ptr + g0, st));
+    }
+    // Features of every target against its block's columns.
+    const GeomArgs ga = gs.args(ts.cols.ptr, n, ts.ncols.ptr, ts.leaves.ptr, o->seed);
+    FFC_TRY(launch_geometry(t->Xt.ptr, t->d, ga, G, st));
+    FFC_TRY(launch_features(t->Xt.ptr, t->d, ga, ts.rows.ptr, m, ts.nrows.ptr, G, ts.feat.ptr, (int64_t)m * kNF,
+                            st));
+  }
   std::vector<int> st_h(G);
   FFC_HIP_TRY(hipMemcpyAsync(st_h.data(), status.ptr, G * sizeof(int), hipMemcpyDeviceToHost, st));
   FFC_HIP_TRY(hipStreamSynchronize(st));
@@ -428,12 +432,16 @@ ffc_status ffc_proposal_train(ffc_proposal* p, const ffc_tree* t, const ffc_kern
   DevBuf<float> step_loss, partial;
   FFC_TRY(step_loss.alloc((size_t)std::max<int64_t>(1, steps_per_epoch * o->epochs)));
   int64_t si = 0;
-  for (int e = 0; e < o->epochs; ++e) {
-    const int64_t stride = epoch_stride(C, o->seed, e);
-    for (int64_t p0 = 0; p0 < C; p0 += o->batch, ++si) {
-      const int64_t bs = std::min<int64_t>(o->batch, C - p0);
-      FFC_TRY(grad_step(p, p->theta.ptr, p->m1.ptr, p->m2.ptr, ts.feat.ptr, ts.target.ptr, C, p0, stride, bs, partial,
-                        nullptr, step_loss.ptr + si, true, o->lr, ++p->step, st));
+  FFC_TRY(partial.alloc((size_t)((std::min<int64_t>(o->batch, C) + kGradBatch - 1) / kGradBatch) * (kNParam + 1)));
+  {
+    StageTimer timer(FFC_STAGE_TRAIN, st);
+    for (int e = 0; e < o->epochs; ++e) {
+      const int64_t stride = epoch_stride(C, o->seed, e);
+      for (int64_t p0 = 0; p0 < C; p0 += o->batch, ++si) {
+        const int64_t bs = std::min<int64_t>(o->batch, C - p0);
+        FFC_TRY(grad_step(p, p->theta.ptr, p->m1.ptr, p->m2.ptr, ts.feat.ptr, ts.target.ptr, C, p0, stride, bs,
+                          partial, nullptr, step_loss.ptr + si, true, o->lr, ++p->step, st));
+      }
     }
   }
   std::vector<float> sl((size_t)si);

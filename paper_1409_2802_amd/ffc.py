@@ -36,7 +36,8 @@ EXPORTS = [
 NPARAM = 5313
 NFEAT = 16
 
-STAGES = ["tree", "sample", "columns", "kblock", "cpqr", "skel", "upward", "evaluate", "direct", "solve"]
+STAGES = ["tree", "sample", "columns", "kblock", "cpqr", "skel", "upward", "evaluate", "direct", "solve",
+          "proposal", "heldout", "labels", "train"]
 
 
 class FfcError(RuntimeError):
