@@ -7,14 +7,24 @@
 // workgroups: a workgroup owns 8 wavefronts x 8 columns, each column held by
 // 16 lanes with up to 32 rows per lane in VGPRs for the whole factorization.
 // One pivot step then needs no block traffic at all:
-//   1. every workgroup reads the winning candidate column (published at the
-//      end of the previous step) and forms the reflector v, beta = 2 / v^T v;
+//   1. every workgroup loads the winning column (published at the end of the
+//      previous step, one row per thread) into LDS and forms the reflector
+//      v, beta = 2 / v^T v;
 //   2. it applies the reflector to its own non-pivot columns in registers and
 //      recomputes their trailing norms exactly (rows k+1..s-1);
-//   3. it publishes its best column (norm, original index, values) to a
-//      double-buffered slot and arrives at the group barrier;
-//   4. after the barrier all workgroups pick the same global best (largest
-//      norm, ties to the smaller original column) and apply the same stop rule.
+//   3. it publishes its best column (largest norm, ties to the smaller
+//      original column): norm, column id and rows k..s-1 go to the group's
+//      double-buffered slot, one word per thread, with no wait;
+//   4. one wave polls the G slots' norm and id words and picks the global
+//      best, which every workgroup then applies alike (pivot and stop rule).
+// Every published word carries the step's tag (1 + k mod 3) in its two lowest
+// mantissa bits, so a reader accepts a word only once the current step's
+// store has reached it and rereads otherwise: no store has to be waited for
+// before another becomes visible. The tag perturbs a published value by at
+// most 3 ulp (its two lowest bits are cleared after the check), the same on
+// every workgroup, far below the rounding of the factorization. Slots are
+// cleared before every launch; a slot read at step k can otherwise only hold
+// step k - 2, whose tag differs.
 // The pivot column is frozen in place (its rows 0..k-1 are R(0:k, k), row k
 // gets alpha), so no columns are swapped; the pivot order is recorded.
 //
@@ -35,7 +45,6 @@ namespace {
 constexpr int NT = 512;
 constexpr int NWV = NT / 64;
 constexpr unsigned int kSpinLimit = 1u << 21;   // ~1 us per poll -> about 2 s
-constexpr int kCtrStride = 64;   // one 256-byte line per group counter (no false sharing)
 
 struct CoopArgs {
   double* A;
@@ -51,8 +60,8 @@ struct CoopArgs {
   int32_t* piv;
   int64_t piv_stride;
   int32_t* task_start;       // [count + 1]
-  unsigned int* counters;    // [count]
-  double* slots;             // [count][2][gmax][s_max + 2]
+  double* slots;             // [count][2][gmax][s_max + 2]: norm, column id, rows (tagged words)
+  int64_t slot_words;
   int gmax;
   int s_max;
   int cols_per_wg;
@@ -72,7 +81,7 @@ __device__ inline double wave_sum(double v) {
 }
 
 // Group tasks per block: G_b = ceil(n_b / cols_per_wg) (at least 1); prefix
-// sums into task_start; counters cleared. One workgroup.
+// sums into task_start. One workgroup.
 __global__ void k_coop_tasks(CoopArgs ca) {
   if (threadIdx.x == 0) {
     int acc = 0;
@@ -83,7 +92,12 @@ __global__ void k_coop_tasks(CoopArgs ca) {
     }
     ca.task_start[ca.count] = acc;
   }
-  for (int b = threadIdx.x; b < ca.count; b += blockDim.x) ca.counters[(int64_t)b * kCtrStride] = 0u;
+}
+
+// Clears the slots (tag 0 is never a step's tag).
+__global__ void k_coop_clear(double* slots, int64_t words) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < words; e += (int64_t)gridDim.x * blockDim.x)
+    slots[e] = 0.0;
 }
 
 __device__ inline double* slot_ptr(const CoopArgs& ca, int b, int buf, int g) {
@@ -91,8 +105,8 @@ __device__ inline double* slot_ptr(const CoopArgs& ca, int b, int buf, int g) {
 }
 
 // Slot traffic uses relaxed agent-scope atomic loads and stores: they are
-// performed coherently across the chiplets' L2 caches, so no cache-wide
-// fence (L2 write-back / invalidate) is needed around the barrier.
+// performed coherently across the chiplets' L2 caches, so no cache-wide fence
+// (L2 write-back / invalidate) is needed.
 __device__ inline void slot_store(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -100,28 +114,12 @@ __device__ inline double slot_load(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Arrive and wait until `target` arrivals; false on timeout. Every wave first
-// waits for its own slot stores to complete, so they precede the arrival.
-__device__ inline bool group_barrier(unsigned int* ctr, unsigned int target, unsigned int* flag, int* s_ok) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned int spins = 0;
-    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kSpinLimit) {
-        atomicOr(flag, 2u);
-        ok = 0;
-        break;
-      }
-    }
-    *s_ok = ok;
-  }
-  __syncthreads();
-  return *s_ok != 0;
+__device__ inline long long step_tag(int k) { return 1 + k % 3; }
+__device__ inline double tagged(double v, long long tag) {
+  return __longlong_as_double((__double_as_longlong(v) & ~3ll) | tag);
 }
+__device__ inline long long tag_of(double v) { return __double_as_longlong(v) & 3ll; }
+__device__ inline double untag(double v) { return __longlong_as_double(__double_as_longlong(v) & ~3ll); }
 
 // All-reduce of a double within each row of 16 lanes by DPP moves (quad
 // swaps, half-row mirror, row mirror). Every step adds two values in the same
@@ -147,9 +145,13 @@ template <int RL>
 __global__ void __launch_bounds__(NT) k_cpqr_coop(CoopArgs ca) {
   constexpr int CS = 64 / RL;          // columns per lane group
   constexpr int CPW = 4 * CS;          // columns per wavefront
+  constexpr int ROWS = 16 * RL;         // rows a lane group holds (LDS rows are padded to it)
   __shared__ Best wb[NWV];
-  __shared__ int s_ok;
-  extern __shared__ double cand[];     // gmax x (s_max + 2): staged candidates of the group
+  __shared__ int s_win[3];             // {ok, winner group, winner column}
+  __shared__ double s_nv;              // winner's norm (tag cleared)
+  extern __shared__ double lds[];      // NWV candidate columns, then the winner column (ROWS each)
+  double* candcol = lds;
+  double* wincol = lds + NWV * ROWS;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int grp = lane >> 4, l16 = lane & 15;
   const int T = ca.task_start[ca.count];
@@ -166,7 +168,6 @@ __global__ void __launch_bounds__(NT) k_cpqr_coop(CoopArgs ca) {
     const int s = ca.s_arr ? ca.s_arr[b] : ca.s_uniform;
     const int n = ca.n_arr ? ca.n_arr[b] : ca.n_uniform;
     double* A = ca.A + (int64_t)b * ca.a_stride;
-    unsigned int* ctr = ca.counters + (int64_t)b * kCtrStride;
     const int col0 = g * ca.cols_per_wg + w * CPW + grp * CS;   // this lane group's first column
 
     double a[CS][RL];
@@ -179,8 +180,8 @@ __global__ void __launch_bounds__(NT) k_cpqr_coop(CoopArgs ca) {
       }
     unsigned int done = 0u;   // bit c: column col0 + c is a frozen pivot
 
-    // Publish this workgroup's best column (trailing norm over rows >= k) into buffer buf.
-    auto publish = [&](int k, int buf) {
+    // Publish this workgroup's best column for step k (trailing norms over rows >= k).
+    auto publish = [&](int k) {
       Best best{-1.0, INT_MAX};
       int bestc = -1;
 #pragma unroll
@@ -207,86 +208,132 @@ __global__ void __launch_bounds__(NT) k_cpqr_coop(CoopArgs ca) {
         const Best o{__shfl(best.v, q * 16, 64), __shfl(best.orig, q * 16, 64)};
         if (better(o.v, o.orig, wbst.v, wbst.orig)) { wbst = o; wg_owner = q; }
       }
-      if (lane == 0) wb[w] = wbst;
-      __syncthreads();
-      Best gb = wb[0];
-      int gw = 0;
-      for (int i = 1; i < NWV; ++i)
-        if (better(wb[i].v, wb[i].orig, gb.v, gb.orig)) { gb = wb[i]; gw = i; }
-      double* sl = slot_ptr(ca, b, buf, g);
-      if (w == gw && grp == wg_owner && gb.orig != INT_MAX) {
+      // The wave's best column goes to its LDS candidate row (all ROWS rows,
+      // unconditionally: only rows k..s-1 are published).
+      if (wbst.orig != INT_MAX && grp == wg_owner) {
 #pragma unroll
         for (int c = 0; c < CS; ++c)
           if (c == bestc)
 #pragma unroll
             for (int m = 0; m < RL; ++m) {
               const int i = l16 + 16 * m;
-              if (i < s) slot_store(sl + 2 + i, a[c][m]);
+              if (i >= k && i < s) candcol[w * ROWS + i] = a[c][m];
             }
       }
+      if (lane == 0) wb[w] = wbst;
+      __syncthreads();
+      Best gb = wb[0];
+      int gw = 0;
+      for (int i = 1; i < NWV; ++i)
+        if (better(wb[i].v, wb[i].orig, gb.v, gb.orig)) { gb = wb[i]; gw = i; }
+      double* sl = slot_ptr(ca, b, k & 1, g);
+      const long long tag = step_tag(k);
+      if (gb.orig != INT_MAX)
+        for (int i = k + (int)threadIdx.x; i < s; i += NT) slot_store(sl + 2 + i, tagged(candcol[gw * ROWS + i], tag));
       if (threadIdx.x == 0) {
-        slot_store(sl, gb.orig == INT_MAX ? -1.0 : gb.v);
-        slot_store(sl + 1, (double)(gb.orig == INT_MAX ? -1 : gb.orig));
+        const bool any = gb.orig != INT_MAX;
+        slot_store(sl + 1, tagged(any ? (double)gb.orig : -1.0, tag));
+        slot_store(sl, tagged(any ? gb.v : -1.0, tag));
       }
     };
-    // Stage the G candidates of buffer buf (headers and columns) into LDS with
-    // batched loads, then pick the global best (norm, column, owner).
-    auto select = [&](int buf, double& nv, int& orig, int& owner) {
-      const int stride = ca.s_max + 2;
-      const int total = G * stride;
-      const double* base = slot_ptr(ca, b, buf, 0);
-      constexpr int BATCH = 8;
-      for (int e0 = 0; e0 < total; e0 += NT * BATCH) {
-        double tmp[BATCH];
+    // Wave 0 waits for the G norm / id words of step k and picks the winner;
+    // the result is shared through LDS so every wave takes the same decisions.
+    auto poll = [&](int k, int& gwin, int& orig) -> bool {
+      if (w == 0) {
+        const long long tag = step_tag(k);
+        Best bb{-1.0, INT_MAX};
+        int bq = -1;
+        bool ok = true;
+        for (int q0 = 0; q0 < G; q0 += 64) {
+          const int q = q0 + lane;
+          Best c{-1.0, INT_MAX};
+          if (q < G) {
+            const double* sq = slot_ptr(ca, b, k & 1, q);
+            unsigned int spins = 0;
+            double nv = 0.0, ov = 0.0;
+            for (;;) {
+              nv = slot_load(sq);
+              ov = slot_load(sq + 1);
+              if (tag_of(nv) == tag && tag_of(ov) == tag) break;
+              if (++spins > kSpinLimit) { ok = false; break; }
+              __builtin_amdgcn_s_sleep(1);
+            }
+            const double o = untag(ov);
+            if (ok && o >= 0.0) c = Best{untag(nv), (int)rint(o)};
+          }
+          int cq = q;
 #pragma unroll
-        for (int u = 0; u < BATCH; ++u) {
-          const int e = e0 + u * NT + (int)threadIdx.x;
-          const int off = e % stride;
-          tmp[u] = (e < total && off < s + 2) ? slot_load(base + e) : 0.0;
+          for (int off = 32; off > 0; off >>= 1) {
+            const Best o{__shfl_xor(c.v, off, 64), __shfl_xor(c.orig, off, 64)};
+            const int oq = __shfl_xor(cq, off, 64);
+            if (better(o.v, o.orig, c.v, c.orig)) { c = o; cq = oq; }
+          }
+          if (c.orig != INT_MAX && better(c.v, c.orig, bb.v, bb.orig)) { bb = c; bq = cq; }
         }
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u) {
-          const int e = e0 + u * NT + (int)threadIdx.x;
-          if (e < total) cand[e] = tmp[u];
+        const bool all_ok = __all(ok);
+        if (!all_ok && lane == 0) atomicOr(ca.flag, 2u);
+        if (lane == 0) {
+          s_win[0] = all_ok ? 1 : 0;
+          s_win[1] = bq;
+          s_win[2] = bb.orig;
+          s_nv = bb.v;
         }
       }
       __syncthreads();
-      nv = -1.0; orig = INT_MAX; owner = -1;
-      for (int q = 0; q < G; ++q) {
-        const double v = cand[q * stride];
-        const int o = (int)cand[q * stride + 1];
-        if (o >= 0 && better(v, o, nv, orig)) { nv = v; orig = o; owner = q; }
+      gwin = s_win[1];
+      orig = s_win[2];
+      return s_win[0] != 0;
+    };
+    // Rows k..s-1 of the winner's column into LDS (one row per thread, reread
+    // until every word carries step k's tag). False on timeout.
+    auto load_winner = [&](int k, int gwin) -> bool {
+      const double* sl = slot_ptr(ca, b, k & 1, gwin);
+      const long long tag = step_tag(k);
+      for (unsigned int spins = 0;; ++spins) {
+        int stale = 0;
+        for (int i = k + (int)threadIdx.x; i < s; i += NT) {
+          const double x = slot_load(sl + 2 + i);
+          stale |= tag_of(x) != tag;
+          wincol[i] = untag(x);
+        }
+        if (!__syncthreads_or(stale)) return true;
+        if (spins > kSpinLimit) {
+          if (threadIdx.x == 0) atomicOr(ca.flag, 2u);
+          return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
     };
 
-    publish(0, 0);
-    bool alive = group_barrier(ctr, (unsigned)G, ca.flag, &s_ok);
-    double nv;
-    int porig, powner;
-    if (alive) select(0, nv, porig, powner);
+    publish(0);
+    int gwin, porig;
+    bool alive = poll(0, gwin, porig);
+    if (alive && porig != INT_MAX) alive = load_winner(0, gwin);
     const int kmax = min(min(s, n), ca.max_rank);
+    double nv = s_nv;
     const double rho0 = (alive && porig != INT_MAX) ? sqrt(nv) : 0.0;
     int k = 0;
     for (; alive && k < kmax; ++k) {
       if (porig == INT_MAX) break;
       const double rho = sqrt(nv);
       if (rho == 0.0 || rho < ca.tol * rho0) break;
-      const double* x = cand + powner * (ca.s_max + 2) + 2;   // staged winner
-      const double xk = x[k];
+      const double xk = wincol[k];
       const double alpha = xk != 0.0 ? -copysign(rho, xk) : -rho;
       double v[RL];
       double part = 0.0;
 #pragma unroll
+      for (int m = 0; m < RL; ++m) v[m] = wincol[l16 + 16 * m];   // unconditional: no branch per read
+#pragma unroll
       for (int m = 0; m < RL; ++m) {
         const int i = l16 + 16 * m;
-        v[m] = (i >= k && i < s) ? (i == k ? xk - alpha : x[i]) : 0.0;
+        v[m] = (i >= k && i < s) ? (i == k ? xk - alpha : v[m]) : 0.0;
         part = fma(v[m], v[m], part);
       }
       // Every lane group holds all rows, so the reflector norm is a 16-lane sum.
       const double vv = row16_sum(part);
       const double beta = vv > 0.0 ? 2.0 / vv : 0.0;
       // Freeze the pivot column: row k becomes alpha.
-      if (g == powner) {
+      if (g == gwin) {
 #pragma unroll
         for (int c = 0; c < CS; ++c)
           if (col0 + c == porig) {
@@ -309,9 +356,10 @@ __global__ void __launch_bounds__(NT) k_cpqr_coop(CoopArgs ca) {
 #pragma unroll
         for (int m = 0; m < RL; ++m) a[c][m] = fma(-v[m], coef, a[c][m]);
       }
-      publish(k + 1, (k + 1) & 1);
-      alive = group_barrier(ctr, (unsigned)(G * (k + 2)), ca.flag, &s_ok);
-      if (alive) select((k + 1) & 1, nv, porig, powner);
+      publish(k + 1);
+      alive = poll(k + 1, gwin, porig);
+      if (alive && porig != INT_MAX && k + 1 < kmax) alive = load_winner(k + 1, gwin);
+      nv = s_nv;
     }
     if (!alive) return;   // timed out: the device flag reports it
     // Write the columns back in place: rows 0..k-1 of every column hold R.
@@ -441,15 +489,11 @@ ffc_status launch_r(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch
   const int cols_per_wg = CPW * NWV;
   const int gmax = std::max(1, (bt.n_max + cols_per_wg - 1) / cols_per_wg);
   const void* kern = reinterpret_cast<const void*>(&k_cpqr_coop<R>);
-  const size_t lds = (size_t)gmax * (bt.s_max + 2) * sizeof(double);
-  if (lds > 150 * 1024) return FFC_OK;   // candidates do not fit in LDS: caller falls back
-  if (lds > 64 * 1024)
-    FFC_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  const size_t lds = (size_t)(NWV + 1) * 16 * R * sizeof(double);
   const int grid_cap = resident_grid(kern, lds);
   if (grid_cap < gmax) return FFC_OK;   // a group would not fit: caller falls back
   const size_t slot_doubles = (size_t)batch * 2 * gmax * (bt.s_max + 2);
-  const size_t bytes = slot_doubles * sizeof(double) + ((size_t)batch + 1) * sizeof(int32_t) + 256 +
-                       (size_t)batch * kCtrStride * sizeof(unsigned int);
+  const size_t bytes = slot_doubles * sizeof(double) + ((size_t)batch + 1) * sizeof(int32_t);
   if (scratch.count < bytes) FFC_TRY(scratch.alloc(bytes));
   CoopArgs ca{};
   ca.A = bt.A;
@@ -466,12 +510,8 @@ ffc_status launch_r(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch
   ca.piv = bt.piv;
   ca.piv_stride = bt.piv_stride;
   ca.slots = reinterpret_cast<double*>(scratch.ptr);
+  ca.slot_words = (int64_t)slot_doubles;
   ca.task_start = reinterpret_cast<int32_t*>(ca.slots + slot_doubles);
-  {
-    // Counters start on a 256-byte boundary after the task table.
-    const uintptr_t p = reinterpret_cast<uintptr_t>(ca.task_start + batch + 1);
-    ca.counters = reinterpret_cast<unsigned int*>((p + 255) & ~uintptr_t(255));
-  }
   ca.gmax = gmax;
   ca.s_max = bt.s_max;
   ca.cols_per_wg = cols_per_wg;
@@ -480,6 +520,9 @@ ffc_status launch_r(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch
     StageTimer tm(FFC_STAGE_SOLVE, st);
     hipLaunchKernelGGL(k_coop_tasks, dim3(1), dim3(256), 0, st, ca);
     FFC_LAUNCH_CHECK("k_coop_tasks");
+    const int cgrid = (int)std::min<int64_t>(1024, (ca.slot_words + 255) / 256);
+    hipLaunchKernelGGL(k_coop_clear, dim3(std::max(1, cgrid)), dim3(256), 0, st, ca.slots, ca.slot_words);
+    FFC_LAUNCH_CHECK("k_coop_clear");
   }
   const int upper_tasks = batch * gmax;
   const int grid = std::min(grid_cap, upper_tasks);
