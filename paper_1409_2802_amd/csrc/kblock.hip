@@ -19,72 +19,12 @@
 // mixed mode) in float with the Laplace power taken in double; the mixed mode
 // of the Gaussian and polynomial kernels runs on matrix cores (gram_mfma.hip).
 #include "ffc_internal.h"
+#include "tile_engine.h"
 
 namespace ffc {
 namespace {
 
-constexpr int BM = 64, BN = 64, KC = 32, NT = 256;
-constexpr int LDSP = BM + 1;   // padded LDS row (bank spread)
-
-template <typename T>
-struct TileSmem {
-  T ys[KC][LDSP];
-  T xs[KC][LDSP];
-};
-
-// Row / column index maps: an explicit index list or a contiguous range.
-struct IdxMap {
-  const int32_t* idx;
-  int64_t base;
-  __device__ inline int64_t operator()(int i) const { return idx ? (int64_t)idx[i] : base + i; }
-};
-
-// acc[i][j] for rows r0 + tr + 16 i and columns c0 + tc + 16 j.
-template <typename T, bool DOT>
-__device__ inline void tile_accumulate(const double* __restrict__ Y, IdxMap rows, int nrows, const double* __restrict__ X,
-                                       IdxMap cols, int ncols, int d, TileSmem<T>& sm, T (&acc)[4][4]) {
-  const int tid = threadIdx.x;
-  const int tr = tid & 15, tc = tid >> 4;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
-  for (int k0 = 0; k0 < d; k0 += KC) {
-#pragma unroll
-    for (int e = tid; e < BM * KC; e += NT) {
-      const int r = e / KC, kk = e % KC;
-      const int k = k0 + kk;
-      T yv = T(0), xv = T(0);
-      if (k < d) {
-        if (r < nrows) yv = (T)Y[rows(r) * d + k];
-        if (r < ncols) xv = (T)X[cols(r) * d + k];
-      }
-      sm.ys[kk][r] = yv;
-      sm.xs[kk][r] = xv;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < KC; ++kk) {
-      T a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = sm.ys[kk][tr + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = sm.xs[kk][tc + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (DOT) {
-            acc[i][j] = fma(a[i], b[j], acc[i][j]);
-          } else {
-            const T df = a[i] - b[j];
-            acc[i][j] = fma(df, df, acc[i][j]);
-          }
-        }
-    }
-    __syncthreads();
-  }
-}
+using namespace tile;
 
 // Kernel function of an accumulated distance^2 (or inner product when DOT).
 template <bool DOT>

@@ -17,6 +17,7 @@
 #include <climits>
 
 #include "ffc_internal.h"
+#include "tile_engine.h"
 
 namespace ffc {
 namespace {
@@ -153,42 +154,103 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
 }
 
 // ---------------------------------------------------------------------------
-// Features: one thread per (node, target).
+// Features: one 256-thread workgroup per 64 targets of a block. Distances to
+// the subsample come from the shared tile engine (64 x 64 tiles, FP64 explicit
+// differences); each thread keeps the 4 smallest distances and the sum for
+// its 4 rows over its columns, merged across the 16 threads of a row in a
+// fixed order (lanes 16 apart by shuffles, then the 4 waves through LDS).
 // ---------------------------------------------------------------------------
+__device__ inline void insert4(double (&b)[4], double v) {   // keep the 4 smallest, ascending
+  if (!(v < b[3])) return;
+  b[3] = v;
+#pragma unroll
+  for (int a = 3; a > 0; --a)
+    if (b[a] < b[a - 1]) { const double t = b[a]; b[a] = b[a - 1]; b[a - 1] = t; }
+}
+
 __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt, int d, GeomArgs ga,
                                                   const int32_t* __restrict__ tgt, int tgt_stride,
-                                                  const int32_t* __restrict__ ntgt, int count_nodes,
+                                                  const int32_t* __restrict__ ntgt, int tiles,
                                                   float* __restrict__ feat, int64_t feat_stride) {
-  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int b = (int)(gid / tgt_stride), i = (int)(gid % tgt_stride);
-  if (b >= count_nodes || i >= ntgt[b]) return;
-  const double* y = Xt + (int64_t)tgt[(int64_t)b * tgt_stride + i] * d;
-  const double* c = ga.cen + (int64_t)b * d;
-  const double rho = ga.rho[b];
+  __shared__ tile::TileSmem<double> sm;
+  const int b = blockIdx.x / tiles, t0 = (blockIdx.x % tiles) * 64;
+  const int nt = ntgt[b];
+  if (t0 >= nt) return;
   const int ns = ga.nsub[b];
+  const double rho = ga.rho[b];
   const int32_t* S = ga.sub + (int64_t)b * SUB;
+  const int32_t* tg = tgt + (int64_t)b * tgt_stride + t0;
+  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+  double best[4][4], sum[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    sum[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) best[i][q] = INFINITY;
+  }
+  for (int c0 = 0; c0 < ns; c0 += 64) {
+    double acc[4][4];
+    tile::tile_accumulate<double, false>(Xt, tile::IdxMap{tg, 0}, nt - t0, Xt, tile::IdxMap{S + c0, 0}, ns - c0, d,
+                                         sm, acc);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (c0 + tc + 16 * j < ns) {
+          const double dist = sqrt(acc[i][j]) / rho;
+          sum[i] += dist;
+          insert4(best[i], dist);
+        }
+  }
+  // Merge the 4 threads of a row inside the wave (lanes tr + 16 q).
+#pragma unroll
+  for (int off = 16; off <= 32; off <<= 1)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double o[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) o[q] = __shfl_xor(best[i][q], off, 64);
+      const double os = __shfl_xor(sum[i], off, 64);
+      // Fixed order: the lower lane's sum first.
+      sum[i] = (tid & off) ? os + sum[i] : sum[i] + os;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) insert4(best[i], o[q]);
+    }
+  // Then the 4 waves, through LDS (the tile buffers are free after the last tile).
+  double* red = reinterpret_cast<double*>(&sm);   // [4 waves][64 rows][5]
+  const int wv = tid >> 6;
+  if ((tid & 63) < 16) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double* r = red + ((int64_t)wv * 64 + tr + 16 * i) * 5;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r[q] = best[i][q];
+      r[4] = sum[i];
+    }
+  }
+  __syncthreads();
+  if (tid >= 64) return;
+  const int row = tid;
+  if (t0 + row >= nt) return;
+  double b4[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+  double tot = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    const double* r = red + ((int64_t)q * 64 + row) * 5;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) insert4(b4, r[u]);
+    tot += r[4];
+  }
+  const double* y = Xt + (int64_t)tg[row] * d;
+  const double* c = ga.cen + (int64_t)b * d;
   double dc = 0.0;
   for (int k = 0; k < d; ++k) { const double df = y[k] - c[k]; dc = fma(df, df, dc); }
   dc = sqrt(dc) / rho;
-  double best[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-  double sum = 0.0;
-  for (int q = 0; q < ns; ++q) {
-    const double* x = Xt + (int64_t)S[q] * d;
-    double s = 0.0;
-    for (int k = 0; k < d; ++k) { const double df = y[k] - x[k]; s = fma(df, df, s); }
-    const double v = sqrt(s) / rho;
-    sum += v;
-    if (v < best[3]) {   // keep the 4 smallest, ascending
-      best[3] = v;
-      for (int a = 3; a > 0 && best[a] < best[a - 1]; --a) { const double tt = best[a]; best[a] = best[a - 1]; best[a - 1] = tt; }
-    }
-  }
-  float* f = feat + (int64_t)b * feat_stride + (int64_t)i * NF;
+  float* f = feat + (int64_t)b * feat_stride + (int64_t)(t0 + row) * NF;
   f[0] = (float)dc;
   f[1] = (float)log(dc + 1e-12);
-  for (int q = 0; q < 4; ++q) f[2 + q] = (float)(q < ns ? best[q] : best[max(ns - 1, 0)]);
-  f[6] = (float)(ns > 0 ? sum / ns : 0.0);
-  f[7] = (float)log(best[0] + 1e-12);
+  for (int q = 0; q < 4; ++q) f[2 + q] = (float)(q < ns ? b4[q] : b4[max(ns - 1, 0)]);
+  f[6] = (float)(ns > 0 ? tot / ns : 0.0);
+  f[7] = (float)log(b4[0] + 1e-12);
   const double* U = ga.U + (int64_t)b * NANCH * d;
   for (int a = 0; a < NANCH; ++a) {
     double p = 0.0;
@@ -549,10 +611,11 @@ ffc_status launch_geometry(const double* Xt, int d, const GeomArgs& ga, int coun
 
 ffc_status launch_features(const double* Xt, int d, const GeomArgs& ga, const int32_t* tgt, int tgt_stride,
                            const int32_t* ntgt, int count, float* feat, int64_t feat_stride, hipStream_t st) {
-  const int64_t threads = (int64_t)count * tgt_stride;
-  if (threads <= 0) return FFC_OK;
-  hipLaunchKernelGGL(k_features, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, Xt, d, ga, tgt, tgt_stride,
-                     ntgt, count, feat, feat_stride);
+  const int tiles = (tgt_stride + 63) / 64;
+  const int64_t blocks = (int64_t)count * tiles;
+  if (blocks <= 0) return FFC_OK;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)blocks), dim3(256), 0, st, Xt, d, ga, tgt, tgt_stride, ntgt, tiles,
+                     feat, feat_stride);
   FFC_LAUNCH_CHECK("k_features");
   return FFC_OK;
 }
