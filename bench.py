@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--compare", action="store_true", help="learned64: uniform vs learned at 1x, 2x, 4x rows")
     ap.add_argument("--variants", default="fp32,mixed",
                     help="other precisions timed on the same workload, each judged against the FP64 path")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run device-to-device copies of MIB MiB (5 times) to calibrate memory counters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     return ap.parse_args()
@@ -182,6 +184,16 @@ def main():
     from paper_1409_2802_amd import ffc
     from paper_1409_2802_amd import workloads as W
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read_per_launch": n * 8, "bytes_written_per_launch": n * 8,
+                          "launches": 5}))
+        return
     ffc.load_library()
     w = dict(WORKLOADS[args.workload])
     if args.train_blocks:
