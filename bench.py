@@ -134,6 +134,23 @@ def stage_roof(stage, nodes, d, skel_evals, eval_evals, mixed, kernel):
     return None, "alu", FP64_PEAK_TFLOPS
 
 
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary, or None when
+    the summary is for another workload or the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("<!-- traffic: "):
+            rec = json.loads(line[len("<!-- traffic: "):].rsplit("-->", 1)[0])
+            src = open(os.path.join(ROOT, rec["kernel_source"]), "rb").read()
+            blob = hashlib.sha1(b"blob %d\0" % len(src) + src).hexdigest()
+            if rec["workload"] == workload and rec["precision"] == precision and blob == rec["source_git_blob"]:
+                return float(rec["bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(w, X, budget_s):
     """The oracle, single-threaded, on a bounded sample of the workload's nodes."""
     from threadpoolctl import threadpool_limits
@@ -349,6 +366,9 @@ def main():
     roof["kernel"] = {"cpqr": "k_cpqr_coop", "solve": "k_coop_tasks + k_id_solve", "kblock": "k_level_kblock",
                       "evaluate": "k_evaluate", "sample": "k_sample_rows_bitmap", "upward": "k_upward",
                       "proposal": "k_geometry + k_features + k_mlp_score + k_select_rows"}.get(dom, dom)
+    if dom == "cpqr":
+        roof["traffic"] = measured_traffic(args.workload, pname, "k_cpqr_coop")
+        roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roof["stage"] = dom
     roof["ms_per_launch"] = ms_per_launch
     roof["launches_per_step"] = launches_per_step
@@ -374,6 +394,7 @@ def main():
         "precision_variants": variants,
         "stage_ms_per_step": {s: prof[s]["ms"] / args.steps for s in prof if prof[s]["launches"]},
         "roofline": roof,
+        "qr_autotune": ffc.autotune_report(),
     }
     if training is not None:
         out["training"] = training

@@ -199,6 +199,25 @@ typedef struct {
 /* Rank statistics of a skeleton set (synchronizes). */
 ffc_status ffc_skel_stats(const ffc_skel* sk, ffc_stats* out);
 
+/* One step of the hot path as a HIP graph: ffc_skeletonize_nodes (reusing `sk`,
+ * with options `o`) followed by ffc_evaluate_sum, captured once on `stream` and
+ * replayed by ffc_graph_launch. Every node of a level still runs in one
+ * persistent cooperative launch; the graph removes the host-side launch work
+ * of the ~40 kernels of a step. `sk` must come from a previous
+ * ffc_skeletonize_nodes call with the same tree, kernel and options (so no
+ * buffer is allocated inside the graph), and keeps being written by every
+ * replay; q_dev, u_dev, u_far_dev (may be NULL) are baked into the graph and
+ * must stay valid while it exists. Not for the learned sampler with a fallback
+ * (its check synchronizes). `stream` must not be the null stream.
+ * Errors: NULL arguments, a null stream, a fallback -> FFC_ERR_INVALID_ARG; a
+ * failed capture -> FFC_ERR_HIP (the stream is left usable). */
+typedef struct ffc_graph ffc_graph;
+ffc_status ffc_step_graph_create(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* k, const ffc_skel_opts* o,
+                                 const double* q_dev, double* u_dev, double* u_far_dev, int32_t precision,
+                                 void* stream, ffc_graph** out);
+ffc_status ffc_graph_launch(ffc_graph* g, void* stream);
+void ffc_graph_free(ffc_graph* g);
+
 /* ---------------------------------------------------------------------------
  * Learned row proposal.
  *
@@ -325,6 +344,13 @@ typedef enum {
   FFC_NUM_STAGES = 14
 } ffc_stage;
 ffc_status ffc_profile_enable(int32_t on);
+/* Autotuner: the first pivoted-QR launch of each block shape times the kernel
+ * variants (rows per lane, workgroup size) that can hold the blocks on a copy of
+ * them and keeps the fastest; FFC_AUTOTUNE=0 in the environment disables it.
+ * Writes up to `cap` entries of 8 int32 (s_max, n_max, batch, rank cap, rows per
+ * lane, threads per workgroup, best time in us, first candidate's time in us)
+ * to out_host and their total number to *count. */
+ffc_status ffc_autotune_report(int32_t* out_host, int32_t cap, int32_t* count);
 ffc_status ffc_profile_read(double* ms_host, int64_t* launches_host, int32_t num_stages, int32_t reset);
 
 void ffc_free_tree(ffc_tree* t);

@@ -531,3 +531,78 @@ void ffc_free_skel(ffc_skel* sk) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Step graphs
+// ---------------------------------------------------------------------------
+struct ffc_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+ffc_status ffc_step_graph_create(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* k, const ffc_skel_opts* o,
+                                 const double* q_dev, double* u_dev, double* u_far_dev, int32_t precision,
+                                 void* stream, ffc_graph** out) {
+  using namespace ffc;
+  if (!t || !sk || !k || !o || !q_dev || !u_dev || !out) {
+    set_error("NULL argument (a skeleton set from a previous skeletonization is required)");
+    return FFC_ERR_INVALID_ARG;
+  }
+  if (!stream) {
+    set_error("graphs need a non-null stream");
+    return FFC_ERR_INVALID_ARG;
+  }
+  if (o->sampler == FFC_SAMPLE_LEARNED && o->fallback_tol > 0.0) {
+    set_error("the learned sampler's fallback check synchronizes and cannot be captured");
+    return FFC_ERR_INVALID_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  FFC_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+  ffc_skel* skp = sk;
+  ffc_status s1 = ffc_skeletonize_nodes(t, k, o, stream, &skp);
+  ffc_status s2 = s1 == FFC_OK ? ffc_evaluate_sum(t, sk, k, q_dev, u_dev, u_far_dev, precision, stream) : s1;
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(st, &graph);
+  if (s2 != FFC_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s2;
+  }
+  if (ec != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+    return FFC_ERR_HIP;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    return FFC_ERR_HIP;
+  }
+  ffc_graph* g = new ffc_graph();
+  g->graph = graph;
+  g->exec = exec;
+  *out = g;
+  return FFC_OK;
+}
+
+ffc_status ffc_graph_launch(ffc_graph* g, void* stream) {
+  if (!g) {
+    ffc::set_error("graph is NULL");
+    return FFC_ERR_INVALID_ARG;
+  }
+  FFC_HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return FFC_OK;
+}
+
+void ffc_graph_free(ffc_graph* g) {
+  if (!g) return;
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+}  // extern "C"

@@ -36,6 +36,9 @@
 // bounded; a timeout raises bit 1 of the device flag and the workgroup
 // abandons its remaining work, so every wave exits.
 #include <climits>
+#include <cstdlib>
+#include <mutex>
+#include <vector>
 
 #include "ffc_internal.h"
 
@@ -141,17 +144,20 @@ __device__ inline double row16_sum(double x) {
 // Register layout: a wavefront is 4 lane groups of 16 lanes; a lane group owns
 // CS columns and each of its lanes keeps RL rows (i = lane16 + 16 m) of them,
 // so a column's dot products and norms are 16-lane DPP reductions.
-template <int RL>
-__global__ void __launch_bounds__(NT) k_cpqr_coop(CoopArgs ca) {
+// Variants: RL rows per lane (16 or 32) and NTC threads per workgroup (512 or
+// 256); both keep at most 256 VGPRs per lane (two waves per SIMD).
+template <int RL, int NTC>
+__global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
   constexpr int CS = 64 / RL;          // columns per lane group
   constexpr int CPW = 4 * CS;          // columns per wavefront
-  constexpr int ROWS = 16 * RL;         // rows a lane group holds (LDS rows are padded to it)
-  __shared__ Best wb[NWV];
+  constexpr int ROWS = 16 * RL;        // rows a lane group holds (LDS rows are padded to it)
+  constexpr int NWVC = NTC / 64;       // wavefronts per workgroup
+  __shared__ Best wb[NWVC];
   __shared__ int s_win[3];             // {ok, winner group, winner column}
   __shared__ double s_nv;              // winner's norm (tag cleared)
-  extern __shared__ double lds[];      // NWV candidate columns, then the winner column (ROWS each)
+  extern __shared__ double lds[];      // NWVC candidate columns, then the winner column (ROWS each)
   double* candcol = lds;
-  double* wincol = lds + NWV * ROWS;
+  double* wincol = lds + NWVC * ROWS;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int grp = lane >> 4, l16 = lane & 15;
   const int T = ca.task_start[ca.count];
@@ -224,12 +230,12 @@ __global__ void __launch_bounds__(NT) k_cpqr_coop(CoopArgs ca) {
       __syncthreads();
       Best gb = wb[0];
       int gw = 0;
-      for (int i = 1; i < NWV; ++i)
+      for (int i = 1; i < NWVC; ++i)
         if (better(wb[i].v, wb[i].orig, gb.v, gb.orig)) { gb = wb[i]; gw = i; }
       double* sl = slot_ptr(ca, b, k & 1, g);
       const long long tag = step_tag(k);
       if (gb.orig != INT_MAX)
-        for (int i = k + (int)threadIdx.x; i < s; i += NT) slot_store(sl + 2 + i, tagged(candcol[gw * ROWS + i], tag));
+        for (int i = k + (int)threadIdx.x; i < s; i += NTC) slot_store(sl + 2 + i, tagged(candcol[gw * ROWS + i], tag));
       if (threadIdx.x == 0) {
         const bool any = gb.orig != INT_MAX;
         slot_store(sl + 1, tagged(any ? (double)gb.orig : -1.0, tag));
@@ -291,7 +297,7 @@ __global__ void __launch_bounds__(NT) k_cpqr_coop(CoopArgs ca) {
       const long long tag = step_tag(k);
       for (unsigned int spins = 0;; ++spins) {
         int stale = 0;
-        for (int i = k + (int)threadIdx.x; i < s; i += NT) {
+        for (int i = k + (int)threadIdx.x; i < s; i += NTC) {
           const double x = slot_load(sl + 2 + i);
           stale |= tag_of(x) != tag;
           wincol[i] = untag(x);
@@ -475,23 +481,26 @@ __global__ void __launch_bounds__(NT) k_id_solve(SolveArgs sa) {
   }
 }
 
-int resident_grid(const void* kern, size_t lds) {
+int resident_grid(const void* kern, int threads, size_t lds) {
   int dev = 0, nb = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, NT, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, threads, lds) != hipSuccess) return 0;
   return nb * cus;
 }
 
-template <int R>
-ffc_status launch_r(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hipStream_t st, bool& used) {
+// The factorization with variant (R, NTC) on the blocks of bt (in place);
+// fits = false (nothing launched) when a block's group cannot be resident.
+template <int R, int NTC>
+ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hipStream_t st, bool& fits) {
   constexpr int CPW = 4 * (64 / R);   // columns per wavefront
-  const int cols_per_wg = CPW * NWV;
+  const int cols_per_wg = CPW * (NTC / 64);
   const int gmax = std::max(1, (bt.n_max + cols_per_wg - 1) / cols_per_wg);
-  const void* kern = reinterpret_cast<const void*>(&k_cpqr_coop<R>);
-  const size_t lds = (size_t)(NWV + 1) * 16 * R * sizeof(double);
-  const int grid_cap = resident_grid(kern, lds);
-  if (grid_cap < gmax) return FFC_OK;   // a group would not fit: caller falls back
+  const void* kern = reinterpret_cast<const void*>(&k_cpqr_coop<R, NTC>);
+  const size_t lds = (size_t)(NTC / 64 + 1) * 16 * R * sizeof(double);
+  const int grid_cap = resident_grid(kern, NTC, lds);
+  fits = grid_cap >= gmax;
+  if (!fits) return FFC_OK;
   const size_t slot_doubles = (size_t)batch * 2 * gmax * (bt.s_max + 2);
   const size_t bytes = slot_doubles * sizeof(double) + ((size_t)batch + 1) * sizeof(int32_t);
   if (scratch.count < bytes) FFC_TRY(scratch.alloc(bytes));
@@ -524,13 +533,16 @@ ffc_status launch_r(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch
     hipLaunchKernelGGL(k_coop_clear, dim3(std::max(1, cgrid)), dim3(256), 0, st, ca.slots, ca.slot_words);
     FFC_LAUNCH_CHECK("k_coop_clear");
   }
-  const int upper_tasks = batch * gmax;
-  const int grid = std::min(grid_cap, upper_tasks);
+  const int grid = std::min(grid_cap, batch * gmax);
   void* args[] = {&ca};
   {
     StageTimer tm(FFC_STAGE_CPQR, st);
-    FFC_HIP_TRY(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(NT), args, (unsigned int)lds, st));
+    FFC_HIP_TRY(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(NTC), args, (unsigned int)lds, st));
   }
+  return FFC_OK;
+}
+
+ffc_status launch_solve(const IdBatch& bt, int batch, hipStream_t st) {
   SolveArgs sa{};
   sa.A = bt.A;
   sa.a_stride = bt.a_stride;
@@ -549,13 +561,90 @@ ffc_status launch_r(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch
   if (slds > 64 * 1024)
     FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_id_solve),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds));
-  {
-    StageTimer tm(FFC_STAGE_SOLVE, st);
-    hipLaunchKernelGGL(k_id_solve, dim3(batch), dim3(NT), slds, st, sa);
-    FFC_LAUNCH_CHECK("k_id_solve");
-  }
-  used = true;
+  StageTimer tm(FFC_STAGE_SOLVE, st);
+  hipLaunchKernelGGL(k_id_solve, dim3(batch), dim3(NT), slds, st, sa);
+  FFC_LAUNCH_CHECK("k_id_solve");
   return FFC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: the first factorization of each shape (s_max, n_max, batch,
+// rank cap) times every variant that can hold the blocks on a scratch copy
+// of the real blocks (best of two runs, HIP events) and keeps the fastest.
+// Disabled by FFC_AUTOTUNE=0 and while the stream is being captured into a
+// graph (then the first valid variant runs).
+// ---------------------------------------------------------------------------
+using QrLaunch = ffc_status (*)(const IdBatch&, int, DevBuf<unsigned char>&, hipStream_t, bool&);
+struct Variant {
+  int R, threads;
+  QrLaunch fn;
+};
+const Variant kVariants[] = {
+    {16, 512, &launch_qr<16, 512>},
+    {16, 256, &launch_qr<16, 256>},
+    {32, 512, &launch_qr<32, 512>},
+    {32, 256, &launch_qr<32, 256>},
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+struct TuneEntry {
+  int s_max, n_max, batch, max_rank;
+  int choice;
+  float best_us, first_us;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+bool autotune_enabled() {
+  const char* e = std::getenv("FFC_AUTOTUNE");
+  return !(e && e[0] == '0');
+}
+
+ffc_status tune(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hipStream_t st,
+                const std::vector<int>& cand, TuneEntry& te) {
+  DevBuf<double> copy;
+  const size_t words = (size_t)batch * bt.a_stride;
+  FFC_TRY(copy.alloc(words));
+  IdBatch tb = bt;
+  tb.A = copy.ptr;
+  hipEvent_t e0, e1;
+  FFC_HIP_TRY(hipEventCreate(&e0));
+  FFC_HIP_TRY(hipEventCreate(&e1));
+  te.choice = -1;
+  te.best_us = te.first_us = 0.f;
+  ffc_status status = FFC_OK;
+  for (int v : cand) {
+    float best = -1.f;
+    for (int rep = 0; rep < 2 && status == FFC_OK; ++rep) {
+      bool fits = false;
+      if (hipMemcpyAsync(copy.ptr, bt.A, words * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
+          hipEventRecord(e0, st) != hipSuccess) {
+        status = FFC_ERR_HIP;
+        break;
+      }
+      status = kVariants[v].fn(tb, batch, scratch, st, fits);
+      if (status != FFC_OK || !fits) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        status = FFC_ERR_HIP;
+        break;
+      }
+      best = best < 0.f ? ms : std::min(best, ms);
+    }
+    if (status != FFC_OK) break;
+    if (best < 0.f) continue;   // does not fit
+    if (te.first_us == 0.f) te.first_us = best * 1e3f;
+    if (te.choice < 0 || best * 1e3f < te.best_us) {
+      te.choice = v;
+      te.best_us = best * 1e3f;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);   // the copy is freed below
+  if (status != FFC_OK) set_error("autotuning of the QR kernel failed");
+  return status;
 }
 
 }  // namespace
@@ -568,9 +657,61 @@ ffc_status launch_interp_decomp_coop(const IdBatch& bt, int batch, DevBuf<unsign
     const int rmax = std::max(1, std::min(bt.max_rank, std::min(bt.s_max, bt.n_max)));
     if ((size_t)SB * rmax * sizeof(double) + 3 * (size_t)bt.n_max * sizeof(int) > 150 * 1024) return FFC_OK;
   }
-  if (bt.s_max <= 256) return launch_r<16>(bt, batch, scratch, st, used);
-  if (bt.s_max <= 512) return launch_r<32>(bt, batch, scratch, st, used);
+  std::vector<int> cand;
+  for (int v = 0; v < kNumVariants; ++v)
+    if (bt.s_max <= 16 * kVariants[v].R) cand.push_back(v);
+  if (cand.empty()) return FFC_OK;
+  int choice = -1;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const TuneEntry& te : g_tune)
+      if (te.s_max == bt.s_max && te.n_max == bt.n_max && te.batch == batch && te.max_rank == bt.max_rank)
+        choice = te.choice;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  FFC_HIP_TRY(hipStreamIsCapturing(st, &cs));
+  if (choice < 0 && cand.size() > 1 && autotune_enabled() && cs == hipStreamCaptureStatusNone) {
+    TuneEntry te{bt.s_max, bt.n_max, batch, bt.max_rank, -1, 0.f, 0.f};
+    FFC_TRY(tune(bt, batch, scratch, st, cand, te));
+    if (te.choice >= 0) {
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      g_tune.push_back(te);
+      choice = te.choice;
+    }
+  }
+  // The chosen variant first, then the others in order (one that fits is used).
+  std::vector<int> order;
+  if (choice >= 0) order.push_back(choice);
+  for (int v : cand)
+    if (v != choice) order.push_back(v);
+  for (int v : order) {
+    bool fits = false;
+    FFC_TRY(kVariants[v].fn(bt, batch, scratch, st, fits));
+    if (fits) {
+      FFC_TRY(launch_solve(bt, batch, st));
+      used = true;
+      return FFC_OK;
+    }
+  }
   return FFC_OK;
+}
+
+int autotune_entries(int32_t* out, int cap) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  const int n = (int)g_tune.size();
+  for (int e = 0; e < n && e < cap; ++e) {
+    const TuneEntry& te = g_tune[e];
+    int32_t* o = out + 8 * e;
+    o[0] = te.s_max;
+    o[1] = te.n_max;
+    o[2] = te.batch;
+    o[3] = te.max_rank;
+    o[4] = kVariants[te.choice].R;
+    o[5] = kVariants[te.choice].threads;
+    o[6] = (int32_t)te.best_us;
+    o[7] = (int32_t)te.first_us;
+  }
+  return n;
 }
 
 }  // namespace ffc

@@ -267,6 +267,10 @@ ffc_status launch_interp_decomp(const IdBatch& b, int batch, hipStream_t st);
 // (and launches nothing) when a block does not fit, so the caller can fall
 // back to launch_interp_decomp. scratch grows as needed and must stay alive
 // until the stream has passed the call.
+// Autotuner choices of the QR kernel so far: 8 int32 per entry (s_max, n_max,
+// batch, rank cap, rows per lane, threads, best us, first candidate's us);
+// writes at most cap entries, returns the number of entries (cpqr_coop.hip).
+int autotune_entries(int32_t* out, int cap);
 ffc_status launch_interp_decomp_coop(const IdBatch& b, int batch, DevBuf<unsigned char>& scratch, hipStream_t st,
                                      bool& used);
 

@@ -39,6 +39,8 @@ bool profiling() { return g_on; }
 
 StageTimer::StageTimer(int stage, hipStream_t st) : stage_(stage), st_(st) {
   if (!g_on) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;   // not inside graphs
   start_ = get_event();
   stop_ = get_event();
   if (!start_ || !stop_) return;
@@ -94,3 +96,12 @@ ffc_status ffc_profile_read(double* ms_host, int64_t* launches_host, int32_t num
 }
 
 }  // extern "C"
+
+extern "C" ffc_status ffc_autotune_report(int32_t* out_host, int32_t cap, int32_t* count) {
+  if (!count || (cap > 0 && !out_host)) {
+    ffc::set_error("NULL argument");
+    return FFC_ERR_INVALID_ARG;
+  }
+  *count = ffc::autotune_entries(out_host, cap > 0 ? cap : 0);
+  return FFC_OK;
+}

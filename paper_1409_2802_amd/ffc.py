@@ -31,6 +31,7 @@ EXPORTS = [
     "ffc_proposal_create", "ffc_proposal_get", "ffc_proposal_free", "ffc_proposal_features",
     "ffc_proposal_fit_standardization", "ffc_proposal_score", "ffc_proposal_gradient", "ffc_proposal_adam",
     "ffc_leverage_labels", "ffc_proposal_train", "ffc_proposal_training_set",
+    "ffc_step_graph_create", "ffc_graph_launch", "ffc_graph_free", "ffc_autotune_report",
 ]
 
 NPARAM = 5313
@@ -107,6 +108,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ffc_proposal_train": [P, P, ctypes.POINTER(KernelC), ctypes.POINTER(TrainOptsC), P, P],
         "ffc_proposal_training_set": [P, ctypes.POINTER(KernelC), ctypes.POINTER(TrainOptsC), P, P, P, P, P, P, P,
                                       P, P],
+        "ffc_step_graph_create": [P, P, ctypes.POINTER(KernelC), ctypes.POINTER(SkelOptsC), P, P, P, I32, P, PP],
+        "ffc_graph_launch": [P, P],
+        "ffc_autotune_report": [P, I32, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -116,6 +120,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ffc_free_tree.restype = None
     lib.ffc_free_skel.argtypes = [P]
     lib.ffc_free_skel.restype = None
+    lib.ffc_graph_free.argtypes = [P]
+    lib.ffc_graph_free.restype = None
     lib.ffc_proposal_free.argtypes = [P]
     lib.ffc_proposal_free.restype = None
     lib.ffc_last_error.argtypes = []
@@ -263,6 +269,33 @@ def skeletonize(tree: Tree, kernel: Kernel, tol: float, max_rank: int, num_sampl
     if reuse is not None:
         return reuse
     return Skeletons(h, tree)
+
+
+class StepGraph:
+    """One step (skeletonize with reuse + evaluate) captured as a HIP graph."""
+
+    def __init__(self, tree: Tree, sk: Skeletons, kernel: Kernel, q: torch.Tensor, u: torch.Tensor,
+                 u_far: torch.Tensor | None, stream, tol: float, max_rank: int, num_samples: int = 0,
+                 precision: int = FP64, seed: int = 0, proposal: "Proposal | None" = None, pool_factor: int = 0):
+        opts = SkelOptsC(tol=tol, max_rank=max_rank, num_samples=num_samples, precision=precision,
+                         sampler=SAMPLE_LEARNED if proposal is not None else SAMPLE_UNIFORM, seed=seed,
+                         proposal=proposal.handle if proposal is not None else None, fallback_tol=0.0,
+                         pool_factor=pool_factor)
+        self._keep = (tree, sk, q, u, u_far, proposal)   # the graph holds their device pointers
+        k = kernel.c_struct()
+        h = ctypes.c_void_p()
+        _check(load_library().ffc_step_graph_create(tree.handle, sk.handle, ctypes.byref(k), ctypes.byref(opts),
+                                                     _ptr(q), _ptr(u), _ptr(u_far), precision, _stream(stream),
+                                                     ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        _check(load_library().ffc_graph_launch(self._h, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ffc_graph_free(self._h)
+            self._h = None
 
 
 def evaluate_sum(tree: Tree, sk: Skeletons, kernel: Kernel, q, precision: int = FP64, stream=None):
@@ -458,3 +491,14 @@ def training_set(tree: Tree, kernel: Kernel, num_blocks: int, block_cols: int, b
     _check(lib.ffc_proposal_training_set(tree.handle, ctypes.byref(k), ctypes.byref(o), None, None, _ptr(leaves),
                                          _ptr(cols), _ptr(rows), _ptr(feat), _ptr(tgt), _ptr(lev), _stream(stream)))
     return {"n": n, "m": m, "leaves": leaves, "cols": cols, "rows": rows, "feat": feat, "target": tgt, "lev": lev}
+
+
+def autotune_report() -> list:
+    """The QR autotuner's choices so far (one dict per block shape)."""
+    lib = load_library()
+    cnt = ctypes.c_int32()
+    _check(lib.ffc_autotune_report(None, 0, ctypes.byref(cnt)))
+    buf = np.zeros(8 * max(cnt.value, 1), dtype=np.int32)
+    _check(lib.ffc_autotune_report(buf.ctypes.data, cnt.value, ctypes.byref(cnt)))
+    keys = ["s_max", "n_max", "batch", "max_rank", "rows_per_lane", "threads", "best_us", "first_us"]
+    return [dict(zip(keys, map(int, buf[8 * e:8 * e + 8]))) for e in range(cnt.value)]

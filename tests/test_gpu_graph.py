@@ -1,0 +1,65 @@
+"""A whole step (skeletonize with reuse + evaluate) captured as a HIP graph and
+replayed: every replay must reproduce the eager result exactly, with eager
+work (including a skeletonization with another seed that rewrites the same
+buffers) between replays."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.kernels import GAUSSIAN, POLYNOMIAL
+from paper_1409_2802_amd import workloads as W
+from tests._parity import gkernel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ffc():
+    from paper_1409_2802_amd import ffc as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.load_library()
+    return m
+
+
+@pytest.mark.parametrize("kind,kw,precision", [(GAUSSIAN, dict(h=1.0), 0), (POLYNOMIAL, dict(h=2.0, p=2), 2)])
+def test_step_graph_replays_match_eager(ffc, kind, kw, precision):
+    X = W.gaussian_mixture(4096, 8, k=8, box=6.0, std=0.5, seed=3)
+    q = torch.as_tensor(W.charges(4096, seed=1), device="cuda")
+    k = gkernel(kind, **kw)
+    opts = dict(tol=1e-7, max_rank=48, num_samples=96, precision=precision, seed=5)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        tree = ffc.build_tree(X, 256)
+        sk = ffc.skeletonize(tree, k, **opts)
+        u_e, uf_e = ffc.evaluate_sum(tree, sk, k, q, precision=precision)
+        stream.synchronize()
+        u_e, uf_e = u_e.cpu().numpy(), uf_e.cpu().numpy()
+        ranks = [sk.node(a)["rank"] for a in range(1, tree.num_nodes)]
+        u = torch.zeros(4096, dtype=torch.float64, device="cuda")
+        uf = torch.zeros(4096, dtype=torch.float64, device="cuda")
+        g = ffc.StepGraph(tree, sk, k, q, u, uf, stream, **opts)
+        for rep in range(3):
+            # Eager work between replays: a skeletonization with another seed
+            # rewrites the shared buffers, and an unrelated direct sum.
+            ffc.skeletonize(tree, k, **dict(opts, seed=11 + rep), reuse=sk)
+            ffc.direct_sum(X[:64], X, q, k)
+            u.zero_()
+            uf.zero_()
+            g.launch(stream)
+            stream.synchronize()
+            np.testing.assert_array_equal(u.cpu().numpy(), u_e, err_msg=f"replay {rep}")
+            np.testing.assert_array_equal(uf.cpu().numpy(), uf_e, err_msg=f"replay {rep}")
+            assert [sk.node(a)["rank"] for a in range(1, tree.num_nodes)] == ranks
+        ffc.check_device(stream)
+
+
+def test_step_graph_rejects_null_stream_and_fallback(ffc):
+    X = W.uniform_cube(1024, 4, seed=0)
+    q = torch.as_tensor(W.charges(1024, seed=1), device="cuda")
+    k = gkernel(GAUSSIAN, h=0.5)
+    tree = ffc.build_tree(X, 128)
+    sk = ffc.skeletonize(tree, k, tol=1e-6, max_rank=32)
+    u = torch.empty(1024, dtype=torch.float64, device="cuda")
+    with pytest.raises(ffc.FfcError) as e:
+        ffc.StepGraph(tree, sk, k, q, u, None, torch.cuda.default_stream(), tol=1e-6, max_rank=32)
+    assert e.value.code == ffc.FFC_ERR_INVALID_ARG
