@@ -81,6 +81,8 @@ def parse():
                     help="other precisions timed on the same workload, each judged against the FP64 path")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (5 times) to calibrate memory counters")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager calls instead of replays of the step captured as a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     return ap.parse_args()
@@ -260,18 +262,35 @@ def main():
         ffc.evaluate_sum_into(tree, sk, k, qd, out[0], out[1], precision=p)
         return sk
 
+    use_graph = not args.eager and not (proposal is not None and w.get("fallback_tol", 0.0) > 0)
+
     def timed(p, steps, warmup, out):
+        """Warm-up with eager calls, then time `steps` steps in precision p (graph replays unless --eager)."""
         sk = None
         for _ in range(max(1, warmup)):
             sk = step(sk, p=p, out=out)
         torch.cuda.synchronize()
+        st = torch.cuda.Stream() if use_graph else torch.cuda.current_stream()
+        st.wait_stream(torch.cuda.current_stream())
+        graph = None
+        if use_graph:
+            graph = ffc.StepGraph(tree, sk, k, qd, out[0], out[1], st, tol=w["tol"], max_rank=w["max_rank"],
+                                  num_samples=w["num_samples"], precision=p, seed=0, proposal=proposal,
+                                  pool_factor=w.get("pool_factor", 0))
+            graph.launch(st)
+        st.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
+        ev0.record(st)
         for _ in range(steps):
-            sk = step(sk, p=p, out=out)
-        ev1.record()
-        torch.cuda.synchronize()
-        ffc.check_device()
+            if graph is not None:
+                graph.launch(st)
+            else:
+                with torch.cuda.stream(st):
+                    sk = step(sk, p=p, out=out)
+        ev1.record(st)
+        st.synchronize()
+        ffc.check_device(st)
+        torch.cuda.current_stream().wait_stream(st)
         return sk, ev0.elapsed_time(ev1) / steps
 
     sk = None
@@ -280,6 +299,7 @@ def main():
     torch.cuda.synchronize()
     ffc.check_device()
     print("[bench] warm-up done", file=sys.stderr, flush=True)
+    # Eager pass with the stage profiler (per-stage times and the roofline of the dominant kernel).
     ffc.profile_read(reset=True)
     ffc.profile_enable(True)
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -291,10 +311,30 @@ def main():
     torch.cuda.synchronize()
     ffc.profile_enable(False)
     prof = ffc.profile_read(reset=True)
-    ms_total = start.elapsed_time(stop)
-    ms_step = ms_total / args.steps
+    ms_eager = start.elapsed_time(stop) / args.steps
     ffc.check_device()
-    print(f"[bench] timed {args.steps} steps: {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
+    print(f"[bench] eager: {args.steps} steps, {ms_eager:.3f} ms/step", file=sys.stderr, flush=True)
+    ms_step, timing = ms_eager, "eager calls"
+    if use_graph:
+        # The same step captured once as a HIP graph (skeletonize with reuse + evaluate) and replayed.
+        gstream = torch.cuda.Stream()
+        gstream.wait_stream(torch.cuda.current_stream())
+        graph = ffc.StepGraph(tree, sk, k, qd, u, uf, gstream, tol=w["tol"], max_rank=w["max_rank"],
+                              num_samples=w["num_samples"], precision=prec, seed=0, proposal=proposal,
+                              pool_factor=w.get("pool_factor", 0))
+        for _ in range(max(1, args.warmup)):
+            graph.launch(gstream)
+        gstream.synchronize()
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record(gstream)
+        for _ in range(args.steps):
+            graph.launch(gstream)
+        g1.record(gstream)
+        gstream.synchronize()
+        ffc.check_device(gstream)
+        ms_step, timing = g0.elapsed_time(g1) / args.steps, "HIP graph replays"
+        torch.cuda.current_stream().wait_stream(gstream)
+        print(f"[bench] graph: {args.steps} steps, {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
 
     # Work counts of one step.
     st = sk.stats()
@@ -376,7 +416,8 @@ def main():
 
     out = {
         "metric": METRIC, "value": nodes_per_s, "unit": "nodes/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": ms_step, "timing": timing, "eager_ms_per_step": ms_eager,
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "bf16x3+f32+f64"}[pname],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {w['text']}, leaf {w['leaf']}, s={w['num_samples']}, "

@@ -424,16 +424,30 @@ __global__ void __launch_bounds__(NT) k_id_solve(SolveArgs sa) {
     pos[j] = l;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {   // remaining columns, ascending, after the pivots
-    int q = 0;
-    for (int j = 0; j < n; ++j)
-      if (pos[j] < 0) {
-        np[q] = j;
-        piv[r + q] = j;
-        ++q;
-      }
+  // Remaining columns, ascending, after the pivots: ballot / popcount prefix
+  // per wavefront, wavefront offsets through LDS.
+  __shared__ int wcount[NWV];
+  __shared__ int s_base;
+  if (threadIdx.x == 0) s_base = 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < n; j0 += NT) {
+    const int j = j0 + (int)threadIdx.x;
+    const bool f = j < n && pos[j] < 0;
+    const unsigned long long m = __ballot(f);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wcount[wv] = __popcll(m);
+    __syncthreads();
+    int off = s_base;
+    for (int q = 0; q < wv; ++q) off += wcount[q];
+    if (f) {
+      np[off + before] = j;
+      piv[r + off + before] = j;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int q = 0; q < NWV; ++q) s_base += wcount[q];
+    __syncthreads();
   }
-  __syncthreads();
   const int nnp = n - r;
   const int rs = sa.r_max;
   for (int c0 = 0; c0 < nnp; c0 += NT) {
