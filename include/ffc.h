@@ -347,9 +347,10 @@ ffc_status ffc_profile_enable(int32_t on);
 /* Autotuner: the first pivoted-QR launch of each block shape times the kernel
  * variants (rows per lane, workgroup size) that can hold the blocks on a copy of
  * them and keeps the fastest; FFC_AUTOTUNE=0 in the environment disables it.
- * Writes up to `cap` entries of 8 int32 (s_max, n_max, batch, rank cap, rows per
- * lane, threads per workgroup, best time in us, first candidate's time in us)
- * to out_host and their total number to *count. */
+ * Writes up to `cap` entries of 8 int32 (s_max, n_max, batch, rank cap, 100 x
+ * rows per lane + columns per lane group, threads per workgroup, best time in
+ * us, first candidate's time in us) to out_host and their total number to
+ * *count. */
 ffc_status ffc_autotune_report(int32_t* out_host, int32_t cap, int32_t* count);
 ffc_status ffc_profile_read(double* ms_host, int64_t* launches_host, int32_t num_stages, int32_t reset);
 

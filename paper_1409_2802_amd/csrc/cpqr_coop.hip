@@ -144,11 +144,11 @@ __device__ inline double row16_sum(double x) {
 // Register layout: a wavefront is 4 lane groups of 16 lanes; a lane group owns
 // CS columns and each of its lanes keeps RL rows (i = lane16 + 16 m) of them,
 // so a column's dot products and norms are 16-lane DPP reductions.
-// Variants: RL rows per lane (16 or 32) and NTC threads per workgroup (512 or
-// 256); both keep at most 256 VGPRs per lane (two waves per SIMD).
-template <int RL, int NTC>
+// Variants: RL rows per lane (16 or 32), CS columns per lane group (64 / RL,
+// or 1 to halve the per-wave work of a step for small batches) and NTC threads
+// per workgroup (512 or 256); all keep at most 256 VGPRs per lane.
+template <int RL, int CS, int NTC>
 __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
-  constexpr int CS = 64 / RL;          // columns per lane group
   constexpr int CPW = 4 * CS;          // columns per wavefront
   constexpr int ROWS = 16 * RL;        // rows a lane group holds (LDS rows are padded to it)
   constexpr int NWVC = NTC / 64;       // wavefronts per workgroup
@@ -505,12 +505,12 @@ int resident_grid(const void* kern, int threads, size_t lds) {
 
 // The factorization with variant (R, NTC) on the blocks of bt (in place);
 // fits = false (nothing launched) when a block's group cannot be resident.
-template <int R, int NTC>
+template <int R, int CS, int NTC>
 ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hipStream_t st, bool& fits) {
-  constexpr int CPW = 4 * (64 / R);   // columns per wavefront
+  constexpr int CPW = 4 * CS;   // columns per wavefront
   const int cols_per_wg = CPW * (NTC / 64);
   const int gmax = std::max(1, (bt.n_max + cols_per_wg - 1) / cols_per_wg);
-  const void* kern = reinterpret_cast<const void*>(&k_cpqr_coop<R, NTC>);
+  const void* kern = reinterpret_cast<const void*>(&k_cpqr_coop<R, CS, NTC>);
   const size_t lds = (size_t)(NTC / 64 + 1) * 16 * R * sizeof(double);
   const int grid_cap = resident_grid(kern, NTC, lds);
   fits = grid_cap >= gmax;
@@ -590,14 +590,14 @@ ffc_status launch_solve(const IdBatch& bt, int batch, hipStream_t st) {
 // ---------------------------------------------------------------------------
 using QrLaunch = ffc_status (*)(const IdBatch&, int, DevBuf<unsigned char>&, hipStream_t, bool&);
 struct Variant {
-  int R, threads;
+  int R, CS, threads;
   QrLaunch fn;
 };
 const Variant kVariants[] = {
-    {16, 512, &launch_qr<16, 512>},
-    {16, 256, &launch_qr<16, 256>},
-    {32, 512, &launch_qr<32, 512>},
-    {32, 256, &launch_qr<32, 256>},
+    {16, 4, 512, &launch_qr<16, 4, 512>}, {16, 4, 256, &launch_qr<16, 4, 256>},
+    {16, 1, 512, &launch_qr<16, 1, 512>}, {32, 2, 512, &launch_qr<32, 2, 512>},
+    {32, 2, 256, &launch_qr<32, 2, 256>}, {32, 1, 512, &launch_qr<32, 1, 512>},
+    {32, 1, 256, &launch_qr<32, 1, 256>},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -720,7 +720,7 @@ int autotune_entries(int32_t* out, int cap) {
     o[1] = te.n_max;
     o[2] = te.batch;
     o[3] = te.max_rank;
-    o[4] = kVariants[te.choice].R;
+    o[4] = kVariants[te.choice].R * 100 + kVariants[te.choice].CS;
     o[5] = kVariants[te.choice].threads;
     o[6] = (int32_t)te.best_us;
     o[7] = (int32_t)te.first_us;

@@ -500,5 +500,11 @@ def autotune_report() -> list:
     _check(lib.ffc_autotune_report(None, 0, ctypes.byref(cnt)))
     buf = np.zeros(8 * max(cnt.value, 1), dtype=np.int32)
     _check(lib.ffc_autotune_report(buf.ctypes.data, cnt.value, ctypes.byref(cnt)))
-    keys = ["s_max", "n_max", "batch", "max_rank", "rows_per_lane", "threads", "best_us", "first_us"]
-    return [dict(zip(keys, map(int, buf[8 * e:8 * e + 8]))) for e in range(cnt.value)]
+    keys = ["s_max", "n_max", "batch", "max_rank", "variant", "threads", "best_us", "first_us"]
+    out = []
+    for e in range(cnt.value):
+        rec = dict(zip(keys, map(int, buf[8 * e:8 * e + 8])))
+        v = rec.pop("variant")
+        rec["rows_per_lane"], rec["cols_per_lane_group"] = v // 100, v % 100
+        out.append(rec)
+    return out
