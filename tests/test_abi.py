@@ -49,3 +49,31 @@ def test_argument_validation_without_gpu():
     out = ctypes.c_void_p()
     assert lib.ffc_build_tree(None, 10, 3, 4, None, ctypes.byref(out)) == ffc.FFC_ERR_INVALID_ARG
     assert lib.ffc_interp_decomp(None, 1, 0, 4, 1e-3, 2, None, None, None, None) == ffc.FFC_ERR_INVALID_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libffc.so not built")
+def test_proposal_graph_and_label_validation_without_gpu():
+    """The proposal, label, graph and autotuner entry points reject bad arguments before any device work."""
+    from paper_1409_2802_amd import ffc
+    lib = ffc.load_library()
+    out = ctypes.c_void_p()
+    assert lib.ffc_proposal_create(None, None, None, ctypes.byref(out)) == ffc.FFC_ERR_INVALID_ARG
+    import numpy as np
+    bad = np.full(ffc.NPARAM, np.nan, dtype=np.float32)
+    assert lib.ffc_proposal_create(bad.ctypes.data, None, None, ctypes.byref(out)) == ffc.FFC_ERR_INVALID_ARG
+    assert b"finite" in lib.ffc_last_error()
+    assert lib.ffc_leverage_labels(None, 4, 3, 1, 0.0, None, None, None) == ffc.FFC_ERR_INVALID_ARG
+    assert lib.ffc_leverage_labels(None, 0, 3, 1, 1e-3, None, None, None) == ffc.FFC_ERR_INVALID_ARG
+    k = ffc.KernelC(kind=ffc.GAUSSIAN, p=1, h=1.0, c=1.0)
+    o = ffc.SkelOptsC(tol=1e-6, max_rank=8, num_samples=0, precision=0, sampler=0, seed=0, proposal=None,
+                      fallback_tol=0.0, pool_factor=0)
+    assert lib.ffc_step_graph_create(None, None, ctypes.byref(k), ctypes.byref(o), None, None, None, 0, None,
+                                     ctypes.byref(out)) == ffc.FFC_ERR_INVALID_ARG
+    skel = ctypes.c_void_p()
+    assert lib.ffc_skeletonize_nodes(None, ctypes.byref(k), ctypes.byref(o), None, ctypes.byref(skel)) == \
+        ffc.FFC_ERR_INVALID_ARG
+    assert b"tree" in lib.ffc_last_error()
+    assert lib.ffc_autotune_report(None, 0, None) == ffc.FFC_ERR_INVALID_ARG
+    t = ffc.TrainOptsC(num_blocks=0, block_cols=8, block_rows=8, epochs=1, batch=8, lr=1e-3, eps=1e-3, seed=0)
+    assert lib.ffc_proposal_train(None, None, ctypes.byref(k), ctypes.byref(t), None, None) == \
+        ffc.FFC_ERR_INVALID_ARG

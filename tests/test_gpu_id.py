@@ -48,7 +48,11 @@ def check_against_oracle(A, rank, piv, P, tol, max_rank):
 
 
 @pytest.mark.parametrize("s,n,tol,max_rank", [(40, 30, 1e-6, 30), (128, 256, 1e-6, 64), (512, 512, 1e-5, 256),
-                                              (100, 7, 0.0, 7), (33, 65, 1e-3, 5), (1, 9, 1e-3, 3), (9, 1, 1e-3, 3)])
+                                              (100, 7, 0.0, 7), (33, 65, 1e-3, 5), (1, 9, 1e-3, 3), (9, 1, 1e-3, 3),
+                                              # 257 rows (32-row lanes), wide blocks (many workgroups per
+                                              # block), and more than 512 rows (the streamed kernel)
+                                              (257, 64, 1e-6, 32), (300, 1500, 1e-6, 128), (700, 300, 1e-6, 100),
+                                              (1024, 50, 1e-4, 50)])
 def test_batched_id_matches_oracle(ffc, s, n, tol, max_rank):
     mats = [decaying(s, n, seed) for seed in range(3)]
     rank, piv, P = ffc.interp_decomp(np.stack(mats), tol, max_rank)

@@ -119,3 +119,19 @@ def test_skeleton_reuse_and_determinism(ffc):
     assert sk2 is sk
     u2, _ = ffc.evaluate_sum(t, sk, gk, q)
     assert torch.equal(u1, u2)
+
+
+@pytest.mark.parametrize("N", [1, 50])
+def test_single_leaf_tree(ffc, N):
+    """Depth 0 (every point in the root leaf): nothing to skeletonize, the far field is empty and the sum is the
+    direct sum."""
+    X = W.uniform_cube(N, 5, seed=4)
+    q = W.charges(N, seed=5)
+    gk, ok = gkernel(GAUSSIAN, h=0.8), okernel(GAUSSIAN, h=0.8)
+    t = ffc.build_tree(X, 64)
+    assert t.depth == 0 and t.num_nodes == 1
+    sk = ffc.skeletonize(t, gk, tol=1e-6, max_rank=16)
+    u, uf = ffc.evaluate_sum(t, sk, gk, q)
+    assert np.all(uf.cpu().numpy() == 0.0)
+    assert rel(u.cpu().numpy(), o_direct(X, X, q, ok)) < 1e-13
+    assert sk.stats()["num_nodes"] == 0
