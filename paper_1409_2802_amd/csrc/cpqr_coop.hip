@@ -155,6 +155,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
   __shared__ Best wb[NWVC];
   __shared__ int s_win[3];             // {ok, winner group, winner column}
   __shared__ double s_nv;              // winner's norm (tag cleared)
+  __shared__ double s_xk;              // winner's row k
   extern __shared__ double lds[];      // NWVC candidate columns, then the winner column (ROWS each)
   double* candcol = lds;
   double* wincol = lds + NWVC * ROWS;
@@ -290,17 +291,27 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       orig = s_win[2];
       return s_win[0] != 0;
     };
-    // Rows k..s-1 of the winner's column into LDS (one row per thread, reread
-    // until every word carries step k's tag). False on timeout.
+    // The reflector v of step k into LDS: rows k+1..s-1 of the winner's column,
+    // x_k - alpha in row k (x_k kept in s_xk), zero elsewhere (rows >= s are
+    // cleared once per block, row k - 1 at step k). One row per thread,
+    // reread until every word carries step k's tag. False on timeout.
     auto load_winner = [&](int k, int gwin) -> bool {
       const double* sl = slot_ptr(ca, b, k & 1, gwin);
       const long long tag = step_tag(k);
+      const double rho = sqrt(s_nv);
+      if (k > 0 && threadIdx.x == 0) wincol[k - 1] = 0.0;
       for (unsigned int spins = 0;; ++spins) {
         int stale = 0;
         for (int i = k + (int)threadIdx.x; i < s; i += NTC) {
-          const double x = slot_load(sl + 2 + i);
-          stale |= tag_of(x) != tag;
-          wincol[i] = untag(x);
+          const double raw = slot_load(sl + 2 + i);
+          stale |= tag_of(raw) != tag;
+          const double x = untag(raw);
+          if (i == k) {
+            s_xk = x;
+            wincol[i] = x - (x != 0.0 ? -copysign(rho, x) : -rho);
+          } else {
+            wincol[i] = x;
+          }
         }
         if (!__syncthreads_or(stale)) return true;
         if (spins > kSpinLimit) {
@@ -311,7 +322,8 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       }
     };
 
-    publish(0);
+    for (int i = threadIdx.x; i < ROWS; i += NTC) wincol[i] = 0.0;
+    publish(0);   // its barrier also orders the clearing above
     int gwin, porig;
     bool alive = poll(0, gwin, porig);
     if (alive && porig != INT_MAX) alive = load_winner(0, gwin);
@@ -323,16 +335,13 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       if (porig == INT_MAX) break;
       const double rho = sqrt(nv);
       if (rho == 0.0 || rho < ca.tol * rho0) break;
-      const double xk = wincol[k];
+      const double xk = s_xk;
       const double alpha = xk != 0.0 ? -copysign(rho, xk) : -rho;
       double v[RL];
       double part = 0.0;
 #pragma unroll
-      for (int m = 0; m < RL; ++m) v[m] = wincol[l16 + 16 * m];   // unconditional: no branch per read
-#pragma unroll
-      for (int m = 0; m < RL; ++m) {
-        const int i = l16 + 16 * m;
-        v[m] = (i >= k && i < s) ? (i == k ? xk - alpha : v[m]) : 0.0;
+      for (int m = 0; m < RL; ++m) {   // the reflector as staged: zero outside rows k..s-1
+        v[m] = wincol[l16 + 16 * m];
         part = fma(v[m], v[m], part);
       }
       // Every lane group holds all rows, so the reflector norm is a 16-lane sum.
