@@ -79,8 +79,8 @@ __global__ void k_sample_rows(const int32_t* __restrict__ nb, const int32_t* __r
 // Bitmap variant (complement size M up to 32 * kMaxBitmapWords): the chosen
 // set lives as a bitmap of {0..M-1} in LDS, so membership is one bit test and
 // the ascending order falls out of a prefix count over the words. The Floyd
-// values t_j are produced in parallel, then one lane applies the sequential
-// insert rule (j replaces t_j when t_j is already taken).
+// values t_j are produced in parallel; the sequential insert rule (j replaces
+// t_j when t_j is already taken) is applied 64 steps at a time.
 constexpr int kMaxBitmapWords = 12288;   // 48 KB of LDS -> M <= 393216
 constexpr int kBitmapThreads = 256;
 
@@ -90,7 +90,7 @@ k_sample_rows_bitmap(const int32_t* __restrict__ nb, const int32_t* __restrict__
                      const unsigned char* __restrict__ mask, int32_t* __restrict__ rows,
                      int32_t* __restrict__ nrows) {
   extern __shared__ unsigned int bits[];            // nwords bitmap words, then s ints of t values
-  __shared__ int wsum[kBitmapThreads];
+  __shared__ int wsum[kBitmapThreads / 64];
   const int node = first + blockIdx.x;
   const int tid = threadIdx.x;
   if (mask && !mask[node]) return;
@@ -113,12 +113,35 @@ k_sample_rows_bitmap(const int32_t* __restrict__ nb, const int32_t* __restrict__
     tv[q] = (int)__umul64hi(u, (uint64_t)(j + 1));
   }
   __syncthreads();
-  if (tid == 0) {
-    for (int q = 0; q < s; ++q) {
-      int t = tv[q];
-      const unsigned int m = 1u << (t & 31);
-      if (bits[t >> 5] & m) t = M - s + q;
-      bits[t >> 5] |= 1u << (t & 31);
+  // The insert rule, 64 steps at a time on wave 0. Against the set as it
+  // stood before the chunk, step q's choice c_q is j_q when t_q is taken and
+  // t_q otherwise. Every c_q is absent from that set (earlier values are all
+  // below j_q), so the chunk's choices agree with the sequential rule exactly
+  // when they are pairwise distinct: a lane that finds its bit already set by
+  // the atomic OR reveals a repeat, the chunk's bits are cleared again and
+  // lane 0 replays those 64 steps one by one.
+  if (tid < 64) {
+    for (int q0 = 0; q0 < s; q0 += 64) {
+      const int q = q0 + tid;
+      const bool act = q < s;
+      int c = 0;
+      unsigned int bit = 0u;
+      if (act) {
+        const int t = tv[q];
+        c = (bits[t >> 5] >> (t & 31)) & 1u ? M - s + q : t;
+        bit = 1u << (c & 31);
+      }
+      const unsigned int old = act ? atomicOr(&bits[c >> 5], bit) : 0u;
+      if (__ballot(act && (old & bit)) != 0ull) {
+        if (act) atomicAnd(&bits[c >> 5], ~bit);
+        if (tid == 0) {
+          for (int p = q0; p < min(s, q0 + 64); ++p) {
+            int t = tv[p];
+            if ((bits[t >> 5] >> (t & 31)) & 1u) t = M - s + p;
+            bits[t >> 5] |= 1u << (t & 31);
+          }
+        }
+      }
     }
   }
   __syncthreads();
@@ -127,18 +150,18 @@ k_sample_rows_bitmap(const int32_t* __restrict__ nb, const int32_t* __restrict__
   const int w0 = tid * per, w1 = min(nwords, w0 + per);
   int cnt = 0;
   for (int w = w0; w < w1; ++w) cnt += __popc(bits[w]);
-  wsum[tid] = cnt;
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int i = 0; i < kBitmapThreads; ++i) {
-      const int c = wsum[i];
-      wsum[i] = acc;
-      acc += c;
-    }
+  // Block-wide exclusive prefix of the counts: a shuffle scan per wave, then
+  // the totals of the waves before this one.
+  const int lane = tid & 63, wid = tid >> 6;
+  int incl = cnt;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
   }
+  if (lane == 63) wsum[wid] = incl;
   __syncthreads();
-  int pos = wsum[tid];
+  int pos = incl - cnt;
+  for (int w = 0; w < wid; ++w) pos += wsum[w];
   for (int w = w0; w < w1; ++w) {
     unsigned int word = bits[w];
     while (word) {
