@@ -504,6 +504,130 @@ __global__ void __launch_bounds__(NT) k_id_solve(SolveArgs sa) {
   }
 }
 
+// Solve for ranks whose right-hand sides fit in LDS. One workgroup of SW
+// wavefronts per (block, chunk of 64 columns): it writes the identity part of
+// P for the pivot columns among columns [64 ch, 64 ch + 64) and solves for the
+// non-pivot columns whose place in the ascending non-pivot order is in the
+// same range. Each lane owns one right-hand column, held in LDS as
+// T(0:r, c). Back substitution runs bottom-up in blocks of SBK rows: each
+// wavefront accumulates the contribution of a contiguous quarter of the rows
+// already solved below the block, reading R through wavefront-uniform scalar
+// loads (R is only read here, so the loads can use the scalar cache); wave 0
+// adds the four partial sums and solves the SBK x SBK triangle, multiplying by
+// the reciprocal of each diagonal entry. The solution goes straight from LDS
+// to P; A is left as the factorization wrote it.
+constexpr int SW = 4, SNT = 64 * SW, SBK = 8, TS = 65;
+
+size_t solve_lds_bytes(int r_max, int n_max) {
+  return (size_t)r_max * TS * sizeof(double) + (size_t)(SW - 1) * SBK * 64 * sizeof(double) +
+         ((size_t)(n_max + 31) / 32 + 128) * sizeof(int);
+}
+
+__global__ void __launch_bounds__(SNT)
+k_id_solve_lds(const double* __restrict__ A, int64_t a_stride, int lda, const int32_t* __restrict__ n_arr,
+               int n_uniform, int n_max, const int32_t* __restrict__ rank, int32_t* __restrict__ piv,
+               int64_t piv_stride, double* __restrict__ P, int64_t p_stride, int p_ld, int r_max) {
+  extern __shared__ double sml[];
+  __shared__ int wcnt[SW];
+  const int b = blockIdx.x, j0 = 64 * (int)blockIdx.y;
+  const int n = n_arr ? n_arr[b] : n_uniform;
+  if (j0 >= n) return;
+  const int r = rank[b];
+  double* T = sml;                                    // r_max x TS
+  double* red = T + (size_t)r_max * TS;               // (SW - 1) x SBK x 64 partial sums
+  unsigned int* isp = reinterpret_cast<unsigned int*>(red + (SW - 1) * SBK * 64);   // pivot bitmap
+  int* npc = reinterpret_cast<int*>(isp + (n_max + 31) / 32);   // this chunk's non-pivot columns
+  int* posl = npc + 64;                                          // pivot position of column j0 + c, or -1
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double* Ab = A + (int64_t)b * a_stride;
+  const int32_t* pb = piv + (int64_t)b * piv_stride;
+  for (int i = tid; i < (n + 31) / 32; i += SNT) isp[i] = 0u;
+  if (tid < 64) posl[tid] = -1;
+  __syncthreads();
+  for (int l = tid; l < r; l += SNT) {
+    const int j = pb[l];
+    atomicOr(&isp[j >> 5], 1u << (j & 31));
+    if (j >= j0 && j < j0 + 64) posl[j - j0] = l;
+  }
+  __syncthreads();
+  // Non-pivot columns in ascending order (place = j minus the pivots below j).
+  int base = 0;
+  for (int c0 = 0; c0 < n && base < j0 + 64; c0 += SNT) {
+    const int j = c0 + tid;
+    const bool f = j < n && !((isp[j >> 5] >> (j & 31)) & 1u);
+    const unsigned long long m = __ballot(f);
+    if (lane == 0) wcnt[w] = __popcll(m);
+    __syncthreads();
+    int q = base + __popcll(m & ((1ull << lane) - 1ull));
+    for (int v = 0; v < SW; ++v) {
+      if (v < w) q += wcnt[v];
+      base += wcnt[v];
+    }
+    if (f && q >= j0 && q < j0 + 64) npc[q - j0] = j;
+    __syncthreads();
+  }
+  const int nq = min(64, n - r - j0);
+  for (int e = tid; e < nq * r; e += SNT) {
+    const int c = e / r, l = e - c * r;
+    T[l * TS + c] = Ab[(int64_t)npc[c] * lda + l];
+  }
+  __syncthreads();
+  if (nq > 0 && r > 0) {
+    for (int kb = ((r - 1) / SBK) * SBK; kb >= 0; kb -= SBK) {
+      double part[SBK];
+#pragma unroll
+      for (int ii = 0; ii < SBK; ++ii) part[ii] = 0.0;
+      const int l0 = kb + SBK, per = (r - l0 + SW - 1) / SW;
+      const int la = l0 + w * per, lb = min(r, la + per);
+#pragma unroll 4
+      for (int l = la; l < lb; ++l) {
+        const double* Rc = Ab + (int64_t)pb[l] * lda + kb;   // R(kb:kb+SBK, l)
+        const double x = T[l * TS + lane];
+#pragma unroll
+        for (int ii = 0; ii < SBK; ++ii) part[ii] = fma(Rc[ii], x, part[ii]);
+      }
+      if (w > 0) {
+#pragma unroll
+        for (int ii = 0; ii < SBK; ++ii) red[((w - 1) * SBK + ii) * 64 + lane] = part[ii];
+      }
+      __syncthreads();
+      if (w == 0) {
+        const int nii = min(SBK, r - kb);
+        double t[SBK];
+#pragma unroll
+        for (int ii = 0; ii < SBK; ++ii) {
+          double acc = part[ii];
+#pragma unroll
+          for (int v = 0; v < SW - 1; ++v) acc += red[(v * SBK + ii) * 64 + lane];
+          t[ii] = ii < nii ? T[(kb + ii) * TS + lane] - acc : 0.0;
+        }
+        // Column-oriented triangle: x_jj is final once the columns right of it
+        // are removed; then column jj of R (rows kb..kb+jj-1) updates the rest.
+#pragma unroll
+        for (int jj = SBK - 1; jj >= 0; --jj) {
+          if (jj < nii) {
+            const double* Rc = Ab + (int64_t)pb[kb + jj] * lda + kb;
+            t[jj] *= 1.0 / Rc[jj];
+            T[(kb + jj) * TS + lane] = t[jj];
+#pragma unroll
+            for (int ii = 0; ii < jj; ++ii) t[ii] = fma(-Rc[ii], t[jj], t[ii]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  double* Pb = P + (int64_t)b * p_stride;
+  for (int e = tid; e < r * 64; e += SNT) {
+    const int i = e >> 6, c = e & 63;
+    if (c < nq) Pb[(int64_t)i * p_ld + npc[c]] = T[i * TS + c];
+    const int pl = posl[c];
+    if (pl >= 0) Pb[(int64_t)i * p_ld + j0 + c] = pl == i ? 1.0 : 0.0;
+  }
+  for (int c = tid; c < nq; c += SNT) piv[(int64_t)b * piv_stride + r + j0 + c] = npc[c];
+}
+
 int resident_grid(const void* kern, int threads, size_t lds) {
   int dev = 0, nb = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -580,6 +704,20 @@ ffc_status launch_solve(const IdBatch& bt, int batch, hipStream_t st) {
   sa.p_stride = bt.p_stride;
   sa.p_ld = bt.p_ld;
   sa.r_max = std::max(1, std::min(bt.max_rank, std::min(bt.s_max, bt.n_max)));
+  int dev = 0, lds_cap = 0;
+  FFC_HIP_TRY(hipGetDevice(&dev));
+  FFC_HIP_TRY(hipDeviceGetAttribute(&lds_cap, hipDeviceAttributeSharedMemPerBlockOptin, dev));
+  const size_t llds = solve_lds_bytes(sa.r_max, bt.n_max);
+  if (llds + SW * sizeof(int) <= (size_t)lds_cap) {
+    const void* kern = reinterpret_cast<const void*>(&k_id_solve_lds);
+    if (llds > 64 * 1024) FFC_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)llds));
+    StageTimer tm(FFC_STAGE_SOLVE, st);
+    hipLaunchKernelGGL(k_id_solve_lds, dim3(batch, (bt.n_max + 63) / 64), dim3(SNT), llds, st, sa.A, sa.a_stride,
+                       sa.lda, sa.n_arr, sa.n_uniform, sa.n_max, sa.rank, sa.piv, sa.piv_stride, sa.P, sa.p_stride,
+                       sa.p_ld, sa.r_max);
+    FFC_LAUNCH_CHECK("k_id_solve_lds");
+    return FFC_OK;
+  }
   const size_t slds = (size_t)SB * sa.r_max * sizeof(double) + 3 * (size_t)bt.n_max * sizeof(int);
   if (slds > 64 * 1024)
     FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_id_solve),
