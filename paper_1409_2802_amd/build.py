@@ -21,6 +21,10 @@ SOURCES = ["api.hip", "tree.hip", "sample.hip", "kblock.hip", "cpqr.hip", "cpqr_
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-file additions. The FP64 matrix-core solve keeps its accumulators in
+# ordinary VGPRs (the default placement copies them to AGPRs and back on
+# every loop iteration); this file's other kernels use no matrix cores.
+FILE_FLAGS = {"cpqr_coop.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _run(cmd: list[str]) -> None:
@@ -33,7 +37,8 @@ def _run(cmd: list[str]) -> None:
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in SOURCES]
-    cmds = [[HIPCC, *FLAGS, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+    cmds = [[HIPCC, *FLAGS, *FILE_FLAGS.get(s, []), "-c", os.path.join(CSRC, s), "-o", o]
+            for s, o in zip(SOURCES, objs)]
     with ThreadPoolExecutor(max_workers=min(8, len(cmds))) as ex:
         list(ex.map(_run, cmds))
     tmp = LIB + ".tmp"

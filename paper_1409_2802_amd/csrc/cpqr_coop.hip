@@ -45,8 +45,6 @@
 namespace ffc {
 namespace {
 
-constexpr int NT = 512;
-constexpr int NWV = NT / 64;
 constexpr unsigned int kSpinLimit = 1u << 21;   // ~1 us per poll -> about 2 s
 
 struct CoopArgs {
@@ -389,243 +387,199 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
   }
 }
 
-// T = R11^{-1} R12 and P for blocks factored in place without swaps: column
-// piv[l] holds R(0:l+1, l); every other column j holds R(0:r, j) in rows 0..r-1.
-struct SolveArgs {
-  int r_max;
-  double* A;
-  int64_t a_stride;
-  int lda;
-  const int32_t* n_arr;
-  int n_uniform;
-  int n_max;
-  const int32_t* rank;
-  int32_t* piv;
-  int64_t piv_stride;
-  double* P;
-  int64_t p_stride;
-  int p_ld;
-};
 
-constexpr int SB = 32;   // rows per solve block
+// ---------------------------------------------------------------------------
+// T = R11^{-1} R12 on matrix cores (v_mfma_f64_16x16x4f64, FP64 operands and
+// accumulation). Back substitution in blocks of 16 rows, bottom-up: the
+// contribution of the rows already solved below a block is one 16 x K by
+// K x 16 product, and the block is then solved by multiplying with the inverse
+// of its 16 x 16 diagonal block of R (formed beforehand by k_diag_inv), one
+// more 16 x 16 x 16 product. One wavefront per (block, 16-column chunk): it
+// writes the identity part of P for the pivot columns among columns
+// [16 ch, 16 ch + 16) and solves for the non-pivot columns whose place in the
+// ascending non-pivot order is in that range, their right-hand sides held in
+// LDS. Operand layouts of the 16x16x4 FP64 instruction (checked on the
+// device): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
+// D[4 v + l / 16][l % 16] for v = 0..3.
+// ---------------------------------------------------------------------------
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int MB = 16;    // rows per diagonal block, columns per chunk
+constexpr int MTS = 17;   // LDS row stride of the right-hand sides, in doubles
 
-// One workgroup per block. T = R11^{-1} R12 by blocked back substitution:
-// R11 rows [kb, kb + SB) are staged in LDS, each thread owns one right-hand
-// column and keeps that block of its solution in registers, first removing
-// the contribution of the already solved rows below, then solving the SB x SB
-// triangle.
-__global__ void __launch_bounds__(NT) k_id_solve(SolveArgs sa) {
-  extern __shared__ double smd[];
-  const int b = blockIdx.x;
-  const int n = sa.n_arr ? sa.n_arr[b] : sa.n_uniform;
-  const int r = sa.rank[b];
-  double* Rb = smd;                                             // SB x r_max
-  int* pos = reinterpret_cast<int*>(Rb + (size_t)SB * sa.r_max);  // n_max: pivot position or -1
-  int* pv = pos + sa.n_max;                                     // n_max: pivot columns in order
-  int* np = pv + sa.n_max;                                      // n_max: non-pivot columns
-  double* A = sa.A + (int64_t)b * sa.a_stride;
-  int32_t* piv = sa.piv + (int64_t)b * sa.piv_stride;
-  for (int j = threadIdx.x; j < n; j += NT) pos[j] = -1;
-  __syncthreads();
-  for (int l = threadIdx.x; l < r; l += NT) {
-    const int j = piv[l];
-    pv[l] = j;
-    pos[j] = l;
-  }
-  __syncthreads();
-  // Remaining columns, ascending, after the pivots: ballot / popcount prefix
-  // per wavefront, wavefront offsets through LDS.
-  __shared__ int wcount[NWV];
-  __shared__ int s_base;
-  if (threadIdx.x == 0) s_base = 0;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int j0 = 0; j0 < n; j0 += NT) {
-    const int j = j0 + (int)threadIdx.x;
-    const bool f = j < n && pos[j] < 0;
-    const unsigned long long m = __ballot(f);
-    const int before = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) wcount[wv] = __popcll(m);
-    __syncthreads();
-    int off = s_base;
-    for (int q = 0; q < wv; ++q) off += wcount[q];
-    if (f) {
-      np[off + before] = j;
-      piv[r + off + before] = j;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-      for (int q = 0; q < NWV; ++q) s_base += wcount[q];
-    __syncthreads();
-  }
-  const int nnp = n - r;
-  const int rs = sa.r_max;
-  for (int c0 = 0; c0 < nnp; c0 += NT) {
-    const int cidx = c0 + (int)threadIdx.x;
-    double* col = cidx < nnp ? A + (int64_t)np[cidx] * sa.lda : nullptr;
-    for (int kb = ((r - 1) / SB) * SB; kb >= 0 && r > 0; kb -= SB) {
-      __syncthreads();
-      // Stage R(kb + ii, l) for l in [kb, r): column pv[l] of A, row kb + ii.
-      const int width = r - kb;
-      for (int e = threadIdx.x; e < SB * width; e += NT) {
-        const int l = kb + e / SB, ii = e % SB;
-        Rb[ii * rs + (l - kb)] = (kb + ii < r) ? A[(int64_t)pv[l] * sa.lda + kb + ii] : 0.0;
-      }
-      __syncthreads();
-      if (col) {
-        double t[SB];
-#pragma unroll
-        for (int ii = 0; ii < SB; ++ii) t[ii] = (kb + ii < r) ? col[kb + ii] : 0.0;
-        for (int l = kb + SB; l < r; ++l) {
-          const double tl = col[l];
-#pragma unroll
-          for (int ii = 0; ii < SB; ++ii) t[ii] = fma(-Rb[ii * rs + (l - kb)], tl, t[ii]);
-        }
-#pragma unroll
-        for (int ii = SB - 1; ii >= 0; --ii) {
-          if (kb + ii < r) {
-#pragma unroll
-            for (int jj = ii + 1; jj < SB; ++jj)
-              if (kb + jj < r) t[ii] = fma(-Rb[ii * rs + jj], t[jj], t[ii]);
-            t[ii] /= Rb[ii * rs + ii];
-          }
-        }
-#pragma unroll
-        for (int ii = 0; ii < SB; ++ii)
-          if (kb + ii < r) col[kb + ii] = t[ii];
-      }
-    }
-  }
-  __syncthreads();
-  double* P = sa.P + (int64_t)b * sa.p_stride;
-  for (int e = threadIdx.x; e < r * n; e += NT) {
-    const int i = e / n, j = e % n;
-    const int pj = pos[j];
-    P[(int64_t)i * sa.p_ld + j] = pj >= 0 ? (pj == i ? 1.0 : 0.0) : A[(int64_t)j * sa.lda + i];
-  }
+int round_mb(int x) { return (x + MB - 1) / MB * MB; }
+__device__ inline int round_mb_dev(int x) { return (x + MB - 1) / MB * MB; }
+
+size_t mfma_solve_lds_bytes(int r_max, int n_max) {
+  return (size_t)(round_mb(r_max) + MB) * MTS * sizeof(double) +
+         ((size_t)r_max + MB + (n_max + 31) / 32 + 2 * MB) * sizeof(int);
 }
 
-// Solve for ranks whose right-hand sides fit in LDS. One workgroup of SW
-// wavefronts per (block, chunk of 64 columns): it writes the identity part of
-// P for the pivot columns among columns [64 ch, 64 ch + 64) and solves for the
-// non-pivot columns whose place in the ascending non-pivot order is in the
-// same range. Each lane owns one right-hand column, held in LDS as
-// T(0:r, c). Back substitution runs bottom-up in blocks of SBK rows: each
-// wavefront accumulates the contribution of a contiguous quarter of the rows
-// already solved below the block, reading R through wavefront-uniform scalar
-// loads (R is only read here, so the loads can use the scalar cache); wave 0
-// adds the four partial sums and solves the SBK x SBK triangle, multiplying by
-// the reciprocal of each diagonal entry. The solution goes straight from LDS
-// to P; A is left as the factorization wrote it.
-constexpr int SW = 4, SNT = 64 * SW, SBK = 8, TS = 65;
+int solve_rank_bound(const IdBatch& bt) { return std::max(1, std::min(bt.max_rank, std::min(bt.s_max, bt.n_max))); }
 
-size_t solve_lds_bytes(int r_max, int n_max) {
-  return (size_t)r_max * TS * sizeof(double) + (size_t)(SW - 1) * SBK * 64 * sizeof(double) +
-         ((size_t)(n_max + 31) / 32 + 128) * sizeof(int);
+// Diagonal block inverses of the matrix-core solve: batch x blocks x 16 x 16.
+size_t solve_scratch_bytes(const IdBatch& bt, int batch) {
+  return (size_t)batch * (round_mb(solve_rank_bound(bt)) / MB) * MB * MB * sizeof(double);
 }
 
-__global__ void __launch_bounds__(SNT)
-k_id_solve_lds(const double* __restrict__ A, int64_t a_stride, int lda, const int32_t* __restrict__ n_arr,
-               int n_uniform, int n_max, const int32_t* __restrict__ rank, int32_t* __restrict__ piv,
-               int64_t piv_stride, double* __restrict__ P, int64_t p_stride, int p_ld, int r_max) {
-  extern __shared__ double sml[];
-  __shared__ int wcnt[SW];
-  const int b = blockIdx.x, j0 = 64 * (int)blockIdx.y;
-  const int n = n_arr ? n_arr[b] : n_uniform;
-  if (j0 >= n) return;
+// Inverse of each 16 x 16 diagonal block of R11, rows and columns past the
+// rank padded with the identity; one wavefront per (block, diagonal block),
+// lane c < 16 back-substituting U x = e_c. Dinv[b][kd] is row-major 16 x 16.
+__global__ void __launch_bounds__(64)
+k_diag_inv(const double* __restrict__ A, int64_t a_stride, int lda, const int32_t* __restrict__ rank,
+           const int32_t* __restrict__ piv, int64_t piv_stride, double* __restrict__ Dinv, int nblk) {
+  __shared__ double U[MB][MB + 1];
+  const int b = blockIdx.x, kd = blockIdx.y, kb = MB * kd;
   const int r = rank[b];
-  double* T = sml;                                    // r_max x TS
-  double* red = T + (size_t)r_max * TS;               // (SW - 1) x SBK x 64 partial sums
-  unsigned int* isp = reinterpret_cast<unsigned int*>(red + (SW - 1) * SBK * 64);   // pivot bitmap
-  int* npc = reinterpret_cast<int*>(isp + (n_max + 31) / 32);   // this chunk's non-pivot columns
-  int* posl = npc + 64;                                          // pivot position of column j0 + c, or -1
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (kb >= r) return;
+  const int nii = min(MB, r - kb);
   const double* Ab = A + (int64_t)b * a_stride;
   const int32_t* pb = piv + (int64_t)b * piv_stride;
-  for (int i = tid; i < (n + 31) / 32; i += SNT) isp[i] = 0u;
-  if (tid < 64) posl[tid] = -1;
-  __syncthreads();
-  for (int l = tid; l < r; l += SNT) {
-    const int j = pb[l];
-    atomicOr(&isp[j >> 5], 1u << (j & 31));
-    if (j >= j0 && j < j0 + 64) posl[j - j0] = l;
+  for (int e = threadIdx.x; e < MB * MB; e += 64) {
+    const int i = e % MB, j = e / MB;   // consecutive lanes walk down a column of R
+    double v = i == j ? 1.0 : 0.0;
+    if (i <= j && j < nii) v = Ab[(int64_t)pb[kb + j] * lda + kb + i];
+    U[i][j] = v;
   }
+  __syncthreads();
+  const int c = threadIdx.x;
+  if (c < MB) {
+    double x[MB];
+#pragma unroll
+    for (int i = MB - 1; i >= 0; --i) {
+      double t = i == c ? 1.0 : 0.0;
+#pragma unroll
+      for (int j = i + 1; j < MB; ++j) t = fma(-U[i][j], x[j], t);
+      x[i] = t / U[i][i];
+    }
+    double* D = Dinv + ((int64_t)b * nblk + kd) * MB * MB;
+#pragma unroll
+    for (int i = 0; i < MB; ++i) D[i * MB + c] = x[i];
+  }
+}
+
+__global__ void __launch_bounds__(64)
+k_id_solve_mfma(const double* __restrict__ A, int64_t a_stride, int lda, const int32_t* __restrict__ n_arr,
+                int n_uniform, int n_max, const int32_t* __restrict__ rank, int32_t* __restrict__ piv,
+                int64_t piv_stride, const double* __restrict__ Dinv, int nblk, double* __restrict__ P,
+                int64_t p_stride, int p_ld, int r_max) {
+  extern __shared__ double smm[];
+  const int b = blockIdx.x, j0 = MB * (int)blockIdx.y;
+  const int n = n_arr ? n_arr[b] : n_uniform;
+  if (j0 >= n) return;
+  const int r = rank[b], r16 = round_mb_dev(r);
+  const int t_rows = round_mb_dev(r_max) + MB;
+  double* T = smm;                                                   // t_rows x MTS
+  int* pv = reinterpret_cast<int*>(T + (size_t)t_rows * MTS);        // r_max + MB pivot columns
+  unsigned int* isp = reinterpret_cast<unsigned int*>(pv + r_max + MB);   // pivot bitmap
+  int* npc = reinterpret_cast<int*>(isp + (n_max + 31) / 32);        // this chunk's non-pivot columns
+  int* posl = npc + MB;                                  // pivot position of column j0 + c, or -1
+  const int lane = threadIdx.x, i16 = lane & 15, g = lane >> 4;
+  const double* Ab = A + (int64_t)b * a_stride;
+  const int32_t* pb = piv + (int64_t)b * piv_stride;
+  for (int w = lane; w < (n + 31) / 32; w += 64) isp[w] = 0u;
+  if (lane < MB) posl[lane] = -1;
+  // Rows r .. r16 + MB - 1 stay zero: the padded part of the last diagonal
+  // block and the tail of the last 16-row chunk of the trailing products.
+  for (int e = lane; e < (r16 + MB) * MB; e += 64) T[(e >> 4) * MTS + (e & 15)] = 0.0;
+  __syncthreads();
+  for (int l = lane; l < r; l += 64) {
+    const int j = pb[l];
+    pv[l] = j;
+    atomicOr(&isp[j >> 5], 1u << (j & 31));
+    if (j >= j0 && j < j0 + MB) posl[j - j0] = l;
+  }
+  // Past the rank the trailing products read a real column of R against
+  // zero right-hand sides, so no lane needs a bounds test.
+  if (r > 0 && lane < MB) pv[r + lane] = pb[0];
   __syncthreads();
   // Non-pivot columns in ascending order (place = j minus the pivots below j).
   int base = 0;
-  for (int c0 = 0; c0 < n && base < j0 + 64; c0 += SNT) {
-    const int j = c0 + tid;
+  for (int c0 = 0; c0 < n && base < j0 + MB; c0 += 64) {
+    const int j = c0 + lane;
     const bool f = j < n && !((isp[j >> 5] >> (j & 31)) & 1u);
     const unsigned long long m = __ballot(f);
-    if (lane == 0) wcnt[w] = __popcll(m);
-    __syncthreads();
-    int q = base + __popcll(m & ((1ull << lane) - 1ull));
-    for (int v = 0; v < SW; ++v) {
-      if (v < w) q += wcnt[v];
-      base += wcnt[v];
-    }
-    if (f && q >= j0 && q < j0 + 64) npc[q - j0] = j;
-    __syncthreads();
+    const int q = base + __popcll(m & ((1ull << lane) - 1ull));
+    if (f && q >= j0 && q < j0 + MB) npc[q - j0] = j;
+    base += __popcll(m);
   }
-  const int nq = min(64, n - r - j0);
-  for (int e = tid; e < nq * r; e += SNT) {
+  __syncthreads();
+  const int nq = min(MB, n - r - j0);
+  for (int e = lane; e < nq * r; e += 64) {
     const int c = e / r, l = e - c * r;
-    T[l * TS + c] = Ab[(int64_t)npc[c] * lda + l];
+    T[l * MTS + c] = Ab[(int64_t)npc[c] * lda + l];
   }
   __syncthreads();
   if (nq > 0 && r > 0) {
-    for (int kb = ((r - 1) / SBK) * SBK; kb >= 0; kb -= SBK) {
-      double part[SBK];
+    for (int kb = r16 - MB; kb >= 0; kb -= MB) {
+      // This block's diagonal inverse (A operands of the last product),
+      // fetched first so that its latency hides behind the trailing products.
+      const double* D = Dinv + ((int64_t)b * nblk + kb / MB) * MB * MB + i16 * MB + g;
+      double dv[MB / 4];
 #pragma unroll
-      for (int ii = 0; ii < SBK; ++ii) part[ii] = 0.0;
-      const int l0 = kb + SBK, per = (r - l0 + SW - 1) / SW;
-      const int la = l0 + w * per, lb = min(r, la + per);
-#pragma unroll 4
-      for (int l = la; l < lb; ++l) {
-        const double* Rc = Ab + (int64_t)pb[l] * lda + kb;   // R(kb:kb+SBK, l)
-        const double x = T[l * TS + lane];
+      for (int k4 = 0; k4 < MB / 4; ++k4) dv[k4] = D[4 * k4];
+      dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+      // Trailing products over 16-row chunks of the solved rows below the
+      // block. Operands are loaded two chunks ahead of their products, into
+      // three buffers used in turn (no register copies, so the waits stay
+      // exact); rows at or past the rank read the zero row r16 of T against
+      // a real column of R.
+      const double* Ak = Ab + kb + i16;
+      auto ld = [&](double(&a)[4], double(&bq)[4], int lc) {
 #pragma unroll
-        for (int ii = 0; ii < SBK; ++ii) part[ii] = fma(Rc[ii], x, part[ii]);
+        for (int m = 0; m < 4; ++m) {
+          const int l = lc + 4 * m + g;
+          const bool in = l < r;
+          a[m] = Ak[(int64_t)pv[in ? l : r] * lda];
+          bq[m] = T[(in ? l : r16) * MTS + i16];
+        }
+      };
+      auto mm = [&](const double(&a)[4], const double(&bq)[4]) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], bq[0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], bq[1], acc1, 0, 0, 0);
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], bq[2], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], bq[3], acc1, 0, 0, 0);
+      };
+      int l0 = kb + MB;
+      if (l0 < r) {
+        double xa[4], xb[4], ya[4], yb[4], za[4], zb[4];
+        ld(xa, xb, l0);
+        ld(ya, yb, l0 + MB);
+        while (true) {
+          ld(za, zb, l0 + 2 * MB);
+          mm(xa, xb);
+          if ((l0 += MB) >= r) break;
+          ld(xa, xb, l0 + 2 * MB);
+          mm(ya, yb);
+          if ((l0 += MB) >= r) break;
+          ld(ya, yb, l0 + 2 * MB);
+          mm(za, zb);
+          if ((l0 += MB) >= r) break;
+        }
       }
-      if (w > 0) {
 #pragma unroll
-        for (int ii = 0; ii < SBK; ++ii) red[((w - 1) * SBK + ii) * 64 + lane] = part[ii];
+      for (int v = 0; v < 4; ++v) {
+        double* t = &T[(kb + 4 * v + g) * MTS + i16];
+        *t = *t - (acc0[v] + acc1[v]);
       }
       __syncthreads();
-      if (w == 0) {
-        const int nii = min(SBK, r - kb);
-        double t[SBK];
+      dbl4 x = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ii = 0; ii < SBK; ++ii) {
-          double acc = part[ii];
+      for (int k4 = 0; k4 < MB / 4; ++k4)
+        x = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[k4], T[(kb + 4 * k4 + g) * MTS + i16], x, 0, 0, 0);
+      __syncthreads();
 #pragma unroll
-          for (int v = 0; v < SW - 1; ++v) acc += red[(v * SBK + ii) * 64 + lane];
-          t[ii] = ii < nii ? T[(kb + ii) * TS + lane] - acc : 0.0;
-        }
-        // Column-oriented triangle: x_jj is final once the columns right of it
-        // are removed; then column jj of R (rows kb..kb+jj-1) updates the rest.
-#pragma unroll
-        for (int jj = SBK - 1; jj >= 0; --jj) {
-          if (jj < nii) {
-            const double* Rc = Ab + (int64_t)pb[kb + jj] * lda + kb;
-            t[jj] *= 1.0 / Rc[jj];
-            T[(kb + jj) * TS + lane] = t[jj];
-#pragma unroll
-            for (int ii = 0; ii < jj; ++ii) t[ii] = fma(-Rc[ii], t[jj], t[ii]);
-          }
-        }
-      }
+      for (int v = 0; v < 4; ++v) T[(kb + 4 * v + g) * MTS + i16] = x[v];
       __syncthreads();
     }
   }
   double* Pb = P + (int64_t)b * p_stride;
-  for (int e = tid; e < r * 64; e += SNT) {
-    const int i = e >> 6, c = e & 63;
-    if (c < nq) Pb[(int64_t)i * p_ld + npc[c]] = T[i * TS + c];
+  for (int e = lane; e < r * MB; e += 64) {
+    const int i = e >> 4, c = e & 15;
+    if (c < nq) Pb[(int64_t)i * p_ld + npc[c]] = T[i * MTS + c];
     const int pl = posl[c];
     if (pl >= 0) Pb[(int64_t)i * p_ld + j0 + c] = pl == i ? 1.0 : 0.0;
   }
-  for (int c = tid; c < nq; c += SNT) piv[(int64_t)b * piv_stride + r + j0 + c] = npc[c];
+  for (int c = lane; c < nq; c += 64) piv[(int64_t)b * piv_stride + r + j0 + c] = npc[c];
 }
 
 int resident_grid(const void* kern, int threads, size_t lds) {
@@ -649,7 +603,9 @@ ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratc
   fits = grid_cap >= gmax;
   if (!fits) return FFC_OK;
   const size_t slot_doubles = (size_t)batch * 2 * gmax * (bt.s_max + 2);
-  const size_t bytes = slot_doubles * sizeof(double) + ((size_t)batch + 1) * sizeof(int32_t);
+  // The solve that follows reuses the scratch: size it for both up front.
+  const size_t bytes = std::max(slot_doubles * sizeof(double) + ((size_t)batch + 1) * sizeof(int32_t),
+                                solve_scratch_bytes(bt, batch));
   if (scratch.count < bytes) FFC_TRY(scratch.alloc(bytes));
   CoopArgs ca{};
   ca.A = bt.A;
@@ -689,42 +645,30 @@ ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratc
   return FFC_OK;
 }
 
-ffc_status launch_solve(const IdBatch& bt, int batch, hipStream_t st) {
-  SolveArgs sa{};
-  sa.A = bt.A;
-  sa.a_stride = bt.a_stride;
-  sa.lda = bt.lda;
-  sa.n_arr = bt.n_arr;
-  sa.n_uniform = bt.n_uniform;
-  sa.n_max = bt.n_max;
-  sa.rank = bt.rank;
-  sa.piv = bt.piv;
-  sa.piv_stride = bt.piv_stride;
-  sa.P = bt.P;
-  sa.p_stride = bt.p_stride;
-  sa.p_ld = bt.p_ld;
-  sa.r_max = std::max(1, std::min(bt.max_rank, std::min(bt.s_max, bt.n_max)));
-  int dev = 0, lds_cap = 0;
-  FFC_HIP_TRY(hipGetDevice(&dev));
-  FFC_HIP_TRY(hipDeviceGetAttribute(&lds_cap, hipDeviceAttributeSharedMemPerBlockOptin, dev));
-  const size_t llds = solve_lds_bytes(sa.r_max, bt.n_max);
-  if (llds + SW * sizeof(int) <= (size_t)lds_cap) {
-    const void* kern = reinterpret_cast<const void*>(&k_id_solve_lds);
-    if (llds > 64 * 1024) FFC_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)llds));
-    StageTimer tm(FFC_STAGE_SOLVE, st);
-    hipLaunchKernelGGL(k_id_solve_lds, dim3(batch, (bt.n_max + 63) / 64), dim3(SNT), llds, st, sa.A, sa.a_stride,
-                       sa.lda, sa.n_arr, sa.n_uniform, sa.n_max, sa.rank, sa.piv, sa.piv_stride, sa.P, sa.p_stride,
-                       sa.p_ld, sa.r_max);
-    FFC_LAUNCH_CHECK("k_id_solve_lds");
-    return FFC_OK;
+// Blocks factored in place without swaps: column piv[l] holds R(0:l+1, l),
+// every other column j holds R(0:r, j) in rows 0..r-1. The QR launch sized
+// the scratch for the diagonal block inverses (it is done with it by now:
+// same stream).
+ffc_status launch_solve(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hipStream_t st) {
+  const int r_max = solve_rank_bound(bt);
+  const int nblk = round_mb(r_max) / MB;
+  if (scratch.count < solve_scratch_bytes(bt, batch)) {
+    set_error("QR scratch smaller than the solve needs");
+    return FFC_ERR_STATE;
   }
-  const size_t slds = (size_t)SB * sa.r_max * sizeof(double) + 3 * (size_t)bt.n_max * sizeof(int);
-  if (slds > 64 * 1024)
-    FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_id_solve),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)slds));
+  double* Dinv = reinterpret_cast<double*>(scratch.ptr);
+  const size_t lds = mfma_solve_lds_bytes(r_max, bt.n_max);
+  if (lds > 64 * 1024)
+    FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_id_solve_mfma),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   StageTimer tm(FFC_STAGE_SOLVE, st);
-  hipLaunchKernelGGL(k_id_solve, dim3(batch), dim3(NT), slds, st, sa);
-  FFC_LAUNCH_CHECK("k_id_solve");
+  hipLaunchKernelGGL(k_diag_inv, dim3(batch, nblk), dim3(64), 0, st, bt.A, bt.a_stride, bt.lda, bt.rank, bt.piv,
+                     bt.piv_stride, Dinv, nblk);
+  FFC_LAUNCH_CHECK("k_diag_inv");
+  hipLaunchKernelGGL(k_id_solve_mfma, dim3(batch, (bt.n_max + MB - 1) / MB), dim3(64), lds, st, bt.A, bt.a_stride,
+                     bt.lda, bt.n_arr, bt.n_uniform, bt.n_max, bt.rank, bt.piv, bt.piv_stride, Dinv, nblk, bt.P,
+                     bt.p_stride, bt.p_ld, r_max);
+  FFC_LAUNCH_CHECK("k_id_solve_mfma");
   return FFC_OK;
 }
 
@@ -814,10 +758,7 @@ ffc_status launch_interp_decomp_coop(const IdBatch& bt, int batch, DevBuf<unsign
                                      bool& used) {
   used = false;
   if (batch <= 0) return FFC_OK;
-  {
-    const int rmax = std::max(1, std::min(bt.max_rank, std::min(bt.s_max, bt.n_max)));
-    if ((size_t)SB * rmax * sizeof(double) + 3 * (size_t)bt.n_max * sizeof(int) > 150 * 1024) return FFC_OK;
-  }
+  if (mfma_solve_lds_bytes(solve_rank_bound(bt), bt.n_max) > 150 * 1024) return FFC_OK;
   std::vector<int> cand;
   for (int v = 0; v < kNumVariants; ++v)
     if (bt.s_max <= 16 * kVariants[v].R) cand.push_back(v);
@@ -849,7 +790,7 @@ ffc_status launch_interp_decomp_coop(const IdBatch& bt, int batch, DevBuf<unsign
     bool fits = false;
     FFC_TRY(kVariants[v].fn(bt, batch, scratch, st, fits));
     if (fits) {
-      FFC_TRY(launch_solve(bt, batch, st));
+      FFC_TRY(launch_solve(bt, batch, scratch, st));
       used = true;
       return FFC_OK;
     }
