@@ -28,13 +28,15 @@
 // The pivot column is frozen in place (its rows 0..k-1 are R(0:k, k), row k
 // gets alpha), so no columns are swapped; the pivot order is recorded.
 //
-// Scheduling: the groups of a level form a flat task list; a persistent grid
-// of co-resident workgroups takes tasks w, w + grid, ... in order. A group's
-// tasks are consecutive, so the smallest unfinished task always has all its
-// members able to reach it: no deadlock as long as G <= grid and the whole
-// grid is resident (guaranteed by the cooperative launch). Barrier waits are
-// bounded; a timeout raises bit 1 of the device flag and the workgroup
-// abandons its remaining work, so every wave exits.
+// Scheduling: the groups of a level form a flat task list (block 0's G_0
+// parts, then block 1's, ...); the workgroups of a persistent grid, all
+// co-resident (guaranteed by the cooperative launch), claim tasks in order
+// from a counter as they become free. The claimed tasks are always a prefix
+// of the list, so every block but the last claimed one has all its members
+// running and finishes, freeing workgroups for the rest: no deadlock as long
+// as G <= grid. Barrier waits are bounded; a timeout raises bit 1 of the
+// device flag and the workgroup abandons its remaining work, so every wave
+// exits.
 #include <climits>
 #include <cstdlib>
 #include <mutex>
@@ -61,6 +63,7 @@ struct CoopArgs {
   int32_t* piv;
   int64_t piv_stride;
   int32_t* task_start;       // [count + 1]
+  int32_t* claim;            // next unclaimed task
   double* slots;             // [count][2][gmax][s_max + 2]: norm, column id, rows (tagged words)
   int64_t slot_words;
   int gmax;
@@ -85,6 +88,7 @@ __device__ inline double wave_sum(double v) {
 // sums into task_start. One workgroup.
 __global__ void k_coop_tasks(CoopArgs ca) {
   if (threadIdx.x == 0) {
+    *ca.claim = 0;
     int acc = 0;
     for (int b = 0; b < ca.count; ++b) {
       ca.task_start[b] = acc;
@@ -159,8 +163,17 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
   double* wincol = lds + NWVC * ROWS;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int grp = lane >> 4, l16 = lane & 15;
+  // Tasks (block b, part g) are taken in order from a counter by whichever
+  // workgroup is free, so a level with more tasks than resident workgroups is
+  // balanced by how long each block takes rather than in fixed rounds.
+  __shared__ int s_task;
   const int T = ca.task_start[ca.count];
-  for (int task = blockIdx.x; task < T; task += gridDim.x) {
+  for (;;) {
+    if (threadIdx.x == 0) s_task = atomicAdd(ca.claim, 1);
+    __syncthreads();
+    const int task = s_task;
+    __syncthreads();   // s_task is rewritten at the next claim
+    if (task >= T) break;
     // Block of this task: largest b with task_start[b] <= task.
     int lo = 0, hi = ca.count - 1;
     while (lo < hi) {
@@ -603,8 +616,9 @@ ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratc
   fits = grid_cap >= gmax;
   if (!fits) return FFC_OK;
   const size_t slot_doubles = (size_t)batch * 2 * gmax * (bt.s_max + 2);
-  // The solve that follows reuses the scratch: size it for both up front.
-  const size_t bytes = std::max(slot_doubles * sizeof(double) + ((size_t)batch + 1) * sizeof(int32_t),
+  // Slots, task offsets, claim counter. The solve that follows reuses the
+  // scratch: size it for both up front.
+  const size_t bytes = std::max(slot_doubles * sizeof(double) + ((size_t)batch + 2) * sizeof(int32_t),
                                 solve_scratch_bytes(bt, batch));
   if (scratch.count < bytes) FFC_TRY(scratch.alloc(bytes));
   CoopArgs ca{};
@@ -624,6 +638,7 @@ ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratc
   ca.slots = reinterpret_cast<double*>(scratch.ptr);
   ca.slot_words = (int64_t)slot_doubles;
   ca.task_start = reinterpret_cast<int32_t*>(ca.slots + slot_doubles);
+  ca.claim = ca.task_start + batch + 1;
   ca.gmax = gmax;
   ca.s_max = bt.s_max;
   ca.cols_per_wg = cols_per_wg;
