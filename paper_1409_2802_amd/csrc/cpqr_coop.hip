@@ -25,8 +25,12 @@
 // every workgroup, far below the rounding of the factorization. Slots are
 // cleared before every launch; a slot read at step k can otherwise only hold
 // step k - 2, whose tag differs.
-// The pivot column is frozen in place (its rows 0..k-1 are R(0:k, k), row k
-// gets alpha), so no columns are swapped; the pivot order is recorded.
+// Row k of every active column is final after step k: its lane stores it to
+// A and clears the register, so the registers hold zeros above the current
+// step and norms need no row masks. The pivot column of step k is frozen in
+// place (its rows 0..k-1 are already stored, row k gets alpha), so no columns
+// are swapped; the pivot order is recorded. A ends with R(0:l+1, l) in
+// column piv[l] and R(0:r, j) in rows 0..r-1 of every other column j.
 //
 // Scheduling: the groups of a level form a flat task list (block 0's G_0
 // parts, then block 1's, ...); the workgroups of a persistent grid, all
@@ -40,6 +44,7 @@
 #include <climits>
 #include <cstdlib>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "ffc_internal.h"
@@ -78,6 +83,11 @@ struct Best {
 };
 
 __device__ inline bool better(double v, int o, double bv, int bo) { return v > bv || (v == bv && o < bo); }
+
+__device__ inline double readlane_d(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -204,13 +214,9 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       int bestc = -1;
 #pragma unroll
       for (int c = 0; c < CS; ++c) {
-        double nrm = 0.0;
+        double nrm = 0.0;   // rows above k are zero in the registers
 #pragma unroll
-        for (int m = 0; m < RL; ++m) {
-          const int i = l16 + 16 * m;
-          const double x = (i >= k) ? a[c][m] : 0.0;
-          nrm = fma(x, x, nrm);
-        }
+        for (int m = 0; m < RL; ++m) nrm = fma(a[c][m], a[c][m], nrm);
         nrm = row16_sum(nrm);
         const int j = col0 + c;
         if (j < n && !(done & (1u << c)) && better(nrm, j, best.v, best.orig)) {
@@ -219,24 +225,31 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
         }
       }
       // Best of the 4 lane groups of the wavefront (same result in every lane).
-      Best wbst{__shfl(best.v, 0, 64), __shfl(best.orig, 0, 64)};
+      Best wbst{readlane_d(best.v, 0), __builtin_amdgcn_readlane(best.orig, 0)};
       int wg_owner = 0;
 #pragma unroll
       for (int q = 1; q < 4; ++q) {
-        const Best o{__shfl(best.v, q * 16, 64), __shfl(best.orig, q * 16, 64)};
+        const Best o{readlane_d(best.v, 16 * q), __builtin_amdgcn_readlane(best.orig, 16 * q)};
         if (better(o.v, o.orig, wbst.v, wbst.orig)) { wbst = o; wg_owner = q; }
       }
-      // The wave's best column goes to its LDS candidate row (all ROWS rows,
-      // unconditionally: only rows k..s-1 are published).
+      // The wave's best column goes to its LDS candidate row (all ROWS rows;
+      // only rows k..s-1 are published).
+      // (The column is picked with selects, in the form that keeps a[][] in
+      // registers: an index into it would move the array to scratch memory.)
       if (wbst.orig != INT_MAX && grp == wg_owner) {
 #pragma unroll
-        for (int c = 0; c < CS; ++c)
-          if (c == bestc)
+        for (int m = 0; m < RL; ++m) {
+          double x = a[0][m];
+          if constexpr (CS == 4) {
+            const double lo = (bestc & 1) ? a[1][m] : a[0][m];
+            const double hi = (bestc & 1) ? a[3][m] : a[2][m];
+            x = (bestc & 2) ? hi : lo;
+          } else {
 #pragma unroll
-            for (int m = 0; m < RL; ++m) {
-              const int i = l16 + 16 * m;
-              if (i >= k && i < s) candcol[w * ROWS + i] = a[c][m];
-            }
+            for (int c = 1; c < CS; ++c) x = bestc == c ? a[c][m] : x;
+          }
+          candcol[w * ROWS + l16 + 16 * m] = x;
+        }
       }
       if (lane == 0) wb[w] = wbst;
       __syncthreads();
@@ -358,15 +371,14 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       // Every lane group holds all rows, so the reflector norm is a 16-lane sum.
       const double vv = row16_sum(part);
       const double beta = vv > 0.0 ? 2.0 / vv : 0.0;
-      // Freeze the pivot column: row k becomes alpha.
+      // Freeze the pivot column: its rows 0..k-1 already hold R in A (stored
+      // step by step below), row k gets alpha.
       if (g == gwin) {
 #pragma unroll
         for (int c = 0; c < CS; ++c)
           if (col0 + c == porig) {
             done |= 1u << c;
-#pragma unroll
-            for (int m = 0; m < RL; ++m)
-              if (l16 + 16 * m == k) a[c][m] = alpha;
+            if (l16 == (k & 15)) A[(int64_t)porig * ca.lda + k] = alpha;
           }
         if (threadIdx.x == 0) ca.piv[(int64_t)b * ca.piv_stride + k] = porig;
       }
@@ -382,20 +394,45 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
 #pragma unroll
         for (int m = 0; m < RL; ++m) a[c][m] = fma(-v[m], coef, a[c][m]);
       }
+      // Row k of the active columns is now final, R(k, j): its lane stores it
+      // where the solve reads R and clears it, so that the registers hold
+      // zeros above the next step (norms and staging need no row masks).
+      // (A switch on the register block k / 16: a binary tree of a few
+      // compares, where a chain of tests would take one per block.)
+      if (l16 == (k & 15)) {
+        auto save_row = [&](auto mc) {
+          constexpr int m = decltype(mc)::value;
+          if constexpr (m < RL) {
+#pragma unroll
+            for (int c = 0; c < CS; ++c) {
+              const int j = col0 + c;
+              if (j < n && !(done & (1u << c))) A[(int64_t)j * ca.lda + k] = a[c][m];
+              a[c][m] = 0.0;
+            }
+          }
+        };
+#define FFC_ROW_CASE(M) \
+  case M:               \
+    save_row(std::integral_constant<int, M>{}); \
+    break;
+        switch (k >> 4) {
+          FFC_ROW_CASE(0) FFC_ROW_CASE(1) FFC_ROW_CASE(2) FFC_ROW_CASE(3) FFC_ROW_CASE(4) FFC_ROW_CASE(5)
+          FFC_ROW_CASE(6) FFC_ROW_CASE(7) FFC_ROW_CASE(8) FFC_ROW_CASE(9) FFC_ROW_CASE(10) FFC_ROW_CASE(11)
+          FFC_ROW_CASE(12) FFC_ROW_CASE(13) FFC_ROW_CASE(14) FFC_ROW_CASE(15) FFC_ROW_CASE(16) FFC_ROW_CASE(17)
+          FFC_ROW_CASE(18) FFC_ROW_CASE(19) FFC_ROW_CASE(20) FFC_ROW_CASE(21) FFC_ROW_CASE(22) FFC_ROW_CASE(23)
+          FFC_ROW_CASE(24) FFC_ROW_CASE(25) FFC_ROW_CASE(26) FFC_ROW_CASE(27) FFC_ROW_CASE(28) FFC_ROW_CASE(29)
+          FFC_ROW_CASE(30) FFC_ROW_CASE(31)
+          default:
+            break;
+        }
+#undef FFC_ROW_CASE
+      }
       publish(k + 1);
       alive = poll(k + 1, gwin, porig);
       if (alive && porig != INT_MAX && k + 1 < kmax) alive = load_winner(k + 1, gwin);
       nv = s_nv;
     }
     if (!alive) return;   // timed out: the device flag reports it
-    // Write the columns back in place: rows 0..k-1 of every column hold R.
-#pragma unroll
-    for (int c = 0; c < CS; ++c)
-#pragma unroll
-      for (int m = 0; m < RL; ++m) {
-        const int i = l16 + 16 * m, j = col0 + c;
-        if (i < s && j < n) A[(int64_t)j * ca.lda + i] = a[c][m];
-      }
     if (g == 0 && threadIdx.x == 0) ca.rank[b] = k;
   }
 }
