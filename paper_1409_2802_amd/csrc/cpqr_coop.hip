@@ -153,6 +153,14 @@ __device__ inline double row16_sum(double x) {
   return x;
 }
 
+__device__ inline double row16_max(double x) {
+  x = fmax(x, dpp_mov<0xB1>(x));
+  x = fmax(x, dpp_mov<0x4E>(x));
+  x = fmax(x, dpp_mov<0x141>(x));
+  x = fmax(x, dpp_mov<0x140>(x));
+  return x;
+}
+
 // Register layout: a wavefront is 4 lane groups of 16 lanes; a lane group owns
 // CS columns and each of its lanes keeps RL rows (i = lane16 + 16 m) of them,
 // so a column's dot products and norms are 16-lane DPP reductions.
@@ -292,14 +300,21 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
             const double o = untag(ov);
             if (ok && o >= 0.0) c = Best{untag(nv), (int)rint(o)};
           }
-          int cq = q;
-#pragma unroll
-          for (int off = 32; off > 0; off >>= 1) {
-            const Best o{__shfl_xor(c.v, off, 64), __shfl_xor(c.orig, off, 64)};
-            const int oq = __shfl_xor(cq, off, 64);
-            if (better(o.v, o.orig, c.v, c.orig)) { c = o; cq = oq; }
+          // Best of these 64 slots: the largest norm (DPP maximum within rows
+          // of 16, then across the four rows), ties to the smallest column id
+          // among the lanes that hold it (found by ballot; usually one).
+          double vm = row16_max(c.v);
+          vm = fmax(fmax(readlane_d(vm, 0), readlane_d(vm, 16)), fmax(readlane_d(vm, 32), readlane_d(vm, 48)));
+          unsigned long long hit = __ballot(c.orig != INT_MAX && c.v == vm);
+          while (hit) {
+            const int L = __ffsll((long long)hit) - 1;
+            hit &= hit - 1;
+            const int o = __builtin_amdgcn_readlane(c.orig, L);
+            if (better(vm, o, bb.v, bb.orig)) {
+              bb = Best{vm, o};
+              bq = q0 + L;
+            }
           }
-          if (c.orig != INT_MAX && better(c.v, c.orig, bb.v, bb.orig)) { bb = c; bq = cq; }
         }
         const bool all_ok = __all(ok);
         if (!all_ok && lane == 0) atomicOr(ca.flag, 2u);
