@@ -267,8 +267,17 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
         if (better(wb[i].v, wb[i].orig, gb.v, gb.orig)) { gb = wb[i]; gw = i; }
       double* sl = slot_ptr(ca, b, k & 1, g);
       const long long tag = step_tag(k);
-      if (gb.orig != INT_MAX)
-        for (int i = k + (int)threadIdx.x; i < s; i += NTC) slot_store(sl + 2 + i, tagged(candcol[gw * ROWS + i], tag));
+      if (gb.orig != INT_MAX) {
+        constexpr int PER = (ROWS + NTC - 1) / NTC;   // rows per thread, all read before any store
+        double x[PER];
+#pragma unroll
+        for (int t = 0; t < PER; ++t) x[t] = candcol[gw * ROWS + min(k + (int)threadIdx.x + t * NTC, ROWS - 1)];
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+          const int i = k + (int)threadIdx.x + t * NTC;
+          if (i < s) slot_store(sl + 2 + i, tagged(x[t], tag));
+        }
+      }
       if (threadIdx.x == 0) {
         const bool any = gb.orig != INT_MAX;
         slot_store(sl + 1, tagged(any ? (double)gb.orig : -1.0, tag));
@@ -339,17 +348,27 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       const long long tag = step_tag(k);
       const double rho = sqrt(s_nv);
       if (k > 0 && threadIdx.x == 0) wincol[k - 1] = 0.0;
+      constexpr int PER = (ROWS + NTC - 1) / NTC;   // rows per thread, all loaded before any is used
       for (unsigned int spins = 0;; ++spins) {
         int stale = 0;
-        for (int i = k + (int)threadIdx.x; i < s; i += NTC) {
-          const double raw = slot_load(sl + 2 + i);
-          stale |= tag_of(raw) != tag;
-          const double x = untag(raw);
-          if (i == k) {
-            s_xk = x;
-            wincol[i] = x - (x != 0.0 ? -copysign(rho, x) : -rho);
-          } else {
-            wincol[i] = x;
+        double raw[PER];
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+          const int i = k + (int)threadIdx.x + t * NTC;
+          raw[t] = i < s ? slot_load(sl + 2 + i) : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+          const int i = k + (int)threadIdx.x + t * NTC;
+          if (i < s) {
+            stale |= tag_of(raw[t]) != tag;
+            const double x = untag(raw[t]);
+            if (i == k) {
+              s_xk = x;
+              wincol[i] = x - (x != 0.0 ? -copysign(rho, x) : -rho);
+            } else {
+              wincol[i] = x;
+            }
           }
         }
         if (!__syncthreads_or(stale)) return true;
