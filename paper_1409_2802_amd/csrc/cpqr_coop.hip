@@ -96,17 +96,39 @@ __device__ inline double wave_sum(double v) {
 
 // Group tasks per block: G_b = ceil(n_b / cols_per_wg) (at least 1); prefix
 // sums into task_start. One workgroup.
-__global__ void k_coop_tasks(CoopArgs ca) {
+__global__ void __launch_bounds__(256) k_coop_tasks(CoopArgs ca) {
+  __shared__ int wtot[4];
+  __shared__ int s_base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   if (threadIdx.x == 0) {
     *ca.claim = 0;
-    int acc = 0;
-    for (int b = 0; b < ca.count; ++b) {
-      ca.task_start[b] = acc;
-      const int n = ca.n_arr ? ca.n_arr[b] : ca.n_uniform;
-      acc += max(1, (n + ca.cols_per_wg - 1) / ca.cols_per_wg);
-    }
-    ca.task_start[ca.count] = acc;
+    s_base = 0;
   }
+  __syncthreads();
+  // Block-wide exclusive scan over chunks of 256 blocks: shuffle scan per
+  // wavefront, then the totals of the wavefronts before this one.
+  for (int b0 = 0; b0 < ca.count; b0 += 256) {
+    const int b = b0 + (int)threadIdx.x;
+    int g = 0;
+    if (b < ca.count) {
+      const int n = ca.n_arr ? ca.n_arr[b] : ca.n_uniform;
+      g = max(1, (n + ca.cols_per_wg - 1) / ca.cols_per_wg);
+    }
+    int incl = g;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off);
+      if (lane >= off) incl += y;
+    }
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    int pos = s_base + incl - g;
+    for (int v = 0; v < w; ++v) pos += wtot[v];
+    if (b < ca.count) ca.task_start[b] = pos;
+    __syncthreads();
+    if (threadIdx.x == 0) s_base += wtot[0] + wtot[1] + wtot[2] + wtot[3];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ca.task_start[ca.count] = s_base;
 }
 
 // Clears the slots (tag 0 is never a step's tag).

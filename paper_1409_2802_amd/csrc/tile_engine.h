@@ -58,8 +58,9 @@ __device__ inline void tile_accumulate(const double* __restrict__ Y, IdxMap rows
       sm.xs[kk][r] = xv;
     }
     __syncthreads();
+    const int kc = min(KC, d - k0);   // dimensions present in this chunk
 #pragma unroll 8
-    for (int kk = 0; kk < KC; ++kk) {
+    for (int kk = 0; kk < kc; ++kk) {
       T a[4], b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) a[i] = sm.ys[kk][tr + 16 * i];
