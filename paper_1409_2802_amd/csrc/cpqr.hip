@@ -17,6 +17,7 @@
 #include <climits>
 
 #include "ffc_internal.h"
+#include "lane_ops.h"
 
 namespace ffc {
 namespace {
@@ -259,10 +260,13 @@ __global__ void k_skeleton_ids(int first, int n_cap, int r_cap, const int32_t* _
 }
 
 // q~ = P q_alpha; q_alpha = the node's own charges (leaf) or the children's
-// equivalent charges, left then right (internal node). One wave per row of P.
-__global__ void k_upward(int first, int leaves, const int32_t* __restrict__ nb, int n_cap, int r_cap,
-                         const int32_t* __restrict__ rank, const int32_t* __restrict__ ncols,
-                         const double* __restrict__ P, const double* __restrict__ q_tree, double* __restrict__ qt) {
+// equivalent charges, left then right (internal node). Each wavefront forms
+// four rows of P q at once (lanes stride the columns), reduced in a fixed
+// order by DPP within rows of 16 lanes and then across the four rows.
+__global__ void __launch_bounds__(256) k_upward(int first, int leaves, const int32_t* __restrict__ nb, int n_cap,
+                                                int r_cap, const int32_t* __restrict__ rank,
+                                                const int32_t* __restrict__ ncols, const double* __restrict__ P,
+                                                const double* __restrict__ q_tree, double* __restrict__ qt) {
   const int node = first + blockIdx.x;
   const int r = rank[node], n = ncols[node];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -271,14 +275,20 @@ __global__ void k_upward(int first, int leaves, const int32_t* __restrict__ nb, 
   const int rl = leaves ? 0 : rank[l];
   const double* ql = leaves ? q_tree + nb[node] : qt + (int64_t)l * r_cap;
   const double* qr = leaves ? nullptr : qt + (int64_t)(l + 1) * r_cap;
-  for (int i = w; i < r; i += nw) {
-    double acc = 0.0;
+  for (int i0 = 4 * w; i0 < r; i0 += 4 * nw) {
+    const int nr = min(4, r - i0);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int j = lane; j < n; j += 64) {
       const double qj = (leaves || j < rl) ? ql[j] : qr[j - rl];
-      acc = fma(Pn[(int64_t)i * n_cap + j], qj, acc);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nr) acc[t] = fma(Pn[(int64_t)(i0 + t) * n_cap + j], qj, acc[t]);
     }
-    acc = wave_sum(acc);
-    if (lane == 0) qt[(int64_t)node * r_cap + i] = acc;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double v = wave_sum_dpp(acc[t]);
+      if (lane == 0 && t < nr) qt[(int64_t)node * r_cap + i0 + t] = v;
+    }
   }
 }
 

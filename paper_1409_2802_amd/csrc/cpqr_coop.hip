@@ -48,6 +48,7 @@
 #include <vector>
 
 #include "ffc_internal.h"
+#include "lane_ops.h"
 
 namespace ffc {
 namespace {
@@ -83,16 +84,6 @@ struct Best {
 };
 
 __device__ inline bool better(double v, int o, double bv, int bo) { return v > bv || (v == bv && o < bo); }
-
-__device__ inline double readlane_d(double x, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
-                          __builtin_amdgcn_readlane(__double2loint(x), l));
-}
-
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // Group tasks per block: G_b = ceil(n_b / cols_per_wg) (at least 1); prefix
 // sums into task_start. One workgroup.
@@ -157,31 +148,6 @@ __device__ inline double tagged(double v, long long tag) {
 }
 __device__ inline long long tag_of(double v) { return __double_as_longlong(v) & 3ll; }
 __device__ inline double untag(double v) { return __longlong_as_double(__double_as_longlong(v) & ~3ll); }
-
-// All-reduce of a double within each row of 16 lanes by DPP moves (quad
-// swaps, half-row mirror, row mirror). Every step adds two values in the same
-// order on both partners, so all 16 lanes end with bitwise-identical sums.
-template <int CTRL>
-__device__ inline double dpp_mov(double x) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ inline double row16_sum(double x) {
-  x += dpp_mov<0xB1>(x);    // quad_perm [1,0,3,2]
-  x += dpp_mov<0x4E>(x);    // quad_perm [2,3,0,1]
-  x += dpp_mov<0x141>(x);   // row_half_mirror
-  x += dpp_mov<0x140>(x);   // row_mirror
-  return x;
-}
-
-__device__ inline double row16_max(double x) {
-  x = fmax(x, dpp_mov<0xB1>(x));
-  x = fmax(x, dpp_mov<0x4E>(x));
-  x = fmax(x, dpp_mov<0x141>(x));
-  x = fmax(x, dpp_mov<0x140>(x));
-  return x;
-}
 
 // Register layout: a wavefront is 4 lane groups of 16 lanes; a lane group owns
 // CS columns and each of its lanes keeps RL rows (i = lane16 + 16 m) of them,
