@@ -260,9 +260,10 @@ __global__ void k_skeleton_ids(int first, int n_cap, int r_cap, const int32_t* _
 }
 
 // q~ = P q_alpha; q_alpha = the node's own charges (leaf) or the children's
-// equivalent charges, left then right (internal node). Each wavefront forms
-// four rows of P q at once (lanes stride the columns), reduced in a fixed
-// order by DPP within rows of 16 lanes and then across the four rows.
+// equivalent charges, left then right (internal node). Workgroup (node, y)
+// forms rows 16 y .. 16 y + 15; each of its wavefronts four of them at once
+// (lanes stride the columns), reduced in a fixed order by DPP within rows of
+// 16 lanes and then across the four rows.
 __global__ void __launch_bounds__(256) k_upward(int first, int leaves, const int32_t* __restrict__ nb, int n_cap,
                                                 int r_cap, const int32_t* __restrict__ rank,
                                                 const int32_t* __restrict__ ncols, const double* __restrict__ P,
@@ -275,7 +276,7 @@ __global__ void __launch_bounds__(256) k_upward(int first, int leaves, const int
   const int rl = leaves ? 0 : rank[l];
   const double* ql = leaves ? q_tree + nb[node] : qt + (int64_t)l * r_cap;
   const double* qr = leaves ? nullptr : qt + (int64_t)(l + 1) * r_cap;
-  for (int i0 = 4 * w; i0 < r; i0 += 4 * nw) {
+  for (int i0 = 16 * (int)blockIdx.y + 4 * w; i0 < min(r, 16 * (int)blockIdx.y + 16); i0 += 4 * nw) {
     const int nr = min(4, r - i0);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int j = lane; j < n; j += 64) {
@@ -330,7 +331,8 @@ ffc_status launch_skeleton_ids(ffc_skel* sk, int first, int count, hipStream_t s
 }
 
 ffc_status launch_upward(const ffc_tree* t, ffc_skel* sk, int first, int count, bool leaves, hipStream_t st) {
-  hipLaunchKernelGGL(k_upward, dim3(count), dim3(256), 0, st, first, leaves ? 1 : 0, t->begin.ptr, sk->n_cap,
+  hipLaunchKernelGGL(k_upward, dim3(count, (sk->r_cap + 15) / 16), dim3(256), 0, st, first, leaves ? 1 : 0,
+                     t->begin.ptr, sk->n_cap,
                      sk->r_cap, sk->rank.ptr, sk->ncols.ptr, sk->P.ptr, t->q_tree.ptr, sk->qt.ptr);
   FFC_LAUNCH_CHECK("k_upward");
   return FFC_OK;

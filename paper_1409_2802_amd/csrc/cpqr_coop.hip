@@ -86,8 +86,8 @@ struct Best {
 __device__ inline bool better(double v, int o, double bv, int bo) { return v > bv || (v == bv && o < bo); }
 
 // Group tasks per block: G_b = ceil(n_b / cols_per_wg) (at least 1); prefix
-// sums into task_start. One workgroup.
-__global__ void __launch_bounds__(256) k_coop_tasks(CoopArgs ca) {
+// sums into task_start. Run by one 256-thread workgroup.
+__device__ void coop_tasks(const CoopArgs& ca) {
   __shared__ int wtot[4];
   __shared__ int s_base;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -122,10 +122,14 @@ __global__ void __launch_bounds__(256) k_coop_tasks(CoopArgs ca) {
   if (threadIdx.x == 0) ca.task_start[ca.count] = s_base;
 }
 
-// Clears the slots (tag 0 is never a step's tag).
-__global__ void k_coop_clear(double* slots, int64_t words) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < words; e += (int64_t)gridDim.x * blockDim.x)
-    slots[e] = 0.0;
+// Set-up of a factorization launch: workgroup 0 computes the task offsets
+// and resets the claim counter; all workgroups clear the slots (tag 0 is
+// never a step's tag).
+__global__ void __launch_bounds__(256) k_coop_setup(CoopArgs ca) {
+  if (blockIdx.x == 0) coop_tasks(ca);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ca.slot_words;
+       e += (int64_t)gridDim.x * blockDim.x)
+    ca.slots[e] = 0.0;
 }
 
 __device__ inline double* slot_ptr(const CoopArgs& ca, int b, int buf, int g) {
@@ -704,11 +708,9 @@ ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratc
   ca.flag = device_flag();
   {
     StageTimer tm(FFC_STAGE_SOLVE, st);
-    hipLaunchKernelGGL(k_coop_tasks, dim3(1), dim3(256), 0, st, ca);
-    FFC_LAUNCH_CHECK("k_coop_tasks");
     const int cgrid = (int)std::min<int64_t>(1024, (ca.slot_words + 255) / 256);
-    hipLaunchKernelGGL(k_coop_clear, dim3(std::max(1, cgrid)), dim3(256), 0, st, ca.slots, ca.slot_words);
-    FFC_LAUNCH_CHECK("k_coop_clear");
+    hipLaunchKernelGGL(k_coop_setup, dim3(std::max(1, cgrid)), dim3(256), 0, st, ca);
+    FFC_LAUNCH_CHECK("k_coop_setup");
   }
   const int grid = std::min(grid_cap, batch * gmax);
   void* args[] = {&ca};
