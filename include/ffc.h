@@ -86,7 +86,16 @@ typedef struct ffc_proposal ffc_proposal;
  *               check synchronizes the stream once per level)
  *  pool_factor  learned sampler only: the candidate pool of a node is
  *               min(M, pool_factor * samples) uniform far points (0 means 8;
- *               the pool is limited to 8192) */
+ *               the pool is limited to 8192)
+ *  adaptive_tol uniform sampler only; > 0 turns on the adaptive sample count
+ *               (the integration question of Section 5): after a level is
+ *               skeletonized, every node whose error estimate on 32 held-out
+ *               uniform far rows, |K_h - K_h(:, J) P|_F / |K_h|_F, exceeds
+ *               adaptive_tol and whose row count can still grow is redone with
+ *               twice the rows (a fresh uniform draw), until all pass or reach
+ *               the cap; each round synchronizes the stream once. <= 0: off.
+ *  max_samples  cap of the adaptive sample count (0 means 4 * the initial
+ *               count); rows never exceed the points outside the node */
 typedef struct {
   double tol;
   int32_t max_rank;
@@ -97,6 +106,8 @@ typedef struct {
   const ffc_proposal* proposal;
   double fallback_tol;
   int32_t pool_factor;
+  double adaptive_tol;
+  int32_t max_samples;
 } ffc_skel_opts;
 
 /* Build a binary ball tree over X (Section 2: hierarchical groupings of the
@@ -193,7 +204,9 @@ typedef struct {
   double rank_mean;
   int32_t rank_cap_hits;    /* nodes whose rank equals max_rank */
   int32_t fallbacks;        /* learned sampler: nodes redone with uniform rows */
-  double kernel_evals;      /* sum over nodes of s * n_cols */
+  double kernel_evals;      /* sum over nodes of s * n_cols (final row counts) */
+  int32_t resampled;        /* adaptive sample count: node redos with doubled rows */
+  int32_t rows_max;         /* largest final row count of a node */
 } ffc_stats;
 
 /* Rank statistics of a skeleton set (synchronizes). */

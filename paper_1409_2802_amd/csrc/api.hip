@@ -237,16 +237,25 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
   if (learned && !o->proposal) return fail(FFC_ERR_INVALID_ARG, "the learned sampler needs a proposal");
   if (learned && !std::isfinite(o->fallback_tol)) return fail(FFC_ERR_INVALID_ARG, "fallback_tol must be finite");
   if (learned && o->pool_factor < 0) return fail(FFC_ERR_INVALID_ARG, "pool_factor must be >= 0");
+  if (!std::isfinite(o->adaptive_tol)) return fail(FFC_ERR_INVALID_ARG, "adaptive_tol must be finite");
+  const bool adaptive = o->adaptive_tol > 0.0;
+  if (adaptive && learned)
+    return fail(FFC_ERR_INVALID_ARG, "the adaptive sample count works with the uniform sampler only");
+  if (o->max_samples < 0) return fail(FFC_ERR_INVALID_ARG, "max_samples must be >= 0");
   hipStream_t st = (hipStream_t)stream;
 
   const int64_t s_req = o->num_samples > 0 ? o->num_samples : 2 * (int64_t)o->max_rank;
+  // Adaptive sample count: rows start at s_req and double up to s_lim.
+  const int64_t s_lim = adaptive ? (o->max_samples > 0 ? o->max_samples : 4 * s_req) : s_req;
+  if (s_lim < s_req) return fail(FFC_ERR_INVALID_ARG, "max_samples must be >= the initial sample count");
   int max_leaf = 0;
   for (int a = (1 << t->depth) - 1; a < t->num_nodes; ++a) max_leaf = std::max(max_leaf, t->end_h[a] - t->begin_h[a]);
   int max_nonroot = 0;
   for (int a = 1; a < t->num_nodes; ++a) max_nonroot = std::max(max_nonroot, t->end_h[a] - t->begin_h[a]);
   const int64_t M_max = t->N - 0;   // largest complement (an empty node)
-  const int s_cap = (int)std::min<int64_t>(s_req, M_max);
-  if (s_cap > 8192) return fail(FFC_ERR_INVALID_ARG, "num_samples above 8192 is not supported");
+  if (s_lim > 8192) return fail(FFC_ERR_INVALID_ARG, "num_samples (or max_samples) above 8192 is not supported");
+  const int s_cap = (int)std::min<int64_t>(s_lim, M_max);
+  const int s0 = (int)std::min<int64_t>(s_req, M_max);   // rows drawn first
   const int r_cap = std::max(1, std::min(o->max_rank, s_cap));
   const int n_cap = std::max(max_leaf, 2 * r_cap);
   if ((size_t)n_cap * 12 + (size_t)s_cap * 8 > 140 * 1024)
@@ -289,6 +298,7 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
   sk->kernel = *k;
   sk->opts = *o;
   sk->fallbacks = 0;
+  sk->resampled = 0;
   const KParams kp = make_kparams(*k, t->d);
   const int max_rank = std::min(o->max_rank, r_cap);
   // Sampled blocks, interpolative decompositions and skeleton ids of one level
@@ -330,6 +340,7 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
   };
   auto run = [&]() -> ffc_status {
     if (learned) FFC_TRY(learned_alloc(t, sk, o->pool_factor > 0 ? o->pool_factor : 8));
+    if (adaptive) FFC_TRY(heldout_alloc(t, sk));
     for (int lev = t->depth; lev >= 1; --lev) {
       const int first = (1 << lev) - 1, count = 1 << lev;
       {
@@ -341,9 +352,31 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
         FFC_TRY(learned_rows_level(t, sk, o->proposal, first, count, s_cap, o->seed, st));
       } else {
         StageTimer tm(FFC_STAGE_SAMPLE, st);
-        FFC_TRY(launch_sample_rows(t, sk, first, count, s_cap, o->seed, st));
+        FFC_TRY(launch_sample_rows(t, sk, first, count, s0, o->seed, st));
       }
       FFC_TRY(skeletonize_level(first, count));
+      if (adaptive) {
+        // Double the rows of the nodes whose held-out estimate is too large
+        // until all pass or reach the cap. The nodes redone in a round all
+        // had the previous round's count (the others passed, and recompute
+        // identically), so one count per round serves them all.
+        {
+          StageTimer tm(FFC_STAGE_HELDOUT, st);
+          FFC_TRY(heldout_prepare_level(t, sk, kp, o->precision, first, count, o->seed, st));
+        }
+        for (int s_round = s0;;) {
+          const int s_next = (int)std::min<int64_t>(2 * (int64_t)s_round, s_cap);
+          int redo = 0;
+          {
+            StageTimer tm(FFC_STAGE_HELDOUT, st);
+            FFC_TRY(adaptive_round_level(t, sk, first, count, o->seed, o->adaptive_tol, s_cap, s_next, redo, st));
+          }
+          if (!redo) break;
+          sk->resampled += redo;
+          s_round = s_next;
+          FFC_TRY(skeletonize_level(first, count));
+        }
+      }
       if (learned && o->fallback_tol > 0.0) {
         int redo = 0;
         {
@@ -501,6 +534,8 @@ ffc_status ffc_skel_stats(const ffc_skel* sk, ffc_stats* out) {
   out->rank_mean = out->num_nodes ? sum / out->num_nodes : 0.0;
   out->fallbacks = sk->fallbacks;
   out->kernel_evals = evals;
+  out->resampled = sk->resampled;
+  for (int a = 1; a < sk->num_nodes; ++a) out->rows_max = std::max(out->rows_max, nr[a]);
   return FFC_OK;
 }
 
@@ -556,6 +591,10 @@ ffc_status ffc_step_graph_create(const ffc_tree* t, ffc_skel* sk, const ffc_kern
   }
   if (o->sampler == FFC_SAMPLE_LEARNED && o->fallback_tol > 0.0) {
     set_error("the learned sampler's fallback check synchronizes and cannot be captured");
+    return FFC_ERR_INVALID_ARG;
+  }
+  if (o->adaptive_tol > 0.0) {
+    set_error("the adaptive sample count synchronizes after every round and cannot be captured");
     return FFC_ERR_INVALID_ARG;
   }
   hipStream_t st = (hipStream_t)stream;

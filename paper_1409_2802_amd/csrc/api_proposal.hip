@@ -249,7 +249,8 @@ ffc_status learned_heldout_level(const ffc_tree* t, ffc_skel* sk, const KParams&
   FFC_TRY(launch_kblock_batch(t, kp, precision, L.hrows.ptr, L.nheld.ptr, kHeld, sk->cols.ptr, sk->ncols.ptr,
                               sk->n_cap, first, count, t->centroid.ptr, L.Kh.ptr, st));
   FFC_HIP_TRY(hipMemsetAsync(L.counter.ptr, 0, sizeof(unsigned int), st));
-  FFC_TRY(launch_heldout_check(L.Kh.ptr, L.nheld.ptr, kHeld, sk, first, count, tol, L.mask.ptr, L.counter.ptr, st));
+  FFC_TRY(launch_heldout_check(L.Kh.ptr, L.nheld.ptr, kHeld, sk, first, count, tol, L.mask.ptr, L.counter.ptr,
+                               HeldoutGrow{}, st));
   unsigned int h = 0;
   FFC_HIP_TRY(hipMemcpyAsync(&h, L.counter.ptr, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
   FFC_HIP_TRY(hipStreamSynchronize(st));
@@ -257,6 +258,50 @@ ffc_status learned_heldout_level(const ffc_tree* t, ffc_skel* sk, const KParams&
   if (h)
     FFC_TRY(launch_sample_rows_into(t, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, first, count, s, seed, 0u, L.mask.ptr,
                                     st));
+  return FFC_OK;
+}
+
+ffc_status heldout_alloc(const ffc_tree* t, ffc_skel* sk) {
+  LearnedScratch& L = sk->learned;
+  if (L.hrows.ptr) return FFC_OK;
+  const size_t nn = t->num_nodes, widest = (size_t)1 << t->depth;
+  FFC_TRY(L.hrows.alloc(nn * kHeld));
+  FFC_TRY(L.nheld.alloc(nn));
+  FFC_TRY(L.Kh.alloc(widest * kHeld * sk->n_cap));
+  FFC_TRY(L.mask.alloc(nn));
+  FFC_TRY(L.counter.alloc(1));
+  return FFC_OK;
+}
+
+ffc_status heldout_prepare_level(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int precision, int first,
+                                 int count, uint64_t seed, hipStream_t st) {
+  LearnedScratch& L = sk->learned;
+  FFC_TRY(launch_sample_rows_into(t, L.hrows.ptr, L.nheld.ptr, kHeld, first, count, kHeld, seed, kStreamHeldout,
+                                  nullptr, st));
+  return launch_kblock_batch(t, kp, precision, L.hrows.ptr, L.nheld.ptr, kHeld, sk->cols.ptr, sk->ncols.ptr,
+                             sk->n_cap, first, count, t->centroid.ptr, L.Kh.ptr, st);
+}
+
+ffc_status adaptive_round_level(const ffc_tree* t, ffc_skel* sk, int first, int count, uint64_t seed, double tol,
+                                int s_limit, int s_next, int& redo, hipStream_t st) {
+  LearnedScratch& L = sk->learned;
+  redo = 0;
+  FFC_HIP_TRY(hipMemsetAsync(L.counter.ptr, 0, sizeof(unsigned int), st));
+  HeldoutGrow grow;
+  grow.nrows = sk->nrows.ptr;
+  grow.nb = t->begin.ptr;
+  grow.ne = t->end.ptr;
+  grow.N = t->N;
+  grow.s_limit = s_limit;
+  FFC_TRY(launch_heldout_check(L.Kh.ptr, L.nheld.ptr, kHeld, sk, first, count, tol, L.mask.ptr, L.counter.ptr, grow,
+                               st));
+  unsigned int h = 0;
+  FFC_HIP_TRY(hipMemcpyAsync(&h, L.counter.ptr, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
+  FFC_HIP_TRY(hipStreamSynchronize(st));
+  redo = (int)h;
+  if (h)
+    FFC_TRY(launch_sample_rows_into(t, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, first, count, s_next, seed, 0u,
+                                    L.mask.ptr, st));
   return FFC_OK;
 }
 

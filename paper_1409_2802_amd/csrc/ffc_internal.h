@@ -189,6 +189,7 @@ struct ffc_skel {
   ffc::DevBuf<unsigned char> qr_scratch;    // group slots / counters of the QR kernel
   ffc::LearnedScratch learned;              // learned sampler (allocated on first use)
   int32_t fallbacks = 0;
+  int32_t resampled = 0;                    // adaptive sample count: node redos
   hipStream_t last_stream = nullptr;
 };
 
@@ -290,6 +291,16 @@ ffc_status learned_rows_level(const ffc_tree* t, ffc_skel* sk, const ffc_proposa
 ffc_status learned_heldout_level(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int precision, int first,
                                  int count, int s, uint64_t seed, double tol, int& redo, hipStream_t st);
 ffc_status learned_alloc(const ffc_tree* t, ffc_skel* sk, int pool_factor);
+// Adaptive sample count (held-out rows and blocks in sk->learned).
+ffc_status heldout_alloc(const ffc_tree* t, ffc_skel* sk);
+// Held-out rows and their kernel block for the nodes of a level (once per level).
+ffc_status heldout_prepare_level(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int precision, int first,
+                                 int count, uint64_t seed, hipStream_t st);
+// One round: nodes whose held-out error exceeds tol and whose rows can grow
+// (below s_limit) get s_next fresh uniform rows; their number goes to `redo`.
+// Synchronizes.
+ffc_status adaptive_round_level(const ffc_tree* t, ffc_skel* sk, int first, int count, uint64_t seed, double tol,
+                                int s_limit, int s_next, int& redo, hipStream_t st);
 
 // Learned proposal (proposal.hip).
 ffc_status launch_geometry(const double* Xt, int d, const GeomArgs& ga, int count, hipStream_t st);
@@ -309,8 +320,20 @@ ffc_status launch_feature_stats(const float* feat, int64_t count, float* mu, flo
 ffc_status launch_select_rows(const float* score, int64_t score_stride, const int32_t* pool, int pool_stride,
                               const int32_t* npool, int first, int count, int s, uint64_t seed, const int32_t* ncols,
                               const unsigned char* mask, int32_t* rows, int s_cap, int32_t* nrows, hipStream_t st);
+// Held-out check of the nodes [first, first+count): err = |K_h - K_h(:, J) P|_F
+// / |K_h|_F; mask[node] = err > tol, and with grow.nrows set also only when
+// the node's row count can still grow (below grow.s_limit and the points
+// outside the node); the number of masked nodes is added to *fallbacks.
+struct HeldoutGrow {
+  const int32_t* nrows = nullptr;
+  const int32_t* nb = nullptr;
+  const int32_t* ne = nullptr;
+  int64_t N = 0;
+  int s_limit = 0;
+};
 ffc_status launch_heldout_check(const double* Kh, const int32_t* nh, int h_cap, const ffc_skel* sk, int first,
-                                int count, double tol, unsigned char* mask, unsigned int* fallbacks, hipStream_t st);
+                                int count, double tol, unsigned char* mask, unsigned int* fallbacks,
+                                const HeldoutGrow& grow, hipStream_t st);
 
 // Ridge leverage labels (leverage.hip) of row-major m x n blocks B_b: G_b =
 // B_b^T B_b, its Cholesky factor with eps^2 tr(G_b) added to the diagonal,

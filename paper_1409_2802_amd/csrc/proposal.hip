@@ -561,7 +561,7 @@ __global__ void __launch_bounds__(256) k_heldout_check(const double* __restrict_
                                                        const int32_t* __restrict__ ncols,
                                                        const int32_t* __restrict__ piv, const double* __restrict__ P,
                                                        double tol, unsigned char* __restrict__ mask,
-                                                       unsigned int* __restrict__ fallbacks) {
+                                                       unsigned int* __restrict__ fallbacks, HeldoutGrow grow) {
   __shared__ double r1[256], r2[256];
   const int b = blockIdx.x, node = first + b, tid = threadIdx.x;
   const int n = ncols[node], r = rank[node], nh = nh_arr[node];
@@ -587,7 +587,12 @@ __global__ void __launch_bounds__(256) k_heldout_check(const double* __restrict_
   }
   if (tid == 0) {
     const double err = r2[0] > 0.0 ? sqrt(r1[0] / r2[0]) : 0.0;
-    const bool fall = err > tol;
+    bool fall = err > tol;
+    if (fall && grow.nrows) {   // adaptive sample count: only nodes whose rows can still grow
+      const int nr = grow.nrows[node];
+      const int64_t M = grow.N - (grow.ne[node] - grow.nb[node]);
+      fall = nr < grow.s_limit && nr < M;
+    }
     mask[node] = fall ? 1 : 0;
     if (fall) atomicAdd(fallbacks, 1u);
   }
@@ -684,10 +689,11 @@ ffc_status launch_select_rows(const float* score, int64_t score_stride, const in
 }
 
 ffc_status launch_heldout_check(const double* Kh, const int32_t* nh, int h_cap, const ffc_skel* sk, int first,
-                                int count, double tol, unsigned char* mask, unsigned int* fallbacks, hipStream_t st) {
+                                int count, double tol, unsigned char* mask, unsigned int* fallbacks,
+                                const HeldoutGrow& grow, hipStream_t st) {
   if (count <= 0) return FFC_OK;
   hipLaunchKernelGGL(k_heldout_check, dim3(count), dim3(256), 0, st, Kh, nh, h_cap, sk->n_cap, sk->r_cap, first,
-                     sk->rank.ptr, sk->ncols.ptr, sk->piv.ptr, sk->P.ptr, tol, mask, fallbacks);
+                     sk->rank.ptr, sk->ncols.ptr, sk->piv.ptr, sk->P.ptr, tol, mask, fallbacks, grow);
   FFC_LAUNCH_CHECK("k_heldout_check");
   return FFC_OK;
 }

@@ -54,13 +54,14 @@ class KernelC(ctypes.Structure):
 class SkelOptsC(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_rank", ctypes.c_int32), ("num_samples", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("sampler", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("proposal", ctypes.c_void_p), ("fallback_tol", ctypes.c_double), ("pool_factor", ctypes.c_int32)]
+                ("proposal", ctypes.c_void_p), ("fallback_tol", ctypes.c_double), ("pool_factor", ctypes.c_int32),
+                ("adaptive_tol", ctypes.c_double), ("max_samples", ctypes.c_int32)]
 
 
 class StatsC(ctypes.Structure):
     _fields_ = [("num_nodes", ctypes.c_int32), ("rank_min", ctypes.c_int32), ("rank_max", ctypes.c_int32),
                 ("rank_mean", ctypes.c_double), ("rank_cap_hits", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
-                ("kernel_evals", ctypes.c_double)]
+                ("kernel_evals", ctypes.c_double), ("resampled", ctypes.c_int32), ("rows_max", ctypes.c_int32)]
 
 
 class TrainOptsC(ctypes.Structure):
@@ -256,12 +257,14 @@ class Skeletons:
 def skeletonize(tree: Tree, kernel: Kernel, tol: float, max_rank: int, num_samples: int = 0,
                 precision: int = FP64, seed: int = 0, reuse: Skeletons | None = None,
                 proposal: "Proposal | None" = None, fallback_tol: float = 0.0, pool_factor: int = 0,
-                stream=None) -> Skeletons:
-    """Skeletonize every non-root node; with `proposal` the rows come from the learned sampler."""
+                adaptive_tol: float = 0.0, max_samples: int = 0, stream=None) -> Skeletons:
+    """Skeletonize every non-root node; with `proposal` the rows come from the learned sampler, with
+    `adaptive_tol` > 0 a node's row count doubles until its held-out error estimate is at most adaptive_tol
+    (or `max_samples` is reached)."""
     opts = SkelOptsC(tol=tol, max_rank=max_rank, num_samples=num_samples, precision=precision,
                      sampler=SAMPLE_LEARNED if proposal is not None else SAMPLE_UNIFORM, seed=seed,
                      proposal=proposal.handle if proposal is not None else None, fallback_tol=fallback_tol,
-                     pool_factor=pool_factor)
+                     pool_factor=pool_factor, adaptive_tol=adaptive_tol, max_samples=max_samples)
     h = ctypes.c_void_p(reuse.handle.value if reuse is not None else None)
     k = kernel.c_struct()
     _check(load_library().ffc_skeletonize_nodes(tree.handle, ctypes.byref(k), ctypes.byref(opts), _stream(stream),
