@@ -303,10 +303,11 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
   const int max_rank = std::min(o->max_rank, r_cap);
   // Sampled blocks, interpolative decompositions and skeleton ids of one level
   // (rows and columns already in place).
-  auto skeletonize_level = [&](int first, int count) -> ffc_status {
+  // With a mask (indexed by node) only the nodes whose entry is set are redone.
+  auto skeletonize_level = [&](int first, int count, const unsigned char* mask = nullptr) -> ffc_status {
     {
       StageTimer tm(FFC_STAGE_KBLOCK, st);
-      FFC_TRY(launch_level_kblock(t, sk, kp, o->precision, first, count, sk->work.ptr, st));
+      FFC_TRY(launch_level_kblock(t, sk, kp, o->precision, first, count, sk->work.ptr, st, mask));
     }
     IdBatch bt{};
     bt.A = sk->work.ptr;
@@ -324,6 +325,7 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
     bt.P = sk->P.ptr + (int64_t)first * r_cap * n_cap;
     bt.p_stride = (int64_t)r_cap * n_cap;
     bt.p_ld = n_cap;
+    bt.mask = mask ? mask + first : nullptr;
     {
       bool used = false;
       FFC_TRY(launch_interp_decomp_coop(bt, count, sk->qr_scratch, st, used));
@@ -334,7 +336,7 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
     }
     {
       StageTimer tm(FFC_STAGE_SKEL, st);
-      FFC_TRY(launch_skeleton_ids(sk, first, count, st));
+      FFC_TRY(launch_skeleton_ids(sk, first, count, st, mask));
     }
     return FFC_OK;
   };
@@ -357,9 +359,9 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
       FFC_TRY(skeletonize_level(first, count));
       if (adaptive) {
         // Double the rows of the nodes whose held-out estimate is too large
-        // until all pass or reach the cap. The nodes redone in a round all
-        // had the previous round's count (the others passed, and recompute
-        // identically), so one count per round serves them all.
+        // until all pass or reach the cap; a round redoes only those nodes
+        // (mask). They all had the previous round's count (the others passed
+        // earlier and keep their skeletons), so one count per round serves.
         {
           StageTimer tm(FFC_STAGE_HELDOUT, st);
           FFC_TRY(heldout_prepare_level(t, sk, kp, o->precision, first, count, o->seed, st));
@@ -374,7 +376,7 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
           if (!redo) break;
           sk->resampled += redo;
           s_round = s_next;
-          FFC_TRY(skeletonize_level(first, count));
+          FFC_TRY(skeletonize_level(first, count, sk->learned.mask.ptr));
         }
       }
       if (learned && o->fallback_tol > 0.0) {
@@ -384,9 +386,9 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
           FFC_TRY(learned_heldout_level(t, sk, kp, o->precision, first, count, s_cap, o->seed, o->fallback_tol, redo,
                                         st));
         }
-        if (redo) {   // failed nodes now hold uniform rows; the others recompute identically
+        if (redo) {   // failed nodes now hold uniform rows and are redone alone (mask)
           sk->fallbacks += redo;
-          FFC_TRY(skeletonize_level(first, count));
+          FFC_TRY(skeletonize_level(first, count, sk->learned.mask.ptr));
         }
       }
     }

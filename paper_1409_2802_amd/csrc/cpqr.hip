@@ -138,6 +138,7 @@ template <int MAXR>
 __global__ void __launch_bounds__(NT) k_cpqr_id(IdBatch bt) {
   extern __shared__ double smem[];
   const int b = blockIdx.x;
+  if (bt.mask && !bt.mask[b]) return;
   const int s = bt.s_arr ? bt.s_arr[b] : bt.s_uniform;
   const int n = bt.n_arr ? bt.n_arr[b] : bt.n_uniform;
   double* A = bt.A + (int64_t)b * bt.a_stride;
@@ -252,8 +253,9 @@ __global__ void __launch_bounds__(NT) k_cpqr_id(IdBatch bt) {
 
 __global__ void k_skeleton_ids(int first, int n_cap, int r_cap, const int32_t* __restrict__ rank,
                                const int32_t* __restrict__ piv, const int32_t* __restrict__ cols,
-                               int32_t* __restrict__ skel) {
+                               int32_t* __restrict__ skel, const unsigned char* __restrict__ mask) {
   const int node = first + blockIdx.x;
+  if (mask && !mask[node]) return;
   const int r = rank[node];
   for (int i = threadIdx.x; i < r; i += blockDim.x)
     skel[(int64_t)node * r_cap + i] = cols[(int64_t)node * n_cap + piv[(int64_t)node * n_cap + i]];
@@ -323,9 +325,9 @@ ffc_status launch_interp_decomp(const IdBatch& bt, int batch, hipStream_t st) {
   return FFC_OK;
 }
 
-ffc_status launch_skeleton_ids(ffc_skel* sk, int first, int count, hipStream_t st) {
+ffc_status launch_skeleton_ids(ffc_skel* sk, int first, int count, hipStream_t st, const unsigned char* mask) {
   hipLaunchKernelGGL(k_skeleton_ids, dim3(count), dim3(256), 0, st, first, sk->n_cap, sk->r_cap, sk->rank.ptr,
-                     sk->piv.ptr, sk->cols.ptr, sk->skel.ptr);
+                     sk->piv.ptr, sk->cols.ptr, sk->skel.ptr, mask);
   FFC_LAUNCH_CHECK("k_skeleton_ids");
   return FFC_OK;
 }

@@ -69,6 +69,7 @@ struct CoopArgs {
   int32_t* piv;
   int64_t piv_stride;
   int32_t* task_start;       // [count + 1]
+  const unsigned char* mask; // [count]: blocks to factor (all when null); the others get no tasks
   int32_t* claim;            // next unclaimed task
   double* slots;             // [count][2][gmax][s_max + 2]: norm, column id, rows (tagged words)
   int64_t slot_words;
@@ -101,7 +102,7 @@ __device__ void coop_tasks(const CoopArgs& ca) {
   for (int b0 = 0; b0 < ca.count; b0 += 256) {
     const int b = b0 + (int)threadIdx.x;
     int g = 0;
-    if (b < ca.count) {
+    if (b < ca.count && !(ca.mask && !ca.mask[b])) {
       const int n = ca.n_arr ? ca.n_arr[b] : ca.n_uniform;
       g = max(1, (n + ca.cols_per_wg - 1) / ca.cols_per_wg);
     }
@@ -502,9 +503,11 @@ size_t solve_scratch_bytes(const IdBatch& bt, int batch) {
 // lane c < 16 back-substituting U x = e_c. Dinv[b][kd] is row-major 16 x 16.
 __global__ void __launch_bounds__(64)
 k_diag_inv(const double* __restrict__ A, int64_t a_stride, int lda, const int32_t* __restrict__ rank,
-           const int32_t* __restrict__ piv, int64_t piv_stride, double* __restrict__ Dinv, int nblk) {
+           const int32_t* __restrict__ piv, int64_t piv_stride, double* __restrict__ Dinv, int nblk,
+           const unsigned char* __restrict__ mask) {
   __shared__ double U[MB][MB + 1];
   const int b = blockIdx.x, kd = blockIdx.y, kb = MB * kd;
+  if (mask && !mask[b]) return;
   const int r = rank[b];
   if (kb >= r) return;
   const int nii = min(MB, r - kb);
@@ -537,9 +540,10 @@ __global__ void __launch_bounds__(64)
 k_id_solve_mfma(const double* __restrict__ A, int64_t a_stride, int lda, const int32_t* __restrict__ n_arr,
                 int n_uniform, int n_max, const int32_t* __restrict__ rank, int32_t* __restrict__ piv,
                 int64_t piv_stride, const double* __restrict__ Dinv, int nblk, double* __restrict__ P,
-                int64_t p_stride, int p_ld, int r_max) {
+                int64_t p_stride, int p_ld, int r_max, const unsigned char* __restrict__ mask) {
   extern __shared__ double smm[];
   const int b = blockIdx.x, j0 = MB * (int)blockIdx.y;
+  if (mask && !mask[b]) return;
   const int n = n_arr ? n_arr[b] : n_uniform;
   if (j0 >= n) return;
   const int r = rank[b], r16 = round_mb_dev(r);
@@ -701,6 +705,7 @@ ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratc
   ca.slots = reinterpret_cast<double*>(scratch.ptr);
   ca.slot_words = (int64_t)slot_doubles;
   ca.task_start = reinterpret_cast<int32_t*>(ca.slots + slot_doubles);
+  ca.mask = bt.mask;
   ca.claim = ca.task_start + batch + 1;
   ca.gmax = gmax;
   ca.s_max = bt.s_max;
@@ -739,11 +744,11 @@ ffc_status launch_solve(const IdBatch& bt, int batch, DevBuf<unsigned char>& scr
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   StageTimer tm(FFC_STAGE_SOLVE, st);
   hipLaunchKernelGGL(k_diag_inv, dim3(batch, nblk), dim3(64), 0, st, bt.A, bt.a_stride, bt.lda, bt.rank, bt.piv,
-                     bt.piv_stride, Dinv, nblk);
+                     bt.piv_stride, Dinv, nblk, bt.mask);
   FFC_LAUNCH_CHECK("k_diag_inv");
   hipLaunchKernelGGL(k_id_solve_mfma, dim3(batch, (bt.n_max + MB - 1) / MB), dim3(64), lds, st, bt.A, bt.a_stride,
                      bt.lda, bt.n_arr, bt.n_uniform, bt.n_max, bt.rank, bt.piv, bt.piv_stride, Dinv, nblk, bt.P,
-                     bt.p_stride, bt.p_ld, r_max);
+                     bt.p_stride, bt.p_ld, r_max, bt.mask);
   FFC_LAUNCH_CHECK("k_id_solve_mfma");
   return FFC_OK;
 }

@@ -224,16 +224,19 @@ ffc_status launch_level_columns(const ffc_tree* t, ffc_skel* sk, int first, int 
                                 hipStream_t st);
 
 // Sampled kernel blocks for nodes [first, first+count) into A (node-major,
-// each s_cap x n_cap column-major with leading dimension s_cap) (kblock.hip).
+// each s_cap x n_cap column-major with leading dimension s_cap); with a mask
+// (indexed by node) only the nodes whose entry is set (kblock.hip).
 ffc_status launch_level_kblock(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision,
-                               int first, int count, double* A, hipStream_t st);
+                               int first, int count, double* A, hipStream_t st,
+                               const unsigned char* mask = nullptr);
 
 // Sampled blocks for nodes [first, first+count) given raw row/column lists
 // (node b: rows + b * s_cap, nrows[b], cols + b * n_cap, ncols[b]; the mixed
 // mode centres block b on centroid + (first + b) * d) (kblock.hip).
 ffc_status launch_kblock_batch(const ffc_tree* t, const KParams& kp, int precision, const int32_t* rows,
                                const int32_t* nrows, int s_cap, const int32_t* cols, const int32_t* ncols, int n_cap,
-                               int first, int count, const double* centroid, double* A, hipStream_t st);
+                               int first, int count, const double* centroid, double* A, hipStream_t st,
+                               const unsigned char* mask = nullptr);
 
 // Gram matrices of column-major m x n blocks, n x n row-major each (kblock.hip).
 ffc_status launch_gram(const double* B, int m, int n, int count, double* G, hipStream_t st);
@@ -261,6 +264,7 @@ struct IdBatch {
   double* P;              // [batch][p_stride], row-major rank x n with row stride n_max? (p_ld)
   int64_t p_stride;
   int p_ld;               // leading dimension of P rows
+  const unsigned char* mask = nullptr;   // [batch]: only entries set are factored (all when null)
 };
 ffc_status launch_interp_decomp(const IdBatch& b, int batch, hipStream_t st);
 
@@ -276,7 +280,8 @@ ffc_status launch_interp_decomp_coop(const IdBatch& b, int batch, DevBuf<unsigne
                                      bool& used);
 
 // Skeleton ids from pivots: skel[node][i] = cols[node][piv[node][i]] (cpqr.hip).
-ffc_status launch_skeleton_ids(ffc_skel* sk, int first, int count, hipStream_t st);
+ffc_status launch_skeleton_ids(ffc_skel* sk, int first, int count, hipStream_t st,
+                               const unsigned char* mask = nullptr);
 
 // Equivalent charges for a level (cpqr.hip).
 ffc_status launch_upward(const ffc_tree* t, ffc_skel* sk, int first, int count, bool leaves, hipStream_t st);
@@ -352,7 +357,8 @@ ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams&
 // kernels (gram_mfma.hip).
 ffc_status launch_kblock_batch_mixed(const ffc_tree* t, const KParams& kp, const int32_t* rows, const int32_t* nrows,
                                      int s_cap, const int32_t* cols, const int32_t* ncols, int n_cap, int first,
-                                     int count, const double* centroid, double* A, hipStream_t st);
+                                     int count, const double* centroid, double* A, hipStream_t st,
+                                     const unsigned char* mask);
 ffc_status launch_evaluate_mixed(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, double* u, double* u_far,
                                  hipStream_t st);
 ffc_status launch_direct_mixed(const double* Y, int64_t m, const double* X, int64_t n, int d, const KParams& kp,

@@ -139,11 +139,13 @@ __global__ void __launch_bounds__(NTH) k_level_kblock_mixed(const double* __rest
                                                             const int32_t* __restrict__ cols,
                                                             const int32_t* __restrict__ ncols_a, int n_cap,
                                                             const double* __restrict__ centroid,
+                                                            const unsigned char* __restrict__ mask,
                                                             double* __restrict__ A, unsigned int* flag) {
   __shared__ MixSmem sm;
   const int tiles = tiles_m * tiles_n;
   const int ln = blockIdx.x / tiles, tile = blockIdx.x % tiles;
   const int node = first + ln;
+  if (mask && !mask[node]) return;
   const int s = nrows_a[node], n = ncols_a[node];
   const int r0 = (tile % tiles_m) * TM, c0 = (tile / tiles_m) * TN;
   if (r0 >= s || c0 >= n) return;
@@ -296,16 +298,17 @@ __global__ void __launch_bounds__(NTH) k_direct_mixed(const double* __restrict__
 
 ffc_status launch_kblock_batch_mixed(const ffc_tree* t, const KParams& kp, const int32_t* rows, const int32_t* nrows,
                                      int s_cap, const int32_t* cols, const int32_t* ncols, int n_cap, int first,
-                                     int count, const double* centroid, double* A, hipStream_t st) {
+                                     int count, const double* centroid, double* A, hipStream_t st,
+                                     const unsigned char* mask) {
   const int tiles_m = (s_cap + TM - 1) / TM, tiles_n = (n_cap + TN - 1) / TN;
   const int64_t blocks = (int64_t)count * tiles_m * tiles_n;
   if (blocks == 0) return FFC_OK;
   if (kp.kind == FFC_POLYNOMIAL)
     hipLaunchKernelGGL(k_level_kblock_mixed<true>, dim3((unsigned)blocks), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
-                       first, tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, centroid, A, device_flag());
+                       first, tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, centroid, mask, A, device_flag());
   else
     hipLaunchKernelGGL(k_level_kblock_mixed<false>, dim3((unsigned)blocks), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
-                       first, tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, centroid, A, device_flag());
+                       first, tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, centroid, mask, A, device_flag());
   FFC_LAUNCH_CHECK("k_level_kblock_mixed");
   return FFC_OK;
 }

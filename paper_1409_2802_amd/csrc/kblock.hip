@@ -62,11 +62,13 @@ __global__ void __launch_bounds__(NT) k_level_kblock(const double* __restrict__ 
                                                      const int32_t* __restrict__ nrows, int s_cap,
                                                      const int32_t* __restrict__ cols,
                                                      const int32_t* __restrict__ ncols, int n_cap,
+                                                     const unsigned char* __restrict__ mask,
                                                      double* __restrict__ A, unsigned int* flag) {
   __shared__ TileSmem<T> sm;
   const int tiles = tiles_m * tiles_n;
   const int ln = blockIdx.x / tiles, tile = blockIdx.x % tiles;
   const int node = first + ln;
+  if (mask && !mask[node]) return;
   const int s = nrows[node], n = ncols[node];
   const int r0 = (tile % tiles_m) * BM, c0 = (tile / tiles_m) * BN;
   if (r0 >= s || c0 >= n) return;
@@ -237,9 +239,11 @@ ffc_status dispatch(int precision, bool dot, F&& f) {
 
 ffc_status launch_kblock_batch(const ffc_tree* t, const KParams& kp, int precision, const int32_t* rows,
                                const int32_t* nrows, int s_cap, const int32_t* cols, const int32_t* ncols, int n_cap,
-                               int first, int count, const double* centroid, double* A, hipStream_t st) {
+                               int first, int count, const double* centroid, double* A, hipStream_t st,
+                               const unsigned char* mask) {
   if (precision == FFC_MIXED_BF16X3 && kp.kind != FFC_LAPLACE)
-    return launch_kblock_batch_mixed(t, kp, rows, nrows, s_cap, cols, ncols, n_cap, first, count, centroid, A, st);
+    return launch_kblock_batch_mixed(t, kp, rows, nrows, s_cap, cols, ncols, n_cap, first, count, centroid, A, st,
+                                     mask);
   const int tiles_m = (s_cap + BM - 1) / BM, tiles_n = (n_cap + BN - 1) / BN;
   const int64_t blocks = (int64_t)count * tiles_m * tiles_n;
   if (blocks == 0) return FFC_OK;
@@ -248,16 +252,16 @@ ffc_status launch_kblock_batch(const ffc_tree* t, const KParams& kp, int precisi
     using T = decltype(tv);
     constexpr bool D = decltype(dv)::value;
     hipLaunchKernelGGL((k_level_kblock<T, D>), dim3((unsigned)blocks), dim3(NT), 0, st, t->Xt.ptr, t->d, kp, first,
-                       tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, A, device_flag());
+                       tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, mask, A, device_flag());
     FFC_LAUNCH_CHECK("k_level_kblock");
     return FFC_OK;
   });
 }
 
 ffc_status launch_level_kblock(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, int first,
-                               int count, double* A, hipStream_t st) {
+                               int count, double* A, hipStream_t st, const unsigned char* mask) {
   return launch_kblock_batch(t, kp, precision, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, sk->cols.ptr, sk->ncols.ptr,
-                             sk->n_cap, first, count, t->centroid.ptr, A, st);
+                             sk->n_cap, first, count, t->centroid.ptr, A, st, mask);
 }
 
 // Gram matrices G_b = B_b^T B_b of column-major m x n blocks (B_b at B + b * m * n):
