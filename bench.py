@@ -61,6 +61,9 @@ WORKLOADS = {
     "highdim1000g": dict(N=65536, d=1000, **HD, kernel="gaussian", h=1.5, leaf=512, max_rank=256,
                          num_samples=512, tol=1e-4, precision="mixed",
                          text="N=65536 d=1000 N(0,I)/sqrt(d) + 64 offsets of norm 3, Gaussian h=1.5"),
+    "adaptive4": dict(N=65536, d=4, data="uniform_cube", kernel="gaussian", h=0.3, leaf=512, max_rank=256,
+                      num_samples=64, adaptive_tol=1e-2, max_samples=512, tol=1e-7, precision="fp64",
+                      text="N=65536 d=4 uniform cube, Gaussian h=0.3, adaptive sample count"),
     "learned64": dict(N=262144, d=64, **SUB, kernel="gaussian", h=1.0, leaf=1024, max_rank=256, num_samples=512,
                       tol=1e-6, precision="mixed", learned=True, train_blocks=2000, block_cols=512,
                       block_rows=4096, epochs=2, batch=4096, lr=1e-3, eps=1e-4, pool_factor=8,
@@ -76,7 +79,8 @@ def parse():
     ap.add_argument("--workload", default="mixture16", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--train-blocks", type=int, default=None, help="learned64: training blocks")
-    ap.add_argument("--compare", action="store_true", help="learned64: uniform vs learned at 1x, 2x, 4x rows")
+    ap.add_argument("--compare", action="store_true",
+                    help="learned64: uniform vs learned at 1x, 2x, 4x rows; adaptive4: fixed row counts")
     ap.add_argument("--variants", default="fp32,mixed",
                     help="other precisions timed on the same workload, each judged against the FP64 path")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -94,6 +98,8 @@ def make_inputs(w):
         X = W.gaussian_mixture(w["N"], w["d"], k=w["clusters"], box=w["box"], std=w["std"], seed=0)
     elif w["data"] == "low_intrinsic":
         X = W.low_intrinsic(w["N"], w["d"], di=w["di"], noise=w["noise"], seed=0)
+    elif w["data"] == "uniform_cube":
+        X = W.uniform_cube(w["N"], w["d"], seed=0)
     else:
         X = W.highdim_clusters(w["N"], w["d"], k=w["clusters"], offset_norm=w["offset"], seed=0)
     q = W.charges(w["N"], seed=1)
@@ -167,16 +173,24 @@ def cpu_baseline(w, X, budget_s):
         Xt = X[ot.perm]
         t0 = time.perf_counter()
         done = 0
+        adaptive = w.get("adaptive_tol", 0.0) > 0
         for a in ot.level_nodes(ot.depth):          # leaves: their columns need no children
             cols = np.arange(ot.begin[a], ot.end[a], dtype=np.int64)
-            skeletonize_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], 0)
+            if adaptive:
+                from oracle.adaptive import adaptive_node
+                adaptive_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], w["max_samples"], 0,
+                              w["adaptive_tol"])
+            else:
+                skeletonize_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], 0)
             done += 1
             if time.perf_counter() - t0 > budget_s:
                 break
         dt = time.perf_counter() - t0
+    rows = (f"{w['num_samples']} sampled rows doubled up to {w['max_samples']} by the adaptive rule" if adaptive
+            else f"{w['num_samples']} sampled rows")
     return {"value": done / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} leaf nodes of the same tree ({w['leaf']} points, {w['num_samples']} sampled rows "
-                      f"each, FP64), single thread, {dt:.1f} s"}
+            "sample": f"{done} leaf nodes of the same tree ({w['leaf']} points, {rows} each, FP64), single thread, "
+                      f"{dt:.1f} s"}
 
 
 def oracle_far_check(w, X, q, u_far_gpu, count=256):
@@ -256,13 +270,17 @@ def main():
                     "train_ms_per_step": tr_ms / max(1, steps), "wall_s": wall}
         print(f"[bench] trained: {json.dumps(training)}", file=sys.stderr, flush=True)
 
-    def step(sk, s=w["num_samples"], mr=w["max_rank"], prop=proposal, p=prec, out=(u, uf)):
+    def step(sk, s=w["num_samples"], mr=w["max_rank"], prop=proposal, p=prec, out=(u, uf),
+             adaptive=w.get("adaptive_tol", 0.0)):
         sk = ffc.skeletonize(tree, k, tol=w["tol"], max_rank=mr, num_samples=s, precision=p, seed=0,
-                             reuse=sk, proposal=prop, pool_factor=w.get("pool_factor", 0))
+                             reuse=sk, proposal=prop, pool_factor=w.get("pool_factor", 0), adaptive_tol=adaptive,
+                             max_samples=w.get("max_samples", 0))
         ffc.evaluate_sum_into(tree, sk, k, qd, out[0], out[1], precision=p)
         return sk
 
-    use_graph = not args.eager and not (proposal is not None and w.get("fallback_tol", 0.0) > 0)
+    # Steps that synchronize inside (the learned fallback check, the adaptive rounds) cannot be captured.
+    use_graph = not args.eager and not (proposal is not None and w.get("fallback_tol", 0.0) > 0) \
+        and not w.get("adaptive_tol", 0.0) > 0
 
     def timed(p, steps, warmup, out):
         """Warm-up with eager calls, then time `steps` steps in precision p (graph replays unless --eager)."""
@@ -403,7 +421,8 @@ def main():
     if flops is not None and launches_per_step > 0:
         roof["achieved"] = flops / launches_per_step / (ms_per_launch * 1e-3) / 1e12
         roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = {"cpqr": "k_cpqr_coop", "solve": "k_coop_tasks + k_id_solve", "kblock": "k_level_kblock",
+    roof["kernel"] = {"cpqr": "k_cpqr_coop", "solve": "k_coop_setup + k_diag_inv + k_id_solve_mfma",
+                      "kblock": "k_level_kblock",
                       "evaluate": "k_evaluate", "sample": "k_sample_rows_bitmap", "upward": "k_upward",
                       "proposal": "k_geometry + k_features + k_mlp_score + k_select_rows"}.get(dom, dom)
     if dom == "cpqr":
@@ -439,6 +458,30 @@ def main():
     }
     if training is not None:
         out["training"] = training
+    if w.get("adaptive_tol", 0.0) > 0:
+        rows = [len(v["rows"]) for v in nodes.values()]
+        out["config"].update(adaptive_tol=w["adaptive_tol"], max_samples=w["max_samples"])
+        out["adaptive"] = {"rows_mean": float(np.mean(rows)), "rows_max": int(max(rows)),
+                           "node_redos": st["resampled"],
+                           "note": "the roofline counts the final factorization of each node only"}
+        if args.compare:
+            # Fixed row counts on the same tree, eager steps timed the same way.
+            cmp = []
+            for s in (64, 128, 256, 512):
+                skc = step(None, s=s, adaptive=0.0)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(args.steps):
+                    skc = step(skc, s=s, adaptive=0.0)
+                e1.record()
+                torch.cuda.synchronize()
+                row = {"num_samples": s, "ms_per_step": e0.elapsed_time(e1) / args.steps,
+                       "e_far_vs_exact": float(np.linalg.norm(uf.cpu().numpy() - far_exact)
+                                               / np.linalg.norm(far_exact))}
+                cmp.append(row)
+                print(f"[bench] fixed rows {row}", file=sys.stderr, flush=True)
+            out["adaptive"]["fixed_rows"] = cmp
     if args.compare and proposal is not None:
         cmp = []
         for mult in (1, 2, 4):

@@ -31,6 +31,24 @@ from .proposal import heldout_error, heldout_rows
 from .skeleton import Skeletons, effective_samples, skeletonize_node
 
 
+def adaptive_node(Xt: np.ndarray, tree, a: int, cols: np.ndarray, k: Kernel, tol: float, max_rank: int, s0: int,
+                  cap: int, seed: int, adaptive_tol: float):
+    """One node (Xt in tree order): returns (NodeSkeleton kept, [(rows, held-out error), ...] per draw)."""
+    b, e = int(tree.begin[a]), int(tree.end[a])
+    M = tree.N - (e - b)
+    Kh = kernel_matrix(Xt[heldout_rows(b, e, tree.N, seed, a)], Xt[cols], k)
+    s = s0
+    tried = []
+    while True:
+        node = skeletonize_node(Xt, tree, a, cols, k, tol, max_rank, s, seed)
+        err = heldout_error(Kh, node.piv[:node.rank], node.P) if len(cols) > 0 else 0.0
+        nr = len(node.rows)
+        tried.append((nr, err))
+        if not (err > adaptive_tol and nr < cap and nr < M):
+            return node, tried
+        s = min(2 * s, cap)
+
+
 def skeletonize_adaptive(X: np.ndarray, tree, k: Kernel, tol: float, max_rank: int, num_samples: int, seed: int,
                          adaptive_tol: float, max_samples: int = 0):
     """Skeletons of all non-root nodes with the adaptive sample count.
@@ -45,23 +63,10 @@ def skeletonize_adaptive(X: np.ndarray, tree, k: Kernel, tol: float, max_rank: i
     history = {}
     for level in range(tree.depth, 0, -1):
         for a in tree.level_nodes(level):
-            b, e = int(tree.begin[a]), int(tree.end[a])
-            M = tree.N - (e - b)
             if level == tree.depth:
-                cols = np.arange(b, e, dtype=np.int64)
+                cols = np.arange(tree.begin[a], tree.end[a], dtype=np.int64)
             else:
                 cols = np.concatenate([out.nodes[2 * a + 1].skel, out.nodes[2 * a + 2].skel])
-            Kh = kernel_matrix(Xt[heldout_rows(b, e, tree.N, seed, a)], Xt[cols], k)
-            s = s0
-            tried = []
-            while True:
-                node = skeletonize_node(Xt, tree, a, cols, k, tol, max_rank, s, seed)
-                err = heldout_error(Kh, node.piv[:node.rank], node.P) if len(cols) > 0 else 0.0
-                nr = len(node.rows)
-                tried.append((nr, err))
-                if not (err > adaptive_tol and nr < cap and nr < M):
-                    break
-                s = min(2 * s, cap)
-            out.nodes[a] = node
-            history[a] = tried
+            out.nodes[a], history[a] = adaptive_node(Xt, tree, a, cols, k, tol, max_rank, s0, cap, seed,
+                                                     adaptive_tol)
     return out, history

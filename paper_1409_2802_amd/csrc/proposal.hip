@@ -555,6 +555,13 @@ __global__ void __launch_bounds__(512) k_select_rows(const float* __restrict__ s
 // Held-out residual: err = ||K_h - K_h(:, piv[:r]) P|| / ||K_h|| per node, over
 // the node's nh_arr[node] held-out rows (K_h column-major, leading dimension
 // h_cap); sets the node's fallback mask when err > tol. One workgroup per node.
+// One workgroup per node. The residual K_h - K_h(:, J) P vanishes exactly on
+// the skeleton columns (P is the identity there), so only the other columns
+// are formed: the skeleton columns of K_h (r x 32) are staged in LDS, each
+// thread owns one column j with its 32 held-out rows in registers and
+// accumulates K_h(:, J) P(:, j) over the rank (P read coalesced, the LDS reads
+// broadcast). Fixed-order reduction of the squared norms.
+constexpr int kHeldRows = 32;
 __global__ void __launch_bounds__(256) k_heldout_check(const double* __restrict__ Kh, const int32_t* __restrict__ nh_arr,
                                                        int h_cap, int n_cap,
                                                        int r_cap, int first, const int32_t* __restrict__ rank,
@@ -562,21 +569,46 @@ __global__ void __launch_bounds__(256) k_heldout_check(const double* __restrict_
                                                        const int32_t* __restrict__ piv, const double* __restrict__ P,
                                                        double tol, unsigned char* __restrict__ mask,
                                                        unsigned int* __restrict__ fallbacks, HeldoutGrow grow) {
+  extern __shared__ double kj[];                  // r_cap x kHeldRows, then the pivot bitmap
+  unsigned int* isp = reinterpret_cast<unsigned int*>(kj + (size_t)r_cap * kHeldRows);
   __shared__ double r1[256], r2[256];
   const int b = blockIdx.x, node = first + b, tid = threadIdx.x;
   const int n = ncols[node], r = rank[node], nh = nh_arr[node];
   const double* K = Kh + (int64_t)b * h_cap * n_cap;   // column-major h_cap x n
   const int32_t* pv = piv + (int64_t)node * n_cap;
   const double* Pn = P + (int64_t)node * r_cap * n_cap;
+  for (int w = tid; w < (n + 31) / 32; w += 256) isp[w] = 0u;
+  for (int e = tid; e < r * kHeldRows; e += 256) {
+    const int i = e / kHeldRows, h = e % kHeldRows;
+    kj[e] = h < nh ? K[(int64_t)pv[i] * h_cap + h] : 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < r; i += 256) atomicOr(&isp[pv[i] >> 5], 1u << (pv[i] & 31));
+  __syncthreads();
   double num = 0.0, den = 0.0;
-  for (int e = tid; e < nh * n; e += 256) {
-    const int h = e % nh, j = e / nh;
-    const double kv = K[(int64_t)j * h_cap + h];
-    double approx = 0.0;
-    for (int i = 0; i < r; ++i) approx = fma(K[(int64_t)pv[i] * h_cap + h], Pn[(int64_t)i * n_cap + j], approx);
-    const double res = kv - approx;
-    num = fma(res, res, num);
-    den = fma(kv, kv, den);
+  for (int j = tid; j < n; j += 256) {
+    double acc[kHeldRows];
+#pragma unroll
+    for (int h = 0; h < kHeldRows; ++h) acc[h] = 0.0;
+    if (!((isp[j >> 5] >> (j & 31)) & 1u)) {
+      for (int i = 0; i < r; ++i) {
+        const double p = Pn[(int64_t)i * n_cap + j];
+#pragma unroll
+        for (int h = 0; h < kHeldRows; ++h) acc[h] = fma(kj[i * kHeldRows + h], p, acc[h]);
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < kHeldRows; ++h) acc[h] = h < nh ? K[(int64_t)j * h_cap + h] : 0.0;   // exact
+    }
+#pragma unroll
+    for (int h = 0; h < kHeldRows; ++h) {
+      if (h < nh) {
+        const double kv = K[(int64_t)j * h_cap + h];
+        const double res = kv - acc[h];
+        num = fma(res, res, num);
+        den = fma(kv, kv, den);
+      }
+    }
   }
   r1[tid] = num;
   r2[tid] = den;
@@ -692,7 +724,15 @@ ffc_status launch_heldout_check(const double* Kh, const int32_t* nh, int h_cap, 
                                 int count, double tol, unsigned char* mask, unsigned int* fallbacks,
                                 const HeldoutGrow& grow, hipStream_t st) {
   if (count <= 0) return FFC_OK;
-  hipLaunchKernelGGL(k_heldout_check, dim3(count), dim3(256), 0, st, Kh, nh, h_cap, sk->n_cap, sk->r_cap, first,
+  if (h_cap != kHeldRows) {
+    set_error("held-out check: 32 held-out rows expected");
+    return FFC_ERR_INVALID_ARG;
+  }
+  const size_t lds = (size_t)sk->r_cap * kHeldRows * sizeof(double) + ((size_t)sk->n_cap + 31) / 32 * sizeof(int);
+  if (lds > 64 * 1024)
+    FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_heldout_check),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_heldout_check, dim3(count), dim3(256), lds, st, Kh, nh, h_cap, sk->n_cap, sk->r_cap, first,
                      sk->rank.ptr, sk->ncols.ptr, sk->piv.ptr, sk->P.ptr, tol, mask, fallbacks, grow);
   FFC_LAUNCH_CHECK("k_heldout_check");
   return FFC_OK;
