@@ -64,7 +64,26 @@ typedef struct {
  * evaluated from explicit float32 differences in that mode). */
 typedef enum { FFC_FP64 = 0, FFC_FP32 = 1, FFC_MIXED_BF16X3 = 2 } ffc_precision;
 
-typedef enum { FFC_SAMPLE_UNIFORM = 0, FFC_SAMPLE_LEARNED = 1 } ffc_sampler;
+/* Row samplers. UNIFORM: uniform without replacement over the points outside
+ * the node (Section 4.1.3). The others choose s rows from a pool of
+ * min(M, pool_factor * s) uniform far points, with the node's column
+ * geometry (centroid c, radius rho, a 256-point column subsample):
+ *  LEARNED   weights from the proposal network's scores (importance sampling
+ *            by predicted leverage, Section 3);
+ *  DISTANCE  the paper's distance sampling (Sections 3.2, 4.1.3): without
+ *            replacement, weights inversely proportional to |y - c| (the
+ *            motivation of Section 3.2; Section 4.1.3's "proportional" would
+ *            favour the least significant rows);
+ *  NEAREST   the paper's nearest neighbours, deterministic: the s pool points
+ *            nearest to the node's columns (distance to the nearest point of
+ *            the column subsample; exact for nodes of at most 256 columns).
+ * All pool samplers support the held-out fallback (fallback_tol). */
+typedef enum {
+  FFC_SAMPLE_UNIFORM = 0,
+  FFC_SAMPLE_LEARNED = 1,
+  FFC_SAMPLE_DISTANCE = 2,
+  FFC_SAMPLE_NEAREST = 3
+} ffc_sampler;
 
 typedef struct ffc_tree ffc_tree;
 typedef struct ffc_skel ffc_skel;
@@ -81,10 +100,10 @@ typedef struct ffc_proposal ffc_proposal;
  *  sampler      ffc_sampler; FFC_SAMPLE_LEARNED needs `proposal` (kept by
  *               reference: it must outlive the call)
  *  seed         seed of the counter-based row sampler
- *  fallback_tol learned sampler only: a node whose held-out error estimate
+ *  fallback_tol pool samplers only: a node whose held-out error estimate
  *               exceeds it is redone with uniform rows (<= 0 disables; the
  *               check synchronizes the stream once per level)
- *  pool_factor  learned sampler only: the candidate pool of a node is
+ *  pool_factor  pool samplers only: the candidate pool of a node is
  *               min(M, pool_factor * samples) uniform far points (0 means 8;
  *               the pool is limited to 8192)
  *  adaptive_tol uniform sampler only; > 0 turns on the adaptive sample count

@@ -231,10 +231,12 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
   if (!(o->tol >= 0.0)) return fail(FFC_ERR_INVALID_ARG, "tol must be >= 0");
   if (o->max_rank < 1) return fail(FFC_ERR_INVALID_ARG, "max_rank must be >= 1");
   if (o->num_samples < 0) return fail(FFC_ERR_INVALID_ARG, "num_samples must be >= 0");
-  if (o->sampler != FFC_SAMPLE_UNIFORM && o->sampler != FFC_SAMPLE_LEARNED)
+  if (o->sampler < FFC_SAMPLE_UNIFORM || o->sampler > FFC_SAMPLE_NEAREST)
     return fail(FFC_ERR_INVALID_ARG, "unknown sampler");
-  const bool learned = o->sampler == FFC_SAMPLE_LEARNED;
-  if (learned && !o->proposal) return fail(FFC_ERR_INVALID_ARG, "the learned sampler needs a proposal");
+  // Every sampler but the uniform one draws from a candidate pool (learned proposal, distance, nearest).
+  const bool learned = o->sampler != FFC_SAMPLE_UNIFORM;
+  if (o->sampler == FFC_SAMPLE_LEARNED && !o->proposal)
+    return fail(FFC_ERR_INVALID_ARG, "the learned sampler needs a proposal");
   if (learned && !std::isfinite(o->fallback_tol)) return fail(FFC_ERR_INVALID_ARG, "fallback_tol must be finite");
   if (learned && o->pool_factor < 0) return fail(FFC_ERR_INVALID_ARG, "pool_factor must be >= 0");
   if (!std::isfinite(o->adaptive_tol)) return fail(FFC_ERR_INVALID_ARG, "adaptive_tol must be finite");
@@ -351,7 +353,7 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
       }
       if (learned) {
         StageTimer tm(FFC_STAGE_PROPOSAL, st);
-        FFC_TRY(learned_rows_level(t, sk, o->proposal, first, count, s_cap, o->seed, st));
+        FFC_TRY(learned_rows_level(t, sk, o->sampler, o->proposal, first, count, s_cap, o->seed, st));
       } else {
         StageTimer tm(FFC_STAGE_SAMPLE, st);
         FFC_TRY(launch_sample_rows(t, sk, first, count, s0, o->seed, st));
@@ -591,8 +593,8 @@ ffc_status ffc_step_graph_create(const ffc_tree* t, ffc_skel* sk, const ffc_kern
     set_error("graphs need a non-null stream");
     return FFC_ERR_INVALID_ARG;
   }
-  if (o->sampler == FFC_SAMPLE_LEARNED && o->fallback_tol > 0.0) {
-    set_error("the learned sampler's fallback check synchronizes and cannot be captured");
+  if (o->sampler != FFC_SAMPLE_UNIFORM && o->fallback_tol > 0.0) {
+    set_error("the pool samplers' fallback check synchronizes and cannot be captured");
     return FFC_ERR_INVALID_ARG;
   }
   if (o->adaptive_tol > 0.0) {

@@ -224,8 +224,8 @@ ffc_status learned_alloc(const ffc_tree* t, ffc_skel* sk, int pool_factor) {
   return FFC_OK;
 }
 
-ffc_status learned_rows_level(const ffc_tree* t, ffc_skel* sk, const ffc_proposal* p, int first, int count, int s,
-                              uint64_t seed, hipStream_t st) {
+ffc_status learned_rows_level(const ffc_tree* t, ffc_skel* sk, int sampler, const ffc_proposal* p, int first,
+                              int count, int s, uint64_t seed, hipStream_t st) {
   LearnedScratch& L = sk->learned;
   const int pc = L.p_cap;
   FFC_TRY(launch_sample_rows_into(t, L.pool.ptr, L.npool.ptr, pc, first, count, pc, seed, kStreamPool, nullptr, st));
@@ -234,10 +234,18 @@ ffc_status learned_rows_level(const ffc_tree* t, ffc_skel* sk, const ffc_proposa
   FFC_TRY(launch_geometry(t->Xt.ptr, t->d, ga, count, st));
   FFC_TRY(launch_features(t->Xt.ptr, t->d, ga, L.pool.ptr + (int64_t)first * pc, pc, L.npool.ptr + first, count,
                           L.feat.ptr, (int64_t)pc * kNF, st));
-  FFC_TRY(launch_mlp_score(p->theta.ptr, p->mu.ptr, p->sd.ptr, L.feat.ptr, (int64_t)count * pc, L.score.ptr, st));
-  FFC_TRY(launch_select_rows(L.score.ptr, pc, L.pool.ptr + (int64_t)first * pc, pc, L.npool.ptr + first, first,
-                             count, s, seed, sk->ncols.ptr, nullptr, sk->rows.ptr, sk->s_cap, sk->nrows.ptr, st));
-  return FFC_OK;
+  if (sampler == FFC_SAMPLE_LEARNED) {
+    FFC_TRY(launch_mlp_score(p->theta.ptr, p->mu.ptr, p->sd.ptr, L.feat.ptr, (int64_t)count * pc, L.score.ptr, st));
+    return launch_select_rows(L.score.ptr, pc, 1, 0, L.pool.ptr + (int64_t)first * pc, pc, L.npool.ptr + first, first,
+                              count, s, seed, sk->ncols.ptr, nullptr, sk->rows.ptr, sk->s_cap, sk->nrows.ptr, st);
+  }
+  // The paper's heuristics (Sections 3.2, 4.1.3) on the same pool: distance
+  // weights from f0 = |y - c| / rho, nearest neighbours by f2 = distance to the
+  // nearest point of the column subsample / rho.
+  const bool dist = sampler == FFC_SAMPLE_DISTANCE;
+  return launch_select_rows(L.feat.ptr + (dist ? 0 : 2), (int64_t)pc * kNF, kNF, dist ? 1 : 2,
+                            L.pool.ptr + (int64_t)first * pc, pc, L.npool.ptr + first, first, count, s, seed,
+                            sk->ncols.ptr, nullptr, sk->rows.ptr, sk->s_cap, sk->nrows.ptr, st);
 }
 
 ffc_status learned_heldout_level(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int precision, int first,

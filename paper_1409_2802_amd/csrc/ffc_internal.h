@@ -289,8 +289,8 @@ ffc_status launch_charges_to_tree(ffc_tree* t, const double* q, hipStream_t st);
 
 // Learned sampler for one level (api_proposal.hip): candidate pool, geometry,
 // features, scores and selection into sk->rows / sk->nrows.
-ffc_status learned_rows_level(const ffc_tree* t, ffc_skel* sk, const ffc_proposal* p, int first, int count, int s,
-                              uint64_t seed, hipStream_t st);
+ffc_status learned_rows_level(const ffc_tree* t, ffc_skel* sk, int sampler, const ffc_proposal* p, int first,
+                              int count, int s, uint64_t seed, hipStream_t st);
 // Held-out check of a skeletonized level; returns in `redo` the number of nodes
 // that failed (their mask is set and their rows redrawn uniformly). Synchronizes.
 ffc_status learned_heldout_level(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int precision, int first,
@@ -319,12 +319,15 @@ ffc_status launch_mlp_grad(const float* theta, const float* mu, const float* sdv
 ffc_status launch_grad_reduce_adam(const float* grads, int nwg, float* theta, float* m1, float* m2, float* gsum,
                                    float* loss_out, bool adam, float lr, int step, int64_t total, hipStream_t st);
 ffc_status launch_feature_stats(const float* feat, int64_t count, float* mu, float* sdv, hipStream_t st);
-// Selection for nodes [first, first+count): pool / npool / score indexed by
-// b = node - first, rows / nrows / ncols / mask by node; nodes with an empty
-// column set get nrows = 0.
-ffc_status launch_select_rows(const float* score, int64_t score_stride, const int32_t* pool, int pool_stride,
-                              const int32_t* npool, int first, int count, int s, uint64_t seed, const int32_t* ncols,
-                              const unsigned char* mask, int32_t* rows, int s_cap, int32_t* nrows, hipStream_t st);
+// Selection for nodes [first, first+count): pool / npool / values indexed by
+// b = node - first (value i at score[b * score_stride + i * elem_stride]),
+// rows / nrows / ncols / mask by node; nodes with an empty column set get
+// nrows = 0. mode 0: learned weights from scores; 1: weights proportional to
+// 1 / value; 2: the s smallest values.
+ffc_status launch_select_rows(const float* score, int64_t score_stride, int elem_stride, int mode,
+                              const int32_t* pool, int pool_stride, const int32_t* npool, int first, int count, int s,
+                              uint64_t seed, const int32_t* ncols, const unsigned char* mask, int32_t* rows, int s_cap,
+                              int32_t* nrows, hipStream_t st);
 // Held-out check of the nodes [first, first+count): err = |K_h - K_h(:, J) P|_F
 // / |K_h|_F; mask[node] = err > tol, and with grow.nrows set also only when
 // the node's row count can still grow (below grow.s_limit and the points

@@ -461,7 +461,11 @@ __global__ void __launch_bounds__(256) k_feature_stats(const float* __restrict__
 // ---------------------------------------------------------------------------
 // Importance selection: one workgroup per node; pool <= 8192 candidates.
 // ---------------------------------------------------------------------------
+// mode 0 (learned): Efraimidis-Spirakis keys -ln(u) / w with w = 0.9 softmax(score) + 0.1 / P;
+// mode 1 (distance): keys -ln(u) * max(v, 1e-12), i.e. weights proportional to 1 / v;
+// mode 2 (nearest): keys v (deterministic). Value i of node b is score[b * score_stride + i * elem_stride].
 __global__ void __launch_bounds__(512) k_select_rows(const float* __restrict__ score, int64_t score_stride,
+                                                     int elem_stride, int mode,
                                                      const int32_t* __restrict__ pool, int pool_stride,
                                                      const int32_t* __restrict__ npool, int first, int s_req,
                                                      uint64_t seed, const int32_t* __restrict__ ncols,
@@ -487,32 +491,41 @@ __global__ void __launch_bounds__(512) k_select_rows(const float* __restrict__ s
     if (tid == 0) nrows[node] = P;
     return;
   }
-  // softmax: max, then sum of exponentials (double, fixed order per thread + tree).
-  double mx = -INFINITY;
-  for (int i = tid; i < P; i += 512) mx = fmax(mx, (double)sc[i]);
-  red[tid] = mx;
-  __syncthreads();
-  for (int off = 256; off > 0; off >>= 1) {
-    if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+  double mx = 0.0, se = 1.0;
+  if (mode == 0) {
+    // softmax: max, then sum of exponentials (double, fixed order per thread + tree).
+    mx = -INFINITY;
+    for (int i = tid; i < P; i += 512) mx = fmax(mx, (double)sc[(int64_t)i * elem_stride]);
+    red[tid] = mx;
     __syncthreads();
-  }
-  mx = red[0];
-  __syncthreads();
-  double se = 0.0;
-  for (int i = tid; i < P; i += 512) se += exp((double)sc[i] - mx);
-  red[tid] = se;
-  __syncthreads();
-  for (int off = 256; off > 0; off >>= 1) {
-    if (tid < off) red[tid] += red[tid + off];
+    for (int off = 256; off > 0; off >>= 1) {
+      if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
+      __syncthreads();
+    }
+    mx = red[0];
     __syncthreads();
+    se = 0.0;
+    for (int i = tid; i < P; i += 512) se += exp((double)sc[(int64_t)i * elem_stride] - mx);
+    red[tid] = se;
+    __syncthreads();
+    for (int off = 256; off > 0; off >>= 1) {
+      if (tid < off) red[tid] += red[tid + off];
+      __syncthreads();
+    }
+    se = red[0];
   }
-  se = red[0];
   for (int i = tid; i < sort_n; i += 512) {
     if (i < P) {
-      const double wgt = 0.9 * exp((double)sc[i] - mx) / se + 0.1 / P;
-      const double u = ((double)(counter_u64(seed, (uint64_t)node | STREAM_KEYS, (uint64_t)i) >> 11) + 0.5) * 0x1.0p-53;
-      const double kv = -log(u) / wgt;
-      key[i] = isfinite(kv) ? kv : INFINITY;   // a non-finite score is drawn last (by index)
+      const double v = (double)sc[(int64_t)i * elem_stride];
+      double kv;
+      if (mode == 2) {
+        kv = v;
+      } else {
+        const double u =
+            ((double)(counter_u64(seed, (uint64_t)node | STREAM_KEYS, (uint64_t)i) >> 11) + 0.5) * 0x1.0p-53;
+        kv = mode == 1 ? -log(u) * fmax(v, 1e-12) : -log(u) / (0.9 * exp(v - mx) / se + 0.1 / P);
+      }
+      key[i] = isfinite(kv) ? kv : INFINITY;   // a non-finite value is drawn last (by index)
       idx[i] = i;
     } else {
       key[i] = INFINITY;
@@ -700,9 +713,10 @@ ffc_status launch_feature_stats(const float* feat, int64_t count, float* mu, flo
   return FFC_OK;
 }
 
-ffc_status launch_select_rows(const float* score, int64_t score_stride, const int32_t* pool, int pool_stride,
-                              const int32_t* npool, int first, int count, int s, uint64_t seed, const int32_t* ncols,
-                              const unsigned char* mask, int32_t* rows, int s_cap, int32_t* nrows, hipStream_t st) {
+ffc_status launch_select_rows(const float* score, int64_t score_stride, int elem_stride, int mode,
+                              const int32_t* pool, int pool_stride, const int32_t* npool, int first, int count, int s,
+                              uint64_t seed, const int32_t* ncols, const unsigned char* mask, int32_t* rows, int s_cap,
+                              int32_t* nrows, hipStream_t st) {
   if (count <= 0) return FFC_OK;
   int sort_n = 1;
   while (sort_n < pool_stride) sort_n <<= 1;
@@ -714,8 +728,8 @@ ffc_status launch_select_rows(const float* score, int64_t score_stride, const in
   if (lds > 64 * 1024)
     FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select_rows),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_select_rows, dim3(count), dim3(512), lds, st, score, score_stride, pool, pool_stride, npool,
-                     first, s, seed, ncols, mask, rows, s_cap, nrows, sort_n);
+  hipLaunchKernelGGL(k_select_rows, dim3(count), dim3(512), lds, st, score, score_stride, elem_stride, mode, pool,
+                     pool_stride, npool, first, s, seed, ncols, mask, rows, s_cap, nrows, sort_n);
   FFC_LAUNCH_CHECK("k_select_rows");
   return FFC_OK;
 }

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libffc.so")
 FFC_OK, FFC_ERR_INVALID_ARG, FFC_ERR_HIP, FFC_ERR_OOM, FFC_ERR_NONFINITE, FFC_ERR_STATE = range(6)
 GAUSSIAN, LAPLACE, POLYNOMIAL = 0, 1, 2
 FP64, FP32, MIXED_BF16X3 = 0, 1, 2
-SAMPLE_UNIFORM, SAMPLE_LEARNED = 0, 1
+SAMPLE_UNIFORM, SAMPLE_LEARNED, SAMPLE_DISTANCE, SAMPLE_NEAREST = 0, 1, 2, 3
 
 # Every exported entry point of include/ffc.h.
 EXPORTS = [
@@ -257,12 +257,16 @@ class Skeletons:
 def skeletonize(tree: Tree, kernel: Kernel, tol: float, max_rank: int, num_samples: int = 0,
                 precision: int = FP64, seed: int = 0, reuse: Skeletons | None = None,
                 proposal: "Proposal | None" = None, fallback_tol: float = 0.0, pool_factor: int = 0,
-                adaptive_tol: float = 0.0, max_samples: int = 0, stream=None) -> Skeletons:
-    """Skeletonize every non-root node; with `proposal` the rows come from the learned sampler, with
+                adaptive_tol: float = 0.0, max_samples: int = 0, sampler: int | None = None,
+                stream=None) -> Skeletons:
+    """Skeletonize every non-root node; with `proposal` the rows come from the learned sampler (or `sampler`:
+    SAMPLE_DISTANCE / SAMPLE_NEAREST for the paper's heuristics on the same candidate pool), with
     `adaptive_tol` > 0 a node's row count doubles until its held-out error estimate is at most adaptive_tol
     (or `max_samples` is reached)."""
+    if sampler is None:
+        sampler = SAMPLE_LEARNED if proposal is not None else SAMPLE_UNIFORM
     opts = SkelOptsC(tol=tol, max_rank=max_rank, num_samples=num_samples, precision=precision,
-                     sampler=SAMPLE_LEARNED if proposal is not None else SAMPLE_UNIFORM, seed=seed,
+                     sampler=sampler, seed=seed,
                      proposal=proposal.handle if proposal is not None else None, fallback_tol=fallback_tol,
                      pool_factor=pool_factor, adaptive_tol=adaptive_tol, max_samples=max_samples)
     h = ctypes.c_void_p(reuse.handle.value if reuse is not None else None)
@@ -279,9 +283,12 @@ class StepGraph:
 
     def __init__(self, tree: Tree, sk: Skeletons, kernel: Kernel, q: torch.Tensor, u: torch.Tensor,
                  u_far: torch.Tensor | None, stream, tol: float, max_rank: int, num_samples: int = 0,
-                 precision: int = FP64, seed: int = 0, proposal: "Proposal | None" = None, pool_factor: int = 0):
+                 precision: int = FP64, seed: int = 0, proposal: "Proposal | None" = None, pool_factor: int = 0,
+                 sampler: int | None = None):
+        if sampler is None:
+            sampler = SAMPLE_LEARNED if proposal is not None else SAMPLE_UNIFORM
         opts = SkelOptsC(tol=tol, max_rank=max_rank, num_samples=num_samples, precision=precision,
-                         sampler=SAMPLE_LEARNED if proposal is not None else SAMPLE_UNIFORM, seed=seed,
+                         sampler=sampler, seed=seed,
                          proposal=proposal.handle if proposal is not None else None, fallback_tol=0.0,
                          pool_factor=pool_factor)
         self._keep = (tree, sk, q, u, u_far, proposal)   # the graph holds their device pointers
