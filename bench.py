@@ -271,10 +271,10 @@ def main():
         print(f"[bench] trained: {json.dumps(training)}", file=sys.stderr, flush=True)
 
     def step(sk, s=w["num_samples"], mr=w["max_rank"], prop=proposal, p=prec, out=(u, uf),
-             adaptive=w.get("adaptive_tol", 0.0)):
+             adaptive=w.get("adaptive_tol", 0.0), sampler=None):
         sk = ffc.skeletonize(tree, k, tol=w["tol"], max_rank=mr, num_samples=s, precision=p, seed=0,
                              reuse=sk, proposal=prop, pool_factor=w.get("pool_factor", 0), adaptive_tol=adaptive,
-                             max_samples=w.get("max_samples", 0))
+                             max_samples=w.get("max_samples", 0), sampler=sampler)
         ffc.evaluate_sum_into(tree, sk, k, qd, out[0], out[1], precision=p)
         return sk
 
@@ -483,18 +483,29 @@ def main():
                 print(f"[bench] fixed rows {row}", file=sys.stderr, flush=True)
             out["adaptive"]["fixed_rows"] = cmp
     if args.compare and proposal is not None:
+        # Far-field error of every sampler at 1x, 2x and 4x the rank cap, and the time of one eager step:
+        # uniform, the learned proposal, and the paper's distance and nearest-neighbour heuristics (on the
+        # same candidate pool as the proposal).
+        samplers = (("uniform", None, ffc.SAMPLE_UNIFORM), ("learned", proposal, ffc.SAMPLE_LEARNED),
+                    ("distance", None, ffc.SAMPLE_DISTANCE), ("nearest", None, ffc.SAMPLE_NEAREST))
         cmp = []
         for mult in (1, 2, 4):
             s = min(mult * w["max_rank"], 1024)
             row = {"num_samples": s}
-            for name, prop in (("uniform", None), ("learned", proposal)):
-                skc = step(None, s=s, prop=prop)
+            for name, prop, smp in samplers:
+                skc = step(None, s=s, prop=prop, sampler=smp)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                skc = step(skc, s=s, prop=prop, sampler=smp)
+                e1.record()
                 torch.cuda.synchronize()
                 row[name] = float(np.linalg.norm(uf.cpu().numpy() - far_exact) / np.linalg.norm(far_exact))
+                row[name + "_ms"] = e0.elapsed_time(e1)
                 row[name + "_fallbacks"] = skc.stats()["fallbacks"]
             cmp.append(row)
             print(f"[bench] compare {row}", file=sys.stderr, flush=True)
-        out["uniform_vs_learned_e_far"] = cmp
+        out["sampler_e_far"] = cmp
     if not args.no_cpu_baseline:
         cb = cpu_baseline(w, X, args.cpu_budget_s)
         cb["e_far_vs_oracle_256_targets"] = oracle_far_check(w, X, q, uf_h)
