@@ -114,7 +114,17 @@ typedef struct ffc_proposal ffc_proposal;
  *               twice the rows (a fresh uniform draw), until all pass or reach
  *               the cap; each round synchronizes the stream once. <= 0: off.
  *  max_samples  cap of the adaptive sample count (0 means 4 * the initial
- *               count); rows never exceed the points outside the node */
+ *               count); rows never exceed the points outside the node
+ *  separation   xi >= 0, the separation of sources and targets (Section 2,
+ *               eq. e:separated; Section 4.1 measures it as a multiple of the
+ *               source ball's radius). A point y outside node a is separated
+ *               from a when |y - c_a|^2 >= (xi rho_a)^2, with c_a and rho_a the
+ *               node's centroid and radius (ffc_tree_arrays). xi > 0 draws the
+ *               rows of every node uniformly from its separated points in
+ *               ascending tree order (Floyd on their count; a node with none
+ *               draws from all points outside it, as xi = 0 does) and makes
+ *               ffc_evaluate_sum a treecode with the same test. 0: the plain
+ *               method. Uniform sampler only, no adaptive count. */
 typedef struct {
   double tol;
   int32_t max_rank;
@@ -127,6 +137,7 @@ typedef struct {
   int32_t pool_factor;
   double adaptive_tol;
   int32_t max_samples;
+  double separation;
 } ffc_skel_opts;
 
 /* Build a binary ball tree over X (Section 2: hierarchical groupings of the
@@ -175,9 +186,15 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
 /* u = K q with the compressed far field (eq. e:id): equivalent charges
  * q~ = P q upward through the tree, then for every target the skeletons of
  * the siblings of its leaf's ancestors (far field) plus its own leaf directly
- * (near field). q_dev and u_dev are N-vectors in caller order; u_far_dev
- * (nullable) receives the far-field part only. precision: ffc_precision of the
- * kernel evaluations. The skeleton must come from the same tree. */
+ * (near field). A skeleton set built with separation xi > 0 is evaluated as a
+ * treecode (Section 2): each target walks down from the root's children; a
+ * node that does not contain it and from which it is separated (the test of
+ * ffc_skel_opts.separation) contributes its skeleton sum and ends that branch,
+ * any other node passes the target to its children, and leaves reached that
+ * way (the target's own among them) are summed directly. q_dev and u_dev are
+ * N-vectors in caller order; u_far_dev (nullable) receives the far-field part
+ * only. precision: ffc_precision of the kernel evaluations (a treecode takes
+ * FFC_FP64 or FFC_FP32). The skeleton must come from the same tree. */
 ffc_status ffc_evaluate_sum(const ffc_tree* t, const ffc_skel* sk, const ffc_kernel* k,
                             const double* q_dev, double* u_dev, double* u_far_dev,
                             int32_t precision, void* stream);

@@ -244,6 +244,11 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
   if (adaptive && learned)
     return fail(FFC_ERR_INVALID_ARG, "the adaptive sample count works with the uniform sampler only");
   if (o->max_samples < 0) return fail(FFC_ERR_INVALID_ARG, "max_samples must be >= 0");
+  if (!(o->separation >= 0.0)) return fail(FFC_ERR_INVALID_ARG, "separation must be >= 0");
+  const bool separated = o->separation > 0.0;
+  if (separated && (learned || adaptive))
+    return fail(FFC_ERR_INVALID_ARG, "separation works with the uniform sampler and a fixed sample count only");
+  if (separated && t->depth > 30) return fail(FFC_ERR_INVALID_ARG, "separation supports trees of depth <= 30");
   hipStream_t st = (hipStream_t)stream;
 
   const int64_t s_req = o->num_samples > 0 ? o->num_samples : 2 * (int64_t)o->max_rank;
@@ -345,6 +350,10 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
   auto run = [&]() -> ffc_status {
     if (learned) FFC_TRY(learned_alloc(t, sk, o->pool_factor > 0 ? o->pool_factor : 8));
     if (adaptive) FFC_TRY(heldout_alloc(t, sk));
+    if (separated) {
+      StageTimer tm(FFC_STAGE_SAMPLE, st);
+      FFC_TRY(launch_separation(t, sk, o->separation, st));
+    }
     for (int lev = t->depth; lev >= 1; --lev) {
       const int first = (1 << lev) - 1, count = 1 << lev;
       {
@@ -354,6 +363,9 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
       if (learned) {
         StageTimer tm(FFC_STAGE_PROPOSAL, st);
         FFC_TRY(learned_rows_level(t, sk, o->sampler, o->proposal, first, count, s_cap, o->seed, st));
+      } else if (separated) {
+        StageTimer tm(FFC_STAGE_SAMPLE, st);
+        FFC_TRY(launch_sample_rows_sep(t, sk, first, count, s0, o->seed, st));
       } else {
         StageTimer tm(FFC_STAGE_SAMPLE, st);
         FFC_TRY(launch_sample_rows(t, sk, first, count, s0, o->seed, st));
@@ -425,7 +437,10 @@ ffc_status ffc_evaluate_sum(const ffc_tree* t, const ffc_skel* sk, const ffc_ker
   }
   {
     StageTimer timer(FFC_STAGE_EVALUATE, st);
-    FFC_TRY(launch_evaluate(t, sk, make_kparams(*k, t->d), precision, u_dev, u_far_dev, st));
+    if (sk->opts.separation > 0.0)
+      FFC_TRY(launch_treecode(t, sk, make_kparams(*k, t->d), precision, u_dev, u_far_dev, st));
+    else
+      FFC_TRY(launch_evaluate(t, sk, make_kparams(*k, t->d), precision, u_dev, u_far_dev, st));
   }
   tm->last_stream = st;
   return FFC_OK;
@@ -600,6 +615,10 @@ ffc_status ffc_step_graph_create(const ffc_tree* t, ffc_skel* sk, const ffc_kern
   if (o->adaptive_tol > 0.0) {
     set_error("the adaptive sample count synchronizes after every round and cannot be captured");
     return FFC_ERR_INVALID_ARG;
+  }
+  if (o->separation > 0.0 && (!sk->sep_bits.ptr || sk->sep_words != (int)((t->N + 63) / 64))) {
+    set_error("separation: skeletonize once with a separation > 0 before capturing (its bitmaps are allocated then)");
+    return FFC_ERR_STATE;
   }
   hipStream_t st = (hipStream_t)stream;
   FFC_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));

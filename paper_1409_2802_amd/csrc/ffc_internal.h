@@ -190,6 +190,12 @@ struct ffc_skel {
   ffc::LearnedScratch learned;              // learned sampler (allocated on first use)
   int32_t fallbacks = 0;
   int32_t resampled = 0;                    // adaptive sample count: node redos
+  // Separation (opts.separation > 0): bit p of sep_bits[a * sep_words + p / 64]
+  // is set when tree position p is outside node a and separated from it;
+  // sep_pre[a * (sep_words + 1) + w] counts the set bits of words 0..w-1.
+  ffc::DevBuf<uint64_t> sep_bits;
+  ffc::DevBuf<int32_t> sep_pre;
+  int32_t sep_words = 0;
   hipStream_t last_stream = nullptr;
 };
 
@@ -218,6 +224,17 @@ ffc_status launch_sample_rows_into(const ffc_tree* t, int32_t* rows, int32_t* nr
 ffc_status launch_draw(const int32_t* nb, const int32_t* ne, int64_t N, bool inside, int32_t* rows, int32_t* nrows,
                        int cap, int first, int count, int s, uint64_t seed, uint32_t stream_or,
                        const unsigned char* mask, hipStream_t st);
+
+// Separated far sets (bits == nullptr: none). A draw outside node g then takes
+// the M = pre[g * (words + 1) + words] separated positions (all outside points
+// when M is 0), candidate t being the t-th set bit of g's bitmap.
+struct SepView {
+  const uint64_t* bits = nullptr;
+  const int32_t* pre = nullptr;
+  int words = 0;
+};
+ffc_status launch_sample_rows_sep(const ffc_tree* t, ffc_skel* sk, int first, int count, int s, uint64_t seed,
+                                  hipStream_t st);
 
 // Column lists of a level (sample.hip).
 ffc_status launch_level_columns(const ffc_tree* t, ffc_skel* sk, int first, int count, bool leaves,
@@ -354,6 +371,11 @@ ffc_status launch_ridge_leverage(double* B, int64_t m, int n, int count, double*
 // Far + near field evaluation (kblock.hip).
 ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision,
                            double* u, double* u_far, hipStream_t st);
+// Separation bitmaps and their word prefixes for every node (kblock.hip), and
+// the treecode evaluation that reads them (FFC_FP64 / FFC_FP32).
+ffc_status launch_separation(const ffc_tree* t, ffc_skel* sk, double xi, hipStream_t st);
+ffc_status launch_treecode(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, double* u,
+                           double* u_far, hipStream_t st);
 
 // Mixed-precision (bf16 hi/lo Gram on matrix cores) variants of the sampled
 // blocks, the evaluation and the direct sum for the Gaussian and polynomial

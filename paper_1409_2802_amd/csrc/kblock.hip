@@ -211,6 +211,177 @@ __global__ void __launch_bounds__(NT) k_evaluate(const double* __restrict__ Xt, 
   if (bad) flag_nonfinite(flag);
 }
 
+// ---------------------------------------------------------------------------
+// Separation (Section 2, eq. e:separated, with the source ball of Section 4.1):
+// tree position p is separated from node a when it lies outside a and
+// |x_p - c_a|^2 >= (xi rho_a)^2. One 64 x 64 tile covers 64 consecutive
+// positions (one bitmap word) against 64 nodes; the squared distances come
+// from the tile engine in FP64 and each wavefront packs its predicates with
+// ballots: lane 16 w' + tr of a wavefront holds row tr of column 4 w + w', so
+// the 16 bits of column tc for rows tr + 16 i sit at bits 16 (tc % 4) of the
+// ballot of (i, j).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NT) k_sep_bitmap(const double* __restrict__ Xt, int64_t N, int d,
+                                                   const double* __restrict__ centroid,
+                                                   const double* __restrict__ radius, const int32_t* __restrict__ nb,
+                                                   const int32_t* __restrict__ ne, int num_nodes, double xi,
+                                                   int words, int tiles_n, uint64_t* __restrict__ bits) {
+  __shared__ TileSmem<double> sm;
+  const int64_t r0 = (int64_t)(blockIdx.x / tiles_n) * BM;
+  const int c0 = (blockIdx.x % tiles_n) * BN;
+  double acc[4][4];
+  tile_accumulate<double, false>(Xt, IdxMap{nullptr, r0}, (int)min<int64_t>(BM, N - r0), centroid,
+                                 IdxMap{nullptr, c0}, num_nodes - c0, d, sm, acc);
+  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
+  const int sub = tc & 3;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = c0 + tc + 16 * j;
+    const bool col = c < num_nodes;
+    const double thr = col ? xi * radius[c] : 0.0;
+    const double thr2 = thr * thr;
+    const int b = col ? nb[c] : 0, e = col ? ne[c] : 0;
+    uint64_t word = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t p = r0 + tr + 16 * i;
+      const bool sep = col && p < N && (p < b || p >= e) && acc[i][j] >= thr2;
+      const uint64_t bal = __ballot(sep);
+      word |= ((bal >> (16 * sub)) & 0xFFFFull) << (16 * i);
+    }
+    if (col && tr == 0) bits[(int64_t)c * words + (r0 >> 6)] = word;
+  }
+}
+
+// Exclusive prefix of the set-bit counts over each node's words:
+// pre[a * (words + 1) + w] = bits set in words 0..w-1 (w = words: all of them).
+constexpr int kPreThreads = 256;
+__global__ void __launch_bounds__(kPreThreads) k_sep_prefix(const uint64_t* __restrict__ bits, int words,
+                                                            int32_t* __restrict__ pre) {
+  __shared__ int wsum[kPreThreads / 64];
+  const int a = blockIdx.x, tid = threadIdx.x;
+  const uint64_t* bw = bits + (int64_t)a * words;
+  int32_t* out = pre + (int64_t)a * (words + 1);
+  const int per = (words + kPreThreads - 1) / kPreThreads;
+  const int w0 = min(words, tid * per), w1 = min(words, w0 + per);
+  int cnt = 0;
+  for (int w = w0; w < w1; ++w) cnt += __popcll((unsigned long long)bw[w]);
+  const int lane = tid & 63, wid = tid >> 6;
+  int incl = cnt;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[wid] = incl;
+  __syncthreads();
+  int pos = incl - cnt;
+  for (int w = 0; w < wid; ++w) pos += wsum[w];
+  for (int w = w0; w < w1; ++w) {
+    out[w] = pos;
+    pos += __popcll((unsigned long long)bw[w]);
+  }
+  if (tid == kPreThreads - 1) out[words] = pos;
+}
+
+// Treecode evaluation with separation for a tile of 64 targets of one leaf.
+// The workgroup walks the tree depth first from the root's children with a
+// stack in LDS. Per node and target row the choice is: apply the node's
+// skeleton (the row reaches the node, the node does not contain it and the
+// separation bit is set), pass the row on (children, or a direct sum at a
+// leaf), or nothing (the row was served higher up). Bit l of arrive[row] says
+// whether the row reaches the node of level l on the current path; a node of
+// level l sets bit l + 1 for its children, and nodes visited before its second
+// child are all deeper, so that bit still holds when the second child is popped.
+template <typename T, bool DOT>
+__global__ void __launch_bounds__(NT) k_treecode(const double* __restrict__ Xt, int d, KParams kp, int depth,
+                                                 const int32_t* __restrict__ tile_leaf,
+                                                 const int32_t* __restrict__ tile_start,
+                                                 const int32_t* __restrict__ nb, const int32_t* __restrict__ ne,
+                                                 const double* __restrict__ q_tree,
+                                                 const int32_t* __restrict__ rank, const int32_t* __restrict__ skel,
+                                                 int r_cap, const double* __restrict__ qt,
+                                                 const uint64_t* __restrict__ sep_bits, int words,
+                                                 const int32_t* __restrict__ perm, double* __restrict__ u,
+                                                 double* __restrict__ u_far, unsigned int* flag) {
+  __shared__ TileSmem<T> sm;
+  __shared__ double red[16 * BM];
+  __shared__ double far_sum[BM], near_sum[BM];
+  __shared__ int stack[64];
+  __shared__ uint32_t arrive[BM];
+  __shared__ unsigned char take[BM];   // 1: skeleton sum, 2: passed on / direct sum, 0: neither
+  const int leaf = tile_leaf[blockIdx.x];
+  const int start = tile_start[blockIdx.x];
+  const int nrows = min(BM, ne[leaf] - start);
+  const IdxMap rmap{nullptr, start};
+  const int tid = threadIdx.x, tr = tid & 15;
+  bool bad = false;
+  double fpart[4] = {0.0, 0.0, 0.0, 0.0}, npart[4] = {0.0, 0.0, 0.0, 0.0};
+  if (tid < BM) arrive[tid] = tid < nrows ? 2u : 0u;   // every row reaches level 1
+  if (tid == 0) {
+    stack[0] = 2;
+    stack[1] = 1;
+  }
+  int sp = 2;   // the same in every thread
+  __syncthreads();
+  while (sp > 0) {
+    const int a = stack[--sp];
+    const int lev = 31 - __clz(a + 1);
+    const bool is_leaf = lev == depth;
+    const bool contains = ((leaf + 1) >> (depth - lev)) == a + 1;
+    int k = 0;
+    if (tid < BM) {
+      if ((arrive[tid] >> lev) & 1u) {
+        bool sep = false;
+        if (!contains) {
+          const int64_t p = start + tid;
+          sep = (sep_bits[(int64_t)a * words + (p >> 6)] >> (p & 63)) & 1ull;
+        }
+        k = sep ? 1 : 2;
+      }
+      take[tid] = (unsigned char)k;
+      if (!is_leaf) arrive[tid] = (arrive[tid] & ~(2u << lev)) | (k == 2 ? (2u << lev) : 0u);
+    }
+    const int any_far = __syncthreads_or(k == 1);
+    const int any_rest = __syncthreads_or(k == 2);
+    if (any_far && rank[a] > 0) {
+      double tmp[4] = {0.0, 0.0, 0.0, 0.0};
+      sum_over_sources<T, DOT>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)a * r_cap, 0}, rank[a],
+                               qt + (int64_t)a * r_cap, d, kp, sm, tmp, bad);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (take[tr + 16 * i] == 1) fpart[i] += tmp[i];
+    }
+    if (any_rest) {
+      if (is_leaf) {
+        const int lb = nb[a];
+        double tmp[4] = {0.0, 0.0, 0.0, 0.0};
+        sum_over_sources<T, DOT>(Xt, rmap, nrows, Xt, IdxMap{nullptr, lb}, ne[a] - lb, q_tree + lb, d, kp, sm, tmp,
+                                 bad);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (take[tr + 16 * i] == 2) npart[i] += tmp[i];
+      } else {
+        if (tid == 0) {   // right child below the left one: the left subtree is walked first
+          stack[sp] = 2 * a + 2;
+          stack[sp + 1] = 2 * a + 1;
+        }
+        sp += 2;
+      }
+    }
+    __syncthreads();
+  }
+  reduce_rows(fpart, red, far_sum);
+  reduce_rows(npart, red, near_sum);
+  if (threadIdx.x < nrows) {
+    const int pos = start + threadIdx.x;
+    const int ci = perm[pos];
+    const double f = far_sum[threadIdx.x];
+    u[ci] = f + near_sum[threadIdx.x];
+    if (u_far) u_far[ci] = f;
+  }
+  if (bad) flag_nonfinite(flag);
+}
+
 // Direct sum over all sources for a tile of 64 targets.
 template <typename T, bool DOT>
 __global__ void __launch_bounds__(NT) k_direct(const double* __restrict__ Y, int64_t m, const double* __restrict__ X,
@@ -319,6 +490,48 @@ ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams&
                        t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
                        sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->perm.ptr, u, u_far, device_flag());
     FFC_LAUNCH_CHECK("k_evaluate");
+    return FFC_OK;
+  });
+}
+
+ffc_status launch_separation(const ffc_tree* t, ffc_skel* sk, double xi, hipStream_t st) {
+  const int words = (int)((t->N + 63) / 64);
+  const size_t nn = (size_t)t->num_nodes;
+  if (sk->sep_words != words || sk->sep_bits.count != nn * words) {
+    FFC_TRY(sk->sep_bits.alloc(nn * words));
+    FFC_TRY(sk->sep_pre.alloc(nn * (words + 1)));
+    sk->sep_words = words;
+  }
+  const int tiles_n = (t->num_nodes + BN - 1) / BN;
+  const int64_t blocks = (int64_t)words * tiles_n;
+  hipLaunchKernelGGL(k_sep_bitmap, dim3((unsigned)blocks), dim3(NT), 0, st, t->Xt.ptr, t->N, t->d, t->centroid.ptr,
+                     t->radius.ptr, t->begin.ptr, t->end.ptr, t->num_nodes, xi, words, tiles_n, sk->sep_bits.ptr);
+  FFC_LAUNCH_CHECK("k_sep_bitmap");
+  hipLaunchKernelGGL(k_sep_prefix, dim3((unsigned)t->num_nodes), dim3(kPreThreads), 0, st, sk->sep_bits.ptr, words,
+                     sk->sep_pre.ptr);
+  FFC_LAUNCH_CHECK("k_sep_prefix");
+  return FFC_OK;
+}
+
+ffc_status launch_treecode(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, double* u,
+                           double* u_far, hipStream_t st) {
+  if (precision == FFC_MIXED_BF16X3) {
+    set_error("a treecode (separation > 0) evaluates in FFC_FP64 or FFC_FP32");
+    return FFC_ERR_INVALID_ARG;
+  }
+  if (!sk->sep_bits.ptr || sk->sep_words != (int)((t->N + 63) / 64) || t->depth > 30) {
+    set_error("separation bitmaps are missing");
+    return FFC_ERR_STATE;
+  }
+  const bool dot = kp.kind == FFC_POLYNOMIAL;
+  return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
+    using T = decltype(tv);
+    constexpr bool D = decltype(dv)::value;
+    hipLaunchKernelGGL((k_treecode<T, D>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
+                       t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
+                       sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, sk->sep_bits.ptr, sk->sep_words,
+                       t->perm.ptr, u, u_far, device_flag());
+    FFC_LAUNCH_CHECK("k_treecode");
     return FFC_OK;
   });
 }

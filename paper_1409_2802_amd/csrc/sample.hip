@@ -6,7 +6,10 @@
 // counter-based SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the value for
 // counter j is the first SplitMix64 output from state seed ^ (node << 32) ^ j,
 // and a uniform integer in [0, j] is the high 64 bits of u64 * (j + 1).
-// Candidate t maps to tree position t (t < begin) or t + node size.
+// Candidate t maps to tree position t (t < begin) or t + node size. With
+// separation the candidates are the node's separated points in ascending tree
+// order (a bitmap per node with a prefix count per 64-bit word): candidate t is
+// the t-th set bit, found by a binary search over the word prefixes.
 //
 // Two kernels implement the same draw. The bitmap kernel (used whenever the
 // bitmap of the complement fits the LDS budget) keeps the chosen set as bits;
@@ -26,21 +29,60 @@ __device__ inline uint64_t splitmix_first(uint64_t state) {
   return z ^ (z >> 31);
 }
 
+// Candidates of a draw: the separated points of the node when it has any
+// (bitmap words and their prefix counts), else the range or its complement.
+struct Candidates {
+  const uint64_t* bits = nullptr;   // non-null: separated candidates
+  const int32_t* pre = nullptr;
+  int words = 0;
+  int lo = 0, shift = 0;
+  __device__ inline int operator()(int t) const {
+    if (!bits) return t < lo ? t : t + shift;
+    int a = 0, z = words - 1;       // the last word whose prefix is <= t holds candidate t
+    while (a < z) {
+      const int mid = (a + z + 1) >> 1;
+      if (pre[mid] <= t) a = mid;
+      else z = mid - 1;
+    }
+    uint64_t w = bits[a];
+    for (int r = t - pre[a]; r > 0; --r) w &= w - 1;
+    return a * 64 + __ffsll((unsigned long long)w) - 1;
+  }
+};
+
+__device__ inline Candidates candidates(const SepView& sv, int node, int b, int e, int64_t N, bool inside,
+                                        int64_t& M) {
+  Candidates c;
+  c.lo = inside ? 0 : b;
+  c.shift = inside ? b : e - b;
+  M = inside ? (e - b) : N - (e - b);
+  if (sv.bits && !inside) {
+    const int32_t* pre = sv.pre + (int64_t)node * (sv.words + 1);
+    const int m = pre[sv.words];
+    if (m > 0) {
+      c.bits = sv.bits + (int64_t)node * sv.words;
+      c.pre = pre;
+      c.words = sv.words;
+      M = m;
+    }
+  }
+  return c;
+}
+
 __global__ void k_sample_rows(const int32_t* __restrict__ nb, const int32_t* __restrict__ ne, int64_t N, int first,
                               int s, int s_cap, int sort_n, uint64_t seed, uint32_t stream_or, int inside,
-                              const unsigned char* __restrict__ mask, int32_t* __restrict__ rows,
+                              const unsigned char* __restrict__ mask, SepView sv, int32_t* __restrict__ rows,
                               int32_t* __restrict__ nrows) {
   extern __shared__ int set[];   // sort_n ints (power of two >= s)
   const int node = first + blockIdx.x;
   const int lane = threadIdx.x;
   if (mask && !mask[node]) return;
   const int b = nb[node], e = ne[node];
-  const int64_t M = inside ? (e - b) : N - (e - b);
-  // Candidate t -> tree position: inside the range, or around it.
-  const int lo = inside ? 0 : b, shift = inside ? b : e - b;
+  int64_t M;
+  const Candidates cand = candidates(sv, node, b, e, N, inside != 0, M);
   int32_t* out = rows + (int64_t)node * s_cap;
   if (s >= M) {
-    for (int64_t i = lane; i < M; i += 64) out[i] = (int32_t)(i < lo ? i : i + shift);
+    for (int64_t i = lane; i < M; i += 64) out[i] = (int32_t)cand((int)i);
     if (lane == 0) nrows[node] = (int32_t)M;
     return;
   }
@@ -69,10 +111,7 @@ __global__ void k_sample_rows(const int32_t* __restrict__ nb, const int32_t* __r
       __syncthreads();
     }
   }
-  for (int i = lane; i < s; i += 64) {
-    const int t = set[i];
-    out[i] = t < lo ? t : t + shift;
-  }
+  for (int i = lane; i < s; i += 64) out[i] = cand(set[i]);
   if (lane == 0) nrows[node] = s;
 }
 
@@ -87,7 +126,7 @@ constexpr int kBitmapThreads = 256;
 __global__ void __launch_bounds__(kBitmapThreads)
 k_sample_rows_bitmap(const int32_t* __restrict__ nb, const int32_t* __restrict__ ne, int64_t N, int first, int s,
                      int s_cap, uint64_t seed, uint32_t stream_or, int inside,
-                     const unsigned char* __restrict__ mask, int32_t* __restrict__ rows,
+                     const unsigned char* __restrict__ mask, SepView sv, int32_t* __restrict__ rows,
                      int32_t* __restrict__ nrows) {
   extern __shared__ unsigned int bits[];            // nwords bitmap words, then s ints of t values
   __shared__ int wsum[kBitmapThreads / 64];
@@ -95,11 +134,12 @@ k_sample_rows_bitmap(const int32_t* __restrict__ nb, const int32_t* __restrict__
   const int tid = threadIdx.x;
   if (mask && !mask[node]) return;
   const int b = nb[node], e = ne[node];
-  const int M = inside ? e - b : (int)(N - (e - b));
-  const int lo = inside ? 0 : b, shift = inside ? b : e - b;
+  int64_t M64;
+  const Candidates cand = candidates(sv, node, b, e, N, inside != 0, M64);
+  const int M = (int)M64;
   int32_t* out = rows + (int64_t)node * s_cap;
   if (s >= M) {
-    for (int i = tid; i < M; i += kBitmapThreads) out[i] = i < lo ? i : i + shift;
+    for (int i = tid; i < M; i += kBitmapThreads) out[i] = cand(i);
     if (tid == 0) nrows[node] = M;
     return;
   }
@@ -167,8 +207,7 @@ k_sample_rows_bitmap(const int32_t* __restrict__ nb, const int32_t* __restrict__
     while (word) {
       const int bit = __ffs(word) - 1;
       word &= word - 1;
-      const int t = w * 32 + bit;
-      out[pos++] = t < lo ? t : t + shift;
+      out[pos++] = cand(w * 32 + bit);
     }
   }
   if (tid == 0) nrows[node] = s;
@@ -195,9 +234,10 @@ __global__ void k_level_columns(const int32_t* __restrict__ nb, const int32_t* _
 
 }  // namespace
 
-ffc_status launch_draw(const int32_t* nb, const int32_t* ne, int64_t N, bool inside, int32_t* rows, int32_t* nrows,
-                       int cap, int first, int count, int s, uint64_t seed, uint32_t stream_or,
-                       const unsigned char* mask, hipStream_t st) {
+namespace {
+ffc_status draw(const int32_t* nb, const int32_t* ne, int64_t N, bool inside, int32_t* rows, int32_t* nrows, int cap,
+                int first, int count, int s, uint64_t seed, uint32_t stream_or, const unsigned char* mask,
+                const SepView& sv, hipStream_t st) {
   if (count <= 0) return FFC_OK;
   if (s > cap) {
     set_error("row sample larger than its buffer");
@@ -207,7 +247,7 @@ ffc_status launch_draw(const int32_t* nb, const int32_t* ne, int64_t N, bool ins
   const size_t lds = (size_t)nwords * sizeof(unsigned int) + (size_t)s * sizeof(int);
   if (nwords <= kMaxBitmapWords && lds <= 64 * 1024) {
     hipLaunchKernelGGL(k_sample_rows_bitmap, dim3(count), dim3(kBitmapThreads), lds, st, nb, ne, N, first, s, cap,
-                       seed, stream_or, inside ? 1 : 0, mask, rows, nrows);
+                       seed, stream_or, inside ? 1 : 0, mask, sv, rows, nrows);
     FFC_LAUNCH_CHECK("k_sample_rows_bitmap");
     return FFC_OK;
   }
@@ -218,9 +258,27 @@ ffc_status launch_draw(const int32_t* nb, const int32_t* ne, int64_t N, bool ins
     return FFC_ERR_INVALID_ARG;
   }
   hipLaunchKernelGGL(k_sample_rows, dim3(count), dim3(64), (size_t)sort_n * sizeof(int), st, nb, ne, N, first, s, cap,
-                     sort_n, seed, stream_or, inside ? 1 : 0, mask, rows, nrows);
+                     sort_n, seed, stream_or, inside ? 1 : 0, mask, sv, rows, nrows);
   FFC_LAUNCH_CHECK("k_sample_rows");
   return FFC_OK;
+}
+}  // namespace
+
+ffc_status launch_draw(const int32_t* nb, const int32_t* ne, int64_t N, bool inside, int32_t* rows, int32_t* nrows,
+                       int cap, int first, int count, int s, uint64_t seed, uint32_t stream_or,
+                       const unsigned char* mask, hipStream_t st) {
+  return draw(nb, ne, N, inside, rows, nrows, cap, first, count, s, seed, stream_or, mask, SepView{}, st);
+}
+
+ffc_status launch_sample_rows_sep(const ffc_tree* t, ffc_skel* sk, int first, int count, int s, uint64_t seed,
+                                  hipStream_t st) {
+  if (!sk->sep_bits.ptr) {
+    set_error("separation bitmaps are missing");
+    return FFC_ERR_STATE;
+  }
+  const SepView sv{sk->sep_bits.ptr, sk->sep_pre.ptr, sk->sep_words};
+  return draw(t->begin.ptr, t->end.ptr, t->N, false, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, first, count, s, seed,
+              0u, nullptr, sv, st);
 }
 
 ffc_status launch_sample_rows_into(const ffc_tree* t, int32_t* rows, int32_t* nrows, int cap, int first, int count,

@@ -55,7 +55,7 @@ class SkelOptsC(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_rank", ctypes.c_int32), ("num_samples", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("sampler", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("proposal", ctypes.c_void_p), ("fallback_tol", ctypes.c_double), ("pool_factor", ctypes.c_int32),
-                ("adaptive_tol", ctypes.c_double), ("max_samples", ctypes.c_int32)]
+                ("adaptive_tol", ctypes.c_double), ("max_samples", ctypes.c_int32), ("separation", ctypes.c_double)]
 
 
 class StatsC(ctypes.Structure):
@@ -258,17 +258,19 @@ def skeletonize(tree: Tree, kernel: Kernel, tol: float, max_rank: int, num_sampl
                 precision: int = FP64, seed: int = 0, reuse: Skeletons | None = None,
                 proposal: "Proposal | None" = None, fallback_tol: float = 0.0, pool_factor: int = 0,
                 adaptive_tol: float = 0.0, max_samples: int = 0, sampler: int | None = None,
-                stream=None) -> Skeletons:
+                separation: float = 0.0, stream=None) -> Skeletons:
     """Skeletonize every non-root node; with `proposal` the rows come from the learned sampler (or `sampler`:
     SAMPLE_DISTANCE / SAMPLE_NEAREST for the paper's heuristics on the same candidate pool), with
     `adaptive_tol` > 0 a node's row count doubles until its held-out error estimate is at most adaptive_tol
-    (or `max_samples` is reached)."""
+    (or `max_samples` is reached); with `separation` xi > 0 the rows come from each node's separated points
+    and evaluate_sum runs the treecode."""
     if sampler is None:
         sampler = SAMPLE_LEARNED if proposal is not None else SAMPLE_UNIFORM
     opts = SkelOptsC(tol=tol, max_rank=max_rank, num_samples=num_samples, precision=precision,
                      sampler=sampler, seed=seed,
                      proposal=proposal.handle if proposal is not None else None, fallback_tol=fallback_tol,
-                     pool_factor=pool_factor, adaptive_tol=adaptive_tol, max_samples=max_samples)
+                     pool_factor=pool_factor, adaptive_tol=adaptive_tol, max_samples=max_samples,
+                     separation=separation)
     h = ctypes.c_void_p(reuse.handle.value if reuse is not None else None)
     k = kernel.c_struct()
     _check(load_library().ffc_skeletonize_nodes(tree.handle, ctypes.byref(k), ctypes.byref(opts), _stream(stream),
@@ -284,13 +286,13 @@ class StepGraph:
     def __init__(self, tree: Tree, sk: Skeletons, kernel: Kernel, q: torch.Tensor, u: torch.Tensor,
                  u_far: torch.Tensor | None, stream, tol: float, max_rank: int, num_samples: int = 0,
                  precision: int = FP64, seed: int = 0, proposal: "Proposal | None" = None, pool_factor: int = 0,
-                 sampler: int | None = None):
+                 sampler: int | None = None, separation: float = 0.0):
         if sampler is None:
             sampler = SAMPLE_LEARNED if proposal is not None else SAMPLE_UNIFORM
         opts = SkelOptsC(tol=tol, max_rank=max_rank, num_samples=num_samples, precision=precision,
                          sampler=sampler, seed=seed,
                          proposal=proposal.handle if proposal is not None else None, fallback_tol=0.0,
-                         pool_factor=pool_factor)
+                         pool_factor=pool_factor, separation=separation)
         self._keep = (tree, sk, q, u, u_far, proposal)   # the graph holds their device pointers
         k = kernel.c_struct()
         h = ctypes.c_void_p()

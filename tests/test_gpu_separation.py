@@ -1,0 +1,143 @@
+"""Separated skeletonization and the treecode on the GPU against the oracle:
+rows bit-exact for every node whose separated far set is unambiguous (no
+point within a relative 1e-9 of the threshold), skeletons and P where the
+pivots are clear, the treecode sum to the FP64 bar when every node matched;
+an infinite separation giving the plain rows and the direct sum; graph
+replays equal to the eager step; option validation."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import separation as S
+from oracle.direct import direct_sum
+from oracle.kernels import GAUSSIAN, LAPLACE, POLYNOMIAL
+from oracle.tree import build_tree as o_build_tree
+from paper_1409_2802_amd import workloads as W
+from tests._parity import FP64_REL, gkernel, okernel, rel, unambiguous
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ffc():
+    from paper_1409_2802_amd import ffc as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    m.load_library()
+    return m
+
+
+def clear_far_set(Xt, ot, a, xi, margin=1e-9):
+    """No point outside node a lies within a relative margin of its separation threshold."""
+    b, e = int(ot.begin[a]), int(ot.end[a])
+    diff = Xt - ot.centroid[a]
+    d2 = np.einsum("ij,ij->i", diff, diff)
+    thr2 = (xi * ot.radius[a]) ** 2
+    out = np.r_[0:b, e:ot.N]
+    return bool(np.all(np.abs(d2[out] - thr2) > margin * max(thr2, 1e-300)))
+
+
+CASES = [
+    (GAUSSIAN, dict(h=1.0), 1.0, 3000, 4, 100),
+    (LAPLACE, dict(), 2.0, 3000, 4, 100),
+    (LAPLACE, dict(), 1.5, 2500, 5, 160),
+    (POLYNOMIAL, dict(h=4.0, p=3), 1.2, 2000, 6, 128),
+]
+
+
+@pytest.mark.parametrize("kind,kw,xi,n,d,leaf", CASES)
+def test_separated_skeletons_and_treecode_match_oracle(ffc, kind, kw, xi, n, d, leaf):
+    X = W.gaussian_mixture(n, d, k=6, box=5.0, std=0.7, seed=3)
+    gk, ok = gkernel(kind, **kw), okernel(kind, **kw)
+    t = ffc.build_tree(X, leaf)
+    ot = o_build_tree(X, leaf)
+    Xt = X[ot.perm]
+    sk = ffc.skeletonize(t, gk, tol=1e-7, max_rank=24, num_samples=64, seed=3, separation=xi)
+    osk = S.skeletonize_separated(X, ot, ok, 1e-7, 24, 64, 3, xi)
+    exact, checked, clear = 0, 0, 0
+    for level in range(ot.depth, 0, -1):
+        for a in ot.level_nodes(level):
+            g, o = sk.node(a), osk.nodes[a]
+            if not np.array_equal(g["cols"], o.cols):
+                continue                    # an ambiguous choice below changed the columns
+            checked += 1
+            if not clear_far_set(Xt, ot, a, xi):
+                continue
+            clear += 1
+            np.testing.assert_array_equal(g["rows"], o.rows, err_msg=f"node {a}")
+            if not unambiguous(o, 1e-7):
+                continue
+            assert g["rank"] == o.rank, f"node {a}"
+            np.testing.assert_array_equal(g["skel"], o.skel)
+            np.testing.assert_allclose(g["P"], o.P, atol=1e-8 * max(1.0, np.abs(o.P).max()))
+            exact += 1
+    assert checked == ot.num_nodes - 1
+    assert exact >= 0.8 * checked, (exact, clear, checked)
+    # Some nodes must draw from a proper subset of their far field.
+    assert any(0 < len(S.separated_far_set(Xt, ot, a, xi)) < ot.N - (ot.end[a] - ot.begin[a])
+               for a in range(1, ot.num_nodes))
+    q = W.charges(ot.N, seed=1)
+    u, uf = ffc.evaluate_sum(t, sk, gk, q)
+    ou, ouf = S.treecode_evaluate(X, ot, osk, ok, q, xi)
+    if exact == checked:
+        assert rel(u.cpu().numpy(), ou) < FP64_REL
+        assert rel(uf.cpu().numpy(), ouf) < FP64_REL
+        u32, _ = ffc.evaluate_sum(t, sk, gk, q, precision=ffc.FP32)
+        assert rel(u32.cpu().numpy(), ou) < 1e-4
+
+
+def test_infinite_separation_is_direct_sum(ffc):
+    X = W.gaussian_mixture(2100, 5, k=6, box=5.0, std=0.7, seed=5)
+    gk, ok = gkernel(GAUSSIAN, h=0.8), okernel(GAUSSIAN, h=0.8)
+    t = ffc.build_tree(X, 120)
+    sk = ffc.skeletonize(t, gk, tol=1e-6, max_rank=16, num_samples=48, seed=2, separation=1e300)
+    plain = ffc.skeletonize(t, gk, tol=1e-6, max_rank=16, num_samples=48, seed=2)
+    for a in range(1, t.num_nodes):
+        np.testing.assert_array_equal(sk.node(a)["rows"], plain.node(a)["rows"])
+    q = W.charges(2100, seed=3)
+    u, uf = ffc.evaluate_sum(t, sk, gk, q)
+    assert torch.count_nonzero(uf).item() == 0
+    ref = direct_sum(X, X, q, ok)
+    assert rel(u.cpu().numpy(), ref) < 1e-12
+
+
+def test_separated_graph_replays(ffc):
+    X = W.gaussian_mixture(4096, 4, k=6, box=5.0, std=0.7, seed=7)
+    gk = gkernel(LAPLACE)
+    t = ffc.build_tree(X, 128)
+    kw = dict(tol=1e-7, max_rank=24, num_samples=64, seed=4, separation=2.0)
+    q = torch.as_tensor(W.charges(4096, seed=2), device="cuda")
+    stream = torch.cuda.Stream()
+    with pytest.raises(ffc.FfcError) as e:       # bitmaps not yet allocated for this handle
+        fresh = ffc.skeletonize(t, gk, tol=1e-7, max_rank=24, num_samples=64, seed=4)
+        ffc.StepGraph(t, fresh, gk, q, torch.empty_like(q), None, stream, **kw)
+    assert e.value.code == ffc.FFC_ERR_STATE
+    sk = ffc.skeletonize(t, gk, **kw)
+    eager, _ = ffc.evaluate_sum(t, sk, gk, q)
+    eager = eager.clone()
+    u = torch.empty_like(q)
+    g = ffc.StepGraph(t, sk, gk, q, u, None, stream, **kw)
+    for _ in range(3):
+        u.fill_(0.0)
+        torch.cuda.synchronize()
+        g.launch(stream)
+        stream.synchronize()
+        assert torch.equal(u, eager)
+        _ = (q * 2.0).sum().item()            # eager work between replays
+
+
+def test_separation_option_validation(ffc):
+    X = W.uniform_cube(1024, 4, seed=0)
+    t = ffc.build_tree(X, 128)
+    gk = gkernel(GAUSSIAN, h=0.5)
+    for kw, msg in ((dict(separation=-1.0), ">= 0"), (dict(separation=float("nan")), ">= 0"),
+                    (dict(separation=1.0, adaptive_tol=1e-3), "uniform sampler"),
+                    (dict(separation=1.0, sampler=ffc.SAMPLE_NEAREST), "uniform sampler")):
+        with pytest.raises(ffc.FfcError) as e:
+            ffc.skeletonize(t, gk, tol=1e-6, max_rank=16, num_samples=32, **kw)
+        assert e.value.code == ffc.FFC_ERR_INVALID_ARG and msg in str(e.value)
+    sk = ffc.skeletonize(t, gk, tol=1e-6, max_rank=16, num_samples=32, separation=1.0)
+    with pytest.raises(ffc.FfcError) as e:
+        ffc.evaluate_sum(t, sk, gk, W.charges(1024, seed=1), precision=ffc.MIXED_BF16X3)
+    assert e.value.code == ffc.FFC_ERR_INVALID_ARG and "FFC_FP64 or FFC_FP32" in str(e.value)
