@@ -64,6 +64,9 @@ WORKLOADS = {
     "adaptive4": dict(N=65536, d=4, data="uniform_cube", kernel="gaussian", h=0.3, leaf=512, max_rank=256,
                       num_samples=64, adaptive_tol=1e-2, max_samples=512, tol=1e-7, precision="fp64",
                       text="N=65536 d=4 uniform cube, Gaussian h=0.3, adaptive sample count"),
+    "separated3": dict(N=65536, d=3, data="normal", kernel="laplace", leaf=256, max_rank=128, num_samples=256,
+                       tol=1e-6, precision="fp64", separation=2.0,
+                       text="N=65536 d=3 N(0,I), Laplace 1/|x-y|, treecode with separation xi=2"),
     "learned64": dict(N=262144, d=64, **SUB, kernel="gaussian", h=1.0, leaf=1024, max_rank=256, num_samples=512,
                       tol=1e-6, precision="mixed", learned=True, train_blocks=2000, block_cols=512,
                       block_rows=4096, epochs=2, batch=4096, lr=1e-3, eps=1e-4, pool_factor=8,
@@ -80,7 +83,8 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--train-blocks", type=int, default=None, help="learned64: training blocks")
     ap.add_argument("--compare", action="store_true",
-                    help="learned64: uniform vs learned at 1x, 2x, 4x rows; adaptive4: fixed row counts")
+                    help="learned64: every sampler at 1x, 2x, 4x rows; adaptive4: fixed row counts; "
+                         "separated3: separation 0, 1, 2, 4")
     ap.add_argument("--variants", default="fp32,mixed",
                     help="other precisions timed on the same workload, each judged against the FP64 path")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -100,6 +104,8 @@ def make_inputs(w):
         X = W.low_intrinsic(w["N"], w["d"], di=w["di"], noise=w["noise"], seed=0)
     elif w["data"] == "uniform_cube":
         X = W.uniform_cube(w["N"], w["d"], seed=0)
+    elif w["data"] == "normal":
+        X = W.normal(w["N"], w["d"], seed=0)
     else:
         X = W.highdim_clusters(w["N"], w["d"], k=w["clusters"], offset_norm=w["offset"], seed=0)
     q = W.charges(w["N"], seed=1)
@@ -164,6 +170,7 @@ def cpu_baseline(w, X, budget_s):
     from threadpoolctl import threadpool_limits
 
     from oracle.kernels import Kernel as OKernel
+    from oracle.separation import separated_rows
     from oracle.skeleton import skeletonize_node
     from oracle.tree import build_tree as o_build_tree
     kind, kw = kernel_args(w)
@@ -180,6 +187,9 @@ def cpu_baseline(w, X, budget_s):
                 from oracle.adaptive import adaptive_node
                 adaptive_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], w["max_samples"], 0,
                               w["adaptive_tol"])
+            elif w.get("separation", 0.0) > 0:
+                rows = separated_rows(Xt, ot, a, w["num_samples"], 0, w["separation"])
+                skeletonize_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], 0, rows=rows)
             else:
                 skeletonize_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], 0)
             done += 1
@@ -188,22 +198,67 @@ def cpu_baseline(w, X, budget_s):
         dt = time.perf_counter() - t0
     rows = (f"{w['num_samples']} sampled rows doubled up to {w['max_samples']} by the adaptive rule" if adaptive
             else f"{w['num_samples']} sampled rows")
+    if w.get("separation", 0.0) > 0:
+        rows += f" from the points separated by xi={w['separation']}"
     return {"value": done / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
             "sample": f"{done} leaf nodes of the same tree ({w['leaf']} points, {rows} each, FP64), single thread, "
                       f"{dt:.1f} s"}
 
 
 def oracle_far_check(w, X, q, u_far_gpu, count=256):
-    """Far-field relative error of the GPU result against the oracle's exact sum on sampled targets."""
+    """Far-field relative error of the GPU result against the oracle's exact sum on sampled targets (with
+    separation: the exact sum over the nodes the oracle's treecode applies to each target)."""
     from oracle.evaluate import exact_far_field, relative_error
     from oracle.kernels import Kernel as OKernel
+    from oracle.kernels import kernel_matrix
+    from oracle.separation import interaction_lists
     from oracle.tree import build_tree as o_build_tree
     from paper_1409_2802_amd import workloads as W
     kind, kw = kernel_args(w)
+    ok = OKernel(kind, **kw)
     ot = o_build_tree(X, w["leaf"])
     tg = W.subset(w["N"], count, seed=2)
-    ex = exact_far_field(X, ot, OKernel(kind, **kw), q, tg)
+    if w.get("separation", 0.0) > 0:
+        Xt, qt = X[ot.perm], q[ot.perm]
+        inv = np.empty(ot.N, dtype=np.int64)
+        inv[ot.perm] = np.arange(ot.N)
+        far, _ = interaction_lists(Xt, ot, w["separation"])
+        ex = np.zeros(len(tg))
+        for a, T in far.items():
+            hit = np.flatnonzero(np.isin(inv[tg], T))
+            if len(hit):
+                b, e = int(ot.begin[a]), int(ot.end[a])
+                ex[hit] += kernel_matrix(Xt[inv[tg[hit]]], Xt[b:e], ok) @ qt[b:e]
+    else:
+        ex = exact_far_field(X, ot, ok, q, tg)
     return relative_error(u_far_gpu[tg], ex)
+
+
+def treecode_work(arr, ranks, xi, Xt):
+    """Kernel evaluations of one treecode evaluation: skeleton sums of the applied nodes plus the direct leaf
+    sums, from the traversal of every target (the separation test on the tree's centroids and radii)."""
+    begin, end, cen, rad = arr["begin"], arr["end"], arr["centroid"], arr["radius"]
+    num_nodes = len(begin)
+    depth = int(np.log2(num_nodes + 1)) - 1
+    N = len(Xt)
+    pos = np.arange(N)
+    arrive = {1: pos, 2: pos}
+    far_evals = near_evals = 0.0
+    for a in range(1, num_nodes):
+        A = arrive.pop(a)
+        lev = int(np.log2(a + 1))
+        b, e = int(begin[a]), int(end[a])
+        diff = Xt[A] - cen[a]
+        thr = xi * rad[a]
+        sep = ((A < b) | (A >= e)) & (np.einsum("ij,ij->i", diff, diff) >= thr * thr)
+        far_evals += float(sep.sum()) * ranks[a]
+        rest = A[~sep]
+        if lev == depth:
+            near_evals += float(len(rest)) * (e - b)
+        else:
+            arrive[2 * a + 1] = rest
+            arrive[2 * a + 2] = rest
+    return far_evals + near_evals, near_evals
 
 
 def main():
@@ -271,10 +326,10 @@ def main():
         print(f"[bench] trained: {json.dumps(training)}", file=sys.stderr, flush=True)
 
     def step(sk, s=w["num_samples"], mr=w["max_rank"], prop=proposal, p=prec, out=(u, uf),
-             adaptive=w.get("adaptive_tol", 0.0), sampler=None):
+             adaptive=w.get("adaptive_tol", 0.0), sampler=None, xi=w.get("separation", 0.0)):
         sk = ffc.skeletonize(tree, k, tol=w["tol"], max_rank=mr, num_samples=s, precision=p, seed=0,
                              reuse=sk, proposal=prop, pool_factor=w.get("pool_factor", 0), adaptive_tol=adaptive,
-                             max_samples=w.get("max_samples", 0), sampler=sampler)
+                             max_samples=w.get("max_samples", 0), sampler=sampler, separation=xi)
         ffc.evaluate_sum_into(tree, sk, k, qd, out[0], out[1], precision=p)
         return sk
 
@@ -294,7 +349,7 @@ def main():
         if use_graph:
             graph = ffc.StepGraph(tree, sk, k, qd, out[0], out[1], st, tol=w["tol"], max_rank=w["max_rank"],
                                   num_samples=w["num_samples"], precision=p, seed=0, proposal=proposal,
-                                  pool_factor=w.get("pool_factor", 0))
+                                  pool_factor=w.get("pool_factor", 0), separation=w.get("separation", 0.0))
             graph.launch(st)
         st.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -339,7 +394,7 @@ def main():
         gstream.wait_stream(torch.cuda.current_stream())
         graph = ffc.StepGraph(tree, sk, k, qd, u, uf, gstream, tol=w["tol"], max_rank=w["max_rank"],
                               num_samples=w["num_samples"], precision=prec, seed=0, proposal=proposal,
-                              pool_factor=w.get("pool_factor", 0))
+                              pool_factor=w.get("pool_factor", 0), separation=w.get("separation", 0.0))
         for _ in range(max(1, args.warmup)):
             graph.launch(gstream)
         gstream.synchronize()
@@ -364,8 +419,13 @@ def main():
         ranks[a] = nodes[a]["rank"]
     sizes = arr["end"] - arr["begin"]
     leaves = range((1 << tree.depth) - 1, tree.num_nodes)
-    eval_evals = float(sum(sizes[a] ** 2 for a in leaves))
-    eval_evals += float(sum(sizes[a + 1 if a % 2 else a - 1] * ranks[a] for a in range(1, tree.num_nodes)))
+    xi = w.get("separation", 0.0)
+    if xi > 0:
+        Xt_h = X[arr["perm"]]
+        eval_evals, near_evals = treecode_work(arr, ranks, xi, Xt_h)
+    else:
+        eval_evals = float(sum(sizes[a] ** 2 for a in leaves))
+        eval_evals += float(sum(sizes[a + 1 if a % 2 else a - 1] * ranks[a] for a in range(1, tree.num_nodes)))
     skel_evals = st["kernel_evals"]
     nodes_per_s = st["num_nodes"] / (ms_step * 1e-3)
     evals_per_s = (skel_evals + eval_evals) / (ms_step * 1e-3)
@@ -423,7 +483,9 @@ def main():
         roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = {"cpqr": "k_cpqr_coop", "solve": "k_coop_setup + k_diag_inv + k_id_solve_mfma",
                       "kblock": "k_level_kblock",
-                      "evaluate": "k_evaluate", "sample": "k_sample_rows_bitmap", "upward": "k_upward",
+                      "evaluate": "k_treecode" if xi > 0 else "k_evaluate",
+                      "sample": "k_sep_bitmap + k_sep_prefix + k_sample_rows_bitmap" if xi > 0
+                      else "k_sample_rows_bitmap", "upward": "k_upward",
                       "proposal": "k_geometry + k_features + k_mlp_score + k_select_rows"}.get(dom, dom)
     if dom == "cpqr":
         roof["traffic"] = measured_traffic(args.workload, pname, "k_cpqr_coop")
@@ -443,7 +505,7 @@ def main():
                                f"max_rank={w['max_rank']}, tol={w['tol']}",
                    "N": w["N"], "d": w["d"], "leaf_size": w["leaf"], "num_samples": w["num_samples"],
                    "max_rank": w["max_rank"], "tol": w["tol"], "precision": pname,
-                   "sampler": "learned" if proposal is not None else "uniform"},
+                   "sampler": "learned" if proposal is not None else "uniform", "separation": xi},
         "kernel_evals_per_s": evals_per_s,
         "skeleton_kernel_evals": skel_evals, "evaluate_kernel_evals": eval_evals,
         "ranks": {"min": st["rank_min"], "mean": st["rank_mean"], "max": st["rank_max"],
@@ -482,6 +544,28 @@ def main():
                 cmp.append(row)
                 print(f"[bench] fixed rows {row}", file=sys.stderr, flush=True)
             out["adaptive"]["fixed_rows"] = cmp
+    if args.compare and xi > 0:
+        # Separation sweep on the same tree: error of the whole sum against the exact one, the share of the
+        # sum carried by skeletons, and one eager step.
+        cmp = []
+        for xs in (0.0, 1.0, 2.0, 4.0):
+            skc = step(None, xi=xs)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            skc = step(skc, xi=xs)
+            e1.record()
+            torch.cuda.synchronize()
+            uh, ufh = u.cpu().numpy(), uf.cpu().numpy()
+            fe = ud_h - (uh - ufh)
+            row = {"separation": xs, "ms_per_step": e0.elapsed_time(e1),
+                   "e_total_vs_exact": float(np.linalg.norm(uh - ud_h) / np.linalg.norm(ud_h)),
+                   "e_far_vs_exact": float(np.linalg.norm(ufh - fe) / max(np.linalg.norm(fe), 1e-300)),
+                   "far_share": float(np.linalg.norm(ufh) / np.linalg.norm(uh)),
+                   "rank_mean": skc.stats()["rank_mean"]}
+            cmp.append(row)
+            print(f"[bench] separation {row}", file=sys.stderr, flush=True)
+        out["separation_sweep"] = cmp
     if args.compare and proposal is not None:
         # Far-field error of every sampler at 1x, 2x and 4x the rank cap, and the time of one eager step:
         # uniform, the learned proposal, and the paper's distance and nearest-neighbour heuristics (on the

@@ -72,6 +72,7 @@ def test_separated_skeletons_and_treecode_match_oracle(ffc, kind, kw, xi, n, d, 
             np.testing.assert_array_equal(g["skel"], o.skel)
             np.testing.assert_allclose(g["P"], o.P, atol=1e-8 * max(1.0, np.abs(o.P).max()))
             exact += 1
+    print(f"nodes: {checked} compared, {clear} with a clear far set, {exact} exact")
     assert checked == ot.num_nodes - 1
     assert exact >= 0.8 * checked, (exact, clear, checked)
     # Some nodes must draw from a proper subset of their far field.
