@@ -45,20 +45,28 @@ __device__ inline void tile_accumulate(const double* __restrict__ Y, IdxMap rows
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
   for (int k0 = 0; k0 < d; k0 += KC) {
+    const int kc = min(KC, d - k0);   // dimensions present in this chunk
+    // Stage 64 rows x kc dimensions: element e is row e >> sh, dimension
+    // e & (2^sh - 1) with 2^sh the power of two >= kc, so a chunk of few
+    // dimensions takes few passes and consecutive lanes still read consecutive
+    // coordinates of a row. Dimensions >= kc are never read below.
+    const int sh = 32 - __clz(kc - 1);
 #pragma unroll
-    for (int e = tid; e < BM * KC; e += NT) {
-      const int r = e / KC, kk = e % KC;
-      const int k = k0 + kk;
-      T yv = T(0), xv = T(0);
-      if (k < d) {
-        if (r < nrows) yv = (T)Y[rows(r) * d + k];
-        if (r < ncols) xv = (T)X[cols(r) * d + k];
+    for (int it = 0; it < BM * KC / NT; ++it) {
+      const int e = tid + it * NT;
+      if (e < (BM << sh)) {
+        const int r = e >> sh, kk = e & ((1 << sh) - 1);
+        if (kk < kc) {
+          const int k = k0 + kk;
+          T yv = T(0), xv = T(0);
+          if (r < nrows) yv = (T)Y[rows(r) * d + k];
+          if (r < ncols) xv = (T)X[cols(r) * d + k];
+          sm.ys[kk][r] = yv;
+          sm.xs[kk][r] = xv;
+        }
       }
-      sm.ys[kk][r] = yv;
-      sm.xs[kk][r] = xv;
     }
     __syncthreads();
-    const int kc = min(KC, d - k0);   // dimensions present in this chunk
 #pragma unroll 8
     for (int kk = 0; kk < kc; ++kk) {
       T a[4], b[4];
