@@ -21,9 +21,9 @@
  *    before anything is launched.
  *  - Handles (ffc_tree, ffc_skel) are opaque, owned by the library and released
  *    with ffc_free_tree / ffc_free_skel.
- *  - Kernel evaluations that are not finite (for instance the Laplace kernel
- *    overflowing at tiny distances) raise a device flag that ffc_check_device
- *    reports as FFC_ERR_NONFINITE.
+ *  - Kernel values that are not finite (for instance the Laplace kernel
+ *    overflowing at tiny distances), and kernel sums that are not, raise a
+ *    device flag that ffc_check_device reports as FFC_ERR_NONFINITE.
  */
 #ifndef FFC_H
 #define FFC_H
@@ -366,7 +366,7 @@ ffc_status ffc_proposal_training_set(const ffc_tree* t, const ffc_kernel* k, con
                                      void* stream);
 
 /* Synchronizes `stream` and reports (then clears) the device error flag:
- * FFC_ERR_NONFINITE if a kernel value was not finite since the last check,
+ * FFC_ERR_NONFINITE if a kernel value or sum was not finite since the last check,
  * FFC_ERR_HIP if a bounded wait inside the QR kernel gave up (its results
  * are then invalid). */
 ffc_status ffc_check_device(void* stream);

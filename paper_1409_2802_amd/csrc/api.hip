@@ -85,7 +85,7 @@ KParams make_kparams(const ffc_kernel& k, int d) {
   p.neg_inv_2h2 = k.kind == FFC_LAPLACE ? 0.0 : -1.0 / (2.0 * k.h * k.h);
   p.lap_expo = (2.0 - d) / 2.0;
   p.lap_small = k.kind == FFC_LAPLACE && d <= 7;
-  p.lap_m = (d - 2) / 2;
+  p.lap_m = (d & 1) ? d - 2 : (d - 2) / 2;
   p.lap_odd = d & 1;
   return p;
 }

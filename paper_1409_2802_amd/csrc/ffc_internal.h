@@ -56,7 +56,7 @@ struct KParams {
   double c;        // polynomial constant
   double neg_inv_2h2;  // -1 / (2 h^2)
   double lap_expo;     // (2 - d) / 2
-  // Laplace for d <= 7: r^(2-d) = 1 / ((r^2)^m * (odd ? sqrt(r^2) : 1)), m = (d - 2) / 2 rounded down.
+  // Laplace for d <= 7: r^(2-d) = (1/r)^m for odd d (m = d - 2), (1/r^2)^m for even d (m = (d - 2) / 2).
   int lap_small;
   int lap_m;
   int lap_odd;

@@ -26,14 +26,26 @@ namespace {
 
 using namespace tile;
 
-// The Laplace kernel r^(2-d) of r2 = r^2 > 0. Up to d = 7 it is a reciprocal of
-// at most two products and a square root (all correctly rounded), several
-// times cheaper than the general power, which serves larger d.
+// The Laplace kernel r^(2-d) of r2 = r^2 > 0. Up to d = 7 it is a small power
+// of y = 1/r (odd d: y^(d-2)) or of z = 1/r^2 (even d: z^((d-2)/2)), each from
+// the hardware estimate refined by two Newton steps (y <- y + y (1 - r2 y^2) / 2,
+// z <- z + z (1 - r2 z)), a few times cheaper than the general power, which
+// serves larger d and r2 below 2^-900 (where the estimate's range ends).
 __device__ inline double laplace_of_r2(double r2, const KParams& kp) {
-  if (kp.lap_small) {
-    double den = kp.lap_m == 0 ? 1.0 : (kp.lap_m == 1 ? r2 : r2 * r2);
-    if (kp.lap_odd) den *= sqrt(r2);
-    return 1.0 / den;
+  if (kp.lap_small && r2 > 0x1p-900) {
+    double b;
+    if (kp.lap_odd) {
+      b = __builtin_amdgcn_rsq(r2);
+      b = fma(0.5 * b, fma(-r2, b * b, 1.0), b);
+      b = fma(0.5 * b, fma(-r2, b * b, 1.0), b);
+    } else {
+      b = __builtin_amdgcn_rcp(r2);
+      b = fma(b, fma(-r2, b, 1.0), b);
+      b = fma(b, fma(-r2, b, 1.0), b);
+    }
+    double v = b;
+    for (int i = 1; i < kp.lap_m; ++i) v *= b;
+    return v;
   }
   return pow(r2, kp.lap_expo);
 }
@@ -153,14 +165,14 @@ __device__ inline void sum_over_sources(const double* __restrict__ Y, IdxMap row
       if (c < ncols) {
         const double qj = q[c];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const double v = kfun<DOT>(acc[i][j], kp);
-          bad |= !isfinite(v);
-          part[i] = fma(v, qj, part[i]);
-        }
+        for (int i = 0; i < 4; ++i) part[i] = fma(kfun<DOT>(acc[i][j], kp), qj, part[i]);
       }
     }
   }
+  // A kernel value that is not finite leaves its partial sum not finite
+  // (q = 0 gives NaN), so one test per row after the loop finds it.
+#pragma unroll
+  for (int i = 0; i < 4; ++i) bad |= !isfinite(part[i]);
 }
 
 // Fixed-order reduction of part[] across the 16 column threads of each row.

@@ -66,3 +66,21 @@ def test_sampled_block_fp64(ffc, name, N, d, s, n):
     Xt = X[perm]
     Ko = kernel_matrix(Xt[rows], Xt[cols], okernel(kind, **kw))
     np.testing.assert_allclose(Kg, Ko, rtol=1e-12, atol=0)
+
+
+def test_nonfinite_kernel_value_sets_the_flag(ffc):
+    # d = 7: r^-5 overflows for r = 1e-70 (1e350); the flag is raised once and cleared by the check.
+    ffc.check_device()
+    X = W.normal(40, 7, seed=8)
+    X[0] = 0.0
+    X[1] = 0.0
+    X[1, 0] = 1e-70
+    q = W.charges(40, seed=9)
+    k = gkernel(1)
+    ffc.direct_sum(X, X, q, k)
+    with pytest.raises(ffc.FfcError) as e:
+        ffc.check_device()
+    assert e.value.code == ffc.FFC_ERR_NONFINITE
+    ffc.check_device()
+    ffc.direct_sum(X[2:], X[2:], q[2:], k)     # well-separated points: no flag
+    ffc.check_device()
