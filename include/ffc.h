@@ -199,6 +199,26 @@ ffc_status ffc_evaluate_sum(const ffc_tree* t, const ffc_skel* sk, const ffc_ker
                             const double* q_dev, double* u_dev, double* u_far_dev,
                             int32_t precision, void* stream);
 
+/* u = K q by the FMM-style scheme that Section 2 sets beside the treecode:
+ * incoming representations from the same skeletons (for the symmetric kernel on
+ * one point set, node b's ID gives K(cols_b, S) ~ P_b^T K(J_b, S) for sources
+ * S in its separated far field). Nodes b != a of one level are admissible when
+ * every point of each is separated from the other (the test of
+ * ffc_skel_opts.separation both ways). From the pairs of the root's children,
+ * an admissible pair contributes K(x_{J_b}, x_{J_a}) q~_a at b's skeleton
+ * points, any other pair of leaves is summed directly, and any other pair
+ * recurses into its four child pairs. The values at skeleton points are passed
+ * down by P^T to the children's skeleton points and, at the leaves, to the
+ * points (far field); direct pairs give the near field. q_dev, u_dev, u_far_dev
+ * as in ffc_evaluate_sum. The interaction lists are built on the first call
+ * with a skeleton set (or after its separation changed), which synchronizes
+ * `stream` once. Errors: a skeleton set built without separation ->
+ * FFC_ERR_STATE; precision other than FFC_FP64 / FFC_FP32, tree depth above
+ * 11 -> FFC_ERR_INVALID_ARG. */
+ffc_status ffc_evaluate_fmm(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* k,
+                            const double* q_dev, double* u_dev, double* u_far_dev,
+                            int32_t precision, void* stream);
+
 /* Direct summation u_i = sum_j K(y_i, x_j) q_j (Section 1, eq. e:sum) for m
  * targets Y (m x d) and n sources X (n x d). Laplace pairs at zero distance
  * contribute 0. Errors: m, n < 0, d < 1, NULL pointers with nonzero sizes. */

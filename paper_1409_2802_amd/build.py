@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libffc.so")
 SOURCES = ["api.hip", "tree.hip", "sample.hip", "kblock.hip", "cpqr.hip", "cpqr_coop.hip", "gram_mfma.hip", "profile.hip", "api_proposal.hip",
-           "proposal.hip", "leverage.hip"]
+           "proposal.hip", "leverage.hip", "fmm.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

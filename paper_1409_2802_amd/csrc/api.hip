@@ -449,6 +449,30 @@ ffc_status ffc_evaluate_sum(const ffc_tree* t, const ffc_skel* sk, const ffc_ker
   return FFC_OK;
 }
 
+ffc_status ffc_evaluate_fmm(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* k, const double* q_dev,
+                            double* u_dev, double* u_far_dev, int32_t precision, void* stream) {
+  if (!t || !sk) return fail(FFC_ERR_INVALID_ARG, "tree or skeleton is NULL");
+  if (!q_dev || !u_dev) return fail(FFC_ERR_INVALID_ARG, "q or u is NULL");
+  if (sk->num_nodes != t->num_nodes || sk->depth != t->depth)
+    return fail(FFC_ERR_STATE, "skeleton set does not belong to this tree");
+  FFC_TRY(check_kernel(k, t->d));
+  FFC_TRY(check_precision(precision));
+  hipStream_t st = (hipStream_t)stream;
+  ffc_tree* tm = const_cast<ffc_tree*>(t);
+  {
+    StageTimer timer(FFC_STAGE_UPWARD, st);
+    FFC_TRY(launch_charges_to_tree(tm, q_dev, st));
+    for (int lev = t->depth; lev >= 1; --lev)
+      FFC_TRY(launch_upward(t, sk, (1 << lev) - 1, 1 << lev, lev == t->depth, st));
+  }
+  {
+    StageTimer timer(FFC_STAGE_EVALUATE, st);
+    FFC_TRY(launch_fmm(t, sk, make_kparams(*k, t->d), precision, u_dev, u_far_dev, st));
+  }
+  tm->last_stream = st;
+  return FFC_OK;
+}
+
 ffc_status ffc_direct_sum(const double* Y_dev, int64_t m, const double* X_dev, int64_t n, int32_t d,
                           const ffc_kernel* k, const double* q_dev, double* u_dev, int32_t precision, void* stream) {
   if (m < 0 || n < 0 || n > INT32_MAX) return fail(FFC_ERR_INVALID_ARG, "m, n must be >= 0 (n < 2^31)");

@@ -200,6 +200,13 @@ struct ffc_skel {
   ffc::DevBuf<uint64_t> sep_bits;
   ffc::DevBuf<int32_t> sep_pre;
   int32_t sep_words = 0;
+  // FMM-style evaluation: multipole-to-local lists per node and direct lists
+  // per leaf (CSR, built for separation fmm_xi), incoming values v at the
+  // skeleton points (num_nodes x r_cap) and the far field in tree order.
+  double fmm_xi = -1.0;
+  ffc::DevBuf<int32_t> fmm_far_off, fmm_far_src, fmm_near_off, fmm_near_src;
+  ffc::DevBuf<double> fmm_v, fmm_ufar;
+  int64_t fmm_far_pairs = 0, fmm_near_pairs = 0;
   hipStream_t last_stream = nullptr;
 };
 
@@ -380,6 +387,10 @@ ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams&
 ffc_status launch_separation(const ffc_tree* t, ffc_skel* sk, double xi, hipStream_t st);
 ffc_status launch_treecode(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, double* u,
                            double* u_far, hipStream_t st);
+// FMM-style evaluation (fmm.hip); builds the interaction lists on first use
+// (synchronizes the stream once).
+ffc_status launch_fmm(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int precision, double* u, double* u_far,
+                      hipStream_t st);
 
 // Mixed-precision (bf16 hi/lo Gram on matrix cores) variants of the sampled
 // blocks, the evaluation and the direct sum for the Gaussian and polynomial

@@ -20,62 +20,12 @@
 // of the Gaussian and polynomial kernels runs on matrix cores (gram_mfma.hip).
 #include "ffc_internal.h"
 #include "tile_engine.h"
+#include "tile_sums.h"
 
 namespace ffc {
 namespace {
 
 using namespace tile;
-
-// The Laplace kernel r^(2-d) of r2 = r^2 > 0. Up to d = 7 it is a small power
-// of y = 1/r (odd d: y^(d-2)) or of z = 1/r^2 (even d: z^((d-2)/2)), each from
-// the hardware estimate refined by two Newton steps (y <- y + y (1 - r2 y^2) / 2,
-// z <- z + z (1 - r2 z)), a few times cheaper than the general power, which
-// serves larger d and r2 below 2^-900 (where the estimate's range ends).
-__device__ inline double laplace_of_r2(double r2, const KParams& kp) {
-  if (kp.lap_small && r2 > 0x1p-900) {
-    double b;
-    if (kp.lap_odd) {
-      b = __builtin_amdgcn_rsq(r2);
-      b = fma(0.5 * b, fma(-r2, b * b, 1.0), b);
-      b = fma(0.5 * b, fma(-r2, b * b, 1.0), b);
-    } else {
-      b = __builtin_amdgcn_rcp(r2);
-      b = fma(b, fma(-r2, b, 1.0), b);
-      b = fma(b, fma(-r2, b, 1.0), b);
-    }
-    double v = b;
-    for (int i = 1; i < kp.lap_m; ++i) v *= b;
-    return v;
-  }
-  return pow(r2, kp.lap_expo);
-}
-
-// Kernel function of an accumulated distance^2 (or inner product when DOT).
-template <bool DOT>
-__device__ inline double kfun(double acc, const KParams& kp) {
-  if (DOT) {
-    const double base = fma(acc, kp.inv_h, kp.c);
-    double r = 1.0;
-    for (int i = 0; i < kp.p; ++i) r *= base;
-    return r;
-  }
-  if (kp.kind == FFC_GAUSSIAN) return exp(acc * kp.neg_inv_2h2);
-  return acc > 0.0 ? laplace_of_r2(acc, kp) : 0.0;   // Laplace
-}
-
-template <bool DOT>
-__device__ inline double kfun(float acc, const KParams& kp) {
-  if (DOT) {
-    const float base = fmaf(acc, (float)kp.inv_h, (float)kp.c);
-    float r = 1.0f;
-    for (int i = 0; i < kp.p; ++i) r *= base;
-    return (double)r;
-  }
-  if (kp.kind == FFC_GAUSSIAN) return (double)expf(acc * (float)kp.neg_inv_2h2);
-  return acc > 0.0f ? laplace_of_r2((double)acc, kp) : 0.0;   // Laplace: power in FP64 (range)
-}
-
-__device__ inline void flag_nonfinite(unsigned int* flag) { atomicOr(flag, 1u); }
 
 // ---------------------------------------------------------------------------
 // Sampled blocks for all nodes of a level.
@@ -145,49 +95,6 @@ __global__ void __launch_bounds__(NT) k_sampled_block(const double* __restrict__
   if (bad) flag_nonfinite(flag);
 }
 
-// ---------------------------------------------------------------------------
-// Kernel sums: accumulate sum_j K(y_i, x_j) q_j over one source set into
-// per-thread partial sums part[i] (rows tr + 16 i of the tile).
-// ---------------------------------------------------------------------------
-template <typename T, bool DOT>
-__device__ inline void sum_over_sources(const double* __restrict__ Y, IdxMap rows, int nrows,
-                                        const double* __restrict__ X, IdxMap cols, int ncols,
-                                        const double* __restrict__ q, int d, const KParams& kp, TileSmem<T>& sm,
-                                        double (&part)[4], bool& bad) {
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
-  for (int c0 = 0; c0 < ncols; c0 += BN) {
-    IdxMap cm{cols.idx ? cols.idx + c0 : nullptr, cols.base + c0};
-    T acc[4][4];
-    tile_accumulate<T, DOT>(Y, rows, nrows, X, cm, ncols - c0, d, sm, acc);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = c0 + tc + 16 * j;
-      if (c < ncols) {
-        const double qj = q[c];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) part[i] = fma(kfun<DOT>(acc[i][j], kp), qj, part[i]);
-      }
-    }
-  }
-  // A kernel value that is not finite leaves its partial sum not finite
-  // (q = 0 gives NaN), so one test per row after the loop finds it.
-#pragma unroll
-  for (int i = 0; i < 4; ++i) bad |= !isfinite(part[i]);
-}
-
-// Fixed-order reduction of part[] across the 16 column threads of each row.
-__device__ inline void reduce_rows(double (&part)[4], double* red /* 16 x 64 */, double* rowsum /* 64 */) {
-  const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) red[tc * BM + tr + 16 * i] = part[i];
-  __syncthreads();
-  if (threadIdx.x < BM) {
-    double s = 0.0;
-    for (int c = 0; c < 16; ++c) s += red[c * BM + threadIdx.x];
-    rowsum[threadIdx.x] = s;
-  }
-  __syncthreads();
-}
 
 // Far field (sibling cover) + near field (own leaf) for a tile of targets.
 template <typename T, bool DOT>

@@ -25,7 +25,7 @@ SAMPLE_UNIFORM, SAMPLE_LEARNED, SAMPLE_DISTANCE, SAMPLE_NEAREST = 0, 1, 2, 3
 # Every exported entry point of include/ffc.h.
 EXPORTS = [
     "ffc_build_tree", "ffc_build_partition", "ffc_tree_info", "ffc_tree_arrays",
-    "ffc_skeletonize_nodes", "ffc_evaluate_sum", "ffc_direct_sum", "ffc_sampled_block",
+    "ffc_skeletonize_nodes", "ffc_evaluate_sum", "ffc_evaluate_fmm", "ffc_direct_sum", "ffc_sampled_block",
     "ffc_interp_decomp", "ffc_skel_node", "ffc_skel_stats", "ffc_check_device",
     "ffc_free_tree", "ffc_free_skel", "ffc_last_error", "ffc_profile_enable", "ffc_profile_read",
     "ffc_proposal_create", "ffc_proposal_get", "ffc_proposal_free", "ffc_proposal_features",
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ffc_tree_arrays": [P, P, P, P, P, P],
         "ffc_skeletonize_nodes": [P, ctypes.POINTER(KernelC), ctypes.POINTER(SkelOptsC), P, PP],
         "ffc_evaluate_sum": [P, P, ctypes.POINTER(KernelC), P, P, P, I32, P],
+        "ffc_evaluate_fmm": [P, P, ctypes.POINTER(KernelC), P, P, P, I32, P],
         "ffc_direct_sum": [P, I64, P, I64, I32, ctypes.POINTER(KernelC), P, P, I32, P],
         "ffc_sampled_block": [P, ctypes.POINTER(KernelC), I32, P, I32, P, I32, P, P],
         "ffc_interp_decomp": [P, I32, I32, I32, D, I32, P, P, P, P],
@@ -318,6 +319,22 @@ def evaluate_sum(tree: Tree, sk: Skeletons, kernel: Kernel, q, precision: int = 
     _check(load_library().ffc_evaluate_sum(tree.handle, sk.handle, ctypes.byref(k), _ptr(qd), _ptr(u), _ptr(uf),
                                            precision, _stream(stream)))
     return u, uf
+
+
+def evaluate_fmm(tree: Tree, sk: Skeletons, kernel: Kernel, q, precision: int = FP64, stream=None):
+    """FMM-style evaluation (incoming representations from the skeletons); returns (u, u_far)."""
+    qd = _dev_f64(q, "q")
+    u = torch.empty(tree.N, dtype=torch.float64, device="cuda")
+    uf = torch.empty(tree.N, dtype=torch.float64, device="cuda")
+    evaluate_fmm_into(tree, sk, kernel, qd, u, uf, precision, stream)
+    return u, uf
+
+
+def evaluate_fmm_into(tree: Tree, sk: Skeletons, kernel: Kernel, q: torch.Tensor, u: torch.Tensor,
+                      u_far: torch.Tensor | None, precision: int = FP64, stream=None) -> None:
+    k = kernel.c_struct()
+    _check(load_library().ffc_evaluate_fmm(tree.handle, sk.handle, ctypes.byref(k), _ptr(q), _ptr(u), _ptr(u_far),
+                                           precision, _stream(stream)))
 
 
 def evaluate_sum_into(tree: Tree, sk: Skeletons, kernel: Kernel, q: torch.Tensor, u: torch.Tensor,
