@@ -67,6 +67,9 @@ WORKLOADS = {
     "separated3": dict(N=65536, d=3, data="normal", kernel="laplace", leaf=256, max_rank=128, num_samples=256,
                        tol=1e-6, precision="fp64", separation=2.0,
                        text="N=65536 d=3 N(0,I), Laplace 1/|x-y|, treecode with separation xi=2"),
+    "fmm3": dict(N=65536, d=3, data="normal", kernel="laplace", leaf=256, max_rank=128, num_samples=256,
+                 tol=1e-6, precision="fp64", separation=1.0, evaluation="fmm",
+                 text="N=65536 d=3 N(0,I), Laplace 1/|x-y|, FMM-style evaluation with separation xi=1"),
     "learned64": dict(N=262144, d=64, **SUB, kernel="gaussian", h=1.0, leaf=1024, max_rank=256, num_samples=512,
                       tol=1e-6, precision="mixed", learned=True, train_blocks=2000, block_cols=512,
                       block_rows=4096, epochs=2, batch=4096, lr=1e-3, eps=1e-4, pool_factor=8,
@@ -84,7 +87,7 @@ def parse():
     ap.add_argument("--train-blocks", type=int, default=None, help="learned64: training blocks")
     ap.add_argument("--compare", action="store_true",
                     help="learned64: every sampler at 1x, 2x, 4x rows; adaptive4: fixed row counts; "
-                         "separated3: separation 0, 1, 2, 4")
+                         "separated3 / fmm3: treecode and FMM-style evaluation at separation 0.5, 1, 2, 4")
     ap.add_argument("--variants", default="fp32,mixed",
                     help="other precisions timed on the same workload, each judged against the FP64 path")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -222,7 +225,17 @@ def oracle_far_check(w, X, q, u_far_gpu, count=256):
         Xt, qt = X[ot.perm], q[ot.perm]
         inv = np.empty(ot.N, dtype=np.int64)
         inv[ot.perm] = np.arange(ot.N)
-        far, _ = interaction_lists(Xt, ot, w["separation"])
+        if w.get("evaluation") == "fmm":
+            from oracle.fmm import fmm_lists
+            pairs, _ = fmm_lists(Xt, ot, w["separation"])
+            leaf_of = ot.leaf_of_position()
+            far = {}
+            for b, srcs in pairs.items():            # far[a] = targets whose far field holds node a
+                for a in srcs:
+                    T = np.arange(ot.begin[b], ot.end[b])
+                    far[a] = np.concatenate([far.get(a, np.zeros(0, dtype=np.int64)), T])
+        else:
+            far, _ = interaction_lists(Xt, ot, w["separation"])
         ex = np.zeros(len(tg))
         for a, T in far.items():
             hit = np.flatnonzero(np.isin(inv[tg], T))
@@ -258,6 +271,32 @@ def treecode_work(arr, ranks, xi, Xt):
         else:
             arrive[2 * a + 1] = rest
             arrive[2 * a + 2] = rest
+    return far_evals + near_evals, near_evals
+
+
+def fmm_work(arr, ranks, xi, Xt):
+    """Kernel evaluations of one FMM-style evaluation: r_b r_a per multipole-to-local pair plus the direct
+    leaf pairs, from the same admissibility test on the tree's centroids and radii."""
+    begin, end, cen, rad = arr["begin"], arr["end"], arr["centroid"], arr["radius"]
+    depth = int(np.log2(len(begin) + 1)) - 1
+
+    def sep_all(a, lo, hi):
+        diff = Xt[lo:hi] - cen[a]
+        thr = xi * rad[a]
+        return bool(np.all(np.einsum("ij,ij->i", diff, diff) >= thr * thr))
+
+    far_evals = near_evals = 0.0
+    pairs = [(1, 1), (1, 2), (2, 1), (2, 2)]
+    for lev in range(1, depth + 1):
+        nxt = []
+        for b, a in pairs:
+            if b != a and sep_all(a, begin[b], end[b]) and sep_all(b, begin[a], end[a]):
+                far_evals += float(ranks[b]) * ranks[a]
+            elif lev == depth:
+                near_evals += float(end[b] - begin[b]) * (end[a] - begin[a])
+            else:
+                nxt += [(cb, ca) for cb in (2 * b + 1, 2 * b + 2) for ca in (2 * a + 1, 2 * a + 2)]
+        pairs = nxt
     return far_evals + near_evals, near_evals
 
 
@@ -326,16 +365,21 @@ def main():
         print(f"[bench] trained: {json.dumps(training)}", file=sys.stderr, flush=True)
 
     def step(sk, s=w["num_samples"], mr=w["max_rank"], prop=proposal, p=prec, out=(u, uf),
-             adaptive=w.get("adaptive_tol", 0.0), sampler=None, xi=w.get("separation", 0.0)):
+             adaptive=w.get("adaptive_tol", 0.0), sampler=None, xi=w.get("separation", 0.0),
+             fmm=w.get("evaluation") == "fmm"):
         sk = ffc.skeletonize(tree, k, tol=w["tol"], max_rank=mr, num_samples=s, precision=p, seed=0,
                              reuse=sk, proposal=prop, pool_factor=w.get("pool_factor", 0), adaptive_tol=adaptive,
                              max_samples=w.get("max_samples", 0), sampler=sampler, separation=xi)
-        ffc.evaluate_sum_into(tree, sk, k, qd, out[0], out[1], precision=p)
+        if fmm:
+            ffc.evaluate_fmm_into(tree, sk, k, qd, out[0], out[1], precision=p)
+        else:
+            ffc.evaluate_sum_into(tree, sk, k, qd, out[0], out[1], precision=p)
         return sk
 
     # Steps that synchronize inside (the learned fallback check, the adaptive rounds) cannot be captured.
+    # The FMM-style evaluation is not part of the captured step (its entry point is not in the graph API).
     use_graph = not args.eager and not (proposal is not None and w.get("fallback_tol", 0.0) > 0) \
-        and not w.get("adaptive_tol", 0.0) > 0
+        and not w.get("adaptive_tol", 0.0) > 0 and w.get("evaluation") != "fmm"
 
     def timed(p, steps, warmup, out):
         """Warm-up with eager calls, then time `steps` steps in precision p (graph replays unless --eager)."""
@@ -422,7 +466,8 @@ def main():
     xi = w.get("separation", 0.0)
     if xi > 0:
         Xt_h = X[arr["perm"]]
-        eval_evals, near_evals = treecode_work(arr, ranks, xi, Xt_h)
+        work = fmm_work if w.get("evaluation") == "fmm" else treecode_work
+        eval_evals, near_evals = work(arr, ranks, xi, Xt_h)
     else:
         eval_evals = float(sum(sizes[a] ** 2 for a in leaves))
         eval_evals += float(sum(sizes[a + 1 if a % 2 else a - 1] * ranks[a] for a in range(1, tree.num_nodes)))
@@ -483,7 +528,8 @@ def main():
         roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = {"cpqr": "k_cpqr_coop", "solve": "k_coop_setup + k_diag_inv + k_id_solve_mfma",
                       "kblock": "k_level_kblock",
-                      "evaluate": "k_treecode" if xi > 0 else "k_evaluate",
+                      "evaluate": ("k_m2l + k_l2l + k_p2p" if w.get("evaluation") == "fmm" else "k_treecode")
+                      if xi > 0 else "k_evaluate",
                       "sample": "k_sep_bitmap + k_sep_prefix + k_sample_rows_bitmap" if xi > 0
                       else "k_sample_rows_bitmap", "upward": "k_upward",
                       "proposal": "k_geometry + k_features + k_mlp_score + k_select_rows"}.get(dom, dom)
@@ -505,7 +551,8 @@ def main():
                                f"max_rank={w['max_rank']}, tol={w['tol']}",
                    "N": w["N"], "d": w["d"], "leaf_size": w["leaf"], "num_samples": w["num_samples"],
                    "max_rank": w["max_rank"], "tol": w["tol"], "precision": pname,
-                   "sampler": "learned" if proposal is not None else "uniform", "separation": xi},
+                   "sampler": "learned" if proposal is not None else "uniform", "separation": xi,
+                   "evaluation": w.get("evaluation", "treecode" if xi > 0 else "sibling cover")},
         "kernel_evals_per_s": evals_per_s,
         "skeleton_kernel_evals": skel_evals, "evaluate_kernel_evals": eval_evals,
         "ranks": {"min": st["rank_min"], "mean": st["rank_mean"], "max": st["rank_max"],
@@ -548,23 +595,24 @@ def main():
         # Separation sweep on the same tree: error of the whole sum against the exact one, the share of the
         # sum carried by skeletons, and one eager step.
         cmp = []
-        for xs in (0.0, 1.0, 2.0, 4.0):
-            skc = step(None, xi=xs)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            skc = step(skc, xi=xs)
-            e1.record()
-            torch.cuda.synchronize()
-            uh, ufh = u.cpu().numpy(), uf.cpu().numpy()
-            fe = ud_h - (uh - ufh)
-            row = {"separation": xs, "ms_per_step": e0.elapsed_time(e1),
-                   "e_total_vs_exact": float(np.linalg.norm(uh - ud_h) / np.linalg.norm(ud_h)),
-                   "e_far_vs_exact": float(np.linalg.norm(ufh - fe) / max(np.linalg.norm(fe), 1e-300)),
-                   "far_share": float(np.linalg.norm(ufh) / np.linalg.norm(uh)),
-                   "rank_mean": skc.stats()["rank_mean"]}
-            cmp.append(row)
-            print(f"[bench] separation {row}", file=sys.stderr, flush=True)
+        for xs in (0.5, 1.0, 2.0, 4.0):
+            for ev in ("treecode", "fmm"):
+                skc = step(None, xi=xs, fmm=ev == "fmm")
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                skc = step(skc, xi=xs, fmm=ev == "fmm")
+                e1.record()
+                torch.cuda.synchronize()
+                uh, ufh = u.cpu().numpy(), uf.cpu().numpy()
+                fe = ud_h - (uh - ufh)
+                row = {"separation": xs, "evaluation": ev, "ms_per_step": e0.elapsed_time(e1),
+                       "e_total_vs_exact": float(np.linalg.norm(uh - ud_h) / np.linalg.norm(ud_h)),
+                       "e_far_vs_exact": float(np.linalg.norm(ufh - fe) / max(np.linalg.norm(fe), 1e-300)),
+                       "far_share": float(np.linalg.norm(ufh) / np.linalg.norm(uh)),
+                       "rank_mean": skc.stats()["rank_mean"]}
+                cmp.append(row)
+                print(f"[bench] separation {row}", file=sys.stderr, flush=True)
         out["separation_sweep"] = cmp
     if args.compare and proposal is not None:
         # Far-field error of every sampler at 1x, 2x and 4x the rank cap, and the time of one eager step:
