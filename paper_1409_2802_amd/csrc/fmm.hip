@@ -58,7 +58,7 @@ __global__ void k_fmm_admissible(const uint64_t* __restrict__ bits, int words, c
   adm[p] = ok ? 1 : 0;
 }
 
-template <typename T, bool DOT>
+template <typename T, bool DOT, int DM>
 __global__ void __launch_bounds__(NT) k_m2l(const double* __restrict__ Xt, int d, KParams kp, int chunks,
                                             const int32_t* __restrict__ rank, const int32_t* __restrict__ skel,
                                             int r_cap, const double* __restrict__ qt,
@@ -71,13 +71,14 @@ __global__ void __launch_bounds__(NT) k_m2l(const double* __restrict__ Xt, int d
   const int nrows = min(BM, rank[b] - c * BM);
   if (nrows <= 0) return;
   const IdxMap rmap{skel + (int64_t)b * r_cap + c * BM, 0};
+  if constexpr (DM > 0) stage_rows<T, DM>(Xt, rmap, nrows, d, sm);
   bool bad = false;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   for (int e = off[b]; e < off[b + 1]; ++e) {
     const int a = src[e];
     if (rank[a] > 0)
-      sum_over_sources<T, DOT>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)a * r_cap, 0}, rank[a],
-                               qt + (int64_t)a * r_cap, d, kp, sm, part, bad);
+      sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)a * r_cap, 0}, rank[a],
+                          qt + (int64_t)a * r_cap, d, kp, sm, part, bad);
   }
   reduce_rows(part, red, rowsum);
   if (threadIdx.x < nrows) v[(int64_t)b * r_cap + c * BM + threadIdx.x] = rowsum[threadIdx.x];
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(256) k_l2l(int first, int leaves, const int32_
   else v[(int64_t)(l + 1) * r_cap + (j - rl)] += w;
 }
 
-template <typename T, bool DOT>
+template <typename T, bool DOT, int DM>
 __global__ void __launch_bounds__(NT) k_p2p(const double* __restrict__ Xt, int d, KParams kp,
                                             const int32_t* __restrict__ tile_leaf,
                                             const int32_t* __restrict__ tile_start, const int32_t* __restrict__ nb,
@@ -124,14 +125,15 @@ __global__ void __launch_bounds__(NT) k_p2p(const double* __restrict__ Xt, int d
   const int start = tile_start[blockIdx.x];
   const int nrows = min(BM, ne[leaf] - start);
   const IdxMap rmap{nullptr, start};
+  if constexpr (DM > 0) stage_rows<T, DM>(Xt, rmap, nrows, d, sm);
   bool bad = false;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   const int li = leaf - leaf0;
   for (int e = off[li]; e < off[li + 1]; ++e) {
     const int a = src[e];
     const int ab = nb[a];
-    sum_over_sources<T, DOT>(Xt, rmap, nrows, Xt, IdxMap{nullptr, ab}, ne[a] - ab, q_tree + ab, d, kp, sm, part,
-                             bad);
+    sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{nullptr, ab}, ne[a] - ab, q_tree + ab, d, kp, sm, part,
+                        bad);
   }
   reduce_rows(part, red, near_sum);
   if (threadIdx.x < nrows) {
@@ -239,23 +241,26 @@ ffc_status launch_fmm(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int pr
   return dispatch_tiles(precision, dot, [&](auto tv, auto dv) -> ffc_status {
     using T = decltype(tv);
     constexpr bool D = decltype(dv)::value;
-    hipLaunchKernelGGL((k_m2l<T, D>), dim3((unsigned)((t->num_nodes - 1) * chunks)), dim3(NT), 0, st, t->Xt.ptr,
-                       t->d, kp, chunks, sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, sk->fmm_far_off.ptr,
-                       sk->fmm_far_src.ptr, sk->fmm_v.ptr, device_flag());
-    FFC_LAUNCH_CHECK("k_m2l");
-    for (int l = 1; l <= t->depth; ++l) {
-      const int first = (1 << l) - 1, count = 1 << l;
-      hipLaunchKernelGGL(k_l2l, dim3((unsigned)count, (unsigned)((sk->n_cap + 255) / 256)), dim3(256), 0, st, first,
-                         l == t->depth ? 1 : 0, sk->rank.ptr, sk->ncols.ptr, sk->P.ptr, sk->r_cap, sk->n_cap,
-                         t->begin.ptr, sk->fmm_v.ptr, sk->fmm_ufar.ptr);
-      FFC_LAUNCH_CHECK("k_l2l");
-    }
-    hipLaunchKernelGGL((k_p2p<T, D>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
-                       t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr, leaf0,
-                       sk->fmm_near_off.ptr, sk->fmm_near_src.ptr, sk->fmm_ufar.ptr, t->perm.ptr, u, u_far,
-                       device_flag());
-    FFC_LAUNCH_CHECK("k_p2p");
-    return FFC_OK;
+    return with_dims(t->d, [&](auto dm) -> ffc_status {
+      constexpr int DM = decltype(dm)::value;
+      hipLaunchKernelGGL((k_m2l<T, D, DM>), dim3((unsigned)((t->num_nodes - 1) * chunks)), dim3(NT), 0, st, t->Xt.ptr,
+                         t->d, kp, chunks, sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, sk->fmm_far_off.ptr,
+                         sk->fmm_far_src.ptr, sk->fmm_v.ptr, device_flag());
+      FFC_LAUNCH_CHECK("k_m2l");
+      for (int l = 1; l <= t->depth; ++l) {
+        const int first = (1 << l) - 1, count = 1 << l;
+        hipLaunchKernelGGL(k_l2l, dim3((unsigned)count, (unsigned)((sk->n_cap + 255) / 256)), dim3(256), 0, st, first,
+                           l == t->depth ? 1 : 0, sk->rank.ptr, sk->ncols.ptr, sk->P.ptr, sk->r_cap, sk->n_cap,
+                           t->begin.ptr, sk->fmm_v.ptr, sk->fmm_ufar.ptr);
+        FFC_LAUNCH_CHECK("k_l2l");
+      }
+      hipLaunchKernelGGL((k_p2p<T, D, DM>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
+                         t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr, leaf0,
+                         sk->fmm_near_off.ptr, sk->fmm_near_src.ptr, sk->fmm_ufar.ptr, t->perm.ptr, u, u_far,
+                         device_flag());
+      FFC_LAUNCH_CHECK("k_p2p");
+      return FFC_OK;
+    });
   });
 }
 

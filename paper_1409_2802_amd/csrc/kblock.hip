@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(NT) k_sampled_block(const double* __restrict__
 
 
 // Far field (sibling cover) + near field (own leaf) for a tile of targets.
-template <typename T, bool DOT>
+template <typename T, bool DOT, int DM>
 __global__ void __launch_bounds__(NT) k_evaluate(const double* __restrict__ Xt, int d, KParams kp, int depth,
                                                  const int32_t* __restrict__ tile_leaf,
                                                  const int32_t* __restrict__ tile_start,
@@ -114,6 +114,7 @@ __global__ void __launch_bounds__(NT) k_evaluate(const double* __restrict__ Xt, 
   const int start = tile_start[blockIdx.x];
   const int nrows = min(BM, ne[leaf] - start);
   const IdxMap rmap{nullptr, start};
+  if constexpr (DM > 0) stage_rows<T, DM>(Xt, rmap, nrows, d, sm);
   bool bad = false;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   // Far field: one cover node per level (the sibling of each ancestor).
@@ -122,15 +123,15 @@ __global__ void __launch_bounds__(NT) k_evaluate(const double* __restrict__ Xt, 
     const int sib = (a & 1) ? a + 1 : a - 1;
     const int r = rank[sib];
     if (r > 0)
-      sum_over_sources<T, DOT>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)sib * r_cap, 0}, r,
-                               qt + (int64_t)sib * r_cap, d, kp, sm, part, bad);
+      sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)sib * r_cap, 0}, r,
+                          qt + (int64_t)sib * r_cap, d, kp, sm, part, bad);
     a = (a - 1) >> 1;
   }
   reduce_rows(part, red, far_sum);
   double npart[4] = {0.0, 0.0, 0.0, 0.0};
   const int lb = nb[leaf];
-  sum_over_sources<T, DOT>(Xt, rmap, nrows, Xt, IdxMap{nullptr, lb}, ne[leaf] - lb, q_tree + lb, d, kp, sm, npart,
-                           bad);
+  sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{nullptr, lb}, ne[leaf] - lb, q_tree + lb, d, kp, sm, npart,
+                      bad);
   reduce_rows(npart, red, near_sum);
   if (threadIdx.x < nrows) {
     const int pos = start + threadIdx.x;
@@ -223,7 +224,7 @@ __global__ void __launch_bounds__(kPreThreads) k_sep_prefix(const uint64_t* __re
 // whether the row reaches the node of level l on the current path; a node of
 // level l sets bit l + 1 for its children, and nodes visited before its second
 // child are all deeper, so that bit still holds when the second child is popped.
-template <typename T, bool DOT>
+template <typename T, bool DOT, int DM>
 __global__ void __launch_bounds__(NT) k_treecode(const double* __restrict__ Xt, int d, KParams kp, int depth,
                                                  const int32_t* __restrict__ tile_leaf,
                                                  const int32_t* __restrict__ tile_start,
@@ -244,6 +245,7 @@ __global__ void __launch_bounds__(NT) k_treecode(const double* __restrict__ Xt, 
   const int start = tile_start[blockIdx.x];
   const int nrows = min(BM, ne[leaf] - start);
   const IdxMap rmap{nullptr, start};
+  if constexpr (DM > 0) stage_rows<T, DM>(Xt, rmap, nrows, d, sm);
   const int tid = threadIdx.x, tr = tid & 15;
   bool bad = false;
   double fpart[4] = {0.0, 0.0, 0.0, 0.0}, npart[4] = {0.0, 0.0, 0.0, 0.0};
@@ -276,8 +278,8 @@ __global__ void __launch_bounds__(NT) k_treecode(const double* __restrict__ Xt, 
     const int any_rest = __syncthreads_or(k == 2);
     if (any_far && rank[a] > 0) {
       double tmp[4] = {0.0, 0.0, 0.0, 0.0};
-      sum_over_sources<T, DOT>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)a * r_cap, 0}, rank[a],
-                               qt + (int64_t)a * r_cap, d, kp, sm, tmp, bad);
+      sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)a * r_cap, 0}, rank[a],
+                          qt + (int64_t)a * r_cap, d, kp, sm, tmp, bad);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
         if (take[tr + 16 * i] == 1) fpart[i] += tmp[i];
@@ -286,8 +288,8 @@ __global__ void __launch_bounds__(NT) k_treecode(const double* __restrict__ Xt, 
       if (is_leaf) {
         const int lb = nb[a];
         double tmp[4] = {0.0, 0.0, 0.0, 0.0};
-        sum_over_sources<T, DOT>(Xt, rmap, nrows, Xt, IdxMap{nullptr, lb}, ne[a] - lb, q_tree + lb, d, kp, sm, tmp,
-                                 bad);
+        sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{nullptr, lb}, ne[a] - lb, q_tree + lb, d, kp, sm, tmp,
+                            bad);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
           if (take[tr + 16 * i] == 2) npart[i] += tmp[i];
@@ -314,7 +316,7 @@ __global__ void __launch_bounds__(NT) k_treecode(const double* __restrict__ Xt, 
 }
 
 // Direct sum over all sources for a tile of 64 targets.
-template <typename T, bool DOT>
+template <typename T, bool DOT, int DM>
 __global__ void __launch_bounds__(NT) k_direct(const double* __restrict__ Y, int64_t m, const double* __restrict__ X,
                                                int64_t n, int d, KParams kp, const double* __restrict__ q,
                                                double* __restrict__ u, unsigned int* flag) {
@@ -325,7 +327,8 @@ __global__ void __launch_bounds__(NT) k_direct(const double* __restrict__ Y, int
   const int nrows = (int)min<int64_t>(BM, m - r0);
   bool bad = false;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
-  sum_over_sources<T, DOT>(Y, IdxMap{nullptr, r0}, nrows, X, IdxMap{nullptr, 0}, (int)n, q, d, kp, sm, part, bad);
+  if constexpr (DM > 0) stage_rows<T, DM>(Y, IdxMap{nullptr, r0}, nrows, d, sm);
+  sum_sources<T, DOT, DM>(Y, IdxMap{nullptr, r0}, nrows, X, IdxMap{nullptr, 0}, (int)n, q, d, kp, sm, part, bad);
   reduce_rows(part, red, rowsum);
   if (threadIdx.x < nrows) u[r0 + threadIdx.x] = rowsum[threadIdx.x];
   if (bad) flag_nonfinite(flag);
@@ -417,11 +420,14 @@ ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams&
   return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
     using T = decltype(tv);
     constexpr bool D = decltype(dv)::value;
-    hipLaunchKernelGGL((k_evaluate<T, D>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
-                       t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
-                       sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->perm.ptr, u, u_far, device_flag());
-    FFC_LAUNCH_CHECK("k_evaluate");
-    return FFC_OK;
+    return with_dims(t->d, [&](auto dm) -> ffc_status {
+      constexpr int DM = decltype(dm)::value;
+      hipLaunchKernelGGL((k_evaluate<T, D, DM>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
+                         t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
+                         sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->perm.ptr, u, u_far, device_flag());
+      FFC_LAUNCH_CHECK("k_evaluate");
+      return FFC_OK;
+    });
   });
 }
 
@@ -458,12 +464,15 @@ ffc_status launch_treecode(const ffc_tree* t, const ffc_skel* sk, const KParams&
   return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
     using T = decltype(tv);
     constexpr bool D = decltype(dv)::value;
-    hipLaunchKernelGGL((k_treecode<T, D>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
-                       t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
-                       sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, sk->sep_bits.ptr, sk->sep_words,
-                       t->perm.ptr, u, u_far, device_flag());
-    FFC_LAUNCH_CHECK("k_treecode");
-    return FFC_OK;
+    return with_dims(t->d, [&](auto dm) -> ffc_status {
+      constexpr int DM = decltype(dm)::value;
+      hipLaunchKernelGGL((k_treecode<T, D, DM>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
+                         t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
+                         sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, sk->sep_bits.ptr, sk->sep_words,
+                         t->perm.ptr, u, u_far, device_flag());
+      FFC_LAUNCH_CHECK("k_treecode");
+      return FFC_OK;
+    });
   });
 }
 
@@ -475,10 +484,13 @@ ffc_status launch_direct_sum(const double* Y, int64_t m, const double* X, int64_
   return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
     using T = decltype(tv);
     constexpr bool D = decltype(dv)::value;
-    hipLaunchKernelGGL((k_direct<T, D>), dim3((unsigned)((m + BM - 1) / BM)), dim3(NT), 0, st, Y, m, X, n, d, kp, q,
-                       u, device_flag());
-    FFC_LAUNCH_CHECK("k_direct");
-    return FFC_OK;
+    return with_dims(d, [&](auto dm) -> ffc_status {
+      constexpr int DM = decltype(dm)::value;
+      hipLaunchKernelGGL((k_direct<T, D, DM>), dim3((unsigned)((m + BM - 1) / BM)), dim3(NT), 0, st, Y, m, X, n, d, kp, q,
+                         u, device_flag());
+      FFC_LAUNCH_CHECK("k_direct");
+      return FFC_OK;
+    });
   });
 }
 

@@ -8,6 +8,8 @@
 #include "ffc_internal.h"
 #include "tile_engine.h"
 
+#include <type_traits>
+
 namespace ffc {
 namespace tile {
 
@@ -90,6 +92,121 @@ __device__ inline void sum_over_sources(const double* __restrict__ Y, IdxMap row
   // (q = 0 gives NaN), so one test per row after the loop finds it.
 #pragma unroll
   for (int i = 0; i < 4; ++i) bad |= !isfinite(part[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel sums for d <= DM (DM = 4 or 32 <= KC), where one chunk holds every
+// dimension. The 64 target rows of a workgroup never change, so stage_rows puts
+// them in LDS once; the sums then stage only source chunks, fetching the next
+// chunk's coordinates into registers (64·DM / 256 per thread) while the current
+// one is computed. The arithmetic per pair is that of sum_over_sources (same
+// order), so the results are the same bits. DM = 0 selects sum_over_sources.
+// ---------------------------------------------------------------------------
+template <typename T, int DM>
+__device__ inline void stage_rows(const double* __restrict__ Y, IdxMap rows, int nrows, int d, TileSmem<T>& sm) {
+  const int tid = threadIdx.x;
+  const int sh = 32 - __clz(d - 1);
+#pragma unroll
+  for (int it = 0; it < BM * DM / NT; ++it) {
+    const int e = tid + it * NT;
+    if (e < (BM << sh)) {
+      const int r = e >> sh, kk = e & ((1 << sh) - 1);
+      if (kk < d) sm.ys[kk][r] = r < nrows ? (T)Y[rows(r) * d + kk] : T(0);
+    }
+  }
+}
+
+template <typename T, bool DOT, int DM>
+__device__ inline void sum_staged_rows(const double* __restrict__ X, IdxMap cols, int ncols,
+                                       const double* __restrict__ q, int d, const KParams& kp, TileSmem<T>& sm,
+                                       double (&part)[4], bool& bad) {
+  constexpr int IT = BM * DM / NT;
+  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+  const int sh = 32 - __clz(d - 1);
+  T pre[IT];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + it * NT;
+      const int r = e >> sh, kk = e & ((1 << sh) - 1);
+      pre[it] = (e < (BM << sh) && kk < d && r < ncols - c0) ? (T)X[cols(c0 + r) * d + kk] : T(0);
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = tid + it * NT;
+      const int r = e >> sh, kk = e & ((1 << sh) - 1);
+      if (e < (BM << sh) && kk < d) sm.xs[kk][r] = pre[it];
+    }
+  };
+  if (ncols <= 0) return;
+  fetch(0);
+  store();
+  __syncthreads();
+  for (int c0 = 0; c0 < ncols; c0 += BN) {
+    const bool more = c0 + BN < ncols;
+    if (more) fetch(c0 + BN);   // in flight while this chunk is computed
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+#pragma unroll (DM < 8 ? DM : 8)
+    for (int kk = 0; kk < d; ++kk) {
+      T a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = sm.ys[kk][tr + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = sm.xs[kk][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (DOT) {
+            acc[i][j] = fma(a[i], b[j], acc[i][j]);
+          } else {
+            const T df = a[i] - b[j];
+            acc[i][j] = fma(df, df, acc[i][j]);
+          }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + tc + 16 * j;
+      if (c < ncols) {
+        const double qj = q[c];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part[i] = fma(kfun<DOT>(acc[i][j], kp), qj, part[i]);
+      }
+    }
+    __syncthreads();   // every thread is done with this chunk's sources
+    if (more) {
+      store();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) bad |= !isfinite(part[i]);
+}
+
+// Sum over one source set with the tile's rows: the staged-rows form when DM > 0
+// (stage_rows must have run in this workgroup), the general form otherwise.
+template <typename T, bool DOT, int DM>
+__device__ inline void sum_sources(const double* __restrict__ Y, IdxMap rows, int nrows, const double* __restrict__ X,
+                                   IdxMap cols, int ncols, const double* __restrict__ q, int d, const KParams& kp,
+                                   TileSmem<T>& sm, double (&part)[4], bool& bad) {
+  if constexpr (DM > 0) sum_staged_rows<T, DOT, DM>(X, cols, ncols, q, d, kp, sm, part, bad);
+  else sum_over_sources<T, DOT>(Y, rows, nrows, X, cols, ncols, q, d, kp, sm, part, bad);
+}
+
+// Host side: the dimension class of the evaluation kernels (4, 32, or 0 for the
+// general path) as a compile-time constant passed to f.
+template <typename F>
+inline auto with_dims(int d, F&& f) {
+  if (d <= 4) return f(std::integral_constant<int, 4>());
+  if (d <= KC) return f(std::integral_constant<int, KC>());
+  return f(std::integral_constant<int, 0>());
 }
 
 // Fixed-order reduction of part[] across the 16 column threads of each row.
