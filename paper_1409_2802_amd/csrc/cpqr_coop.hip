@@ -769,7 +769,8 @@ const Variant kVariants[] = {
     {16, 4, 512, &launch_qr<16, 4, 512>}, {16, 4, 256, &launch_qr<16, 4, 256>},
     {16, 1, 512, &launch_qr<16, 1, 512>}, {32, 2, 512, &launch_qr<32, 2, 512>},
     {32, 2, 256, &launch_qr<32, 2, 256>}, {32, 1, 512, &launch_qr<32, 1, 512>},
-    {32, 1, 256, &launch_qr<32, 1, 256>},
+    {32, 1, 256, &launch_qr<32, 1, 256>}, {32, 1, 128, &launch_qr<32, 1, 128>},
+    {16, 1, 128, &launch_qr<16, 1, 128>},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -850,6 +851,12 @@ ffc_status launch_interp_decomp_coop(const IdBatch& bt, int batch, DevBuf<unsign
     for (const TuneEntry& te : g_tune)
       if (te.s_max == bt.s_max && te.n_max == bt.n_max && te.batch == batch && te.max_rank == bt.max_rank)
         choice = te.choice;
+  }
+  // FFC_QR_VARIANT=i forces variant i when it can hold the blocks (tests run
+  // every variant this way; the variants give the same bits).
+  if (const char* fv = std::getenv("FFC_QR_VARIANT")) {
+    const int v = std::atoi(fv);
+    if (v >= 0 && v < kNumVariants && bt.s_max <= 16 * kVariants[v].R) choice = v;
   }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   FFC_HIP_TRY(hipStreamIsCapturing(st, &cs));

@@ -88,3 +88,23 @@ def test_polynomial_exact_rank(ffc, p, expected):
     K = kernel_matrix(Y, X, k)
     pv = piv[0].cpu().numpy()[:r]
     assert np.linalg.norm(K - K[:, pv] @ P[0].cpu().numpy()[:r]) / np.linalg.norm(K) < 1e-9
+
+
+@pytest.mark.parametrize("s,n,tol,max_rank", [(512, 512, 1e-5, 256), (256, 600, 1e-6, 128), (100, 40, 1e-8, 40)])
+def test_every_qr_variant_gives_the_same_bits(ffc, monkeypatch, s, n, tol, max_rank):
+    """Each register-resident QR variant (rows per lane, columns per lane group,
+    workgroup size) that can hold the blocks, forced in turn, gives the same
+    rank, pivots and P, and those match the oracle."""
+    mats = np.stack([decaying(s, n, seed) for seed in (11, 12)])
+    ref = None
+    for v in range(9):
+        monkeypatch.setenv("FFC_QR_VARIANT", str(v))
+        rank, piv, P = (x.cpu().numpy() for x in ffc.interp_decomp(mats, tol, max_rank))
+        if ref is None:
+            ref = (rank, piv, P)
+            for b, A in enumerate(mats):
+                check_against_oracle(A, int(rank[b]), piv[b], P[b], tol, max_rank)
+        else:
+            np.testing.assert_array_equal(rank, ref[0], err_msg=f"variant {v}")
+            np.testing.assert_array_equal(piv, ref[1], err_msg=f"variant {v}")
+            np.testing.assert_array_equal(P, ref[2], err_msg=f"variant {v}")
