@@ -128,15 +128,26 @@ k_sample_rows_bitmap(const int32_t* __restrict__ nb, const int32_t* __restrict__
                      int s_cap, uint64_t seed, uint32_t stream_or, int inside,
                      const unsigned char* __restrict__ mask, SepView sv, int32_t* __restrict__ rows,
                      int32_t* __restrict__ nrows) {
-  extern __shared__ unsigned int bits[];            // nwords bitmap words, then s ints of t values
+  // LDS: with separation the node's word prefixes (sv.words + 1 ints, read by
+  // every candidate lookup's binary search), then nwords bitmap words, then s
+  // ints of t values.
+  extern __shared__ unsigned int lds_words[];
+  const int pre_len = sv.bits ? sv.words + 1 : 0;
+  unsigned int* bits = lds_words + pre_len;
   __shared__ int wsum[kBitmapThreads / 64];
   const int node = first + blockIdx.x;
   const int tid = threadIdx.x;
   if (mask && !mask[node]) return;
   const int b = nb[node], e = ne[node];
   int64_t M64;
-  const Candidates cand = candidates(sv, node, b, e, N, inside != 0, M64);
+  Candidates cand = candidates(sv, node, b, e, N, inside != 0, M64);
   const int M = (int)M64;
+  if (cand.bits) {
+    int32_t* spre = reinterpret_cast<int32_t*>(lds_words);
+    for (int w = tid; w <= cand.words; w += kBitmapThreads) spre[w] = cand.pre[w];
+    cand.pre = spre;
+    __syncthreads();
+  }
   int32_t* out = rows + (int64_t)node * s_cap;
   if (s >= M) {
     for (int i = tid; i < M; i += kBitmapThreads) out[i] = cand(i);
@@ -244,7 +255,8 @@ ffc_status draw(const int32_t* nb, const int32_t* ne, int64_t N, bool inside, in
     return FFC_ERR_INVALID_ARG;
   }
   const int64_t nwords = (N + 31) / 32;
-  const size_t lds = (size_t)nwords * sizeof(unsigned int) + (size_t)s * sizeof(int);
+  const size_t lds = (size_t)nwords * sizeof(unsigned int) + (size_t)s * sizeof(int) +
+                     (sv.bits ? (size_t)(sv.words + 1) * sizeof(int32_t) : 0);
   if (nwords <= kMaxBitmapWords && lds <= 64 * 1024) {
     hipLaunchKernelGGL(k_sample_rows_bitmap, dim3(count), dim3(kBitmapThreads), lds, st, nb, ne, N, first, s, cap,
                        seed, stream_or, inside ? 1 : 0, mask, sv, rows, nrows);
