@@ -149,6 +149,12 @@ struct ffc_tree {
   ffc::DevBuf<int32_t> tile_leaf, tile_start;
   int32_t num_tiles = 0;
   int32_t tile_rows = 0;
+  // Tree-order coordinates split into bfloat16 hi + lo (rows padded with zeros
+  // to bf_dp, a multiple of 32) and their squared norms, made on the first use
+  // of the matrix-core kernels.
+  ffc::DevBuf<uint16_t> bf_hi, bf_lo;
+  ffc::DevBuf<float> bf_nrm;
+  int32_t bf_dp = 0;
   hipStream_t last_stream = nullptr;
 };
 

@@ -1,20 +1,27 @@
 // Mixed-precision kernel tiles on matrix cores (FFC_MIXED_BF16X3).
 //
 // Distances in high dimension are Gram contractions: ||y - x||^2 =
-// ||y||^2 + ||x||^2 - 2 y.x. Coordinates are first centred on a common point
-// (the node centroid) so the norms stay small, then each centred coordinate
-// z is split into bfloat16 parts hi = bf16(z), lo = bf16(z - hi), which carry
-// z to about 2^-17 relative. The Gram product is hi.hi + hi.lo + lo.hi (the
-// lo.lo term is below that error) on v_mfma_f32_16x16x32_bf16 with float32
-// accumulation; the norms are float32 sums of squares. The kernel function
-// (Gaussian exp, or the polynomial power of the uncentred inner product) runs
-// in float32 in the epilogue and the block is stored in float64 for the QR.
+// ||y||^2 + ||x||^2 - 2 y.x. Each coordinate z is split into bfloat16 parts
+// hi = bf16(z), lo = bf16(z - hi), which carry z to about 2^-17 relative. The
+// Gram product is hi.hi + hi.lo + lo.hi (the lo.lo term is below that error) on
+// v_mfma_f32_16x16x32_bf16 with float32 accumulation. The kernel function
+// (Gaussian exp of the distance, or the polynomial power of the inner product)
+// runs in float32 in the epilogue; sampled blocks are stored in float64 for
+// the QR.
 //
-// A 256-thread workgroup computes a 64 x 64 tile; coordinates go through LDS
-// 32 dimensions at a time. The MFMA A operand holds the column points and B
-// the row points, so each output lane owns one sampled row of a column and
-// the column-major stores coalesce. Operand layout of the instruction (lane
-// l, element i): A[l % 16][(l / 16) * 8 + i], B[(l / 16) * 8 + i][l % 16],
+// The tree's points are split once (tree order, rows padded with zeros to a
+// multiple of 32 dimensions) with their squared norms summed in FP64 and
+// rounded to FP32; the sampled blocks and the evaluation then stage 16-byte
+// groups of ready operands and prefetch the next 32-dimension chunk while the
+// matrix cores work. The direct sum, on arbitrary point sets, converts while
+// staging and centres both sets on its first target (distances do not depend
+// on the centre; a nearby one keeps the norms small).
+//
+// A 256-thread workgroup computes a 64 x 64 tile; operands go through LDS 32
+// dimensions at a time. The MFMA A operand holds the column points and B the
+// row points, so each output lane owns one sampled row of a column and the
+// column-major stores coalesce. Operand layout of the instruction (lane l,
+// element i): A[l % 16][(l / 16) * 8 + i], B[(l / 16) * 8 + i][l % 16],
 // D[(l / 16) * 4 + i][l % 16].
 #include "ffc_internal.h"
 
@@ -117,6 +124,96 @@ __device__ void mixed_tile(const double* __restrict__ Y, Idx rows, int nrows, co
   }
 }
 
+// Tree-order points split once into bf16 hi + lo (rows of dp values, zero past
+// d): the same values mixed_tile forms when it stages uncentred coordinates.
+__global__ void k_bf16_split(const double* __restrict__ Xt, int64_t N, int d, int dp, __bf16* __restrict__ hi,
+                             __bf16* __restrict__ lo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * dp) return;
+  const int64_t p = e / dp;
+  const int k = (int)(e % dp);
+  const double v = k < d ? Xt[p * d + k] : 0.0;
+  const __bf16 h = (__bf16)(float)v;
+  hi[e] = h;
+  lo[e] = (__bf16)(float)(v - (double)(float)h);
+}
+
+// Squared norms of the tree-order points, summed in FP64 and rounded to FP32.
+__global__ void k_point_norms(const double* __restrict__ Xt, int64_t N, int d, float* __restrict__ nrm) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double* x = Xt + p * d;
+  double s = 0.0;
+  for (int k = 0; k < d; ++k) s = fma(x[k], x[k], s);
+  nrm[p] = (float)s;
+}
+
+// The Gram tile of mixed_tile, uncentred, from the pre-split points: each
+// thread stages one 16-byte group of 8 values of each of the four operands per
+// 32-dimension chunk, and fetches the next chunk's groups while the matrix
+// cores work on the current one. Same operands and chunk order as
+// mixed_tile<false>, so the same bits. With nrm, the points' squared norms go
+// to sm.yn / sm.xn for the distance epilogue.
+__device__ void mixed_tile_split(const __bf16* __restrict__ Hh, const __bf16* __restrict__ Hl,
+                                 const float* __restrict__ nrm, int dp, Idx rows, int nrows, Idx cols, int ncols,
+                                 MixSmem& sm, f32x4 (&acc)[2][2]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int p = tid >> 2, part = (tid & 3) * 8;
+  const int64_t yrow = p < nrows ? rows(p) : -1;
+  const int64_t xrow = p < ncols ? cols(p) : -1;
+  const uint4 zero{0u, 0u, 0u, 0u};
+  if (nrm && (tid & 3) == 0) {
+    sm.yn[p] = yrow >= 0 ? nrm[yrow] : 0.f;
+    sm.xn[p] = xrow >= 0 ? nrm[xrow] : 0.f;
+  }
+  uint4 yh, yl, xh, xl;
+  auto fetch = [&](int k0) {
+    yh = yrow >= 0 ? *reinterpret_cast<const uint4*>(Hh + yrow * dp + k0 + part) : zero;
+    yl = yrow >= 0 ? *reinterpret_cast<const uint4*>(Hl + yrow * dp + k0 + part) : zero;
+    xh = xrow >= 0 ? *reinterpret_cast<const uint4*>(Hh + xrow * dp + k0 + part) : zero;
+    xl = xrow >= 0 ? *reinterpret_cast<const uint4*>(Hl + xrow * dp + k0 + part) : zero;
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < dp; k0 += KCH) {
+    *reinterpret_cast<uint4*>(&sm.yh[p][part]) = yh;
+    *reinterpret_cast<uint4*>(&sm.yl[p][part]) = yl;
+    *reinterpret_cast<uint4*>(&sm.xh[p][part]) = xh;
+    *reinterpret_cast<uint4*>(&sm.xl[p][part]) = xl;
+    __syncthreads();
+    if (k0 + KCH < dp) fetch(k0 + KCH);
+    const int kofs = (lane >> 4) * 8;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const int xr = (w >> 1) * 32 + bi * 16 + (lane & 15);
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sm.xh[xr][kofs]);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(&sm.xl[xr][kofs]);
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&sm.yh[yr][kofs]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&sm.yl[yr][kofs]);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[bi][bj], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Pre-split points of the tree (and, for the Gaussian, their squared norms):
+// null pointers select the staging from float64.
+struct Split {
+  const __bf16* hi;
+  const __bf16* lo;
+  const float* nrm;
+  int dp;
+};
+
 template <bool DOT>
 __device__ inline float kfun_mixed(float g, float yn, float xn, const KParams& kp) {
   if (DOT) {
@@ -139,7 +236,7 @@ __global__ void __launch_bounds__(NTH) k_level_kblock_mixed(const double* __rest
                                                             const int32_t* __restrict__ cols,
                                                             const int32_t* __restrict__ ncols_a, int n_cap,
                                                             const double* __restrict__ centroid,
-                                                            const unsigned char* __restrict__ mask,
+                                                            const unsigned char* __restrict__ mask, Split sp,
                                                             double* __restrict__ A, unsigned int* flag) {
   __shared__ MixSmem sm;
   const int tiles = tiles_m * tiles_n;
@@ -150,9 +247,13 @@ __global__ void __launch_bounds__(NTH) k_level_kblock_mixed(const double* __rest
   const int r0 = (tile % tiles_m) * TM, c0 = (tile / tiles_m) * TN;
   if (r0 >= s || c0 >= n) return;
   f32x4 acc[2][2];
-  mixed_tile<!DOT>(Xt, Idx{rows + (int64_t)node * s_cap + r0, 0}, min(TM, s - r0), Xt,
-                   Idx{cols + (int64_t)node * n_cap + c0, 0}, min(TN, n - c0), d, centroid + (int64_t)node * d, sm,
-                   acc);
+  if (sp.hi)
+    mixed_tile_split(sp.hi, sp.lo, sp.nrm, sp.dp, Idx{rows + (int64_t)node * s_cap + r0, 0}, min(TM, s - r0),
+                     Idx{cols + (int64_t)node * n_cap + c0, 0}, min(TN, n - c0), sm, acc);
+  else
+    mixed_tile<!DOT>(Xt, Idx{rows + (int64_t)node * s_cap + r0, 0}, min(TM, s - r0), Xt,
+                     Idx{cols + (int64_t)node * n_cap + c0, 0}, min(TN, n - c0), d, centroid + (int64_t)node * d, sm,
+                     acc);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   double* out = A + (int64_t)ln * s_cap * n_cap;
   bool bad = false;
@@ -180,12 +281,13 @@ template <bool DOT>
 __device__ inline void mixed_sum(const double* __restrict__ Y, Idx rows, int nrows, const double* __restrict__ X,
                                  Idx cols, int ncols, const double* __restrict__ q, int d,
                                  const double* __restrict__ center, const KParams& kp, MixSmem& sm, double (&part)[2],
-                                 bool& bad) {
+                                 bool& bad, Split sp = Split{nullptr, nullptr, nullptr, 0}) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int c0 = 0; c0 < ncols; c0 += TN) {
     Idx cm{cols.idx ? cols.idx + c0 : nullptr, cols.base + c0};
     f32x4 acc[2][2];
-    mixed_tile<!DOT>(Y, rows, nrows, X, cm, min(TN, ncols - c0), d, center, sm, acc);
+    if (sp.hi) mixed_tile_split(sp.hi, sp.lo, sp.nrm, sp.dp, rows, nrows, cm, min(TN, ncols - c0), sm, acc);
+    else mixed_tile<!DOT>(Y, rows, nrows, X, cm, min(TN, ncols - c0), d, center, sm, acc);
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
       const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
@@ -236,8 +338,9 @@ __global__ void __launch_bounds__(NTH) k_evaluate_mixed(const double* __restrict
                                                         const int32_t* __restrict__ skel, int r_cap,
                                                         const double* __restrict__ qt,
                                                         const double* __restrict__ centroid,
-                                                        const int32_t* __restrict__ perm, double* __restrict__ u,
-                                                        double* __restrict__ u_far, unsigned int* flag) {
+                                                        const int32_t* __restrict__ perm, Split sp,
+                                                        double* __restrict__ u, double* __restrict__ u_far,
+                                                        unsigned int* flag) {
   __shared__ MixSmem sm;
   __shared__ double red[8 * 64];
   __shared__ double far_sum[TM], near_sum[TM];
@@ -254,13 +357,13 @@ __global__ void __launch_bounds__(NTH) k_evaluate_mixed(const double* __restrict
     const int r = rank[sib];
     if (r > 0)
       mixed_sum<DOT>(Xt, rmap, nrows, Xt, Idx{skel + (int64_t)sib * r_cap, 0}, r, qt + (int64_t)sib * r_cap, d, cen,
-                     kp, sm, part, bad);
+                     kp, sm, part, bad, sp);
     a = (a - 1) >> 1;
   }
   mixed_reduce(part, red, far_sum);
   double npart[2] = {0.0, 0.0};
   const int lb = nb[leaf];
-  mixed_sum<DOT>(Xt, rmap, nrows, Xt, Idx{nullptr, lb}, ne[leaf] - lb, q_tree + lb, d, cen, kp, sm, npart, bad);
+  mixed_sum<DOT>(Xt, rmap, nrows, Xt, Idx{nullptr, lb}, ne[leaf] - lb, q_tree + lb, d, cen, kp, sm, npart, bad, sp);
   mixed_reduce(npart, red, near_sum);
   if (threadIdx.x < nrows) {
     const int ci = perm[start + threadIdx.x];
@@ -296,6 +399,33 @@ __global__ void __launch_bounds__(NTH) k_direct_mixed(const double* __restrict__
 
 }  // namespace
 
+namespace {
+// The tree's pre-split points and norms (made on first use; a stream being
+// captured must find them made).
+ffc_status tree_split(const ffc_tree* t, const KParams& kp, hipStream_t st, Split& sp) {
+  sp = Split{nullptr, nullptr, nullptr, 0};
+  if (kp.kind == FFC_LAPLACE) return FFC_OK;
+  ffc_tree* tm = const_cast<ffc_tree*>(t);
+  const int dp = (t->d + KCH - 1) / KCH * KCH;
+  const size_t n = (size_t)t->N * dp;
+  if (tm->bf_dp != dp || tm->bf_hi.count != n) {
+    FFC_TRY(tm->bf_hi.alloc(n));
+    FFC_TRY(tm->bf_lo.alloc(n));
+    FFC_TRY(tm->bf_nrm.alloc((size_t)t->N));
+    hipLaunchKernelGGL(k_bf16_split, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t->Xt.ptr, t->N, t->d, dp,
+                       reinterpret_cast<__bf16*>(tm->bf_hi.ptr), reinterpret_cast<__bf16*>(tm->bf_lo.ptr));
+    FFC_LAUNCH_CHECK("k_bf16_split");
+    hipLaunchKernelGGL(k_point_norms, dim3((unsigned)((t->N + 255) / 256)), dim3(256), 0, st, t->Xt.ptr, t->N, t->d,
+                       tm->bf_nrm.ptr);
+    FFC_LAUNCH_CHECK("k_point_norms");
+    tm->bf_dp = dp;
+  }
+  sp = Split{reinterpret_cast<const __bf16*>(t->bf_hi.ptr), reinterpret_cast<const __bf16*>(t->bf_lo.ptr),
+             kp.kind == FFC_GAUSSIAN ? t->bf_nrm.ptr : nullptr, dp};
+  return FFC_OK;
+}
+}  // namespace
+
 ffc_status launch_kblock_batch_mixed(const ffc_tree* t, const KParams& kp, const int32_t* rows, const int32_t* nrows,
                                      int s_cap, const int32_t* cols, const int32_t* ncols, int n_cap, int first,
                                      int count, const double* centroid, double* A, hipStream_t st,
@@ -303,27 +433,33 @@ ffc_status launch_kblock_batch_mixed(const ffc_tree* t, const KParams& kp, const
   const int tiles_m = (s_cap + TM - 1) / TM, tiles_n = (n_cap + TN - 1) / TN;
   const int64_t blocks = (int64_t)count * tiles_m * tiles_n;
   if (blocks == 0) return FFC_OK;
+  Split sp;
+  FFC_TRY(tree_split(t, kp, st, sp));
   if (kp.kind == FFC_POLYNOMIAL)
     hipLaunchKernelGGL(k_level_kblock_mixed<true>, dim3((unsigned)blocks), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
-                       first, tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, centroid, mask, A, device_flag());
+                       first, tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, centroid, mask, sp, A,
+                       device_flag());
   else
     hipLaunchKernelGGL(k_level_kblock_mixed<false>, dim3((unsigned)blocks), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
-                       first, tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, centroid, mask, A, device_flag());
+                       first, tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, centroid, mask, sp, A,
+                       device_flag());
   FFC_LAUNCH_CHECK("k_level_kblock_mixed");
   return FFC_OK;
 }
 
 ffc_status launch_evaluate_mixed(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, double* u, double* u_far,
                                  hipStream_t st) {
+  Split sp;
+  FFC_TRY(tree_split(t, kp, st, sp));
   if (kp.kind == FFC_POLYNOMIAL)
     hipLaunchKernelGGL(k_evaluate_mixed<true>, dim3((unsigned)t->num_tiles), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
                        t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
-                       sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->centroid.ptr, t->perm.ptr, u, u_far,
+                       sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->centroid.ptr, t->perm.ptr, sp, u, u_far,
                        device_flag());
   else
     hipLaunchKernelGGL(k_evaluate_mixed<false>, dim3((unsigned)t->num_tiles), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
                        t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
-                       sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->centroid.ptr, t->perm.ptr, u, u_far,
+                       sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->centroid.ptr, t->perm.ptr, sp, u, u_far,
                        device_flag());
   FFC_LAUNCH_CHECK("k_evaluate_mixed");
   return FFC_OK;
