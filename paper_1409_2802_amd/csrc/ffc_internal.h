@@ -211,7 +211,7 @@ struct ffc_skel {
   // skeleton points (num_nodes x r_cap) and the far field in tree order.
   double fmm_xi = -1.0;
   ffc::DevBuf<int32_t> fmm_far_off, fmm_far_src, fmm_near_off, fmm_near_src;
-  ffc::DevBuf<double> fmm_v, fmm_ufar;
+  ffc::DevBuf<double> fmm_v, fmm_vpart, fmm_ufar;   // vpart: partial sums of the list quarters
   int64_t fmm_far_pairs = 0, fmm_near_pairs = 0;
   hipStream_t last_stream = nullptr;
 };

@@ -14,7 +14,8 @@
 //     pairs, other leaf pairs are direct pairs, other pairs recurse into their
 //     four child pairs. Pairs are visited in (target, source) order;
 //   * k_m2l: v_b = sum over b's list of K(x_{J_b}, x_{J_a}) q~_a, one workgroup
-//     per (node, 64 skeleton points);
+//     per (node, 64 skeleton points, quarter of the list: entries e with
+//     e mod 4 = part), whose partial sums k_m2l_fold adds in part order;
 //   * k_l2l (top-down, one launch per level): P_b^T v_b is added to the
 //     children's v at their skeleton points, or is the far field at a leaf's
 //     points; one thread per column, the rank loop in a fixed order;
@@ -58,31 +59,49 @@ __global__ void k_fmm_admissible(const uint64_t* __restrict__ bits, int words, c
   adm[p] = ok ? 1 : 0;
 }
 
+constexpr int kM2lParts = 4;
+
 template <typename T, bool DOT, int DM>
 __global__ void __launch_bounds__(NT) k_m2l(const double* __restrict__ Xt, int d, KParams kp, int chunks,
-                                            const int32_t* __restrict__ rank, const int32_t* __restrict__ skel,
-                                            int r_cap, const double* __restrict__ qt,
-                                            const int32_t* __restrict__ off, const int32_t* __restrict__ src,
-                                            double* __restrict__ v, unsigned int* flag) {
+                                            int num_nodes, const int32_t* __restrict__ rank,
+                                            const int32_t* __restrict__ skel, int r_cap,
+                                            const double* __restrict__ qt, const int32_t* __restrict__ off,
+                                            const int32_t* __restrict__ src, double* __restrict__ vpart,
+                                            unsigned int* flag) {
   __shared__ TileSmem<T> sm;
   __shared__ double red[16 * BM];
   __shared__ double rowsum[BM];
-  const int b = 1 + blockIdx.x / chunks, c = blockIdx.x % chunks;
+  const int part = blockIdx.x % kM2lParts;
+  const int bc = blockIdx.x / kM2lParts;
+  const int b = 1 + bc / chunks, c = bc % chunks;
   const int nrows = min(BM, rank[b] - c * BM);
   if (nrows <= 0) return;
   const IdxMap rmap{skel + (int64_t)b * r_cap + c * BM, 0};
   if constexpr (DM > 0) stage_rows<T, DM>(Xt, rmap, nrows, d, sm);
   bool bad = false;
-  double part[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int e = off[b]; e < off[b + 1]; ++e) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int e = off[b] + part; e < off[b + 1]; e += kM2lParts) {
     const int a = src[e];
     if (rank[a] > 0)
       sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)a * r_cap, 0}, rank[a],
-                          qt + (int64_t)a * r_cap, d, kp, sm, part, bad);
+                          qt + (int64_t)a * r_cap, d, kp, sm, acc, bad);
   }
-  reduce_rows(part, red, rowsum);
-  if (threadIdx.x < nrows) v[(int64_t)b * r_cap + c * BM + threadIdx.x] = rowsum[threadIdx.x];
+  reduce_rows(acc, red, rowsum);
+  if (threadIdx.x < nrows)
+    vpart[((int64_t)part * num_nodes + b) * r_cap + c * BM + threadIdx.x] = rowsum[threadIdx.x];
   if (bad) flag_nonfinite(flag);
+}
+
+// v_b = the partial sums of b's list quarters, in part order.
+__global__ void k_m2l_fold(int num_nodes, int r_cap, const int32_t* __restrict__ rank,
+                           const double* __restrict__ vpart, double* __restrict__ v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)num_nodes * r_cap) return;
+  const int b = (int)(e / r_cap), i = (int)(e % r_cap);
+  if (b == 0 || i >= rank[b]) return;
+  double s = 0.0;
+  for (int p = 0; p < kM2lParts; ++p) s += vpart[(int64_t)p * num_nodes * r_cap + e];
+  v[e] = s;
 }
 
 // Nodes [first, first + count) of one level: w = P_b^T v_b at b's columns, added
@@ -233,7 +252,9 @@ ffc_status launch_fmm(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int pr
     return FFC_ERR_INVALID_ARG;
   }
   if (sk->fmm_xi != sk->opts.separation || !sk->fmm_far_off.ptr) FFC_TRY(build_fmm_lists(t, sk, st));
-  if (sk->fmm_v.count != (size_t)t->num_nodes * sk->r_cap) FFC_TRY(sk->fmm_v.alloc((size_t)t->num_nodes * sk->r_cap));
+  const size_t nv = (size_t)t->num_nodes * sk->r_cap;
+  if (sk->fmm_v.count != nv) FFC_TRY(sk->fmm_v.alloc(nv));
+  if (sk->fmm_vpart.count != nv * kM2lParts) FFC_TRY(sk->fmm_vpart.alloc(nv * kM2lParts));
   if (sk->fmm_ufar.count != (size_t)t->N) FFC_TRY(sk->fmm_ufar.alloc((size_t)t->N));
   const bool dot = kp.kind == FFC_POLYNOMIAL;
   const int chunks = (sk->r_cap + BM - 1) / BM;
@@ -243,10 +264,14 @@ ffc_status launch_fmm(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int pr
     constexpr bool D = decltype(dv)::value;
     return with_dims(t->d, [&](auto dm) -> ffc_status {
       constexpr int DM = decltype(dm)::value;
-      hipLaunchKernelGGL((k_m2l<T, D, DM>), dim3((unsigned)((t->num_nodes - 1) * chunks)), dim3(NT), 0, st, t->Xt.ptr,
-                         t->d, kp, chunks, sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, sk->fmm_far_off.ptr,
-                         sk->fmm_far_src.ptr, sk->fmm_v.ptr, device_flag());
+      hipLaunchKernelGGL((k_m2l<T, D, DM>), dim3((unsigned)((t->num_nodes - 1) * chunks * kM2lParts)), dim3(NT), 0, st,
+                         t->Xt.ptr, t->d, kp, chunks, t->num_nodes, sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr,
+                         sk->fmm_far_off.ptr, sk->fmm_far_src.ptr, sk->fmm_vpart.ptr, device_flag());
       FFC_LAUNCH_CHECK("k_m2l");
+      const int64_t nv = (int64_t)t->num_nodes * sk->r_cap;
+      hipLaunchKernelGGL(k_m2l_fold, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st, t->num_nodes, sk->r_cap,
+                         sk->rank.ptr, sk->fmm_vpart.ptr, sk->fmm_v.ptr);
+      FFC_LAUNCH_CHECK("k_m2l_fold");
       for (int l = 1; l <= t->depth; ++l) {
         const int first = (1 << l) - 1, count = 1 << l;
         hipLaunchKernelGGL(k_l2l, dim3((unsigned)count, (unsigned)((sk->n_cap + 255) / 256)), dim3(256), 0, st, first,
