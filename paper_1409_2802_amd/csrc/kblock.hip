@@ -1,5 +1,7 @@
-// Kernel-function tiles: sampled blocks K', far/near-field evaluation and the
-// direct sum.
+// Kernel-function tiles: sampled blocks K', far/near-field evaluation (the
+// sibling cover, and the treecode with separation of Section 2 together with
+// its per-node separation bitmaps) and the direct sum. Kernel values and the
+// tile sums live in tile_sums.h, shared with the FMM-style kernels (fmm.hip).
 //
 // Every stage that evaluates the kernel shares one tile engine: a 256-thread
 // workgroup computes a 64 x 64 tile of squared distances (Gaussian, Laplace)
@@ -486,8 +488,8 @@ ffc_status launch_direct_sum(const double* Y, int64_t m, const double* X, int64_
     constexpr bool D = decltype(dv)::value;
     return with_dims(d, [&](auto dm) -> ffc_status {
       constexpr int DM = decltype(dm)::value;
-      hipLaunchKernelGGL((k_direct<T, D, DM>), dim3((unsigned)((m + BM - 1) / BM)), dim3(NT), 0, st, Y, m, X, n, d, kp, q,
-                         u, device_flag());
+      hipLaunchKernelGGL((k_direct<T, D, DM>), dim3((unsigned)((m + BM - 1) / BM)), dim3(NT), 0, st, Y, m, X, n, d,
+                         kp, q, u, device_flag());
       FFC_LAUNCH_CHECK("k_direct");
       return FFC_OK;
     });
