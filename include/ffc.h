@@ -254,6 +254,25 @@ ffc_status ffc_skel_node(const ffc_skel* sk, int32_t node, int32_t* rank, int32_
                          int32_t* n_rows, int32_t* cols_host, int32_t* rows_host,
                          int32_t* skel_host, double* P_host);
 
+/* A skeleton set from host arrays, such as a checkpoint written with
+ * ffc_skel_node, for evaluation without skeletonizing. For every node a in
+ * [1, num_nodes): rank_host[a] and ncols_host[a]; skel_host[a * r_max + i]
+ * (i < rank, tree positions) and P_host[(a * r_max + i) * n_max + j]
+ * (i < rank, j < ncols; entries past them are ignored). The columns are
+ * implied by the tree: a leaf's points, an internal node's children's
+ * skeletons (left, then right), so ncols must be the leaf's size or the sum of
+ * the children's ranks. Only opts->separation is read (> 0 prepares the
+ * separation bitmaps for the treecode and FMM-style evaluations); no rows are
+ * stored, so the set cannot be passed back to ffc_skeletonize_nodes. Copies
+ * the arrays (they may be freed on return) and synchronizes `stream`.
+ * Errors: NULL arguments, r_max or n_max < 1, a rank outside [0,
+ * min(r_max, ncols)], an ncols that breaks the nesting or exceeds n_max, a
+ * skeleton id outside [0, N), a non-finite P entry, separation < 0 ->
+ * FFC_ERR_INVALID_ARG. */
+ffc_status ffc_skel_load(const ffc_tree* t, const ffc_skel_opts* o, const int32_t* rank_host,
+                         const int32_t* ncols_host, const int32_t* skel_host, const double* P_host,
+                         int32_t r_max, int32_t n_max, void* stream, ffc_skel** out);
+
 typedef struct {
   int32_t num_nodes;        /* skeletonized nodes (all non-root nodes) */
   int32_t rank_min, rank_max;
@@ -317,6 +336,13 @@ ffc_status ffc_proposal_create(const float* theta_host, const float* mu_host, co
 /* Copies the current theta / mu / sd to the host (any may be NULL); synchronizes
  * the device. */
 ffc_status ffc_proposal_get(const ffc_proposal* p, float* theta_host, float* mu_host, float* sd_host);
+/* Adam state, for checkpoints that resume training: the first and second
+ * moments (FFC_PROPOSAL_NPARAM float32 each) and the number of steps taken.
+ * get: any output may be NULL; synchronizes the device. set: m1_host and
+ * m2_host required, step >= 0; synchronous. Errors: NULL handle, NULL moments
+ * (set), step < 0 or non-finite moments -> FFC_ERR_INVALID_ARG. */
+ffc_status ffc_proposal_get_adam(const ffc_proposal* p, float* m1_host, float* m2_host, int32_t* step);
+ffc_status ffc_proposal_set_adam(ffc_proposal* p, const float* m1_host, const float* m2_host, int32_t step);
 void ffc_proposal_free(ffc_proposal* p);
 
 /* Features of target rows against column sets, for `count` blocks: block g

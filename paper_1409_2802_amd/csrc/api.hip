@@ -557,6 +557,87 @@ ffc_status ffc_skel_node(const ffc_skel* sk, int32_t node, int32_t* rank, int32_
   return FFC_OK;
 }
 
+ffc_status ffc_skel_load(const ffc_tree* t, const ffc_skel_opts* o, const int32_t* rank_host,
+                         const int32_t* ncols_host, const int32_t* skel_host, const double* P_host, int32_t r_max,
+                         int32_t n_max, void* stream, ffc_skel** out) {
+  if (!t || !o || !rank_host || !ncols_host || !skel_host || !P_host || !out)
+    return fail(FFC_ERR_INVALID_ARG, "NULL argument");
+  if (r_max < 1 || n_max < 1) return fail(FFC_ERR_INVALID_ARG, "r_max and n_max must be >= 1");
+  if (!(o->separation >= 0.0)) return fail(FFC_ERR_INVALID_ARG, "separation must be >= 0");
+  if (o->separation > 0.0 && t->depth > 30)
+    return fail(FFC_ERR_INVALID_ARG, "separation supports trees of depth <= 30");
+  const int nn = t->num_nodes, leaf0 = (1 << t->depth) - 1;
+  for (int a = 1; a < nn; ++a) {
+    const int n = ncols_host[a], r = rank_host[a];
+    const int want = a >= leaf0 ? t->end_h[a] - t->begin_h[a] : rank_host[2 * a + 1] + rank_host[2 * a + 2];
+    if (n != want || n > n_max)
+      return fail(FFC_ERR_INVALID_ARG, "node " + std::to_string(a) + ": ncols must be the leaf size or the sum "
+                                       "of the children's ranks, and at most n_max");
+    if (r < 0 || r > std::min(r_max, n))
+      return fail(FFC_ERR_INVALID_ARG, "node " + std::to_string(a) + ": rank outside [0, min(r_max, ncols)]");
+    for (int i = 0; i < r; ++i) {
+      const int32_t j = skel_host[(int64_t)a * r_max + i];
+      if (j < 0 || j >= t->N) return fail(FFC_ERR_INVALID_ARG, "skeleton id outside [0, N)");
+      for (int c = 0; c < n; ++c)
+        if (!std::isfinite(P_host[((int64_t)a * r_max + i) * n_max + c]))
+          return fail(FFC_ERR_INVALID_ARG, "P entries must be finite");
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  ffc_skel* sk = new ffc_skel();
+  sk->num_nodes = nn;
+  sk->depth = t->depth;
+  sk->s_cap = 1;
+  sk->r_cap = r_max;
+  sk->n_cap = n_max;
+  sk->opts = *o;
+  sk->opts.max_rank = r_max;
+  auto load = [&]() -> ffc_status {
+    std::vector<int32_t> nrows(nn, 0), rank(rank_host, rank_host + nn), ncols(ncols_host, ncols_host + nn);
+    rank[0] = ncols[0] = 0;
+    // Column lists implied by the nesting (for ffc_skel_node): leaf ranges,
+    // else the children's skeletons.
+    std::vector<int32_t> cols((size_t)nn * n_max, 0);
+    for (int a = 1; a < nn; ++a) {
+      int32_t* c = cols.data() + (int64_t)a * n_max;
+      if (a >= leaf0) {
+        for (int j = 0; j < ncols[a]; ++j) c[j] = t->begin_h[a] + j;
+      } else {
+        const int l = 2 * a + 1;
+        std::copy(skel_host + (int64_t)l * r_max, skel_host + (int64_t)l * r_max + rank[l], c);
+        std::copy(skel_host + (int64_t)(l + 1) * r_max, skel_host + (int64_t)(l + 1) * r_max + rank[l + 1],
+                  c + rank[l]);
+      }
+    }
+    FFC_TRY(sk->rank.alloc(nn));
+    FFC_TRY(sk->ncols.alloc(nn));
+    FFC_TRY(sk->nrows.alloc(nn));
+    FFC_TRY(sk->cols.alloc((size_t)nn * n_max));
+    FFC_TRY(sk->rows.alloc((size_t)nn));
+    FFC_TRY(sk->piv.alloc((size_t)nn * n_max));
+    FFC_TRY(sk->skel.alloc((size_t)nn * r_max));
+    FFC_TRY(sk->P.alloc((size_t)nn * r_max * n_max));
+    FFC_TRY(sk->qt.alloc((size_t)nn * r_max));
+    FFC_HIP_TRY(hipMemcpy(sk->rank.ptr, rank.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice));
+    FFC_HIP_TRY(hipMemcpy(sk->ncols.ptr, ncols.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice));
+    FFC_HIP_TRY(hipMemcpy(sk->nrows.ptr, nrows.data(), nn * sizeof(int32_t), hipMemcpyHostToDevice));
+    FFC_HIP_TRY(hipMemcpy(sk->cols.ptr, cols.data(), cols.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    FFC_HIP_TRY(hipMemcpy(sk->skel.ptr, skel_host, (size_t)nn * r_max * sizeof(int32_t), hipMemcpyHostToDevice));
+    FFC_HIP_TRY(hipMemcpy(sk->P.ptr, P_host, (size_t)nn * r_max * n_max * sizeof(double), hipMemcpyHostToDevice));
+    if (o->separation > 0.0) FFC_TRY(launch_separation(t, sk, o->separation, st));
+    FFC_HIP_TRY(hipStreamSynchronize(st));
+    return FFC_OK;
+  };
+  const ffc_status s = load();
+  if (s != FFC_OK) {
+    delete sk;
+    return s;
+  }
+  sk->last_stream = st;
+  *out = sk;
+  return FFC_OK;
+}
+
 ffc_status ffc_skel_stats(const ffc_skel* sk, ffc_stats* out) {
   if (!sk || !out) return fail(FFC_ERR_INVALID_ARG, "NULL argument");
   FFC_HIP_TRY(hipStreamSynchronize(sk->last_stream));

@@ -354,6 +354,29 @@ ffc_status ffc_proposal_create(const float* theta_host, const float* mu_host, co
   return FFC_OK;
 }
 
+ffc_status ffc_proposal_get_adam(const ffc_proposal* p, float* m1_host, float* m2_host, int32_t* step) {
+  if (!p) return fail(FFC_ERR_INVALID_ARG, "proposal is NULL");
+  FFC_HIP_TRY(hipDeviceSynchronize());
+  if (m1_host) FFC_HIP_TRY(hipMemcpy(m1_host, p->m1.ptr, kNParam * sizeof(float), hipMemcpyDeviceToHost));
+  if (m2_host) FFC_HIP_TRY(hipMemcpy(m2_host, p->m2.ptr, kNParam * sizeof(float), hipMemcpyDeviceToHost));
+  if (step) *step = p->step;
+  return FFC_OK;
+}
+
+ffc_status ffc_proposal_set_adam(ffc_proposal* p, const float* m1_host, const float* m2_host, int32_t step) {
+  if (!p || !m1_host || !m2_host) return fail(FFC_ERR_INVALID_ARG, "proposal or moments are NULL");
+  if (step < 0) return fail(FFC_ERR_INVALID_ARG, "step must be >= 0");
+  if (!all_finite(m1_host, kNParam) || !all_finite(m2_host, kNParam))
+    return fail(FFC_ERR_INVALID_ARG, "Adam moments must be finite");
+  for (int i = 0; i < kNParam; ++i)
+    if (m2_host[i] < 0.f) return fail(FFC_ERR_INVALID_ARG, "second moments must be >= 0");
+  FFC_HIP_TRY(hipDeviceSynchronize());
+  FFC_HIP_TRY(hipMemcpy(p->m1.ptr, m1_host, kNParam * sizeof(float), hipMemcpyHostToDevice));
+  FFC_HIP_TRY(hipMemcpy(p->m2.ptr, m2_host, kNParam * sizeof(float), hipMemcpyHostToDevice));
+  p->step = step;
+  return FFC_OK;
+}
+
 ffc_status ffc_proposal_get(const ffc_proposal* p, float* theta_host, float* mu_host, float* sd_host) {
   if (!p) return fail(FFC_ERR_INVALID_ARG, "proposal is NULL");
   FFC_HIP_TRY(hipDeviceSynchronize());

@@ -32,6 +32,7 @@ EXPORTS = [
     "ffc_proposal_fit_standardization", "ffc_proposal_score", "ffc_proposal_gradient", "ffc_proposal_adam",
     "ffc_leverage_labels", "ffc_proposal_train", "ffc_proposal_training_set",
     "ffc_step_graph_create", "ffc_graph_launch", "ffc_graph_free", "ffc_autotune_report",
+    "ffc_skel_load", "ffc_proposal_get_adam", "ffc_proposal_set_adam",
 ]
 
 NPARAM = 5313
@@ -96,6 +97,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ffc_interp_decomp": [P, I32, I32, I32, D, I32, P, P, P, P],
         "ffc_skel_node": [P, I32, P, P, P, P, P, P, P],
         "ffc_skel_stats": [P, ctypes.POINTER(StatsC)],
+        "ffc_skel_load": [P, ctypes.POINTER(SkelOptsC), P, P, P, P, I32, I32, P, PP],
+        "ffc_proposal_get_adam": [P, P, P, P],
+        "ffc_proposal_set_adam": [P, P, P, I32],
         "ffc_check_device": [P],
         "ffc_profile_enable": [I32],
         "ffc_profile_read": [P, P, I32, I32],
@@ -249,10 +253,52 @@ class Skeletons:
         _check(load_library().ffc_skel_stats(self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in StatsC._fields_}
 
+    def export(self) -> dict:
+        """Every node's rank, column count, skeleton and P in the padded layout of ffc_skel_load."""
+        nn = self.tree.num_nodes
+        nodes = {a: self.node(a) for a in range(1, nn)}
+        r_max = max([1] + [v["rank"] for v in nodes.values()])
+        n_max = max([1] + [len(v["cols"]) for v in nodes.values()])
+        rank = np.zeros(nn, dtype=np.int32)
+        ncols = np.zeros(nn, dtype=np.int32)
+        skel = np.zeros((nn, r_max), dtype=np.int32)
+        P = np.zeros((nn, r_max, n_max), dtype=np.float64)
+        for a, v in nodes.items():
+            r, n = v["rank"], len(v["cols"])
+            rank[a], ncols[a] = r, n
+            skel[a, :r] = v["skel"]
+            P[a, :r, :n] = v["P"]
+        return {"rank": rank, "ncols": ncols, "skel": skel, "P": P}
+
+    def save(self, path: str, separation: float = 0.0) -> None:
+        """Checkpoint (numpy .npz of plain arrays) that load_skeletons reads back."""
+        np.savez(path, separation=np.float64(separation), **self.export())
+
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.ffc_free_skel(self._h)
             self._h = None
+
+
+def load_skeletons(tree: Tree, source, separation: float | None = None, stream=None) -> Skeletons:
+    """A skeleton set from Skeletons.export() arrays or a Skeletons.save() checkpoint, for evaluation."""
+    if isinstance(source, (str, os.PathLike)):
+        with np.load(source, allow_pickle=False) as z:
+            source = {k: z[k] for k in z.files}
+    if separation is None:
+        separation = float(source.get("separation", 0.0))
+    rank = np.ascontiguousarray(source["rank"], dtype=np.int32)
+    ncols = np.ascontiguousarray(source["ncols"], dtype=np.int32)
+    skel = np.ascontiguousarray(source["skel"], dtype=np.int32)
+    P = np.ascontiguousarray(source["P"], dtype=np.float64)
+    if rank.shape != (tree.num_nodes,) or skel.shape[0] != tree.num_nodes or P.shape[:2] != skel.shape:
+        raise ValueError("checkpoint arrays do not match the tree")
+    opts = SkelOptsC(separation=separation)
+    h = ctypes.c_void_p()
+    _check(load_library().ffc_skel_load(tree.handle, ctypes.byref(opts), rank.ctypes.data, ncols.ctypes.data,
+                                        skel.ctypes.data, P.ctypes.data, skel.shape[1], P.shape[2], _stream(stream),
+                                        ctypes.byref(h)))
+    return Skeletons(h, tree)
 
 
 def skeletonize(tree: Tree, kernel: Kernel, tol: float, max_rank: int, num_samples: int = 0,
@@ -436,6 +482,33 @@ class Proposal:
         sd = np.empty(NFEAT, dtype=np.float32)
         _check(load_library().ffc_proposal_get(self._h, th.ctypes.data, mu.ctypes.data, sd.ctypes.data))
         return th, mu, sd
+
+    def adam_state(self):
+        m1 = np.empty(NPARAM, dtype=np.float32)
+        m2 = np.empty(NPARAM, dtype=np.float32)
+        step = ctypes.c_int32()
+        _check(load_library().ffc_proposal_get_adam(self._h, m1.ctypes.data, m2.ctypes.data, ctypes.byref(step)))
+        return m1, m2, step.value
+
+    def set_adam_state(self, m1, m2, step: int) -> None:
+        a = np.ascontiguousarray(m1, dtype=np.float32)
+        b = np.ascontiguousarray(m2, dtype=np.float32)
+        if a.shape != (NPARAM,) or b.shape != (NPARAM,):
+            raise ValueError(f"moments must have {NPARAM} entries")
+        _check(load_library().ffc_proposal_set_adam(self._h, a.ctypes.data, b.ctypes.data, int(step)))
+
+    def save(self, path: str) -> None:
+        """Checkpoint (numpy .npz): parameters, standardization and Adam state."""
+        th, mu, sd = self.get()
+        m1, m2, step = self.adam_state()
+        np.savez(path, theta=th, mu=mu, sd=sd, m1=m1, m2=m2, step=np.int32(step))
+
+    @classmethod
+    def load(cls, path: str) -> "Proposal":
+        with np.load(path, allow_pickle=False) as z:
+            p = cls(z["theta"], z["mu"], z["sd"])
+            p.set_adam_state(z["m1"], z["m2"], int(z["step"]))
+        return p
 
     def fit_standardization(self, feat: torch.Tensor, stream=None) -> None:
         f = _dev_f32(feat, "feat")
