@@ -2,6 +2,7 @@
 // management and the level-by-level schedule of the skeletonization.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -75,6 +76,11 @@ ffc_status finish_tree_common(ffc_tree* t, hipStream_t st) {
 void set_error(const std::string& msg) { g_error = msg; }
 
 ffc_status validate_kernel(const ffc_kernel* k, int d) { return check_kernel(k, d); }
+
+bool alloc_forced_to_fail() {
+  const char* e = std::getenv("FFC_FAIL_ALLOC");
+  return e && e[0] == '1';
+}
 
 KParams make_kparams(const ffc_kernel& k, int d) {
   KParams p{};

@@ -89,6 +89,10 @@ unsigned int* device_flag();
 // ---------------------------------------------------------------------------
 // Opaque handle layouts
 // ---------------------------------------------------------------------------
+// Failure injection for tests: with FFC_FAIL_ALLOC=1 in the environment every
+// device allocation of the library fails with FFC_ERR_OOM.
+bool alloc_forced_to_fail();
+
 template <typename T>
 struct DevBuf {
   T* ptr = nullptr;
@@ -105,6 +109,10 @@ struct DevBuf {
   ffc_status alloc(size_t n) {
     release();
     if (n == 0) return FFC_OK;
+    if (alloc_forced_to_fail()) {
+      set_error("device allocation refused (FFC_FAIL_ALLOC is set)");
+      return FFC_ERR_OOM;
+    }
     hipError_t e = hipMalloc(&ptr, n * sizeof(T));
     if (e != hipSuccess) {
       ptr = nullptr;

@@ -91,3 +91,31 @@ def test_proposal_checkpoint_resumes_training(ffc, tmp_path):
         np.testing.assert_array_equal(x, y)
     with pytest.raises(ffc.FfcError):
         b.set_adam_state(np.zeros(ffc.NPARAM), -np.ones(ffc.NPARAM), 1)
+
+
+def test_forced_allocation_failure_is_reported_and_recoverable(ffc, monkeypatch):
+    """With FFC_FAIL_ALLOC=1 every device allocation of the library fails: the
+    calls that allocate return FFC_ERR_OOM with a message, leave the existing
+    handles usable, and work again once the knob is cleared."""
+    X = W.uniform_cube(2048, 4, seed=2)
+    t = ffc.build_tree(X, 128)
+    k = gkernel(GAUSSIAN, h=0.5)
+    sk = ffc.skeletonize(t, k, tol=1e-6, max_rank=16, num_samples=32)
+    q = W.charges(2048, seed=3)
+    u0, _ = ffc.evaluate_sum(t, sk, k, q)
+    monkeypatch.setenv("FFC_FAIL_ALLOC", "1")
+    for call in (lambda: ffc.build_tree(X, 128),
+                 lambda: ffc.skeletonize(t, k, tol=1e-6, max_rank=16, num_samples=32),
+                 lambda: ffc.skeletonize(t, k, tol=1e-6, max_rank=16, num_samples=32, separation=1.0)):
+        with pytest.raises(ffc.FfcError) as e:
+            call()
+        assert e.value.code == ffc.FFC_ERR_OOM and "FFC_FAIL_ALLOC" in str(e.value)
+    # Reusing a handle allocates nothing new: it still works under the knob.
+    ffc.skeletonize(t, k, tol=1e-6, max_rank=16, num_samples=32, reuse=sk)
+    u1, _ = ffc.evaluate_sum(t, sk, k, q)
+    assert torch.equal(u0, u1)
+    monkeypatch.delenv("FFC_FAIL_ALLOC")
+    ffc.check_device()
+    sk2 = ffc.skeletonize(t, k, tol=1e-6, max_rank=16, num_samples=32)
+    u2, _ = ffc.evaluate_sum(t, sk2, k, q)
+    assert torch.equal(u0, u2)
