@@ -1,6 +1,10 @@
 // Stage profiler: optional HIP events around every stage launch, recorded on
-// the stream the stage runs on, accumulated per stage on read.
+// the stream the stage runs on, accumulated per stage on read. Every stage is
+// also a roctx range ("ffc:<stage>"), which rocprofv3 --marker-trace records
+// beside the kernel trace.
 #include <mutex>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "ffc_internal.h"
 
@@ -37,7 +41,12 @@ int64_t g_launches[FFC_NUM_STAGES] = {};
 
 bool profiling() { return g_on; }
 
+const char* const kStageRanges[FFC_NUM_STAGES] = {
+    "ffc:tree",  "ffc:sample", "ffc:columns",  "ffc:kblock",  "ffc:cpqr",   "ffc:skel",   "ffc:upward",
+    "ffc:evaluate", "ffc:direct", "ffc:solve", "ffc:proposal", "ffc:heldout", "ffc:labels", "ffc:train"};
+
 StageTimer::StageTimer(int stage, hipStream_t st) : stage_(stage), st_(st) {
+  roctxRangePushA(kStageRanges[stage]);
   if (!g_on) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;   // not inside graphs
@@ -48,6 +57,7 @@ StageTimer::StageTimer(int stage, hipStream_t st) : stage_(stage), st_(st) {
 }
 
 StageTimer::~StageTimer() {
+  roctxRangePop();
   if (!active_) return;
   (void)hipEventRecord(stop_, st_);
   std::lock_guard<std::mutex> lock(g_mu);
