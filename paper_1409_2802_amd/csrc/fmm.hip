@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(NT) k_m2l(const double* __restrict__ Xt, int d
                                             const double* __restrict__ qt, const int32_t* __restrict__ off,
                                             const int32_t* __restrict__ src, double* __restrict__ vpart,
                                             unsigned int* flag) {
-  __shared__ TileSmem<T> sm;
+  __shared__ EvalSmem<T, DM> sm;
   __shared__ double red[16 * BM];
   __shared__ double rowsum[BM];
   const int part = blockIdx.x % kM2lParts;
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(NT) k_p2p(const double* __restrict__ Xt, int d
                                             const int32_t* __restrict__ src, const double* __restrict__ ufar,
                                             const int32_t* __restrict__ perm, double* __restrict__ u,
                                             double* __restrict__ u_far, unsigned int* flag) {
-  __shared__ TileSmem<T> sm;
+  __shared__ EvalSmem<T, DM> sm;
   __shared__ double red[16 * BM];
   __shared__ double near_sum[BM];
   const int leaf = tile_leaf[blockIdx.x];

@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(NT) k_evaluate(const double* __restrict__ Xt, 
                                                  int r_cap, const double* __restrict__ qt,
                                                  const int32_t* __restrict__ perm, double* __restrict__ u,
                                                  double* __restrict__ u_far, unsigned int* flag) {
-  __shared__ TileSmem<T> sm;
+  __shared__ EvalSmem<T, DM> sm;
   __shared__ double red[16 * BM];
   __shared__ double far_sum[BM], near_sum[BM];
   const int leaf = tile_leaf[blockIdx.x];
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(NT) k_treecode(const double* __restrict__ Xt, 
                                                  const uint64_t* __restrict__ sep_bits, int words,
                                                  const int32_t* __restrict__ perm, double* __restrict__ u,
                                                  double* __restrict__ u_far, unsigned int* flag) {
-  __shared__ TileSmem<T> sm;
+  __shared__ EvalSmem<T, DM> sm;
   __shared__ double red[16 * BM];
   __shared__ double far_sum[BM], near_sum[BM];
   __shared__ int stack[64];
@@ -322,7 +322,7 @@ template <typename T, bool DOT, int DM>
 __global__ void __launch_bounds__(NT) k_direct(const double* __restrict__ Y, int64_t m, const double* __restrict__ X,
                                                int64_t n, int d, KParams kp, const double* __restrict__ q,
                                                double* __restrict__ u, unsigned int* flag) {
-  __shared__ TileSmem<T> sm;
+  __shared__ EvalSmem<T, DM> sm;
   __shared__ double red[16 * BM];
   __shared__ double rowsum[BM];
   const int64_t r0 = (int64_t)blockIdx.x * BM;

@@ -21,10 +21,12 @@ namespace tile {
 constexpr int BM = 64, BN = 64, KC = 32, NT = 256;
 constexpr int LDSP = BM + 1;   // padded LDS row (bank spread)
 
-template <typename T>
+// K dimensions per chunk (KC for the general path; the evaluation kernels for
+// small d stage only DM of them and size their LDS to match).
+template <typename T, int K = KC>
 struct TileSmem {
-  T ys[KC][LDSP];
-  T xs[KC][LDSP];
+  T ys[K][LDSP];
+  T xs[K][LDSP];
 };
 
 // Row / column index maps: an explicit index list or a contiguous range.

@@ -102,8 +102,13 @@ __device__ inline void sum_over_sources(const double* __restrict__ Y, IdxMap row
 // one is computed. The arithmetic per pair is that of sum_over_sources (same
 // order), so the results are the same bits. DM = 0 selects sum_over_sources.
 // ---------------------------------------------------------------------------
+// LDS of the evaluation kernels: DM dimensions per chunk when DM > 0.
 template <typename T, int DM>
-__device__ inline void stage_rows(const double* __restrict__ Y, IdxMap rows, int nrows, int d, TileSmem<T>& sm) {
+using EvalSmem = TileSmem<T, (DM > 0 ? DM : KC)>;
+
+template <typename T, int DM>
+__device__ inline void stage_rows(const double* __restrict__ Y, IdxMap rows, int nrows, int d,
+                                  EvalSmem<T, DM>& sm) {
   const int tid = threadIdx.x;
   const int sh = 32 - __clz(d - 1);
 #pragma unroll
@@ -118,7 +123,7 @@ __device__ inline void stage_rows(const double* __restrict__ Y, IdxMap rows, int
 
 template <typename T, bool DOT, int DM>
 __device__ inline void sum_staged_rows(const double* __restrict__ X, IdxMap cols, int ncols,
-                                       const double* __restrict__ q, int d, const KParams& kp, TileSmem<T>& sm,
+                                       const double* __restrict__ q, int d, const KParams& kp, EvalSmem<T, DM>& sm,
                                        double (&part)[4], bool& bad) {
   constexpr int IT = BM * DM / NT;
   const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
@@ -195,7 +200,7 @@ __device__ inline void sum_staged_rows(const double* __restrict__ X, IdxMap cols
 template <typename T, bool DOT, int DM>
 __device__ inline void sum_sources(const double* __restrict__ Y, IdxMap rows, int nrows, const double* __restrict__ X,
                                    IdxMap cols, int ncols, const double* __restrict__ q, int d, const KParams& kp,
-                                   TileSmem<T>& sm, double (&part)[4], bool& bad) {
+                                   EvalSmem<T, DM>& sm, double (&part)[4], bool& bad) {
   if constexpr (DM > 0) sum_staged_rows<T, DOT, DM>(X, cols, ncols, q, d, kp, sm, part, bad);
   else sum_over_sources<T, DOT>(Y, rows, nrows, X, cols, ncols, q, d, kp, sm, part, bad);
 }
