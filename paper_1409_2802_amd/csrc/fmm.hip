@@ -61,7 +61,7 @@ __global__ void k_fmm_admissible(const uint64_t* __restrict__ bits, int words, c
 
 constexpr int kM2lParts = 4;
 
-template <typename T, bool DOT, int DM>
+template <typename T, int KF, int DM>
 __global__ void __launch_bounds__(NT) k_m2l(const double* __restrict__ Xt, int d, KParams kp, int chunks,
                                             int num_nodes, const int32_t* __restrict__ rank,
                                             const int32_t* __restrict__ skel, int r_cap,
@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(NT) k_m2l(const double* __restrict__ Xt, int d
   for (int e = off[b] + part; e < off[b + 1]; e += kM2lParts) {
     const int a = src[e];
     if (rank[a] > 0)
-      sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)a * r_cap, 0}, rank[a],
+      sum_sources<T, KF, DM>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)a * r_cap, 0}, rank[a],
                           qt + (int64_t)a * r_cap, d, kp, sm, acc, bad);
   }
   reduce_rows(acc, red, rowsum);
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) k_l2l(int first, int leaves, const int32_
   else v[(int64_t)(l + 1) * r_cap + (j - rl)] += w;
 }
 
-template <typename T, bool DOT, int DM>
+template <typename T, int KF, int DM>
 __global__ void __launch_bounds__(NT) k_p2p(const double* __restrict__ Xt, int d, KParams kp,
                                             const int32_t* __restrict__ tile_leaf,
                                             const int32_t* __restrict__ tile_start, const int32_t* __restrict__ nb,
@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(NT) k_p2p(const double* __restrict__ Xt, int d
   for (int e = off[li]; e < off[li + 1]; ++e) {
     const int a = src[e];
     const int ab = nb[a];
-    sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{nullptr, ab}, ne[a] - ab, q_tree + ab, d, kp, sm, part,
+    sum_sources<T, KF, DM>(Xt, rmap, nrows, Xt, IdxMap{nullptr, ab}, ne[a] - ab, q_tree + ab, d, kp, sm, part,
                         bad);
   }
   reduce_rows(part, red, near_sum);
@@ -166,9 +166,11 @@ __global__ void __launch_bounds__(NT) k_p2p(const double* __restrict__ Xt, int d
 }
 
 template <typename F>
-ffc_status dispatch_tiles(int precision, bool dot, F&& f) {
-  if (precision == FFC_FP64) return dot ? f(double(), std::true_type()) : f(double(), std::false_type());
-  return dot ? f(float(), std::true_type()) : f(float(), std::false_type());
+ffc_status dispatch_tiles(int precision, int kind, F&& f) {
+  return with_kind(kind, [&](auto kv) -> ffc_status {
+    if (precision == FFC_FP64) return f(double(), kv);
+    return f(float(), kv);
+  });
 }
 
 // Interaction lists of the skeleton set's separation (synchronizes `st`).
@@ -256,15 +258,14 @@ ffc_status launch_fmm(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int pr
   if (sk->fmm_v.count != nv) FFC_TRY(sk->fmm_v.alloc(nv));
   if (sk->fmm_vpart.count != nv * kM2lParts) FFC_TRY(sk->fmm_vpart.alloc(nv * kM2lParts));
   if (sk->fmm_ufar.count != (size_t)t->N) FFC_TRY(sk->fmm_ufar.alloc((size_t)t->N));
-  const bool dot = kp.kind == FFC_POLYNOMIAL;
   const int chunks = (sk->r_cap + BM - 1) / BM;
   const int leaf0 = (1 << t->depth) - 1;
-  return dispatch_tiles(precision, dot, [&](auto tv, auto dv) -> ffc_status {
+  return dispatch_tiles(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
-    constexpr bool D = decltype(dv)::value;
+    constexpr int KF = decltype(kv)::value;
     return with_dims(t->d, [&](auto dm) -> ffc_status {
       constexpr int DM = decltype(dm)::value;
-      hipLaunchKernelGGL((k_m2l<T, D, DM>), dim3((unsigned)((t->num_nodes - 1) * chunks * kM2lParts)), dim3(NT), 0, st,
+      hipLaunchKernelGGL((k_m2l<T, KF, DM>), dim3((unsigned)((t->num_nodes - 1) * chunks * kM2lParts)), dim3(NT), 0, st,
                          t->Xt.ptr, t->d, kp, chunks, t->num_nodes, sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr,
                          sk->fmm_far_off.ptr, sk->fmm_far_src.ptr, sk->fmm_vpart.ptr, device_flag());
       FFC_LAUNCH_CHECK("k_m2l");
@@ -279,7 +280,7 @@ ffc_status launch_fmm(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int pr
                            t->begin.ptr, sk->fmm_v.ptr, sk->fmm_ufar.ptr);
         FFC_LAUNCH_CHECK("k_l2l");
       }
-      hipLaunchKernelGGL((k_p2p<T, D, DM>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
+      hipLaunchKernelGGL((k_p2p<T, KF, DM>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
                          t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr, leaf0,
                          sk->fmm_near_off.ptr, sk->fmm_near_src.ptr, sk->fmm_ufar.ptr, t->perm.ptr, u, u_far,
                          device_flag());

@@ -32,7 +32,7 @@ using namespace tile;
 // ---------------------------------------------------------------------------
 // Sampled blocks for all nodes of a level.
 // ---------------------------------------------------------------------------
-template <typename T, bool DOT>
+template <typename T, int KF>
 __global__ void __launch_bounds__(NT) k_level_kblock(const double* __restrict__ Xt, int d, KParams kp, int first,
                                                      int tiles_m, int tiles_n, const int32_t* __restrict__ rows,
                                                      const int32_t* __restrict__ nrows, int s_cap,
@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(NT) k_level_kblock(const double* __restrict__ 
   const IdxMap rmap{rows + (int64_t)node * s_cap + r0, 0};
   const IdxMap cmap{cols + (int64_t)node * n_cap + c0, 0};
   T acc[4][4];
-  tile_accumulate<T, DOT>(Xt, rmap, s - r0, Xt, cmap, n - c0, d, sm, acc);
+  tile_accumulate<T, KF == FFC_POLYNOMIAL>(Xt, rmap, s - r0, Xt, cmap, n - c0, d, sm, acc);
   double* out = A + (int64_t)ln * s_cap * n_cap;
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
   bool bad = false;
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(NT) k_level_kblock(const double* __restrict__ 
     for (int i = 0; i < 4; ++i) {
       const int r = r0 + tr + 16 * i;
       if (r < s && c < n) {
-        const double v = kfun<DOT>(acc[i][j], kp);
+        const double v = kfun<KF>(acc[i][j], kp);
         bad |= !isfinite(v);
         out[(int64_t)c * s_cap + r] = v;
       }
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(NT) k_level_kblock(const double* __restrict__ 
 }
 
 // Standalone sampled block: rows/cols are explicit lists of tree positions.
-template <typename T, bool DOT>
+template <typename T, int KF>
 __global__ void __launch_bounds__(NT) k_sampled_block(const double* __restrict__ Xt, int d, KParams kp,
                                                       const int32_t* __restrict__ rows, int s,
                                                       const int32_t* __restrict__ cols, int n, int tiles_m,
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(NT) k_sampled_block(const double* __restrict__
   __shared__ TileSmem<T> sm;
   const int r0 = (blockIdx.x % tiles_m) * BM, c0 = (blockIdx.x / tiles_m) * BN;
   T acc[4][4];
-  tile_accumulate<T, DOT>(Xt, IdxMap{rows + r0, 0}, s - r0, Xt, IdxMap{cols + c0, 0}, n - c0, d, sm, acc);
+  tile_accumulate<T, KF == FFC_POLYNOMIAL>(Xt, IdxMap{rows + r0, 0}, s - r0, Xt, IdxMap{cols + c0, 0}, n - c0, d, sm, acc);
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
   bool bad = false;
 #pragma unroll
@@ -89,7 +89,7 @@ __global__ void __launch_bounds__(NT) k_sampled_block(const double* __restrict__
     for (int i = 0; i < 4; ++i) {
       const int r = r0 + tr + 16 * i, c = c0 + tc + 16 * j;
       if (r < s && c < n) {
-        const double v = kfun<DOT>(acc[i][j], kp);
+        const double v = kfun<KF>(acc[i][j], kp);
         bad |= !isfinite(v);
         out[(int64_t)c * s + r] = v;
       }
@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(NT) k_sampled_block(const double* __restrict__
 
 
 // Far field (sibling cover) + near field (own leaf) for a tile of targets.
-template <typename T, bool DOT, int DM>
+template <typename T, int KF, int DM>
 __global__ void __launch_bounds__(NT) k_evaluate(const double* __restrict__ Xt, int d, KParams kp, int depth,
                                                  const int32_t* __restrict__ tile_leaf,
                                                  const int32_t* __restrict__ tile_start,
@@ -125,14 +125,14 @@ __global__ void __launch_bounds__(NT) k_evaluate(const double* __restrict__ Xt, 
     const int sib = (a & 1) ? a + 1 : a - 1;
     const int r = rank[sib];
     if (r > 0)
-      sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)sib * r_cap, 0}, r,
+      sum_sources<T, KF, DM>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)sib * r_cap, 0}, r,
                           qt + (int64_t)sib * r_cap, d, kp, sm, part, bad);
     a = (a - 1) >> 1;
   }
   reduce_rows(part, red, far_sum);
   double npart[4] = {0.0, 0.0, 0.0, 0.0};
   const int lb = nb[leaf];
-  sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{nullptr, lb}, ne[leaf] - lb, q_tree + lb, d, kp, sm, npart,
+  sum_sources<T, KF, DM>(Xt, rmap, nrows, Xt, IdxMap{nullptr, lb}, ne[leaf] - lb, q_tree + lb, d, kp, sm, npart,
                       bad);
   reduce_rows(npart, red, near_sum);
   if (threadIdx.x < nrows) {
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(kPreThreads) k_sep_prefix(const uint64_t* __re
 // whether the row reaches the node of level l on the current path; a node of
 // level l sets bit l + 1 for its children, and nodes visited before its second
 // child are all deeper, so that bit still holds when the second child is popped.
-template <typename T, bool DOT, int DM>
+template <typename T, int KF, int DM>
 __global__ void __launch_bounds__(NT) k_treecode(const double* __restrict__ Xt, int d, KParams kp, int depth,
                                                  const int32_t* __restrict__ tile_leaf,
                                                  const int32_t* __restrict__ tile_start,
@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(NT) k_treecode(const double* __restrict__ Xt, 
     const int any_rest = __syncthreads_or(k == 2);
     if (any_far && rank[a] > 0) {
       double tmp[4] = {0.0, 0.0, 0.0, 0.0};
-      sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)a * r_cap, 0}, rank[a],
+      sum_sources<T, KF, DM>(Xt, rmap, nrows, Xt, IdxMap{skel + (int64_t)a * r_cap, 0}, rank[a],
                           qt + (int64_t)a * r_cap, d, kp, sm, tmp, bad);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
@@ -290,7 +290,7 @@ __global__ void __launch_bounds__(NT) k_treecode(const double* __restrict__ Xt, 
       if (is_leaf) {
         const int lb = nb[a];
         double tmp[4] = {0.0, 0.0, 0.0, 0.0};
-        sum_sources<T, DOT, DM>(Xt, rmap, nrows, Xt, IdxMap{nullptr, lb}, ne[a] - lb, q_tree + lb, d, kp, sm, tmp,
+        sum_sources<T, KF, DM>(Xt, rmap, nrows, Xt, IdxMap{nullptr, lb}, ne[a] - lb, q_tree + lb, d, kp, sm, tmp,
                             bad);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(NT) k_treecode(const double* __restrict__ Xt, 
 }
 
 // Direct sum over all sources for a tile of 64 targets.
-template <typename T, bool DOT, int DM>
+template <typename T, int KF, int DM>
 __global__ void __launch_bounds__(NT) k_direct(const double* __restrict__ Y, int64_t m, const double* __restrict__ X,
                                                int64_t n, int d, KParams kp, const double* __restrict__ q,
                                                double* __restrict__ u, unsigned int* flag) {
@@ -330,16 +330,18 @@ __global__ void __launch_bounds__(NT) k_direct(const double* __restrict__ Y, int
   bool bad = false;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   if constexpr (DM > 0) stage_rows<T, DM>(Y, IdxMap{nullptr, r0}, nrows, d, sm);
-  sum_sources<T, DOT, DM>(Y, IdxMap{nullptr, r0}, nrows, X, IdxMap{nullptr, 0}, (int)n, q, d, kp, sm, part, bad);
+  sum_sources<T, KF, DM>(Y, IdxMap{nullptr, r0}, nrows, X, IdxMap{nullptr, 0}, (int)n, q, d, kp, sm, part, bad);
   reduce_rows(part, red, rowsum);
   if (threadIdx.x < nrows) u[r0 + threadIdx.x] = rowsum[threadIdx.x];
   if (bad) flag_nonfinite(flag);
 }
 
 template <typename F>
-ffc_status dispatch(int precision, bool dot, F&& f) {
-  if (precision == FFC_FP64) return dot ? f(double(), std::true_type()) : f(double(), std::false_type());
-  return dot ? f(float(), std::true_type()) : f(float(), std::false_type());
+ffc_status dispatch(int precision, int kind, F&& f) {
+  return with_kind(kind, [&](auto kv) -> ffc_status {
+    if (precision == FFC_FP64) return f(double(), kv);
+    return f(float(), kv);
+  });
 }
 
 }  // namespace
@@ -354,11 +356,10 @@ ffc_status launch_kblock_batch(const ffc_tree* t, const KParams& kp, int precisi
   const int tiles_m = (s_cap + BM - 1) / BM, tiles_n = (n_cap + BN - 1) / BN;
   const int64_t blocks = (int64_t)count * tiles_m * tiles_n;
   if (blocks == 0) return FFC_OK;
-  const bool dot = kp.kind == FFC_POLYNOMIAL;
-  return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
+  return dispatch(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
-    constexpr bool D = decltype(dv)::value;
-    hipLaunchKernelGGL((k_level_kblock<T, D>), dim3((unsigned)blocks), dim3(NT), 0, st, t->Xt.ptr, t->d, kp, first,
+    constexpr int KF = decltype(kv)::value;
+    hipLaunchKernelGGL((k_level_kblock<T, KF>), dim3((unsigned)blocks), dim3(NT), 0, st, t->Xt.ptr, t->d, kp, first,
                        tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, mask, A, device_flag());
     FFC_LAUNCH_CHECK("k_level_kblock");
     return FFC_OK;
@@ -404,11 +405,10 @@ ffc_status launch_gram(const double* B, int m, int n, int count, double* G, hipS
 ffc_status launch_sampled_block(const ffc_tree* t, const KParams& kp, int precision, const int32_t* rows, int s,
                                 const int32_t* cols, int n, double* out, hipStream_t st) {
   const int tiles_m = (s + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
-  const bool dot = kp.kind == FFC_POLYNOMIAL;
-  return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
+  return dispatch(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
-    constexpr bool D = decltype(dv)::value;
-    hipLaunchKernelGGL((k_sampled_block<T, D>), dim3((unsigned)(tiles_m * tiles_n)), dim3(NT), 0, st, t->Xt.ptr,
+    constexpr int KF = decltype(kv)::value;
+    hipLaunchKernelGGL((k_sampled_block<T, KF>), dim3((unsigned)(tiles_m * tiles_n)), dim3(NT), 0, st, t->Xt.ptr,
                        t->d, kp, rows, s, cols, n, tiles_m, out, device_flag());
     FFC_LAUNCH_CHECK("k_sampled_block");
     return FFC_OK;
@@ -418,13 +418,12 @@ ffc_status launch_sampled_block(const ffc_tree* t, const KParams& kp, int precis
 ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, double* u,
                            double* u_far, hipStream_t st) {
   if (precision == FFC_MIXED_BF16X3 && kp.kind != FFC_LAPLACE) return launch_evaluate_mixed(t, sk, kp, u, u_far, st);
-  const bool dot = kp.kind == FFC_POLYNOMIAL;
-  return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
+  return dispatch(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
-    constexpr bool D = decltype(dv)::value;
+    constexpr int KF = decltype(kv)::value;
     return with_dims(t->d, [&](auto dm) -> ffc_status {
       constexpr int DM = decltype(dm)::value;
-      hipLaunchKernelGGL((k_evaluate<T, D, DM>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
+      hipLaunchKernelGGL((k_evaluate<T, KF, DM>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
                          t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
                          sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->perm.ptr, u, u_far, device_flag());
       FFC_LAUNCH_CHECK("k_evaluate");
@@ -462,13 +461,12 @@ ffc_status launch_treecode(const ffc_tree* t, const ffc_skel* sk, const KParams&
     set_error("separation bitmaps are missing");
     return FFC_ERR_STATE;
   }
-  const bool dot = kp.kind == FFC_POLYNOMIAL;
-  return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
+  return dispatch(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
-    constexpr bool D = decltype(dv)::value;
+    constexpr int KF = decltype(kv)::value;
     return with_dims(t->d, [&](auto dm) -> ffc_status {
       constexpr int DM = decltype(dm)::value;
-      hipLaunchKernelGGL((k_treecode<T, D, DM>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
+      hipLaunchKernelGGL((k_treecode<T, KF, DM>), dim3((unsigned)t->num_tiles), dim3(NT), 0, st, t->Xt.ptr, t->d, kp,
                          t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,
                          sk->rank.ptr, sk->skel.ptr, sk->r_cap, sk->qt.ptr, sk->sep_bits.ptr, sk->sep_words,
                          t->perm.ptr, u, u_far, device_flag());
@@ -482,13 +480,12 @@ ffc_status launch_direct_sum(const double* Y, int64_t m, const double* X, int64_
                              int precision, const double* q, double* u, hipStream_t st) {
   if (m == 0) return FFC_OK;
   if (precision == FFC_MIXED_BF16X3 && kp.kind != FFC_LAPLACE) return launch_direct_mixed(Y, m, X, n, d, kp, q, u, st);
-  const bool dot = kp.kind == FFC_POLYNOMIAL;
-  return dispatch(precision, dot, [&](auto tv, auto dv) -> ffc_status {
+  return dispatch(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
-    constexpr bool D = decltype(dv)::value;
+    constexpr int KF = decltype(kv)::value;
     return with_dims(d, [&](auto dm) -> ffc_status {
       constexpr int DM = decltype(dm)::value;
-      hipLaunchKernelGGL((k_direct<T, D, DM>), dim3((unsigned)((m + BM - 1) / BM)), dim3(NT), 0, st, Y, m, X, n, d,
+      hipLaunchKernelGGL((k_direct<T, KF, DM>), dim3((unsigned)((m + BM - 1) / BM)), dim3(NT), 0, st, Y, m, X, n, d,
                          kp, q, u, device_flag());
       FFC_LAUNCH_CHECK("k_direct");
       return FFC_OK;

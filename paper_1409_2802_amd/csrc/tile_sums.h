@@ -18,6 +18,10 @@ namespace tile {
 // the hardware estimate refined by two Newton steps (y <- y + y (1 - r2 y^2) / 2,
 // z <- z + z (1 - r2 z)), a few times cheaper than the general power, which
 // serves larger d and r2 below 2^-900 (where the estimate's range ends).
+// The general power, out of line: the kernels call it only for d > 7 or tiny
+// distances, so it is kept out of their unrolled loops.
+__device__ __attribute__((noinline)) double laplace_pow(double r2, double expo) { return pow(r2, expo); }
+
 __device__ inline double laplace_of_r2(double r2, const KParams& kp) {
   if (kp.lap_small && r2 > 0x1p-900) {
     double b;
@@ -34,32 +38,38 @@ __device__ inline double laplace_of_r2(double r2, const KParams& kp) {
     for (int i = 1; i < kp.lap_m; ++i) v *= b;
     return v;
   }
-  return pow(r2, kp.lap_expo);
+  return laplace_pow(r2, kp.lap_expo);
 }
 
-// Kernel function of an accumulated distance^2 (or inner product when DOT).
-template <bool DOT>
+// Kernel function of an accumulated distance^2 (or inner product for the
+// polynomial kernel); KF is the ffc_kernel_kind, fixed at compile time so each
+// kernel instance holds only its own function.
+template <int KF>
 __device__ inline double kfun(double acc, const KParams& kp) {
-  if (DOT) {
+  if constexpr (KF == FFC_POLYNOMIAL) {
     const double base = fma(acc, kp.inv_h, kp.c);
     double r = 1.0;
     for (int i = 0; i < kp.p; ++i) r *= base;
     return r;
+  } else if constexpr (KF == FFC_GAUSSIAN) {
+    return exp(acc * kp.neg_inv_2h2);
+  } else {
+    return acc > 0.0 ? laplace_of_r2(acc, kp) : 0.0;
   }
-  if (kp.kind == FFC_GAUSSIAN) return exp(acc * kp.neg_inv_2h2);
-  return acc > 0.0 ? laplace_of_r2(acc, kp) : 0.0;   // Laplace
 }
 
-template <bool DOT>
+template <int KF>
 __device__ inline double kfun(float acc, const KParams& kp) {
-  if (DOT) {
+  if constexpr (KF == FFC_POLYNOMIAL) {
     const float base = fmaf(acc, (float)kp.inv_h, (float)kp.c);
     float r = 1.0f;
     for (int i = 0; i < kp.p; ++i) r *= base;
     return (double)r;
+  } else if constexpr (KF == FFC_GAUSSIAN) {
+    return (double)expf(acc * (float)kp.neg_inv_2h2);
+  } else {
+    return acc > 0.0f ? laplace_of_r2((double)acc, kp) : 0.0;   // the power in FP64 (range)
   }
-  if (kp.kind == FFC_GAUSSIAN) return (double)expf(acc * (float)kp.neg_inv_2h2);
-  return acc > 0.0f ? laplace_of_r2((double)acc, kp) : 0.0;   // Laplace: power in FP64 (range)
 }
 
 __device__ inline void flag_nonfinite(unsigned int* flag) { atomicOr(flag, 1u); }
@@ -68,7 +78,7 @@ __device__ inline void flag_nonfinite(unsigned int* flag) { atomicOr(flag, 1u); 
 // Kernel sums: accumulate sum_j K(y_i, x_j) q_j over one source set into
 // per-thread partial sums part[i] (rows tr + 16 i of the tile).
 // ---------------------------------------------------------------------------
-template <typename T, bool DOT>
+template <typename T, int KF>
 __device__ inline void sum_over_sources(const double* __restrict__ Y, IdxMap rows, int nrows,
                                         const double* __restrict__ X, IdxMap cols, int ncols,
                                         const double* __restrict__ q, int d, const KParams& kp, TileSmem<T>& sm,
@@ -77,14 +87,14 @@ __device__ inline void sum_over_sources(const double* __restrict__ Y, IdxMap row
   for (int c0 = 0; c0 < ncols; c0 += BN) {
     IdxMap cm{cols.idx ? cols.idx + c0 : nullptr, cols.base + c0};
     T acc[4][4];
-    tile_accumulate<T, DOT>(Y, rows, nrows, X, cm, ncols - c0, d, sm, acc);
+    tile_accumulate<T, KF == FFC_POLYNOMIAL>(Y, rows, nrows, X, cm, ncols - c0, d, sm, acc);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int c = c0 + tc + 16 * j;
       if (c < ncols) {
         const double qj = q[c];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) part[i] = fma(kfun<DOT>(acc[i][j], kp), qj, part[i]);
+        for (int i = 0; i < 4; ++i) part[i] = fma(kfun<KF>(acc[i][j], kp), qj, part[i]);
       }
     }
   }
@@ -121,11 +131,12 @@ __device__ inline void stage_rows(const double* __restrict__ Y, IdxMap rows, int
   }
 }
 
-template <typename T, bool DOT, int DM>
+template <typename T, int KF, int DM>
 __device__ inline void sum_staged_rows(const double* __restrict__ X, IdxMap cols, int ncols,
                                        const double* __restrict__ q, int d, const KParams& kp, EvalSmem<T, DM>& sm,
                                        double (&part)[4], bool& bad) {
   constexpr int IT = BM * DM / NT;
+  constexpr bool DOT = KF == FFC_POLYNOMIAL;
   const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
   const int sh = 32 - __clz(d - 1);
   T pre[IT];
@@ -182,7 +193,7 @@ __device__ inline void sum_staged_rows(const double* __restrict__ X, IdxMap cols
       if (c < ncols) {
         const double qj = q[c];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) part[i] = fma(kfun<DOT>(acc[i][j], kp), qj, part[i]);
+        for (int i = 0; i < 4; ++i) part[i] = fma(kfun<KF>(acc[i][j], kp), qj, part[i]);
       }
     }
     __syncthreads();   // every thread is done with this chunk's sources
@@ -197,12 +208,20 @@ __device__ inline void sum_staged_rows(const double* __restrict__ X, IdxMap cols
 
 // Sum over one source set with the tile's rows: the staged-rows form when DM > 0
 // (stage_rows must have run in this workgroup), the general form otherwise.
-template <typename T, bool DOT, int DM>
+template <typename T, int KF, int DM>
 __device__ inline void sum_sources(const double* __restrict__ Y, IdxMap rows, int nrows, const double* __restrict__ X,
                                    IdxMap cols, int ncols, const double* __restrict__ q, int d, const KParams& kp,
                                    EvalSmem<T, DM>& sm, double (&part)[4], bool& bad) {
-  if constexpr (DM > 0) sum_staged_rows<T, DOT, DM>(X, cols, ncols, q, d, kp, sm, part, bad);
-  else sum_over_sources<T, DOT>(Y, rows, nrows, X, cols, ncols, q, d, kp, sm, part, bad);
+  if constexpr (DM > 0) sum_staged_rows<T, KF, DM>(X, cols, ncols, q, d, kp, sm, part, bad);
+  else sum_over_sources<T, KF>(Y, rows, nrows, X, cols, ncols, q, d, kp, sm, part, bad);
+}
+
+// Host side: the kernel function (ffc_kernel_kind) as a compile-time constant.
+template <typename F>
+inline auto with_kind(int kind, F&& f) {
+  if (kind == FFC_GAUSSIAN) return f(std::integral_constant<int, FFC_GAUSSIAN>());
+  if (kind == FFC_LAPLACE) return f(std::integral_constant<int, FFC_LAPLACE>());
+  return f(std::integral_constant<int, FFC_POLYNOMIAL>());
 }
 
 // Host side: the dimension class of the evaluation kernels (4, 32, or 0 for the
