@@ -228,6 +228,25 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
       r[4] = sum[i];
     }
   }
+  // The centroid distance and the anchor projections of every row: 64 rows x
+  // (1 + NANCH) dot products over d, spread over all threads (each one a
+  // sequential sum, so the values do not depend on the spreading).
+  double* dots = red + 4 * 64 * 5;   // [64 rows][1 + NANCH]
+  const double* c = ga.cen + (int64_t)b * d;
+  const double* U = ga.U + (int64_t)b * NANCH * d;
+  for (int task = tid; task < 64 * (1 + NANCH); task += 256) {
+    const int row = task / (1 + NANCH), a = task % (1 + NANCH);
+    if (t0 + row >= nt) continue;
+    const double* y = Xt + (int64_t)tg[row] * d;
+    double p = 0.0;
+    if (a == 0) {
+      for (int k = 0; k < d; ++k) { const double df = y[k] - c[k]; p = fma(df, df, p); }
+    } else {
+      const double* u = U + (int64_t)(a - 1) * d;
+      for (int k = 0; k < d; ++k) p = fma(y[k] - c[k], u[k], p);
+    }
+    dots[row * (1 + NANCH) + a] = p;
+  }
   __syncthreads();
   if (tid >= 64) return;
   const int row = tid;
@@ -240,23 +259,14 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
     for (int u = 0; u < 4; ++u) insert4(b4, r[u]);
     tot += r[4];
   }
-  const double* y = Xt + (int64_t)tg[row] * d;
-  const double* c = ga.cen + (int64_t)b * d;
-  double dc = 0.0;
-  for (int k = 0; k < d; ++k) { const double df = y[k] - c[k]; dc = fma(df, df, dc); }
-  dc = sqrt(dc) / rho;
+  const double dc = sqrt(dots[row * (1 + NANCH)]) / rho;
   float* f = feat + (int64_t)b * feat_stride + (int64_t)(t0 + row) * NF;
   f[0] = (float)dc;
   f[1] = (float)log(dc + 1e-12);
   for (int q = 0; q < 4; ++q) f[2 + q] = (float)(q < ns ? b4[q] : b4[max(ns - 1, 0)]);
   f[6] = (float)(ns > 0 ? tot / ns : 0.0);
   f[7] = (float)log(b4[0] + 1e-12);
-  const double* U = ga.U + (int64_t)b * NANCH * d;
-  for (int a = 0; a < NANCH; ++a) {
-    double p = 0.0;
-    for (int k = 0; k < d; ++k) p = fma(y[k] - c[k], U[(int64_t)a * d + k], p);
-    f[8 + a] = (float)(p / rho);
-  }
+  for (int a = 0; a < NANCH; ++a) f[8 + a] = (float)(dots[row * (1 + NANCH) + 1 + a] / rho);
   f[15] = 1.0f;
 }
 
