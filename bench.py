@@ -507,6 +507,10 @@ def main():
     if prec == ffc.FP64 and proposal is None:
         for vname in [v for v in args.variants.split(",") if v]:
             vp = {"fp32": ffc.FP32, "mixed": ffc.MIXED_BF16X3}[vname]
+            if vp == ffc.MIXED_BF16X3 and xi > 0:
+                # The separated (treecode and FMM-style) evaluations run in FP64 or FP32 only.
+                print(f"[bench] variant {vname}: not available with separation", file=sys.stderr, flush=True)
+                continue
             uv, ufv = torch.empty_like(u), torch.empty_like(uf)
             skv, msv = timed(vp, args.steps, args.warmup, (uv, ufv))
             ufv_h = ufv.cpu().numpy()
