@@ -304,7 +304,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the method's kernels are measured on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(the library has no multi-GPU path; how the method would shard is described in the design notes)", file=sys.stderr)
         sys.exit(2)
     import torch
 
