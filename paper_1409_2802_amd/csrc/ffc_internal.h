@@ -157,12 +157,18 @@ struct ffc_tree {
   ffc::DevBuf<int32_t> tile_leaf, tile_start;
   int32_t num_tiles = 0;
   int32_t tile_rows = 0;
-  // Tree-order coordinates split into bfloat16 hi + lo (rows padded with zeros
-  // to bf_dp, a multiple of 32) and their squared norms, made on the first use
-  // of the matrix-core kernels.
+  // Operands of the matrix-core kernels, made on their first use (rows padded
+  // with zeros to bf_dp, a multiple of 32): the tree-order coordinates split
+  // into bfloat16 hi + lo with their squared norms; and, where distances need
+  // centring on each tile (bf_frame == 0), the coordinates less the root
+  // centroid in float32 with every node's centroid in the same frame plus one
+  // last row holding the origin. bf_frame: -1 not yet decided, 1 the split
+  // coordinates serve the Gaussian too, 0 the Gaussian centres per tile.
   ffc::DevBuf<uint16_t> bf_hi, bf_lo;
   ffc::DevBuf<float> bf_nrm;
+  ffc::DevBuf<float> bf_x, bf_cc;
   int32_t bf_dp = 0;
+  int32_t bf_frame = -1;
   hipStream_t last_stream = nullptr;
 };
 

@@ -9,13 +9,19 @@
 // runs in float32 in the epilogue; sampled blocks are stored in float64 for
 // the QR.
 //
-// The tree's points are split once (tree order, rows padded with zeros to a
-// multiple of 32 dimensions) with their squared norms summed in FP64 and
-// rounded to FP32; the sampled blocks and the evaluation then stage 16-byte
-// groups of ready operands and prefetch the next 32-dimension chunk while the
-// matrix cores work. The direct sum, on arbitrary point sets, converts while
-// staging and centres both sets on its first target (distances do not depend
-// on the centre; a nearby one keeps the norms small).
+// The split only carries 16 bits, so coordinates are centred first: on the
+// node's centroid for a sampled block and on the target leaf's centroid for
+// the evaluation (distances do not depend on the centre, and a nearby one keeps
+// the coordinates and norms small; the polynomial kernel needs the raw inner
+// product and centres on the origin). Left uncentred, points far from the
+// origin lose the distance of near pairs to cancellation. The tree's points
+// are stored once in float32 less the root centroid (tree order, rows padded
+// with zeros to a multiple of 32 dimensions), with the nodes' centroids in the
+// same frame; a tile loads 16-byte groups of them, subtracts its centre,
+// splits and forms the squared norms while staging, and prefetches the next
+// 32-dimension chunk while the matrix cores work. The direct sum, on arbitrary
+// point sets, converts from float64 while staging and centres both sets on its
+// first target.
 //
 // A 256-thread workgroup computes a 64 x 64 tile; operands go through LDS 32
 // dimensions at a time. The MFMA A operand holds the column points and B the
@@ -23,6 +29,8 @@
 // column-major stores coalesce. Operand layout of the instruction (lane l,
 // element i): A[l % 16][(l / 16) * 8 + i], B[(l / 16) * 8 + i][l % 16],
 // D[(l / 16) * 4 + i][l % 16].
+#include <vector>
+
 #include "ffc_internal.h"
 
 namespace ffc {
@@ -205,13 +213,135 @@ __device__ void mixed_tile_split(const __bf16* __restrict__ Hh, const __bf16* __
   }
 }
 
-// Pre-split points of the tree (and, for the Gaussian, their squared norms):
-// null pointers select the staging from float64.
+// Tree-order points less the root centroid g, in float32 (rows of dp values,
+// zero past d).
+__global__ void k_offset_points(const double* __restrict__ Xt, int64_t N, int d, int dp,
+                                const double* __restrict__ g, float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * dp) return;
+  const int64_t p = e / dp;
+  const int k = (int)(e % dp);
+  out[e] = k < d ? (float)(Xt[p * d + k] - g[k]) : 0.f;
+}
+
+// Node centres in the same frame: row a < nodes is centroid[a] - g, row
+// nodes is -g (the origin).
+__global__ void k_offset_centres(const double* __restrict__ centroid, int nodes, int d, int dp,
+                                 float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)(nodes + 1) * dp) return;
+  const int a = (int)(e / dp), k = (int)(e % dp);
+  const double c = a < nodes ? centroid[(int64_t)a * d + k] : 0.0;
+  out[e] = k < d ? (float)(c - centroid[k]) : 0.f;
+}
+
+// Splits eight centred values into bf16 hi and lo (16 bytes each) and adds
+// their squares to nsum.
+__device__ inline void split8(const float4& a, const float4& b, const float4& ca, const float4& cb, uint4& hi,
+                              uint4& lo, float& nsum) {
+  const float z[8] = {a.x - ca.x, a.y - ca.y, a.z - ca.z, a.w - ca.w, b.x - cb.x, b.y - cb.y, b.z - cb.z, b.w - cb.w};
+  __bf16 h[8], l[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    h[i] = (__bf16)z[i];
+    l[i] = (__bf16)(z[i] - (float)h[i]);
+    nsum = fmaf(z[i], z[i], nsum);
+  }
+  hi = *reinterpret_cast<const uint4*>(h);
+  lo = *reinterpret_cast<const uint4*>(l);
+}
+
+// The Gram tile of mixed_tile from the float32 points: both sets are centred
+// on cen (a row of the centre table), split and staged 32 dimensions at a
+// time; each thread handles 8 dimensions of one row point and one column
+// point and fetches the next chunk's groups while the matrix cores work on
+// the current one. With NORMS the centred points' squared norms go to sm.yn /
+// sm.xn for the distance epilogue.
+template <bool NORMS>
+__device__ void mixed_tile_cached(const float* __restrict__ P, const float* __restrict__ cen, int dp, Idx rows,
+                                  int nrows, Idx cols, int ncols, MixSmem& sm, f32x4 (&acc)[2][2]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int p = tid >> 2, part = (tid & 3) * 8;
+  const int64_t yrow = p < nrows ? rows(p) : -1;
+  const int64_t xrow = p < ncols ? cols(p) : -1;
+  const float4 zero{0.f, 0.f, 0.f, 0.f};
+  float4 y0, y1, x0, x1, c0, c1;
+  auto fetch = [&](int k0) {
+    const float4* yp = reinterpret_cast<const float4*>(P + yrow * dp + k0 + part);
+    const float4* xp = reinterpret_cast<const float4*>(P + xrow * dp + k0 + part);
+    const float4* cp = reinterpret_cast<const float4*>(cen + k0 + part);
+    y0 = yrow >= 0 ? yp[0] : zero;
+    y1 = yrow >= 0 ? yp[1] : zero;
+    x0 = xrow >= 0 ? xp[0] : zero;
+    x1 = xrow >= 0 ? xp[1] : zero;
+    c0 = cp[0];
+    c1 = cp[1];
+  };
+  float yn = 0.f, xn = 0.f;
+  fetch(0);
+  for (int k0 = 0; k0 < dp; k0 += KCH) {
+    uint4 h, l;
+    // Padded rows stage zeros (not minus the centre) so they add nothing.
+    split8(y0, y1, yrow >= 0 ? c0 : zero, yrow >= 0 ? c1 : zero, h, l, yn);
+    *reinterpret_cast<uint4*>(&sm.yh[p][part]) = h;
+    *reinterpret_cast<uint4*>(&sm.yl[p][part]) = l;
+    split8(x0, x1, xrow >= 0 ? c0 : zero, xrow >= 0 ? c1 : zero, h, l, xn);
+    *reinterpret_cast<uint4*>(&sm.xh[p][part]) = h;
+    *reinterpret_cast<uint4*>(&sm.xl[p][part]) = l;
+    __syncthreads();
+    if (k0 + KCH < dp) fetch(k0 + KCH);
+    const int kofs = (lane >> 4) * 8;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const int xr = (w >> 1) * 32 + bi * 16 + (lane & 15);
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sm.xh[xr][kofs]);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(&sm.xl[xr][kofs]);
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&sm.yh[yr][kofs]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&sm.yl[yr][kofs]);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[bi][bj], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  if (NORMS) {
+    // The four threads of a point are adjacent lanes.
+    yn += __shfl_xor(yn, 1, 64);
+    xn += __shfl_xor(xn, 1, 64);
+    yn += __shfl_xor(yn, 2, 64);
+    xn += __shfl_xor(xn, 2, 64);
+    if ((tid & 3) == 0) {
+      sm.yn[p] = yn;
+      sm.xn[p] = xn;
+    }
+    __syncthreads();
+  }
+}
+
+// Operands of the tree's points for the matrix-core tiles: pre-split in the
+// origin frame (hi, lo, with norms for the Gaussian), or in float32 with the
+// centre table for tiles that centre while staging; all null: stage from
+// float64.
 struct Split {
   const __bf16* hi;
   const __bf16* lo;
   const float* nrm;
+  const float* x;
+  const float* cc;
   int dp;
+  int origin;   // row of cc holding the origin
+  // Centre row of a tile whose Gaussian centre is node a (the polynomial
+  // kernel's inner products centre on the origin).
+  template <bool DOT>
+  __device__ inline const float* centre(int a) const { return cc + (int64_t)(DOT ? origin : a) * dp; }
 };
 
 template <bool DOT>
@@ -250,6 +380,9 @@ __global__ void __launch_bounds__(NTH) k_level_kblock_mixed(const double* __rest
   if (sp.hi)
     mixed_tile_split(sp.hi, sp.lo, sp.nrm, sp.dp, Idx{rows + (int64_t)node * s_cap + r0, 0}, min(TM, s - r0),
                      Idx{cols + (int64_t)node * n_cap + c0, 0}, min(TN, n - c0), sm, acc);
+  else if (sp.x)
+    mixed_tile_cached<!DOT>(sp.x, sp.centre<DOT>(node), sp.dp, Idx{rows + (int64_t)node * s_cap + r0, 0},
+                            min(TM, s - r0), Idx{cols + (int64_t)node * n_cap + c0, 0}, min(TN, n - c0), sm, acc);
   else
     mixed_tile<!DOT>(Xt, Idx{rows + (int64_t)node * s_cap + r0, 0}, min(TM, s - r0), Xt,
                      Idx{cols + (int64_t)node * n_cap + c0, 0}, min(TN, n - c0), d, centroid + (int64_t)node * d, sm,
@@ -281,12 +414,15 @@ template <bool DOT>
 __device__ inline void mixed_sum(const double* __restrict__ Y, Idx rows, int nrows, const double* __restrict__ X,
                                  Idx cols, int ncols, const double* __restrict__ q, int d,
                                  const double* __restrict__ center, const KParams& kp, MixSmem& sm, double (&part)[2],
-                                 bool& bad, Split sp = Split{nullptr, nullptr, nullptr, 0}) {
+                                 bool& bad, Split sp = Split{}, int cen_node = 0) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int c0 = 0; c0 < ncols; c0 += TN) {
     Idx cm{cols.idx ? cols.idx + c0 : nullptr, cols.base + c0};
     f32x4 acc[2][2];
-    if (sp.hi) mixed_tile_split(sp.hi, sp.lo, sp.nrm, sp.dp, rows, nrows, cm, min(TN, ncols - c0), sm, acc);
+    if (sp.hi)
+      mixed_tile_split(sp.hi, sp.lo, sp.nrm, sp.dp, rows, nrows, cm, min(TN, ncols - c0), sm, acc);
+    else if (sp.x)
+      mixed_tile_cached<!DOT>(sp.x, sp.centre<DOT>(cen_node), sp.dp, rows, nrows, cm, min(TN, ncols - c0), sm, acc);
     else mixed_tile<!DOT>(Y, rows, nrows, X, cm, min(TN, ncols - c0), d, center, sm, acc);
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
@@ -357,13 +493,14 @@ __global__ void __launch_bounds__(NTH) k_evaluate_mixed(const double* __restrict
     const int r = rank[sib];
     if (r > 0)
       mixed_sum<DOT>(Xt, rmap, nrows, Xt, Idx{skel + (int64_t)sib * r_cap, 0}, r, qt + (int64_t)sib * r_cap, d, cen,
-                     kp, sm, part, bad, sp);
+                     kp, sm, part, bad, sp, leaf);
     a = (a - 1) >> 1;
   }
   mixed_reduce(part, red, far_sum);
   double npart[2] = {0.0, 0.0};
   const int lb = nb[leaf];
-  mixed_sum<DOT>(Xt, rmap, nrows, Xt, Idx{nullptr, lb}, ne[leaf] - lb, q_tree + lb, d, cen, kp, sm, npart, bad, sp);
+  mixed_sum<DOT>(Xt, rmap, nrows, Xt, Idx{nullptr, lb}, ne[leaf] - lb, q_tree + lb, d, cen, kp, sm, npart, bad, sp,
+                 leaf);
   mixed_reduce(npart, red, near_sum);
   if (threadIdx.x < nrows) {
     const int ci = perm[start + threadIdx.x];
@@ -400,15 +537,51 @@ __global__ void __launch_bounds__(NTH) k_direct_mixed(const double* __restrict__
 }  // namespace
 
 namespace {
-// The tree's pre-split points and norms (made on first use; a stream being
-// captured must find them made).
+// Whether the Gaussian can take the split coordinates as they are. The
+// split's error on a squared distance grows with the two points' norms, so
+// they are taken only where every leaf's centroid lies within four leaf radii
+// of the origin: near pairs' norms then exceed what centring on their leaf
+// would give at most 25-fold (about 4.6 of the split's 16 bits). Otherwise
+// every tile centres while staging. Reads the leaves' centroids and radii
+// back once.
+ffc_status gaussian_frame_ok(const ffc_tree* t, hipStream_t st, bool& ok) {
+  const int first = (1 << t->depth) - 1, leaves = 1 << t->depth;
+  std::vector<double> c((size_t)leaves * t->d), r(leaves);
+  FFC_HIP_TRY(hipMemcpyAsync(c.data(), t->centroid.ptr + (int64_t)first * t->d, c.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+  FFC_HIP_TRY(hipMemcpyAsync(r.data(), t->radius.ptr + first, r.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  FFC_HIP_TRY(hipStreamSynchronize(st));
+  ok = true;
+  for (int l = 0; l < leaves && ok; ++l) {
+    double n2 = 0.0;
+    for (int k = 0; k < t->d; ++k) n2 += c[(size_t)l * t->d + k] * c[(size_t)l * t->d + k];
+    ok = n2 <= 16.0 * r[l] * r[l];
+  }
+  return FFC_OK;
+}
+
+// The tree's matrix-core operands (made on first use; a stream being captured
+// must find them made).
 ffc_status tree_split(const ffc_tree* t, const KParams& kp, hipStream_t st, Split& sp) {
-  sp = Split{nullptr, nullptr, nullptr, 0};
+  sp = Split{};
   if (kp.kind == FFC_LAPLACE) return FFC_OK;
   ffc_tree* tm = const_cast<ffc_tree*>(t);
   const int dp = (t->d + KCH - 1) / KCH * KCH;
-  const size_t n = (size_t)t->N * dp;
-  if (tm->bf_dp != dp || tm->bf_hi.count != n) {
+  const size_t n = (size_t)t->N * dp, nc = (size_t)(t->num_nodes + 1) * dp;
+  const bool make = tm->bf_dp != dp || tm->bf_hi.count != n;
+  if (make || (kp.kind == FFC_GAUSSIAN && tm->bf_frame < 0)) {
+    // Made once, eagerly: a captured graph would only make them when replayed.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    FFC_HIP_TRY(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) {
+      set_error("mixed precision: skeletonize or evaluate once in mixed precision with this kernel function on "
+                "this tree before capturing (the matrix-core operands are prepared then)");
+      return FFC_ERR_STATE;
+    }
+  }
+  if (make) {
+    tm->bf_dp = 0;
+    tm->bf_frame = -1;
     FFC_TRY(tm->bf_hi.alloc(n));
     FFC_TRY(tm->bf_lo.alloc(n));
     FFC_TRY(tm->bf_nrm.alloc((size_t)t->N));
@@ -420,8 +593,31 @@ ffc_status tree_split(const ffc_tree* t, const KParams& kp, hipStream_t st, Spli
     FFC_LAUNCH_CHECK("k_point_norms");
     tm->bf_dp = dp;
   }
-  sp = Split{reinterpret_cast<const __bf16*>(t->bf_hi.ptr), reinterpret_cast<const __bf16*>(t->bf_lo.ptr),
-             kp.kind == FFC_GAUSSIAN ? t->bf_nrm.ptr : nullptr, dp};
+  if (kp.kind == FFC_GAUSSIAN && tm->bf_frame < 0) {
+    bool ok = false;
+    FFC_TRY(gaussian_frame_ok(t, st, ok));
+    if (!ok) {
+      FFC_TRY(tm->bf_x.alloc(n));
+      FFC_TRY(tm->bf_cc.alloc(nc));
+      hipLaunchKernelGGL(k_offset_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t->Xt.ptr, t->N, t->d,
+                         dp, t->centroid.ptr, tm->bf_x.ptr);
+      FFC_LAUNCH_CHECK("k_offset_points");
+      hipLaunchKernelGGL(k_offset_centres, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, t->centroid.ptr,
+                         t->num_nodes, t->d, dp, tm->bf_cc.ptr);
+      FFC_LAUNCH_CHECK("k_offset_centres");
+    }
+    tm->bf_frame = ok ? 1 : 0;
+  }
+  if (kp.kind == FFC_GAUSSIAN && tm->bf_frame == 0) {
+    sp.x = t->bf_x.ptr;
+    sp.cc = t->bf_cc.ptr;
+    sp.origin = t->num_nodes;
+  } else {
+    sp.hi = reinterpret_cast<const __bf16*>(t->bf_hi.ptr);
+    sp.lo = reinterpret_cast<const __bf16*>(t->bf_lo.ptr);
+    sp.nrm = kp.kind == FFC_GAUSSIAN ? t->bf_nrm.ptr : nullptr;
+  }
+  sp.dp = dp;
   return FFC_OK;
 }
 }  // namespace

@@ -21,7 +21,10 @@ def ffc():
     return m
 
 
-@pytest.mark.parametrize("kind,kw,precision", [(GAUSSIAN, dict(h=1.0), 0), (POLYNOMIAL, dict(h=2.0, p=2), 2)])
+# Mixed precision (2) with the Gaussian on these clusters centres every tile while staging; the
+# polynomial kernel takes the split coordinates as they are.
+@pytest.mark.parametrize("kind,kw,precision", [(GAUSSIAN, dict(h=1.0), 0), (POLYNOMIAL, dict(h=2.0, p=2), 2),
+                                               (GAUSSIAN, dict(h=1.0), 2)])
 def test_step_graph_replays_match_eager(ffc, kind, kw, precision):
     X = W.gaussian_mixture(4096, 8, k=8, box=6.0, std=0.5, seed=3)
     q = torch.as_tensor(W.charges(4096, seed=1), device="cuda")
@@ -63,3 +66,30 @@ def test_step_graph_rejects_null_stream_and_fallback(ffc):
     with pytest.raises(ffc.FfcError) as e:
         ffc.StepGraph(tree, sk, k, q, u, None, torch.cuda.default_stream(), tol=1e-6, max_rank=32)
     assert e.value.code == ffc.FFC_ERR_INVALID_ARG
+
+
+def test_mixed_graph_needs_its_operands_prepared_eagerly(ffc):
+    """The matrix-core operands of a tree are prepared by the first eager
+    mixed-precision call; capturing before that is refused with FFC_ERR_STATE
+    instead of recording a preparation that would only run at replay."""
+    X = W.gaussian_mixture(2048, 8, k=4, box=6.0, std=0.5, seed=2)
+    q = torch.as_tensor(W.charges(2048, seed=1), device="cuda")
+    k = gkernel(GAUSSIAN, h=1.0)
+    opts = dict(tol=1e-6, max_rank=32, num_samples=64, seed=1)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        tree = ffc.build_tree(X, 256)
+        sk = ffc.skeletonize(tree, k, **opts)
+        u = torch.zeros(2048, dtype=torch.float64, device="cuda")
+        uf = torch.zeros(2048, dtype=torch.float64, device="cuda")
+        with pytest.raises(ffc.FfcError) as e:
+            ffc.StepGraph(tree, sk, k, q, u, uf, stream, precision=ffc.MIXED_BF16X3, **opts)
+        assert e.value.code == ffc.FFC_ERR_STATE
+        sk = ffc.skeletonize(tree, k, precision=ffc.MIXED_BF16X3, **opts)
+        u_e, uf_e = ffc.evaluate_sum(tree, sk, k, q, precision=ffc.MIXED_BF16X3)
+        g = ffc.StepGraph(tree, sk, k, q, u, uf, stream, precision=ffc.MIXED_BF16X3, **opts)
+        g.launch(stream)
+        stream.synchronize()
+        np.testing.assert_array_equal(u.cpu().numpy(), u_e.cpu().numpy())
+        np.testing.assert_array_equal(uf.cpu().numpy(), uf_e.cpu().numpy())
+    ffc.check_device(stream)

@@ -69,6 +69,9 @@ def test_direct_sum_mixed_laplace_uses_float_differences(ffc):
 @pytest.mark.parametrize("name,make,kind,kw,leaf,tol,mr", [
     ("poly-d4-p3", lambda: W.uniform_cube(4096, 4, seed=0), POLYNOMIAL, dict(h=1.0, p=3), 256, 1e-9, 128),
     ("gauss-d8-h3", lambda: W.uniform_cube(4096, 8, seed=0), GAUSSIAN, dict(h=3.0), 256, 1e-8, 128),
+    # The same points moved far from the origin: distances, and so the result, must not change. Split
+    # without centring, the coordinates' 16 bits would lose near pairs' distances to cancellation.
+    ("gauss-d8-h3-offset", lambda: W.uniform_cube(4096, 8, seed=0) + 40.0, GAUSSIAN, dict(h=3.0), 256, 1e-8, 128),
 ])
 def test_mixed_far_field_within_1e4_of_fp64_oracle(ffc, name, make, kind, kw, leaf, tol, mr):
     X = make()
