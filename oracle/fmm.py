@@ -63,8 +63,11 @@ def fmm_lists(Xt: np.ndarray, tree: Tree, xi: float):
     return far, near
 
 
-def fmm_evaluate(X: np.ndarray, tree: Tree, sk: Skeletons, k: Kernel, q: np.ndarray, xi: float):
-    """Return (u, u_far) in caller order."""
+def fmm_evaluate(X: np.ndarray, tree: Tree, sk: Skeletons, k: Kernel, q: np.ndarray, xi: float,
+                 targets: np.ndarray | None = None):
+    """Return (u, u_far) in caller order; with targets (caller indices), only
+    those entries, in that order (the direct leaf sums of the other targets
+    are skipped)."""
     Xt = np.asarray(X, dtype=np.float64)[tree.perm]
     q_tree = np.asarray(q, dtype=np.float64)[tree.perm]
     qt = upward_charges(tree, sk, q_tree)
@@ -86,14 +89,22 @@ def fmm_evaluate(X: np.ndarray, tree: Tree, sk: Skeletons, k: Kernel, q: np.ndar
                 rl = sk.nodes[2 * b + 1].rank
                 v[2 * b + 1] += w[:rl]
                 v[2 * b + 2] += w[rl:]
+    keep = np.ones(tree.N, dtype=bool)
+    if targets is not None:
+        keep[:] = False
+        keep[np.argsort(tree.perm)[np.asarray(targets)]] = True
     u_near = np.zeros(tree.N)
     for L, srcs in near.items():
         b, e = int(tree.begin[L]), int(tree.end[L])
+        T = b + np.flatnonzero(keep[b:e])
         for a in srcs:
             ab, ae = int(tree.begin[a]), int(tree.end[a])
-            u_near[b:e] += kernel_matrix(Xt[b:e], Xt[ab:ae], k) @ q_tree[ab:ae]
+            if len(T):
+                u_near[T] += kernel_matrix(Xt[T], Xt[ab:ae], k) @ q_tree[ab:ae]
     u = np.empty(tree.N)
     uf = np.empty(tree.N)
     u[tree.perm] = u_far + u_near
     uf[tree.perm] = u_far
+    if targets is not None:
+        return u[targets], uf[targets]
     return u, uf

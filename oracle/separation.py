@@ -102,12 +102,19 @@ def interaction_lists(Xt: np.ndarray, tree: Tree, xi: float):
     return far, near
 
 
-def treecode_evaluate(X: np.ndarray, tree: Tree, sk: Skeletons, k: Kernel, q: np.ndarray, xi: float):
-    """Return (u, u_far) in caller order."""
+def treecode_evaluate(X: np.ndarray, tree: Tree, sk: Skeletons, k: Kernel, q: np.ndarray, xi: float,
+                      targets: np.ndarray | None = None):
+    """Return (u, u_far) in caller order; with targets (caller indices), only
+    those entries, in that order (the sums of the other targets are skipped)."""
     Xt = np.asarray(X, dtype=np.float64)[tree.perm]
     q_tree = np.asarray(q, dtype=np.float64)[tree.perm]
     qt = upward_charges(tree, sk, q_tree)
     far, near = interaction_lists(Xt, tree, xi)
+    if targets is not None:
+        keep = np.zeros(tree.N, dtype=bool)
+        keep[np.argsort(tree.perm)[np.asarray(targets)]] = True
+        far = {a: T[keep[T]] for a, T in far.items()}
+        near = {a: T[keep[T]] for a, T in near.items()}
     u_far = np.zeros(tree.N)
     u_near = np.zeros(tree.N)
     for a in range(1, tree.num_nodes):
@@ -124,4 +131,6 @@ def treecode_evaluate(X: np.ndarray, tree: Tree, sk: Skeletons, k: Kernel, q: np
     uf = np.empty(tree.N)
     u[tree.perm] = u_far + u_near
     uf[tree.perm] = u_far
+    if targets is not None:
+        return u[targets], uf[targets]
     return u, uf

@@ -114,3 +114,22 @@ def test_separated_laplace_close_to_treecode():
     e_fmm = np.linalg.norm(u_fmm - ref) / np.linalg.norm(ref)
     assert np.linalg.norm(uf) > 0.05 * np.linalg.norm(u_fmm)
     assert e_fmm < 1e-3 and e_fmm <= e_tc, (e_fmm, e_tc)
+
+
+def test_target_subsets_give_the_same_values():
+    """With a target subset, the treecode and the FMM-style evaluation skip the
+    other targets' sums and return the full evaluation's entries (up to the
+    rounding of the library's matrix-vector products, whose blocking depends
+    on the number of rows)."""
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((2000, 3))
+    t = build_tree(X, 100)
+    k = Kernel(LAPLACE)
+    q = W.charges(t.N, seed=2)
+    sk = S.skeletonize_separated(X, t, k, tol=1e-8, max_rank=24, num_samples=64, seed=1, xi=1.0)
+    tg = W.subset(t.N, 97, seed=5)
+    for ev in (S.treecode_evaluate, F.fmm_evaluate):
+        u, uf = ev(X, t, sk, k, q, 1.0)
+        us, ufs = ev(X, t, sk, k, q, 1.0, targets=tg)
+        np.testing.assert_allclose(us, u[tg], rtol=1e-13, atol=1e-13 * np.abs(u).max())
+        np.testing.assert_allclose(ufs, uf[tg], rtol=1e-13, atol=1e-13 * np.abs(uf).max())
