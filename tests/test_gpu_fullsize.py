@@ -1,12 +1,16 @@
 """Parity at the workloads' full sizes, in the configuration bench.py times:
-every node of the mixture16 tree (N = 65536, d = 16) against the oracle's own
-skeletonization and evaluation; sampled leaves and sampled direct-sum targets
-of the d = 1000 and N = 262144 workloads."""
+every node of the mixture16 tree (N = 65536, d = 16) and of the separated
+Laplace trees (N = 65536, d = 3; treecode at separation 2, FMM-style at 1)
+against the oracle's own skeletonization and evaluation (the Laplace sums on
+sampled targets); sampled leaves and sampled direct-sum targets of the
+d = 1000 and N = 262144 workloads."""
 import numpy as np
 import pytest
 import torch
 
 from oracle.direct import direct_sum as o_direct
+from oracle.fmm import fmm_evaluate
+from oracle.separation import skeletonize_separated, treecode_evaluate
 from oracle.evaluate import evaluate as o_evaluate
 from oracle.kernels import GAUSSIAN, LAPLACE, POLYNOMIAL
 from oracle.skeleton import skeletonize as o_skeletonize
@@ -111,3 +115,36 @@ def test_subspace64_sampled_leaves(ffc):
         o = skeletonize_node(Xt, ot, int(a), cols, ok, 1e-6, 256, 512, 0)
         compared += check_node(sk.node(int(a)), o, 1e-6)
     assert compared >= 2
+
+
+@pytest.mark.parametrize("xi,fmm", [(2.0, False), (1.0, True)])
+def test_separated_laplace_every_node(ffc, xi, fmm):
+    """The separated3 (treecode, xi = 2) and fmm3 (FMM-style, xi = 1) workloads: N=65536, d=3 N(0,I), Laplace
+    1/r, leaf 256, s=256, rank cap 128, tol 1e-6, FP64: all 510 nodes, then the far field and the whole sum at
+    512 sampled targets."""
+    X = W.normal(65536, 3, seed=0)
+    q = W.charges(65536, seed=1)
+    gk, ok = gkernel(LAPLACE), okernel(LAPLACE)
+    t = ffc.build_tree(X, 256)
+    sk = ffc.skeletonize(t, gk, tol=1e-6, max_rank=128, num_samples=256, seed=0, separation=xi)
+    u, uf = (ffc.evaluate_fmm if fmm else ffc.evaluate_sum)(t, sk, gk, q)
+    u, uf = u.cpu().numpy(), uf.cpu().numpy()
+    ot = o_build_tree(X, 256)
+    np.testing.assert_array_equal(t.arrays()["perm"], ot.perm)
+    osk = skeletonize_separated(X, ot, ok, 1e-6, 128, 256, 0, xi)
+    full, stop = 0, None
+    for level in range(ot.depth, 0, -1):
+        for a in ot.level_nodes(level):
+            if stop is not None:
+                break
+            if check_node(sk.node(a), osk.nodes[a], 1e-6):
+                full += 1
+            else:
+                stop = a
+    assert full >= (1 << ot.depth), (full, stop)
+    print(f"xi={xi} fmm={fmm}: {full} nodes compared in full, first ambiguous node {stop}")
+    if stop is None:
+        tg = W.subset(65536, 512, seed=2)
+        ou, ouf = (fmm_evaluate if fmm else treecode_evaluate)(X, ot, osk, ok, q, xi, targets=tg)
+        assert rel(uf[tg], ouf) < FP64_REL
+        assert rel(u[tg], ou) < FP64_REL
