@@ -166,8 +166,8 @@ __global__ void __launch_bounds__(NT) k_p2p(const double* __restrict__ Xt, int d
 }
 
 template <typename F>
-ffc_status dispatch_tiles(int precision, int kind, F&& f) {
-  return with_kind(kind, [&](auto kv) -> ffc_status {
+ffc_status dispatch_tiles(int precision, const KParams& kp, F&& f) {
+  return with_kind(kp, [&](auto kv) -> ffc_status {
     if (precision == FFC_FP64) return f(double(), kv);
     return f(float(), kv);
   });
@@ -260,7 +260,7 @@ ffc_status launch_fmm(const ffc_tree* t, ffc_skel* sk, const KParams& kp, int pr
   if (sk->fmm_ufar.count != (size_t)t->N) FFC_TRY(sk->fmm_ufar.alloc((size_t)t->N));
   const int chunks = (sk->r_cap + BM - 1) / BM;
   const int leaf0 = (1 << t->depth) - 1;
-  return dispatch_tiles(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
+  return dispatch_tiles(precision, kp, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
     constexpr int KF = decltype(kv)::value;
     return with_dims(t->d, [&](auto dm) -> ffc_status {

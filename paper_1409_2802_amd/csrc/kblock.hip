@@ -337,8 +337,8 @@ __global__ void __launch_bounds__(NT) k_direct(const double* __restrict__ Y, int
 }
 
 template <typename F>
-ffc_status dispatch(int precision, int kind, F&& f) {
-  return with_kind(kind, [&](auto kv) -> ffc_status {
+ffc_status dispatch(int precision, const KParams& kp, F&& f) {
+  return with_kind(kp, [&](auto kv) -> ffc_status {
     if (precision == FFC_FP64) return f(double(), kv);
     return f(float(), kv);
   });
@@ -356,7 +356,7 @@ ffc_status launch_kblock_batch(const ffc_tree* t, const KParams& kp, int precisi
   const int tiles_m = (s_cap + BM - 1) / BM, tiles_n = (n_cap + BN - 1) / BN;
   const int64_t blocks = (int64_t)count * tiles_m * tiles_n;
   if (blocks == 0) return FFC_OK;
-  return dispatch(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
+  return dispatch(precision, kp, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
     constexpr int KF = decltype(kv)::value;
     hipLaunchKernelGGL((k_level_kblock<T, KF>), dim3((unsigned)blocks), dim3(NT), 0, st, t->Xt.ptr, t->d, kp, first,
@@ -405,7 +405,7 @@ ffc_status launch_gram(const double* B, int m, int n, int count, double* G, hipS
 ffc_status launch_sampled_block(const ffc_tree* t, const KParams& kp, int precision, const int32_t* rows, int s,
                                 const int32_t* cols, int n, double* out, hipStream_t st) {
   const int tiles_m = (s + BM - 1) / BM, tiles_n = (n + BN - 1) / BN;
-  return dispatch(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
+  return dispatch(precision, kp, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
     constexpr int KF = decltype(kv)::value;
     hipLaunchKernelGGL((k_sampled_block<T, KF>), dim3((unsigned)(tiles_m * tiles_n)), dim3(NT), 0, st, t->Xt.ptr,
@@ -418,7 +418,7 @@ ffc_status launch_sampled_block(const ffc_tree* t, const KParams& kp, int precis
 ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, double* u,
                            double* u_far, hipStream_t st) {
   if (precision == FFC_MIXED_BF16X3 && kp.kind != FFC_LAPLACE) return launch_evaluate_mixed(t, sk, kp, u, u_far, st);
-  return dispatch(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
+  return dispatch(precision, kp, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
     constexpr int KF = decltype(kv)::value;
     return with_dims(t->d, [&](auto dm) -> ffc_status {
@@ -461,7 +461,7 @@ ffc_status launch_treecode(const ffc_tree* t, const ffc_skel* sk, const KParams&
     set_error("separation bitmaps are missing");
     return FFC_ERR_STATE;
   }
-  return dispatch(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
+  return dispatch(precision, kp, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
     constexpr int KF = decltype(kv)::value;
     return with_dims(t->d, [&](auto dm) -> ffc_status {
@@ -480,7 +480,7 @@ ffc_status launch_direct_sum(const double* Y, int64_t m, const double* X, int64_
                              int precision, const double* q, double* u, hipStream_t st) {
   if (m == 0) return FFC_OK;
   if (precision == FFC_MIXED_BF16X3 && kp.kind != FFC_LAPLACE) return launch_direct_mixed(Y, m, X, n, d, kp, q, u, st);
-  return dispatch(precision, kp.kind, [&](auto tv, auto kv) -> ffc_status {
+  return dispatch(precision, kp, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
     constexpr int KF = decltype(kv)::value;
     return with_dims(d, [&](auto dm) -> ffc_status {

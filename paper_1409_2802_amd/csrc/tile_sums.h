@@ -41,9 +41,25 @@ __device__ inline double laplace_of_r2(double r2, const KParams& kp) {
   return laplace_pow(r2, kp.lap_expo);
 }
 
+// Kernel-function code of the Laplace kernel in d = 3 (1/r): its own kernel
+// instances, whose values need no run-time choice of power.
+constexpr int KF_LAPLACE_R1 = 3;
+
+// 1/r of r2 for the d = 3 Laplace kernel: the arithmetic of laplace_of_r2
+// (odd d, power 1), with r2 = 0 selected to 0 and only the rare range
+// (0, 2^-900] branching to the general power.
+__device__ inline double laplace_r1(double r2, const KParams& kp) {
+  double b = __builtin_amdgcn_rsq(r2);
+  b = fma(0.5 * b, fma(-r2, b * b, 1.0), b);
+  b = fma(0.5 * b, fma(-r2, b * b, 1.0), b);
+  double v = r2 > 0x1p-900 ? b : 0.0;
+  if (r2 > 0.0 && !(r2 > 0x1p-900)) v = laplace_pow(r2, kp.lap_expo);
+  return v;
+}
+
 // Kernel function of an accumulated distance^2 (or inner product for the
-// polynomial kernel); KF is the ffc_kernel_kind, fixed at compile time so each
-// kernel instance holds only its own function.
+// polynomial kernel); KF is the ffc_kernel_kind (or KF_LAPLACE_R1), fixed at
+// compile time so each kernel instance holds only its own function.
 template <int KF>
 __device__ inline double kfun(double acc, const KParams& kp) {
   if constexpr (KF == FFC_POLYNOMIAL) {
@@ -53,6 +69,8 @@ __device__ inline double kfun(double acc, const KParams& kp) {
     return r;
   } else if constexpr (KF == FFC_GAUSSIAN) {
     return exp(acc * kp.neg_inv_2h2);
+  } else if constexpr (KF == KF_LAPLACE_R1) {
+    return laplace_r1(acc, kp);
   } else {
     return acc > 0.0 ? laplace_of_r2(acc, kp) : 0.0;
   }
@@ -216,11 +234,14 @@ __device__ inline void sum_sources(const double* __restrict__ Y, IdxMap rows, in
   else sum_over_sources<T, KF>(Y, rows, nrows, X, cols, ncols, q, d, kp, sm, part, bad);
 }
 
-// Host side: the kernel function (ffc_kernel_kind) as a compile-time constant.
+// Host side: the kernel function (ffc_kernel_kind, or KF_LAPLACE_R1 for the
+// Laplace kernel in d = 3) as a compile-time constant.
 template <typename F>
-inline auto with_kind(int kind, F&& f) {
-  if (kind == FFC_GAUSSIAN) return f(std::integral_constant<int, FFC_GAUSSIAN>());
-  if (kind == FFC_LAPLACE) return f(std::integral_constant<int, FFC_LAPLACE>());
+inline auto with_kind(const KParams& kp, F&& f) {
+  if (kp.kind == FFC_GAUSSIAN) return f(std::integral_constant<int, FFC_GAUSSIAN>());
+  if (kp.kind == FFC_LAPLACE && kp.lap_small && kp.lap_odd && kp.lap_m == 1)
+    return f(std::integral_constant<int, KF_LAPLACE_R1>());
+  if (kp.kind == FFC_LAPLACE) return f(std::integral_constant<int, FFC_LAPLACE>());
   return f(std::integral_constant<int, FFC_POLYNOMIAL>());
 }
 
