@@ -21,6 +21,25 @@ def ffc():
     return m
 
 
+def test_laplace_d3_coincident_and_tiny_distances(ffc):
+    """The d = 3 Laplace kernel (1/r, its own kernel instances): coincident points give 0, and squared
+    distances in (0, 2^-900], below the range of the reciprocal square root estimate, take the general
+    power; both in the direct sum against the oracle."""
+    Y = W.normal(70, 3, seed=4)
+    X = W.normal(130, 3, seed=5)
+    X[:3] = Y[:3]                              # r = 0
+    Y[3:6] = 0.0
+    X[3:6] = 0.0
+    X[3:6, 0] = [1e-140, 3e-137, 2e-160]       # r^2 = 1e-280, 9e-274, 4e-320 (subnormal)
+    q = W.charges(130, seed=6)
+    k = dict()
+    u = ffc.direct_sum(Y, X, q, gkernel(1, **k)).cpu().numpy()
+    ref = o_direct(Y, X, q, okernel(1, **k))
+    assert np.all(np.isfinite(u)) and np.abs(u[3:6]).min() > 1e130
+    assert np.all(np.abs(u - ref) <= direct_bound(Y, X, q, 1, k))
+    ffc.check_device()
+
+
 @pytest.mark.parametrize("name", list(KERNELS))
 @pytest.mark.parametrize("m,n,d", [(1, 1, 3), (65, 130, 4), (333, 1000, 16), (200, 257, 64), (70, 90, 1000)])
 def test_direct_sum_fp64(ffc, name, m, n, d):

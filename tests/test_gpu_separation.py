@@ -41,6 +41,7 @@ def clear_far_set(Xt, ot, a, xi, margin=1e-9):
 CASES = [
     (GAUSSIAN, dict(h=1.0), 1.0, 3000, 4, 100),
     (LAPLACE, dict(), 2.0, 3000, 4, 100),
+    (LAPLACE, dict(), 2.0, 3000, 3, 100),
     (LAPLACE, dict(), 1.5, 2500, 5, 160),
     (POLYNOMIAL, dict(h=4.0, p=3), 1.2, 2000, 6, 128),
 ]
