@@ -61,7 +61,13 @@ typedef struct {
  * float64. FFC_MIXED_BF16X3 splits coordinates into bfloat16 hi + lo parts and
  * forms the Gram products hi*hi + hi*lo + lo*hi on matrix cores with float32
  * accumulation (Gaussian and polynomial kernels; the Laplace kernel is always
- * evaluated from explicit float32 differences in that mode). */
+ * evaluated from explicit float32 differences in that mode). For the Gaussian,
+ * coordinates are centred on each tile's node (or target leaf) before the
+ * split unless every leaf of the tree lies within four of its radii of the
+ * origin. The first mixed-precision call on a tree prepares these operands
+ * (4 N dp bytes of device memory kept with the tree, 8 N dp with per-tile
+ * centring; dp = d rounded up to a multiple of 32) and cannot be made while
+ * the stream is captured (FFC_ERR_STATE). */
 typedef enum { FFC_FP64 = 0, FFC_FP32 = 1, FFC_MIXED_BF16X3 = 2 } ffc_precision;
 
 /* Row samplers. UNIFORM: uniform without replacement over the points outside
