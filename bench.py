@@ -381,9 +381,8 @@ def main():
         return sk
 
     # Steps that synchronize inside (the learned fallback check, the adaptive rounds) cannot be captured.
-    # The FMM-style evaluation is not part of the captured step (its entry point is not in the graph API).
     use_graph = not args.eager and not (proposal is not None and w.get("fallback_tol", 0.0) > 0) \
-        and not w.get("adaptive_tol", 0.0) > 0 and w.get("evaluation") != "fmm"
+        and not w.get("adaptive_tol", 0.0) > 0
 
     def timed(p, steps, warmup, out):
         """Warm-up with eager calls, then time `steps` steps in precision p (graph replays unless --eager)."""
@@ -397,7 +396,8 @@ def main():
         if use_graph:
             graph = ffc.StepGraph(tree, sk, k, qd, out[0], out[1], st, tol=w["tol"], max_rank=w["max_rank"],
                                   num_samples=w["num_samples"], precision=p, seed=0, proposal=proposal,
-                                  pool_factor=w.get("pool_factor", 0), separation=w.get("separation", 0.0))
+                                  pool_factor=w.get("pool_factor", 0), separation=w.get("separation", 0.0),
+                                  fmm=w.get("evaluation") == "fmm")
             graph.launch(st)
         st.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

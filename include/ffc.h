@@ -309,6 +309,14 @@ typedef struct ffc_graph ffc_graph;
 ffc_status ffc_step_graph_create(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* k, const ffc_skel_opts* o,
                                  const double* q_dev, double* u_dev, double* u_far_dev, int32_t precision,
                                  void* stream, ffc_graph** out);
+/* The same with the FMM-style evaluation (ffc_evaluate_fmm) in place of
+ * ffc_evaluate_sum: o->separation must be > 0 (FFC_ERR_INVALID_ARG), and one
+ * eager ffc_evaluate_fmm with this skeleton set at that separation must come
+ * first, since it builds the interaction lists on the host (FFC_ERR_STATE
+ * otherwise). */
+ffc_status ffc_step_graph_create_fmm(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* k, const ffc_skel_opts* o,
+                                     const double* q_dev, double* u_dev, double* u_far_dev, int32_t precision,
+                                     void* stream, ffc_graph** out);
 ffc_status ffc_graph_launch(ffc_graph* g, void* stream);
 void ffc_graph_free(ffc_graph* g);
 

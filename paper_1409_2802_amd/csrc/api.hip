@@ -708,11 +708,13 @@ struct ffc_graph {
   hipGraphExec_t exec = nullptr;
 };
 
-extern "C" {
+namespace {
 
-ffc_status ffc_step_graph_create(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* k, const ffc_skel_opts* o,
-                                 const double* q_dev, double* u_dev, double* u_far_dev, int32_t precision,
-                                 void* stream, ffc_graph** out) {
+// One captured step: skeletonize with reuse, then the sibling-cover or
+// treecode evaluation (fmm false) or the FMM-style evaluation (fmm true).
+ffc_status create_step_graph(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* k, const ffc_skel_opts* o,
+                             const double* q_dev, double* u_dev, double* u_far_dev, int32_t precision,
+                             void* stream, bool fmm, ffc_graph** out) {
   using namespace ffc;
   if (!t || !sk || !k || !o || !q_dev || !u_dev || !out) {
     set_error("NULL argument (a skeleton set from a previous skeletonization is required)");
@@ -734,11 +736,23 @@ ffc_status ffc_step_graph_create(const ffc_tree* t, ffc_skel* sk, const ffc_kern
     set_error("separation: skeletonize once with a separation > 0 before capturing (its bitmaps are allocated then)");
     return FFC_ERR_STATE;
   }
+  if (fmm && !(o->separation > 0.0)) {
+    set_error("the FMM-style evaluation needs a separation > 0");
+    return FFC_ERR_INVALID_ARG;
+  }
+  if (fmm && (sk->fmm_xi != o->separation || !sk->fmm_far_off.ptr || !sk->fmm_ufar.ptr)) {
+    set_error("FMM-style graph: evaluate once eagerly with ffc_evaluate_fmm at this separation before capturing "
+              "(its interaction lists and buffers are made then)");
+    return FFC_ERR_STATE;
+  }
   hipStream_t st = (hipStream_t)stream;
   FFC_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
   ffc_skel* skp = sk;
   ffc_status s1 = ffc_skeletonize_nodes(t, k, o, stream, &skp);
-  ffc_status s2 = s1 == FFC_OK ? ffc_evaluate_sum(t, sk, k, q_dev, u_dev, u_far_dev, precision, stream) : s1;
+  ffc_status s2 = s1;
+  if (s1 == FFC_OK)
+    s2 = fmm ? ffc_evaluate_fmm(t, sk, k, q_dev, u_dev, u_far_dev, precision, stream)
+             : ffc_evaluate_sum(t, sk, k, q_dev, u_dev, u_far_dev, precision, stream);
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(st, &graph);
   if (s2 != FFC_OK) {
@@ -762,6 +776,22 @@ ffc_status ffc_step_graph_create(const ffc_tree* t, ffc_skel* sk, const ffc_kern
   g->exec = exec;
   *out = g;
   return FFC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ffc_status ffc_step_graph_create(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* k, const ffc_skel_opts* o,
+                                 const double* q_dev, double* u_dev, double* u_far_dev, int32_t precision,
+                                 void* stream, ffc_graph** out) {
+  return create_step_graph(t, sk, k, o, q_dev, u_dev, u_far_dev, precision, stream, false, out);
+}
+
+ffc_status ffc_step_graph_create_fmm(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* k, const ffc_skel_opts* o,
+                                     const double* q_dev, double* u_dev, double* u_far_dev, int32_t precision,
+                                     void* stream, ffc_graph** out) {
+  return create_step_graph(t, sk, k, o, q_dev, u_dev, u_far_dev, precision, stream, true, out);
 }
 
 ffc_status ffc_graph_launch(ffc_graph* g, void* stream) {

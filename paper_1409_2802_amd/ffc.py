@@ -31,7 +31,7 @@ EXPORTS = [
     "ffc_proposal_create", "ffc_proposal_get", "ffc_proposal_free", "ffc_proposal_features",
     "ffc_proposal_fit_standardization", "ffc_proposal_score", "ffc_proposal_gradient", "ffc_proposal_adam",
     "ffc_leverage_labels", "ffc_proposal_train", "ffc_proposal_training_set",
-    "ffc_step_graph_create", "ffc_graph_launch", "ffc_graph_free", "ffc_autotune_report",
+    "ffc_step_graph_create", "ffc_step_graph_create_fmm", "ffc_graph_launch", "ffc_graph_free", "ffc_autotune_report",
     "ffc_skel_load", "ffc_proposal_get_adam", "ffc_proposal_set_adam",
 ]
 
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ffc_proposal_training_set": [P, ctypes.POINTER(KernelC), ctypes.POINTER(TrainOptsC), P, P, P, P, P, P, P,
                                       P, P],
         "ffc_step_graph_create": [P, P, ctypes.POINTER(KernelC), ctypes.POINTER(SkelOptsC), P, P, P, I32, P, PP],
+        "ffc_step_graph_create_fmm": [P, P, ctypes.POINTER(KernelC), ctypes.POINTER(SkelOptsC), P, P, P, I32, P, PP],
         "ffc_graph_launch": [P, P],
         "ffc_autotune_report": [P, I32, P],
     }
@@ -328,12 +329,13 @@ def skeletonize(tree: Tree, kernel: Kernel, tol: float, max_rank: int, num_sampl
 
 
 class StepGraph:
-    """One step (skeletonize with reuse + evaluate) captured as a HIP graph."""
+    """One step (skeletonize with reuse + evaluate) captured as a HIP graph; fmm selects the FMM-style
+    evaluation (after one eager evaluate_fmm at the same separation)."""
 
     def __init__(self, tree: Tree, sk: Skeletons, kernel: Kernel, q: torch.Tensor, u: torch.Tensor,
                  u_far: torch.Tensor | None, stream, tol: float, max_rank: int, num_samples: int = 0,
                  precision: int = FP64, seed: int = 0, proposal: "Proposal | None" = None, pool_factor: int = 0,
-                 sampler: int | None = None, separation: float = 0.0):
+                 sampler: int | None = None, separation: float = 0.0, fmm: bool = False):
         if sampler is None:
             sampler = SAMPLE_LEARNED if proposal is not None else SAMPLE_UNIFORM
         opts = SkelOptsC(tol=tol, max_rank=max_rank, num_samples=num_samples, precision=precision,
@@ -343,9 +345,9 @@ class StepGraph:
         self._keep = (tree, sk, q, u, u_far, proposal)   # the graph holds their device pointers
         k = kernel.c_struct()
         h = ctypes.c_void_p()
-        _check(load_library().ffc_step_graph_create(tree.handle, sk.handle, ctypes.byref(k), ctypes.byref(opts),
-                                                     _ptr(q), _ptr(u), _ptr(u_far), precision, _stream(stream),
-                                                     ctypes.byref(h)))
+        create = load_library().ffc_step_graph_create_fmm if fmm else load_library().ffc_step_graph_create
+        _check(create(tree.handle, sk.handle, ctypes.byref(k), ctypes.byref(opts), _ptr(q), _ptr(u), _ptr(u_far),
+                      precision, _stream(stream), ctypes.byref(h)))
         self._h = h
 
     def launch(self, stream=None) -> None:

@@ -112,3 +112,34 @@ def test_fmm_errors(ffc):
     with pytest.raises(ffc.FfcError) as e:
         ffc.evaluate_fmm(t, sep, gk, q, precision=ffc.MIXED_BF16X3)
     assert e.value.code == ffc.FFC_ERR_INVALID_ARG
+
+
+def test_fmm_graph_replays(ffc):
+    """A step graph with the FMM-style evaluation: refused before the lists exist and without separation;
+    replays give the eager bits, with an eager skeletonization of another seed between them."""
+    X = W.gaussian_mixture(4096, 3, k=6, box=5.0, std=0.7, seed=7)
+    gk = gkernel(LAPLACE)
+    t = ffc.build_tree(X, 128)
+    kw = dict(tol=1e-7, max_rank=24, num_samples=64, seed=4, separation=1.0)
+    q = torch.as_tensor(W.charges(4096, seed=2), device="cuda")
+    u = torch.zeros_like(q)
+    uf = torch.zeros_like(q)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        sk = ffc.skeletonize(t, gk, **kw)
+        with pytest.raises(ffc.FfcError) as e:     # interaction lists not built yet
+            ffc.StepGraph(t, sk, gk, q, u, uf, stream, fmm=True, **kw)
+        assert e.value.code == ffc.FFC_ERR_STATE
+        eager, eager_far = ffc.evaluate_fmm(t, sk, gk, q)
+        with pytest.raises(ffc.FfcError) as e:
+            ffc.StepGraph(t, sk, gk, q, u, uf, stream, fmm=True, **dict(kw, separation=0.0))
+        assert e.value.code == ffc.FFC_ERR_INVALID_ARG
+        g = ffc.StepGraph(t, sk, gk, q, u, uf, stream, fmm=True, **kw)
+        for rep in range(3):
+            ffc.skeletonize(t, gk, **dict(kw, seed=11 + rep), reuse=sk)
+            u.zero_()
+            uf.zero_()
+            g.launch(stream)
+            stream.synchronize()
+            assert torch.equal(u, eager) and torch.equal(uf, eager_far), rep
+    ffc.check_device(stream)
