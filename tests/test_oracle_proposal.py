@@ -125,3 +125,74 @@ def test_leverage_sampling_beats_uniform_on_coherent_laplace_block():
         idd = interpolative_decomposition(K[rows], 1e-6, 100)
         errs[name] = np.linalg.norm(K - K[:, idd.skel] @ idd.P) / np.linalg.norm(K)
     assert errs["lev"] < 1e-2 * errs["uni"]
+
+
+def _hand_theta():
+    """A sparse parameter vector whose forward pass is worked out by hand below (flat layout: W1 16 x 64
+    row-major at 0, b1 at 1024, W2 64 x 64 row-major at 1088, b2 at 5184, w3 at 5248, b3 at 5312)."""
+    th = np.zeros(P.NPARAM)
+    th[0 * 64 + 0] = 1.0      # W1[0, 0]
+    th[1 * 64 + 1] = -2.0     # W1[1, 1]
+    th[0 * 64 + 2] = 0.5      # W1[0, 2]
+    th[3 * 64 + 0] = 4.0      # W1[3, 0]
+    th[1024 + 0] = 0.25       # b1[0]
+    th[1024 + 1] = 1.0        # b1[1]
+    th[1024 + 2] = -3.0       # b1[2]
+    th[1088 + 0 * 64 + 0] = 1.0    # W2[0, 0]
+    th[1088 + 1 * 64 + 0] = 10.0   # W2[1, 0]
+    th[1088 + 0 * 64 + 1] = -1.0   # W2[0, 1]
+    th[1088 + 2 * 64 + 1] = 3.0    # W2[2, 1]
+    th[5184 + 0] = 0.5        # b2[0]
+    th[5184 + 1] = 1.0        # b2[1]
+    th[5248 + 0] = 2.0        # w3[0]
+    th[5248 + 1] = 5.0        # w3[1]
+    th[5312] = 0.125          # b3
+    return th
+
+
+def test_mlp_forward_hand_values():
+    """Forward pass on hand-worked values, so that a swapped layer, a missing ReLU, a transposed weight or a
+    dropped bias each changes an output (the finite-difference pin only checks the gradient against the
+    forward pass itself).
+
+    Row 1, z = (2, 1, 0, ...): layer 1 pre-activations a = (2 + 0.25, -2 + 1, 1 - 3) = (2.25, -1, -2) -> ReLU
+    (2.25, 0, 0); layer 2: a0 = 2.25 + 10 * 0 + 0.5 = 2.75, a1 = -2.25 + 3 * 0 + 1 = -1.25 -> (2.75, 0);
+    output 2 * 2.75 + 5 * 0 + 0.125 = 5.625.
+    Row 2, z = (-1, -1, 0, 0.5, ...): layer 1 a = (-1 + 2 + 0.25, 2 + 1, -0.5 - 3) = (1.25, 3, -3.5) -> (1.25,
+    3, 0); layer 2: a0 = 1.25 + 30 + 0.5 = 31.75, a1 = -1.25 + 0 + 1 = -0.25 -> (31.75, 0); output 63.625.
+    Row 3, z = (0, ..., 0): hidden units b1 -> (0.25, 1, 0); layer 2: a0 = 0.25 + 10 + 0.5 = 10.75, a1 =
+    -0.25 + 1 = 0.75; output 21.5 + 3.75 + 0.125 = 25.375."""
+    th = _hand_theta()
+    Z = np.zeros((3, P.NF))
+    Z[0, :2] = [2.0, 1.0]
+    Z[1, :4] = [-1.0, -1.0, 0.0, 0.5]
+    y, (_, A1, H1, A2, H2) = P.mlp_forward(th, Z)
+    np.testing.assert_array_equal(y, [5.625, 63.625, 25.375])
+    np.testing.assert_array_equal(A1[0, :3], [2.25, -1.0, -2.0])
+    np.testing.assert_array_equal(H1[0, :3], [2.25, 0.0, 0.0])
+    np.testing.assert_array_equal(A2[1, :2], [31.75, -0.25])
+    np.testing.assert_array_equal(H2[2, :2], [10.75, 0.75])
+    assert np.all(A1[:, 3:] == 0) and np.all(A2[:, 2:] == 0)
+
+
+def test_column_geometry_anchor_order_hand_example():
+    """Farthest-point anchors on four points with centroid 0 (n <= 256, so the subsample is every point in
+    order). Distances to c: P0 4, P1 sqrt(13.25), P2 3, P3 sqrt(21.25). Anchor 1 = P3 (farthest from c);
+    anchor 2 = P0 (farthest from P3: 8.56 against 8.25 and 1.80); anchor 3 = P2 (its distance to the nearer
+    anchor is 1.80, P1's is sqrt(1.25)); anchor 4 = P1. Choosing by distance to c each time would give P3, P0,
+    P1, P2 instead."""
+    Xc = np.array([[4.0, 0.0], [3.5, 1.0], [-3.0, 0.0], [-4.5, -1.0]])
+    g = P.column_geometry(Xc, seed=0, node=1)
+    np.testing.assert_array_equal(g.c, [0.0, 0.0])
+    assert g.rho == pytest.approx(math.sqrt(21.25), rel=1e-15)
+    expect = np.zeros((7, 2))
+    expect[0] = np.array([-4.5, -1.0]) / math.sqrt(21.25)
+    expect[1] = [1.0, 0.0]
+    expect[2] = [-1.0, 0.0]
+    expect[3] = np.array([3.5, 1.0]) / math.sqrt(13.25)
+    np.testing.assert_allclose(g.U, expect, rtol=0, atol=1e-15)
+    # Projections of y = (1, 2): f8..f14 = (y - c) . u_k / rho.
+    F = P.features(np.array([[1.0, 2.0]]), g)
+    rho = math.sqrt(21.25)
+    np.testing.assert_allclose(F[0, 8:15], [-6.5 / math.sqrt(21.25) / rho, 1.0 / rho, -1.0 / rho,
+                                           5.5 / math.sqrt(13.25) / rho, 0.0, 0.0, 0.0], rtol=1e-14, atol=1e-15)
