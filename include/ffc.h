@@ -184,10 +184,22 @@ ffc_status ffc_tree_arrays(const ffc_tree* t, int32_t* perm_host, int64_t* begin
  * stage. *out must be NULL (a new handle is returned) or a handle from an
  * earlier call on the same tree with the same sample count and rank cap,
  * whose storage is then reused and overwritten (FFC_ERR_STATE otherwise).
+ * node_ids_host: NULL (every non-root node; num_ids must be 0) or num_ids >= 1
+ * distinct node ids in [1, num_nodes) (host memory, read during the call):
+ * only those nodes are skeletonized (outgoing representations per source
+ * node, Section 2.2), deepest level first; the others keep what the handle
+ * holds (rank 0 and no columns in a new handle). A listed internal node takes
+ * as columns its children's skeletons as they stand when its level is
+ * reached, so listing a node together with its descendants gives exactly what
+ * the full call gives for it. Subsets work with the uniform sampler (also
+ * with separation) and a fixed sample count; the call copies the list to the
+ * device and synchronizes the stream once, so it cannot be captured.
  * Errors: invalid kernel (h <= 0, p < 1, Laplace with d = 2), tol < 0,
- * max_rank < 1, num_samples < 0, learned sampler without proposal. */
+ * max_rank < 1, num_samples < 0, learned sampler without proposal, a bad
+ * node list (out of range, repeated, num_ids inconsistent with the pointer,
+ * another sampler or the adaptive count) -> FFC_ERR_INVALID_ARG. */
 ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const ffc_skel_opts* o,
-                                 void* stream, ffc_skel** out);
+                                 const int32_t* node_ids_host, int32_t num_ids, void* stream, ffc_skel** out);
 
 /* u = K q with the compressed far field (eq. e:id): equivalent charges
  * q~ = P q upward through the tree, then for every target the skeletons of
@@ -318,6 +330,14 @@ ffc_status ffc_step_graph_create_fmm(const ffc_tree* t, ffc_skel* sk, const ffc_
                                      const double* q_dev, double* u_dev, double* u_far_dev, int32_t precision,
                                      void* stream, ffc_graph** out);
 ffc_status ffc_graph_launch(ffc_graph* g, void* stream);
+/* Lifetime: a graph bakes in device buffers of its tree and skeleton set.
+ * While it exists, a call that would allocate, resize or replace any of them
+ * (an eager ffc_skeletonize_nodes with another separation, sampler, pool or
+ * sample count; ffc_evaluate_fmm at another separation, which rebuilds the
+ * FMM lists) fails with FFC_ERR_STATE and changes nothing; calls that reuse
+ * the buffers as they are stay allowed. ffc_free_tree / ffc_free_skel on a
+ * handle that a graph still holds only mark it: the last ffc_graph_free of
+ * those graphs deletes it. ffc_graph_free synchronizes the device. */
 void ffc_graph_free(ffc_graph* g);
 
 /* ---------------------------------------------------------------------------
@@ -358,6 +378,19 @@ ffc_status ffc_proposal_get(const ffc_proposal* p, float* theta_host, float* mu_
 ffc_status ffc_proposal_get_adam(const ffc_proposal* p, float* m1_host, float* m2_host, int32_t* step);
 ffc_status ffc_proposal_set_adam(ffc_proposal* p, const float* m1_host, const float* m2_host, int32_t step);
 void ffc_proposal_free(ffc_proposal* p);
+/* Checkpoint of a proposal (the learned sampler of Section 3's importance
+ * sampling; the network itself is this library's): parameters,
+ * standardization and Adam state in a versioned binary file (version 1,
+ * little-endian: magic "FFCPROP1", uint32 version, uint32 parameter count,
+ * uint32 feature count, int32 Adam step, float32 theta, mu, sd, m1, m2, then
+ * a 64-bit FNV-1a hash of all preceding bytes). save synchronizes the device
+ * and writes `path` (host file name, overwritten); load reads it and returns a
+ * new handle (free with ffc_proposal_free) whose scores, training and Adam
+ * steps continue exactly where the saved one stood. Errors: NULL arguments, a
+ * file that cannot be opened or written, a wrong size, magic, version,
+ * network shape or hash -> FFC_ERR_INVALID_ARG (nothing is created). */
+ffc_status ffc_proposal_save(const ffc_proposal* p, const char* path);
+ffc_status ffc_proposal_load(const char* path, ffc_proposal** out);
 
 /* Features of target rows against column sets, for `count` blocks: block g
  * has columns cols_dev[g * col_stride + j], j < ncols_dev[g] (tree positions,
@@ -465,6 +498,14 @@ ffc_status ffc_profile_read(double* ms_host, int64_t* launches_host, int32_t num
 
 void ffc_free_tree(ffc_tree* t);
 void ffc_free_skel(ffc_skel* sk);
+/* Releases the library's process-wide device resources: synchronizes the
+ * device, destroys the stage profiler's pooled HIP events and frees the
+ * per-device error flags. Call it after the last handle is freed and before
+ * the process exits, so that nothing of the library's is torn down by static
+ * destructors or runtime teardown (the Python binding calls it at interpreter
+ * exit, after freeing its live handles). Later calls of the library remain
+ * valid and recreate what they need. */
+void ffc_shutdown(void);
 const char* ffc_last_error(void);
 
 #ifdef __cplusplus

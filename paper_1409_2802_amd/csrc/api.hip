@@ -75,6 +75,12 @@ ffc_status finish_tree_common(ffc_tree* t, hipStream_t st) {
 
 void set_error(const std::string& msg) { g_error = msg; }
 
+ffc_status refuse_pinned_alloc() {
+  set_error("a step graph holds this handle's device buffers: free the graph (ffc_graph_free) before a call that "
+            "would resize or replace them (another separation, sampler, pool or sample count, new FMM lists)");
+  return FFC_ERR_STATE;
+}
+
 ffc_status validate_kernel(const ffc_kernel* k, int d) { return check_kernel(k, d); }
 
 bool alloc_forced_to_fail() {
@@ -230,8 +236,8 @@ ffc_status ffc_tree_arrays(const ffc_tree* t, int32_t* perm_host, int64_t* begin
   return FFC_OK;
 }
 
-ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const ffc_skel_opts* o, void* stream,
-                                 ffc_skel** out) {
+ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const ffc_skel_opts* o,
+                                 const int32_t* node_ids_host, int32_t num_ids, void* stream, ffc_skel** out) {
   if (!t) return fail(FFC_ERR_INVALID_ARG, "tree is NULL");
   if (!o) return fail(FFC_ERR_INVALID_ARG, "options are NULL");
   if (!out) return fail(FFC_ERR_INVALID_ARG, "out is NULL");
@@ -258,6 +264,27 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
   if (separated && (learned || adaptive))
     return fail(FFC_ERR_INVALID_ARG, "separation works with the uniform sampler and a fixed sample count only");
   if (separated && t->depth > 30) return fail(FFC_ERR_INVALID_ARG, "separation supports trees of depth <= 30");
+  // Node subset: a host byte per node, set for the listed ones.
+  const bool subset = node_ids_host != nullptr;
+  std::vector<unsigned char> listed;
+  std::vector<int> level_listed(t->depth + 1, 0);
+  if (subset) {
+    if (num_ids < 1) return fail(FFC_ERR_INVALID_ARG, "num_ids must be >= 1 with a node list");
+    if (learned || adaptive)
+      return fail(FFC_ERR_INVALID_ARG, "a node subset works with the uniform sampler and a fixed sample count only");
+    listed.assign(t->num_nodes, 0);
+    for (int32_t i = 0; i < num_ids; ++i) {
+      const int32_t a = node_ids_host[i];
+      if (a < 1 || a >= t->num_nodes) return fail(FFC_ERR_INVALID_ARG, "node id out of range (the root has no far field)");
+      if (listed[a]) return fail(FFC_ERR_INVALID_ARG, "node id listed twice");
+      listed[a] = 1;
+      int lev = 0;
+      while (((2 << lev) - 1) <= a) ++lev;
+      level_listed[lev] += 1;
+    }
+  } else if (num_ids != 0) {
+    return fail(FFC_ERR_INVALID_ARG, "num_ids must be 0 without a node list");
+  }
   hipStream_t st = (hipStream_t)stream;
 
   const int64_t s_req = o->num_samples > 0 ? o->num_samples : 2 * (int64_t)o->max_rank;
@@ -310,6 +337,19 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
     FFC_HIP_TRY(hipMemsetAsync(sk->rank.ptr, 0, nn * sizeof(int32_t), st));
     FFC_HIP_TRY(hipMemsetAsync(sk->ncols.ptr, 0, nn * sizeof(int32_t), st));
     FFC_HIP_TRY(hipMemsetAsync(sk->nrows.ptr, 0, nn * sizeof(int32_t), st));
+  }
+  const unsigned char* smask = nullptr;   // device copy of `listed`
+  if (subset) {
+    if (sk->subset.count != (size_t)t->num_nodes) {
+      const ffc_status sa = sk->subset.alloc(t->num_nodes);
+      if (sa != FFC_OK) {
+        if (!reuse) delete sk;
+        return sa;
+      }
+    }
+    FFC_HIP_TRY(hipMemcpyAsync(sk->subset.ptr, listed.data(), listed.size(), hipMemcpyHostToDevice, st));
+    FFC_HIP_TRY(hipStreamSynchronize(st));   // `listed` is pageable host memory that ends with this call
+    smask = sk->subset.ptr;
   }
   sk->kernel = *k;
   sk->opts = *o;
@@ -365,21 +405,22 @@ ffc_status ffc_skeletonize_nodes(const ffc_tree* t, const ffc_kernel* k, const f
     }
     for (int lev = t->depth; lev >= 1; --lev) {
       const int first = (1 << lev) - 1, count = 1 << lev;
+      if (subset && !level_listed[lev]) continue;
       {
         StageTimer tm(FFC_STAGE_COLUMNS, st);
-        FFC_TRY(launch_level_columns(t, sk, first, count, lev == t->depth, st));
+        FFC_TRY(launch_level_columns(t, sk, first, count, lev == t->depth, st, smask));
       }
       if (learned) {
         StageTimer tm(FFC_STAGE_PROPOSAL, st);
         FFC_TRY(learned_rows_level(t, sk, o->sampler, o->proposal, first, count, s_cap, o->seed, st));
       } else if (separated) {
         StageTimer tm(FFC_STAGE_SAMPLE, st);
-        FFC_TRY(launch_sample_rows_sep(t, sk, first, count, s0, o->seed, st));
+        FFC_TRY(launch_sample_rows_sep(t, sk, first, count, s0, o->seed, st, smask));
       } else {
         StageTimer tm(FFC_STAGE_SAMPLE, st);
-        FFC_TRY(launch_sample_rows(t, sk, first, count, s0, o->seed, st));
+        FFC_TRY(launch_sample_rows(t, sk, first, count, s0, o->seed, st, smask));
       }
-      FFC_TRY(skeletonize_level(first, count));
+      FFC_TRY(skeletonize_level(first, count, smask));
       if (adaptive) {
         // Double the rows of the nodes whose held-out estimate is too large
         // until all pass or reach the cap; a round redoes only those nodes
@@ -686,14 +727,36 @@ ffc_status ffc_check_device(void* stream) {
   return FFC_OK;
 }
 
+void ffc_shutdown(void) {
+  (void)hipDeviceSynchronize();
+  ffc::profiler_release();
+  int cur = 0;
+  const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+  std::lock_guard<std::mutex> lock(g_flag_mu);
+  for (int dev = 0; dev < 64; ++dev) {
+    if (!g_flags[dev]) continue;
+    if (hipSetDevice(dev) == hipSuccess) (void)hipFree(g_flags[dev]);
+    g_flags[dev] = nullptr;
+  }
+  if (have_cur) (void)hipSetDevice(cur);
+}
+
 void ffc_free_tree(ffc_tree* t) {
   if (!t) return;
+  if (t->graphs > 0) {   // a step graph still reads its buffers: the last ffc_graph_free deletes it
+    t->orphaned = true;
+    return;
+  }
   (void)hipStreamSynchronize(t->last_stream);
   delete t;
 }
 
 void ffc_free_skel(ffc_skel* sk) {
   if (!sk) return;
+  if (sk->graphs > 0) {
+    sk->orphaned = true;
+    return;
+  }
   (void)hipStreamSynchronize(sk->last_stream);
   delete sk;
 }
@@ -706,6 +769,8 @@ void ffc_free_skel(ffc_skel* sk) {
 struct ffc_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  ffc_tree* tree = nullptr;   // handles whose buffers the graph has baked in
+  ffc_skel* skel = nullptr;
 };
 
 namespace {
@@ -723,6 +788,10 @@ ffc_status create_step_graph(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* 
   if (!stream) {
     set_error("graphs need a non-null stream");
     return FFC_ERR_INVALID_ARG;
+  }
+  if (t->orphaned || sk->orphaned) {
+    set_error("the tree or skeleton set has been freed");
+    return FFC_ERR_STATE;
   }
   if (o->sampler != FFC_SAMPLE_UNIFORM && o->fallback_tol > 0.0) {
     set_error("the pool samplers' fallback check synchronizes and cannot be captured");
@@ -748,7 +817,7 @@ ffc_status create_step_graph(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* 
   hipStream_t st = (hipStream_t)stream;
   FFC_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
   ffc_skel* skp = sk;
-  ffc_status s1 = ffc_skeletonize_nodes(t, k, o, stream, &skp);
+  ffc_status s1 = ffc_skeletonize_nodes(t, k, o, nullptr, 0, stream, &skp);
   ffc_status s2 = s1;
   if (s1 == FFC_OK)
     s2 = fmm ? ffc_evaluate_fmm(t, sk, k, q_dev, u_dev, u_far_dev, precision, stream)
@@ -774,6 +843,10 @@ ffc_status create_step_graph(const ffc_tree* t, ffc_skel* sk, const ffc_kernel* 
   ffc_graph* g = new ffc_graph();
   g->graph = graph;
   g->exec = exec;
+  g->tree = const_cast<ffc_tree*>(t);
+  g->skel = sk;
+  g->tree->graphs += 1;
+  g->skel->graphs += 1;
   *out = g;
   return FFC_OK;
 }
@@ -808,6 +881,8 @@ void ffc_graph_free(ffc_graph* g) {
   (void)hipDeviceSynchronize();
   if (g->exec) (void)hipGraphExecDestroy(g->exec);
   if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->skel && --g->skel->graphs == 0 && g->skel->orphaned) delete g->skel;
+  if (g->tree && --g->tree->graphs == 0 && g->tree->orphaned) delete g->tree;
   delete g;
 }
 

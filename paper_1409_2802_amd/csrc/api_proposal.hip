@@ -14,6 +14,8 @@
 //   7 * 2^29 | 2^28, e     epoch e: the stride of its visiting order
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <numeric>
 #include <vector>
 
@@ -201,7 +203,6 @@ ffc_status learned_alloc(const ffc_tree* t, ffc_skel* sk, int pool_factor) {
   if (L.p_cap == p_cap && L.ids.ptr) return FFC_OK;
   if (p_cap > 8192)
     return fail(FFC_ERR_INVALID_ARG, "the learned sampler's candidate pool (pool_factor * samples) is limited to 8192");
-  L.p_cap = p_cap;
   const size_t nn = t->num_nodes, widest = (size_t)1 << t->depth, d = t->d;
   FFC_TRY(L.ids.alloc(nn));
   std::vector<int32_t> iota(nn);
@@ -221,6 +222,7 @@ ffc_status learned_alloc(const ffc_tree* t, ffc_skel* sk, int pool_factor) {
   FFC_TRY(L.Kh.alloc(widest * kHeld * sk->n_cap));
   FFC_TRY(L.mask.alloc(nn));
   FFC_TRY(L.counter.alloc(1));
+  L.p_cap = p_cap;   // only once every buffer has its new size
   return FFC_OK;
 }
 
@@ -390,6 +392,101 @@ void ffc_proposal_free(ffc_proposal* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
   delete p;
+}
+
+// Proposal checkpoint file, version 1 (little-endian): 8-byte magic
+// "FFCPROP1", uint32 version, uint32 parameter count, uint32 feature count,
+// int32 Adam step, then float32 theta, mu, sd, m1, m2, then the 64-bit FNV-1a
+// hash of every preceding byte.
+}  // extern "C"
+
+namespace {
+constexpr char kPropMagic[8] = {'F', 'F', 'C', 'P', 'R', 'O', 'P', '1'};
+constexpr uint32_t kPropVersion = 1;
+
+uint64_t fnv1a(const unsigned char* b, size_t n) {
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+template <typename T>
+void put(std::vector<unsigned char>& buf, const T* v, size_t n) {
+  const size_t at = buf.size();
+  buf.resize(at + n * sizeof(T));
+  std::memcpy(buf.data() + at, v, n * sizeof(T));
+}
+}  // namespace
+
+extern "C" {
+
+ffc_status ffc_proposal_save(const ffc_proposal* p, const char* path) {
+  if (!p || !path) return fail(FFC_ERR_INVALID_ARG, "proposal or path is NULL");
+  std::vector<float> th(kNParam), mu(kNF), sd(kNF), m1(kNParam), m2(kNParam);
+  FFC_TRY(ffc_proposal_get(p, th.data(), mu.data(), sd.data()));
+  int32_t step = 0;
+  FFC_TRY(ffc_proposal_get_adam(p, m1.data(), m2.data(), &step));
+  std::vector<unsigned char> buf;
+  put(buf, kPropMagic, 8);
+  const uint32_t hdr[3] = {kPropVersion, (uint32_t)kNParam, (uint32_t)kNF};
+  put(buf, hdr, 3);
+  put(buf, &step, 1);
+  put(buf, th.data(), kNParam);
+  put(buf, mu.data(), kNF);
+  put(buf, sd.data(), kNF);
+  put(buf, m1.data(), kNParam);
+  put(buf, m2.data(), kNParam);
+  const uint64_t h = fnv1a(buf.data(), buf.size());
+  put(buf, &h, 1);
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return fail(FFC_ERR_INVALID_ARG, std::string("cannot open ") + path + " for writing");
+  const bool ok = std::fwrite(buf.data(), 1, buf.size(), f) == buf.size();
+  if (std::fclose(f) != 0 || !ok) return fail(FFC_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  return FFC_OK;
+}
+
+ffc_status ffc_proposal_load(const char* path, ffc_proposal** out) {
+  if (!path || !out) return fail(FFC_ERR_INVALID_ARG, "path or out is NULL");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(FFC_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  const size_t want = 8 + 4 * sizeof(uint32_t) + (3 * (size_t)kNParam + 2 * kNF) * sizeof(float) + sizeof(uint64_t);
+  std::vector<unsigned char> buf(want + 1);
+  const size_t got = std::fread(buf.data(), 1, buf.size(), f);
+  std::fclose(f);
+  if (got != want) return fail(FFC_ERR_INVALID_ARG, std::string(path) + ": not a proposal checkpoint (wrong size)");
+  if (std::memcmp(buf.data(), kPropMagic, 8) != 0)
+    return fail(FFC_ERR_INVALID_ARG, std::string(path) + ": not a proposal checkpoint (bad magic)");
+  uint32_t hdr[3];
+  std::memcpy(hdr, buf.data() + 8, sizeof(hdr));
+  if (hdr[0] != kPropVersion)
+    return fail(FFC_ERR_INVALID_ARG, std::string(path) + ": unsupported checkpoint version " + std::to_string(hdr[0]));
+  if (hdr[1] != (uint32_t)kNParam || hdr[2] != (uint32_t)kNF)
+    return fail(FFC_ERR_INVALID_ARG, std::string(path) + ": network shape does not match this library");
+  uint64_t h = 0;
+  std::memcpy(&h, buf.data() + want - sizeof(uint64_t), sizeof(h));
+  if (h != fnv1a(buf.data(), want - sizeof(uint64_t)))
+    return fail(FFC_ERR_INVALID_ARG, std::string(path) + ": checksum mismatch (corrupt checkpoint)");
+  const unsigned char* c = buf.data() + 8 + sizeof(hdr);
+  int32_t step = 0;
+  std::memcpy(&step, c, sizeof(step));
+  c += sizeof(step);
+  std::vector<float> th(kNParam), mu(kNF), sd(kNF), m1(kNParam), m2(kNParam);
+  for (std::vector<float>* v : {&th, &mu, &sd, &m1, &m2}) {
+    std::memcpy(v->data(), c, v->size() * sizeof(float));
+    c += v->size() * sizeof(float);
+  }
+  ffc_proposal* p = nullptr;
+  FFC_TRY(ffc_proposal_create(th.data(), mu.data(), sd.data(), &p));
+  const ffc_status s = ffc_proposal_set_adam(p, m1.data(), m2.data(), step);
+  if (s != FFC_OK) {
+    ffc_proposal_free(p);
+    return s;
+  }
+  *out = p;
+  return FFC_OK;
 }
 
 ffc_status ffc_proposal_features(const ffc_tree* t, const int32_t* cols_dev, int32_t col_stride,

@@ -69,6 +69,8 @@ ffc_status validate_kernel(const ffc_kernel* k, int d);
 // Stage profiler: a StageTimer brackets the launches of one stage with events
 // on the stage's stream while profiling is enabled.
 bool profiling();
+// Destroys the profiler's pooled events (ffc_shutdown).
+void profiler_release();
 class StageTimer {
  public:
   StageTimer(int stage, hipStream_t st);
@@ -93,10 +95,16 @@ unsigned int* device_flag();
 // device allocation of the library fails with FFC_ERR_OOM.
 bool alloc_forced_to_fail();
 
+// Buffers of a handle that a step graph has baked in must not move while the
+// graph exists: `pin` points at the handle's live-graph count, and a
+// (re)allocation while it is non-zero fails with FFC_ERR_STATE.
+ffc_status refuse_pinned_alloc();
+
 template <typename T>
 struct DevBuf {
   T* ptr = nullptr;
   size_t count = 0;
+  const int32_t* pin = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
@@ -107,6 +115,7 @@ struct DevBuf {
     count = 0;
   }
   ffc_status alloc(size_t n) {
+    if (pin && *pin > 0) return refuse_pinned_alloc();
     release();
     if (n == 0) return FFC_OK;
     if (alloc_forced_to_fail()) {
@@ -123,6 +132,11 @@ struct DevBuf {
     return FFC_OK;
   }
 };
+
+template <typename... B>
+void pin_buffers(const int32_t* count, B&... bufs) {
+  ((bufs.pin = count), ...);
+}
 
 // Column geometry of node blocks for the learned proposal (proposal.hip).
 struct GeomArgs {
@@ -170,6 +184,14 @@ struct ffc_tree {
   int32_t bf_dp = 0;
   int32_t bf_frame = -1;
   hipStream_t last_stream = nullptr;
+  // Step graphs holding this tree's buffers; ffc_free_tree while some exist
+  // only marks the tree, and the last ffc_graph_free deletes it.
+  int32_t graphs = 0;
+  bool orphaned = false;
+  ffc_tree() {
+    ffc::pin_buffers(&graphs, X, Xt, perm, begin, end, centroid, radius, q_tree, tile_leaf, tile_start, bf_hi, bf_lo,
+                     bf_nrm, bf_x, bf_cc);
+  }
 };
 
 struct ffc_proposal {
@@ -212,6 +234,7 @@ struct ffc_skel {
   ffc::DevBuf<double> work;                 // sampled blocks of the widest level
   ffc::DevBuf<unsigned char> qr_scratch;    // group slots / counters of the QR kernel
   ffc::LearnedScratch learned;              // learned sampler (allocated on first use)
+  ffc::DevBuf<unsigned char> subset;        // node subset of the last call (num_nodes bytes)
   int32_t fallbacks = 0;
   int32_t resampled = 0;                    // adaptive sample count: node redos
   // Separation (opts.separation > 0): bit p of sep_bits[a * sep_words + p / 64]
@@ -228,6 +251,17 @@ struct ffc_skel {
   ffc::DevBuf<double> fmm_v, fmm_vpart, fmm_ufar;   // vpart: partial sums of the list quarters
   int64_t fmm_far_pairs = 0, fmm_near_pairs = 0;
   hipStream_t last_stream = nullptr;
+  // Step graphs holding this set's buffers (see ffc_tree::graphs).
+  int32_t graphs = 0;
+  bool orphaned = false;
+  ffc_skel() {
+    ffc::pin_buffers(&graphs, rank, ncols, nrows, cols, rows, piv, skel, P, qt, work, qr_scratch, subset, sep_bits,
+                     sep_pre,
+                     fmm_far_off, fmm_far_src, fmm_near_off, fmm_near_src, fmm_v, fmm_vpart, fmm_ufar);
+    ffc::LearnedScratch& L = learned;
+    ffc::pin_buffers(&graphs, L.ids, L.pool, L.npool, L.cen, L.rho, L.U, L.sub, L.nsub, L.feat, L.score, L.hrows,
+                     L.nheld, L.Kh, L.mask, L.counter);
+  }
 };
 
 namespace ffc {
@@ -243,7 +277,7 @@ ffc_status launch_gather_tree_points(ffc_tree* t, hipStream_t st);
 
 // Uniform row sampling (sample.hip): rows[node] for nodes [first, first+count).
 ffc_status launch_sample_rows(const ffc_tree* t, ffc_skel* sk, int first, int count, int s,
-                              uint64_t seed, hipStream_t st);
+                              uint64_t seed, hipStream_t st, const unsigned char* mask = nullptr);
 // General form: draws into rows + node * cap (counts in nrows[node]) with the
 // Floyd stream node | stream_or; nodes with mask[node] == 0 are skipped when
 // mask is non-null.
@@ -265,11 +299,12 @@ struct SepView {
   int words = 0;
 };
 ffc_status launch_sample_rows_sep(const ffc_tree* t, ffc_skel* sk, int first, int count, int s, uint64_t seed,
-                                  hipStream_t st);
+                                  hipStream_t st, const unsigned char* mask = nullptr);
 
-// Column lists of a level (sample.hip).
+// Column lists of a level (sample.hip); with a mask (indexed by node) only
+// the nodes whose entry is set.
 ffc_status launch_level_columns(const ffc_tree* t, ffc_skel* sk, int first, int count, bool leaves,
-                                hipStream_t st);
+                                hipStream_t st, const unsigned char* mask = nullptr);
 
 // Sampled kernel blocks for nodes [first, first+count) into A (node-major,
 // each s_cap x n_cap column-major with leading dimension s_cap); with a mask

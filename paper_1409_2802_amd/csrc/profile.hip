@@ -41,6 +41,19 @@ int64_t g_launches[FFC_NUM_STAGES] = {};
 
 bool profiling() { return g_on; }
 
+void profiler_release() {
+  std::lock_guard<std::mutex> lock(g_mu);
+  g_on = false;
+  for (const Pending& p : g_pending) {
+    (void)hipEventSynchronize(p.stop);
+    (void)hipEventDestroy(p.start);
+    (void)hipEventDestroy(p.stop);
+  }
+  g_pending.clear();
+  for (hipEvent_t e : g_free) (void)hipEventDestroy(e);
+  g_free.clear();
+}
+
 const char* const kStageRanges[FFC_NUM_STAGES] = {
     "ffc:tree",  "ffc:sample", "ffc:columns",  "ffc:kblock",  "ffc:cpqr",   "ffc:skel",   "ffc:upward",
     "ffc:evaluate", "ffc:direct", "ffc:solve", "ffc:proposal", "ffc:heldout", "ffc:labels", "ffc:train"};

@@ -227,8 +227,9 @@ k_sample_rows_bitmap(const int32_t* __restrict__ nb, const int32_t* __restrict__
 __global__ void k_level_columns(const int32_t* __restrict__ nb, const int32_t* __restrict__ ne, int first,
                                 int leaves, int n_cap, int r_cap, const int32_t* __restrict__ rank,
                                 const int32_t* __restrict__ skel, int32_t* __restrict__ cols,
-                                int32_t* __restrict__ ncols) {
+                                int32_t* __restrict__ ncols, const unsigned char* __restrict__ mask) {
   const int node = first + blockIdx.x;
+  if (mask && !mask[node]) return;
   int32_t* out = cols + (int64_t)node * n_cap;
   if (leaves) {
     const int b = nb[node], n = ne[node] - b;
@@ -283,14 +284,14 @@ ffc_status launch_draw(const int32_t* nb, const int32_t* ne, int64_t N, bool ins
 }
 
 ffc_status launch_sample_rows_sep(const ffc_tree* t, ffc_skel* sk, int first, int count, int s, uint64_t seed,
-                                  hipStream_t st) {
+                                  hipStream_t st, const unsigned char* mask) {
   if (!sk->sep_bits.ptr) {
     set_error("separation bitmaps are missing");
     return FFC_ERR_STATE;
   }
   const SepView sv{sk->sep_bits.ptr, sk->sep_pre.ptr, sk->sep_words};
   return draw(t->begin.ptr, t->end.ptr, t->N, false, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, first, count, s, seed,
-              0u, nullptr, sv, st);
+              0u, mask, sv, st);
 }
 
 ffc_status launch_sample_rows_into(const ffc_tree* t, int32_t* rows, int32_t* nrows, int cap, int first, int count,
@@ -301,15 +302,15 @@ ffc_status launch_sample_rows_into(const ffc_tree* t, int32_t* rows, int32_t* nr
 }
 
 ffc_status launch_sample_rows(const ffc_tree* t, ffc_skel* sk, int first, int count, int s, uint64_t seed,
-                              hipStream_t st) {
-  return launch_sample_rows_into(t, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, first, count, s, seed, 0u, nullptr, st);
+                              hipStream_t st, const unsigned char* mask) {
+  return launch_sample_rows_into(t, sk->rows.ptr, sk->nrows.ptr, sk->s_cap, first, count, s, seed, 0u, mask, st);
 }
 
 ffc_status launch_level_columns(const ffc_tree* t, ffc_skel* sk, int first, int count, bool leaves,
-                                hipStream_t st) {
+                                hipStream_t st, const unsigned char* mask) {
   hipLaunchKernelGGL(k_level_columns, dim3(count), dim3(256), 0, st, t->begin.ptr, t->end.ptr, first,
                      leaves ? 1 : 0, sk->n_cap, sk->r_cap, sk->rank.ptr, sk->skel.ptr, sk->cols.ptr,
-                     sk->ncols.ptr);
+                     sk->ncols.ptr, mask);
   FFC_LAUNCH_CHECK("k_level_columns");
   return FFC_OK;
 }

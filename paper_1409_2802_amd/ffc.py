@@ -7,8 +7,10 @@ missing or the GPU is absent, the calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -32,7 +34,8 @@ EXPORTS = [
     "ffc_proposal_fit_standardization", "ffc_proposal_score", "ffc_proposal_gradient", "ffc_proposal_adam",
     "ffc_leverage_labels", "ffc_proposal_train", "ffc_proposal_training_set",
     "ffc_step_graph_create", "ffc_step_graph_create_fmm", "ffc_graph_launch", "ffc_graph_free", "ffc_autotune_report",
-    "ffc_skel_load", "ffc_proposal_get_adam", "ffc_proposal_set_adam",
+    "ffc_skel_load", "ffc_proposal_get_adam", "ffc_proposal_set_adam", "ffc_shutdown",
+    "ffc_proposal_save", "ffc_proposal_load",
 ]
 
 NPARAM = 5313
@@ -89,7 +92,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ffc_build_partition": [P, I64, I32, I64, P, PP],
         "ffc_tree_info": [P, P, P, P, P],
         "ffc_tree_arrays": [P, P, P, P, P, P],
-        "ffc_skeletonize_nodes": [P, ctypes.POINTER(KernelC), ctypes.POINTER(SkelOptsC), P, PP],
+        "ffc_skeletonize_nodes": [P, ctypes.POINTER(KernelC), ctypes.POINTER(SkelOptsC), P, I32, P, PP],
         "ffc_evaluate_sum": [P, P, ctypes.POINTER(KernelC), P, P, P, I32, P],
         "ffc_evaluate_fmm": [P, P, ctypes.POINTER(KernelC), P, P, P, I32, P],
         "ffc_direct_sum": [P, I64, P, I64, I32, ctypes.POINTER(KernelC), P, P, I32, P],
@@ -118,6 +121,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ffc_step_graph_create_fmm": [P, P, ctypes.POINTER(KernelC), ctypes.POINTER(SkelOptsC), P, P, P, I32, P, PP],
         "ffc_graph_launch": [P, P],
         "ffc_autotune_report": [P, I32, P],
+        "ffc_proposal_save": [P, ctypes.c_char_p],
+        "ffc_proposal_load": [ctypes.c_char_p, PP],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -133,8 +138,34 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ffc_proposal_free.restype = None
     lib.ffc_last_error.argtypes = []
     lib.ffc_last_error.restype = ctypes.c_char_p
+    lib.ffc_shutdown.argtypes = []
+    lib.ffc_shutdown.restype = None
     _lib = lib
     return lib
+
+
+# Live handles, released in a fixed order (graphs, skeleton sets, proposals,
+# trees) at interpreter exit, before the library's process-wide resources are
+# freed by ffc_shutdown: nothing of the library's is left for finalizers that
+# run during teardown.
+_live: "weakref.WeakSet" = weakref.WeakSet()
+_RELEASE_ORDER = ("StepGraph", "Skeletons", "Proposal", "Tree")
+
+
+def _register(obj) -> None:
+    _live.add(obj)
+
+
+@atexit.register
+def _shutdown() -> None:
+    if _lib is None:
+        return
+    objs = list(_live)
+    for kind in _RELEASE_ORDER:
+        for o in objs:
+            if type(o).__name__ == kind:
+                o._release()
+    _lib.ffc_shutdown()
 
 
 def _check(code: int) -> None:
@@ -187,6 +218,7 @@ class Tree:
         _check(load_library().ffc_tree_info(handle, ctypes.byref(depth), ctypes.byref(nn), ctypes.byref(N),
                                             ctypes.byref(d)))
         self.depth, self.num_nodes, self.N, self.d = depth.value, nn.value, N.value, d.value
+        _register(self)
 
     @property
     def handle(self):
@@ -202,10 +234,13 @@ class Tree:
                                               cen.ctypes.data, rad.ctypes.data))
         return {"perm": perm, "begin": b, "end": e, "centroid": cen, "radius": rad}
 
-    def __del__(self):
+    def _release(self) -> None:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.ffc_free_tree(self._h)
-            self._h = None
+        self._h = None
+
+    def __del__(self):
+        self._release()
 
 
 def build_tree(X, leaf_size: int, stream=None) -> Tree:
@@ -230,6 +265,7 @@ class Skeletons:
     def __init__(self, handle: ctypes.c_void_p, tree: Tree):
         self._h = handle
         self.tree = tree
+        _register(self)
 
     @property
     def handle(self):
@@ -275,10 +311,13 @@ class Skeletons:
         """Checkpoint (numpy .npz of plain arrays) that load_skeletons reads back."""
         np.savez(path, separation=np.float64(separation), **self.export())
 
-    def __del__(self):
+    def _release(self) -> None:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.ffc_free_skel(self._h)
-            self._h = None
+        self._h = None
+
+    def __del__(self):
+        self._release()
 
 
 def load_skeletons(tree: Tree, source, separation: float | None = None, stream=None) -> Skeletons:
@@ -306,12 +345,13 @@ def skeletonize(tree: Tree, kernel: Kernel, tol: float, max_rank: int, num_sampl
                 precision: int = FP64, seed: int = 0, reuse: Skeletons | None = None,
                 proposal: "Proposal | None" = None, fallback_tol: float = 0.0, pool_factor: int = 0,
                 adaptive_tol: float = 0.0, max_samples: int = 0, sampler: int | None = None,
-                separation: float = 0.0, stream=None) -> Skeletons:
+                separation: float = 0.0, node_ids=None, stream=None) -> Skeletons:
     """Skeletonize every non-root node; with `proposal` the rows come from the learned sampler (or `sampler`:
     SAMPLE_DISTANCE / SAMPLE_NEAREST for the paper's heuristics on the same candidate pool), with
     `adaptive_tol` > 0 a node's row count doubles until its held-out error estimate is at most adaptive_tol
     (or `max_samples` is reached); with `separation` xi > 0 the rows come from each node's separated points
-    and evaluate_sum runs the treecode."""
+    and evaluate_sum runs the treecode; `node_ids` restricts the call to those nodes (the others keep what
+    `reuse` holds)."""
     if sampler is None:
         sampler = SAMPLE_LEARNED if proposal is not None else SAMPLE_UNIFORM
     opts = SkelOptsC(tol=tol, max_rank=max_rank, num_samples=num_samples, precision=precision,
@@ -321,8 +361,10 @@ def skeletonize(tree: Tree, kernel: Kernel, tol: float, max_rank: int, num_sampl
                      separation=separation)
     h = ctypes.c_void_p(reuse.handle.value if reuse is not None else None)
     k = kernel.c_struct()
-    _check(load_library().ffc_skeletonize_nodes(tree.handle, ctypes.byref(k), ctypes.byref(opts), _stream(stream),
-                                                ctypes.byref(h)))
+    ids = None if node_ids is None else np.ascontiguousarray(node_ids, dtype=np.int32)
+    _check(load_library().ffc_skeletonize_nodes(tree.handle, ctypes.byref(k), ctypes.byref(opts),
+                                                None if ids is None else ids.ctypes.data,
+                                                0 if ids is None else len(ids), _stream(stream), ctypes.byref(h)))
     if reuse is not None:
         return reuse
     return Skeletons(h, tree)
@@ -349,14 +391,18 @@ class StepGraph:
         _check(create(tree.handle, sk.handle, ctypes.byref(k), ctypes.byref(opts), _ptr(q), _ptr(u), _ptr(u_far),
                       precision, _stream(stream), ctypes.byref(h)))
         self._h = h
+        _register(self)
 
     def launch(self, stream=None) -> None:
         _check(load_library().ffc_graph_launch(self._h, _stream(stream)))
 
-    def __del__(self):
+    def _release(self) -> None:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.ffc_graph_free(self._h)
-            self._h = None
+        self._h = None
+
+    def __del__(self):
+        self._release()
 
 
 def evaluate_sum(tree: Tree, sk: Skeletons, kernel: Kernel, q, precision: int = FP64, stream=None):
@@ -463,7 +509,11 @@ def _dev_f32(x, name: str) -> torch.Tensor:
 class Proposal:
     """Handle to the 16-64-64-1 proposal network (parameters, standardization, Adam state)."""
 
-    def __init__(self, theta, mu=None, sd=None):
+    def __init__(self, theta, mu=None, sd=None, _handle=None):
+        if _handle is not None:   # from ffc_proposal_load
+            self._h = _handle
+            _register(self)
+            return
         th = np.ascontiguousarray(theta, dtype=np.float32)
         if th.shape != (NPARAM,):
             raise ValueError(f"theta must have {NPARAM} entries")
@@ -473,6 +523,7 @@ class Proposal:
         _check(load_library().ffc_proposal_create(th.ctypes.data, None if m is None else m.ctypes.data,
                                                   None if v is None else v.ctypes.data, ctypes.byref(h)))
         self._h = h
+        _register(self)
 
     @property
     def handle(self):
@@ -500,17 +551,25 @@ class Proposal:
         _check(load_library().ffc_proposal_set_adam(self._h, a.ctypes.data, b.ctypes.data, int(step)))
 
     def save(self, path: str) -> None:
-        """Checkpoint (numpy .npz): parameters, standardization and Adam state."""
-        th, mu, sd = self.get()
-        m1, m2, step = self.adam_state()
-        np.savez(path, theta=th, mu=mu, sd=sd, m1=m1, m2=m2, step=np.int32(step))
+        """Checkpoint of parameters, standardization and Adam state: the library's versioned binary
+        (ffc_proposal_save), or a numpy .npz mirror of the same arrays when the name ends in .npz."""
+        if str(path).endswith(".npz"):
+            th, mu, sd = self.get()
+            m1, m2, step = self.adam_state()
+            np.savez(path, theta=th, mu=mu, sd=sd, m1=m1, m2=m2, step=np.int32(step))
+        else:
+            _check(load_library().ffc_proposal_save(self._h, os.fsencode(path)))
 
     @classmethod
     def load(cls, path: str) -> "Proposal":
-        with np.load(path, allow_pickle=False) as z:
-            p = cls(z["theta"], z["mu"], z["sd"])
-            p.set_adam_state(z["m1"], z["m2"], int(z["step"]))
-        return p
+        if str(path).endswith(".npz"):
+            with np.load(path, allow_pickle=False) as z:
+                p = cls(z["theta"], z["mu"], z["sd"])
+                p.set_adam_state(z["m1"], z["m2"], int(z["step"]))
+            return p
+        h = ctypes.c_void_p()
+        _check(load_library().ffc_proposal_load(os.fsencode(path), ctypes.byref(h)))
+        return cls(None, _handle=h)
 
     def fit_standardization(self, feat: torch.Tensor, stream=None) -> None:
         f = _dev_f32(feat, "feat")
@@ -545,10 +604,13 @@ class Proposal:
                                                  loss.ctypes.data, _stream(stream)))
         return loss[:epochs]
 
-    def __del__(self):
+    def _release(self) -> None:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.ffc_proposal_free(self._h)
-            self._h = None
+        self._h = None
+
+    def __del__(self):
+        self._release()
 
 
 def proposal_features(tree: Tree, cols, ncols, ids, tgt, ntgt, seed: int, stream=None) -> torch.Tensor:

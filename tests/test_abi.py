@@ -70,7 +70,7 @@ def test_proposal_graph_and_label_validation_without_gpu():
     assert lib.ffc_step_graph_create(None, None, ctypes.byref(k), ctypes.byref(o), None, None, None, 0, None,
                                      ctypes.byref(out)) == ffc.FFC_ERR_INVALID_ARG
     skel = ctypes.c_void_p()
-    assert lib.ffc_skeletonize_nodes(None, ctypes.byref(k), ctypes.byref(o), None, ctypes.byref(skel)) == \
+    assert lib.ffc_skeletonize_nodes(None, ctypes.byref(k), ctypes.byref(o), None, 0, None, ctypes.byref(skel)) == \
         ffc.FFC_ERR_INVALID_ARG
     assert b"tree" in lib.ffc_last_error()
     assert lib.ffc_autotune_report(None, 0, None) == ffc.FFC_ERR_INVALID_ARG

@@ -119,3 +119,34 @@ def test_forced_allocation_failure_is_reported_and_recoverable(ffc, monkeypatch)
     sk2 = ffc.skeletonize(t, k, tol=1e-6, max_rank=16, num_samples=32)
     u2, _ = ffc.evaluate_sum(t, sk2, k, q)
     assert torch.equal(u0, u2)
+
+
+@pytest.mark.parametrize("suffix", [".bin", ".npz"])
+def test_proposal_binary_checkpoint(ffc, tmp_path, suffix):
+    """ffc_proposal_save / ffc_proposal_load (versioned binary through the C ABI) and the .npz mirror give
+    back the same bits; corrupt, truncated or foreign files are refused."""
+    X = W.low_intrinsic(4096, 16, di=4, noise=1e-2, seed=1)
+    t = ffc.build_tree(X, 256)
+    k = gkernel(GAUSSIAN, h=1.0)
+    a = ffc.Proposal(W.mlp_init(3))
+    a.train(t, k, 8, 256, 1024, epochs=1, batch=512, lr=1e-3, eps=1e-4, seed=5)
+    path = str(tmp_path / ("prop" + suffix))
+    a.save(path)
+    b = ffc.Proposal.load(path)
+    for x, y in zip(a.get() + a.adam_state()[:2], b.get() + b.adam_state()[:2]):
+        np.testing.assert_array_equal(x, y)
+    assert a.adam_state()[2] == b.adam_state()[2] > 0
+    if suffix != ".bin":
+        return
+    raw = bytearray(open(path, "rb").read())
+    assert raw[:8] == b"FFCPROP1" and int.from_bytes(raw[8:12], "little") == 1
+    for name, data in (("flipped", raw[:100] + bytes([raw[100] ^ 1]) + raw[101:]), ("truncated", raw[:-9]),
+                       ("magic", b"XXXXXXXX" + raw[8:]),
+                       ("version", raw[:8] + (2).to_bytes(4, "little") + raw[12:])):
+        bad = tmp_path / f"bad_{name}.bin"
+        bad.write_bytes(bytes(data))
+        with pytest.raises(ffc.FfcError) as e:
+            ffc.Proposal.load(str(bad))
+        assert e.value.code == ffc.FFC_ERR_INVALID_ARG, name
+    with pytest.raises(ffc.FfcError):
+        ffc.Proposal.load(str(tmp_path / "missing.bin"))
