@@ -425,17 +425,41 @@ ffc_status ffc_proposal_adam(ffc_proposal* p, const float* grad_dev, float lr, v
 ffc_status ffc_leverage_labels(const double* B_dev, int64_t m, int32_t n, int32_t count, double eps,
                                double* lev_dev, float* target_dev, void* stream);
 
+/* Statistical leverage at the block's rank (Section 3, definition of
+ * statistical leverage), from the method's own factorization: the column-
+ * pivoted QR of each row-major m x n block B (largest trailing column norm
+ * first, ties to the smaller column; stopped at the first pivot whose norm
+ * is below eps times the first one's, else at min(m, n)) picks r columns J,
+ * and l_i is the squared norm of row i of an orthonormal basis of
+ * span(B(:, J)); sum(l) = r, and for a block of exact rank r this is the
+ * leverage of its top r singular vectors. Computed through B^T B, whose
+ * diagonal-pivoted Cholesky factorization has the same pivots and R.
+ * B_dev (count blocks back to back) is not modified; lev_dev gets count x m
+ * scores, target_dev (may be NULL) ln(max(l_i, 1e-12) m / sum(l));
+ * rank_host (may be NULL) the r of each block, piv_host (may be NULL,
+ * count x n) the pivot order (its first r entries are J). A zero block gives
+ * zeros and rank 0. Errors: n > 1024, eps outside (0, 1), bad sizes or NULL
+ * arrays -> FFC_ERR_INVALID_ARG. Synchronizes (scratch). */
+ffc_status ffc_pivoted_leverage_labels(const double* B_dev, int64_t m, int32_t n, int32_t count, double eps,
+                                       double* lev_dev, float* target_dev, int32_t* rank_host, int32_t* piv_host,
+                                       void* stream);
+
 /* Proposal training. Block g of the training set takes a random leaf of the
  * tree, n = min(block_cols, smallest leaf) of its points as columns and m =
  * min(block_rows, N - largest leaf) points outside it as targets (counter-based
  * draws from `seed`); its samples are the targets' features and the targets
- * of the ridge leverage of K(targets, columns) in float64. Training fits the
+ * of the leverage of K(targets, columns) in float64 (o->label: the pivoted
+ * leverage at the block's eps-rank, or the ridge form). Training fits the
  * standardization on all samples, then runs `epochs` passes of mini-batch Adam
  * (`batch` samples per step, learning rate lr) on the mean squared error, the
  * epoch's order a seeded stride permutation. loss_host (epochs floats, may be
  * NULL) receives each epoch's mean loss. Synchronizes.
  * Errors: num_blocks < 1, block sizes < 1, batch < 1, epochs < 0 ->
  * FFC_ERR_INVALID_ARG. */
+typedef enum {
+  FFC_LABEL_PIVOTED = 0,   /* ffc_pivoted_leverage_labels: leverage at the block's eps-rank (default) */
+  FFC_LABEL_RIDGE = 1      /* ffc_leverage_labels: ridge leverage with lambda = eps^2 ||B||_F^2 */
+} ffc_label_kind;
 typedef struct {
   int32_t num_blocks;
   int32_t block_cols;
@@ -445,6 +469,7 @@ typedef struct {
   float lr;
   double eps;
   uint64_t seed;
+  int32_t label;   /* ffc_label_kind of the targets */
 } ffc_train_opts;
 ffc_status ffc_proposal_train(ffc_proposal* p, const ffc_tree* t, const ffc_kernel* k, const ffc_train_opts* o,
                               float* loss_host, void* stream);

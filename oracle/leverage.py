@@ -6,13 +6,20 @@ of row j of U_r in K = U Sigma V^T. The coherence is the largest score, and
 r/m <= coherence <= 1 (Section 3, after eq. e:gamma_def).
 
 The rank is the epsilon-rank of the block (the paper does not say which r the
-labels use). "Parity unpinned" does not apply: the scores are pinned by their
+labels use).
+
+pivoted_leverage is the same quantity from the method's own factorization:
+the column-pivoted QR of the block (the rank rule and pivoting of
+cpqr_id.cpqr, tol = eps, no rank cap) picks r columns J, and the scores are
+the squared row norms of an orthonormal basis Q_r of span(B(:, J)). When the
+block has exact rank r the two subspaces coincide and so do the scores. "Parity unpinned" does not apply: the scores are pinned by their
 invariants (sum = r, range [0, 1]) and by the paper's rank-two problem case.
 """
 from __future__ import annotations
 
 import numpy as np
 
+from .cpqr_id import cpqr
 from .theory import epsilon_rank
 
 
@@ -28,3 +35,16 @@ def row_leverage(K: np.ndarray, r: int) -> np.ndarray:
 def row_leverage_eps(K: np.ndarray, eps: float) -> tuple[np.ndarray, int]:
     r = epsilon_rank(K, eps)
     return row_leverage(K, r), r
+
+
+def pivoted_leverage(B: np.ndarray, eps: float):
+    """(scores, r, J, gap): squared row norms of Q_r, Q_r an orthonormal basis of the first r pivot
+    columns of the column-pivoted QR of B stopped at rho_k < eps rho_0; gap as in cpqr."""
+    B = np.asarray(B, dtype=np.float64)
+    m, n = B.shape
+    r, piv, _, _, gap = cpqr(B, eps, n)
+    J = piv[:r].copy()
+    if r == 0:
+        return np.zeros(m), 0, J, gap
+    Q, _ = np.linalg.qr(B[:, J])
+    return (Q * Q).sum(axis=1), r, J, gap

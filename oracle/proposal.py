@@ -31,10 +31,13 @@ Parameters, flat: W1 (16 x 64, row-major), b1 (64), W2 (64 x 64), b2 (64),
 w3 (64), b3 (1): 5313 values. Loss: mean squared error. Adam (Kingma & Ba
 2015) with bias correction.
 
-Labels: ridge leverage of the rows of a block B (m x n), lambda = eps^2 *
-||B||_F^2: l_i = b_i^T (B^T B + lambda I)^{-1} b_i, i.e. sum_k U_ik^2
-sigma_k^2 / (sigma_k^2 + lambda); a smoothed form of the rank-r leverage of
-Section 3 (Definition of statistical leverage) that needs no rank choice.
+Labels (default): the leverage of Section 3 (Definition of statistical
+leverage) at the block's rank, taken from the method's own column-pivoted QR
+of the block B (m x n) stopped by the rank rule with tol = eps: squared row
+norms of an orthonormal basis of the r pivot columns (leverage.
+pivoted_leverage). Optional: the ridge leverage, lambda = eps^2 ||B||_F^2:
+l_i = b_i^T (B^T B + lambda I)^{-1} b_i, i.e. sum_k U_ik^2 sigma_k^2 /
+(sigma_k^2 + lambda), a smoothed form that needs no rank choice.
 Target t_i = ln(max(l_i, 1e-12) * m / sum(l)).
 
 Training set: block g (g < 2^28) picks leaf first_leaf + uniform_below(
@@ -67,6 +70,7 @@ import numpy as np
 
 from .cpqr_id import interpolative_decomposition
 from .kernels import Kernel, kernel_matrix
+from .leverage import pivoted_leverage
 from .sampling import counter_u64, floyd_sample, sample_far_rows, uniform_below
 
 NF = 16
@@ -337,8 +341,11 @@ def training_blocks(tree, num_blocks: int, block_cols: int, block_rows: int, see
     return out, n, m
 
 
-def training_set(X, tree, k: Kernel, num_blocks: int, block_cols: int, block_rows: int, eps: float, seed: int):
-    """Features F (C x 16), ridge leverages and targets of all training samples, block-major."""
+def training_set(X, tree, k: Kernel, num_blocks: int, block_cols: int, block_rows: int, eps: float, seed: int,
+                 label: str = "pivoted"):
+    """Features F (C x 16), leverages and targets of all training samples, block-major. label "pivoted":
+    the leverage at the block's eps-rank from its column-pivoted QR (Section 3's definition,
+    leverage.pivoted_leverage); "ridge": the ridge form."""
     Xt = np.asarray(X, dtype=np.float64)[tree.perm]
     blocks, n, m = training_blocks(tree, num_blocks, block_cols, block_rows, seed)
     F, lev, tgt = [], [], []
@@ -346,7 +353,7 @@ def training_set(X, tree, k: Kernel, num_blocks: int, block_cols: int, block_row
         geo = column_geometry(Xt[blk.cols], seed, blk.leaf)
         F.append(features(Xt[blk.rows], geo))
         B = kernel_matrix(Xt[blk.rows], Xt[blk.cols], k)
-        l = ridge_leverage(B, eps)
+        l = pivoted_leverage(B, eps)[0] if label == "pivoted" else ridge_leverage(B, eps)
         lev.append(l)
         tgt.append(leverage_targets(l))
     if not blocks:

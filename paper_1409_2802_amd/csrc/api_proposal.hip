@@ -107,6 +107,7 @@ ffc_status check_train_opts(const ffc_tree* t, const ffc_kernel* k, const ffc_tr
   if (!(o->eps > 0.0) || !std::isfinite(o->eps)) return fail(FFC_ERR_INVALID_ARG, "eps must be > 0");
   if (o->epochs < 0 || o->batch < 1) return fail(FFC_ERR_INVALID_ARG, "epochs must be >= 0 and batch >= 1");
   if (!(o->lr > 0.f) || !std::isfinite(o->lr)) return fail(FFC_ERR_INVALID_ARG, "lr must be > 0");
+  if (o->label != FFC_LABEL_PIVOTED && o->label != FFC_LABEL_RIDGE) return fail(FFC_ERR_INVALID_ARG, "unknown label kind");
   return validate_kernel(k, t->d);
 }
 
@@ -121,6 +122,8 @@ ffc_status train_sizes(const ffc_tree* t, const ffc_train_opts* o, int& n, int& 
   m = (int)std::min<int64_t>(o->block_rows, t->N - max_leaf);
   if (n < 1 || m < 1) return fail(FFC_ERR_INVALID_ARG, "tree too small for training blocks (needs two non-empty leaves)");
   if (n > 4096) return fail(FFC_ERR_INVALID_ARG, "block_cols above 4096 is not supported");
+  if (o->label == FFC_LABEL_PIVOTED && n > 1024)
+    return fail(FFC_ERR_INVALID_ARG, "pivoted leverage labels support block_cols <= 1024");
   if ((int64_t)m > 65536) return fail(FFC_ERR_INVALID_ARG, "block_rows above 65536 is not supported");
   return FFC_OK;
 }
@@ -158,13 +161,19 @@ ffc_status build_training_set(const ffc_tree* t, const ffc_kernel* k, const ffc_
   FFC_TRY(ts.lev.alloc(C));
   // Labels in chunks of blocks (about 1 GiB of blocks and Gram matrices each).
   const KParams kp = make_kparams(*k, t->d);
-  const size_t per_block = (size_t)m * n + (size_t)n * n;
+  const bool pivoted = o->label == FFC_LABEL_PIVOTED;
+  const size_t per_block = (size_t)m * n + (size_t)n * n * (pivoted ? 2 : 1);
   const int chunk = (int)std::max<size_t>(1, std::min<size_t>(G, ((size_t)1 << 27) / per_block));
-  DevBuf<double> B, Gm;
-  DevBuf<int> status;
+  DevBuf<double> B, Gm, Lc;
+  DevBuf<int> status, perm, rank;
   FFC_TRY(B.alloc((size_t)chunk * m * n));
   FFC_TRY(Gm.alloc((size_t)chunk * n * n));
   FFC_TRY(status.alloc(G));
+  if (pivoted) {
+    FFC_TRY(Lc.alloc((size_t)chunk * n * n));
+    FFC_TRY(perm.alloc((size_t)chunk * n));
+    FFC_TRY(rank.alloc(chunk));
+  }
   GeomScratch gs;   // outlives the launches below (freed after the synchronization)
   FFC_TRY(gs.alloc(G, t->d));
   {
@@ -175,8 +184,13 @@ ffc_status build_training_set(const ffc_tree* t, const ffc_kernel* k, const ffc_
       // columns, its "columns" the targets (the kernels are symmetric).
       FFC_TRY(launch_kblock_batch(t, kp, FFC_FP64, ts.cols.ptr + (int64_t)g0 * n, ts.ncols.ptr + g0, n,
                                   ts.rows.ptr + (int64_t)g0 * m, ts.nrows.ptr + g0, m, 0, c, nullptr, B.ptr, st));
-      FFC_TRY(launch_ridge_leverage(B.ptr, m, n, c, Gm.ptr, o->eps, ts.lev.ptr + (int64_t)g0 * m,
-                                    ts.target.ptr + (int64_t)g0 * m, status.ptr + g0, st));
+      if (pivoted)
+        FFC_TRY(launch_pivoted_leverage(B.ptr, m, n, c, Gm.ptr, Lc.ptr, perm.ptr, rank.ptr, o->eps,
+                                        ts.lev.ptr + (int64_t)g0 * m, ts.target.ptr + (int64_t)g0 * m,
+                                        status.ptr + g0, st));
+      else
+        FFC_TRY(launch_ridge_leverage(B.ptr, m, n, c, Gm.ptr, o->eps, ts.lev.ptr + (int64_t)g0 * m,
+                                      ts.target.ptr + (int64_t)g0 * m, status.ptr + g0, st));
     }
     // Features of every target against its block's columns.
     const GeomArgs ga = gs.args(ts.cols.ptr, n, ts.ncols.ptr, ts.leaves.ptr, o->seed);
@@ -565,6 +579,35 @@ ffc_status ffc_leverage_labels(const double* B_dev, int64_t m, int32_t n, int32_
   FFC_HIP_TRY(hipStreamSynchronize(st));
   for (int g = 0; g < count; ++g)
     if (sh[g] == 2) return fail(FFC_ERR_NONFINITE, "leverage labels: Cholesky factorization failed");
+  return FFC_OK;
+}
+
+ffc_status ffc_pivoted_leverage_labels(const double* B_dev, int64_t m, int32_t n, int32_t count, double eps,
+                                       double* lev_dev, float* target_dev, int32_t* rank_host, int32_t* piv_host,
+                                       void* stream) {
+  if (m < 1 || n < 1 || count < 0) return fail(FFC_ERR_INVALID_ARG, "m and n must be >= 1, count >= 0");
+  if (n > 1024) return fail(FFC_ERR_INVALID_ARG, "pivoted leverage supports n <= 1024");
+  if (!(eps > 0.0) || !(eps < 1.0)) return fail(FFC_ERR_INVALID_ARG, "eps must be in (0, 1)");
+  if (count == 0) return FFC_OK;
+  if (!B_dev || !lev_dev) return fail(FFC_ERR_INVALID_ARG, "B or lev is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  DevBuf<double> B, G, Lc;
+  DevBuf<int> status, perm, rank;
+  FFC_TRY(B.alloc((size_t)count * m * n));
+  FFC_TRY(G.alloc((size_t)count * n * n));
+  FFC_TRY(Lc.alloc((size_t)count * n * n));
+  FFC_TRY(status.alloc(count));
+  FFC_TRY(perm.alloc((size_t)count * n));
+  FFC_TRY(rank.alloc(count));
+  FFC_HIP_TRY(hipMemcpyAsync(B.ptr, B_dev, (size_t)count * m * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  FFC_TRY(launch_pivoted_leverage(B.ptr, m, n, count, G.ptr, Lc.ptr, perm.ptr, rank.ptr, eps, lev_dev, target_dev,
+                                  status.ptr, st));
+  std::vector<int> rh(count);
+  FFC_HIP_TRY(hipMemcpyAsync(rh.data(), rank.ptr, count * sizeof(int), hipMemcpyDeviceToHost, st));
+  if (piv_host)
+    FFC_HIP_TRY(hipMemcpyAsync(piv_host, perm.ptr, (size_t)count * n * sizeof(int), hipMemcpyDeviceToHost, st));
+  FFC_HIP_TRY(hipStreamSynchronize(st));
+  if (rank_host) std::copy(rh.begin(), rh.end(), rank_host);
   return FFC_OK;
 }
 

@@ -434,6 +434,15 @@ ffc_status launch_heldout_check(const double* Kh, const int32_t* nh, int h_cap, 
 ffc_status launch_ridge_leverage(double* B, int64_t m, int n, int count, double* G, double eps, double* lev,
                                  float* target, int* status, hipStream_t st);
 
+// Pivoted (rank-r) leverage labels (leverage.hip) of row-major m x n blocks
+// (n <= 1024): G_b = B_b^T B_b, its diagonal-pivoted Cholesky factor (column-
+// major in Lc, pivot order in perm, pivots in rank) stopped at sqrt(d_k) <
+// eps sqrt(d_0), lev[b][i] = |B_b(i, J) L11^{-T}|^2 (B overwritten at the
+// pivot columns) and, when target is non-null, the log targets as above.
+// status[b]: 0 factorized, 1 zero block.
+ffc_status launch_pivoted_leverage(double* B, int64_t m, int n, int count, double* G, double* Lc, int* perm,
+                                   int* rank, double eps, double* lev, float* target, int* status, hipStream_t st);
+
 // Far + near field evaluation (kblock.hip).
 ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision,
                            double* u, double* u_far, hipStream_t st);

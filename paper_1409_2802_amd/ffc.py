@@ -23,6 +23,7 @@ FFC_OK, FFC_ERR_INVALID_ARG, FFC_ERR_HIP, FFC_ERR_OOM, FFC_ERR_NONFINITE, FFC_ER
 GAUSSIAN, LAPLACE, POLYNOMIAL = 0, 1, 2
 FP64, FP32, MIXED_BF16X3 = 0, 1, 2
 SAMPLE_UNIFORM, SAMPLE_LEARNED, SAMPLE_DISTANCE, SAMPLE_NEAREST = 0, 1, 2, 3
+LABEL_PIVOTED, LABEL_RIDGE = 0, 1
 
 # Every exported entry point of include/ffc.h.
 EXPORTS = [
@@ -35,7 +36,7 @@ EXPORTS = [
     "ffc_leverage_labels", "ffc_proposal_train", "ffc_proposal_training_set",
     "ffc_step_graph_create", "ffc_step_graph_create_fmm", "ffc_graph_launch", "ffc_graph_free", "ffc_autotune_report",
     "ffc_skel_load", "ffc_proposal_get_adam", "ffc_proposal_set_adam", "ffc_shutdown",
-    "ffc_proposal_save", "ffc_proposal_load",
+    "ffc_proposal_save", "ffc_proposal_load", "ffc_pivoted_leverage_labels",
 ]
 
 NPARAM = 5313
@@ -71,7 +72,7 @@ class StatsC(ctypes.Structure):
 class TrainOptsC(ctypes.Structure):
     _fields_ = [("num_blocks", ctypes.c_int32), ("block_cols", ctypes.c_int32), ("block_rows", ctypes.c_int32),
                 ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
-                ("eps", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("eps", ctypes.c_double), ("seed", ctypes.c_uint64), ("label", ctypes.c_int32)]
 
 
 _lib = None
@@ -114,6 +115,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ffc_proposal_gradient": [P, P, P, I64, P, P, P],
         "ffc_proposal_adam": [P, P, ctypes.c_float, P],
         "ffc_leverage_labels": [P, I64, I32, I32, D, P, P, P],
+        "ffc_pivoted_leverage_labels": [P, I64, I32, I32, D, P, P, P, P, P],
         "ffc_proposal_train": [P, P, ctypes.POINTER(KernelC), ctypes.POINTER(TrainOptsC), P, P],
         "ffc_proposal_training_set": [P, ctypes.POINTER(KernelC), ctypes.POINTER(TrainOptsC), P, P, P, P, P, P, P,
                                       P, P],
@@ -594,10 +596,11 @@ class Proposal:
         _check(load_library().ffc_proposal_adam(self._h, _ptr(g), lr, _stream(stream)))
 
     def train(self, tree: Tree, kernel: Kernel, num_blocks: int, block_cols: int, block_rows: int, epochs: int,
-              batch: int, lr: float, eps: float, seed: int = 0, stream=None) -> np.ndarray:
+              batch: int, lr: float, eps: float, seed: int = 0, label: int = LABEL_PIVOTED,
+              stream=None) -> np.ndarray:
         """Builds the training set on the GPU and trains; returns the per-epoch loss."""
         o = TrainOptsC(num_blocks=num_blocks, block_cols=block_cols, block_rows=block_rows, epochs=epochs,
-                       batch=batch, lr=lr, eps=eps, seed=seed)
+                       batch=batch, lr=lr, eps=eps, seed=seed, label=label)
         loss = np.zeros(max(epochs, 1), dtype=np.float32)
         k = kernel.c_struct()
         _check(load_library().ffc_proposal_train(self._h, tree.handle, ctypes.byref(k), ctypes.byref(o),
@@ -636,11 +639,26 @@ def leverage_labels(B, eps: float, stream=None):
     return lev, tgt
 
 
+def pivoted_leverage_labels(B, eps: float, stream=None):
+    """Leverage at each block's eps-rank from its column-pivoted QR: (lev, targets, ranks, pivot order)."""
+    Bd = _dev_f64(B, "B")
+    if Bd.dim() == 2:
+        Bd = Bd[None]
+    count, m, n = Bd.shape
+    lev = torch.empty((count, m), dtype=torch.float64, device="cuda")
+    tgt = torch.empty((count, m), dtype=torch.float32, device="cuda")
+    rank = np.zeros(count, dtype=np.int32)
+    piv = np.zeros((count, n), dtype=np.int32)
+    _check(load_library().ffc_pivoted_leverage_labels(_ptr(Bd), m, n, count, eps, _ptr(lev), _ptr(tgt),
+                                                      rank.ctypes.data, piv.ctypes.data, _stream(stream)))
+    return lev, tgt, rank, piv
+
+
 def training_set(tree: Tree, kernel: Kernel, num_blocks: int, block_cols: int, block_rows: int, eps: float,
-                 seed: int = 0, stream=None) -> dict:
+                 seed: int = 0, label: int = LABEL_PIVOTED, stream=None) -> dict:
     """The proposal's training set as built on the GPU (leaves, columns, targets, features, labels)."""
     o = TrainOptsC(num_blocks=num_blocks, block_cols=block_cols, block_rows=block_rows, epochs=0, batch=1, lr=1e-3,
-                   eps=eps, seed=seed)
+                   eps=eps, seed=seed, label=label)
     k = kernel.c_struct()
     n, m = ctypes.c_int32(), ctypes.c_int32()
     lib = load_library()

@@ -1,5 +1,6 @@
 """Learned row proposal on the GPU against the oracle: features, network
-scores, gradients, Adam, standardization, ridge leverage labels, the training
+scores, gradients, Adam, standardization, leverage labels (at the block's
+eps-rank, and the ridge form), the training
 set, training, learned skeletonization with its held-out fallback, and the
 gain over uniform sampling (Section 3 importance sampling; Section 3.2
 cheap heuristics; Section 4.1.3 sampling distributions)."""
@@ -167,6 +168,73 @@ def test_leverage_labels_match_oracle(ffc, shape, kind):
                                    atol=1e-5 + float(np.max(_lev_tol(n, eps) / lo[big], initial=0.0)))
 
 
+def _pivoted_reference(B, eps):
+    """Oracle pivoted leverage plus whether its decisions are clear of the Gram route's rounding: every
+    pivot's relative gap of squared norms above 1e-6 and every rho_k / rho_0 (k <= r) more than 1e-6
+    relative away from eps."""
+    from oracle.cpqr_id import cpqr
+    from oracle.leverage import pivoted_leverage
+    lev, r, J, gap = pivoted_leverage(B, eps)
+    _, _, _, rho, _ = cpqr(B, 0.0, min(B.shape))
+    clear = bool(gap.size == 0 or gap[:r + 1].min() > 1e-6)
+    if rho.size and rho[0] > 0:
+        ratios = rho[:r + 1] / rho[0]
+        clear = clear and bool(np.all(np.abs(ratios / eps - 1.0) > 1e-6))
+    return lev, r, J, clear
+
+
+def _piv_lev_tol(n, r, eps):
+    # Through B^T B: Cholesky backward error ~ n u |G| becomes a loss of orthonormality of
+    # W = B(:, J) R11^{-1} of about n u cond(B(:, J))^2, cond <= ~ sqrt(r) / eps under the stopping rule.
+    return 100.0 * n * U64 * max(r, 1) / eps ** 2
+
+
+@pytest.mark.parametrize("shape,kind", [((300, 100), "kernel"), ((130, 70), "gauss"), ((50, 120), "gauss"),
+                                        ((64, 32), "zero"), ((257, 97), "lowrank"), ((400, 80), "poly")])
+def test_pivoted_leverage_labels_match_oracle(ffc, shape, kind):
+    """Leverage at the block's eps-rank (Section 3) from the GPU's diagonal-pivoted Cholesky of B^T B
+    against the oracle's column-pivoted QR of B: same rank and pivots where the decisions are clear,
+    scores within the Gram route's rounding, sum(scores) = rank; an exactly low-rank polynomial block
+    gives the singular-vector leverage."""
+    from oracle.kernels import POLYNOMIAL
+    from oracle.leverage import row_leverage
+    m, n = shape
+    rng = np.random.default_rng(11)
+    if kind == "kernel":
+        X = W.low_intrinsic(m + n, 8, di=3, seed=1)
+        B = kernel_matrix(X[:m], X[m:], okernel(LAPLACE))
+    elif kind == "gauss":
+        B = rng.standard_normal((m, n))
+    elif kind == "lowrank":
+        B = rng.standard_normal((m, 5)) @ rng.standard_normal((5, n))
+    elif kind == "poly":
+        Y = rng.uniform(-1, 1, (m + n, 4))
+        B = kernel_matrix(Y[:m], Y[m:], okernel(POLYNOMIAL, h=1.0, p=3))
+    else:
+        B = np.zeros((m, n))
+    eps = 1e-3
+    Bs = np.stack([B, 0.5 * B[::-1]])
+    lev, tgt, rank, piv = ffc.pivoted_leverage_labels(Bs, eps)
+    lev, tgt = lev.cpu().numpy(), tgt.cpu().numpy()
+    for b in range(2):
+        lo, ro, Jo, clear = _pivoted_reference(Bs[b], eps)
+        if kind == "zero":
+            assert rank[b] == 0 and np.all(lev[b] == 0.0)
+            continue
+        assert clear, "test blocks are chosen without near-ties"
+        assert rank[b] == ro, (b, rank[b], ro)
+        np.testing.assert_array_equal(piv[b][:ro], Jo)
+        tol = _piv_lev_tol(n, ro, eps)
+        assert np.max(np.abs(lev[b] - lo)) <= tol, np.max(np.abs(lev[b] - lo))
+        assert abs(lev[b].sum() - ro) <= m * tol
+        big = lo > 1e-6
+        np.testing.assert_allclose(tgt[b][big], pr.leverage_targets(lo)[big], rtol=1e-5,
+                                   atol=1e-5 + float(np.max(tol / lo[big], initial=0.0)))
+        if kind == "poly":
+            assert ro == 35
+            np.testing.assert_allclose(lev[b], row_leverage(Bs[b], 35), atol=tol)
+
+
 def _learning_data():
     return W.low_intrinsic(3000, 8, di=3, noise=1e-2, seed=5)
 
@@ -174,8 +242,9 @@ def _learning_data():
 def test_training_set_matches_oracle(ffc):
     X = _learning_data()
     t, ot = trees(ffc, X, 200)
-    ts = ffc.training_set(t, gkernel(GAUSSIAN, h=1.0), 6, 120, 500, eps=1e-3, seed=3)
-    F, lev, tgt, blocks = pr.training_set(X, ot, okernel(GAUSSIAN, h=1.0), 6, 120, 500, eps=1e-3, seed=3)
+    ts = ffc.training_set(t, gkernel(GAUSSIAN, h=1.0), 6, 120, 500, eps=1e-3, seed=3, label=ffc.LABEL_RIDGE)
+    F, lev, tgt, blocks = pr.training_set(X, ot, okernel(GAUSSIAN, h=1.0), 6, 120, 500, eps=1e-3, seed=3,
+                                          label="ridge")
     m = len(blocks[0].rows)
     assert ts["n"] == len(blocks[0].cols) and ts["m"] == m
     np.testing.assert_array_equal(ts["leaves"].cpu().numpy(), [b.leaf for b in blocks])
@@ -187,15 +256,41 @@ def test_training_set_matches_oracle(ffc):
     np.testing.assert_allclose(ts["target"].cpu().numpy()[big], tgt[big], rtol=1e-6, atol=1e-4)
 
 
+def test_pivoted_training_set_matches_oracle(ffc):
+    """The default labels (leverage at each block's eps-rank) of the training set against the oracle's,
+    block by block: ranks and scores where the block's pivots are clear."""
+    X = _learning_data()
+    t, ot = trees(ffc, X, 200)
+    ts = ffc.training_set(t, gkernel(GAUSSIAN, h=1.0), 6, 120, 500, eps=1e-3, seed=3)
+    F, lev, tgt, blocks = pr.training_set(X, ot, okernel(GAUSSIAN, h=1.0), 6, 120, 500, eps=1e-3, seed=3)
+    n, m = ts["n"], ts["m"]
+    np.testing.assert_allclose(ts["feat"].cpu().numpy(), F, rtol=1e-6, atol=1e-6)
+    glev = ts["lev"].cpu().numpy()
+    Xt = X[ot.perm]
+    compared = 0
+    for g, blk in enumerate(blocks):
+        B = kernel_matrix(Xt[blk.rows], Xt[blk.cols], okernel(GAUSSIAN, h=1.0))
+        lo, ro, _, clear = _pivoted_reference(B, 1e-3)
+        np.testing.assert_array_equal(lo, lev[g * m:(g + 1) * m])
+        gl = glev[g * m:(g + 1) * m]
+        assert abs(gl.sum() - round(gl.sum())) < 1e-6 * m            # the scores sum to an integer rank
+        if clear:
+            compared += 1
+            assert abs(gl.sum() - ro) < 1e-6 * m
+            assert np.max(np.abs(gl - lo)) <= _piv_lev_tol(n, ro, 1e-3)
+    assert compared >= 1
+
+
 def test_training_matches_oracle(ffc):
     X = _learning_data()
     t, ot = trees(ffc, X, 200)
     theta0 = f32(W.mlp_init(5))
     p = ffc.Proposal(theta0)
     epochs, batch, lr = 2, 256, 1e-3
-    hist = p.train(t, gkernel(GAUSSIAN, h=1.0), 6, 120, 500, epochs=epochs, batch=batch, lr=lr, eps=1e-3, seed=3)
+    hist = p.train(t, gkernel(GAUSSIAN, h=1.0), 6, 120, 500, epochs=epochs, batch=batch, lr=lr, eps=1e-3, seed=3,
+                   label=ffc.LABEL_RIDGE)
     th, mu, sd = p.get()
-    F, _, tgt, _ = pr.training_set(X, ot, okernel(GAUSSIAN, h=1.0), 6, 120, 500, eps=1e-3, seed=3)
+    F, _, tgt, _ = pr.training_set(X, ot, okernel(GAUSSIAN, h=1.0), 6, 120, 500, eps=1e-3, seed=3, label="ridge")
     muo, sdo = pr.fit_standardization(F)
     np.testing.assert_allclose(mu, muo, rtol=1e-5, atol=1e-5)
     np.testing.assert_allclose(sd, sdo, rtol=1e-5)
@@ -283,18 +378,20 @@ def test_learned_fallback_matches_oracle(ffc):
     assert sk2.stats()["fallbacks"] == 0 and not any(fell2.values())
 
 
-def test_learned_beats_uniform(ffc):
+@pytest.mark.parametrize("label", [0, 1])
+def test_learned_beats_uniform(ffc, label):
     """Gain test: Laplace kernel on points near a 4-dimensional subspace of
     R^16, where a few near targets carry the far field and uniform rows miss
     them (the coherence problem of Section 3). The proposal is trained on the
-    GPU and sees every far point as a candidate (pool factor 64)."""
+    GPU (labels: leverage at each block's eps-rank, or the ridge form) and sees
+    every far point as a candidate (pool factor 64)."""
     N, d = 4096, 16
     X = W.low_intrinsic(N, d, di=4, noise=1e-2, seed=0)
     q = W.charges(N, seed=1)
     t, ot = trees(ffc, X, 256)
     gk, ok = gkernel(LAPLACE), okernel(LAPLACE)
     p = ffc.Proposal(W.mlp_init(5))
-    hist = p.train(t, gk, 48, 256, 2048, epochs=8, batch=512, lr=1e-3, eps=1e-4, seed=7)
+    hist = p.train(t, gk, 48, 256, 2048, epochs=8, batch=512, lr=1e-3, eps=1e-4, seed=7, label=label)
     assert hist[-1] < 0.2 * hist[0]
     ex = exact_far_field(X, ot, ok, q)
     uni = ffc.skeletonize(t, gk, tol=1e-6, max_rank=64, num_samples=64, seed=0)

@@ -7,7 +7,8 @@ import os
 import numpy as np
 import pytest
 
-from oracle.leverage import row_leverage, row_leverage_eps
+from oracle.kernels import POLYNOMIAL, Kernel, kernel_matrix
+from oracle.leverage import pivoted_leverage, row_leverage, row_leverage_eps
 from oracle.sampling import floyd_sample
 from oracle.theory import epsilon_rank, reconstruction_factor, sample_count, silverman_bandwidth
 
@@ -89,3 +90,39 @@ def test_epsilon_rank():
     assert epsilon_rank(A, 1e-2) == 2
     assert epsilon_rank(A, 1e-4) == 3
     assert epsilon_rank(np.zeros((3, 3)), 1e-2) == 0
+
+
+@pytest.mark.parametrize("p,rank", [(2, 15), (3, 35)])
+def test_pivoted_leverage_equals_the_svd_leverage_on_exactly_low_rank_blocks(p, rank):
+    """A polynomial kernel block in d = 4 has exact rank C(4 + p, p): the pivoted QR stops there, the
+    span of its r skeleton columns is the block's range, and the scores equal the singular-vector
+    leverage of Section 3 at that rank."""
+    g = np.random.default_rng(p)
+    Y, X = g.uniform(-1, 1, (300, 4)), g.uniform(-1, 1, (80, 4))
+    B = kernel_matrix(Y, X, Kernel(POLYNOMIAL, h=1.0, c=1.0, p=p))
+    lev, r, J, _ = pivoted_leverage(B, 1e-9)
+    assert r == rank == math.comb(4 + p, p)
+    np.testing.assert_allclose(lev, row_leverage(B, rank), atol=1e-9)
+    assert lev.sum() == pytest.approx(rank)
+
+
+def test_pivoted_leverage_invariants_and_problem_case():
+    """Scores lie in [0, 1] and sum to the rank; at full column rank they are the hat-matrix diagonal;
+    in the paper's rank-two problem case the first row has leverage 1."""
+    g = np.random.default_rng(3)
+    K = g.standard_normal((70, 9)) * np.linspace(1, 3, 9)
+    lev, r, J, _ = pivoted_leverage(K, 1e-12)
+    assert r == 9 and sorted(J) == list(range(9))
+    assert lev.min() >= -1e-15 and lev.max() <= 1 + 1e-12
+    np.testing.assert_allclose(lev, np.diag(K @ np.linalg.pinv(K)), atol=1e-10)
+    m, n = 400, 10
+    v1, v2 = np.eye(n)[0], np.eye(n)[1]
+    P = np.vstack([v1] + [v2] * (m - 1))
+    lev, r, J, _ = pivoted_leverage(P, 1e-8)
+    assert r == 2 and lev[0] == pytest.approx(1.0) and lev[1:].sum() == pytest.approx(1.0)
+    # A truncated factorization: the first pivot is the column of largest norm, and the scores sum to r.
+    D = g.standard_normal((50, 6)) @ np.diag([1.0, 0.5, 1e-3, 1e-5, 1e-7, 1e-9]) @ np.linalg.qr(
+        g.standard_normal((6, 6)))[0]
+    lev, r, J, _ = pivoted_leverage(D, 1e-4)
+    assert J[0] == int(np.argmax(np.linalg.norm(D, axis=0)))
+    assert 2 <= r <= 4 and lev.sum() == pytest.approx(r)
