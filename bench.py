@@ -8,7 +8,7 @@ upward, far + near field sums). The tree is built once, outside the timed
 region; so is the proposal's training, which is timed on its own.
 
 Workloads (synthetic, seeded):
-  mixture16   (default) N = 65536 points in d = 16 from a mixture of 32
+  mixture16   N = 65536 points in d = 16 from a mixture of 32
               Gaussian clusters (centres uniform in [0, 10]^16, std 0.5),
               Gaussian kernel h = 1, leaf size 512, rank cap 256 and 2 x 256
               sampled rows per node, ID tolerance 1e-5, q ~ N(0, 1), FP64
@@ -18,11 +18,14 @@ Workloads (synthetic, seeded):
   highdim1000 N = 65536, d = 1000, N(0, I)/sqrt(d) plus 64 offsets of norm 3,
               polynomial kernel (x.y + 1)^3, leaf 512, tol 1e-4, mixed
   highdim1000g  the same points with the Gaussian kernel h = 1.5
-  learned64   the subspace64 points with the Gaussian kernel h = 1 and the
-              learned proposal, trained on the GPU first (2000 blocks of 512
-              columns x 4096 targets by default)
+  learned64   (default) the subspace64 points with the Gaussian kernel h = 1
+              and the learned proposal, trained on the GPU first (2000 blocks
+              of 512 columns x 4096 targets, labels = leverage at each
+              block's eps-rank); mixed precision, timed against the plain
+              FP64 uniform-sampling path on the same tree
 
-Prints one JSON line: value = skeletonized nodes per second of step time.
+Prints one JSON line: value = skeletonized nodes per second of step time;
+meets_1e-4 = far-field error against the exact FP64 sum at most 1e-4.
 """
 from __future__ import annotations
 
@@ -83,7 +86,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mixture16", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="learned64", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--train-blocks", type=int, default=None, help="learned64: training blocks")
     ap.add_argument("--compare", action="store_true",
@@ -96,6 +99,8 @@ def parse():
     ap.add_argument("--eager", action="store_true",
                     help="time eager calls instead of replays of the step captured as a HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-floor", action="store_true",
+                    help="skip the singular-value floor of the exact far blocks of a few leaves")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     return ap.parse_args()
 
@@ -169,47 +174,132 @@ def measured_traffic(workload, precision, kernel):
     return None
 
 
-def cpu_baseline(w, X, budget_s):
-    """The oracle, single-threaded, on a bounded sample of the workload's nodes."""
+# State shared with the oracle's worker processes (set before they fork).
+_CPU = {}
+
+
+def _oracle_node(Xt, ot, a, cols):
+    """Skeletonize one node with the oracle, the way the timed GPU step does it (sampler, separation,
+    adaptive count); returns its skeleton."""
+    from oracle.skeleton import skeletonize_node
+    w, ok = _CPU["w"], _CPU["ok"]
+    if w.get("adaptive_tol", 0.0) > 0:
+        from oracle.adaptive import adaptive_node
+        node, _ = adaptive_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], w["max_samples"], 0,
+                                w["adaptive_tol"])
+        return node
+    if w.get("separation", 0.0) > 0:
+        from oracle.separation import separated_rows
+        rows = separated_rows(Xt, ot, a, w["num_samples"], 0, w["separation"])
+        return skeletonize_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], 0, rows=rows)
+    if _CPU.get("proposal") is not None:
+        from oracle.proposal import skeletonize_learned_node
+        th, mu, sd = _CPU["proposal"]
+        node, _ = skeletonize_learned_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], 0, th, mu,
+                                           sd, 0.0, w.get("pool_factor", 8))
+        return node
+    return skeletonize_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], 0)
+
+
+def _oracle_subtrees(args):
+    """Skeletonize whole subtrees (two leaves, then their parent) bottom-up with the oracle on one thread
+    until the budget is spent; returns the seconds of every leaf and every internal node."""
+    roots, budget_s = args
     from threadpoolctl import threadpool_limits
+    Xt, ot = _CPU["Xt"], _CPU["ot"]
+    t_leaf, t_int = [], []
+    t_start = time.perf_counter()
+    with threadpool_limits(limits=1):
+        for a in itertools.cycle(roots):
+            kids = []
+            for c in (2 * a + 1, 2 * a + 2):
+                t0 = time.perf_counter()
+                kids.append(_oracle_node(Xt, ot, c, np.arange(ot.begin[c], ot.end[c], dtype=np.int64)))
+                t_leaf.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            _oracle_node(Xt, ot, a, np.concatenate([kids[0].skel, kids[1].skel]).astype(np.int64))
+            t_int.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_start > budget_s:
+                break
+    return t_leaf, t_int
+
+
+def cpu_baseline(w, X, budget_s, proposal_params=None, nodes_mix=None):
+    """The oracle on the same per-node work as the GPU step (same samplers, sample counts and rank rule; an
+    internal node's columns are its children's skeletons), on bounded samples: whole subtrees of two
+    leaves and their parent, timed node by node, once on one thread and once on every host core (one
+    single-threaded process per core, disjoint subtrees). Rates are for the GPU step's node mix (all
+    levels): nodes / (leaves x mean leaf time + internal nodes x mean internal time)."""
+    import multiprocessing as mp
 
     from oracle.kernels import Kernel as OKernel
-    from oracle.separation import separated_rows
-    from oracle.skeleton import skeletonize_node
     from oracle.tree import build_tree as o_build_tree
     kind, kw = kernel_args(w)
-    ok = OKernel(kind, **kw)
-    with threadpool_limits(limits=1):
-        ot = o_build_tree(X, w["leaf"])
-        Xt = X[ot.perm]
-        t0 = time.perf_counter()
-        done = passes = 0
-        adaptive = w.get("adaptive_tol", 0.0) > 0
-        leaves = ot.level_nodes(ot.depth)            # leaves: their columns need no children
-        # Passes over the leaves until the budget is spent (the last pass may stop part-way).
-        for i, a in enumerate(itertools.cycle(leaves)):
-            passes = i // len(leaves) + 1
-            cols = np.arange(ot.begin[a], ot.end[a], dtype=np.int64)
-            if adaptive:
-                from oracle.adaptive import adaptive_node
-                adaptive_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], w["max_samples"], 0,
-                              w["adaptive_tol"])
-            elif w.get("separation", 0.0) > 0:
-                rows = separated_rows(Xt, ot, a, w["num_samples"], 0, w["separation"])
-                skeletonize_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], 0, rows=rows)
-            else:
-                skeletonize_node(Xt, ot, a, cols, ok, w["tol"], w["max_rank"], w["num_samples"], 0)
-            done += 1
-            if time.perf_counter() - t0 > budget_s:
-                break
-        dt = time.perf_counter() - t0
-    rows = (f"{w['num_samples']} sampled rows doubled up to {w['max_samples']} by the adaptive rule" if adaptive
-            else f"{w['num_samples']} sampled rows")
-    if w.get("separation", 0.0) > 0:
-        rows += f" from the points separated by xi={w['separation']}"
-    return {"value": done / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} leaf-node skeletonizations ({passes} passes over the {len(leaves)} leaves of the same "
-                      f"tree; {w['leaf']} points, {rows} each, FP64), single thread, {dt:.1f} s"}
+    ot = o_build_tree(X, w["leaf"])
+    _CPU.update(w=w, ok=OKernel(kind, **kw), ot=ot, Xt=X[ot.perm], proposal=proposal_params)
+    parents = list(ot.level_nodes(ot.depth - 1))
+    n_leaf, n_int = nodes_mix
+    cores = max(1, min(os.cpu_count() or 1, 16))
+
+    def rate(tl, ti):
+        return (n_leaf + n_int) / (n_leaf * float(np.mean(tl)) + n_int * float(np.mean(ti)))
+
+    tl, ti = _oracle_subtrees((parents[:1] + parents[1:], budget_s))
+    one = rate(tl, ti)
+    chunks = [parents[c::cores] for c in range(cores)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_subtrees, [(c, budget_s) for c in chunks if c])
+    allc = sum(rate(a, b) for a, b in res)
+    leaves_all = sum(len(a) for a, _ in res)
+    int_all = sum(len(b) for _, b in res)
+    smp = "learned proposal" if proposal_params is not None else (
+        "adaptive sample count" if w.get("adaptive_tol", 0.0) > 0 else
+        f"rows from the points separated by xi={w['separation']}" if w.get("separation", 0.0) > 0 else "uniform rows")
+    return {"value": allc, "unit": "nodes/s", "cores": cores, "kind": "oracle",
+            "single_core": {"value": one, "leaf_s": float(np.mean(tl)), "internal_s": float(np.mean(ti)),
+                            "leaves": len(tl), "internal": len(ti)},
+            "sample": f"FP64 numpy oracle, {smp}, {w['num_samples']} rows, rank cap {w['max_rank']}: whole subtrees "
+                      f"(two leaves then their parent) for {budget_s:.0f} s per process; one thread: {len(tl)} leaves "
+                      f"+ {len(ti)} internal nodes; {cores} processes x 1 thread: {leaves_all} leaves + {int_all} "
+                      f"internal nodes; rate for the GPU step's mix of {n_leaf} leaves + {n_int} internal nodes"}
+
+
+def far_block_floor(w, X, tree, k, ffc, leaves=(0, 255), target=1e-4):
+    """Eckart-Young floor of the far field: for a few leaves, the singular values of the exact far block
+    K(all points outside the leaf, leaf points) (FP64 blocks from the library, Gram matrix and its
+    eigenvalues on the host). For any representation of rank r the relative Frobenius error of that block
+    is at least tail(r) = sqrt(sum_{k>r} s_k^2 / sum s_k^2); with charges q ~ N(0, I) that is also the
+    expected relative error of the far field K q. Reports tail(rank cap) and the least r with
+    tail(r) <= target."""
+    import torch
+    arr = tree.arrays()
+    first = (1 << tree.depth) - 1
+    nleaf = 1 << tree.depth
+    out = []
+    for li in leaves:
+        if li >= nleaf:
+            continue
+        a = first + li
+        b, e = int(arr["begin"][a]), int(arr["end"][a])
+        cols = torch.arange(b, e, dtype=torch.int32, device="cuda")
+        far = np.r_[0:b, e:tree.N].astype(np.int32)
+        G = np.zeros((e - b, e - b))
+        for c0 in range(0, len(far), 16384):
+            rows = torch.as_tensor(far[c0:c0 + 16384], device="cuda")
+            Kb = ffc.sampled_block(tree, k, rows, cols, precision=ffc.FP64).cpu().numpy()   # rows x columns
+            G += Kb.T @ Kb
+        lam = np.clip(np.linalg.eigvalsh(G)[::-1], 0.0, None)
+        tot = lam.sum()
+        tail = np.sqrt(np.maximum(tot - np.cumsum(lam), 0.0) / tot) if tot > 0 else np.zeros_like(lam)
+        r_cap = min(w["max_rank"], len(lam))
+        need = int(np.argmax(tail <= target)) + 1 if np.any(tail <= target) else None
+        out.append({"leaf": a, "columns": e - b, "rows": len(far), "tail_at_rank_cap": float(tail[r_cap - 1]),
+                    "rank_cap": r_cap, "least_rank_for_target": need})
+        print(f"[bench] far-block floor, leaf {a}: {out[-1]}", file=sys.stderr, flush=True)
+    return {"target": target, "leaves": out,
+            "note": "Eckart-Young: no rank-r representation of a leaf's exact far block beats tail(r) in relative "
+                    "Frobenius norm (the expected far-field error for random charges)"}
 
 
 def oracle_far_check(w, X, q, u_far_gpu, count=256):
@@ -384,18 +474,20 @@ def main():
     use_graph = not args.eager and not (proposal is not None and w.get("fallback_tol", 0.0) > 0) \
         and not w.get("adaptive_tol", 0.0) > 0
 
-    def timed(p, steps, warmup, out):
-        """Warm-up with eager calls, then time `steps` steps in precision p (graph replays unless --eager)."""
+    def timed(p, steps, warmup, out, prop=proposal):
+        """Warm-up with eager calls, then time `steps` steps in precision p with proposal prop (None: uniform
+        rows) as graph replays unless --eager."""
+        sampler = ffc.SAMPLE_LEARNED if prop is not None else ffc.SAMPLE_UNIFORM
         sk = None
         for _ in range(max(1, warmup)):
-            sk = step(sk, p=p, out=out)
+            sk = step(sk, p=p, out=out, prop=prop, sampler=sampler)
         torch.cuda.synchronize()
         st = torch.cuda.Stream() if use_graph else torch.cuda.current_stream()
         st.wait_stream(torch.cuda.current_stream())
         graph = None
         if use_graph:
             graph = ffc.StepGraph(tree, sk, k, qd, out[0], out[1], st, tol=w["tol"], max_rank=w["max_rank"],
-                                  num_samples=w["num_samples"], precision=p, seed=0, proposal=proposal,
+                                  num_samples=w["num_samples"], precision=p, seed=0, proposal=prop,
                                   pool_factor=w.get("pool_factor", 0), separation=w.get("separation", 0.0),
                                   fmm=w.get("evaluation") == "fmm")
             graph.launch(st)
@@ -407,7 +499,7 @@ def main():
                 graph.launch(st)
             else:
                 with torch.cuda.stream(st):
-                    sk = step(sk, p=p, out=out)
+                    sk = step(sk, p=p, out=out, prop=prop, sampler=sampler)
         ev1.record(st)
         st.synchronize()
         ffc.check_device(st)
@@ -507,15 +599,17 @@ def main():
         e_seeds.append(float(np.linalg.norm(ufs.cpu().numpy() - far_exact) / np.linalg.norm(far_exact)))
     print(f"[bench] e_far over seeds 0..4: {e_seeds}", file=sys.stderr, flush=True)
 
-    # The plain FP64 path on the same workload (same sampler and seeds): the reference the metric's
-    # 1e-4 far-field tolerance is read against, and the baseline of the speedups.
+    # The plain FP64 uniform-sampling GPU path on the same tree and seeds: the baseline of the speedup,
+    # and the result the mixed / learned far field is compared with (besides the exact sum).
     u64r, uf64r = torch.empty_like(u), torch.empty_like(uf)
-    if prec == ffc.FP64:
+    if prec == ffc.FP64 and proposal is None:
         uf64_h, ms64 = uf_h, ms_step
     else:
-        _, ms64 = timed(ffc.FP64, args.steps, args.warmup, (u64r, uf64r))
+        _, ms64 = timed(ffc.FP64, args.steps, args.warmup, (u64r, uf64r), prop=None)
         uf64_h = uf64r.cpu().numpy()
+        print(f"[bench] plain FP64 uniform path: {ms64:.3f} ms/step", file=sys.stderr, flush=True)
     e_vs64 = float(np.linalg.norm(uf_h - uf64_h) / np.linalg.norm(uf64_h))
+    e_far64_exact = float(np.linalg.norm(uf64_h - far_exact) / np.linalg.norm(far_exact))
     variants = {}
     if prec == ffc.FP64 and proposal is None:
         for vname in [v for v in args.variants.split(",") if v]:
@@ -574,9 +668,10 @@ def main():
         "skeleton_kernel_evals": skel_evals, "evaluate_kernel_evals": eval_evals,
         "ranks": {"min": st["rank_min"], "mean": st["rank_mean"], "max": st["rank_max"],
                   "cap_hits": st["rank_cap_hits"]},
-        "e_far_vs_fp64_path": e_vs64, "meets_1e-4": e_vs64 <= 1e-4,
-        "speedup_vs_fp64_path": ms64 / ms_step,
+        "meets_1e-4": e_far_gpu <= 1e-4,
         "e_far_vs_exact": e_far_gpu, "e_total_vs_exact": e_tot_gpu,
+        "speedup_vs_fp64_uniform_path": ms64 / ms_step, "fp64_uniform_ms_per_step": ms64,
+        "e_far_vs_fp64_uniform_path": e_vs64, "fp64_uniform_e_far_vs_exact": e_far64_exact,
         "e_far_vs_exact_seeds": {"seeds": [0, 1, 2, 3, 4], "values": e_seeds, "mean": float(np.mean(e_seeds)),
                                  "std": float(np.std(e_seeds))},
         "precision_variants": variants,
@@ -657,8 +752,15 @@ def main():
             cmp.append(row)
             print(f"[bench] compare {row}", file=sys.stderr, flush=True)
         out["sampler_e_far"] = cmp
+    if not args.no_floor:
+        out["compressibility"] = far_block_floor(w, X, tree, k, ffc)
     if not args.no_cpu_baseline:
-        cb = cpu_baseline(w, X, args.cpu_budget_s)
+        n_leaf = 1 << tree.depth
+        pp = None
+        if proposal is not None:
+            th, mu, sd = proposal.get()
+            pp = (th.astype(np.float64), mu.astype(np.float64), sd.astype(np.float64))
+        cb = cpu_baseline(w, X, args.cpu_budget_s, proposal_params=pp, nodes_mix=(n_leaf, tree.num_nodes - 1 - n_leaf))
         cb["e_far_vs_oracle_256_targets"] = oracle_far_check(w, X, q, uf_h)
         out["cpu_baseline"] = cb
     print(json.dumps(out))

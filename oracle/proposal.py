@@ -371,7 +371,7 @@ def skeletonize_learned(X, tree, k: Kernel, tol: float, max_rank: int, num_sampl
 
     Returns (Skeletons, fallback flags per node).
     """
-    from .skeleton import NodeSkeleton, Skeletons, effective_samples
+    from .skeleton import Skeletons, effective_samples
     Xt = np.asarray(X, dtype=np.float64)[tree.perm]
     s = effective_samples(num_samples, max_rank)
     out = Skeletons()
@@ -383,25 +383,32 @@ def skeletonize_learned(X, tree, k: Kernel, tol: float, max_rank: int, num_sampl
                 cols = np.arange(b, e, dtype=np.int64)
             else:
                 cols = np.concatenate([out.nodes[2 * a + 1].skel, out.nodes[2 * a + 2].skel])
-            node = None
-            fell[a] = False
-            if len(cols) > 0:
-                pool = candidate_pool(b, e, tree.N, s, seed, a, pool_factor)
-                geo = column_geometry(Xt[cols], seed, a)
-                scores, _ = mlp_forward(theta, standardize(features(Xt[pool], geo), mu, sd))
-                rows = select_rows(scores, pool, s, seed, a)
-                Kp = kernel_matrix(Xt[rows], Xt[cols], k)
-                idd = interpolative_decomposition(Kp, tol, max_rank)
-                node = NodeSkeleton(cols=cols, rows=rows, rank=idd.rank, piv=idd.piv, skel=cols[idd.skel],
-                                    P=idd.P, rho=idd.rho, gap=idd.gap)
-                if fallback_tol > 0:
-                    hr = heldout_rows(b, e, tree.N, seed, a)
-                    Kh = kernel_matrix(Xt[hr], Xt[cols], k)
-                    if heldout_error(Kh, idd.skel, idd.P) > fallback_tol:
-                        node = None
-                        fell[a] = True
-            if node is None:
-                from .skeleton import skeletonize_node
-                node = skeletonize_node(Xt, tree, a, cols, k, tol, max_rank, s, seed)
-            out.nodes[a] = node
+            out.nodes[a], fell[a] = skeletonize_learned_node(Xt, tree, a, cols, k, tol, max_rank, s, seed, theta,
+                                                             mu, sd, fallback_tol, pool_factor)
     return out, fell
+
+
+def skeletonize_learned_node(Xt, tree, a: int, cols: np.ndarray, k: Kernel, tol: float, max_rank: int, s: int,
+                             seed: int, theta: np.ndarray, mu: np.ndarray, sd: np.ndarray, fallback_tol: float,
+                             pool_factor: int = POOL_FACTOR):
+    """One node of skeletonize_learned (tree-order points Xt, the node's columns given): (NodeSkeleton,
+    whether it fell back to uniform rows)."""
+    from .skeleton import NodeSkeleton, skeletonize_node
+    b, e = int(tree.begin[a]), int(tree.end[a])
+    if len(cols) > 0:
+        pool = candidate_pool(b, e, tree.N, s, seed, a, pool_factor)
+        geo = column_geometry(Xt[cols], seed, a)
+        scores, _ = mlp_forward(theta, standardize(features(Xt[pool], geo), mu, sd))
+        rows = select_rows(scores, pool, s, seed, a)
+        Kp = kernel_matrix(Xt[rows], Xt[cols], k)
+        idd = interpolative_decomposition(Kp, tol, max_rank)
+        node = NodeSkeleton(cols=cols, rows=rows, rank=idd.rank, piv=idd.piv, skel=cols[idd.skel],
+                            P=idd.P, rho=idd.rho, gap=idd.gap)
+        if fallback_tol <= 0:
+            return node, False
+        hr = heldout_rows(b, e, tree.N, seed, a)
+        Kh = kernel_matrix(Xt[hr], Xt[cols], k)
+        if heldout_error(Kh, idd.skel, idd.P) <= fallback_tol:
+            return node, False
+        return skeletonize_node(Xt, tree, a, cols, k, tol, max_rank, s, seed), True
+    return skeletonize_node(Xt, tree, a, cols, k, tol, max_rank, s, seed), False
