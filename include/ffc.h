@@ -264,6 +264,26 @@ ffc_status ffc_interp_decomp(double* A_dev, int32_t batch, int32_t s, int32_t n,
                              int32_t max_rank, int32_t* rank_dev, int32_t* piv_dev,
                              double* P_dev, void* stream);
 
+/* The same decompositions for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): nothing is allocated, freed or synchronized. The QR's exchange
+ * slots, task counter and the solve's diagonal inverses live in a file-scope
+ * device array of FFC_NOALLOC_SCRATCH_BYTES bytes that each GPU holds once
+ * for the life of the process; the call clears what must start at zero. The
+ * QR variant is the one the autotuner picked earlier for the same shape (via
+ * ffc_interp_decomp or a skeletonization), else the first that fits; nothing
+ * is timed. Limits: s <= 512 (the register-resident QR; no streamed fallback)
+ * and the blocks' scratch within the array (about 66 KB per 512 x 512 block,
+ * so up to ~250 such blocks). The call is asynchronous on `stream`: inputs
+ * and outputs must stay valid until the stream passes it. Calls that overlap
+ * on one GPU (other streams, other threads) share the array and race: order
+ * them on one stream. Errors: as ffc_interp_decomp, plus s > 512 or blocks
+ * beyond the scratch -> FFC_ERR_INVALID_ARG (nothing launched). */
+#define FFC_NOALLOC_SCRATCH_BYTES (16u << 20)
+ffc_status ffc_interp_decomp_noalloc(double* A_dev, int32_t batch, int32_t s, int32_t n, double tol,
+                                     int32_t max_rank, int32_t* rank_dev, int32_t* piv_dev, double* P_dev,
+                                     void* stream);
+
 /* Per-node results copied to host (synchronizes). node in [1, num_nodes).
  * rank, n_cols, n_rows are required; cols/rows/skel (tree positions) and P
  * (rank x n_cols, row-major) may be NULL; buffers must hold n_cols, n_rows,
@@ -523,9 +543,10 @@ ffc_status ffc_profile_read(double* ms_host, int64_t* launches_host, int32_t num
 
 void ffc_free_tree(ffc_tree* t);
 void ffc_free_skel(ffc_skel* sk);
-/* Releases the library's process-wide device resources: synchronizes the
- * device, destroys the stage profiler's pooled HIP events and frees the
- * per-device error flags. Call it after the last handle is freed and before
+/* Releases the library's process-wide resources: synchronizes the device and
+ * destroys the stage profiler's pooled HIP events (the device error flag is a
+ * file-scope device word and needs no release). Call it after the last handle
+ * is freed and before
  * the process exits, so that nothing of the library's is torn down by static
  * destructors or runtime teardown (the Python binding calls it at interpreter
  * exit, after freeing its live handles). Later calls of the library remain

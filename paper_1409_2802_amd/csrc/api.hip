@@ -13,7 +13,11 @@ namespace ffc {
 namespace {
 thread_local std::string g_error;
 std::mutex g_flag_mu;
-unsigned int* g_flags[64] = {};
+unsigned int* g_flags[64] = {};   // per device: address of g_device_flag
+// The device error flag word (bit 0: a non-finite kernel value, bit 1: a QR
+// wait timed out). A file-scope device variable, so reading the flag never
+// allocates; each device holds its own copy, zero at load.
+__device__ unsigned int g_device_flag = 0u;
 
 ffc_status fail(ffc_status code, const std::string& msg) {
   set_error(msg);
@@ -106,10 +110,10 @@ unsigned int* device_flag() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
   std::lock_guard<std::mutex> lock(g_flag_mu);
-  if (!g_flags[dev]) {
+  if (!g_flags[dev]) {   // this device's copy of the file-scope word (nothing is allocated)
     unsigned int* p = nullptr;
-    if (hipMalloc(&p, sizeof(unsigned int)) != hipSuccess) return nullptr;
-    if (hipMemset(p, 0, sizeof(unsigned int)) != hipSuccess) return nullptr;
+    if (hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(g_device_flag)) != hipSuccess || !p)
+      return nullptr;
     g_flags[dev] = p;
   }
   return g_flags[dev];
@@ -730,15 +734,6 @@ ffc_status ffc_check_device(void* stream) {
 void ffc_shutdown(void) {
   (void)hipDeviceSynchronize();
   ffc::profiler_release();
-  int cur = 0;
-  const bool have_cur = hipGetDevice(&cur) == hipSuccess;
-  std::lock_guard<std::mutex> lock(g_flag_mu);
-  for (int dev = 0; dev < 64; ++dev) {
-    if (!g_flags[dev]) continue;
-    if (hipSetDevice(dev) == hipSuccess) (void)hipFree(g_flags[dev]);
-    g_flags[dev] = nullptr;
-  }
-  if (have_cur) (void)hipSetDevice(cur);
 }
 
 void ffc_free_tree(ffc_tree* t) {

@@ -670,10 +670,42 @@ int resident_grid(const void* kern, int threads, size_t lds) {
   return nb * cus;
 }
 
+// Scratch of a factorization launch: a growable buffer, or a fixed region
+// that must already be large enough (nothing is allocated then).
+struct QrScratch {
+  DevBuf<unsigned char>* buf = nullptr;
+  unsigned char* fixed = nullptr;
+  size_t fixed_bytes = 0;
+  ffc_status ensure(size_t bytes) {
+    if (buf) return buf->count < bytes ? buf->alloc(bytes) : FFC_OK;
+    if (bytes > fixed_bytes) {
+      set_error("the blocks need " + std::to_string(bytes) + " bytes of QR scratch, above the fixed " +
+                std::to_string(fixed_bytes));
+      return FFC_ERR_INVALID_ARG;
+    }
+    return FFC_OK;
+  }
+  unsigned char* ptr() const { return buf ? buf->ptr : fixed; }
+  size_t bytes() const { return buf ? buf->count : fixed_bytes; }
+};
+
+// Scratch bytes of variant (R, CS, NTC) for the blocks of bt: slots, task
+// offsets and claim counter of the QR, or the solve's diagonal inverses,
+// whichever is larger (the solve reuses the QR's scratch).
+template <int R, int CS, int NTC>
+size_t qr_scratch_bytes(const IdBatch& bt, int batch) {
+  constexpr int CPW = 4 * CS;
+  const int cols_per_wg = CPW * (NTC / 64);
+  const int gmax = std::max(1, (bt.n_max + cols_per_wg - 1) / cols_per_wg);
+  const size_t slot_doubles = (size_t)batch * 2 * gmax * (bt.s_max + 2);
+  return std::max(slot_doubles * sizeof(double) + ((size_t)batch + 2) * sizeof(int32_t),
+                  solve_scratch_bytes(bt, batch));
+}
+
 // The factorization with variant (R, NTC) on the blocks of bt (in place);
 // fits = false (nothing launched) when a block's group cannot be resident.
 template <int R, int CS, int NTC>
-ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hipStream_t st, bool& fits) {
+ffc_status launch_qr(const IdBatch& bt, int batch, QrScratch scratch, hipStream_t st, bool& fits) {
   constexpr int CPW = 4 * CS;   // columns per wavefront
   const int cols_per_wg = CPW * (NTC / 64);
   const int gmax = std::max(1, (bt.n_max + cols_per_wg - 1) / cols_per_wg);
@@ -685,9 +717,7 @@ ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratc
   const size_t slot_doubles = (size_t)batch * 2 * gmax * (bt.s_max + 2);
   // Slots, task offsets, claim counter. The solve that follows reuses the
   // scratch: size it for both up front.
-  const size_t bytes = std::max(slot_doubles * sizeof(double) + ((size_t)batch + 2) * sizeof(int32_t),
-                                solve_scratch_bytes(bt, batch));
-  if (scratch.count < bytes) FFC_TRY(scratch.alloc(bytes));
+  FFC_TRY(scratch.ensure(qr_scratch_bytes<R, CS, NTC>(bt, batch)));
   CoopArgs ca{};
   ca.A = bt.A;
   ca.a_stride = bt.a_stride;
@@ -702,7 +732,7 @@ ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratc
   ca.rank = bt.rank;
   ca.piv = bt.piv;
   ca.piv_stride = bt.piv_stride;
-  ca.slots = reinterpret_cast<double*>(scratch.ptr);
+  ca.slots = reinterpret_cast<double*>(scratch.ptr());
   ca.slot_words = (int64_t)slot_doubles;
   ca.task_start = reinterpret_cast<int32_t*>(ca.slots + slot_doubles);
   ca.mask = bt.mask;
@@ -730,14 +760,14 @@ ffc_status launch_qr(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratc
 // every other column j holds R(0:r, j) in rows 0..r-1. The QR launch sized
 // the scratch for the diagonal block inverses (it is done with it by now:
 // same stream).
-ffc_status launch_solve(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hipStream_t st) {
+ffc_status launch_solve(const IdBatch& bt, int batch, QrScratch scratch, hipStream_t st) {
   const int r_max = solve_rank_bound(bt);
   const int nblk = round_mb(r_max) / MB;
-  if (scratch.count < solve_scratch_bytes(bt, batch)) {
+  if (scratch.bytes() < solve_scratch_bytes(bt, batch)) {
     set_error("QR scratch smaller than the solve needs");
     return FFC_ERR_STATE;
   }
-  double* Dinv = reinterpret_cast<double*>(scratch.ptr);
+  double* Dinv = reinterpret_cast<double*>(scratch.ptr());
   const size_t lds = mfma_solve_lds_bytes(r_max, bt.n_max);
   if (lds > 64 * 1024)
     FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_id_solve_mfma),
@@ -760,18 +790,20 @@ ffc_status launch_solve(const IdBatch& bt, int batch, DevBuf<unsigned char>& scr
 // Disabled by FFC_AUTOTUNE=0 and while the stream is being captured into a
 // graph (then the first valid variant runs).
 // ---------------------------------------------------------------------------
-using QrLaunch = ffc_status (*)(const IdBatch&, int, DevBuf<unsigned char>&, hipStream_t, bool&);
+using QrLaunch = ffc_status (*)(const IdBatch&, int, QrScratch, hipStream_t, bool&);
+using QrBytes = size_t (*)(const IdBatch&, int);
 struct Variant {
   int R, CS, threads;
   QrLaunch fn;
+  QrBytes bytes;
 };
+#define FFC_VARIANT(R, CS, T) {R, CS, T, &launch_qr<R, CS, T>, &qr_scratch_bytes<R, CS, T>}
 const Variant kVariants[] = {
-    {16, 4, 512, &launch_qr<16, 4, 512>}, {16, 4, 256, &launch_qr<16, 4, 256>},
-    {16, 1, 512, &launch_qr<16, 1, 512>}, {32, 2, 512, &launch_qr<32, 2, 512>},
-    {32, 2, 256, &launch_qr<32, 2, 256>}, {32, 1, 512, &launch_qr<32, 1, 512>},
-    {32, 1, 256, &launch_qr<32, 1, 256>}, {32, 1, 128, &launch_qr<32, 1, 128>},
-    {16, 1, 128, &launch_qr<16, 1, 128>},
+    FFC_VARIANT(16, 4, 512), FFC_VARIANT(16, 4, 256), FFC_VARIANT(16, 1, 512), FFC_VARIANT(32, 2, 512),
+    FFC_VARIANT(32, 2, 256), FFC_VARIANT(32, 1, 512), FFC_VARIANT(32, 1, 256), FFC_VARIANT(32, 1, 128),
+    FFC_VARIANT(16, 1, 128),
 };
+#undef FFC_VARIANT
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 struct TuneEntry {
@@ -787,8 +819,8 @@ bool autotune_enabled() {
   return !(e && e[0] == '0');
 }
 
-ffc_status tune(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hipStream_t st,
-                const std::vector<int>& cand, TuneEntry& te) {
+ffc_status tune(const IdBatch& bt, int batch, QrScratch scratch, hipStream_t st, const std::vector<int>& cand,
+                TuneEntry& te) {
   DevBuf<double> copy;
   const size_t words = (size_t)batch * bt.a_stride;
   FFC_TRY(copy.alloc(words));
@@ -836,15 +868,8 @@ ffc_status tune(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hi
 
 }  // namespace
 
-ffc_status launch_interp_decomp_coop(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch, hipStream_t st,
-                                     bool& used) {
-  used = false;
-  if (batch <= 0) return FFC_OK;
-  if (mfma_solve_lds_bytes(solve_rank_bound(bt), bt.n_max) > 150 * 1024) return FFC_OK;
-  std::vector<int> cand;
-  for (int v = 0; v < kNumVariants; ++v)
-    if (bt.s_max <= 16 * kVariants[v].R) cand.push_back(v);
-  if (cand.empty()) return FFC_OK;
+// The autotuner's earlier choice for this shape (or FFC_QR_VARIANT), -1 if none.
+int tuned_choice(const IdBatch& bt, int batch) {
   int choice = -1;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -858,6 +883,21 @@ ffc_status launch_interp_decomp_coop(const IdBatch& bt, int batch, DevBuf<unsign
     const int v = std::atoi(fv);
     if (v >= 0 && v < kNumVariants && bt.s_max <= 16 * kVariants[v].R) choice = v;
   }
+  return choice;
+}
+
+ffc_status launch_interp_decomp_coop(const IdBatch& bt, int batch, DevBuf<unsigned char>& scratch_buf, hipStream_t st,
+                                     bool& used) {
+  QrScratch scratch;
+  scratch.buf = &scratch_buf;
+  used = false;
+  if (batch <= 0) return FFC_OK;
+  if (mfma_solve_lds_bytes(solve_rank_bound(bt), bt.n_max) > 150 * 1024) return FFC_OK;
+  std::vector<int> cand;
+  for (int v = 0; v < kNumVariants; ++v)
+    if (bt.s_max <= 16 * kVariants[v].R) cand.push_back(v);
+  if (cand.empty()) return FFC_OK;
+  int choice = tuned_choice(bt, batch);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   FFC_HIP_TRY(hipStreamIsCapturing(st, &cs));
   if (choice < 0 && cand.size() > 1 && autotune_enabled() && cs == hipStreamCaptureStatusNone) {
@@ -884,6 +924,32 @@ ffc_status launch_interp_decomp_coop(const IdBatch& bt, int batch, DevBuf<unsign
     }
   }
   return FFC_OK;
+}
+
+ffc_status launch_interp_decomp_fixed(const IdBatch& bt, int batch, unsigned char* fixed, size_t fixed_bytes,
+                                      hipStream_t st) {
+  if (batch <= 0) return FFC_OK;
+  if (mfma_solve_lds_bytes(solve_rank_bound(bt), bt.n_max) > 150 * 1024) {
+    set_error("the interpolation solve of these blocks does not fit in LDS");
+    return FFC_ERR_INVALID_ARG;
+  }
+  const int choice = tuned_choice(bt, batch);
+  std::vector<int> order;
+  if (choice >= 0) order.push_back(choice);
+  for (int v = 0; v < kNumVariants; ++v)
+    if (v != choice && bt.s_max <= 16 * kVariants[v].R) order.push_back(v);
+  QrScratch scratch;
+  scratch.fixed = fixed;
+  scratch.fixed_bytes = fixed_bytes;
+  for (int v : order) {
+    if (kVariants[v].bytes(bt, batch) > fixed_bytes) continue;
+    bool fits = false;
+    FFC_TRY(kVariants[v].fn(bt, batch, scratch, st, fits));
+    if (fits) return launch_solve(bt, batch, scratch, st);
+  }
+  set_error("no register-resident QR variant holds these blocks within the fixed scratch (rows above 512, or "
+            "too many blocks)");
+  return FFC_ERR_INVALID_ARG;
 }
 
 int autotune_entries(int32_t* out, int cap) {

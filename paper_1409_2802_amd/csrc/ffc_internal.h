@@ -361,6 +361,12 @@ ffc_status launch_interp_decomp(const IdBatch& b, int batch, hipStream_t st);
 int autotune_entries(int32_t* out, int cap);
 ffc_status launch_interp_decomp_coop(const IdBatch& b, int batch, DevBuf<unsigned char>& scratch, hipStream_t st,
                                      bool& used);
+// The same without any allocation: the QR's slots and the solve's scratch
+// come from `fixed` (fixed_bytes long), the variant is the autotuner's earlier
+// choice for this shape or else the first that fits, and nothing is timed.
+// FFC_ERR_INVALID_ARG when no variant fits s_max or the scratch is too small.
+ffc_status launch_interp_decomp_fixed(const IdBatch& b, int batch, unsigned char* fixed, size_t fixed_bytes,
+                                      hipStream_t st);
 
 // Skeleton ids from pivots: skel[node][i] = cols[node][piv[node][i]] (cpqr.hip).
 ffc_status launch_skeleton_ids(ffc_skel* sk, int first, int count, hipStream_t st,

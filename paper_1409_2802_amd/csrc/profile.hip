@@ -1,15 +1,39 @@
 // Stage profiler: optional HIP events around every stage launch, recorded on
-// the stream the stage runs on, accumulated per stage on read. Every stage is
-// also a roctx range ("ffc:<stage>"), which rocprofv3 --marker-trace records
-// beside the kernel trace.
-#include <mutex>
+// the stream the stage runs on, accumulated per stage on read. With FFC_ROCTX=1
+// in the environment every stage is also a roctx range ("ffc:<stage>"), which
+// rocprofv3 --marker-trace records beside the kernel trace; the roctx runtime
+// is then loaded on first use (the library does not link it otherwise).
+#include <dlfcn.h>
 
-#include <rocprofiler-sdk-roctx/roctx.h>
+#include <cstdlib>
+#include <mutex>
 
 #include "ffc_internal.h"
 
 namespace ffc {
 namespace {
+
+using PushFn = int (*)(const char*);
+using PopFn = int (*)();
+struct Roctx {
+  PushFn push = nullptr;
+  PopFn pop = nullptr;
+};
+
+const Roctx& roctx() {
+  static const Roctx r = [] {
+    Roctx out;
+    const char* e = std::getenv("FFC_ROCTX");
+    if (!e || e[0] != '1') return out;
+    void* h = dlopen("librocprofiler-sdk-roctx.so", RTLD_NOW | RTLD_GLOBAL);
+    if (!h) return out;
+    out.push = reinterpret_cast<PushFn>(dlsym(h, "roctxRangePushA"));
+    out.pop = reinterpret_cast<PopFn>(dlsym(h, "roctxRangePop"));
+    if (!out.push || !out.pop) out = Roctx{};
+    return out;
+  }();
+  return r;
+}
 
 struct Pending {
   int stage;
@@ -59,7 +83,7 @@ const char* const kStageRanges[FFC_NUM_STAGES] = {
     "ffc:evaluate", "ffc:direct", "ffc:solve", "ffc:proposal", "ffc:heldout", "ffc:labels", "ffc:train"};
 
 StageTimer::StageTimer(int stage, hipStream_t st) : stage_(stage), st_(st) {
-  roctxRangePushA(kStageRanges[stage]);
+  if (roctx().push) roctx().push(kStageRanges[stage]);
   if (!g_on) return;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(st_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;   // not inside graphs
@@ -70,7 +94,7 @@ StageTimer::StageTimer(int stage, hipStream_t st) : stage_(stage), st_(st) {
 }
 
 StageTimer::~StageTimer() {
-  roctxRangePop();
+  if (roctx().pop) roctx().pop();
   if (!active_) return;
   (void)hipEventRecord(stop_, st_);
   std::lock_guard<std::mutex> lock(g_mu);

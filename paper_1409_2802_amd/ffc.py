@@ -36,7 +36,7 @@ EXPORTS = [
     "ffc_leverage_labels", "ffc_proposal_train", "ffc_proposal_training_set",
     "ffc_step_graph_create", "ffc_step_graph_create_fmm", "ffc_graph_launch", "ffc_graph_free", "ffc_autotune_report",
     "ffc_skel_load", "ffc_proposal_get_adam", "ffc_proposal_set_adam", "ffc_shutdown",
-    "ffc_proposal_save", "ffc_proposal_load", "ffc_pivoted_leverage_labels",
+    "ffc_proposal_save", "ffc_proposal_load", "ffc_pivoted_leverage_labels", "ffc_interp_decomp_noalloc",
 ]
 
 NPARAM = 5313
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "ffc_direct_sum": [P, I64, P, I64, I32, ctypes.POINTER(KernelC), P, P, I32, P],
         "ffc_sampled_block": [P, ctypes.POINTER(KernelC), I32, P, I32, P, I32, P, P],
         "ffc_interp_decomp": [P, I32, I32, I32, D, I32, P, P, P, P],
+        "ffc_interp_decomp_noalloc": [P, I32, I32, I32, D, I32, P, P, P, P],
         "ffc_skel_node": [P, I32, P, P, P, P, P, P, P],
         "ffc_skel_stats": [P, ctypes.POINTER(StatsC)],
         "ffc_skel_load": [P, ctypes.POINTER(SkelOptsC), P, P, P, P, I32, I32, P, PP],
