@@ -17,18 +17,19 @@
 #include <climits>
 
 #include "ffc_internal.h"
+#include "feature_rows.h"
 #include "tile_engine.h"
 
 namespace ffc {
 namespace {
 
-constexpr int NF = 16, NH = 64;
+constexpr int NF = feat::kNF, NH = 64;
 constexpr int NPARAM = NF * NH + NH + NH * NH + NH + NH + 1;   // 5313
 constexpr int OFF_W1 = 0, OFF_B1 = NF * NH, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH,
               OFF_B3 = OFF_W3 + NH;
-constexpr int SUB = 256;         // column subsample size
+constexpr int SUB = feat::kSub;  // column subsample size
 constexpr int kMaxGeomCols = 16384;   // column-set bitmap capacity (512 words of LDS)
-constexpr int NANCH = 7;
+constexpr int NANCH = feat::kNAnch;
 constexpr uint64_t STREAM_SUBSAMPLE = 1ull << 30, STREAM_KEYS = 3ull << 30;
 
 __device__ inline uint64_t splitmix_first(uint64_t state) {
@@ -56,13 +57,36 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
   const int32_t* cols = ga.cols + (int64_t)b * ga.col_stride;
   double* cen = ga.cen + (int64_t)b * d;
   const uint64_t node = (uint64_t)ga.node_ids[b];
-  // Centroid (each thread owns dimensions; fixed summation order).
-  for (int k = tid; k < d; k += 256) {
-    double s = 0.0;
-    for (int j = 0; j < n; ++j) s += Xt[(int64_t)cols[j] * d + k];
-    cen[k] = n > 0 ? s / n : 0.0;
+  // Centroid: dimension k is summed in P interleaved column parts (part p
+  // takes columns p, p + P, ...), each with two alternating accumulators, and
+  // the parts are added in order (a fixed summation order).
+  {
+    const int P = d >= 256 ? 1 : min(16, 256 / d);
+    for (int e = tid; e < d * P; e += 256) {
+      const int k = e % d, part = e / d;
+      double s0 = 0.0, s1 = 0.0;
+      int j = part;
+      for (; j + P < n; j += 2 * P) {
+        s0 += Xt[(int64_t)cols[j] * d + k];
+        s1 += Xt[(int64_t)cols[j + P] * d + k];
+      }
+      if (j < n) s0 += Xt[(int64_t)cols[j] * d + k];
+      if (P == 1) {
+        cen[k] = n > 0 ? (s0 + s1) / n : 0.0;
+      } else {
+        red[e] = s0 + s1;
+      }
+    }
+    __syncthreads();
+    if (P > 1) {
+      for (int k = tid; k < d; k += 256) {
+        double s = 0.0;
+        for (int part = 0; part < P; ++part) s += red[part * d + k];
+        cen[k] = n > 0 ? s / n : 0.0;
+      }
+      __syncthreads();
+    }
   }
-  __syncthreads();
   // Radius.
   double mx = 0.0;
   for (int j = tid; j < n; j += 256) {
@@ -121,13 +145,36 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
   }
   __syncthreads();
   const int na = min(NANCH, ns);
+  __shared__ double wbv[4];
+  __shared__ int wbi[4];
   for (int a = 0; a < na; ++a) {
+    // Arg-max of the key over the subsample, ties to the smaller index: per
+    // wavefront by shuffles, then over the four wavefronts.
+    const double* key = a == 0 ? sd2 : mind;
+    double bv = tid < ns ? key[tid] : -INFINITY;
+    int bi = tid < ns ? tid : INT_MAX;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if ((tid & 63) == 0) {
+      wbv[tid >> 6] = bv;
+      wbi[tid >> 6] = bi;
+    }
+    __syncthreads();
     if (tid == 0) {
-      const double* key = a == 0 ? sd2 : mind;
-      int best = 0;
-      for (int q = 1; q < ns; ++q)
-        if (key[q] > key[best]) best = q;
-      anchors[a] = best;
+      double v = wbv[0];
+      int i = wbi[0];
+      for (int q = 1; q < 4; ++q)
+        if (wbv[q] > v || (wbv[q] == v && wbi[q] < i)) {
+          v = wbv[q];
+          i = wbi[q];
+        }
+      anchors[a] = i;
     }
     __syncthreads();
     if (tid < ns) {
@@ -160,13 +207,7 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
 // its 4 rows over its columns, merged across the 16 threads of a row in a
 // fixed order (lanes 16 apart by shuffles, then the 4 waves through LDS).
 // ---------------------------------------------------------------------------
-__device__ inline void insert4(double (&b)[4], double v) {   // keep the 4 smallest, ascending
-  if (!(v < b[3])) return;
-  b[3] = v;
-#pragma unroll
-  for (int a = 3; a > 0; --a)
-    if (b[a] < b[a - 1]) { const double t = b[a]; b[a] = b[a - 1]; b[a - 1] = t; }
-}
+using feat::insert4;
 
 __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt, int d, GeomArgs ga,
                                                   const int32_t* __restrict__ tgt, int tgt_stride,
@@ -228,46 +269,9 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
       r[4] = sum[i];
     }
   }
-  // The centroid distance and the anchor projections of every row: 64 rows x
-  // (1 + NANCH) dot products over d, spread over all threads (each one a
-  // sequential sum, so the values do not depend on the spreading).
   double* dots = red + 4 * 64 * 5;   // [64 rows][1 + NANCH]
-  const double* c = ga.cen + (int64_t)b * d;
-  const double* U = ga.U + (int64_t)b * NANCH * d;
-  for (int task = tid; task < 64 * (1 + NANCH); task += 256) {
-    const int row = task / (1 + NANCH), a = task % (1 + NANCH);
-    if (t0 + row >= nt) continue;
-    const double* y = Xt + (int64_t)tg[row] * d;
-    double p = 0.0;
-    if (a == 0) {
-      for (int k = 0; k < d; ++k) { const double df = y[k] - c[k]; p = fma(df, df, p); }
-    } else {
-      const double* u = U + (int64_t)(a - 1) * d;
-      for (int k = 0; k < d; ++k) p = fma(y[k] - c[k], u[k], p);
-    }
-    dots[row * (1 + NANCH) + a] = p;
-  }
   __syncthreads();
-  if (tid >= 64) return;
-  const int row = tid;
-  if (t0 + row >= nt) return;
-  double b4[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
-  double tot = 0.0;
-  for (int q = 0; q < 4; ++q) {
-    const double* r = red + ((int64_t)q * 64 + row) * 5;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) insert4(b4, r[u]);
-    tot += r[4];
-  }
-  const double dc = sqrt(dots[row * (1 + NANCH)]) / rho;
-  float* f = feat + (int64_t)b * feat_stride + (int64_t)(t0 + row) * NF;
-  f[0] = (float)dc;
-  f[1] = (float)log(dc + 1e-12);
-  for (int q = 0; q < 4; ++q) f[2 + q] = (float)(q < ns ? b4[q] : b4[max(ns - 1, 0)]);
-  f[6] = (float)(ns > 0 ? tot / ns : 0.0);
-  f[7] = (float)log(b4[0] + 1e-12);
-  for (int a = 0; a < NANCH; ++a) f[8 + a] = (float)(dots[row * (1 + NANCH) + 1 + a] / rho);
-  f[15] = 1.0f;
+  feat::finish_rows(Xt, d, ga, b, tg, t0, nt, ns, rho, red, 4, dots, feat, feat_stride);
 }
 
 // ---------------------------------------------------------------------------
