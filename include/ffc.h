@@ -60,11 +60,16 @@ typedef struct {
  * kernel function). The QR, the interpolation solve and the charges are always
  * float64. FFC_MIXED_BF16X3 splits coordinates into bfloat16 hi + lo parts and
  * forms the Gram products hi*hi + hi*lo + lo*hi on matrix cores with float32
- * accumulation (Gaussian and polynomial kernels; the Laplace kernel is always
- * evaluated from explicit float32 differences in that mode). For the Gaussian,
+ * accumulation (Gaussian and polynomial kernels). The Laplace kernel's power
+ * (d - 2) / 2 amplifies errors of r^2, so its sampled blocks and evaluation
+ * split into three bf16 parts (six products, about float32 precision), take
+ * r^2 of pairs much closer to each other than to the tile's centre from
+ * explicit float32 differences, and form the power in float64; its direct sum
+ * uses float32 differences. For the Gaussian,
  * coordinates are centred on each tile's node (or target leaf) before the
  * split unless every leaf of the tree lies within four of its radii of the
- * origin. The first mixed-precision call on a tree prepares these operands
+ * origin; the Laplace kernel always centres. The first mixed-precision call
+ * on a tree prepares these operands
  * (4 N dp bytes of device memory kept with the tree, 8 N dp with per-tile
  * centring; dp = d rounded up to a multiple of 32) and cannot be made while
  * the stream is captured (FFC_ERR_STATE). */

@@ -326,6 +326,226 @@ __device__ void mixed_tile_cached(const float* __restrict__ P, const float* __re
   }
 }
 
+// ---------------------------------------------------------------------------
+// The Laplace kernel r^(2-d) on matrix cores. Its power turns a relative error
+// e of r^2 into (d - 2) / 2 times e (31 e at d = 64), so its Gram products take
+// three bf16 parts per coordinate, hi + mid + lo (the float32 value to about
+// 2^-27), and the six products hh, hm, mh, hl, lh, mm (the others lie below
+// float32 rounding), and a pair close enough for the Gram form to cancel
+// takes explicit differences (laplace_value). Coordinates come from the
+// float32 frame (points less the root centroid) and are centred on the tile's
+// node; r^2 = |y - c|^2 + |x - c|^2 - 2 (y - c).(x - c) in float32 and the
+// power in float64 (r^-62 spans more than float32's range). A pair of the same
+// tree position, or with r^2 <= 0, contributes 0.
+// ---------------------------------------------------------------------------
+struct __attribute__((aligned(16))) LapSmem {
+  __bf16 xh[TN][LROW], xm[TN][LROW], xl[TN][LROW];   // column points (A operand)
+  __bf16 yh[TM][LROW], ym[TM][LROW], yl[TM][LROW];   // row points (B operand)
+  float xn[TN], yn[TM];                               // squared norms of the centred points
+};
+
+__device__ inline void split8x3(const float4& a, const float4& b, const float4& ca, const float4& cb, uint4& hi,
+                                uint4& mi, uint4& lo, float& nsum) {
+  const float z[8] = {a.x - ca.x, a.y - ca.y, a.z - ca.z, a.w - ca.w, b.x - cb.x, b.y - cb.y, b.z - cb.z, b.w - cb.w};
+  __bf16 h[8], m[8], l[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    h[i] = (__bf16)z[i];
+    const float r1 = z[i] - (float)h[i];   // exact
+    m[i] = (__bf16)r1;
+    l[i] = (__bf16)(r1 - (float)m[i]);
+    nsum = fmaf(z[i], z[i], nsum);
+  }
+  hi = *reinterpret_cast<const uint4*>(h);
+  mi = *reinterpret_cast<const uint4*>(m);
+  lo = *reinterpret_cast<const uint4*>(l);
+}
+
+// Gram tile of centred points from the float32 frame (the layout of
+// mixed_tile_cached; norms always), three-part split, six products.
+__device__ void laplace_tile(const float* __restrict__ P, const float* __restrict__ cen, int dp, Idx rows, int nrows,
+                             Idx cols, int ncols, LapSmem& sm, f32x4 (&acc)[2][2]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int p = tid >> 2, part = (tid & 3) * 8;
+  const int64_t yrow = p < nrows ? rows(p) : -1;
+  const int64_t xrow = p < ncols ? cols(p) : -1;
+  const float4 zero{0.f, 0.f, 0.f, 0.f};
+  float4 y0, y1, x0, x1, c0, c1;
+  auto fetch = [&](int k0) {
+    const float4* yp = reinterpret_cast<const float4*>(P + yrow * dp + k0 + part);
+    const float4* xp = reinterpret_cast<const float4*>(P + xrow * dp + k0 + part);
+    const float4* cp = reinterpret_cast<const float4*>(cen + k0 + part);
+    y0 = yrow >= 0 ? yp[0] : zero;
+    y1 = yrow >= 0 ? yp[1] : zero;
+    x0 = xrow >= 0 ? xp[0] : zero;
+    x1 = xrow >= 0 ? xp[1] : zero;
+    c0 = cp[0];
+    c1 = cp[1];
+  };
+  float yn = 0.f, xn = 0.f;
+  fetch(0);
+  for (int k0 = 0; k0 < dp; k0 += KCH) {
+    uint4 h, m, l;
+    split8x3(y0, y1, yrow >= 0 ? c0 : zero, yrow >= 0 ? c1 : zero, h, m, l, yn);
+    *reinterpret_cast<uint4*>(&sm.yh[p][part]) = h;
+    *reinterpret_cast<uint4*>(&sm.ym[p][part]) = m;
+    *reinterpret_cast<uint4*>(&sm.yl[p][part]) = l;
+    split8x3(x0, x1, xrow >= 0 ? c0 : zero, xrow >= 0 ? c1 : zero, h, m, l, xn);
+    *reinterpret_cast<uint4*>(&sm.xh[p][part]) = h;
+    *reinterpret_cast<uint4*>(&sm.xm[p][part]) = m;
+    *reinterpret_cast<uint4*>(&sm.xl[p][part]) = l;
+    __syncthreads();
+    if (k0 + KCH < dp) fetch(k0 + KCH);
+    const int kofs = (lane >> 4) * 8;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const int xr = (w >> 1) * 32 + bi * 16 + (lane & 15);
+      const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sm.xh[xr][kofs]);
+      const bf16x8 am = *reinterpret_cast<const bf16x8*>(&sm.xm[xr][kofs]);
+      const bf16x8 al = *reinterpret_cast<const bf16x8*>(&sm.xl[xr][kofs]);
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+        const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&sm.yh[yr][kofs]);
+        const bf16x8 bm = *reinterpret_cast<const bf16x8*>(&sm.ym[yr][kofs]);
+        const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&sm.yl[yr][kofs]);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[bi][bj], 0, 0, 0);
+        acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc[bi][bj], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  yn += __shfl_xor(yn, 1, 64);
+  xn += __shfl_xor(xn, 1, 64);
+  yn += __shfl_xor(yn, 2, 64);
+  xn += __shfl_xor(xn, 2, 64);
+  if ((tid & 3) == 0) {
+    sm.yn[p] = yn;
+    sm.xn[p] = xn;
+  }
+  __syncthreads();
+}
+
+// r^(2-d) = (1 / r^2)^((d - 2) / 2): an integer power by squaring, times
+// sqrt(1 / r^2) for odd d; 0 for r^2 <= 0. The Gram form of r^2 loses
+// about 2^-22 (|y - c|^2 + |x - c|^2) to cancellation, so a pair with r^2
+// below 1/16 of that sum (rare: points much closer to each other than to the
+// centre) takes r^2 from explicit float32 differences of its two points
+// instead, which keeps every pair within about 2^-18 relative on r^2.
+__device__ inline float exact_r2(const float* __restrict__ px, int dp, int64_t a, int64_t b) {
+  const float4* pa = reinterpret_cast<const float4*>(px + a * dp);
+  const float4* pb = reinterpret_cast<const float4*>(px + b * dp);
+  float s = 0.f;
+  for (int k = 0; k < dp / 4; ++k) {
+    const float4 x = pa[k], y = pb[k];
+    const float d0 = x.x - y.x, d1 = x.y - y.y, d2 = x.z - y.z, d3 = x.w - y.w;
+    s = fmaf(d0, d0, s);
+    s = fmaf(d1, d1, s);
+    s = fmaf(d2, d2, s);
+    s = fmaf(d3, d3, s);
+  }
+  return s;
+}
+
+__device__ inline double laplace_value(float g, float yn, float xn, int d, const float* __restrict__ px, int dp,
+                                       int64_t prow, int64_t pcol) {
+  float r2 = yn + xn - 2.f * g;
+  if (r2 < 0.0625f * (yn + xn)) r2 = exact_r2(px, dp, prow, pcol);
+  if (!(r2 > 0.f)) return 0.0;
+  const double x = 1.0 / (double)r2;
+  double p = 1.0, b = x;
+  for (int e = (d - 2) >> 1; e; e >>= 1) {
+    if (e & 1) p *= b;
+    b *= b;
+  }
+  return (d & 1) ? p * sqrt(x) : p;
+}
+
+// Sampled blocks of a level, Laplace kernel (centred on the node's centroid).
+__global__ void __launch_bounds__(NTH) k_level_kblock_laplace(int d, int first, int tiles_m, int tiles_n,
+                                                              const int32_t* __restrict__ rows,
+                                                              const int32_t* __restrict__ nrows_a, int s_cap,
+                                                              const int32_t* __restrict__ cols,
+                                                              const int32_t* __restrict__ ncols_a, int n_cap,
+                                                              const unsigned char* __restrict__ mask,
+                                                              const float* __restrict__ px,
+                                                              const float* __restrict__ cc, int dp,
+                                                              double* __restrict__ A, unsigned int* flag) {
+  __shared__ LapSmem sm;
+  const int tiles = tiles_m * tiles_n;
+  const int ln = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+  const int node = first + ln;
+  if (mask && !mask[node]) return;
+  const int s = nrows_a[node], n = ncols_a[node];
+  const int r0 = (tile % tiles_m) * TM, c0 = (tile / tiles_m) * TN;
+  if (r0 >= s || c0 >= n) return;
+  const int32_t* rp = rows + (int64_t)node * s_cap + r0;
+  const int32_t* cp = cols + (int64_t)node * n_cap + c0;
+  f32x4 acc[2][2];
+  laplace_tile(px, cc + (int64_t)node * dp, dp, Idx{rp, 0}, min(TM, s - r0), Idx{cp, 0}, min(TN, n - c0), sm, acc);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* out = A + (int64_t)ln * s_cap * n_cap;
+  bool bad = false;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int xc = (w >> 1) * 32 + bi * 16 + (lane >> 4) * 4 + e;
+        if (r0 + yr < s && c0 + xc < n) {
+          const double v = rp[yr] == cp[xc] ? 0.0
+                                             : laplace_value(acc[bi][bj][e], sm.yn[yr], sm.xn[xc], d, px, dp, rp[yr],
+                                                             cp[xc]);
+          bad |= !isfinite(v);
+          out[(int64_t)(c0 + xc) * s_cap + (r0 + yr)] = v;
+        }
+      }
+    }
+  if (bad) atomicOr(flag, 1u);
+}
+
+// part[bj] += sum_x K(y, x) q_x for the row point (w & 1) * 32 + bj * 16 + l % 16
+// (row positions rbase + i, columns cols(j)), Laplace kernel, centred on cen.
+__device__ inline void laplace_sum(const float* __restrict__ px, const float* __restrict__ cen, int dp, int d,
+                                   int64_t rbase, int nrows, Idx cols, int ncols, const double* __restrict__ q,
+                                   LapSmem& sm, double (&part)[2], bool& bad) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < ncols; c0 += TN) {
+    Idx cm{cols.idx ? cols.idx + c0 : nullptr, cols.base + c0};
+    f32x4 acc[2][2];
+    laplace_tile(px, cen, dp, Idx{nullptr, rbase}, nrows, cm, min(TN, ncols - c0), sm, acc);
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+      double s = 0.0;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int xc = (w >> 1) * 32 + bi * 16 + (lane >> 4) * 4 + e;
+          if (c0 + xc < ncols) {
+            const int64_t pr = rbase + yr, pc = cm(xc);
+            const double v = pr == pc ? 0.0 : laplace_value(acc[bi][bj][e], sm.yn[yr], sm.xn[xc], d, px, dp, pr, pc);
+            bad |= !isfinite(v);
+            s = fma(v, q[c0 + xc], s);
+          }
+        }
+      part[bj] += s;
+    }
+    __syncthreads();   // norms in LDS are rewritten by the next tile
+  }
+}
+
 // Operands of the tree's points for the matrix-core tiles: pre-split in the
 // origin frame (hi, lo, with norms for the Gaussian), or in float32 with the
 // centre table for tiles that centre while staging; all null: stage from
@@ -511,6 +731,52 @@ __global__ void __launch_bounds__(NTH) k_evaluate_mixed(const double* __restrict
   if (bad) atomicOr(flag, 1u);
 }
 
+// Far + near field of the Laplace kernel for one 64-target tile of a leaf
+// (the layout of k_evaluate_mixed), every tile centred on the target leaf.
+__global__ void __launch_bounds__(NTH) k_evaluate_laplace(int d, int depth, const int32_t* __restrict__ tile_leaf,
+                                                          const int32_t* __restrict__ tile_start,
+                                                          const int32_t* __restrict__ nb,
+                                                          const int32_t* __restrict__ ne,
+                                                          const double* __restrict__ q_tree,
+                                                          const int32_t* __restrict__ rank,
+                                                          const int32_t* __restrict__ skel, int r_cap,
+                                                          const double* __restrict__ qt,
+                                                          const int32_t* __restrict__ perm,
+                                                          const float* __restrict__ px, const float* __restrict__ cc,
+                                                          int dp, double* __restrict__ u, double* __restrict__ u_far,
+                                                          unsigned int* flag) {
+  __shared__ LapSmem sm;
+  __shared__ double red[8 * 64];
+  __shared__ double far_sum[TM], near_sum[TM];
+  const int leaf = tile_leaf[blockIdx.x];
+  const int start = tile_start[blockIdx.x];
+  const int nrows = min(TM, ne[leaf] - start);
+  const float* cen = cc + (int64_t)leaf * dp;
+  bool bad = false;
+  double part[2] = {0.0, 0.0};
+  int a = leaf;
+  for (int lev = depth; lev >= 1; --lev) {
+    const int sib = (a & 1) ? a + 1 : a - 1;
+    const int r = rank[sib];
+    if (r > 0)
+      laplace_sum(px, cen, dp, d, start, nrows, Idx{skel + (int64_t)sib * r_cap, 0}, r, qt + (int64_t)sib * r_cap, sm,
+                  part, bad);
+    a = (a - 1) >> 1;
+  }
+  mixed_reduce(part, red, far_sum);
+  double npart[2] = {0.0, 0.0};
+  const int lb = nb[leaf];
+  laplace_sum(px, cen, dp, d, start, nrows, Idx{nullptr, lb}, ne[leaf] - lb, q_tree + lb, sm, npart, bad);
+  mixed_reduce(npart, red, near_sum);
+  if (threadIdx.x < nrows) {
+    const int ci = perm[start + threadIdx.x];
+    const double f = far_sum[threadIdx.x];
+    u[ci] = f + near_sum[threadIdx.x];
+    if (u_far) u_far[ci] = f;
+  }
+  if (bad) atomicOr(flag, 1u);
+}
+
 template <bool DOT>
 __global__ void __launch_bounds__(NTH) k_direct_mixed(const double* __restrict__ Y, int64_t m,
                                                       const double* __restrict__ X, int64_t n, int d, KParams kp,
@@ -564,10 +830,34 @@ ffc_status gaussian_frame_ok(const ffc_tree* t, hipStream_t st, bool& ok) {
 // must find them made).
 ffc_status tree_split(const ffc_tree* t, const KParams& kp, hipStream_t st, Split& sp) {
   sp = Split{};
-  if (kp.kind == FFC_LAPLACE) return FFC_OK;
   ffc_tree* tm = const_cast<ffc_tree*>(t);
   const int dp = (t->d + KCH - 1) / KCH * KCH;
   const size_t n = (size_t)t->N * dp, nc = (size_t)(t->num_nodes + 1) * dp;
+  if (kp.kind == FFC_LAPLACE) {
+    // The float32 frame only (every Laplace tile centres while staging).
+    if (tm->bf_x.count != n || tm->bf_cc.count != nc) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      FFC_HIP_TRY(hipStreamIsCapturing(st, &cs));
+      if (cs != hipStreamCaptureStatusNone) {
+        set_error("mixed precision: skeletonize or evaluate once in mixed precision with this kernel function on "
+                  "this tree before capturing (the matrix-core operands are prepared then)");
+        return FFC_ERR_STATE;
+      }
+      FFC_TRY(tm->bf_x.alloc(n));
+      FFC_TRY(tm->bf_cc.alloc(nc));
+      hipLaunchKernelGGL(k_offset_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, t->Xt.ptr, t->N, t->d,
+                         dp, t->centroid.ptr, tm->bf_x.ptr);
+      FFC_LAUNCH_CHECK("k_offset_points");
+      hipLaunchKernelGGL(k_offset_centres, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, t->centroid.ptr,
+                         t->num_nodes, t->d, dp, tm->bf_cc.ptr);
+      FFC_LAUNCH_CHECK("k_offset_centres");
+    }
+    sp.x = t->bf_x.ptr;
+    sp.cc = t->bf_cc.ptr;
+    sp.origin = t->num_nodes;
+    sp.dp = dp;
+    return FFC_OK;
+  }
   const bool make = tm->bf_dp != dp || tm->bf_hi.count != n;
   if (make || (kp.kind == FFC_GAUSSIAN && tm->bf_frame < 0)) {
     // Made once, eagerly: a captured graph would only make them when replayed.
@@ -631,6 +921,12 @@ ffc_status launch_kblock_batch_mixed(const ffc_tree* t, const KParams& kp, const
   if (blocks == 0) return FFC_OK;
   Split sp;
   FFC_TRY(tree_split(t, kp, st, sp));
+  if (kp.kind == FFC_LAPLACE) {
+    hipLaunchKernelGGL(k_level_kblock_laplace, dim3((unsigned)blocks), dim3(NTH), 0, st, t->d, first, tiles_m, tiles_n,
+                       rows, nrows, s_cap, cols, ncols, n_cap, mask, sp.x, sp.cc, sp.dp, A, device_flag());
+    FFC_LAUNCH_CHECK("k_level_kblock_laplace");
+    return FFC_OK;
+  }
   if (kp.kind == FFC_POLYNOMIAL)
     hipLaunchKernelGGL(k_level_kblock_mixed<true>, dim3((unsigned)blocks), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
                        first, tiles_m, tiles_n, rows, nrows, s_cap, cols, ncols, n_cap, centroid, mask, sp, A,
@@ -647,6 +943,14 @@ ffc_status launch_evaluate_mixed(const ffc_tree* t, const ffc_skel* sk, const KP
                                  hipStream_t st) {
   Split sp;
   FFC_TRY(tree_split(t, kp, st, sp));
+  if (kp.kind == FFC_LAPLACE) {
+    hipLaunchKernelGGL(k_evaluate_laplace, dim3((unsigned)t->num_tiles), dim3(NTH), 0, st, t->d, t->depth,
+                       t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr, sk->rank.ptr,
+                       sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->perm.ptr, sp.x, sp.cc, sp.dp, u, u_far,
+                       device_flag());
+    FFC_LAUNCH_CHECK("k_evaluate_laplace");
+    return FFC_OK;
+  }
   if (kp.kind == FFC_POLYNOMIAL)
     hipLaunchKernelGGL(k_evaluate_mixed<true>, dim3((unsigned)t->num_tiles), dim3(NTH), 0, st, t->Xt.ptr, t->d, kp,
                        t->depth, t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr,

@@ -17,9 +17,10 @@
 //   * kernel sums u_i = sum_j K(y_i, x_j) q_j (Section 1, eq. e:sum; eq. e:id
 //     with the skeleton points and equivalent charges), reduced across the
 //     16 threads sharing a row in a fixed order, so results are deterministic.
-// Precision: FP64 tiles in double; FP32 tiles (and the Laplace kernel in the
-// mixed mode) in float with the Laplace power taken in double; the mixed mode
-// of the Gaussian and polynomial kernels runs on matrix cores (gram_mfma.hip).
+// Precision: FP64 tiles in double; FP32 tiles (and the direct sum of the
+// Laplace kernel in the mixed mode) in float with the Laplace power taken in
+// double; the mixed mode of the sampled blocks and the evaluation runs on
+// matrix cores for every kernel function (gram_mfma.hip).
 #include "ffc_internal.h"
 #include "tile_engine.h"
 #include "tile_sums.h"
@@ -350,7 +351,7 @@ ffc_status launch_kblock_batch(const ffc_tree* t, const KParams& kp, int precisi
                                const int32_t* nrows, int s_cap, const int32_t* cols, const int32_t* ncols, int n_cap,
                                int first, int count, const double* centroid, double* A, hipStream_t st,
                                const unsigned char* mask) {
-  if (precision == FFC_MIXED_BF16X3 && kp.kind != FFC_LAPLACE)
+  if (precision == FFC_MIXED_BF16X3)
     return launch_kblock_batch_mixed(t, kp, rows, nrows, s_cap, cols, ncols, n_cap, first, count, centroid, A, st,
                                      mask);
   const int tiles_m = (s_cap + BM - 1) / BM, tiles_n = (n_cap + BN - 1) / BN;
@@ -417,7 +418,7 @@ ffc_status launch_sampled_block(const ffc_tree* t, const KParams& kp, int precis
 
 ffc_status launch_evaluate(const ffc_tree* t, const ffc_skel* sk, const KParams& kp, int precision, double* u,
                            double* u_far, hipStream_t st) {
-  if (precision == FFC_MIXED_BF16X3 && kp.kind != FFC_LAPLACE) return launch_evaluate_mixed(t, sk, kp, u, u_far, st);
+  if (precision == FFC_MIXED_BF16X3) return launch_evaluate_mixed(t, sk, kp, u, u_far, st);
   return dispatch(precision, kp, [&](auto tv, auto kv) -> ffc_status {
     using T = decltype(tv);
     constexpr int KF = decltype(kv)::value;

@@ -91,3 +91,32 @@ def test_mixed_far_field_within_1e4_of_fp64_oracle(ffc, name, make, kind, kw, le
     assert errs[ffc.FP64] < 1e-5        # the method is accurate on this configuration
     assert errs[ffc.MIXED_BF16X3] < 1e-4
     assert gap < 1e-4
+
+
+@pytest.mark.parametrize("d,leaf", [(6, 128), (16, 128), (64, 256)])
+def test_mixed_laplace_on_matrix_cores_matches_the_direct_sum(ffc, d, leaf):
+    """Laplace kernel |x - y|^(2-d) in the mixed mode: sampled blocks and evaluation on matrix cores (three-part
+    bf16 split, float64 power, explicit differences for pairs that would cancel). At full rank (tol 0 and every
+    node's rows at least its columns, so every node keeps all its columns and P is a permutation) the
+    compressed sum is the direct sum with the same charges, so each target's error is the kernel's own:
+    the power (d - 2) / 2 times the relative error of r^2, at most (2d + 4) 2^-20 (float32 staging and
+    accumulation over d terms on a pair with r^2 >= 1/16 of the centred norms; closer pairs take explicit
+    differences), times sum_j |K_ij q_j|."""
+    N = 2048
+    X = W.low_intrinsic(N, d, di=4, noise=1e-2, seed=3)
+    q = W.charges(N, seed=4)
+    gk, ok = gkernel(LAPLACE), okernel(LAPLACE)
+    t = ffc.build_tree(X, leaf)
+    sk = ffc.skeletonize(t, gk, tol=0.0, max_rank=1024, num_samples=1024, seed=0, precision=ffc.MIXED_BF16X3)
+    for a in range(1, t.num_nodes):
+        v = sk.node(a)
+        assert v["rank"] == len(v["cols"]), a          # every node kept at full rank
+    u, _ = ffc.evaluate_sum(t, sk, gk, q, precision=ffc.MIXED_BF16X3)
+    ffc.check_device()
+    u = u.cpu().numpy()
+    ref = o_direct(X, X, q, ok)
+    absum = direct_abs_sum(X, X, q, ok)
+    bound = ((d - 2) / 2 * (2 * d + 4) * 2.0 ** -20 + 2.0 ** -40) * absum
+    ratio = np.abs(u - ref) / bound
+    print(f"d={d}: max error / bound {ratio.max():.3e}, rel 2-norm {rel(u, ref):.3e}")
+    assert np.all(np.abs(u - ref) <= bound)
