@@ -280,15 +280,21 @@ def unit_uniform(seed: int, stream: int, i: int) -> float:
     return ((counter_u64(seed, stream, i) >> 11) + 0.5) * 2.0 ** -53
 
 
+def selection_keys(scores: np.ndarray, seed: int, node: int) -> np.ndarray:
+    """Efraimidis-Spirakis keys -ln(U_i) / w_i of the pool entries, w = 0.9 softmax(scores) + 0.1 / pool."""
+    P = len(scores)
+    z = scores - scores.max()
+    sm = np.exp(z) / np.exp(z).sum()
+    w = 0.9 * sm + 0.1 / P
+    return np.array([-math.log(unit_uniform(seed, node | STREAM_KEYS, i)) / w[i] for i in range(P)])
+
+
 def select_rows(scores: np.ndarray, pool: np.ndarray, s: int, seed: int, node: int) -> np.ndarray:
     """Weighted selection without replacement of s pool entries (ES keys), ascending."""
     P = len(pool)
     if s >= P:
         return np.sort(pool)
-    z = scores - scores.max()
-    sm = np.exp(z) / np.exp(z).sum()
-    w = 0.9 * sm + 0.1 / P
-    keys = np.array([-math.log(unit_uniform(seed, node | STREAM_KEYS, i)) / w[i] for i in range(P)])
+    keys = selection_keys(scores, seed, node)
     order = np.lexsort((np.arange(P), keys))
     return np.sort(pool[order[:s]])
 

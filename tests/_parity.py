@@ -74,3 +74,74 @@ def direct_bound(Y, X, q, kind, kw):
         amp = kw.get("p", 1) * float(np.max(np.abs(a) / np.maximum(np.abs(a + c), 1e-300)))
     budget = (2 * (d + 2) * (amp + 1) + 4 + 2 * X.shape[0]) * U64
     return budget * direct_abs_sum(Y, X, q, ok)
+
+
+def local_pivots(g):
+    """Positions of the GPU node's skeleton points in its column list (the ID's pivot columns)."""
+    import numpy as np
+    pos = {int(c): i for i, c in enumerate(g["cols"])}
+    return np.array([pos[int(x)] for x in g["skel"]], dtype=np.int64)
+
+
+def recon_residual(A, J, P):
+    """||A - A(:, J) P||_F / ||A||_F (0 for a zero block)."""
+    import numpy as np
+    den = np.linalg.norm(A)
+    if den == 0:
+        return 0.0
+    return float(np.linalg.norm(A - A[:, J] @ P) / den)
+
+
+def valid_pivot_sequence(A, piv, rank, tol, max_rank, rel_tie=1e-9):
+    """Whether the pivot order piv[:rank] is a column-pivoted QR of A up to near-ties: at every step the chosen
+    column's trailing squared norm is within rel_tie of the largest remaining one (Householder steps taken in
+    that order), every accepted pivot passes the rank rule and the first rejected one fails it, within the same
+    tolerance."""
+    import numpy as np
+    A = np.array(A, dtype=np.float64, copy=True)
+    s, n = A.shape
+    remaining = list(range(n))
+    rho0 = None
+    for k in range(rank):
+        sub = A[k:, remaining]
+        norms2 = np.einsum("ij,ij->j", sub, sub)
+        best = norms2.max()
+        c = int(piv[k])
+        if c not in remaining:
+            return False
+        nc = norms2[remaining.index(c)]
+        if nc < (1 - rel_tie) * best:
+            return False
+        rho = np.sqrt(nc)
+        rho0 = rho if k == 0 else rho0
+        if rho == 0.0 or rho < tol * rho0 * (1 - 1e-6):
+            return False
+        # Householder step on column c, moved to position k.
+        j = remaining.index(c)
+        remaining.pop(j)
+        x = A[k:, c].copy()
+        alpha = -np.copysign(rho, x[0]) if x[0] != 0 else -rho
+        v = x
+        v[0] -= alpha
+        vv = float(v @ v)
+        if vv > 0:
+            A[k:, remaining] -= np.outer(v, (2.0 / vv) * (v @ A[k:, remaining]))
+    if rank < min(s, n, max_rank) and remaining and rank > 0:
+        sub = A[rank:, remaining]
+        rho_next = np.sqrt(np.einsum("ij,ij->j", sub, sub).max())
+        if rho_next >= tol * rho0 * (1 + 1e-6) and rho_next > 0:
+            return False
+    return True
+
+
+def gpu_skeletons(sk, num_nodes):
+    """The GPU's skeleton set as oracle NodeSkeletons (for evaluating the GPU's skeletons with the oracle)."""
+    import numpy as np
+    from oracle.skeleton import NodeSkeleton, Skeletons
+    out = Skeletons()
+    for a in range(1, num_nodes):
+        g = sk.node(a)
+        out.nodes[a] = NodeSkeleton(cols=g["cols"].astype(np.int64), rows=g["rows"].astype(np.int64), rank=g["rank"],
+                                    piv=local_pivots(g), skel=g["skel"].astype(np.int64), P=g["P"],
+                                    rho=np.zeros(g["rank"]), gap=np.ones(g["rank"]))
+    return out

@@ -98,3 +98,25 @@ def test_polynomial_kernel_exact_rank_and_sampled_reconstruction(p, rank):
     K = kernel_matrix(Y, X, k)
     rel = np.linalg.norm(K - K[:, idd.skel] @ idd.P) / np.linalg.norm(K)
     assert rel < 1e-9
+
+
+def test_pivot_validity_checker_of_the_parity_tests():
+    """The parity tests accept a GPU pivot order that differs from the oracle's only through a near-tie; the
+    checker they use accepts the oracle's own order and rejects a swapped pivot or a wrong stopping point."""
+    import sys
+    from tests._parity import valid_pivot_sequence
+    g = np.random.default_rng(0)
+    A = g.standard_normal((40, 30)) @ np.diag(10.0 ** -np.linspace(0, 6, 30))
+    o = interpolative_decomposition(A, 1e-4, 30)
+    assert valid_pivot_sequence(A, o.piv, o.rank, 1e-4, 30)
+    bad = o.piv.copy()
+    bad[[0, 1]] = bad[[1, 0]]
+    assert not valid_pivot_sequence(A, bad, o.rank, 1e-4, 30)
+    assert not valid_pivot_sequence(A, o.piv, o.rank - 1, 1e-4, 30)
+    # Two equal columns: either order is a valid pivot sequence.
+    B = np.hstack([A[:, :1], A[:, :1], A[:, 1:5]])
+    ob = interpolative_decomposition(B, 1e-12, 6)
+    swapped = ob.piv.copy()
+    i, j = list(swapped).index(0), list(swapped).index(1)
+    swapped[[i, j]] = swapped[[j, i]]
+    assert valid_pivot_sequence(B, swapped, ob.rank, 1e-12, 6)
