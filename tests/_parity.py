@@ -145,3 +145,27 @@ def gpu_skeletons(sk, num_nodes):
                                     piv=local_pivots(g), skel=g["skel"].astype(np.int64), P=g["P"],
                                     rho=np.zeros(g["rank"]), gap=np.ones(g["rank"]))
     return out
+
+
+def check_node_fp64(g, o, Xt, ok, tol, max_rank):
+    """FP64 node against the oracle node with the same rows and columns: 'exact' where the oracle's pivots are
+    clear (rank, skeleton, P to 1e-8 of its largest entry), else 'valid': the GPU's order is a valid pivoted QR
+    of the same block with the oracle's residual."""
+    import numpy as np
+    np.testing.assert_array_equal(g["rows"], o.rows)
+    np.testing.assert_array_equal(g["cols"], o.cols)
+    if unambiguous(o, tol):
+        assert g["rank"] == o.rank
+        np.testing.assert_array_equal(g["skel"], o.skel)
+        np.testing.assert_allclose(g["P"], o.P, atol=1e-8 * max(1.0, np.abs(o.P).max()))
+        return "exact"
+    from oracle.kernels import kernel_matrix
+    A = kernel_matrix(Xt[o.rows], Xt[o.cols], ok)
+    J = local_pivots(g)
+    order = np.concatenate([J, np.setdiff1d(np.arange(A.shape[1]), J)])
+    assert valid_pivot_sequence(A, order, g["rank"], tol, max_rank)
+    np.testing.assert_array_equal(g["P"][:, J], np.eye(g["rank"]))
+    # A near-tie only swaps which of two equally good columns is kept: the residual stays the oracle's, up to
+    # the rank shift a tie at the stopping threshold allows (one column of relative size tol).
+    assert recon_residual(A, J, g["P"]) <= (1 + 1e-6) * recon_residual(A, o.piv[:o.rank], o.P) + 2 * tol
+    return "valid"

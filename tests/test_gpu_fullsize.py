@@ -30,8 +30,8 @@ from oracle.separation import separated_rows, treecode_evaluate
 from oracle.skeleton import skeletonize_node
 from oracle.tree import build_tree as o_build_tree
 from paper_1409_2802_amd import workloads as W
-from tests._parity import (FP64_REL, direct_bound, gkernel, gpu_skeletons, local_pivots, okernel, recon_residual,
-                           rel, unambiguous, valid_pivot_sequence)
+from tests._parity import (FP64_REL, check_node_fp64, direct_bound, gkernel, gpu_skeletons, local_pivots, okernel,
+                           recon_residual, rel)
 
 pytestmark = pytest.mark.gpu
 
@@ -52,26 +52,6 @@ def ffc():
 
 def node_cols(g):
     return g["cols"].astype(np.int64)
-
-
-def check_node_fp64(g, o, Xt, ok, tol, max_rank):
-    """FP64 node against the oracle node with the same rows and columns: 'exact' or 'valid' (near-tie)."""
-    np.testing.assert_array_equal(g["rows"], o.rows)
-    np.testing.assert_array_equal(g["cols"], o.cols)
-    if unambiguous(o, tol):
-        assert g["rank"] == o.rank
-        np.testing.assert_array_equal(g["skel"], o.skel)
-        np.testing.assert_allclose(g["P"], o.P, atol=1e-8 * max(1.0, np.abs(o.P).max()))
-        return "exact"
-    A = kernel_matrix(Xt[o.rows], Xt[o.cols], ok)
-    J = local_pivots(g)
-    order = np.concatenate([J, np.setdiff1d(np.arange(A.shape[1]), J)])
-    assert valid_pivot_sequence(A, order, g["rank"], tol, max_rank)
-    np.testing.assert_array_equal(g["P"][:, J], np.eye(g["rank"]))
-    # A near-tie only swaps which of two equally good columns is kept: the residual stays the oracle's, up to
-    # the rank shift a tie at the stopping threshold allows (one column of relative size tol).
-    assert recon_residual(A, J, g["P"]) <= (1 + 1e-6) * recon_residual(A, o.piv[:o.rank], o.P) + 2 * tol
-    return "valid"
 
 
 def check_node_reduced(g, o, Xt, ok, kerr):

@@ -330,35 +330,43 @@ def _learned_case(ffc, fallback_tol):
 
 
 def test_learned_skeletonize_matches_oracle(ffc):
+    """Every node against the oracle's learned skeletonization of that node from the same columns: rows exact
+    where the key cut is clear (float32 scores), else every chosen key within a 1e-4 slack of the cut; the ID
+    on the GPU's rows exact where the pivots are clear, else a valid pivoted QR; the far field against the
+    oracle's evaluation of the GPU's skeletons."""
+    from oracle.skeleton import skeletonize_node
+    from tests._parity import check_node_fp64, gpu_skeletons
     X, t, ot, sk, osk, fell, theta, mu, sd, gk, ok = _learned_case(ffc, 0.0)
     Xt = X[ot.perm]
-    exact, checked = 0, 0
-    for level in range(ot.depth, 0, -1):
-        for a in ot.level_nodes(level):
-            g, o = sk.node(a), osk.nodes[a]
-            if not np.array_equal(g["cols"], o.cols):
-                continue                            # an ambiguous choice below changed the columns
-            checked += 1
-            b, e = int(ot.begin[a]), int(ot.end[a])
-            pool = pr.candidate_pool(b, e, ot.N, 48, 4, a)
-            sc, _ = pr.mlp_forward(theta, pr.standardize(pr.features(Xt[pool], pr.column_geometry(Xt[o.cols], 4, a)),
-                                                         mu, sd))
-            if len(o.cols) == 0 or _selection_gap(sc, pool, 48, 4, a) < 1e-4:
-                continue
-            np.testing.assert_array_equal(g["rows"], o.rows, err_msg=f"node {a}")
-            if not unambiguous(o, 1e-6):
-                continue
-            assert g["rank"] == o.rank, f"node {a}"
-            np.testing.assert_array_equal(g["skel"], o.skel)
-            np.testing.assert_allclose(g["P"], o.P, atol=1e-8 * max(1.0, np.abs(o.P).max()))
-            exact += 1
-    assert checked == ot.num_nodes - 1
-    assert exact >= 0.8 * checked, (exact, checked)
+    kinds = {"exact": 0, "valid": 0}
+    cut_exact = 0
+    for a in range(1, ot.num_nodes):
+        g = sk.node(a)
+        cols = g["cols"].astype(np.int64)
+        if len(cols) == 0:
+            continue
+        b, e = int(ot.begin[a]), int(ot.end[a])
+        pool = pr.candidate_pool(b, e, ot.N, 48, 4, a)
+        sc, _ = pr.mlp_forward(theta, pr.standardize(pr.features(Xt[pool], pr.column_geometry(Xt[cols], 4, a)),
+                                                     mu, sd))
+        rows = pr.select_rows(sc, pool, 48, 4, a)
+        if _selection_gap(sc, pool, 48, 4, a) >= 1e-4:
+            np.testing.assert_array_equal(g["rows"], rows, err_msg=f"node {a}")
+            cut_exact += 1
+        else:
+            keys = dict(zip(pool.tolist(), pr.selection_keys(sc, 4, a)))
+            cut = np.sort(list(keys.values()))[len(rows) - 1]
+            assert len(g["rows"]) == len(rows)
+            assert all(keys[int(x)] <= cut * (1 + 1e-4) for x in g["rows"]), a
+        o = skeletonize_node(Xt, ot, a, cols, ok, 1e-6, 24, 48, 4, rows=g["rows"].astype(np.int64))
+        kinds[check_node_fp64(g, o, Xt, ok, 1e-6, 24)] += 1
+    print(f"{cut_exact} nodes with a clear cut, ID checks {kinds}")
+    assert cut_exact >= (ot.num_nodes - 1) // 2
     q = W.charges(ot.N, seed=1)
     u, uf = ffc.evaluate_sum(t, sk, gk, q)
-    ou, ouf = o_evaluate(X, ot, osk, ok, q)
-    if exact == checked:
-        assert rel(uf.cpu().numpy(), ouf) < FP64_REL
+    ou, ouf = o_evaluate(X, ot, gpu_skeletons(sk, ot.num_nodes), ok, q)
+    assert rel(uf.cpu().numpy(), ouf) < FP64_REL
+    assert rel(u.cpu().numpy(), ou) < FP64_REL
 
 
 def test_learned_fallback_matches_oracle(ffc):

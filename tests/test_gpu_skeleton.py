@@ -12,7 +12,8 @@ from oracle.skeleton import skeletonize as o_skeletonize
 from oracle.tree import build_partition as o_partition
 from oracle.tree import build_tree as o_build_tree
 from paper_1409_2802_amd import workloads as W
-from tests._parity import FP64_REL, gkernel, okernel, rel, unambiguous
+from oracle.skeleton import skeletonize_node
+from tests._parity import FP64_REL, check_node_fp64, gkernel, gpu_skeletons, okernel, rel, unambiguous
 
 pytestmark = pytest.mark.gpu
 
@@ -82,14 +83,22 @@ def test_tree_config(ffc, kind, kw, data, N, d, leaf, tol, mr):
     sk = ffc.skeletonize(t, gk, tol=tol, max_rank=mr, seed=3)
     u, uf = ffc.evaluate_sum(t, sk, gk, q)
     ot = o_build_tree(X, leaf)
-    osk = o_skeletonize(X, ot, ok, tol=tol, max_rank=mr, seed=3)
-    ou, ouf = o_evaluate(X, ot, osk, ok, q)
-    exact, stop = compare_nodes(sk, osk, t.num_nodes, tol)
-    if stop is None:
-        assert rel(uf.cpu().numpy(), ouf) < FP64_REL
-        assert rel(u.cpu().numpy(), ou) < FP64_REL
-    else:
-        pytest.xfail(f"near-tie pivot at node {stop}; {exact} nodes matched exactly before it")
+    Xt = X[ot.perm]
+    # Every node against the oracle's node from the same columns; a near-tie is accepted as a valid pivoted QR.
+    kinds = {"exact": 0, "valid": 0}
+    for a in range(1, ot.num_nodes):
+        g = sk.node(a)
+        o = skeletonize_node(Xt, ot, a, g["cols"].astype(np.int64), ok, tol, mr, 2 * mr, 3)
+        kinds[check_node_fp64(g, o, Xt, ok, tol, mr)] += 1
+    assert kinds["exact"] >= 1
+    # The sums against the oracle's evaluation of the GPU's skeletons, and (where no tie moved a skeleton) of
+    # the oracle's own.
+    ou, ouf = o_evaluate(X, ot, gpu_skeletons(sk, ot.num_nodes), ok, q)
+    assert rel(uf.cpu().numpy(), ouf) < FP64_REL
+    assert rel(u.cpu().numpy(), ou) < FP64_REL
+    if kinds["valid"] == 0:
+        ou2, _ = o_evaluate(X, ot, o_skeletonize(X, ot, ok, tol=tol, max_rank=mr, seed=3), ok, q)
+        assert rel(u.cpu().numpy(), ou2) < FP64_REL
     ffc.check_device()
 
 
