@@ -541,8 +541,12 @@ ffc_status ffc_profile_enable(int32_t on);
  * them and keeps the fastest; FFC_AUTOTUNE=0 in the environment disables it.
  * Writes up to `cap` entries of 8 int32 (s_max, n_max, batch, rank cap, 100 x
  * rows per lane + columns per lane group, threads per workgroup, best time in
- * us, first candidate's time in us) to out_host and their total number to
- * *count. */
+ * us, first candidate's time in us or -1 for a choice read from the cache) to
+ * out_host and their total number to *count. With FFC_TUNE_CACHE=<file> in
+ * the environment the choices persist: they are read from the file on first
+ * use and each new one is appended (one text line per choice, keyed by the
+ * device's architecture name and compute-unit count), so later processes on
+ * the same kind of device skip the timing. */
 ffc_status ffc_autotune_report(int32_t* out_host, int32_t cap, int32_t* count);
 ffc_status ffc_profile_read(double* ms_host, int64_t* launches_host, int32_t num_stages, int32_t reset);
 

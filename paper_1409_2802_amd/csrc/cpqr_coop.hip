@@ -42,7 +42,9 @@
 // device flag and the workgroup abandons its remaining work, so every wave
 // exits.
 #include <climits>
+#include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <mutex>
 #include <type_traits>
 #include <vector>
@@ -810,6 +812,7 @@ struct TuneEntry {
   int s_max, n_max, batch, max_rank;
   int choice;
   float best_us, first_us;
+  bool from_cache;
 };
 std::mutex g_tune_mu;
 std::vector<TuneEntry> g_tune;
@@ -817,6 +820,67 @@ std::vector<TuneEntry> g_tune;
 bool autotune_enabled() {
   const char* e = std::getenv("FFC_AUTOTUNE");
   return !(e && e[0] == '0');
+}
+
+// Persistent choices: with FFC_TUNE_CACHE=<file>, choices are read from the
+// file on first use and every new one is appended, so later processes on the
+// same kind of device skip the timing. One line per choice: device key
+// (architecture name and compute-unit count), s_max, n_max, batch, rank cap,
+// rows per lane, columns per lane group, threads, best us. Lines for other
+// devices or unknown variants are ignored.
+std::string device_key() {
+  int dev = 0, cus = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  std::string arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == ' ' || c == ':') c = '_';
+  return arch + "-" + std::to_string(cus);
+}
+
+bool g_cache_loaded = false;
+
+int variant_index(int R, int CS, int threads) {
+  for (int v = 0; v < kNumVariants; ++v)
+    if (kVariants[v].R == R && kVariants[v].CS == CS && kVariants[v].threads == threads) return v;
+  return -1;
+}
+
+// Called with g_tune_mu held.
+void load_tune_cache() {
+  if (g_cache_loaded) return;
+  g_cache_loaded = true;
+  const char* path = std::getenv("FFC_TUNE_CACHE");
+  if (!path || !path[0]) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  const std::string key = device_key();
+  char dk[128];
+  TuneEntry te{};
+  int R = 0, CS = 0, T = 0;
+  float best = 0.f;
+  while (std::fscanf(f, "%127s %d %d %d %d %d %d %d %f", dk, &te.s_max, &te.n_max, &te.batch, &te.max_rank, &R, &CS,
+                     &T, &best) == 9) {
+    const int v = variant_index(R, CS, T);
+    if (key != dk || v < 0) continue;
+    te.choice = v;
+    te.best_us = te.first_us = best;
+    te.from_cache = true;
+    g_tune.push_back(te);
+  }
+  std::fclose(f);
+}
+
+void append_tune_cache(const TuneEntry& te) {
+  const char* path = std::getenv("FFC_TUNE_CACHE");
+  if (!path || !path[0]) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  const Variant& v = kVariants[te.choice];
+  std::fprintf(f, "%s %d %d %d %d %d %d %d %.1f\n", device_key().c_str(), te.s_max, te.n_max, te.batch, te.max_rank,
+               v.R, v.CS, v.threads, te.best_us);
+  std::fclose(f);
 }
 
 ffc_status tune(const IdBatch& bt, int batch, QrScratch scratch, hipStream_t st, const std::vector<int>& cand,
@@ -873,6 +937,7 @@ int tuned_choice(const IdBatch& bt, int batch) {
   int choice = -1;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
+    load_tune_cache();
     for (const TuneEntry& te : g_tune)
       if (te.s_max == bt.s_max && te.n_max == bt.n_max && te.batch == batch && te.max_rank == bt.max_rank)
         choice = te.choice;
@@ -901,11 +966,12 @@ ffc_status launch_interp_decomp_coop(const IdBatch& bt, int batch, DevBuf<unsign
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   FFC_HIP_TRY(hipStreamIsCapturing(st, &cs));
   if (choice < 0 && cand.size() > 1 && autotune_enabled() && cs == hipStreamCaptureStatusNone) {
-    TuneEntry te{bt.s_max, bt.n_max, batch, bt.max_rank, -1, 0.f, 0.f};
+    TuneEntry te{bt.s_max, bt.n_max, batch, bt.max_rank, -1, 0.f, 0.f, false};
     FFC_TRY(tune(bt, batch, scratch, st, cand, te));
     if (te.choice >= 0) {
       std::lock_guard<std::mutex> lock(g_tune_mu);
       g_tune.push_back(te);
+      append_tune_cache(te);
       choice = te.choice;
     }
   }
@@ -954,6 +1020,7 @@ ffc_status launch_interp_decomp_fixed(const IdBatch& bt, int batch, unsigned cha
 
 int autotune_entries(int32_t* out, int cap) {
   std::lock_guard<std::mutex> lock(g_tune_mu);
+  load_tune_cache();
   const int n = (int)g_tune.size();
   for (int e = 0; e < n && e < cap; ++e) {
     const TuneEntry& te = g_tune[e];
@@ -965,7 +1032,7 @@ int autotune_entries(int32_t* out, int cap) {
     o[4] = kVariants[te.choice].R * 100 + kVariants[te.choice].CS;
     o[5] = kVariants[te.choice].threads;
     o[6] = (int32_t)te.best_us;
-    o[7] = (int32_t)te.first_us;
+    o[7] = te.from_cache ? -1 : (int32_t)te.first_us;
   }
   return n;
 }

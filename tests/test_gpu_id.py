@@ -108,3 +108,35 @@ def test_every_qr_variant_gives_the_same_bits(ffc, monkeypatch, s, n, tol, max_r
             np.testing.assert_array_equal(rank, ref[0], err_msg=f"variant {v}")
             np.testing.assert_array_equal(piv, ref[1], err_msg=f"variant {v}")
             np.testing.assert_array_equal(P, ref[2], err_msg=f"variant {v}")
+
+
+def test_autotune_cache_persists_choices(tmp_path):
+    """With FFC_TUNE_CACHE the QR autotuner's choice made in one process is read back by the next one, which
+    then times nothing (its report marks the choice as from the cache) and gives the same bits."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = (
+        "import sys, json, numpy as np\n"
+        f"sys.path.insert(0, {root!r})\n"
+        "from paper_1409_2802_amd import ffc\n"
+        "g = np.random.default_rng(1)\n"
+        "A = np.stack([g.standard_normal((300, 200)) @ np.diag(10.0 ** -np.linspace(0, 8, 200)) for _ in range(6)])\n"
+        "r, p, P = ffc.interp_decomp(A, 1e-7, 96)\n"
+        "print(json.dumps({'rank': r.cpu().tolist(), 'piv': p.cpu().numpy()[:, :40].tolist(),\n"
+        "                  'P': float(P.cpu().numpy().sum()), 'report': ffc.autotune_report()}))\n")
+    env = dict(os.environ, FFC_TUNE_CACHE=str(tmp_path / "qr_tune.txt"))
+    env.pop("FFC_QR_VARIANT", None)
+    env.pop("FFC_AUTOTUNE", None)
+    outs = []
+    for _ in range(2):
+        res = subprocess.run([sys.executable, "-c", script], env=env, capture_output=True, text=True, timeout=300)
+        assert res.returncode == 0, res.stderr[-2000:]
+        outs.append(json.loads(res.stdout.strip().splitlines()[-1]))
+    first, second = outs
+    assert (tmp_path / "qr_tune.txt").read_text().strip()
+    assert any(not e["from_cache"] for e in first["report"])
+    assert second["report"] and all(e["from_cache"] for e in second["report"])
+    assert first["rank"] == second["rank"] and first["piv"] == second["piv"] and first["P"] == second["P"]
