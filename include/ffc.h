@@ -264,7 +264,13 @@ ffc_status ffc_sampled_block(const ffc_tree* t, const ffc_kernel* k, int32_t pre
  * rows i >= rank are left untouched. Same QR and solve as the skeletonization
  * (Appendix 6.1; Theorem thm_compute_id). piv_dev entries k >= rank list the
  * remaining columns. Returns after the stream has finished the work (the call
- * owns temporary device scratch). Errors: s, n < 1, max_rank < 1. */
+ * owns temporary device scratch). Errors: s, n < 1, max_rank < 1.
+ * The QR (here and in the skeletonization) is a cooperative launch when the
+ * blocks fit in registers (s <= 512). A process that has made one holds the
+ * device's cooperative-launch resource until it exits; while it does, the
+ * same call in another process on that device falls back to the
+ * one-workgroup-per-block kernel (slower; results within the same parity
+ * bar, not bitwise the same). */
 ffc_status ffc_interp_decomp(double* A_dev, int32_t batch, int32_t s, int32_t n, double tol,
                              int32_t max_rank, int32_t* rank_dev, int32_t* piv_dev,
                              double* P_dev, void* stream);
@@ -283,7 +289,9 @@ ffc_status ffc_interp_decomp(double* A_dev, int32_t batch, int32_t s, int32_t n,
  * and outputs must stay valid until the stream passes it. Calls that overlap
  * on one GPU (other streams, other threads) share the array and race: order
  * them on one stream. Errors: as ffc_interp_decomp, plus s > 512 or blocks
- * beyond the scratch -> FFC_ERR_INVALID_ARG (nothing launched). */
+ * beyond the scratch -> FFC_ERR_INVALID_ARG (nothing launched); the
+ * cooperative launch refused because another process holds the device's
+ * cooperative-launch resource -> FFC_ERR_STATE (there is no fallback here). */
 #define FFC_NOALLOC_SCRATCH_BYTES (16u << 20)
 ffc_status ffc_interp_decomp_noalloc(double* A_dev, int32_t batch, int32_t s, int32_t n, double tol,
                                      int32_t max_rank, int32_t* rank_dev, int32_t* piv_dev, double* P_dev,
@@ -548,6 +556,10 @@ ffc_status ffc_profile_enable(int32_t on);
  * device's architecture name and compute-unit count), so later processes on
  * the same kind of device skip the timing. */
 ffc_status ffc_autotune_report(int32_t* out_host, int32_t cap, int32_t* count);
+/* Forgets the autotuner's choices in this process; the next factorization
+ * reads FFC_TUNE_CACHE again (when set) and times the shapes it does not find
+ * there. Not to be called while another thread factors blocks. */
+void ffc_autotune_reset(void);
 ffc_status ffc_profile_read(double* ms_host, int64_t* launches_host, int32_t num_stages, int32_t reset);
 
 void ffc_free_tree(ffc_tree* t);

@@ -159,9 +159,9 @@ __device__ inline double untag(double v) { return __longlong_as_double(__double_
 // Register layout: a wavefront is 4 lane groups of 16 lanes; a lane group owns
 // CS columns and each of its lanes keeps RL rows (i = lane16 + 16 m) of them,
 // so a column's dot products and norms are 16-lane DPP reductions.
-// Variants: RL rows per lane (16 or 32), CS columns per lane group (64 / RL,
-// or 1 to halve the per-wave work of a step for small batches) and NTC threads
-// per workgroup (512 or 256); all keep at most 256 VGPRs per lane.
+// Variants: RL rows per lane (16 or 32), CS columns per lane group (2, or 1
+// to halve the per-wave work of a step for small batches) and NTC threads per
+// workgroup (512, 256 or 128); all keep at most 256 VGPRs per lane.
 template <int RL, int CS, int NTC>
 __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
   constexpr int CPW = 4 * CS;          // columns per wavefront
@@ -171,6 +171,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
   __shared__ int s_win[3];             // {ok, winner group, winner column}
   __shared__ double s_nv;              // winner's norm (tag cleared)
   __shared__ double s_xk;              // winner's row k
+  __shared__ double s_vcb[16];         // the reflector's rows in the current register block
   extern __shared__ double lds[];      // NWVC candidate columns, then the winner column (ROWS each)
   double* candcol = lds;
   double* wincol = lds + NWVC * ROWS;
@@ -201,15 +202,45 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
     double* A = ca.A + (int64_t)b * ca.a_stride;
     const int col0 = g * ca.cols_per_wg + w * CPW + grp * CS;   // this lane group's first column
 
+    // Row l16 + 16 m exists for m < mlim. (Comparing m, an immediate, with
+    // one per-lane bound keeps the compiler from holding all RL row indices
+    // in registers across the task loop.)
+    const int mlim = s > l16 ? (s - l16 + 15) >> 4 : 0;
     double a[CS][RL];
 #pragma unroll
-    for (int c = 0; c < CS; ++c)
+    for (int c = 0; c < CS; ++c) {
+      const double* colp = A + (int64_t)(col0 + c) * ca.lda + l16;
+      const bool jin = col0 + c < n;
 #pragma unroll
-      for (int m = 0; m < RL; ++m) {
-        const int i = l16 + 16 * m, j = col0 + c;
-        a[c][m] = (i < s && j < n) ? A[(int64_t)j * ca.lda + i] : 0.0;
-      }
+      for (int m = 0; m < RL; ++m) a[c][m] = (jin && m < mlim) ? colp[16 * m] : 0.0;
+    }
     unsigned int done = 0u;   // bit c: column col0 + c is a frozen pivot
+
+    // The register block that holds row k (block kb = k / 16, rows
+    // 16 kb + l16) lives in cur[] instead of a[][kb], which is kept zero
+    // together with every block above it. Rows above the active ones thus
+    // drop out of the norms and of the reflector products without a
+    // register index that depends on k: R(k, j) is read from cur, and only
+    // the move of a new block into cur, once every 16 steps, indexes the
+    // registers. The reflector's rows of the current block are staged apart
+    // (s_vcb) and are zero in wincol, so the loops over a[][] never touch
+    // them.
+    double cur[CS];
+#pragma unroll
+    for (int c = 0; c < CS; ++c) {
+      cur[c] = a[c][0];
+      a[c][0] = 0.0;
+    }
+    int kb = 0;
+    // Norm of the rows at or below row kk (kk in the current block or the
+    // first row of the next one).
+    auto active_norm = [&](int c, int kk) -> double {
+      double n2[2] = {0.0, 0.0};   // even and odd m: two chains of dependent FMAs
+#pragma unroll
+      for (int m = 0; m < RL; ++m) n2[m & 1] = fma(a[c][m], a[c][m], n2[m & 1]);
+      const double y = 16 * kb + l16 >= kk ? cur[c] : 0.0;
+      return row16_sum(fma(y, y, n2[0] + n2[1]));
+    };
 
     // Publish this workgroup's best column for step k (trailing norms over rows >= k).
     auto publish = [&](int k) {
@@ -217,10 +248,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       int bestc = -1;
 #pragma unroll
       for (int c = 0; c < CS; ++c) {
-        double nrm = 0.0;   // rows above k are zero in the registers
-#pragma unroll
-        for (int m = 0; m < RL; ++m) nrm = fma(a[c][m], a[c][m], nrm);
-        nrm = row16_sum(nrm);
+        const double nrm = active_norm(c, k);
         const int j = col0 + c;
         if (j < n && !(done & (1u << c)) && better(nrm, j, best.v, best.orig)) {
           best = Best{nrm, j};
@@ -243,16 +271,14 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
 #pragma unroll
         for (int m = 0; m < RL; ++m) {
           double x = a[0][m];
-          if constexpr (CS == 4) {
-            const double lo = (bestc & 1) ? a[1][m] : a[0][m];
-            const double hi = (bestc & 1) ? a[3][m] : a[2][m];
-            x = (bestc & 2) ? hi : lo;
-          } else {
 #pragma unroll
-            for (int c = 1; c < CS; ++c) x = bestc == c ? a[c][m] : x;
-          }
+          for (int c = 1; c < CS; ++c) x = bestc == c ? a[c][m] : x;
           candcol[w * ROWS + l16 + 16 * m] = x;
         }
+        double y = cur[0];
+#pragma unroll
+        for (int c = 1; c < CS; ++c) y = bestc == c ? cur[c] : y;
+        candcol[w * ROWS + 16 * kb + l16] = y;   // the current block (zero in a[][kb])
       }
       if (lane == 0) wb[w] = wbst;
       __syncthreads();
@@ -342,7 +368,11 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       const double* sl = slot_ptr(ca, b, k & 1, gwin);
       const long long tag = step_tag(k);
       const double rho = sqrt(s_nv);
-      if (k > 0 && threadIdx.x == 0) wincol[k - 1] = 0.0;
+      // Rows of block k / 16 (the current register block at step k) go to
+      // s_vcb and are zero in wincol; row k - 1, when it is in that block,
+      // is cleared in s_vcb (the rows of earlier blocks are already zero).
+      const int vb = (k >> 4) << 4;   // first row of the current block
+      if (k > vb && threadIdx.x == 0) s_vcb[(k - 1) & 15] = 0.0;
       constexpr int PER = (ROWS + NTC - 1) / NTC;   // rows per thread, all loaded before any is used
       for (unsigned int spins = 0;; ++spins) {
         int stale = 0;
@@ -355,15 +385,17 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
           const int i = k + (int)threadIdx.x + t * NTC;
-          if (i < s) {
-            stale |= tag_of(raw[t]) != tag;
-            const double x = untag(raw[t]);
-            if (i == k) {
-              s_xk = x;
-              wincol[i] = x - (x != 0.0 ? -copysign(rho, x) : -rho);
-            } else {
-              wincol[i] = x;
-            }
+          if (i < s) stale |= tag_of(raw[t]) != tag;
+          double x = untag(raw[t]);   // 0 for rows >= s
+          if (i == k) {
+            s_xk = x;
+            x = x - (x != 0.0 ? -copysign(rho, x) : -rho);
+          }
+          if (i < vb + 16) {
+            s_vcb[i & 15] = x;
+            wincol[i] = 0.0;
+          } else if (i < ROWS) {
+            wincol[i] = x;
           }
         }
         if (!__syncthreads_or(stale)) return true;
@@ -376,6 +408,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
     };
 
     for (int i = threadIdx.x; i < ROWS; i += NTC) wincol[i] = 0.0;
+    if (threadIdx.x < 16) s_vcb[threadIdx.x] = 0.0;
     publish(0);   // its barrier also orders the clearing above
     int gwin, porig;
     bool alive = poll(0, gwin, porig);
@@ -390,15 +423,52 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       if (rho == 0.0 || rho < ca.tol * rho0) break;
       const double xk = s_xk;
       const double alpha = xk != 0.0 ? -copysign(rho, xk) : -rho;
-      double v[RL];
-      double part = 0.0;
+      if (k > 0 && (k & 15) == 0) {
+        // Row k opens register block kb + 1: its rows move into cur (the old
+        // block's rows are all stored in A) and a[][kb + 1] becomes zero.
+        // A switch on the uniform block index, once every 16 steps.
+        ++kb;
+        auto take = [&](auto mc) {
+          constexpr int m = decltype(mc)::value;
+          if constexpr (m < RL) {
 #pragma unroll
-      for (int m = 0; m < RL; ++m) {   // the reflector as staged: zero outside rows k..s-1
-        v[m] = wincol[l16 + 16 * m];
-        part = fma(v[m], v[m], part);
+            for (int c = 0; c < CS; ++c) {
+              cur[c] = a[c][m];
+              a[c][m] = 0.0;
+            }
+          }
+        };
+#define FFC_TAKE_CASE(M) \
+  case M:                \
+    take(std::integral_constant<int, M>{}); \
+    break;
+        switch (kb) {
+          FFC_TAKE_CASE(1) FFC_TAKE_CASE(2) FFC_TAKE_CASE(3) FFC_TAKE_CASE(4) FFC_TAKE_CASE(5) FFC_TAKE_CASE(6)
+          FFC_TAKE_CASE(7) FFC_TAKE_CASE(8) FFC_TAKE_CASE(9) FFC_TAKE_CASE(10) FFC_TAKE_CASE(11) FFC_TAKE_CASE(12)
+          FFC_TAKE_CASE(13) FFC_TAKE_CASE(14) FFC_TAKE_CASE(15) FFC_TAKE_CASE(16) FFC_TAKE_CASE(17)
+          FFC_TAKE_CASE(18) FFC_TAKE_CASE(19) FFC_TAKE_CASE(20) FFC_TAKE_CASE(21) FFC_TAKE_CASE(22)
+          FFC_TAKE_CASE(23) FFC_TAKE_CASE(24) FFC_TAKE_CASE(25) FFC_TAKE_CASE(26) FFC_TAKE_CASE(27)
+          FFC_TAKE_CASE(28) FFC_TAKE_CASE(29) FFC_TAKE_CASE(30) FFC_TAKE_CASE(31)
+          default:
+            break;
+        }
+#undef FFC_TAKE_CASE
       }
-      // Every lane group holds all rows, so the reflector norm is a 16-lane sum.
-      const double vv = row16_sum(part);
+      const double vcur = s_vcb[l16];
+      double v[RL];   // the reflector's rows of this lane, for the second pass
+      // v^T a for each held column, in two partial sums (even and odd m).
+      double dots[CS][2];
+#pragma unroll
+      for (int c = 0; c < CS; ++c) dots[c][0] = dots[c][1] = 0.0;
+#pragma unroll
+      for (int m = 0; m < RL; ++m) {   // wincol: the reflector below the current block, zero above
+        v[m] = wincol[l16 + 16 * m];
+#pragma unroll
+        for (int c = 0; c < CS; ++c) dots[c][m & 1] = fma(v[m], a[c][m], dots[c][m & 1]);
+      }
+      // v^T v in closed form: v = x - alpha e_k with x^T x = rho^2 and
+      // alpha = -sign(x_k) rho, so v^T v = 2 rho (rho + |x_k|).
+      const double vv = 2.0 * rho * (rho + fabs(xk));
       const double beta = vv > 0.0 ? 2.0 / vv : 0.0;
       // Freeze the pivot column: its rows 0..k-1 already hold R in A (stored
       // step by step below), row k gets alpha.
@@ -413,48 +483,25 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       }
       // Apply the reflector to the non-pivot columns (a frozen or absent
       // column gets a zero coefficient, which leaves it unchanged).
+      double coef[CS];
 #pragma unroll
       for (int c = 0; c < CS; ++c) {
-        double dot = 0.0;
-#pragma unroll
-        for (int m = 0; m < RL; ++m) dot = fma(v[m], a[c][m], dot);
-        dot = row16_sum(dot);
-        const double coef = (col0 + c < n && !(done & (1u << c))) ? dot * beta : 0.0;
-#pragma unroll
-        for (int m = 0; m < RL; ++m) a[c][m] = fma(-v[m], coef, a[c][m]);
+        const double dot = row16_sum(fma(vcur, cur[c], dots[c][0] + dots[c][1]));
+        coef[c] = (col0 + c < n && !(done & (1u << c))) ? dot * beta : 0.0;
       }
-      // Row k of the active columns is now final, R(k, j): its lane stores it
-      // where the solve reads R and clears it, so that the registers hold
-      // zeros above the next step (norms and staging need no row masks).
-      // (A switch on the register block k / 16: a binary tree of a few
-      // compares, where a chain of tests would take one per block.)
-      if (l16 == (k & 15)) {
-        auto save_row = [&](auto mc) {
-          constexpr int m = decltype(mc)::value;
-          if constexpr (m < RL) {
 #pragma unroll
-            for (int c = 0; c < CS; ++c) {
-              const int j = col0 + c;
-              if (j < n && !(done & (1u << c))) A[(int64_t)j * ca.lda + k] = a[c][m];
-              a[c][m] = 0.0;
-            }
-          }
-        };
-#define FFC_ROW_CASE(M) \
-  case M:               \
-    save_row(std::integral_constant<int, M>{}); \
-    break;
-        switch (k >> 4) {
-          FFC_ROW_CASE(0) FFC_ROW_CASE(1) FFC_ROW_CASE(2) FFC_ROW_CASE(3) FFC_ROW_CASE(4) FFC_ROW_CASE(5)
-          FFC_ROW_CASE(6) FFC_ROW_CASE(7) FFC_ROW_CASE(8) FFC_ROW_CASE(9) FFC_ROW_CASE(10) FFC_ROW_CASE(11)
-          FFC_ROW_CASE(12) FFC_ROW_CASE(13) FFC_ROW_CASE(14) FFC_ROW_CASE(15) FFC_ROW_CASE(16) FFC_ROW_CASE(17)
-          FFC_ROW_CASE(18) FFC_ROW_CASE(19) FFC_ROW_CASE(20) FFC_ROW_CASE(21) FFC_ROW_CASE(22) FFC_ROW_CASE(23)
-          FFC_ROW_CASE(24) FFC_ROW_CASE(25) FFC_ROW_CASE(26) FFC_ROW_CASE(27) FFC_ROW_CASE(28) FFC_ROW_CASE(29)
-          FFC_ROW_CASE(30) FFC_ROW_CASE(31)
-          default:
-            break;
-        }
-#undef FFC_ROW_CASE
+      for (int m = 0; m < RL; ++m) {
+#pragma unroll
+        for (int c = 0; c < CS; ++c) a[c][m] = fma(-v[m], coef[c], a[c][m]);
+      }
+      // Row k of the active columns is now final, R(k, j): the lane that
+      // holds it stores it where the solve reads R. (It stays in cur; the
+      // norms and products of later steps leave it out.)
+#pragma unroll
+      for (int c = 0; c < CS; ++c) {
+        cur[c] = fma(-vcur, coef[c], cur[c]);
+        const int j = col0 + c;
+        if (l16 == (k & 15) && j < n && !(done & (1u << c))) A[(int64_t)j * ca.lda + k] = cur[c];
       }
       publish(k + 1);
       alive = poll(k + 1, gwin, porig);
@@ -664,6 +711,9 @@ k_id_solve_mfma(const double* __restrict__ A, int64_t a_stride, int lda, const i
   for (int c = lane; c < nq; c += 64) piv[(int64_t)b * piv_stride + r + j0 + c] = npc[c];
 }
 
+// Set when a cooperative QR launch was refused on this thread (see launch_qr).
+thread_local bool g_coop_refused = false;
+
 int resident_grid(const void* kern, int threads, size_t lds) {
   int dev = 0, nb = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -751,9 +801,24 @@ ffc_status launch_qr(const IdBatch& bt, int batch, QrScratch scratch, hipStream_
   }
   const int grid = std::min(grid_cap, batch * gmax);
   void* args[] = {&ca};
+  hipError_t le;
   {
     StageTimer tm(FFC_STAGE_CPQR, st);
-    FFC_HIP_TRY(hipLaunchCooperativeKernel(kern, dim3(grid), dim3(NTC), args, (unsigned int)lds, st));
+    le = hipLaunchCooperativeKernel(kern, dim3(grid), dim3(NTC), args, (unsigned int)lds, st);
+  }
+  if (le == hipErrorIllegalState || le == hipErrorCooperativeLaunchTooLarge) {
+    // The device's cooperative-launch resource (global wave sync) belongs to
+    // another process that has made such a launch, or the grid cannot be
+    // co-resident after all: nothing was launched, and the caller falls back
+    // to the one-workgroup-per-block kernel.
+    (void)hipGetLastError();
+    g_coop_refused = true;
+    fits = false;
+    return FFC_OK;
+  }
+  if (le != hipSuccess) {
+    set_error(std::string("hipLaunchCooperativeKernel (QR): ") + hipGetErrorString(le));
+    return le == hipErrorOutOfMemory ? FFC_ERR_OOM : FFC_ERR_HIP;
   }
   return FFC_OK;
 }
@@ -801,9 +866,8 @@ struct Variant {
 };
 #define FFC_VARIANT(R, CS, T) {R, CS, T, &launch_qr<R, CS, T>, &qr_scratch_bytes<R, CS, T>}
 const Variant kVariants[] = {
-    FFC_VARIANT(16, 4, 512), FFC_VARIANT(16, 4, 256), FFC_VARIANT(16, 1, 512), FFC_VARIANT(32, 2, 512),
-    FFC_VARIANT(32, 2, 256), FFC_VARIANT(32, 1, 512), FFC_VARIANT(32, 1, 256), FFC_VARIANT(32, 1, 128),
-    FFC_VARIANT(16, 1, 128),
+    FFC_VARIANT(32, 2, 512), FFC_VARIANT(32, 2, 256), FFC_VARIANT(32, 1, 512), FFC_VARIANT(32, 1, 256),
+    FFC_VARIANT(32, 1, 128), FFC_VARIANT(16, 1, 512), FFC_VARIANT(16, 1, 128),
 };
 #undef FFC_VARIANT
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -900,16 +964,21 @@ ffc_status tune(const IdBatch& bt, int batch, QrScratch scratch, hipStream_t st,
     float best = -1.f;
     for (int rep = 0; rep < 2 && status == FFC_OK; ++rep) {
       bool fits = false;
-      if (hipMemcpyAsync(copy.ptr, bt.A, words * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
-          hipEventRecord(e0, st) != hipSuccess) {
+      hipError_t he = hipMemcpyAsync(copy.ptr, bt.A, words * sizeof(double), hipMemcpyDeviceToDevice, st);
+      if (he == hipSuccess) he = hipEventRecord(e0, st);
+      if (he != hipSuccess) {
+        set_error(std::string("copy of the blocks or start event: ") + hipGetErrorString(he));
         status = FFC_ERR_HIP;
         break;
       }
       status = kVariants[v].fn(tb, batch, scratch, st, fits);
       if (status != FFC_OK || !fits) break;
       float ms = 0.f;
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      he = hipEventRecord(e1, st);
+      if (he == hipSuccess) he = hipEventSynchronize(e1);
+      if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+      if (he != hipSuccess) {
+        set_error(std::string("timing of variant ") + std::to_string(v) + ": " + hipGetErrorString(he));
         status = FFC_ERR_HIP;
         break;
       }
@@ -926,7 +995,7 @@ ffc_status tune(const IdBatch& bt, int batch, QrScratch scratch, hipStream_t st,
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(st);   // the copy is freed below
-  if (status != FFC_OK) set_error("autotuning of the QR kernel failed");
+  if (status != FFC_OK) set_error(std::string("autotuning of the QR kernel failed: ") + ffc_last_error());
   return status;
 }
 
@@ -1000,6 +1069,7 @@ ffc_status launch_interp_decomp_fixed(const IdBatch& bt, int batch, unsigned cha
     return FFC_ERR_INVALID_ARG;
   }
   const int choice = tuned_choice(bt, batch);
+  g_coop_refused = false;
   std::vector<int> order;
   if (choice >= 0) order.push_back(choice);
   for (int v = 0; v < kNumVariants; ++v)
@@ -1013,9 +1083,20 @@ ffc_status launch_interp_decomp_fixed(const IdBatch& bt, int batch, unsigned cha
     FFC_TRY(kVariants[v].fn(bt, batch, scratch, st, fits));
     if (fits) return launch_solve(bt, batch, scratch, st);
   }
+  if (g_coop_refused) {
+    set_error("the cooperative QR launch was refused: another process on this device holds its cooperative-launch "
+              "resource");
+    return FFC_ERR_STATE;
+  }
   set_error("no register-resident QR variant holds these blocks within the fixed scratch (rows above 512, or "
             "too many blocks)");
   return FFC_ERR_INVALID_ARG;
+}
+
+void autotune_reset() {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune.clear();
+  g_cache_loaded = false;
 }
 
 int autotune_entries(int32_t* out, int cap) {

@@ -359,6 +359,7 @@ ffc_status launch_interp_decomp(const IdBatch& b, int batch, hipStream_t st);
 // batch, rank cap, rows per lane, threads, best us, first candidate's us);
 // writes at most cap entries, returns the number of entries (cpqr_coop.hip).
 int autotune_entries(int32_t* out, int cap);
+void autotune_reset();
 ffc_status launch_interp_decomp_coop(const IdBatch& b, int batch, DevBuf<unsigned char>& scratch, hipStream_t st,
                                      bool& used);
 // The same without any allocation: the QR's slots and the solve's scratch

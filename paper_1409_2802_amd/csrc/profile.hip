@@ -152,3 +152,5 @@ extern "C" ffc_status ffc_autotune_report(int32_t* out_host, int32_t cap, int32_
   *count = ffc::autotune_entries(out_host, cap > 0 ? cap : 0);
   return FFC_OK;
 }
+
+extern "C" void ffc_autotune_reset(void) { ffc::autotune_reset(); }

@@ -35,6 +35,7 @@ EXPORTS = [
     "ffc_proposal_fit_standardization", "ffc_proposal_score", "ffc_proposal_gradient", "ffc_proposal_adam",
     "ffc_leverage_labels", "ffc_proposal_train", "ffc_proposal_training_set",
     "ffc_step_graph_create", "ffc_step_graph_create_fmm", "ffc_graph_launch", "ffc_graph_free", "ffc_autotune_report",
+    "ffc_autotune_reset",
     "ffc_skel_load", "ffc_proposal_get_adam", "ffc_proposal_set_adam", "ffc_shutdown",
     "ffc_proposal_save", "ffc_proposal_load", "ffc_pivoted_leverage_labels", "ffc_interp_decomp_noalloc",
 ]
@@ -143,6 +144,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ffc_last_error.restype = ctypes.c_char_p
     lib.ffc_shutdown.argtypes = []
     lib.ffc_shutdown.restype = None
+    lib.ffc_autotune_reset.argtypes = []
+    lib.ffc_autotune_reset.restype = None
     _lib = lib
     return lib
 
@@ -676,6 +679,11 @@ def training_set(tree: Tree, kernel: Kernel, num_blocks: int, block_cols: int, b
     _check(lib.ffc_proposal_training_set(tree.handle, ctypes.byref(k), ctypes.byref(o), None, None, _ptr(leaves),
                                          _ptr(cols), _ptr(rows), _ptr(feat), _ptr(tgt), _ptr(lev), _stream(stream)))
     return {"n": n, "m": m, "leaves": leaves, "cols": cols, "rows": rows, "feat": feat, "target": tgt, "lev": lev}
+
+
+def autotune_reset() -> None:
+    """Forget the QR autotuner's choices in this process (FFC_TUNE_CACHE is read again on next use)."""
+    load_library().ffc_autotune_reset()
 
 
 def autotune_report() -> list:
