@@ -25,12 +25,15 @@
 // every workgroup, far below the rounding of the factorization. Slots are
 // cleared before every launch; a slot read at step k can otherwise only hold
 // step k - 2, whose tag differs.
-// Row k of every active column is final after step k: its lane stores it to
-// A and clears the register, so the registers hold zeros above the current
-// step and norms need no row masks. The pivot column of step k is frozen in
-// place (its rows 0..k-1 are already stored, row k gets alpha), so no columns
-// are swapped; the pivot order is recorded. A ends with R(0:l+1, l) in
-// column piv[l] and R(0:r, j) in rows 0..r-1 of every other column j.
+// Row k of every active column is final after step k: the lane holding it
+// stores it to A. The register block that holds row k is kept in its own
+// register (cur) and is zero in the block array, as are the blocks above, so
+// norms and reflector products over the array need no row masks, and the
+// current block's finished rows are masked by lane. The pivot column of step
+// k is frozen in place (its rows 0..k-1 are already stored, row k gets
+// alpha), so no columns are swapped; the pivot order is recorded. A ends with
+// R(0:l+1, l) in column piv[l] and R(0:r, j) in rows 0..r-1 of every other
+// column j.
 //
 // Scheduling: the groups of a level form a flat task list (block 0's G_0
 // parts, then block 1's, ...); the workgroups of a persistent grid, all
@@ -199,8 +202,9 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
     const int G = ca.task_start[b + 1] - ca.task_start[b];
     const int s = ca.s_arr ? ca.s_arr[b] : ca.s_uniform;
     const int n = ca.n_arr ? ca.n_arr[b] : ca.n_uniform;
-    double* A = ca.A + (int64_t)b * ca.a_stride;
+    double* A = ca.A + (int64_t)b * ca.a_stride;   // element offsets within a block fit in 32 bits
     const int col0 = g * ca.cols_per_wg + w * CPW + grp * CS;   // this lane group's first column
+    int32_t* pivb = ca.piv + (int64_t)b * ca.piv_stride;
 
     // Row l16 + 16 m exists for m < mlim. (Comparing m, an immediate, with
     // one per-lane bound keeps the compiler from holding all RL row indices
@@ -425,34 +429,24 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       const double alpha = xk != 0.0 ? -copysign(rho, xk) : -rho;
       if (k > 0 && (k & 15) == 0) {
         // Row k opens register block kb + 1: its rows move into cur (the old
-        // block's rows are all stored in A) and a[][kb + 1] becomes zero.
-        // A switch on the uniform block index, once every 16 steps.
+        // block's rows are all stored in A) and a[][kb + 1] becomes zero,
+        // once every 16 steps. Straight-line selects against a per-lane copy
+        // of the block index: branches on it would merge every register of
+        // a[][] at their joins.
         ++kb;
-        auto take = [&](auto mc) {
-          constexpr int m = decltype(mc)::value;
-          if constexpr (m < RL) {
+        int kbv;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(kbv) : "s"(kb));
 #pragma unroll
-            for (int c = 0; c < CS; ++c) {
-              cur[c] = a[c][m];
-              a[c][m] = 0.0;
-            }
+        for (int c = 0; c < CS; ++c) {
+          double y = 0.0;
+#pragma unroll
+          for (int m = 1; m < RL; ++m) {
+            const bool hit = kbv == m;
+            y = hit ? a[c][m] : y;
+            a[c][m] = hit ? 0.0 : a[c][m];
           }
-        };
-#define FFC_TAKE_CASE(M) \
-  case M:                \
-    take(std::integral_constant<int, M>{}); \
-    break;
-        switch (kb) {
-          FFC_TAKE_CASE(1) FFC_TAKE_CASE(2) FFC_TAKE_CASE(3) FFC_TAKE_CASE(4) FFC_TAKE_CASE(5) FFC_TAKE_CASE(6)
-          FFC_TAKE_CASE(7) FFC_TAKE_CASE(8) FFC_TAKE_CASE(9) FFC_TAKE_CASE(10) FFC_TAKE_CASE(11) FFC_TAKE_CASE(12)
-          FFC_TAKE_CASE(13) FFC_TAKE_CASE(14) FFC_TAKE_CASE(15) FFC_TAKE_CASE(16) FFC_TAKE_CASE(17)
-          FFC_TAKE_CASE(18) FFC_TAKE_CASE(19) FFC_TAKE_CASE(20) FFC_TAKE_CASE(21) FFC_TAKE_CASE(22)
-          FFC_TAKE_CASE(23) FFC_TAKE_CASE(24) FFC_TAKE_CASE(25) FFC_TAKE_CASE(26) FFC_TAKE_CASE(27)
-          FFC_TAKE_CASE(28) FFC_TAKE_CASE(29) FFC_TAKE_CASE(30) FFC_TAKE_CASE(31)
-          default:
-            break;
+          cur[c] = y;
         }
-#undef FFC_TAKE_CASE
       }
       const double vcur = s_vcb[l16];
       double v[RL];   // the reflector's rows of this lane, for the second pass
@@ -477,9 +471,9 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
         for (int c = 0; c < CS; ++c)
           if (col0 + c == porig) {
             done |= 1u << c;
-            if (l16 == (k & 15)) A[(int64_t)porig * ca.lda + k] = alpha;
+            if (l16 == (k & 15)) A[(uint32_t)(porig * ca.lda + k)] = alpha;
           }
-        if (threadIdx.x == 0) ca.piv[(int64_t)b * ca.piv_stride + k] = porig;
+        if (threadIdx.x == 0) pivb[k] = porig;
       }
       // Apply the reflector to the non-pivot columns (a frozen or absent
       // column gets a zero coefficient, which leaves it unchanged).
@@ -501,7 +495,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       for (int c = 0; c < CS; ++c) {
         cur[c] = fma(-vcur, coef[c], cur[c]);
         const int j = col0 + c;
-        if (l16 == (k & 15) && j < n && !(done & (1u << c))) A[(int64_t)j * ca.lda + k] = cur[c];
+        if (l16 == (k & 15) && j < n && !(done & (1u << c))) A[(uint32_t)(j * ca.lda + k)] = cur[c];
       }
       publish(k + 1);
       alive = poll(k + 1, gwin, porig);
