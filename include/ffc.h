@@ -266,7 +266,7 @@ ffc_status ffc_sampled_block(const ffc_tree* t, const ffc_kernel* k, int32_t pre
  * remaining columns. Returns after the stream has finished the work (the call
  * owns temporary device scratch). Errors: s, n < 1, max_rank < 1.
  * The QR (here and in the skeletonization) is a cooperative launch when the
- * blocks fit in registers (s <= 512). A process that has made one holds the
+ * blocks fit in registers (s <= 1024). A process that has made one holds the
  * device's cooperative-launch resource until it exits; while it does, the
  * same call in another process on that device falls back to the
  * one-workgroup-per-block kernel (slower; results within the same parity
@@ -283,12 +283,12 @@ ffc_status ffc_interp_decomp(double* A_dev, int32_t batch, int32_t s, int32_t n,
  * for the life of the process; the call clears what must start at zero. The
  * QR variant is the one the autotuner picked earlier for the same shape (via
  * ffc_interp_decomp or a skeletonization), else the first that fits; nothing
- * is timed. Limits: s <= 512 (the register-resident QR; no streamed fallback)
+ * is timed. Limits: s <= 1024 (the register-resident QR; no streamed fallback)
  * and the blocks' scratch within the array (about 66 KB per 512 x 512 block,
  * so up to ~250 such blocks). The call is asynchronous on `stream`: inputs
  * and outputs must stay valid until the stream passes it. Calls that overlap
  * on one GPU (other streams, other threads) share the array and race: order
- * them on one stream. Errors: as ffc_interp_decomp, plus s > 512 or blocks
+ * them on one stream. Errors: as ffc_interp_decomp, plus s > 1024 or blocks
  * beyond the scratch -> FFC_ERR_INVALID_ARG (nothing launched); the
  * cooperative launch refused because another process holds the device's
  * cooperative-launch resource -> FFC_ERR_STATE (there is no fallback here). */
@@ -545,10 +545,10 @@ typedef enum {
 } ffc_stage;
 ffc_status ffc_profile_enable(int32_t on);
 /* Autotuner: the first pivoted-QR launch of each block shape times the kernel
- * variants (rows per lane, workgroup size) that can hold the blocks on a copy of
+ * variants (lanes and rows per column, workgroup size) that can hold the blocks on a copy of
  * them and keeps the fastest; FFC_AUTOTUNE=0 in the environment disables it.
  * Writes up to `cap` entries of 8 int32 (s_max, n_max, batch, rank cap, 100 x
- * rows per lane + columns per lane group, threads per workgroup, best time in
+ * the most rows the variant holds + columns per lane group, threads per workgroup, best time in
  * us, first candidate's time in us or -1 for a choice read from the cache) to
  * out_host and their total number to *count. With FFC_TUNE_CACHE=<file> in
  * the environment the choices persist: they are read from the file on first

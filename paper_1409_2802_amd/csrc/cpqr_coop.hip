@@ -3,9 +3,10 @@
 //
 // Right-looking Householder QR with column pivoting re-reads the whole
 // trailing block at every pivot step, so with the block in HBM it is bound by
-// memory traffic. Here each block (s <= 512 rows) is spread over G
+// memory traffic. Here each block (s <= 1024 rows) is spread over G
 // workgroups: a workgroup owns 8 wavefronts x 8 columns, each column held by
-// 16 lanes with up to 32 rows per lane in VGPRs for the whole factorization.
+// 16 lanes (32 lanes and 4 columns per wavefront for blocks of more than 512
+// rows) with up to 32 rows per lane in VGPRs for the whole factorization.
 // One pivot step then needs no block traffic at all:
 //   1. every workgroup loads the winning column (published at the end of the
 //      previous step, one row per thread) into LDS and forms the reflector
@@ -159,27 +160,38 @@ __device__ inline double tagged(double v, long long tag) {
 __device__ inline long long tag_of(double v) { return __double_as_longlong(v) & 3ll; }
 __device__ inline double untag(double v) { return __longlong_as_double(__double_as_longlong(v) & ~3ll); }
 
-// Register layout: a wavefront is 4 lane groups of 16 lanes; a lane group owns
-// CS columns and each of its lanes keeps RL rows (i = lane16 + 16 m) of them,
-// so a column's dot products and norms are 16-lane DPP reductions.
+// Register layout: a wavefront is 64 / LG lane groups of LG lanes (16 or 32);
+// a lane group owns CS columns and each of its lanes keeps RL rows
+// (i = lg + LG m) of them, so a column's dot products and norms are LG-lane
+// reductions (16-lane DPP, plus one exchange between row pairs for LG = 32).
 // Variants: RL rows per lane (16 or 32), CS columns per lane group (2, or 1
-// to halve the per-wave work of a step for small batches) and NTC threads per
-// workgroup (512, 256 or 128); all keep at most 256 VGPRs per lane.
-template <int RL, int CS, int NTC>
+// to halve the per-wave work of a step for small batches), NTC threads per
+// workgroup (512, 256 or 128) and LG (32 for blocks of up to 1024 rows); all
+// keep at most 256 VGPRs per lane.
+template <int LG>
+__device__ inline double group_sum(double x) {
+  x = row16_sum(x);
+  if constexpr (LG == 32) x += __shfl_xor(x, 16, 64);   // a + b = b + a: both rows end equal
+  return x;
+}
+
+template <int RL, int CS, int NTC, int LG>
 __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
-  constexpr int CPW = 4 * CS;          // columns per wavefront
-  constexpr int ROWS = 16 * RL;        // rows a lane group holds (LDS rows are padded to it)
+  static_assert(LG == 16 || LG == 32, "lane groups of 16 or 32 lanes");
+  constexpr int NG = 64 / LG;          // lane groups per wavefront
+  constexpr int CPW = NG * CS;         // columns per wavefront
+  constexpr int ROWS = LG * RL;        // rows a lane group holds (LDS rows are padded to it)
   constexpr int NWVC = NTC / 64;       // wavefronts per workgroup
   __shared__ Best wb[NWVC];
   __shared__ int s_win[3];             // {ok, winner group, winner column}
   __shared__ double s_nv;              // winner's norm (tag cleared)
   __shared__ double s_xk;              // winner's row k
-  __shared__ double s_vcb[16];         // the reflector's rows in the current register block
+  __shared__ double s_vcb[LG];         // the reflector's rows in the current register block
   extern __shared__ double lds[];      // NWVC candidate columns, then the winner column (ROWS each)
   double* candcol = lds;
   double* wincol = lds + NWVC * ROWS;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int grp = lane >> 4, l16 = lane & 15;
+  const int grp = lane / LG, lg = lane & (LG - 1);
   // Tasks (block b, part g) are taken in order from a counter by whichever
   // workgroup is free, so a level with more tasks than resident workgroups is
   // balanced by how long each block takes rather than in fixed rounds.
@@ -206,26 +218,26 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
     const int col0 = g * ca.cols_per_wg + w * CPW + grp * CS;   // this lane group's first column
     int32_t* pivb = ca.piv + (int64_t)b * ca.piv_stride;
 
-    // Row l16 + 16 m exists for m < mlim. (Comparing m, an immediate, with
+    // Row lg + LG m exists for m < mlim. (Comparing m, an immediate, with
     // one per-lane bound keeps the compiler from holding all RL row indices
     // in registers across the task loop.)
-    const int mlim = s > l16 ? (s - l16 + 15) >> 4 : 0;
+    const int mlim = s > lg ? (s - lg + LG - 1) / LG : 0;
     double a[CS][RL];
 #pragma unroll
     for (int c = 0; c < CS; ++c) {
-      const double* colp = A + (int64_t)(col0 + c) * ca.lda + l16;
+      const double* colp = A + (int64_t)(col0 + c) * ca.lda + lg;
       const bool jin = col0 + c < n;
 #pragma unroll
-      for (int m = 0; m < RL; ++m) a[c][m] = (jin && m < mlim) ? colp[16 * m] : 0.0;
+      for (int m = 0; m < RL; ++m) a[c][m] = (jin && m < mlim) ? colp[LG * m] : 0.0;
     }
     unsigned int done = 0u;   // bit c: column col0 + c is a frozen pivot
 
-    // The register block that holds row k (block kb = k / 16, rows
-    // 16 kb + l16) lives in cur[] instead of a[][kb], which is kept zero
+    // The register block that holds row k (block kb = k / LG, rows
+    // LG kb + lg) lives in cur[] instead of a[][kb], which is kept zero
     // together with every block above it. Rows above the active ones thus
     // drop out of the norms and of the reflector products without a
     // register index that depends on k: R(k, j) is read from cur, and only
-    // the move of a new block into cur, once every 16 steps, indexes the
+    // the move of a new block into cur, once every LG steps, indexes the
     // registers. The reflector's rows of the current block are staged apart
     // (s_vcb) and are zero in wincol, so the loops over a[][] never touch
     // them.
@@ -242,8 +254,8 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       double n2[2] = {0.0, 0.0};   // even and odd m: two chains of dependent FMAs
 #pragma unroll
       for (int m = 0; m < RL; ++m) n2[m & 1] = fma(a[c][m], a[c][m], n2[m & 1]);
-      const double y = 16 * kb + l16 >= kk ? cur[c] : 0.0;
-      return row16_sum(fma(y, y, n2[0] + n2[1]));
+      const double y = LG * kb + lg >= kk ? cur[c] : 0.0;
+      return group_sum<LG>(fma(y, y, n2[0] + n2[1]));
     };
 
     // Publish this workgroup's best column for step k (trailing norms over rows >= k).
@@ -259,12 +271,12 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
           bestc = c;
         }
       }
-      // Best of the 4 lane groups of the wavefront (same result in every lane).
+      // Best of the lane groups of the wavefront (same result in every lane).
       Best wbst{readlane_d(best.v, 0), __builtin_amdgcn_readlane(best.orig, 0)};
       int wg_owner = 0;
 #pragma unroll
-      for (int q = 1; q < 4; ++q) {
-        const Best o{readlane_d(best.v, 16 * q), __builtin_amdgcn_readlane(best.orig, 16 * q)};
+      for (int q = 1; q < NG; ++q) {
+        const Best o{readlane_d(best.v, LG * q), __builtin_amdgcn_readlane(best.orig, LG * q)};
         if (better(o.v, o.orig, wbst.v, wbst.orig)) { wbst = o; wg_owner = q; }
       }
       // The wave's best column goes to its LDS candidate row (all ROWS rows;
@@ -277,12 +289,12 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
           double x = a[0][m];
 #pragma unroll
           for (int c = 1; c < CS; ++c) x = bestc == c ? a[c][m] : x;
-          candcol[w * ROWS + l16 + 16 * m] = x;
+          candcol[w * ROWS + lg + LG * m] = x;
         }
         double y = cur[0];
 #pragma unroll
         for (int c = 1; c < CS; ++c) y = bestc == c ? cur[c] : y;
-        candcol[w * ROWS + 16 * kb + l16] = y;   // the current block (zero in a[][kb])
+        candcol[w * ROWS + LG * kb + lg] = y;   // the current block (zero in a[][kb])
       }
       if (lane == 0) wb[w] = wbst;
       __syncthreads();
@@ -372,11 +384,11 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       const double* sl = slot_ptr(ca, b, k & 1, gwin);
       const long long tag = step_tag(k);
       const double rho = sqrt(s_nv);
-      // Rows of block k / 16 (the current register block at step k) go to
+      // Rows of block k / LG (the current register block at step k) go to
       // s_vcb and are zero in wincol; row k - 1, when it is in that block,
       // is cleared in s_vcb (the rows of earlier blocks are already zero).
-      const int vb = (k >> 4) << 4;   // first row of the current block
-      if (k > vb && threadIdx.x == 0) s_vcb[(k - 1) & 15] = 0.0;
+      const int vb = k / LG * LG;   // first row of the current block
+      if (k > vb && threadIdx.x == 0) s_vcb[(k - 1) & (LG - 1)] = 0.0;
       constexpr int PER = (ROWS + NTC - 1) / NTC;   // rows per thread, all loaded before any is used
       for (unsigned int spins = 0;; ++spins) {
         int stale = 0;
@@ -395,8 +407,8 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
             s_xk = x;
             x = x - (x != 0.0 ? -copysign(rho, x) : -rho);
           }
-          if (i < vb + 16) {
-            s_vcb[i & 15] = x;
+          if (i < vb + LG) {
+            s_vcb[i & (LG - 1)] = x;
             wincol[i] = 0.0;
           } else if (i < ROWS) {
             wincol[i] = x;
@@ -412,7 +424,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
     };
 
     for (int i = threadIdx.x; i < ROWS; i += NTC) wincol[i] = 0.0;
-    if (threadIdx.x < 16) s_vcb[threadIdx.x] = 0.0;
+    if (threadIdx.x < LG) s_vcb[threadIdx.x] = 0.0;
     publish(0);   // its barrier also orders the clearing above
     int gwin, porig;
     bool alive = poll(0, gwin, porig);
@@ -427,10 +439,10 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       if (rho == 0.0 || rho < ca.tol * rho0) break;
       const double xk = s_xk;
       const double alpha = xk != 0.0 ? -copysign(rho, xk) : -rho;
-      if (k > 0 && (k & 15) == 0) {
+      if (k > 0 && k % LG == 0) {
         // Row k opens register block kb + 1: its rows move into cur (the old
         // block's rows are all stored in A) and a[][kb + 1] becomes zero,
-        // once every 16 steps. Straight-line selects against a per-lane copy
+        // once every LG steps. Straight-line selects against a per-lane copy
         // of the block index: branches on it would merge every register of
         // a[][] at their joins.
         ++kb;
@@ -448,7 +460,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
           cur[c] = y;
         }
       }
-      const double vcur = s_vcb[l16];
+      const double vcur = s_vcb[lg];
       double v[RL];   // the reflector's rows of this lane, for the second pass
       // v^T a for each held column, in two partial sums (even and odd m).
       double dots[CS][2];
@@ -456,7 +468,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       for (int c = 0; c < CS; ++c) dots[c][0] = dots[c][1] = 0.0;
 #pragma unroll
       for (int m = 0; m < RL; ++m) {   // wincol: the reflector below the current block, zero above
-        v[m] = wincol[l16 + 16 * m];
+        v[m] = wincol[lg + LG * m];
 #pragma unroll
         for (int c = 0; c < CS; ++c) dots[c][m & 1] = fma(v[m], a[c][m], dots[c][m & 1]);
       }
@@ -471,7 +483,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
         for (int c = 0; c < CS; ++c)
           if (col0 + c == porig) {
             done |= 1u << c;
-            if (l16 == (k & 15)) A[(uint32_t)(porig * ca.lda + k)] = alpha;
+            if (lg == (k & (LG - 1))) A[(uint32_t)(porig * ca.lda + k)] = alpha;
           }
         if (threadIdx.x == 0) pivb[k] = porig;
       }
@@ -480,7 +492,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       double coef[CS];
 #pragma unroll
       for (int c = 0; c < CS; ++c) {
-        const double dot = row16_sum(fma(vcur, cur[c], dots[c][0] + dots[c][1]));
+        const double dot = group_sum<LG>(fma(vcur, cur[c], dots[c][0] + dots[c][1]));
         coef[c] = (col0 + c < n && !(done & (1u << c))) ? dot * beta : 0.0;
       }
 #pragma unroll
@@ -495,7 +507,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       for (int c = 0; c < CS; ++c) {
         cur[c] = fma(-vcur, coef[c], cur[c]);
         const int j = col0 + c;
-        if (l16 == (k & 15) && j < n && !(done & (1u << c))) A[(uint32_t)(j * ca.lda + k)] = cur[c];
+        if (lg == (k & (LG - 1)) && j < n && !(done & (1u << c))) A[(uint32_t)(j * ca.lda + k)] = cur[c];
       }
       publish(k + 1);
       alive = poll(k + 1, gwin, porig);
@@ -738,9 +750,9 @@ struct QrScratch {
 // Scratch bytes of variant (R, CS, NTC) for the blocks of bt: slots, task
 // offsets and claim counter of the QR, or the solve's diagonal inverses,
 // whichever is larger (the solve reuses the QR's scratch).
-template <int R, int CS, int NTC>
+template <int R, int CS, int NTC, int LG>
 size_t qr_scratch_bytes(const IdBatch& bt, int batch) {
-  constexpr int CPW = 4 * CS;
+  constexpr int CPW = 64 / LG * CS;
   const int cols_per_wg = CPW * (NTC / 64);
   const int gmax = std::max(1, (bt.n_max + cols_per_wg - 1) / cols_per_wg);
   const size_t slot_doubles = (size_t)batch * 2 * gmax * (bt.s_max + 2);
@@ -750,20 +762,22 @@ size_t qr_scratch_bytes(const IdBatch& bt, int batch) {
 
 // The factorization with variant (R, NTC) on the blocks of bt (in place);
 // fits = false (nothing launched) when a block's group cannot be resident.
-template <int R, int CS, int NTC>
+template <int R, int CS, int NTC, int LG>
 ffc_status launch_qr(const IdBatch& bt, int batch, QrScratch scratch, hipStream_t st, bool& fits) {
-  constexpr int CPW = 4 * CS;   // columns per wavefront
+  constexpr int CPW = 64 / LG * CS;   // columns per wavefront
   const int cols_per_wg = CPW * (NTC / 64);
   const int gmax = std::max(1, (bt.n_max + cols_per_wg - 1) / cols_per_wg);
-  const void* kern = reinterpret_cast<const void*>(&k_cpqr_coop<R, CS, NTC>);
-  const size_t lds = (size_t)(NTC / 64 + 1) * 16 * R * sizeof(double);
+  const void* kern = reinterpret_cast<const void*>(&k_cpqr_coop<R, CS, NTC, LG>);
+  const size_t lds = (size_t)(NTC / 64 + 1) * LG * R * sizeof(double);
+  if (lds > 64 * 1024)
+    FFC_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   const int grid_cap = resident_grid(kern, NTC, lds);
   fits = grid_cap >= gmax;
   if (!fits) return FFC_OK;
   const size_t slot_doubles = (size_t)batch * 2 * gmax * (bt.s_max + 2);
   // Slots, task offsets, claim counter. The solve that follows reuses the
   // scratch: size it for both up front.
-  FFC_TRY(scratch.ensure(qr_scratch_bytes<R, CS, NTC>(bt, batch)));
+  FFC_TRY(scratch.ensure(qr_scratch_bytes<R, CS, NTC, LG>(bt, batch)));
   CoopArgs ca{};
   ca.A = bt.A;
   ca.a_stride = bt.a_stride;
@@ -854,14 +868,21 @@ ffc_status launch_solve(const IdBatch& bt, int batch, QrScratch scratch, hipStre
 using QrLaunch = ffc_status (*)(const IdBatch&, int, QrScratch, hipStream_t, bool&);
 using QrBytes = size_t (*)(const IdBatch&, int);
 struct Variant {
-  int R, CS, threads;
+  int R, CS, threads, LG;
   QrLaunch fn;
   QrBytes bytes;
+  int rows() const { return R * LG; }   // the most rows a block may have
+  // 32-lane groups only for blocks that 16-lane groups cannot hold: the two
+  // sum rows in different orders, and every variant that a shape may use
+  // gives the same bits.
+  bool holds(int s_max) const { return s_max <= rows() && (LG == 16 || s_max > 16 * 32); }
 };
-#define FFC_VARIANT(R, CS, T) {R, CS, T, &launch_qr<R, CS, T>, &qr_scratch_bytes<R, CS, T>}
+#define FFC_VARIANT(R, CS, T, LG) {R, CS, T, LG, &launch_qr<R, CS, T, LG>, &qr_scratch_bytes<R, CS, T, LG>}
 const Variant kVariants[] = {
-    FFC_VARIANT(32, 2, 512), FFC_VARIANT(32, 2, 256), FFC_VARIANT(32, 1, 512), FFC_VARIANT(32, 1, 256),
-    FFC_VARIANT(32, 1, 128), FFC_VARIANT(16, 1, 512), FFC_VARIANT(16, 1, 128),
+    FFC_VARIANT(32, 2, 512, 16), FFC_VARIANT(32, 2, 256, 16), FFC_VARIANT(32, 1, 512, 16),
+    FFC_VARIANT(32, 1, 256, 16), FFC_VARIANT(32, 1, 128, 16), FFC_VARIANT(16, 1, 512, 16),
+    FFC_VARIANT(16, 1, 128, 16), FFC_VARIANT(32, 2, 512, 32), FFC_VARIANT(32, 1, 512, 32),
+    FFC_VARIANT(32, 2, 256, 32), FFC_VARIANT(32, 1, 256, 32),
 };
 #undef FFC_VARIANT
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
@@ -884,7 +905,7 @@ bool autotune_enabled() {
 // file on first use and every new one is appended, so later processes on the
 // same kind of device skip the timing. One line per choice: device key
 // (architecture name and compute-unit count), s_max, n_max, batch, rank cap,
-// rows per lane, columns per lane group, threads, best us. Lines for other
+// the most rows the variant holds, columns per lane group, threads, best us. Lines for other
 // devices or unknown variants are ignored.
 std::string device_key() {
   int dev = 0, cus = 0;
@@ -899,9 +920,9 @@ std::string device_key() {
 
 bool g_cache_loaded = false;
 
-int variant_index(int R, int CS, int threads) {
+int variant_index(int rows, int CS, int threads) {
   for (int v = 0; v < kNumVariants; ++v)
-    if (kVariants[v].R == R && kVariants[v].CS == CS && kVariants[v].threads == threads) return v;
+    if (kVariants[v].rows() == rows && kVariants[v].CS == CS && kVariants[v].threads == threads) return v;
   return -1;
 }
 
@@ -937,7 +958,7 @@ void append_tune_cache(const TuneEntry& te) {
   if (!f) return;
   const Variant& v = kVariants[te.choice];
   std::fprintf(f, "%s %d %d %d %d %d %d %d %.1f\n", device_key().c_str(), te.s_max, te.n_max, te.batch, te.max_rank,
-               v.R, v.CS, v.threads, te.best_us);
+               v.rows(), v.CS, v.threads, te.best_us);
   std::fclose(f);
 }
 
@@ -1009,7 +1030,7 @@ int tuned_choice(const IdBatch& bt, int batch) {
   // every variant this way; the variants give the same bits).
   if (const char* fv = std::getenv("FFC_QR_VARIANT")) {
     const int v = std::atoi(fv);
-    if (v >= 0 && v < kNumVariants && bt.s_max <= 16 * kVariants[v].R) choice = v;
+    if (v >= 0 && v < kNumVariants && kVariants[v].holds(bt.s_max)) choice = v;
   }
   return choice;
 }
@@ -1023,7 +1044,7 @@ ffc_status launch_interp_decomp_coop(const IdBatch& bt, int batch, DevBuf<unsign
   if (mfma_solve_lds_bytes(solve_rank_bound(bt), bt.n_max) > 150 * 1024) return FFC_OK;
   std::vector<int> cand;
   for (int v = 0; v < kNumVariants; ++v)
-    if (bt.s_max <= 16 * kVariants[v].R) cand.push_back(v);
+    if (kVariants[v].holds(bt.s_max)) cand.push_back(v);
   if (cand.empty()) return FFC_OK;
   int choice = tuned_choice(bt, batch);
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1067,7 +1088,7 @@ ffc_status launch_interp_decomp_fixed(const IdBatch& bt, int batch, unsigned cha
   std::vector<int> order;
   if (choice >= 0) order.push_back(choice);
   for (int v = 0; v < kNumVariants; ++v)
-    if (v != choice && bt.s_max <= 16 * kVariants[v].R) order.push_back(v);
+    if (v != choice && kVariants[v].holds(bt.s_max)) order.push_back(v);
   QrScratch scratch;
   scratch.fixed = fixed;
   scratch.fixed_bytes = fixed_bytes;
@@ -1104,7 +1125,7 @@ int autotune_entries(int32_t* out, int cap) {
     o[1] = te.n_max;
     o[2] = te.batch;
     o[3] = te.max_rank;
-    o[4] = kVariants[te.choice].R * 100 + kVariants[te.choice].CS;
+    o[4] = kVariants[te.choice].rows() * 100 + kVariants[te.choice].CS;
     o[5] = kVariants[te.choice].threads;
     o[6] = (int32_t)te.best_us;
     o[7] = te.from_cache ? -1 : (int32_t)te.first_us;

@@ -52,7 +52,7 @@ extern "C" ffc_status ffc_interp_decomp_noalloc(double* A_dev, int32_t batch, in
                                                 void* stream) {
   if (batch < 0) return fail(FFC_ERR_INVALID_ARG, "batch must be >= 0");
   if (s < 1 || n < 1) return fail(FFC_ERR_INVALID_ARG, "s and n must be >= 1");
-  if (s > 512) return fail(FFC_ERR_INVALID_ARG, "s above 512 needs the streamed QR, which allocates");
+  if (s > 1024) return fail(FFC_ERR_INVALID_ARG, "s above 1024 needs the streamed QR, which allocates");
   if (max_rank < 1) return fail(FFC_ERR_INVALID_ARG, "max_rank must be >= 1");
   if (!(tol >= 0.0)) return fail(FFC_ERR_INVALID_ARG, "tol must be >= 0");
   if (batch == 0) return FFC_OK;

@@ -698,7 +698,7 @@ def autotune_report() -> list:
     for e in range(cnt.value):
         rec = dict(zip(keys, map(int, buf[8 * e:8 * e + 8])))
         v = rec.pop("variant")
-        rec["rows_per_lane"], rec["cols_per_lane_group"] = v // 100, v % 100
+        rec["max_rows"], rec["cols_per_lane_group"] = v // 100, v % 100
         rec["from_cache"] = rec["first_us"] < 0
         out.append(rec)
     return out

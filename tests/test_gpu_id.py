@@ -90,14 +90,16 @@ def test_polynomial_exact_rank(ffc, p, expected):
     assert np.linalg.norm(K - K[:, pv] @ P[0].cpu().numpy()[:r]) / np.linalg.norm(K) < 1e-9
 
 
-@pytest.mark.parametrize("s,n,tol,max_rank", [(512, 512, 1e-5, 256), (256, 600, 1e-6, 128), (100, 40, 1e-8, 40)])
+@pytest.mark.parametrize("s,n,tol,max_rank", [(512, 512, 1e-5, 256), (256, 600, 1e-6, 128), (100, 40, 1e-8, 40),
+                                              (1024, 700, 1e-6, 200), (700, 130, 1e-9, 130)])
 def test_every_qr_variant_gives_the_same_bits(ffc, monkeypatch, s, n, tol, max_rank):
-    """Each register-resident QR variant (rows per lane, columns per lane group,
-    workgroup size) that can hold the blocks, forced in turn, gives the same
-    rank, pivots and P, and those match the oracle."""
+    """Each register-resident QR variant (lanes and rows per column, columns
+    per lane group, workgroup size) that may take the blocks (16-lane groups up
+    to 512 rows, 32-lane groups above), forced in turn, gives the same rank,
+    pivots and P, and those match the oracle."""
     mats = np.stack([decaying(s, n, seed) for seed in (11, 12)])
     ref = None
-    for v in range(7):   # every entry of the QR variant table
+    for v in range(11):   # every entry of the QR variant table
         monkeypatch.setenv("FFC_QR_VARIANT", str(v))
         rank, piv, P = (x.cpu().numpy() for x in ffc.interp_decomp(mats, tol, max_rank))
         if ref is None:
@@ -133,7 +135,7 @@ def test_autotune_cache_persists_choices(ffc, tmp_path, monkeypatch):
     assert len(lines) == 1 and lines[0].split()[1:5] == ["300", "200", "6", "96"]
     assert len(rep0) == 1 and not rep0[0]["from_cache"]
     assert len(rep1) == 1 and rep1[0]["from_cache"]
-    for key in ("rows_per_lane", "cols_per_lane_group", "threads"):
+    for key in ("max_rows", "cols_per_lane_group", "threads"):
         assert rep0[0][key] == rep1[0][key]
     np.testing.assert_array_equal(r0, r1)
     np.testing.assert_array_equal(p0, p1)

@@ -41,7 +41,8 @@ def test_noalloc_id_matches_the_allocating_call(monkeypatch):
     assert torch.cuda.is_available()
     lib = ffc.load_library()
     stream = torch.cuda.Stream()
-    cases = [(5, 300, 200, 1e-7, 96), (3, 120, 72, 1e-6, 40)]   # the second call on smaller blocks
+    # The second call on smaller blocks; a third with more than 512 rows (32-lane groups).
+    cases = [(5, 300, 200, 1e-7, 96), (3, 120, 72, 1e-6, 40), (2, 900, 160, 1e-7, 80)]
     for i, (b, s, n, tol, mr) in enumerate(cases):
         mats = np.stack([decaying(s, n, 10 * i + j) for j in range(b)])
         ref = run(lib, "ffc_interp_decomp", mats, tol, mr, stream)
@@ -64,14 +65,14 @@ def test_noalloc_id_matches_the_allocating_call(monkeypatch):
 def test_noalloc_id_refuses_what_it_cannot_hold():
     from paper_1409_2802_amd import ffc
     lib = ffc.load_library()
-    A = torch.zeros((600, 8), dtype=torch.float64, device="cuda")
+    A = torch.zeros((1100, 8), dtype=torch.float64, device="cuda")
     r = torch.zeros(1, dtype=torch.int32, device="cuda")
     pv = torch.zeros(8, dtype=torch.int32, device="cuda")
     P = torch.zeros((8, 8), dtype=torch.float64, device="cuda")
     ptrs = [ctypes.c_void_p(t.data_ptr()) for t in (A, r, pv, P)]
-    assert lib.ffc_interp_decomp_noalloc(ptrs[0], 1, 600, 8, 1e-6, 8, ptrs[1], ptrs[2], ptrs[3], None) == \
+    assert lib.ffc_interp_decomp_noalloc(ptrs[0], 1, 1100, 8, 1e-6, 8, ptrs[1], ptrs[2], ptrs[3], None) == \
         ffc.FFC_ERR_INVALID_ARG
-    assert b"512" in lib.ffc_last_error()
+    assert b"1024" in lib.ffc_last_error()
     # More 512 x 512 blocks than the fixed scratch holds.
     assert lib.ffc_interp_decomp_noalloc(ptrs[0], 4000, 512, 512, 1e-6, 256, ptrs[1], ptrs[2], ptrs[3], None) == \
         ffc.FFC_ERR_INVALID_ARG
