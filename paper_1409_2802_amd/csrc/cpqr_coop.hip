@@ -26,13 +26,14 @@
 // every workgroup, far below the rounding of the factorization. Slots are
 // cleared before every launch; a slot read at step k can otherwise only hold
 // step k - 2, whose tag differs.
-// Row k of every active column is final after step k: the lane holding it
-// stores it to A. The register block that holds row k is kept in its own
-// register (cur) and is zero in the block array, as are the blocks above, so
-// norms and reflector products over the array need no row masks, and the
-// current block's finished rows are masked by lane. The pivot column of step
-// k is frozen in place (its rows 0..k-1 are already stored, row k gets
-// alpha), so no columns are swapped; the pivot order is recorded. A ends with
+// Row k of every active column is final after step k. The register block
+// that holds row k is kept in its own register (cur) and is zero in the block
+// array, as are the blocks above, so norms and reflector products over the
+// array need no row masks, and the current block's finished rows are masked
+// by lane; when the next block takes its place, the finished block goes to A
+// as one contiguous segment per column. The pivot column of step k is frozen
+// in place (its rows 0..k-1 go to A with their blocks, row k gets alpha), so
+// no columns are swapped; the pivot order is recorded. A ends with
 // R(0:l+1, l) in column piv[l] and R(0:r, j) in rows 0..r-1 of every other
 // column j.
 //
@@ -231,6 +232,9 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       for (int m = 0; m < RL; ++m) a[c][m] = (jin && m < mlim) ? colp[LG * m] : 0.0;
     }
     unsigned int done = 0u;   // bit c: column col0 + c is a frozen pivot
+    int kfz[CS];              // the step at which column col0 + c was frozen
+#pragma unroll
+    for (int c = 0; c < CS; ++c) kfz[c] = INT_MAX;
 
     // The register block that holds row k (block kb = k / LG, rows
     // LG kb + lg) lives in cur[] instead of a[][kb], which is kept zero
@@ -248,6 +252,16 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       a[c][0] = 0.0;
     }
     int kb = 0;
+    // R rows leave the registers a block at a time: the finished rows of the
+    // current block (those below lim) go to A as one contiguous LG-row
+    // segment per column, instead of one scattered word per row and step.
+    auto store_block = [&](int lim) {
+#pragma unroll
+      for (int c = 0; c < CS; ++c) {
+        const int j = col0 + c, row = LG * kb + lg;
+        if (j < n && row < min(lim, kfz[c])) A[(uint32_t)(j * ca.lda + row)] = cur[c];
+      }
+    };
     // Norm of the rows at or below row kk (kk in the current block or the
     // first row of the next one).
     auto active_norm = [&](int c, int kk) -> double {
@@ -440,11 +454,12 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       const double xk = s_xk;
       const double alpha = xk != 0.0 ? -copysign(rho, xk) : -rho;
       if (k > 0 && k % LG == 0) {
-        // Row k opens register block kb + 1: its rows move into cur (the old
-        // block's rows are all stored in A) and a[][kb + 1] becomes zero,
-        // once every LG steps. Straight-line selects against a per-lane copy
-        // of the block index: branches on it would merge every register of
-        // a[][] at their joins.
+        // Row k opens register block kb + 1: the old block's rows, all final,
+        // go to A; the new block's rows move into cur and a[][kb + 1] becomes
+        // zero, once every LG steps. Straight-line selects against a per-lane
+        // copy of the block index: branches on it would merge every register
+        // of a[][] at their joins.
+        store_block(k);
         ++kb;
         int kbv;
         asm volatile("v_mov_b32 %0, %1" : "=v"(kbv) : "s"(kb));
@@ -483,6 +498,7 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
         for (int c = 0; c < CS; ++c)
           if (col0 + c == porig) {
             done |= 1u << c;
+            kfz[c] = k;
             if (lg == (k & (LG - 1))) A[(uint32_t)(porig * ca.lda + k)] = alpha;
           }
         if (threadIdx.x == 0) pivb[k] = porig;
@@ -500,21 +516,18 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
 #pragma unroll
         for (int c = 0; c < CS; ++c) a[c][m] = fma(-v[m], coef[c], a[c][m]);
       }
-      // Row k of the active columns is now final, R(k, j): the lane that
-      // holds it stores it where the solve reads R. (It stays in cur; the
-      // norms and products of later steps leave it out.)
+      // Row k of the active columns is now final, R(k, j). It stays in cur
+      // (the norms and products of later steps leave it out) until its block
+      // is stored.
 #pragma unroll
-      for (int c = 0; c < CS; ++c) {
-        cur[c] = fma(-vcur, coef[c], cur[c]);
-        const int j = col0 + c;
-        if (lg == (k & (LG - 1)) && j < n && !(done & (1u << c))) A[(uint32_t)(j * ca.lda + k)] = cur[c];
-      }
+      for (int c = 0; c < CS; ++c) cur[c] = fma(-vcur, coef[c], cur[c]);
       publish(k + 1);
       alive = poll(k + 1, gwin, porig);
       if (alive && porig != INT_MAX && k + 1 < kmax) alive = load_winner(k + 1, gwin);
       nv = s_nv;
     }
     if (!alive) return;   // timed out: the device flag reports it
+    store_block(k);       // the rows 0..k-1 of the last block
     if (g == 0 && threadIdx.x == 0) ca.rank[b] = k;
   }
 }
