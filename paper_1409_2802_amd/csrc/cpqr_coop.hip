@@ -491,8 +491,8 @@ __global__ void __launch_bounds__(NTC, 2) k_cpqr_coop(CoopArgs ca) {
       // alpha = -sign(x_k) rho, so v^T v = 2 rho (rho + |x_k|).
       const double vv = 2.0 * rho * (rho + fabs(xk));
       const double beta = vv > 0.0 ? 2.0 / vv : 0.0;
-      // Freeze the pivot column: its rows 0..k-1 already hold R in A (stored
-      // step by step below), row k gets alpha.
+      // Freeze the pivot column: its rows 0..k-1 go to A with their blocks,
+      // row k gets alpha now.
       if (g == gwin) {
 #pragma unroll
         for (int c = 0; c < CS; ++c)
