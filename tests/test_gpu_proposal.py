@@ -44,8 +44,9 @@ def f32(x):
     return np.asarray(x, dtype=np.float32).astype(np.float64)
 
 
-def test_features_match_oracle(ffc):
-    X = W.gaussian_mixture(3000, 6, k=8, box=6.0, std=0.5, seed=0)
+@pytest.mark.parametrize("d", [6, 64, 100])
+def test_features_match_oracle(ffc, d):
+    X = W.gaussian_mixture(3000, d, k=8, box=6.0, std=0.5, seed=0)
     t, ot = trees(ffc, X, 200)
     Xt = X[ot.perm]
     rng = np.random.default_rng(4)
