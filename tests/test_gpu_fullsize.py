@@ -17,7 +17,8 @@ Laplace trees (N = 65536, d = 3; treecode at separation 2, FMM-style at 1);
 highdim1000 / highdim1000g (N = 65536, d = 1000) in mixed precision on 64
 seeded random nodes; subspace64 (N = 262144, d = 64, Laplace) in mixed
 precision on sampled leaves; learned64 (the same points, Gaussian h = 1,
-learned proposal, mixed) on sampled nodes."""
+learned proposal, mixed) on sampled nodes, and the same points with 1024
+sampled rows (uniform, mixed)."""
 import numpy as np
 import pytest
 import torch
@@ -251,6 +252,34 @@ def test_learned64_sampled_nodes(ffc):
         check_node_reduced(g, o_rows, Xt, ok, kerr)
     assert exact >= 10
     print("learned64 sampled nodes with the oracle's exact rows:", exact)
+
+
+def test_learned64_points_1024_rows(ffc):
+    """The learned64 points with 1024 sampled rows per node (4x the rank cap, the register-resident QR's 32-lane
+    groups): N=262144, d=64, Gaussian h=1, leaf 1024, rank cap 256, uniform rows, mixed precision. On 4 sampled
+    leaves and 1 node of every other level the rows equal the oracle's, and the GPU's skeleton reconstructs the
+    exact FP64 block of those rows within the mixed kernel error."""
+    N, d = 262144, 64
+    X = W.low_intrinsic(N, d, di=8, noise=1e-2, seed=0)
+    gk, ok = gkernel(GAUSSIAN, h=1.0), okernel(GAUSSIAN, h=1.0)
+    t = ffc.build_tree(X, 1024)
+    sk = ffc.skeletonize(t, gk, tol=1e-6, max_rank=256, num_samples=1024, seed=0, precision=ffc.MIXED_BF16X3)
+    ffc.check_device()
+    ot = o_build_tree(X, 1024)
+    Xt = X[ot.perm]
+    rng = np.random.default_rng(10)
+    picks = []
+    for level in range(ot.depth, 0, -1):
+        nodes = list(ot.level_nodes(level))
+        picks += [int(a) for a in rng.choice(nodes, 4 if level == ot.depth else 1, replace=False)]
+    gnodes = {a: sk.node(a) for a in picks}
+    onodes = oracle_nodes([lambda a=a: skeletonize_node(Xt, ot, a, node_cols(gnodes[a]), ok, 1e-6, 256, 1024, 0)
+                           for a in picks])
+    for a, o in zip(picks, onodes):
+        g = gnodes[a]
+        assert len(g["rows"]) == min(1024, ot.N - (int(ot.end[a]) - int(ot.begin[a])))
+        kerr = gram_kerr_gaussian(Xt[g["rows"]], Xt[node_cols(g)], ot.centroid[a], 1.0)
+        check_node_reduced(g, o, Xt, ok, kerr)
 
 
 @pytest.mark.parametrize("xi,fmm", [(2.0, False), (1.0, True)])
