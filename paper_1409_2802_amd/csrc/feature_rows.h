@@ -44,13 +44,17 @@ __device__ inline void finish_rows(const double* __restrict__ Xt, int d, const G
     if (t0 + row >= nt) continue;
     const double* y = Xt + (int64_t)tg[row] * d;
     double p = 0.0;
+    // (Unrolled so that many coordinates' loads are in flight at once; the
+    // sums stay sequential.)
     if (a == 0) {
+#pragma unroll 32
       for (int k = 0; k < d; ++k) {
         const double df = y[k] - c[k];
         p = fma(df, df, p);
       }
     } else {
       const double* u = U + (int64_t)(a - 1) * d;
+#pragma unroll 32
       for (int k = 0; k < d; ++k) p = fma(y[k] - c[k], u[k], p);
     }
     dots[row * (1 + kNAnch) + a] = p;

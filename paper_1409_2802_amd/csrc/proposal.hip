@@ -92,6 +92,7 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
   for (int j = tid; j < n; j += 256) {
     const double* x = Xt + (int64_t)cols[j] * d;
     double s = 0.0;
+#pragma unroll 16
     for (int k = 0; k < d; ++k) { const double df = x[k] - cen[k]; s = fma(df, df, s); }
     mx = fmax(mx, s);
   }
@@ -139,6 +140,7 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
     if (tid < ns) {
       const double* x = Xt + (int64_t)cols[sidx[tid]] * d;
       s = 0.0;
+#pragma unroll 16
       for (int k = 0; k < d; ++k) { const double df = x[k] - cen[k]; s = fma(df, df, s); }
     }
     sd2[tid] = s;
@@ -181,6 +183,7 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
       const double* x = Xt + (int64_t)cols[sidx[tid]] * d;
       const double* y = Xt + (int64_t)cols[sidx[anchors[a]]] * d;
       double s = 0.0;
+#pragma unroll 16
       for (int k = 0; k < d; ++k) { const double df = x[k] - y[k]; s = fma(df, df, s); }
       mind[tid] = a == 0 ? s : fmin(mind[tid], s);
     }
@@ -192,6 +195,7 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
     double nrm2 = 0.0;
     if (a < na) {
       const double* y = Xt + (int64_t)cols[sidx[anchors[a]]] * d;
+#pragma unroll 16
       for (int k = 0; k < d; ++k) { const double df = y[k] - cen[k]; nrm2 = fma(df, df, nrm2); }
     }
     const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
