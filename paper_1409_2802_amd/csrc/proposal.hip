@@ -66,6 +66,9 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
       const int k = e % d, part = e / d;
       double s0 = 0.0, s1 = 0.0;
       int j = part;
+      // (Unrolled so that many columns' index and coordinate loads are in
+      // flight at once; the two sums keep their order.)
+#pragma unroll 8
       for (; j + P < n; j += 2 * P) {
         s0 += Xt[(int64_t)cols[j] * d + k];
         s1 += Xt[(int64_t)cols[j + P] * d + k];
