@@ -18,7 +18,6 @@
 
 #include "ffc_internal.h"
 #include "feature_rows.h"
-#include "tile_engine.h"
 
 namespace ffc {
 namespace {
@@ -28,7 +27,7 @@ constexpr int NPARAM = NF * NH + NH + NH * NH + NH + NH + 1;   // 5313
 constexpr int OFF_W1 = 0, OFF_B1 = NF * NH, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH,
               OFF_B3 = OFF_W3 + NH;
 constexpr int SUB = feat::kSub;  // column subsample size
-constexpr int kMaxGeomCols = 16384;   // column-set bitmap capacity (512 words of LDS)
+constexpr int kMaxGeomCols = 16384;   // column-set capacity (the indices are held in 64 KiB of LDS)
 constexpr int NANCH = feat::kNAnch;
 constexpr uint64_t STREAM_SUBSAMPLE = 1ull << 30, STREAM_KEYS = 3ull << 30;
 
@@ -43,20 +42,54 @@ __device__ inline uint64_t counter_u64(uint64_t seed, uint64_t stream, uint64_t 
 }
 
 // ---------------------------------------------------------------------------
-// Column geometry: one workgroup per node.
+// Column geometry: one 256-thread workgroup per node. The node's column
+// indices go to LDS first, so that every coordinate load is a single hop; for
+// d <= kGeomStageD the subsample's coordinates are then staged in LDS as well
+// (rows padded to d + 1 doubles) and the anchor search and directions read
+// them there. Every sum keeps one fixed order: the centroid's as described
+// below, the squared distances sequential over the coordinates.
 // ---------------------------------------------------------------------------
+constexpr int kGeomStageD = 64;
+
+// Dynamic LDS of k_geometry: the centroid (d doubles), then the column indices
+// and the radius pass's four transposition tiles or, once they are no longer
+// needed, the staged subsample.
+size_t geometry_lds(int d, int64_t col_stride) {
+  const size_t idx = (size_t)((col_stride + 1) & ~1ll) * sizeof(int32_t) + 4 * 16 * 65 * sizeof(double);
+  const size_t sub = d <= kGeomStageD ? (size_t)SUB * (d + 1) * sizeof(double) : 0;
+  return (size_t)d * sizeof(double) + (idx > sub ? idx : sub);
+}
+
+// Max of v over the workgroup (exact in any order): shuffles, then the 4 waves.
+__device__ inline double block_max(double v, double* wred) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return fmax(fmax(wred[0], wred[1]), fmax(wred[2], wred[3]));
+}
+
 __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt, int d, GeomArgs ga) {
+  extern __shared__ double geo_dyn[];
+  double* scen = geo_dyn;                                   // [d]
+  int32_t* scol = reinterpret_cast<int32_t*>(geo_dyn + d);  // [n] column indices
+  double* sx = geo_dyn + d;                                  // [SUB][d + 1] staged subsample (after scol)
+  __shared__ __align__(16) int sval[SUB];
   __shared__ int sidx[SUB];
+  __shared__ int srej[SUB];
   __shared__ double sd2[SUB], mind[SUB];
   __shared__ double red[256];
-  __shared__ unsigned int bits[kMaxGeomCols / 32];
-  __shared__ int s_k, anchors[NANCH];
+  __shared__ double wred[4], snrm[NANCH];
+  __shared__ int s_changed, anchors[NANCH];
   const int b = blockIdx.x;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int n = ga.ncols[b];
   const int32_t* cols = ga.cols + (int64_t)b * ga.col_stride;
   double* cen = ga.cen + (int64_t)b * d;
   const uint64_t node = (uint64_t)ga.node_ids[b];
+  for (int j = tid; j < n; j += 256) scol[j] = cols[j];
+  __syncthreads();
   // Centroid: dimension k is summed in P interleaved column parts (part p
   // takes columns p, p + P, ...), each with two alternating accumulators, and
   // the parts are added in order (a fixed summation order).
@@ -66,16 +99,18 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
       const int k = e % d, part = e / d;
       double s0 = 0.0, s1 = 0.0;
       int j = part;
-      // (Unrolled so that many columns' index and coordinate loads are in
-      // flight at once; the two sums keep their order.)
-#pragma unroll 8
+      // (Unrolled so that many columns' coordinate loads are in flight at
+      // once; the two sums keep their order.)
+#pragma unroll 16
       for (; j + P < n; j += 2 * P) {
-        s0 += Xt[(int64_t)cols[j] * d + k];
-        s1 += Xt[(int64_t)cols[j + P] * d + k];
+        s0 += Xt[(int64_t)scol[j] * d + k];
+        s1 += Xt[(int64_t)scol[j + P] * d + k];
       }
-      if (j < n) s0 += Xt[(int64_t)cols[j] * d + k];
+      if (j < n) s0 += Xt[(int64_t)scol[j] * d + k];
       if (P == 1) {
-        cen[k] = n > 0 ? (s0 + s1) / n : 0.0;
+        const double c = n > 0 ? (s0 + s1) / n : 0.0;
+        cen[k] = c;
+        scen[k] = c;
       } else {
         red[e] = s0 + s1;
       }
@@ -85,143 +120,248 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
       for (int k = tid; k < d; k += 256) {
         double s = 0.0;
         for (int part = 0; part < P; ++part) s += red[part * d + k];
-        cen[k] = n > 0 ? s / n : 0.0;
+        const double c = n > 0 ? s / n : 0.0;
+        cen[k] = c;
+        scen[k] = c;
       }
       __syncthreads();
     }
   }
-  // Radius.
+  // Radius. Each wave takes 64 columns at a time, one per lane; their
+  // coordinates arrive in chunks of 16, loaded coalesced (16 lanes per
+  // column segment, the next chunk in flight) and transposed through the
+  // wave's own LDS tile, from which each lane sums its column's squared
+  // differences in order.
   double mx = 0.0;
-  for (int j = tid; j < n; j += 256) {
-    const double* x = Xt + (int64_t)cols[j] * d;
-    double s = 0.0;
+  {
+    const int wv = tid >> 6;
+    double* tw = reinterpret_cast<double*>(scol + ((ga.col_stride + 1) & ~1ll)) + wv * (16 * 65);   // [16][65]
+    const int nchunk = (d + 15) / 16, ngroup = (n + 255 - wv * 64) / 256;  // this wave's 64-column groups
+    const int steps = ngroup * nchunk;
+    int ci[16];
+    double r[16];
+    auto load = [&](int st) {
+      const int g = st / nchunk, ch = st - g * nchunk, c0 = wv * 64 + g * 256, k = ch * 16 + (lane & 15);
+      if (ch == 0)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int cc = c0 + 4 * i + (lane >> 4);
+          ci[i] = cc < n ? scol[cc] : -1;
+        }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) r[i] = ci[i] >= 0 && k < d ? Xt[(int64_t)ci[i] * d + k] : 0.0;
+    };
+    double sq = 0.0;
+    if (steps > 0) load(0);
+    for (int st = 0; st < steps; ++st) {
+      const int g = st / nchunk, ch = st - g * nchunk;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) tw[(lane & 15) * 65 + 4 * i + (lane >> 4)] = r[i];
+      __builtin_amdgcn_wave_barrier();
+      if (st + 1 < steps) load(st + 1);
+      const int kc = min(16, d - ch * 16);
 #pragma unroll 16
-    for (int k = 0; k < d; ++k) { const double df = x[k] - cen[k]; s = fma(df, df, s); }
-    mx = fmax(mx, s);
-  }
-  red[tid] = mx;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
-    __syncthreads();
-  }
-  // Subsample: Floyd's algorithm over {0..n-1} (values t_j drawn in parallel,
-  // the insert rule applied in order against an LDS bitmap), then ascending.
-  const int nwords = (min(n, kMaxGeomCols) + 31) / 32;
-  for (int w = tid; w < nwords; w += 256) bits[w] = 0u;
-  if (n > SUB)
-    for (int q = tid; q < SUB; q += 256) {
-      const int j = n - SUB + q;
-      sidx[q] = (int)__umul64hi(counter_u64(ga.seed, node | STREAM_SUBSAMPLE, (uint64_t)j), (uint64_t)(j + 1));
+      for (int kk = 0; kk < kc; ++kk) {
+        const double df = tw[kk * 65 + lane] - scen[ch * 16 + kk];
+        sq = fma(df, df, sq);
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (ch == nchunk - 1) {
+        if (wv * 64 + g * 256 + lane < n) mx = fmax(mx, sq);
+        sq = 0.0;
+      }
     }
-  __syncthreads();
+  }
+  mx = block_max(mx, wred);
   if (tid == 0) {
-    const double r = sqrt(red[0]);
+    const double r = sqrt(mx);
     ga.rho[b] = r > 0.0 ? r : 1.0;
-    int cnt = 0;
-    if (n <= SUB) {
-      for (int j = 0; j < n; ++j) sidx[cnt++] = j;
-    } else {
-      for (int q = 0; q < SUB; ++q) {
-        int t = sidx[q];
-        if (bits[t >> 5] & (1u << (t & 31))) t = n - SUB + q;
-        bits[t >> 5] |= 1u << (t & 31);
-      }
-      for (int w = 0; w < nwords; ++w)
-        for (unsigned int word = bits[w]; word; word &= word - 1) sidx[cnt++] = w * 32 + __ffs(word) - 1;
-    }
-    s_k = cnt;
   }
-  __syncthreads();
-  const int ns = s_k;
-  int32_t* S_out = ga.sub + (int64_t)b * SUB;
-  for (int q = tid; q < SUB; q += 256) S_out[q] = q < ns ? cols[sidx[q]] : -1;
-  if (tid == 0) ga.nsub[b] = ns;
-  // Anchors: farthest-point selection, starting from the point farthest from c.
-  if (tid < SUB) {
-    double s = -1.0;
-    if (tid < ns) {
-      const double* x = Xt + (int64_t)cols[sidx[tid]] * d;
-      s = 0.0;
-#pragma unroll 16
-      for (int k = 0; k < d; ++k) { const double df = x[k] - cen[k]; s = fma(df, df, s); }
-    }
-    sd2[tid] = s;
-  }
-  __syncthreads();
-  const int na = min(NANCH, ns);
-  __shared__ double wbv[4];
-  __shared__ int wbi[4];
-  for (int a = 0; a < na; ++a) {
-    // Arg-max of the key over the subsample, ties to the smaller index: per
-    // wavefront by shuffles, then over the four wavefronts.
-    const double* key = a == 0 ? sd2 : mind;
-    double bv = tid < ns ? key[tid] : -INFINITY;
-    int bi = tid < ns ? tid : INT_MAX;
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
-    if ((tid & 63) == 0) {
-      wbv[tid >> 6] = bv;
-      wbi[tid >> 6] = bi;
+  // Subsample: Floyd's algorithm over {0..n-1}. Step q draws t_q in
+  // [0, n - SUB + q] and takes t_q unless it is already taken, else
+  // n - SUB + q. t_q is taken before step q exactly when an earlier draw
+  // equals it, or when t_q = n - SUB + p for an earlier step p that was
+  // itself refused; the refusals are resolved from the first rule by
+  // propagating the second to a fixed point. The taken values are then put in
+  // ascending order by counting.
+  const int ns = min(n, SUB);
+  if (n > SUB) {
+    int t = 0;
+    if (tid < SUB) {
+      const int j = n - SUB + tid;
+      t = (int)__umul64hi(counter_u64(ga.seed, node | STREAM_SUBSAMPLE, (uint64_t)j), (uint64_t)(j + 1));
+      sval[tid] = t;
     }
     __syncthreads();
-    if (tid == 0) {
-      double v = wbv[0];
+    if (tid < SUB) {
+      int dup = 0;
+      const int4* s4 = reinterpret_cast<const int4*>(sval);
+      for (int p = 0; p < (tid + 3) / 4; ++p) {
+        const int4 w = s4[p];
+        dup |= (w.x == t) | ((4 * p + 1 < tid) & (w.y == t)) | ((4 * p + 2 < tid) & (w.z == t)) |
+               ((4 * p + 3 < tid) & (w.w == t));
+      }
+      srej[tid] = dup;
+    }
+    const int pq = t - (n - SUB);   // the earlier step whose fallback value equals t_q, if 0 <= pq < q
+    for (;;) {
+      if (tid == 0) s_changed = 0;
+      __syncthreads();
+      if (tid < SUB && !srej[tid] && pq >= 0 && pq < tid && srej[pq]) {
+        srej[tid] = 1;
+        s_changed = 1;
+      }
+      __syncthreads();
+      const int more = s_changed;
+      __syncthreads();
+      if (!more) break;
+    }
+    const int v = srej[tid < SUB ? tid : 0] ? n - SUB + tid : t;
+    if (tid < SUB) sval[tid] = v;
+    __syncthreads();
+    if (tid < SUB) {
+      int rank = 0;
+      const int4* s4 = reinterpret_cast<const int4*>(sval);
+#pragma unroll 8
+      for (int p = 0; p < SUB / 4; ++p) {
+        const int4 w = s4[p];
+        rank += (w.x < v) + (w.y < v) + (w.z < v) + (w.w < v);
+      }
+      sidx[rank] = v;
+    }
+  } else if (tid < ns) {
+    sidx[tid] = tid;
+  }
+  __syncthreads();
+  if (tid < ns) sval[tid] = scol[sidx[tid]];   // tree positions of the subsample
+  int32_t* S_out = ga.sub + (int64_t)b * SUB;
+  if (tid < SUB) S_out[tid] = tid < ns ? scol[sidx[tid]] : -1;
+  if (tid == 0) ga.nsub[b] = ns;
+  __syncthreads();
+  // Stage the subsample (the column indices are dead from here on).
+  const bool staged = d <= kGeomStageD;
+  if (staged) {
+    const int wv = tid >> 6;
+    if (lane < d)
+#pragma unroll 8
+      for (int q = wv; q < ns; q += 4) sx[q * (d + 1) + lane] = Xt[(int64_t)sval[q] * d + lane];
+    __syncthreads();
+  }
+  // The anchor search and directions, instantiated for LDS rows and for
+  // global rows (so that the LDS instance compiles to LDS loads).
+  __shared__ int wbi[4];
+  const int na = min(NANCH, ns);
+  auto search = [&](auto xrow) {
+    // Anchors: farthest-point selection, starting from the point farthest from c.
+    if (tid < SUB) {
+      double sq = -1.0;
+      if (tid < ns) {
+        const double* x = xrow(tid);
+        sq = 0.0;
+#pragma unroll 16
+        for (int k = 0; k < d; ++k) {
+          const double df = x[k] - scen[k];
+          sq = fma(df, df, sq);
+        }
+      }
+      sd2[tid] = sq;
+    }
+    __syncthreads();
+    for (int a = 0; a < na; ++a) {
+      // Arg-max of the key over the subsample, ties to the smaller index: per
+      // wavefront by shuffles, then over the four wavefronts.
+      const double* key = a == 0 ? sd2 : mind;
+      double bv = tid < ns ? key[tid] : -INFINITY;
+      int bi = tid < ns ? tid : INT_MAX;
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        wred[tid >> 6] = bv;
+        wbi[tid >> 6] = bi;
+      }
+      __syncthreads();
+      double v = wred[0];
       int i = wbi[0];
       for (int q = 1; q < 4; ++q)
-        if (wbv[q] > v || (wbv[q] == v && wbi[q] < i)) {
-          v = wbv[q];
+        if (wred[q] > v || (wred[q] == v && wbi[q] < i)) {
+          v = wred[q];
           i = wbi[q];
         }
-      anchors[a] = i;
+      if (tid == 0) anchors[a] = i;
+      if (tid < ns) {
+        const double* x = xrow(tid);
+        const double* y = xrow(i);
+        double sq = 0.0;
+#pragma unroll 16
+        for (int k = 0; k < d; ++k) {
+          const double df = x[k] - y[k];
+          sq = fma(df, df, sq);
+        }
+        mind[tid] = a == 0 ? sq : fmin(mind[tid], sq);
+      }
+      __syncthreads();
+    }
+    // Anchor directions: the norms one thread each, then the unit vectors.
+    if (tid < na) {
+      const double* y = xrow(anchors[tid]);
+      double nrm2 = 0.0;
+#pragma unroll 16
+      for (int k = 0; k < d; ++k) {
+        const double df = y[k] - scen[k];
+        nrm2 = fma(df, df, nrm2);
+      }
+      snrm[tid] = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
     }
     __syncthreads();
-    if (tid < ns) {
-      const double* x = Xt + (int64_t)cols[sidx[tid]] * d;
-      const double* y = Xt + (int64_t)cols[sidx[anchors[a]]] * d;
-      double s = 0.0;
-#pragma unroll 16
-      for (int k = 0; k < d; ++k) { const double df = x[k] - y[k]; s = fma(df, df, s); }
-      mind[tid] = a == 0 ? s : fmin(mind[tid], s);
+    double* U = ga.U + (int64_t)b * NANCH * d;
+    for (int a = 0; a < NANCH; ++a) {
+      const double* y = a < na ? xrow(anchors[a]) : nullptr;
+      for (int k = tid; k < d; k += 256) U[(int64_t)a * d + k] = a < na ? (y[k] - scen[k]) * snrm[a] : 0.0;
     }
-    __syncthreads();
-  }
-  // Anchor directions.
-  double* U = ga.U + (int64_t)b * NANCH * d;
-  for (int a = 0; a < NANCH; ++a) {
-    double nrm2 = 0.0;
-    if (a < na) {
-      const double* y = Xt + (int64_t)cols[sidx[anchors[a]]] * d;
-#pragma unroll 16
-      for (int k = 0; k < d; ++k) { const double df = y[k] - cen[k]; nrm2 = fma(df, df, nrm2); }
-    }
-    const double inv = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-    for (int k = tid; k < d; k += 256)
-      U[(int64_t)a * d + k] = a < na ? (Xt[(int64_t)cols[sidx[anchors[a]]] * d + k] - cen[k]) * inv : 0.0;
-  }
+  };
+  if (staged)
+    search([&](int q) -> const double* { return sx + q * (d + 1); });
+  else
+    search([&](int q) -> const double* { return Xt + (int64_t)sval[q] * d; });
 }
 
 // ---------------------------------------------------------------------------
-// Features: one 256-thread workgroup per 64 targets of a block. Distances to
-// the subsample come from the shared tile engine (64 x 64 tiles, FP64 explicit
-// differences); each thread keeps the 4 smallest distances and the sum for
-// its 4 rows over its columns, merged across the 16 threads of a row in a
-// fixed order (lanes 16 apart by shuffles, then the 4 waves through LDS).
+// Features: one 256-thread workgroup per 64 targets of a block. The distances
+// to the column subsample are formed in passes of 16 JT subsample points:
+// thread (tr, tc) = (tid % 16, tid / 16) owns targets tr + 16 i (i < 4) and
+// points tc + 16 j (j < JT) of the pass and sums FP64 explicit differences
+// over the coordinates, which pass through a double-buffered LDS tile 16 at a
+// time while the next 16 are being loaded (coordinates past d are staged as
+// zeros and add exact zeros). Each thread keeps the 4 smallest distances and
+// the sum over its points (tc + 16 m, m ascending), merged across the 16
+// threads of a row in a fixed order: lanes 16 apart by shuffles, then the 4
+// waves through LDS.
 // ---------------------------------------------------------------------------
 using feat::insert4;
 
+constexpr int FT = 64, FK = 16;   // targets per workgroup, coordinates per staged chunk
+
+template <int JT>
+struct FeatSmem {
+  double ys[2][FK][FT + 1];
+  double xs[2][FK][16 * JT + 1];
+};
+
+template <int JT>
 __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt, int d, GeomArgs ga,
                                                   const int32_t* __restrict__ tgt, int tgt_stride,
                                                   const int32_t* __restrict__ ntgt, int tiles,
                                                   float* __restrict__ feat, int64_t feat_stride) {
-  __shared__ tile::TileSmem<double> sm;
-  const int b = blockIdx.x / tiles, t0 = (blockIdx.x % tiles) * 64;
+  constexpr int FP = 16 * JT;   // subsample points per pass
+  constexpr int YE = FT * FK / 256, XE = FP * FK / 256;   // staged elements per thread
+  __shared__ FeatSmem<JT> sm;
+  const int b = blockIdx.x / tiles, t0 = (blockIdx.x % tiles) * FT;
   const int nt = ntgt[b];
   if (t0 >= nt) return;
   const int ns = ga.nsub[b];
@@ -229,26 +369,78 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
   const int32_t* S = ga.sub + (int64_t)b * SUB;
   const int32_t* tg = tgt + (int64_t)b * tgt_stride + t0;
   const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
-  double best[4][4], sum[4];
+  const int nrow = min(FT, nt - t0);
+  // Staged element e = tid + 256 it is row e / FK, coordinate e % FK of the
+  // chunk: a thread's rows are fixed (tc + 16 it), its coordinate is tr.
+  int yrow[YE];
+#pragma unroll
+  for (int it = 0; it < YE; ++it) yrow[it] = tc + 16 * it < nrow ? tg[tc + 16 * it] : -1;
+  double best[4][4], sum[4], acc[4][JT];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     sum[i] = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) best[i][q] = INFINITY;
+#pragma unroll
+    for (int j = 0; j < JT; ++j) acc[i][j] = 0.0;
   }
-  for (int c0 = 0; c0 < ns; c0 += 64) {
-    double acc[4][4];
-    tile::tile_accumulate<double, false>(Xt, tile::IdxMap{tg, 0}, nt - t0, Xt, tile::IdxMap{S + c0, 0}, ns - c0, d,
-                                         sm, acc);
+  const int nchunk = (d + FK - 1) / FK, npass = (ns + FP - 1) / FP, total = npass * nchunk;
+  double ry[YE], rx[XE];
+  auto load = [&](int q) {
+    const int c = (q / nchunk) * FP, k = (q % nchunk) * FK + tr;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int it = 0; it < YE; ++it) ry[it] = yrow[it] >= 0 && k < d ? Xt[(int64_t)yrow[it] * d + k] : 0.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (c0 + tc + 16 * j < ns) {
-          const double dist = sqrt(acc[i][j]) / rho;
-          sum[i] += dist;
-          insert4(best[i], dist);
+    for (int it = 0; it < XE; ++it) {
+      const int r = c + tc + 16 * it;
+      rx[it] = r < ns && k < d ? Xt[(int64_t)S[r] * d + k] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int it = 0; it < YE; ++it) sm.ys[buf][tr][tc + 16 * it] = ry[it];
+#pragma unroll
+    for (int it = 0; it < XE; ++it) sm.xs[buf][tr][tc + 16 * it] = rx[it];
+  };
+  if (total > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int q = 0; q < total; ++q) {
+    const int buf = q & 1;
+    if (q + 1 < total) load(q + 1);
+#pragma unroll
+    for (int kk = 0; kk < FK; ++kk) {
+      double av[4], bv[JT];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = sm.ys[buf][kk][tr + 16 * i];
+#pragma unroll
+      for (int j = 0; j < JT; ++j) bv[j] = sm.xs[buf][kk][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < JT; ++j) {
+          const double df = av[i] - bv[j];
+          acc[i][j] = fma(df, df, acc[i][j]);
         }
+    }
+    if (q % nchunk == nchunk - 1) {   // the pass is complete
+      const int c = (q / nchunk) * FP;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < JT; ++j) {
+          if (c + tc + 16 * j < ns) {
+            const double dist = sqrt(acc[i][j]) / rho;
+            sum[i] += dist;
+            insert4(best[i], dist);
+          }
+          acc[i][j] = 0.0;
+        }
+    }
+    if (q + 1 < total) store(buf ^ 1);
+    __syncthreads();
   }
   // Merge the 4 threads of a row inside the wave (lanes tr + 16 q).
 #pragma unroll
@@ -264,7 +456,8 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
 #pragma unroll
       for (int q = 0; q < 4; ++q) insert4(best[i], o[q]);
     }
-  // Then the 4 waves, through LDS (the tile buffers are free after the last tile).
+  // Then the 4 waves, through LDS (the tile buffers are free after the last
+  // chunk's barrier).
   double* red = reinterpret_cast<double*>(&sm);   // [4 waves][64 rows][5]
   const int wv = tid >> 6;
   if ((tid & 63) < 16) {
@@ -675,18 +868,31 @@ ffc_status launch_geometry(const double* Xt, int d, const GeomArgs& ga, int coun
     set_error("column sets above 16384 points are not supported by the proposal features");
     return FFC_ERR_INVALID_ARG;
   }
-  hipLaunchKernelGGL(k_geometry, dim3(count), dim3(256), 0, st, Xt, d, ga);
+  const size_t lds = geometry_lds(d, ga.col_stride);
+  if (lds > 144 * 1024) {
+    set_error("the proposal geometry does not fit in LDS for this dimension");
+    return FFC_ERR_INVALID_ARG;
+  }
+  static size_t lds_set = 64 * 1024;
+  if (lds > lds_set) {
+    FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_geometry),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    lds_set = lds;
+  }
+  hipLaunchKernelGGL(k_geometry, dim3(count), dim3(256), lds, st, Xt, d, ga);
   FFC_LAUNCH_CHECK("k_geometry");
   return FFC_OK;
 }
 
+constexpr int kFeatJT = 4;   // subsample points per thread and pass (64-point passes)
+
 ffc_status launch_features(const double* Xt, int d, const GeomArgs& ga, const int32_t* tgt, int tgt_stride,
                            const int32_t* ntgt, int count, float* feat, int64_t feat_stride, hipStream_t st) {
-  const int tiles = (tgt_stride + 63) / 64;
+  const int tiles = (tgt_stride + FT - 1) / FT;
   const int64_t blocks = (int64_t)count * tiles;
   if (blocks <= 0) return FFC_OK;
-  hipLaunchKernelGGL(k_features, dim3((unsigned)blocks), dim3(256), 0, st, Xt, d, ga, tgt, tgt_stride, ntgt, tiles,
-                     feat, feat_stride);
+  hipLaunchKernelGGL(k_features<kFeatJT>, dim3((unsigned)blocks), dim3(256), 0, st, Xt, d, ga, tgt, tgt_stride, ntgt,
+                     tiles, feat, feat_stride);
   FFC_LAUNCH_CHECK("k_features");
   return FFC_OK;
 }

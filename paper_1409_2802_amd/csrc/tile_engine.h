@@ -1,5 +1,5 @@
 // The 64 x 64 point-pair tile engine shared by the kernel tiles (sampled
-// blocks, evaluation, direct sums) and the proposal's feature distances.
+// blocks, evaluation, direct sums).
 //
 // A 256-thread workgroup computes a 64 x 64 tile of squared distances (or, with
 // DOT, inner products) between a row set and a column set of points stored
