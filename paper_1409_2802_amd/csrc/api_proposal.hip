@@ -65,10 +65,11 @@ bool all_finite(const float* v, size_t n) {
 
 // Geometry scratch for `count` column sets.
 struct GeomScratch {
-  DevBuf<double> cen, rho, U;
+  DevBuf<double> cen, rho, U, subn2;
   DevBuf<int32_t> sub, nsub;
   ffc_status alloc(int count, int d) {
     FFC_TRY(cen.alloc((size_t)count * d));
+    FFC_TRY(subn2.alloc((size_t)count * 256));
     FFC_TRY(rho.alloc(count));
     FFC_TRY(U.alloc((size_t)count * 7 * d));
     FFC_TRY(sub.alloc((size_t)count * 256));
@@ -76,7 +77,7 @@ struct GeomScratch {
     return FFC_OK;
   }
   GeomArgs args(const int32_t* cols, int64_t stride, const int32_t* ncols, const int32_t* ids, uint64_t seed) {
-    return GeomArgs{cols, stride, ncols, ids, seed, cen.ptr, rho.ptr, sub.ptr, nsub.ptr, U.ptr};
+    return GeomArgs{cols, stride, ncols, ids, seed, cen.ptr, rho.ptr, sub.ptr, nsub.ptr, U.ptr, subn2.ptr};
   }
 };
 
@@ -227,6 +228,7 @@ ffc_status learned_alloc(const ffc_tree* t, ffc_skel* sk, int pool_factor) {
   FFC_TRY(L.cen.alloc(widest * d));
   FFC_TRY(L.rho.alloc(widest));
   FFC_TRY(L.U.alloc(widest * 7 * d));
+  FFC_TRY(L.subn2.alloc(widest * 256));
   FFC_TRY(L.sub.alloc(widest * 256));
   FFC_TRY(L.nsub.alloc(widest));
   FFC_TRY(L.feat.alloc(widest * p_cap * kNF));
@@ -246,7 +248,7 @@ ffc_status learned_rows_level(const ffc_tree* t, ffc_skel* sk, int sampler, cons
   const int pc = L.p_cap;
   FFC_TRY(launch_sample_rows_into(t, L.pool.ptr, L.npool.ptr, pc, first, count, pc, seed, kStreamPool, nullptr, st));
   const GeomArgs ga{sk->cols.ptr + (int64_t)first * sk->n_cap, sk->n_cap, sk->ncols.ptr + first, L.ids.ptr + first,
-                    seed, L.cen.ptr, L.rho.ptr, L.sub.ptr, L.nsub.ptr, L.U.ptr};
+                    seed, L.cen.ptr, L.rho.ptr, L.sub.ptr, L.nsub.ptr, L.U.ptr, L.subn2.ptr};
   FFC_TRY(launch_geometry(t->Xt.ptr, t->d, ga, count, st));
   FFC_TRY(launch_features(t->Xt.ptr, t->d, ga, L.pool.ptr + (int64_t)first * pc, pc, L.npool.ptr + first, count,
                           L.feat.ptr, (int64_t)pc * kNF, st));

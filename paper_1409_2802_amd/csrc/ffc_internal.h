@@ -150,6 +150,7 @@ struct GeomArgs {
   int32_t* sub;             // [count][256] subsample (tree positions)
   int32_t* nsub;            // [count]
   double* U;                // [count][7][d] anchor directions
+  double* subn2;            // [count][256] squared norms of the subsample points (0 past nsub)
 };
 
 }  // namespace ffc
@@ -206,7 +207,7 @@ struct LearnedScratch {
   int32_t p_cap = 0;                  // candidate pool capacity per node
   DevBuf<int32_t> ids;                // node ids 0..num_nodes-1
   DevBuf<int32_t> pool, npool;        // num_nodes x p_cap
-  DevBuf<double> cen, rho, U;         // geometry of one level
+  DevBuf<double> cen, rho, U, subn2;  // geometry of one level
   DevBuf<int32_t> sub, nsub;          // 256-point column subsamples
   DevBuf<float> feat, score;          // level x p_cap (x 16)
   DevBuf<int32_t> hrows, nheld;       // num_nodes x 32 held-out rows

@@ -17,18 +17,17 @@
 #include <climits>
 
 #include "ffc_internal.h"
-#include "feature_rows.h"
 
 namespace ffc {
 namespace {
 
-constexpr int NF = feat::kNF, NH = 64;
+constexpr int NF = 16, NH = 64;   // features per target, hidden width
 constexpr int NPARAM = NF * NH + NH + NH * NH + NH + NH + 1;   // 5313
 constexpr int OFF_W1 = 0, OFF_B1 = NF * NH, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH,
               OFF_B3 = OFF_W3 + NH;
-constexpr int SUB = feat::kSub;  // column subsample size
+constexpr int SUB = 256;   // column subsample size
 constexpr int kMaxGeomCols = 16384;   // column-set capacity (the indices are held in 64 KiB of LDS)
-constexpr int NANCH = feat::kNAnch;
+constexpr int NANCH = 7;    // anchor directions
 constexpr uint64_t STREAM_SUBSAMPLE = 1ull << 30, STREAM_KEYS = 3ull << 30;
 
 __device__ inline uint64_t splitmix_first(uint64_t state) {
@@ -252,9 +251,10 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
   __shared__ int wbi[4];
   const int na = min(NANCH, ns);
   auto search = [&](auto xrow) {
-    // Anchors: farthest-point selection, starting from the point farthest from c.
+    // Anchors: farthest-point selection, starting from the point farthest from
+    // c. (The squared norms of the subsample points are formed on the way.)
     if (tid < SUB) {
-      double sq = -1.0;
+      double sq = -1.0, nx = 0.0;
       if (tid < ns) {
         const double* x = xrow(tid);
         sq = 0.0;
@@ -262,9 +262,11 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
         for (int k = 0; k < d; ++k) {
           const double df = x[k] - scen[k];
           sq = fma(df, df, sq);
+          nx = fma(x[k], x[k], nx);
         }
       }
       sd2[tid] = sq;
+      ga.subn2[(int64_t)b * SUB + tid] = nx;
     }
     __syncthreads();
     for (int a = 0; a < na; ++a) {
@@ -332,146 +334,225 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
 }
 
 // ---------------------------------------------------------------------------
-// Features: one 256-thread workgroup per 64 targets of a block. The distances
-// to the column subsample are formed in passes of 16 JT subsample points:
-// thread (tr, tc) = (tid % 16, tid / 16) owns targets tr + 16 i (i < 4) and
-// points tc + 16 j (j < JT) of the pass and sums FP64 explicit differences
-// over the coordinates, which pass through a double-buffered LDS tile 16 at a
-// time while the next 16 are being loaded (coordinates past d are staged as
-// zeros and add exact zeros). Each thread keeps the 4 smallest distances and
-// the sum over its points (tc + 16 m, m ascending), merged across the 16
-// threads of a row in a fixed order: lanes 16 apart by shuffles, then the 4
-// waves through LDS.
+// Features on the FP64 matrix cores. One 256-thread workgroup per 64 targets
+// of a block; wave w owns targets 16 w .. 16 w + 15. The subsample is taken in
+// rounds of 64 points, each swept over the coordinates in chunks of 16 that
+// pass through a double-buffered LDS stage (targets and points row-major, the
+// next chunk's loads in flight). Per chunk a wave issues 4 x 4
+// v_mfma_f64_16x16x4f64 for the inner products of its 16 targets with the
+// round's 64 points; step u of a chunk takes coordinates 4 g + u of the chunk
+// from lane group g = lane / 16, so that a lane reads its 4 values of a row
+// with two 16-byte LDS loads. Operand layouts of the instruction: lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
+// D[4 v + l / 16][l % 16] for v = 0..3.
+//
+// Squared distances are taken in Gram form |y|^2 + |x|^2 - 2 y.x; a pair whose
+// Gram value is below 2^-10 (|y|^2 + |x|^2), where the form could have lost
+// more than 10 bits, is recomputed from explicit coordinate differences. Lane
+// l holds targets 16 w + 4 v + l / 16 (v < 4) against points l % 16 + 16 c
+// (c < 4) of each round, keeps per target the 4 smallest squared distances
+// and the sum of the distances, and the 16 lanes of a target group merge
+// them at the end in a fixed order (shuffles at lane distance 1, 2, 4, 8).
+// The target norms, the distance to the centroid and the anchor projections
+// are summed in order over the coordinates from the first round's stages.
 // ---------------------------------------------------------------------------
-using feat::insert4;
+// Keep the 4 smallest values, ascending (a branch-free insertion).
+__device__ inline void insert4(double (&b)[4], double v) {
+  b[3] = fmin(b[3], v);
+#pragma unroll
+  for (int a = 3; a > 0; --a) {
+    const double lo = fmin(b[a - 1], b[a]), hi = fmax(b[a - 1], b[a]);
+    b[a - 1] = lo;
+    b[a] = hi;
+  }
+}
 
-constexpr int FT = 64, FK = 16;   // targets per workgroup, coordinates per staged chunk
+// sqrt(g) for g >= 0 to about 2^-45 relative: the hardware reciprocal square
+// root refined by one Newton step on h^2 = g (values below 2^-900 give 0).
+// Used only for the sum of the distances, a float feature.
+__device__ inline double sqrt_sum(double g) {
+  const double r = __builtin_amdgcn_rsq(g), h = g * r;
+  const double s = fma(fma(-h, h, g), 0.5 * r, h);
+  return g > 0x1p-900 ? s : 0.0;
+}
 
-template <int JT>
+typedef double fdbl4 __attribute__((ext_vector_type(4)));
+constexpr int FT = 64, FR = 64, FK = 32, FKP = FK + 2;   // targets, points per round, chunk, LDS row
+constexpr int FSR = 256 / FK, FNI = FT / FSR;           // stage rows per pass, passes (targets = points)
 struct FeatSmem {
-  double ys[2][FK][FT + 1];
-  double xs[2][FK][16 * JT + 1];
+  double ys[2][FT][FKP];
+  double xs[2][FR][FKP];
+  double cu[2][1 + NANCH][FK];   // centroid and anchor directions, first round
+  double ny[FT];
 };
 
-template <int JT>
 __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt, int d, GeomArgs ga,
                                                   const int32_t* __restrict__ tgt, int tgt_stride,
                                                   const int32_t* __restrict__ ntgt, int tiles,
                                                   float* __restrict__ feat, int64_t feat_stride) {
-  constexpr int FP = 16 * JT;   // subsample points per pass
-  constexpr int YE = FT * FK / 256, XE = FP * FK / 256;   // staged elements per thread
-  __shared__ FeatSmem<JT> sm;
+  __shared__ __align__(16) FeatSmem sm;
   const int b = blockIdx.x / tiles, t0 = (blockIdx.x % tiles) * FT;
   const int nt = ntgt[b];
   if (t0 >= nt) return;
   const int ns = ga.nsub[b];
   const double rho = ga.rho[b];
   const int32_t* S = ga.sub + (int64_t)b * SUB;
+  const double* nxg = ga.subn2 + (int64_t)b * SUB;
+  const double* cen = ga.cen + (int64_t)b * d;
+  const double* U = ga.U + (int64_t)b * NANCH * d;
   const int32_t* tg = tgt + (int64_t)b * tgt_stride + t0;
-  const int tid = threadIdx.x, tr = tid & 15, tc = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lg = lane >> 4;
   const int nrow = min(FT, nt - t0);
-  // Staged element e = tid + 256 it is row e / FK, coordinate e % FK of the
-  // chunk: a thread's rows are fixed (tc + 16 it), its coordinate is tr.
-  int yrow[YE];
+  // Stage map: element tid + 256 it of a 64 x FK stage is row tid / FK + FSR it,
+  // coordinate tid % FK.
+  const int sr = tid / FK, sk = tid % FK;
+  int yrow[FNI];
 #pragma unroll
-  for (int it = 0; it < YE; ++it) yrow[it] = tc + 16 * it < nrow ? tg[tc + 16 * it] : -1;
-  double best[4][4], sum[4], acc[4][JT];
+  for (int it = 0; it < FNI; ++it) yrow[it] = sr + FSR * it < nrow ? tg[sr + FSR * it] : -1;
+  const int nchunk = (d + FK - 1) / FK, nround = max(1, (ns + FR - 1) / FR), total = nround * nchunk;
+  double ry[FNI], rx[FNI], rc = 0.0;
+  auto load = [&](int st) {
+    const int r = st / nchunk, k = (st - r * nchunk) * FK + sk;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    sum[i] = 0.0;
+    for (int it = 0; it < FNI; ++it) ry[it] = yrow[it] >= 0 && k < d ? Xt[(int64_t)yrow[it] * d + k] : 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) best[i][q] = INFINITY;
-#pragma unroll
-    for (int j = 0; j < JT; ++j) acc[i][j] = 0.0;
-  }
-  const int nchunk = (d + FK - 1) / FK, npass = (ns + FP - 1) / FP, total = npass * nchunk;
-  double ry[YE], rx[XE];
-  auto load = [&](int q) {
-    const int c = (q / nchunk) * FP, k = (q % nchunk) * FK + tr;
-#pragma unroll
-    for (int it = 0; it < YE; ++it) ry[it] = yrow[it] >= 0 && k < d ? Xt[(int64_t)yrow[it] * d + k] : 0.0;
-#pragma unroll
-    for (int it = 0; it < XE; ++it) {
-      const int r = c + tc + 16 * it;
-      rx[it] = r < ns && k < d ? Xt[(int64_t)S[r] * d + k] : 0.0;
+    for (int it = 0; it < FNI; ++it) {
+      const int p = r * FR + sr + FSR * it;
+      rx[it] = p < ns && k < d ? Xt[(int64_t)S[p] * d + k] : 0.0;
+    }
+    if (r == 0 && tid < (1 + NANCH) * FK) {
+      const int a = tid / FK;
+      rc = k < d ? (a == 0 ? cen[k] : U[(int64_t)(a - 1) * d + k]) : 0.0;
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int st, int buf) {
 #pragma unroll
-    for (int it = 0; it < YE; ++it) sm.ys[buf][tr][tc + 16 * it] = ry[it];
-#pragma unroll
-    for (int it = 0; it < XE; ++it) sm.xs[buf][tr][tc + 16 * it] = rx[it];
+    for (int it = 0; it < FNI; ++it) {
+      sm.ys[buf][sr + FSR * it][sk] = ry[it];
+      sm.xs[buf][sr + FSR * it][sk] = rx[it];
+    }
+    if (st < nchunk && tid < (1 + NANCH) * FK) sm.cu[buf][tid / FK][sk] = rc;
   };
-  if (total > 0) {
-    load(0);
-    store(0);
+  fdbl4 acc[4];
+  double best[4][4], sum[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    acc[v] = fdbl4{0.0, 0.0, 0.0, 0.0};
+    sum[v] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) best[v][i] = INFINITY;
   }
+  // First-round sums: the norm of target tid (tid < 64), and dot products
+  // 2 (tid % 4), 2 (tid % 4) + 1 of target tid / 4 (0: |y - c|^2, a > 0:
+  // (y - c) . u_a).
+  double nyv = 0.0, dp0 = 0.0, dp1 = 0.0;
+  const int drow = tid >> 2, da = 2 * (tid & 3);
+  load(0);
+  store(0, 0);
   __syncthreads();
-  for (int q = 0; q < total; ++q) {
-    const int buf = q & 1;
-    if (q + 1 < total) load(q + 1);
+  for (int st = 0; st < total; ++st) {
+    const int buf = st & 1, r = st / nchunk, ch = st - r * nchunk;
+    if (st + 1 < total) load(st + 1);
 #pragma unroll
-    for (int kk = 0; kk < FK; ++kk) {
-      double av[4], bv[JT];
+    for (int h = 0; h < FK / 16; ++h) {
+      const double2* ya = reinterpret_cast<const double2*>(&sm.ys[buf][16 * w + li][16 * h + 4 * lg]);
+      const double2 a01 = ya[0], a23 = ya[1];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) av[i] = sm.ys[buf][kk][tr + 16 * i];
-#pragma unroll
-      for (int j = 0; j < JT; ++j) bv[j] = sm.xs[buf][kk][tc + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < JT; ++j) {
-          const double df = av[i] - bv[j];
-          acc[i][j] = fma(df, df, acc[i][j]);
-        }
+      for (int c = 0; c < 4; ++c) {
+        const double2* xb = reinterpret_cast<const double2*>(&sm.xs[buf][16 * c + li][16 * h + 4 * lg]);
+        const double2 b01 = xb[0], b23 = xb[1];
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x, b01.x, acc[c], 0, 0, 0);
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.y, b01.y, acc[c], 0, 0, 0);
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.x, b23.x, acc[c], 0, 0, 0);
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a23.y, b23.y, acc[c], 0, 0, 0);
+      }
     }
-    if (q % nchunk == nchunk - 1) {   // the pass is complete
-      const int c = (q / nchunk) * FP;
+    if (r == 0) {
+#pragma unroll 4
+      for (int kk = 0; kk < FK; ++kk) {
+        const double df = sm.ys[buf][drow][kk] - sm.cu[buf][0][kk], u0 = sm.cu[buf][da][kk];
+        dp0 = fma(df, da == 0 ? df : u0, dp0);
+        dp1 = fma(df, sm.cu[buf][da + 1][kk], dp1);
+      }
+      if (tid < FT)
+#pragma unroll 4
+        for (int kk = 0; kk < FK; ++kk) nyv = fma(sm.ys[buf][tid][kk], sm.ys[buf][tid][kk], nyv);
+    }
+    if (ch == nchunk - 1) {   // the round is complete
+      if (r == 0) {
+        if (tid < FT) sm.ny[tid] = nyv;
+        __syncthreads();
+      }
+      double nyr[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int v = 0; v < 4; ++v) nyr[v] = sm.ny[16 * w + 4 * v + lg];
 #pragma unroll
-        for (int j = 0; j < JT; ++j) {
-          if (c + tc + 16 * j < ns) {
-            const double dist = sqrt(acc[i][j]) / rho;
-            sum[i] += dist;
-            insert4(best[i], dist);
+      for (int c = 0; c < 4; ++c) {
+        const int p = r * FR + 16 * c + li;
+        if (p < ns) {
+          const double nx = nxg[p];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = 16 * w + 4 * v + lg;
+            const double n2 = nyr[v] + nx;
+            double g = fma(-2.0, acc[c][v], n2);
+            if (!(g >= 0x1p-10 * n2) && row < nrow) {   // explicit differences
+              const double* y = Xt + (int64_t)tg[row] * d;
+              const double* x = Xt + (int64_t)S[p] * d;
+              g = 0.0;
+              for (int k = 0; k < d; ++k) {
+                const double df = y[k] - x[k];
+                g = fma(df, df, g);
+              }
+            }
+            g = fmax(g, 0.0);
+            sum[v] += sqrt_sum(g);
+            insert4(best[v], g);
           }
-          acc[i][j] = 0.0;
         }
+        acc[c] = fdbl4{0.0, 0.0, 0.0, 0.0};
+      }
     }
-    if (q + 1 < total) store(buf ^ 1);
+    if (st + 1 < total) store(st + 1, buf ^ 1);
     __syncthreads();
   }
-  // Merge the 4 threads of a row inside the wave (lanes tr + 16 q).
+  // Merge the 16 lanes of a target group, lower lane's sum first.
 #pragma unroll
-  for (int off = 16; off <= 32; off <<= 1)
+  for (int off = 1; off < 16; off <<= 1)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int v = 0; v < 4; ++v) {
       double o[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) o[q] = __shfl_xor(best[i][q], off, 64);
-      const double os = __shfl_xor(sum[i], off, 64);
-      // Fixed order: the lower lane's sum first.
-      sum[i] = (tid & off) ? os + sum[i] : sum[i] + os;
+      for (int i = 0; i < 4; ++i) o[i] = __shfl_xor(best[v][i], off, 64);
+      const double os = __shfl_xor(sum[v], off, 64);
+      sum[v] = (lane & off) ? os + sum[v] : sum[v] + os;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) insert4(best[i], o[q]);
+      for (int i = 0; i < 4; ++i) insert4(best[v], o[i]);
     }
-  // Then the 4 waves, through LDS (the tile buffers are free after the last
-  // chunk's barrier).
-  double* red = reinterpret_cast<double*>(&sm);   // [4 waves][64 rows][5]
-  const int wv = tid >> 6;
-  if ((tid & 63) < 16) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double* r = red + ((int64_t)wv * 64 + tr + 16 * i) * 5;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) r[q] = best[i][q];
-      r[4] = sum[i];
-    }
-  }
-  double* dots = red + 4 * 64 * 5;   // [64 rows][1 + NANCH]
+  // The first-round dot products go through LDS (the stage buffers are free).
+  double* dots = &sm.ys[0][0][0];   // [64 targets][1 + NANCH]
+  dots[drow * (1 + NANCH) + da] = dp0;
+  dots[drow * (1 + NANCH) + da + 1] = dp1;
   __syncthreads();
-  feat::finish_rows(Xt, d, ga, b, tg, t0, nt, ns, rho, red, 4, dots, feat, feat_stride);
+  if (li != 0) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = 16 * w + 4 * v + lg;
+    if (row >= nrow) continue;
+    const double* dr = dots + row * (1 + NANCH);
+    double b4[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b4[i] = sqrt(best[v][i]) / rho;
+    const double dc = sqrt(dr[0]) / rho;
+    float* f = feat + (int64_t)b * feat_stride + (int64_t)(t0 + row) * NF;
+    f[0] = (float)dc;
+    f[1] = (float)log(dc + 1e-12);
+    for (int i = 0; i < 4; ++i) f[2 + i] = (float)(i < ns ? b4[i] : b4[max(ns - 1, 0)]);
+    f[6] = (float)(ns > 0 ? sum[v] / rho / ns : 0.0);
+    f[7] = (float)log(b4[0] + 1e-12);
+    for (int a = 0; a < NANCH; ++a) f[8 + a] = (float)(dr[1 + a] / rho);
+    f[15] = 1.0f;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -884,15 +965,13 @@ ffc_status launch_geometry(const double* Xt, int d, const GeomArgs& ga, int coun
   return FFC_OK;
 }
 
-constexpr int kFeatJT = 4;   // subsample points per thread and pass (64-point passes)
-
 ffc_status launch_features(const double* Xt, int d, const GeomArgs& ga, const int32_t* tgt, int tgt_stride,
                            const int32_t* ntgt, int count, float* feat, int64_t feat_stride, hipStream_t st) {
   const int tiles = (tgt_stride + FT - 1) / FT;
   const int64_t blocks = (int64_t)count * tiles;
   if (blocks <= 0) return FFC_OK;
-  hipLaunchKernelGGL(k_features<kFeatJT>, dim3((unsigned)blocks), dim3(256), 0, st, Xt, d, ga, tgt, tgt_stride, ntgt,
-                     tiles, feat, feat_stride);
+  hipLaunchKernelGGL(k_features, dim3((unsigned)blocks), dim3(256), 0, st, Xt, d, ga, tgt, tgt_stride, ntgt, tiles,
+                     feat, feat_stride);
   FFC_LAUNCH_CHECK("k_features");
   return FFC_OK;
 }
