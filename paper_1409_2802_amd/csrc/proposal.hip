@@ -336,13 +336,15 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
 // ---------------------------------------------------------------------------
 // Features on the FP64 matrix cores. One 256-thread workgroup per 64 targets
 // of a block; wave w owns targets 16 w .. 16 w + 15. The subsample is taken in
-// rounds of 64 points, each swept over the coordinates in chunks of 16 that
+// rounds of 64 points, each swept over the coordinates in chunks of 32 that
 // pass through a double-buffered LDS stage (targets and points row-major, the
-// next chunk's loads in flight). Per chunk a wave issues 4 x 4
+// next chunk's loads in flight). Per chunk a wave issues 8 x 4
 // v_mfma_f64_16x16x4f64 for the inner products of its 16 targets with the
-// round's 64 points; step u of a chunk takes coordinates 4 g + u of the chunk
-// from lane group g = lane / 16, so that a lane reads its 4 values of a row
-// with two 16-byte LDS loads. Operand layouts of the instruction: lane l
+// round's 64 points; step u of each 16 coordinates of a chunk takes their
+// coordinates 4 g + u from lane group g = lane / 16, so that a lane reads its
+// 4 values of a row with two 16-byte LDS loads (rows padded to 34 doubles,
+// which spreads the 16 rows of a read over all banks). Operand layouts of the
+// instruction: lane l
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
 // D[4 v + l / 16][l % 16] for v = 0..3.
 //
@@ -352,7 +354,7 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
 // l holds targets 16 w + 4 v + l / 16 (v < 4) against points l % 16 + 16 c
 // (c < 4) of each round, keeps per target the 4 smallest squared distances
 // and the sum of the distances, and the 16 lanes of a target group merge
-// them at the end in a fixed order (shuffles at lane distance 1, 2, 4, 8).
+// them at the end in a fixed order (four DPP exchange steps).
 // The target norms, the distance to the centroid and the anchor projections
 // are summed in order over the coordinates from the first round's stages.
 // ---------------------------------------------------------------------------
@@ -376,13 +378,41 @@ __device__ inline double sqrt_sum(double g) {
   return g > 0x1p-900 ? s : 0.0;
 }
 
+// x of the DPP partner lane (CTRL: a DPP row control: quad permutation or
+// mirror).
+template <int CTRL>
+__device__ inline double dpp_partner(double x) {
+  const long long u = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One exchange step of the 4-smallest lists and sums of 4 targets.
+template <int CTRL>
+__device__ inline void merge_step(double (&best)[4][4], double (&sum)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    sum[v] += dpp_partner<CTRL>(sum[v]);
+    double c[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = fmin(best[v][i], dpp_partner<CTRL>(best[v][3 - i]));
+    // c is bitonic; sort it.
+    const double a0 = fmin(c[0], c[2]), a2 = fmax(c[0], c[2]), a1 = fmin(c[1], c[3]), a3 = fmax(c[1], c[3]);
+    best[v][0] = fmin(a0, a1);
+    best[v][1] = fmax(a0, a1);
+    best[v][2] = fmin(a2, a3);
+    best[v][3] = fmax(a2, a3);
+  }
+}
+
 typedef double fdbl4 __attribute__((ext_vector_type(4)));
 constexpr int FT = 64, FR = 64, FK = 32, FKP = FK + 2;   // targets, points per round, chunk, LDS row
 constexpr int FSR = 256 / FK, FNI = FT / FSR;           // stage rows per pass, passes (targets = points)
 struct FeatSmem {
   double ys[2][FT][FKP];
   double xs[2][FR][FKP];
-  double cu[2][1 + NANCH][FK];   // centroid and anchor directions, first round
+  double cu[2][1 + NANCH][FK + 1];   // centroid and anchor directions, first round
   double ny[FT];
 };
 
@@ -442,9 +472,8 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
 #pragma unroll
     for (int i = 0; i < 4; ++i) best[v][i] = INFINITY;
   }
-  // First-round sums: the norm of target tid (tid < 64), and dot products
-  // 2 (tid % 4), 2 (tid % 4) + 1 of target tid / 4 (0: |y - c|^2, a > 0:
-  // (y - c) . u_a).
+  // First-round sums of target tid / 4: its squared norm, and dot products
+  // 2 (tid % 4), 2 (tid % 4) + 1 (0: |y - c|^2, a > 0: (y - c) . u_a).
   double nyv = 0.0, dp0 = 0.0, dp1 = 0.0;
   const int drow = tid >> 2, da = 2 * (tid & 3);
   load(0);
@@ -470,17 +499,15 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
     if (r == 0) {
 #pragma unroll 4
       for (int kk = 0; kk < FK; ++kk) {
-        const double df = sm.ys[buf][drow][kk] - sm.cu[buf][0][kk], u0 = sm.cu[buf][da][kk];
+        const double y = sm.ys[buf][drow][kk], df = y - sm.cu[buf][0][kk], u0 = sm.cu[buf][da][kk];
         dp0 = fma(df, da == 0 ? df : u0, dp0);
         dp1 = fma(df, sm.cu[buf][da + 1][kk], dp1);
+        nyv = fma(y, y, nyv);
       }
-      if (tid < FT)
-#pragma unroll 4
-        for (int kk = 0; kk < FK; ++kk) nyv = fma(sm.ys[buf][tid][kk], sm.ys[buf][tid][kk], nyv);
     }
     if (ch == nchunk - 1) {   // the round is complete
       if (r == 0) {
-        if (tid < FT) sm.ny[tid] = nyv;
+        if ((tid & 3) == 0) sm.ny[drow] = nyv;
         __syncthreads();
       }
       double nyr[4];
@@ -516,19 +543,14 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
     if (st + 1 < total) store(st + 1, buf ^ 1);
     __syncthreads();
   }
-  // Merge the 16 lanes of a target group, lower lane's sum first.
-#pragma unroll
-  for (int off = 1; off < 16; off <<= 1)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      double o[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) o[i] = __shfl_xor(best[v][i], off, 64);
-      const double os = __shfl_xor(sum[v], off, 64);
-      sum[v] = (lane & off) ? os + sum[v] : sum[v] + os;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) insert4(best[v], o[i]);
-    }
+  // Merge the 16 lanes of a target group in four exchange steps (partners by
+  // DPP: lane ^ 1, lane ^ 2, then mirrored within 8 and within 16 lanes, so
+  // that every lane ends with the whole group): the sums add (both partners
+  // get the same value), the two sorted 4-lists merge bitonically.
+  merge_step<0xB1>(best, sum);
+  merge_step<0x4E>(best, sum);
+  merge_step<0x141>(best, sum);
+  merge_step<0x140>(best, sum);
   // The first-round dot products go through LDS (the stage buffers are free).
   double* dots = &sm.ys[0][0][0];   // [64 targets][1 + NANCH]
   dots[drow * (1 + NANCH) + da] = dp0;
