@@ -776,11 +776,49 @@ __global__ void __launch_bounds__(256) k_feature_stats(const float* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Importance selection: one workgroup per node; pool <= 8192 candidates.
-// ---------------------------------------------------------------------------
+// Importance selection: one 512-thread workgroup per node; pool <= 8192
+// candidates.
 // mode 0 (learned): Efraimidis-Spirakis keys -ln(u) / w with w = 0.9 softmax(score) + 0.1 / P;
 // mode 1 (distance): keys -ln(u) * max(v, 1e-12), i.e. weights proportional to 1 / v;
 // mode 2 (nearest): keys v (deterministic). Value i of node b is score[b * score_stride + i * elem_stride].
+// The s smallest keys, ties to the smaller index, are found by a radix select
+// on order-preserving 64-bit images of the keys (8 passes of 8 bits over LDS
+// histograms); the ties at the cut are taken in index order. Thread t holds
+// candidates [t E, t E + E). The chosen rows are written in candidate order,
+// which is ascending for an ascending pool; another pool's rows are sorted.
+// ---------------------------------------------------------------------------
+constexpr int SEL_T = 512, SEL_E = 16;   // threads, candidates per thread
+
+// a < b exactly when image(a) < image(b) (-0 counts as +0).
+__device__ inline uint64_t order_image(double kv) {
+  const uint64_t u = (uint64_t)__double_as_longlong(kv == 0.0 ? 0.0 : kv);
+  return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+
+// Exclusive prefix sum of v over the 512 threads; `total` receives the sum.
+// wsum: 8 ints of LDS. Synchronizes twice.
+__device__ inline int block_exscan(int v, int* wsum, int& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) wsum[wv] = x;
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < SEL_T / 64; ++q) {
+    const int t = wsum[q];
+    before += q < wv ? t : 0;
+    all += t;
+  }
+  total = all;
+  return before + x - v;
+}
+
 __global__ void __launch_bounds__(512) k_select_rows(const float* __restrict__ score, int64_t score_stride,
                                                      int elem_stride, int mode,
                                                      const int32_t* __restrict__ pool, int pool_stride,
@@ -788,12 +826,12 @@ __global__ void __launch_bounds__(512) k_select_rows(const float* __restrict__ s
                                                      uint64_t seed, const int32_t* __restrict__ ncols,
                                                      const unsigned char* __restrict__ mask,
                                                      int32_t* __restrict__ rows, int s_cap, int32_t* __restrict__ nrows,
-                                                     int sort_n) {
-  extern __shared__ unsigned char sel_raw[];
-  double* key = reinterpret_cast<double*>(sel_raw);      // sort_n
-  int* idx = reinterpret_cast<int*>(key + sort_n);      // sort_n
-  __shared__ double red[512];
-  const int b = blockIdx.x, node = first + b, tid = threadIdx.x;
+                                                     int sort_s) {
+  extern __shared__ int sel_out[];   // sort_s chosen rows
+  __shared__ double red[SEL_T];
+  __shared__ int hist[256], wsum[SEL_T / 64], s_k;
+  __shared__ uint64_t s_prefix;
+  const int b = blockIdx.x, node = first + b, tid = threadIdx.x, lane = tid & 63;
   if (mask && !mask[node]) return;
   if (ncols[node] == 0) {   // empty column set: nothing to sample for
     if (tid == 0) nrows[node] = 0;
@@ -804,81 +842,149 @@ __global__ void __launch_bounds__(512) k_select_rows(const float* __restrict__ s
   const int32_t* pl = pool + (int64_t)b * pool_stride;
   int32_t* out = rows + (int64_t)node * s_cap;
   if (s_req >= P) {   // every candidate is taken
-    for (int i = tid; i < P; i += 512) out[i] = pl[i];
+    for (int i = tid; i < P; i += SEL_T) out[i] = pl[i];
     if (tid == 0) nrows[node] = P;
     return;
   }
   double mx = 0.0, se = 1.0;
   if (mode == 0) {
-    // softmax: max, then sum of exponentials (double, fixed order per thread + tree).
+    // Softmax: the maximum, then the sum of exponentials (each thread sums
+    // candidates tid, tid + 512, ... in order, then a pairwise tree: halves
+    // 256, 128, 64 through LDS, the rest by shuffles in wave 0).
     mx = -INFINITY;
-    for (int i = tid; i < P; i += 512) mx = fmax(mx, (double)sc[(int64_t)i * elem_stride]);
-    red[tid] = mx;
+    for (int i = tid; i < P; i += SEL_T) mx = fmax(mx, (double)sc[(int64_t)i * elem_stride]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if (lane == 0) red[tid >> 6] = mx;
     __syncthreads();
-    for (int off = 256; off > 0; off >>= 1) {
-      if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
-      __syncthreads();
-    }
-    mx = red[0];
+#pragma unroll
+    for (int q = 0; q < SEL_T / 64; ++q) mx = fmax(mx, red[q]);
     __syncthreads();
     se = 0.0;
-    for (int i = tid; i < P; i += 512) se += exp((double)sc[(int64_t)i * elem_stride] - mx);
+    for (int i = tid; i < P; i += SEL_T) se += exp((double)sc[(int64_t)i * elem_stride] - mx);
     red[tid] = se;
     __syncthreads();
-    for (int off = 256; off > 0; off >>= 1) {
+    for (int off = SEL_T / 2; off >= 64; off >>= 1) {
       if (tid < off) red[tid] += red[tid + off];
       __syncthreads();
     }
+    if (tid < 64) {
+      double x = red[tid];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double y = __shfl_down(x, off, 64);
+        if (tid < off) x += y;
+      }
+      if (tid == 0) red[0] = x;
+    }
+    __syncthreads();
     se = red[0];
   }
-  for (int i = tid; i < sort_n; i += 512) {
-    if (i < P) {
+  // Keys of this thread's candidates (padding sorts after every key).
+  const int E = (P + SEL_T - 1) / SEL_T, i0 = tid * E;
+  uint64_t u[SEL_E];
+#pragma unroll
+  for (int j = 0; j < SEL_E; ++j) {
+    const int i = i0 + j;
+    u[j] = ~0ull;
+    if (j < E && i < P) {
       const double v = (double)sc[(int64_t)i * elem_stride];
       double kv;
       if (mode == 2) {
         kv = v;
       } else {
-        const double u =
+        const double uu =
             ((double)(counter_u64(seed, (uint64_t)node | STREAM_KEYS, (uint64_t)i) >> 11) + 0.5) * 0x1.0p-53;
-        kv = mode == 1 ? -log(u) * fmax(v, 1e-12) : -log(u) / (0.9 * exp(v - mx) / se + 0.1 / P);
+        kv = mode == 1 ? -log(uu) * fmax(v, 1e-12) : -log(uu) / (0.9 * exp(v - mx) / se + 0.1 / P);
       }
-      key[i] = isfinite(kv) ? kv : INFINITY;   // a non-finite value is drawn last (by index)
-      idx[i] = i;
-    } else {
-      key[i] = INFINITY;
-      idx[i] = INT_MAX;
+      u[j] = order_image(isfinite(kv) ? kv : INFINITY);   // a non-finite value is drawn last (by index)
     }
   }
-  __syncthreads();
-  // Bitonic sort by (key, index).
-  for (int k = 2; k <= sort_n; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = tid; t < sort_n / 2; t += 512) {
-        const int i = (t / j) * 2 * j + (t % j);
-        const bool asc = (i & k) == 0;
-        const double ka = key[i], kb = key[i + j];
-        const int ia = idx[i], ib = idx[i + j];
-        const bool less = kb < ka || (kb == ka && ib < ia);
-        if (less == asc) { key[i] = kb; key[i + j] = ka; idx[i] = ib; idx[i + j] = ia; }
+  // Radix select of the image T of the s-th smallest key, and its rank k
+  // among the keys equal to T.
+  uint64_t prefix = 0;
+  int k = s_req - 1;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    const uint64_t hmask = shift == 56 ? 0ull : ~0ull << (shift + 8);
+    if (tid < 256) hist[tid] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SEL_E; ++j)
+      if ((u[j] & hmask) == prefix) atomicAdd(&hist[(u[j] >> shift) & 255], 1);
+    __syncthreads();
+    if (tid < 64) {
+      const int c0 = hist[4 * lane], c1 = hist[4 * lane + 1], c2 = hist[4 * lane + 2], c3 = hist[4 * lane + 3];
+      const int part = c0 + c1 + c2 + c3;
+      int incl = part;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
       }
-      __syncthreads();
-    }
-  // The s smallest keys; then their rows in ascending order (sort the positions,
-  // held exactly as doubles in the key array).
-  // (every real candidate sorts before the padding, so idx[i] < P for i < s_req < P)
-  for (int i = tid; i < sort_n; i += 512) key[i] = i < s_req ? (double)pl[idx[i]] : INFINITY;
-  __syncthreads();
-  for (int k = 2; k <= sort_n; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = tid; t < sort_n / 2; t += 512) {
-        const int i = (t / j) * 2 * j + (t % j);
-        const bool asc = (i & k) == 0;
-        const double ka = key[i], kb = key[i + j];
-        if ((kb < ka) == asc) { key[i] = kb; key[i + j] = ka; }
+      const int excl = incl - part;
+      if (excl <= k && k < incl) {
+        int kk = k - excl, dg = 4 * lane;
+        if (kk >= c0) {
+          kk -= c0;
+          ++dg;
+          if (kk >= c1) {
+            kk -= c1;
+            ++dg;
+            if (kk >= c2) {
+              kk -= c2;
+              ++dg;
+            }
+          }
+        }
+        s_prefix = prefix | ((uint64_t)dg << shift);
+        s_k = kk;
       }
-      __syncthreads();
     }
-  for (int i = tid; i < s_req; i += 512) out[i] = (int32_t)key[i];
+    __syncthreads();
+    prefix = s_prefix;
+    k = s_k;
+  }
+  // Candidates below T are chosen, and the first k + 1 equal to T by index.
+  const uint64_t T = prefix;
+  int neq = 0;
+#pragma unroll
+  for (int j = 0; j < SEL_E; ++j) neq += u[j] == T;
+  int total = 0;
+  int req = block_exscan(neq, wsum, total);
+  unsigned int chosen = 0;
+  int nsel = 0;
+#pragma unroll
+  for (int j = 0; j < SEL_E; ++j) {
+    const bool eq = u[j] == T, take = u[j] < T || (eq && req <= k);
+    req += eq;
+    chosen |= (unsigned int)take << j;
+    nsel += take;
+  }
+  int o = block_exscan(nsel, wsum, total);
+  bool descent = false;   // the pool is not ascending here
+#pragma unroll
+  for (int j = 0; j < SEL_E; ++j) {
+    const int i = i0 + j;
+    if (j < E && i + 1 < P) descent |= pl[i + 1] <= pl[i];
+    if ((chosen >> j) & 1) sel_out[o++] = pl[i];
+  }
+  if (__syncthreads_or(descent)) {   // bitonic sort of the chosen rows
+    for (int i = s_req + tid; i < sort_s; i += SEL_T) sel_out[i] = INT_MAX;
+    __syncthreads();
+    for (int kk = 2; kk <= sort_s; kk <<= 1)
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int t = tid; t < sort_s / 2; t += SEL_T) {
+          const int i = (t / j) * 2 * j + (t % j);
+          const int a0 = sel_out[i], a1 = sel_out[i + j];
+          if ((a1 < a0) == ((i & kk) == 0)) {
+            sel_out[i] = a1;
+            sel_out[i + j] = a0;
+          }
+        }
+        __syncthreads();
+      }
+  }
+  for (int i = tid; i < s_req; i += SEL_T) out[i] = sel_out[i];
   if (tid == 0) nrows[node] = s_req;
 }
 
@@ -1046,18 +1152,19 @@ ffc_status launch_select_rows(const float* score, int64_t score_stride, int elem
                               uint64_t seed, const int32_t* ncols, const unsigned char* mask, int32_t* rows, int s_cap,
                               int32_t* nrows, hipStream_t st) {
   if (count <= 0) return FFC_OK;
-  int sort_n = 1;
-  while (sort_n < pool_stride) sort_n <<= 1;
-  const size_t lds = (size_t)sort_n * (sizeof(double) + sizeof(int));
-  if (lds > 150 * 1024) {
+  if (pool_stride > SEL_T * SEL_E) {
     set_error("candidate pool too large for the selection kernel");
     return FFC_ERR_INVALID_ARG;
   }
-  if (lds > 64 * 1024)
-    FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_select_rows),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(k_select_rows, dim3(count), dim3(512), lds, st, score, score_stride, elem_stride, mode, pool,
-                     pool_stride, npool, first, s, seed, ncols, mask, rows, s_cap, nrows, sort_n);
+  int sort_s = 1;
+  while (sort_s < s) sort_s <<= 1;
+  const size_t lds = (size_t)sort_s * sizeof(int);
+  if (lds > 64 * 1024) {
+    set_error("too many rows requested for the selection kernel");
+    return FFC_ERR_INVALID_ARG;
+  }
+  hipLaunchKernelGGL(k_select_rows, dim3(count), dim3(SEL_T), lds, st, score, score_stride, elem_stride, mode, pool,
+                     pool_stride, npool, first, s, seed, ncols, mask, rows, s_cap, nrows, sort_s);
   FFC_LAUNCH_CHECK("k_select_rows");
   return FFC_OK;
 }
