@@ -578,38 +578,91 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
 }
 
 // ---------------------------------------------------------------------------
-// Network inference: one thread per sample, parameters in LDS.
+// Network inference on the matrix cores (v_mfma_f32_16x16x4f32, FP32
+// operands and accumulation). Each wavefront takes 16 samples at a time (a
+// grid-stride loop) with the layers transposed, so that the samples run
+// along the instruction's N dimension: H1^T = W1^T Z^T, then H2^T = W2^T
+// relu(H1^T + b1), then y = b3 + w3 . relu(H2^T + b2) by lane sums. Operand
+// layouts: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
+// receives D[kMlpRow(l / 16, v)][l % 16], v = 0..3. The K index of step v
+// of a 16-row block is kMlpRow(g, v) for lane group g = l / 16, so a lane's
+// outputs of one layer are its operands for the next; for the first layer,
+// step v takes feature 4 g + v, so a lane reads its 4 features at once. The
+// weights stay in registers for the whole loop.
 // ---------------------------------------------------------------------------
+typedef float ff4 __attribute__((ext_vector_type(4)));
+__device__ constexpr int kMlpRow(int g, int v) { return 4 * g + v; }
+
 __global__ void __launch_bounds__(256) k_mlp_score(const float* __restrict__ theta, const float* __restrict__ mu,
                                                    const float* __restrict__ sdv, const float* __restrict__ feat,
                                                    int64_t count, float* __restrict__ score) {
-  __shared__ float w[NPARAM];
-  __shared__ float smu[NF], ssd[NF];
-  for (int p = threadIdx.x; p < NPARAM; p += blockDim.x) w[p] = theta[p];
-  for (int p = threadIdx.x; p < NF; p += blockDim.x) { smu[p] = mu[p]; ssd[p] = sdv[p]; }
-  __syncthreads();
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  float z[NF];
+  const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int64_t ntile = (count + 15) / 16;
+  const int64_t wave0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  if (wave0 >= ntile) return;
+  float a1[4][4], a2[4][16], b1[4][4], b2[4][4], w3[4][4], zm[4], zs[4];
 #pragma unroll
-  for (int q = 0; q < NF; ++q) z[q] = (feat[i * NF + q] - smu[q]) / ssd[q];
-  z[NF - 1] = 1.f;
-  float h1[NH];
+  for (int m = 0; m < 4; ++m) {
 #pragma unroll
-  for (int j = 0; j < NH; ++j) {
-    float a = w[OFF_B1 + j];
+    for (int v = 0; v < 4; ++v) {
+      const int out = 16 * m + li, row = 16 * m + kMlpRow(g, v);   // (A row, and the hidden unit this lane holds)
+      a1[m][v] = theta[OFF_W1 + (4 * g + v) * NH + out];
+      b1[m][v] = theta[OFF_B1 + row];
+      b2[m][v] = theta[OFF_B2 + row];
+      w3[m][v] = theta[OFF_W3 + row];
+    }
 #pragma unroll
-    for (int q = 0; q < NF; ++q) a = fmaf(z[q], w[OFF_W1 + q * NH + j], a);
-    h1[j] = fmaxf(a, 0.f);
+    for (int m1 = 0; m1 < 4; ++m1)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) a2[m][4 * m1 + v] = theta[OFF_W2 + (16 * m1 + kMlpRow(g, v)) * NH + 16 * m + li];
   }
-  float y = w[OFF_B3];
-  for (int j = 0; j < NH; ++j) {
-    float a = w[OFF_B2 + j];
 #pragma unroll
-    for (int q = 0; q < NH; ++q) a = fmaf(h1[q], w[OFF_W2 + q * NH + j], a);
-    y = fmaf(fmaxf(a, 0.f), w[OFF_W3 + j], y);
+  for (int v = 0; v < 4; ++v) {
+    zm[v] = mu[4 * g + v];
+    zs[v] = sdv[4 * g + v];
   }
-  score[i] = y;
+  const float b3 = theta[OFF_B3];
+  for (int64_t t = wave0; t < ntile; t += nwaves) {
+    const int64_t smp = 16 * t + li;
+    float z[4];
+    if (smp < count) {
+      const float4 f = *reinterpret_cast<const float4*>(feat + smp * NF + 4 * g);
+      z[0] = f.x;
+      z[1] = f.y;
+      z[2] = f.z;
+      z[3] = f.w;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) z[v] = 0.f;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) z[v] = (4 * g + v == NF - 1) ? 1.f : (z[v] - zm[v]) / zs[v];
+    ff4 h1[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      h1[m] = ff4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) h1[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[m][v], z[v], h1[m], 0, 0, 0);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) h1[m][v] = fmaxf(h1[m][v] + b1[m][v], 0.f);
+    float y = 0.f;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      ff4 h2 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int m1 = 0; m1 < 4; ++m1)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) h2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[m][4 * m1 + v], h1[m1][v], h2, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) y = fmaf(fmaxf(h2[v] + b2[m][v], 0.f), w3[m][v], y);
+    }
+    y += __shfl_xor(y, 16, 64);
+    y += __shfl_xor(y, 32, 64);
+    if (g == 0 && smp < count) score[smp] = y + b3;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1107,7 +1160,8 @@ ffc_status launch_features(const double* Xt, int d, const GeomArgs& ga, const in
 ffc_status launch_mlp_score(const float* theta, const float* mu, const float* sdv, const float* feat, int64_t count,
                             float* score, hipStream_t st) {
   if (count <= 0) return FFC_OK;
-  hipLaunchKernelGGL(k_mlp_score, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, theta, mu, sdv, feat, count,
+  const int64_t waves = std::min<int64_t>((count + 15) / 16, 2048);
+  hipLaunchKernelGGL(k_mlp_score, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, theta, mu, sdv, feat, count,
                      score);
   FFC_LAUNCH_CHECK("k_mlp_score");
   return FFC_OK;
