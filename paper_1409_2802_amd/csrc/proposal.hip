@@ -408,7 +408,8 @@ __device__ inline void merge_step(double (&best)[4][4], double (&sum)[4]) {
 
 typedef double fdbl4 __attribute__((ext_vector_type(4)));
 constexpr int FT = 64, FR = 64, FK = 32, FKP = FK + 2;   // targets, points per round, chunk, LDS row
-constexpr int FSR = 256 / FK, FNI = FT / FSR;           // stage rows per pass, passes (targets = points)
+constexpr int FSR = 256 / FK, FNI = FT / FSR, FNP = FR / FSR;   // stage rows per pass; passes for targets, points
+constexpr int FCT = FR / 16;                                      // column tiles per round
 struct FeatSmem {
   double ys[2][FT][FKP];
   double xs[2][FR][FKP];
@@ -440,13 +441,13 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
 #pragma unroll
   for (int it = 0; it < FNI; ++it) yrow[it] = sr + FSR * it < nrow ? tg[sr + FSR * it] : -1;
   const int nchunk = (d + FK - 1) / FK, nround = max(1, (ns + FR - 1) / FR), total = nround * nchunk;
-  double ry[FNI], rx[FNI], rc = 0.0;
+  double ry[FNI], rx[FNP], rc = 0.0;
   auto load = [&](int st) {
     const int r = st / nchunk, k = (st - r * nchunk) * FK + sk;
 #pragma unroll
     for (int it = 0; it < FNI; ++it) ry[it] = yrow[it] >= 0 && k < d ? Xt[(int64_t)yrow[it] * d + k] : 0.0;
 #pragma unroll
-    for (int it = 0; it < FNI; ++it) {
+    for (int it = 0; it < FNP; ++it) {
       const int p = r * FR + sr + FSR * it;
       rx[it] = p < ns && k < d ? Xt[(int64_t)S[p] * d + k] : 0.0;
     }
@@ -457,17 +458,17 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
   };
   auto store = [&](int st, int buf) {
 #pragma unroll
-    for (int it = 0; it < FNI; ++it) {
-      sm.ys[buf][sr + FSR * it][sk] = ry[it];
-      sm.xs[buf][sr + FSR * it][sk] = rx[it];
-    }
+    for (int it = 0; it < FNI; ++it) sm.ys[buf][sr + FSR * it][sk] = ry[it];
+#pragma unroll
+    for (int it = 0; it < FNP; ++it) sm.xs[buf][sr + FSR * it][sk] = rx[it];
     if (st < nchunk && tid < (1 + NANCH) * FK) sm.cu[buf][tid / FK][sk] = rc;
   };
-  fdbl4 acc[4];
+  fdbl4 acc[FCT];
   double best[4][4], sum[4];
 #pragma unroll
+  for (int c = 0; c < FCT; ++c) acc[c] = fdbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
   for (int v = 0; v < 4; ++v) {
-    acc[v] = fdbl4{0.0, 0.0, 0.0, 0.0};
     sum[v] = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) best[v][i] = INFINITY;
@@ -487,7 +488,7 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
       const double2* ya = reinterpret_cast<const double2*>(&sm.ys[buf][16 * w + li][16 * h + 4 * lg]);
       const double2 a01 = ya[0], a23 = ya[1];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < FCT; ++c) {
         const double2* xb = reinterpret_cast<const double2*>(&sm.xs[buf][16 * c + li][16 * h + 4 * lg]);
         const double2 b01 = xb[0], b23 = xb[1];
         acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a01.x, b01.x, acc[c], 0, 0, 0);
@@ -514,7 +515,7 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
 #pragma unroll
       for (int v = 0; v < 4; ++v) nyr[v] = sm.ny[16 * w + 4 * v + lg];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < FCT; ++c) {
         const int p = r * FR + 16 * c + li;
         if (p < ns) {
           const double nx = nxg[p];
