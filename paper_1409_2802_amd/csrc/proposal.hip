@@ -415,6 +415,7 @@ struct FeatSmem {
   double xs[2][FR][FKP];
   double cu[2][1 + NANCH][FK + 1];   // centroid and anchor directions, first round
   double ny[FT];
+  int sub[SUB];                      // the subsample's tree positions
 };
 
 __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt, int d, GeomArgs ga,
@@ -449,7 +450,7 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
 #pragma unroll
     for (int it = 0; it < FNP; ++it) {
       const int p = r * FR + sr + FSR * it;
-      rx[it] = p < ns && k < d ? Xt[(int64_t)S[p] * d + k] : 0.0;
+      rx[it] = p < ns && k < d ? Xt[(int64_t)sm.sub[p] * d + k] : 0.0;
     }
     if (r == 0 && tid < (1 + NANCH) * FK) {
       const int a = tid / FK;
@@ -477,6 +478,11 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
   // 2 (tid % 4), 2 (tid % 4) + 1 (0: |y - c|^2, a > 0: (y - c) . u_a).
   double nyv = 0.0, dp0 = 0.0, dp1 = 0.0;
   const int drow = tid >> 2, da = 2 * (tid & 3);
+  // The subsample's positions go to LDS first: a coordinate load then waits
+  // on an LDS read, not on an earlier global load (which would serialize the
+  // stage's loads).
+  for (int q = tid; q < SUB; q += 256) sm.sub[q] = q < ns ? S[q] : 0;
+  __syncthreads();
   load(0);
   store(0, 0);
   __syncthreads();
@@ -526,7 +532,7 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
             double g = fma(-2.0, acc[c][v], n2);
             if (!(g >= 0x1p-10 * n2) && row < nrow) {   // explicit differences
               const double* y = Xt + (int64_t)tg[row] * d;
-              const double* x = Xt + (int64_t)S[p] * d;
+              const double* x = Xt + (int64_t)sm.sub[p] * d;
               g = 0.0;
               for (int k = 0; k < d; ++k) {
                 const double df = y[k] - x[k];
