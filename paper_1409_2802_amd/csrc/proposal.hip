@@ -336,23 +336,23 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
 // ---------------------------------------------------------------------------
 // Features on the FP64 matrix cores. One 256-thread workgroup per 64 targets
 // of a block; wave w owns targets 16 w .. 16 w + 15. The subsample is taken in
-// rounds of 64 points, each swept over the coordinates in chunks of 32 that
+// rounds of 128 points, each swept over the coordinates in chunks of 16 that
 // pass through a double-buffered LDS stage (targets and points row-major, the
-// next chunk's loads in flight). Per chunk a wave issues 8 x 4
+// next chunk's loads in flight, the subsample's positions read from LDS so
+// that the loads do not wait on one another). Per chunk a wave issues 8 x 4
 // v_mfma_f64_16x16x4f64 for the inner products of its 16 targets with the
-// round's 64 points; step u of each 16 coordinates of a chunk takes their
-// coordinates 4 g + u from lane group g = lane / 16, so that a lane reads its
-// 4 values of a row with two 16-byte LDS loads (rows padded to 34 doubles,
-// which spreads the 16 rows of a read over all banks). Operand layouts of the
-// instruction: lane l
-// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
-// D[4 v + l / 16][l % 16] for v = 0..3.
+// round's 128 points; step u of a chunk takes coordinates 4 g + u from lane
+// group g = lane / 16, so that a lane reads its 4 values of a row with two
+// 16-byte LDS loads (rows padded to 18 doubles, which spreads the 16 rows of a
+// read over all banks). Operand layouts of the instruction: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4 v + l / 16][l % 16]
+// for v = 0..3.
 //
 // Squared distances are taken in Gram form |y|^2 + |x|^2 - 2 y.x; a pair whose
 // Gram value is below 2^-10 (|y|^2 + |x|^2), where the form could have lost
 // more than 10 bits, is recomputed from explicit coordinate differences. Lane
 // l holds targets 16 w + 4 v + l / 16 (v < 4) against points l % 16 + 16 c
-// (c < 4) of each round, keeps per target the 4 smallest squared distances
+// (c < 8) of each round, keeps per target the 4 smallest squared distances
 // and the sum of the distances, and the 16 lanes of a target group merge
 // them at the end in a fixed order (four DPP exchange steps).
 // The target norms, the distance to the centroid and the anchor projections
@@ -370,12 +370,13 @@ __device__ inline void insert4(double (&b)[4], double v) {
 }
 
 // sqrt(g) for g >= 0 to about 2^-45 relative: the hardware reciprocal square
-// root refined by one Newton step on h^2 = g (values below 2^-900 give 0).
-// Used only for the sum of the distances, a float feature.
+// root refined by one Newton step on h^2 = g (g is raised to 2^-900 first, so
+// a zero distance adds 2^-450). Used only for the sum of the distances, a
+// float feature.
 __device__ inline double sqrt_sum(double g) {
+  g = fmax(g, 0x1p-900);
   const double r = __builtin_amdgcn_rsq(g), h = g * r;
-  const double s = fma(fma(-h, h, g), 0.5 * r, h);
-  return g > 0x1p-900 ? s : 0.0;
+  return fma(fma(-h, h, g), 0.5 * r, h);
 }
 
 // x of the DPP partner lane (CTRL: a DPP row control: quad permutation or
@@ -407,7 +408,7 @@ __device__ inline void merge_step(double (&best)[4][4], double (&sum)[4]) {
 }
 
 typedef double fdbl4 __attribute__((ext_vector_type(4)));
-constexpr int FT = 64, FR = 64, FK = 32, FKP = FK + 2;   // targets, points per round, chunk, LDS row
+constexpr int FT = 64, FR = 128, FK = 16, FKP = FK + 2;   // targets, points per round, chunk, LDS row
 constexpr int FSR = 256 / FK, FNI = FT / FSR, FNP = FR / FSR;   // stage rows per pass; passes for targets, points
 constexpr int FCT = FR / 16;                                      // column tiles per round
 struct FeatSmem {
@@ -539,7 +540,8 @@ __global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt,
                 g = fma(df, df, g);
               }
             }
-            g = fmax(g, 0.0);
+            // (g >= 0 here for every real target: a smaller Gram value took
+            // the explicit differences.)
             sum[v] += sqrt_sum(g);
             insert4(best[v], g);
           }
