@@ -336,12 +336,12 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
 // ---------------------------------------------------------------------------
 // Features on the FP64 matrix cores. One 256-thread workgroup per 64 targets
 // of a block; wave w owns targets 16 w .. 16 w + 15. The subsample is taken in
-// rounds of 128 points, each swept over the coordinates in chunks of 16 that
+// rounds of 64 points, each swept over the coordinates in chunks of 16 that
 // pass through a double-buffered LDS stage (targets and points row-major, the
 // next chunk's loads in flight, the subsample's positions read from LDS so
-// that the loads do not wait on one another). Per chunk a wave issues 8 x 4
+// that the loads do not wait on one another). Per chunk a wave issues 4 x 4
 // v_mfma_f64_16x16x4f64 for the inner products of its 16 targets with the
-// round's 128 points; step u of a chunk takes coordinates 4 g + u from lane
+// round's 64 points; step u of a chunk takes coordinates 4 g + u from lane
 // group g = lane / 16, so that a lane reads its 4 values of a row with two
 // 16-byte LDS loads (rows padded to 18 doubles, which spreads the 16 rows of a
 // read over all banks). Operand layouts of the instruction: lane l supplies
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
 // Gram value is below 2^-10 (|y|^2 + |x|^2), where the form could have lost
 // more than 10 bits, is recomputed from explicit coordinate differences. Lane
 // l holds targets 16 w + 4 v + l / 16 (v < 4) against points l % 16 + 16 c
-// (c < 8) of each round, keeps per target the 4 smallest squared distances
+// (c < 4) of each round, keeps per target the 4 smallest squared distances
 // and the sum of the distances, and the 16 lanes of a target group merge
 // them at the end in a fixed order (four DPP exchange steps).
 // The target norms, the distance to the centroid and the anchor projections
@@ -408,7 +408,7 @@ __device__ inline void merge_step(double (&best)[4][4], double (&sum)[4]) {
 }
 
 typedef double fdbl4 __attribute__((ext_vector_type(4)));
-constexpr int FT = 64, FR = 128, FK = 16, FKP = FK + 2;   // targets, points per round, chunk, LDS row
+constexpr int FT = 64, FR = 64, FK = 16, FKP = FK + 2;   // targets, points per round, chunk, LDS row
 constexpr int FSR = 256 / FK, FNI = FT / FSR, FNP = FR / FSR;   // stage rows per pass; passes for targets, points
 constexpr int FCT = FR / 16;                                      // column tiles per round
 struct FeatSmem {
@@ -419,7 +419,9 @@ struct FeatSmem {
   int sub[SUB];                      // the subsample's tree positions
 };
 
-__global__ void __launch_bounds__(256) k_features(const double* __restrict__ Xt, int d, GeomArgs ga,
+// (At most 168 registers, three workgroups per compute unit: the extra
+// resident waves hide the stage loads better than larger rounds would.)
+__global__ void __launch_bounds__(256, 3) k_features(const double* __restrict__ Xt, int d, GeomArgs ga,
                                                   const int32_t* __restrict__ tgt, int tgt_stride,
                                                   const int32_t* __restrict__ ntgt, int tiles,
                                                   float* __restrict__ feat, int64_t feat_stride) {
