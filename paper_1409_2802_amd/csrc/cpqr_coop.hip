@@ -630,11 +630,24 @@ k_id_solve_mfma(const double* __restrict__ A, int64_t a_stride, int lda, const i
   // block and the tail of the last 16-row chunk of the trailing products.
   for (int e = lane; e < (r16 + MB) * MB; e += 64) T[(e >> 4) * MTS + (e & 15)] = 0.0;
   __syncthreads();
-  for (int l = lane; l < r; l += 64) {
-    const int j = pb[l];
-    pv[l] = j;
-    atomicOr(&isp[j >> 5], 1u << (j & 31));
-    if (j >= j0 && j < j0 + MB) posl[j - j0] = l;
+  // (Pivot loads of up to 8 passes are issued together, then used: one
+  // memory round trip instead of one per pass.)
+  for (int l0 = 0; l0 < r; l0 += 64 * 8) {
+    int jl[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int l = l0 + 64 * u + lane;
+      jl[u] = l < r ? pb[l] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int l = l0 + 64 * u + lane, j = jl[u];
+      if (l < r) {
+        pv[l] = j;
+        atomicOr(&isp[j >> 5], 1u << (j & 31));
+        if (j >= j0 && j < j0 + MB) posl[j - j0] = l;
+      }
+    }
   }
   // Past the rank the trailing products read a real column of R against
   // zero right-hand sides, so no lane needs a bounds test.
@@ -652,9 +665,25 @@ k_id_solve_mfma(const double* __restrict__ A, int64_t a_stride, int lda, const i
   }
   __syncthreads();
   const int nq = min(MB, n - r - j0);
-  for (int e = lane; e < nq * r; e += 64) {
-    const int c = e / r, l = e - c * r;
-    T[l * MTS + c] = Ab[(int64_t)npc[c] * lda + l];
+  // The right-hand sides (nq non-pivot columns x r rows) go to LDS, 16
+  // elements per lane at a time, their loads in flight together.
+  const int ne = nq * r;
+  for (int e0 = 0; e0 < ne; e0 += 64 * 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 64 * u + lane;
+      const int c = e < ne ? e / r : 0, l = e < ne ? e - c * r : 0;
+      v[u] = e < ne ? Ab[(int64_t)npc[c] * lda + l] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 64 * u + lane;
+      if (e < ne) {
+        const int c = e / r, l = e - c * r;
+        T[l * MTS + c] = v[u];
+      }
+    }
   }
   __syncthreads();
   if (nq > 0 && r > 0) {
@@ -667,42 +696,36 @@ k_id_solve_mfma(const double* __restrict__ A, int64_t a_stride, int lda, const i
       for (int k4 = 0; k4 < MB / 4; ++k4) dv[k4] = D[4 * k4];
       dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
       // Trailing products over 16-row chunks of the solved rows below the
-      // block. Operands are loaded two chunks ahead of their products, into
-      // three buffers used in turn (no register copies, so the waits stay
-      // exact); rows at or past the rank read the zero row r16 of T against
-      // a real column of R.
+      // block, in batches of up to 16 chunks: a batch's R operands are all
+      // loaded first (one memory round trip per batch instead of one per
+      // chunk), then multiplied in chunk order. Rows at or past the rank read
+      // the zero row r16 of T against a real column of R.
       const double* Ak = Ab + kb + i16;
-      auto ld = [&](double(&a)[4], double(&bq)[4], int lc) {
+      for (int l0 = kb + MB; l0 < r; l0 += 16 * MB) {
+        const int nch = min(16, (r - l0 + MB - 1) / MB);
+        double a[16][4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int l = lc + 4 * m + g;
-          const bool in = l < r;
-          a[m] = Ak[(int64_t)pv[in ? l : r] * lda];
-          bq[m] = T[(in ? l : r16) * MTS + i16];
-        }
-      };
-      auto mm = [&](const double(&a)[4], const double(&bq)[4]) {
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], bq[0], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], bq[1], acc1, 0, 0, 0);
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], bq[2], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], bq[3], acc1, 0, 0, 0);
-      };
-      int l0 = kb + MB;
-      if (l0 < r) {
-        double xa[4], xb[4], ya[4], yb[4], za[4], zb[4];
-        ld(xa, xb, l0);
-        ld(ya, yb, l0 + MB);
-        while (true) {
-          ld(za, zb, l0 + 2 * MB);
-          mm(xa, xb);
-          if ((l0 += MB) >= r) break;
-          ld(xa, xb, l0 + 2 * MB);
-          mm(ya, yb);
-          if ((l0 += MB) >= r) break;
-          ld(ya, yb, l0 + 2 * MB);
-          mm(za, zb);
-          if ((l0 += MB) >= r) break;
-        }
+        for (int c = 0; c < 16; ++c)
+          if (c < nch)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              const int l = l0 + MB * c + 4 * m + g;
+              a[c][m] = Ak[(int64_t)pv[l < r ? l : r] * lda];
+            }
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c < nch) {
+            double bq[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              const int l = l0 + MB * c + 4 * m + g;
+              bq[m] = T[(l < r ? l : r16) * MTS + i16];
+            }
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][0], bq[0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][1], bq[1], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][2], bq[2], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][3], bq[3], acc1, 0, 0, 0);
+          }
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
