@@ -915,8 +915,13 @@ __global__ void __launch_bounds__(512) k_select_rows(const float* __restrict__ s
     // Softmax: the maximum, then the sum of exponentials (each thread sums
     // candidates tid, tid + 512, ... in order, then a pairwise tree: halves
     // 256, 128, 64 through LDS, the rest by shuffles in wave 0).
+    float st[SEL_E];   // candidates tid + 512 j, loaded together
+#pragma unroll
+    for (int j = 0; j < SEL_E; ++j) st[j] = sc[(int64_t)min(tid + SEL_T * j, P - 1) * elem_stride];
     mx = -INFINITY;
-    for (int i = tid; i < P; i += SEL_T) mx = fmax(mx, (double)sc[(int64_t)i * elem_stride]);
+#pragma unroll
+    for (int j = 0; j < SEL_E; ++j)
+      if (tid + SEL_T * j < P) mx = fmax(mx, (double)st[j]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
     if (lane == 0) red[tid >> 6] = mx;
@@ -925,7 +930,9 @@ __global__ void __launch_bounds__(512) k_select_rows(const float* __restrict__ s
     for (int q = 0; q < SEL_T / 64; ++q) mx = fmax(mx, red[q]);
     __syncthreads();
     se = 0.0;
-    for (int i = tid; i < P; i += SEL_T) se += exp((double)sc[(int64_t)i * elem_stride] - mx);
+#pragma unroll
+    for (int j = 0; j < SEL_E; ++j)
+      if (tid + SEL_T * j < P) se += exp((double)st[j] - mx);
     red[tid] = se;
     __syncthreads();
     for (int off = SEL_T / 2; off >= 64; off >>= 1) {
@@ -946,13 +953,17 @@ __global__ void __launch_bounds__(512) k_select_rows(const float* __restrict__ s
   }
   // Keys of this thread's candidates (padding sorts after every key).
   const int E = (P + SEL_T - 1) / SEL_T, i0 = tid * E;
+  // (The scores are loaded first, all together, from clamped positions.)
+  float sv[SEL_E];
+#pragma unroll
+  for (int j = 0; j < SEL_E; ++j) sv[j] = sc[(int64_t)min(i0 + j, P - 1) * elem_stride];
   uint64_t u[SEL_E];
 #pragma unroll
   for (int j = 0; j < SEL_E; ++j) {
     const int i = i0 + j;
     u[j] = ~0ull;
     if (j < E && i < P) {
-      const double v = (double)sc[(int64_t)i * elem_stride];
+      const double v = (double)sv[j];
       double kv;
       if (mode == 2) {
         kv = v;
@@ -1025,12 +1036,15 @@ __global__ void __launch_bounds__(512) k_select_rows(const float* __restrict__ s
     nsel += take;
   }
   int o = block_exscan(nsel, wsum, total);
+  int pv[SEL_E + 1];   // this thread's pool rows and the next one (loaded together)
+#pragma unroll
+  for (int j = 0; j <= SEL_E; ++j) pv[j] = pl[min(i0 + j, P - 1)];
   bool descent = false;   // the pool is not ascending here
 #pragma unroll
   for (int j = 0; j < SEL_E; ++j) {
     const int i = i0 + j;
-    if (j < E && i + 1 < P) descent |= pl[i + 1] <= pl[i];
-    if ((chosen >> j) & 1) sel_out[o++] = pl[i];
+    if (j < E && i + 1 < P) descent |= pv[j + 1] <= pv[j];
+    if ((chosen >> j) & 1) sel_out[o++] = pv[j];
   }
   if (__syncthreads_or(descent)) {   // bitonic sort of the chosen rows
     for (int i = s_req + tid; i < sort_s; i += SEL_T) sel_out[i] = INT_MAX;
