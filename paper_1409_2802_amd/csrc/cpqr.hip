@@ -281,7 +281,26 @@ __global__ void __launch_bounds__(256) k_upward(int first, int leaves, const int
   for (int i0 = 16 * (int)blockIdx.y + 4 * w; i0 < min(r, 16 * (int)blockIdx.y + 16); i0 += 4 * nw) {
     const int nr = min(4, r - i0);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int j = lane; j < n; j += 64) {
+    // Four passes at a time with their loads issued first (rows past nr
+    // read row i0), then the products in pass order, so each sum keeps its
+    // order.
+    int j = lane;
+    for (; j + 192 < n; j += 256) {
+      double qv[4], pv[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int jj = j + 64 * u;
+        qv[u] = *((leaves || jj < rl) ? ql + jj : qr + (jj - rl));
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pv[u][t] = Pn[(int64_t)(i0 + (t < nr ? t : 0)) * n_cap + jj];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t < nr) acc[t] = fma(pv[u][t], qv[u], acc[t]);
+    }
+    for (; j < n; j += 64) {
       const double qj = (leaves || j < rl) ? ql[j] : qr[j - rl];
 #pragma unroll
       for (int t = 0; t < 4; ++t)

@@ -87,7 +87,15 @@ __global__ void __launch_bounds__(256) k_geometry(const double* __restrict__ Xt,
   const int32_t* cols = ga.cols + (int64_t)b * ga.col_stride;
   double* cen = ga.cen + (int64_t)b * d;
   const uint64_t node = (uint64_t)ga.node_ids[b];
-  for (int j = tid; j < n; j += 256) scol[j] = cols[j];
+  // (Eight passes' loads at a time, issued before their stores.)
+  for (int j0 = 0; j0 < n; j0 += 256 * 8) {
+    int cv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) cv[u] = cols[min(j0 + 256 * u + tid, n - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (j0 + 256 * u + tid < n) scol[j0 + 256 * u + tid] = cv[u];
+  }
   __syncthreads();
   // Centroid: dimension k is summed in P interleaved column parts (part p
   // takes columns p, p + P, ...), each with two alternating accumulators, and
