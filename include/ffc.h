@@ -430,14 +430,17 @@ ffc_status ffc_proposal_load(const char* path, ffc_proposal** out);
  * at least 1), stream id ids_dev[g] (the node id in skeletonization) and
  * targets tgt_dev[g * tgt_stride + i], i < ntgt_dev[g] (tree positions); the
  * features go to feat_dev[(g * tgt_stride + i) * 16 + f] (other slots are not
- * written). All arrays are device arrays. Synchronizes (geometry scratch). */
+ * written). All arrays are device arrays. Synchronizes (geometry scratch).
+ * FFC_ERR_INVALID_ARG when col_stride > 16384 or when the column geometry of
+ * dimension d does not fit in a compute unit's LDS (d above about 9000). */
 ffc_status ffc_proposal_features(const ffc_tree* t, const int32_t* cols_dev, int32_t col_stride,
                                  const int32_t* ncols_dev, const int32_t* ids_dev, const int32_t* tgt_dev,
                                  int32_t tgt_stride, const int32_t* ntgt_dev, int32_t count, uint64_t seed,
                                  float* feat_dev, void* stream);
 /* Sets mu, sd from `count` feature rows (population std floored at 1e-6). */
 ffc_status ffc_proposal_fit_standardization(ffc_proposal* p, const float* feat_dev, int64_t count, void* stream);
-/* score_dev[i] = network output for feature row i. */
+/* score_dev[i] = network output for feature row i (feat_dev: count x 16 floats,
+ * 16-byte aligned, as device allocations are; FP32 matrix-core arithmetic). */
 ffc_status ffc_proposal_score(const ffc_proposal* p, const float* feat_dev, int64_t count, float* score_dev,
                               void* stream);
 /* Mean squared error of the scores against target_dev over `count` rows and
