@@ -431,8 +431,9 @@ ffc_status ffc_proposal_load(const char* path, ffc_proposal** out);
  * targets tgt_dev[g * tgt_stride + i], i < ntgt_dev[g] (tree positions); the
  * features go to feat_dev[(g * tgt_stride + i) * 16 + f] (other slots are not
  * written). All arrays are device arrays. Synchronizes (geometry scratch).
- * FFC_ERR_INVALID_ARG when col_stride > 16384 or when the column geometry of
- * dimension d does not fit in a compute unit's LDS (d above about 9000). */
+ * FFC_ERR_INVALID_ARG when col_stride > 16384 or when the column geometry does
+ * not fit in a compute unit's LDS (8 d + 4 col_stride above about 114000
+ * bytes for d > 64). */
 ffc_status ffc_proposal_features(const ffc_tree* t, const int32_t* cols_dev, int32_t col_stride,
                                  const int32_t* ncols_dev, const int32_t* ids_dev, const int32_t* tgt_dev,
                                  int32_t tgt_stride, const int32_t* ntgt_dev, int32_t count, uint64_t seed,
