@@ -14,6 +14,7 @@ from oracle import proposal as pr
 from oracle.evaluate import evaluate as o_evaluate
 from oracle.evaluate import exact_far_field
 from oracle.kernels import GAUSSIAN, LAPLACE, kernel_matrix
+from oracle.sampling import floyd_sample
 from oracle.skeleton import skeletonize as o_skeletonize
 from oracle.tree import build_tree as o_build_tree
 from paper_1409_2802_amd import workloads as W
@@ -62,6 +63,33 @@ def test_features_match_oracle(ffc, d):
     feat = ffc.proposal_features(t, cols, ncols, ids, tgt, ntgt, seed=11).cpu().numpy()
     for g in range(5):
         geo = pr.column_geometry(Xt[cols[g, :ncols[g]]], 11, ids[g])
+        F = pr.features(Xt[tgt[g, :ntgt[g]]], geo)
+        np.testing.assert_allclose(feat[g, :ntgt[g]], F, rtol=1e-6, atol=1e-6, err_msg=f"block {g}")
+
+
+@pytest.mark.parametrize("d", [64, 100])
+def test_features_largest_column_set(ffc, d):
+    """A column set at the 16384-point capacity (the geometry's largest LDS layout: staged subsample for d <= 64,
+    column indices and transposition tiles otherwise), one with a ragged tail, and targets that include column
+    points (zero distances: the explicit-difference path of the Gram-form distances)."""
+    X = W.gaussian_mixture(20000, d, k=8, box=6.0, std=0.5, seed=3)
+    t, ot = trees(ffc, X, 2500)
+    Xt = X[ot.perm]
+    rng = np.random.default_rng(7)
+    ncols = [16384, 16383]
+    ntgt = [130, 67]
+    ids = [9, 1 << 19]
+    cols = np.zeros((2, 16384), dtype=np.int32)
+    tgt = np.zeros((2, 130), dtype=np.int32)
+    for g in range(2):
+        cols[g, :ncols[g]] = np.sort(rng.choice(20000, ncols[g], replace=False))
+        pick = rng.choice(20000, ntgt[g], replace=False)
+        sub = floyd_sample(ncols[g], pr.SUB, 5, ids[g] | pr.STREAM_SUBSAMPLE)
+        pick[:20] = cols[g, sub[:20]]   # targets that are subsample points: zero distances
+        tgt[g, :ntgt[g]] = pick
+    feat = ffc.proposal_features(t, cols, ncols, ids, tgt, ntgt, seed=5).cpu().numpy()
+    for g in range(2):
+        geo = pr.column_geometry(Xt[cols[g, :ncols[g]]], 5, ids[g])
         F = pr.features(Xt[tgt[g, :ntgt[g]]], geo)
         np.testing.assert_allclose(feat[g, :ntgt[g]], F, rtol=1e-6, atol=1e-6, err_msg=f"block {g}")
 
