@@ -604,31 +604,16 @@ k_diag_inv(const double* __restrict__ A, int64_t a_stride, int lda, const int32_
   }
 }
 
-__global__ void __launch_bounds__(64)
-k_id_solve_mfma(const double* __restrict__ A, int64_t a_stride, int lda, const int32_t* __restrict__ n_arr,
-                int n_uniform, int n_max, const int32_t* __restrict__ rank, int32_t* __restrict__ piv,
-                int64_t piv_stride, const double* __restrict__ Dinv, int nblk, double* __restrict__ P,
-                int64_t p_stride, int p_ld, int r_max, const unsigned char* __restrict__ mask) {
-  extern __shared__ double smm[];
-  const int b = blockIdx.x, j0 = MB * (int)blockIdx.y;
-  if (mask && !mask[b]) return;
-  const int n = n_arr ? n_arr[b] : n_uniform;
-  if (j0 >= n) return;
-  const int r = rank[b], r16 = round_mb_dev(r);
-  const int t_rows = round_mb_dev(r_max) + MB;
-  double* T = smm;                                                   // t_rows x MTS
-  int* pv = reinterpret_cast<int*>(T + (size_t)t_rows * MTS);        // r_max + MB pivot columns
-  unsigned int* isp = reinterpret_cast<unsigned int*>(pv + r_max + MB);   // pivot bitmap
-  int* npc = reinterpret_cast<int*>(isp + (n_max + 31) / 32);        // this chunk's non-pivot columns
-  int* posl = npc + MB;                                  // pivot position of column j0 + c, or -1
-  const int lane = threadIdx.x, i16 = lane & 15, g = lane >> 4;
-  const double* Ab = A + (int64_t)b * a_stride;
-  const int32_t* pb = piv + (int64_t)b * piv_stride;
+// The columns of a solve chunk, in LDS: pv = the pivot order (pv[r..r+15] =
+// pv[0], a real column for the rows past the rank), isp = the pivot bitmap,
+// npc = the chunk's non-pivot columns (place j0 + c in ascending non-pivot
+// order), posl = the pivot position of column j0 + c or -1. One wavefront;
+// synchronizes.
+__device__ inline void solve_columns(const int32_t* __restrict__ pb, int r, int n, int j0, int* pv,
+                                     unsigned int* isp, int* npc, int* posl) {
+  const int lane = threadIdx.x;
   for (int w = lane; w < (n + 31) / 32; w += 64) isp[w] = 0u;
   if (lane < MB) posl[lane] = -1;
-  // Rows r .. r16 + MB - 1 stay zero: the padded part of the last diagonal
-  // block and the tail of the last 16-row chunk of the trailing products.
-  for (int e = lane; e < (r16 + MB) * MB; e += 64) T[(e >> 4) * MTS + (e & 15)] = 0.0;
   __syncthreads();
   // (Pivot loads of up to 8 passes are issued together, then used: one
   // memory round trip instead of one per pass.)
@@ -664,6 +649,32 @@ k_id_solve_mfma(const double* __restrict__ A, int64_t a_stride, int lda, const i
     base += __popcll(m);
   }
   __syncthreads();
+}
+
+__global__ void __launch_bounds__(64)
+k_id_solve_mfma(const double* __restrict__ A, int64_t a_stride, int lda, const int32_t* __restrict__ n_arr,
+                int n_uniform, int n_max, const int32_t* __restrict__ rank, int32_t* __restrict__ piv,
+                int64_t piv_stride, const double* __restrict__ Dinv, int nblk, double* __restrict__ P,
+                int64_t p_stride, int p_ld, int r_max, const unsigned char* __restrict__ mask) {
+  extern __shared__ double smm[];
+  const int b = blockIdx.x, j0 = MB * (int)blockIdx.y;
+  if (mask && !mask[b]) return;
+  const int n = n_arr ? n_arr[b] : n_uniform;
+  if (j0 >= n) return;
+  const int r = rank[b], r16 = round_mb_dev(r);
+  const int t_rows = round_mb_dev(r_max) + MB;
+  double* T = smm;                                                   // t_rows x MTS
+  int* pv = reinterpret_cast<int*>(T + (size_t)t_rows * MTS);        // r_max + MB pivot columns
+  unsigned int* isp = reinterpret_cast<unsigned int*>(pv + r_max + MB);   // pivot bitmap
+  int* npc = reinterpret_cast<int*>(isp + (n_max + 31) / 32);        // this chunk's non-pivot columns
+  int* posl = npc + MB;                                  // pivot position of column j0 + c, or -1
+  const int lane = threadIdx.x, i16 = lane & 15, g = lane >> 4;
+  const double* Ab = A + (int64_t)b * a_stride;
+  const int32_t* pb = piv + (int64_t)b * piv_stride;
+  // Rows r .. r16 + MB - 1 stay zero: the padded part of the last diagonal
+  // block and the tail of the last 16-row chunk of the trailing products.
+  for (int e = lane; e < (r16 + MB) * MB; e += 64) T[(e >> 4) * MTS + (e & 15)] = 0.0;
+  solve_columns(pb, r, n, j0, pv, isp, npc, posl);
   const int nq = min(MB, n - r - j0);
   // The right-hand sides (nq non-pivot columns x r rows) go to LDS, 16
   // elements per lane at a time, their loads in flight together.
@@ -749,6 +760,112 @@ k_id_solve_mfma(const double* __restrict__ A, int64_t a_stride, int lda, const i
     if (c < nq) Pb[(int64_t)i * p_ld + npc[c]] = T[i * MTS + c];
     const int pl = posl[c];
     if (pl >= 0) Pb[(int64_t)i * p_ld + j0 + c] = pl == i ? 1.0 : 0.0;
+  }
+  for (int c = lane; c < nq; c += 64) piv[(int64_t)b * piv_stride + r + j0 + c] = npc[c];
+}
+
+// The same solve for ranks up to kRegSolveRank with the right-hand sides in
+// registers: lane (i16, g) holds T[4 i + g][i16], i < 64. Those are exactly
+// the B operands it supplies to the trailing products and to the product with
+// the diagonal inverse, and the rows of the block it updates, so T needs
+// neither LDS nor barriers, and two wavefronts share a SIMD (the LDS-resident
+// version's 37 KB of T allowed one). The 16 blocks and their chunks are
+// unrolled so that every register index is fixed; the products run in the
+// same order as in k_id_solve_mfma, so the results are the same bits.
+constexpr int kRegSolveRank = 256;
+
+__global__ void __launch_bounds__(64, 2)
+k_id_solve_regs(const double* __restrict__ A, int64_t a_stride, int lda, const int32_t* __restrict__ n_arr,
+                int n_uniform, int n_max, const int32_t* __restrict__ rank, int32_t* __restrict__ piv,
+                int64_t piv_stride, const double* __restrict__ Dinv, int nblk, double* __restrict__ P,
+                int64_t p_stride, int p_ld, int r_max, const unsigned char* __restrict__ mask) {
+  extern __shared__ int smi[];
+  const int b = blockIdx.x, j0 = MB * (int)blockIdx.y;
+  if (mask && !mask[b]) return;
+  const int n = n_arr ? n_arr[b] : n_uniform;
+  if (j0 >= n) return;
+  const int r = rank[b], r16 = round_mb_dev(r);
+  int* pv = smi;                                                          // r_max + MB
+  unsigned int* isp = reinterpret_cast<unsigned int*>(pv + r_max + MB);  // pivot bitmap
+  int* npc = reinterpret_cast<int*>(isp + (n_max + 31) / 32);
+  int* posl = npc + MB;
+  const int lane = threadIdx.x, i16 = lane & 15, g = lane >> 4;
+  const double* Ab = A + (int64_t)b * a_stride;
+  const int32_t* pb = piv + (int64_t)b * piv_stride;
+  solve_columns(pb, r, n, j0, pv, isp, npc, posl);
+  const int nq = min(MB, n - r - j0);
+  constexpr int NR = kRegSolveRank / 4;
+  double T[NR];
+  {
+    const double* col = Ab + (int64_t)npc[i16 < nq ? i16 : 0] * lda;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int l = 4 * i + g;
+      T[i] = (l < r && i16 < nq) ? col[l] : 0.0;
+    }
+  }
+  if (nq > 0 && r > 0) {
+#pragma unroll
+    for (int bi = kRegSolveRank / MB - 1; bi >= 0; --bi) {
+      if (MB * bi >= r16) continue;
+      const int kb = MB * bi;
+      const double* D = Dinv + ((int64_t)b * nblk + bi) * MB * MB + i16 * MB + g;
+      double dv[MB / 4];
+#pragma unroll
+      for (int k4 = 0; k4 < MB / 4; ++k4) dv[k4] = D[4 * k4];
+      dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+      // R operands are addressed by 32-bit byte offsets from the uniform
+      // base of the block (the host keeps the block under 2^32 bytes).
+      const char* Abc = reinterpret_cast<const char*>(Ab);
+      const unsigned ko = (unsigned)(kb + i16);
+      // Trailing products over the chunks cb > bi that start below the rank,
+      // two chunks' R operands loaded at a time.
+#pragma unroll
+      for (int c0 = bi + 1; c0 < kRegSolveRank / MB; c0 += 2) {
+        if (MB * c0 >= r) break;
+        double a[2][4];
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+          if (c0 + c < kRegSolveRank / MB && MB * (c0 + c) < r)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              const int l = MB * (c0 + c) + 4 * m + g;
+              const unsigned off = ((unsigned)pv[l < r ? l : r] * (unsigned)lda + ko) * 8u;
+              a[c][m] = *reinterpret_cast<const double*>(Abc + off);
+            }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int cb = c0 + c;
+          if (cb < kRegSolveRank / MB && MB * cb < r) {
+            double bq[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) bq[m] = MB * cb + 4 * m + g < r ? T[4 * cb + m] : 0.0;
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][0], bq[0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][1], bq[1], acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][2], bq[2], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][3], bq[3], acc1, 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[4 * bi + v] = T[4 * bi + v] - (acc0[v] + acc1[v]);
+      dbl4 x = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k4 = 0; k4 < MB / 4; ++k4) x = __builtin_amdgcn_mfma_f64_16x16x4f64(dv[k4], T[4 * bi + k4], x, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[4 * bi + v] = x[v];
+    }
+  }
+  double* Pb = P + (int64_t)b * p_stride;
+  const int pl = posl[i16];
+  const int npj = npc[i16 < nq ? i16 : 0];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int l = 4 * i + g;
+    if (l < r) {
+      if (i16 < nq) Pb[(int64_t)l * p_ld + npj] = T[i];
+      if (pl >= 0) Pb[(int64_t)l * p_ld + j0 + i16] = pl == l ? 1.0 : 0.0;
+    }
   }
   for (int c = lane; c < nq; c += 64) piv[(int64_t)b * piv_stride + r + j0 + c] = npc[c];
 }
@@ -879,18 +996,27 @@ ffc_status launch_solve(const IdBatch& bt, int batch, QrScratch scratch, hipStre
     return FFC_ERR_STATE;
   }
   double* Dinv = reinterpret_cast<double*>(scratch.ptr());
-  const size_t lds = mfma_solve_lds_bytes(r_max, bt.n_max);
-  if (lds > 64 * 1024)
+  const bool regs = r_max <= kRegSolveRank && (int64_t)bt.lda * bt.n_max * (int64_t)sizeof(double) < (INT64_C(1) << 32);
+  const size_t lds = regs ? ((size_t)r_max + 3 * MB + (bt.n_max + 31) / 32) * sizeof(int)
+                          : mfma_solve_lds_bytes(r_max, bt.n_max);
+  if (!regs && lds > 64 * 1024)
     FFC_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_id_solve_mfma),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   StageTimer tm(FFC_STAGE_SOLVE, st);
   hipLaunchKernelGGL(k_diag_inv, dim3(batch, nblk), dim3(64), 0, st, bt.A, bt.a_stride, bt.lda, bt.rank, bt.piv,
                      bt.piv_stride, Dinv, nblk, bt.mask);
   FFC_LAUNCH_CHECK("k_diag_inv");
-  hipLaunchKernelGGL(k_id_solve_mfma, dim3(batch, (bt.n_max + MB - 1) / MB), dim3(64), lds, st, bt.A, bt.a_stride,
-                     bt.lda, bt.n_arr, bt.n_uniform, bt.n_max, bt.rank, bt.piv, bt.piv_stride, Dinv, nblk, bt.P,
-                     bt.p_stride, bt.p_ld, r_max, bt.mask);
-  FFC_LAUNCH_CHECK("k_id_solve_mfma");
+  if (regs) {
+    hipLaunchKernelGGL(k_id_solve_regs, dim3(batch, (bt.n_max + MB - 1) / MB), dim3(64), lds, st, bt.A,
+                       bt.a_stride, bt.lda, bt.n_arr, bt.n_uniform, bt.n_max, bt.rank, bt.piv, bt.piv_stride, Dinv,
+                       nblk, bt.P, bt.p_stride, bt.p_ld, r_max, bt.mask);
+    FFC_LAUNCH_CHECK("k_id_solve_regs");
+  } else {
+    hipLaunchKernelGGL(k_id_solve_mfma, dim3(batch, (bt.n_max + MB - 1) / MB), dim3(64), lds, st, bt.A,
+                       bt.a_stride, bt.lda, bt.n_arr, bt.n_uniform, bt.n_max, bt.rank, bt.piv, bt.piv_stride, Dinv,
+                       nblk, bt.P, bt.p_stride, bt.p_ld, r_max, bt.mask);
+    FFC_LAUNCH_CHECK("k_id_solve_mfma");
+  }
   return FFC_OK;
 }
 
