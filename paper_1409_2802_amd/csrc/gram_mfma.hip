@@ -38,6 +38,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // (selects on it are per element)
 
 constexpr int TM = 64, TN = 64, KCH = 32, NTH = 256;
 constexpr int LROW = KCH + 8;   // bf16 per LDS row (16-byte aligned, spread over banks)
@@ -733,6 +734,250 @@ __global__ void __launch_bounds__(NTH, 3) k_evaluate_mixed(const double* __restr
   if (bad) atomicOr(flag, 1u);
 }
 
+// k_evaluate_mixed on the pre-split operands for rows of at most 64
+// dimensions, staged per workgroup. The 64 target rows and their norms go to
+// LDS once for all tiles. Each 64-point column tile (a sibling's skeleton
+// points at every level from the leaf up, then the leaf's own points) is staged
+// at full width with its norms and charges, and the next tiles' loads are in
+// flight while a tile is multiplied: the points of tile t + 1 and the skeleton
+// indices of tile t + 2 during tile t. Same products in the same order and the
+// same sums as k_evaluate_mixed, so the same bits.
+constexpr int kStagedTiles = 96;   // column tiles a workgroup's list holds
+
+template <int NC>
+struct __attribute__((aligned(16))) StagedSmem {
+  __bf16 yh[TM][NC * KCH + 8], yl[TM][NC * KCH + 8];   // target rows (B operand), 16-byte rows
+  __bf16 xh[TN][NC * KCH + 8], xl[TN][NC * KCH + 8];   // column points (A operand)
+  double xq[TN];                                       // the column points' charges
+  float yn[TM], xn[TN];
+  int64_t tb[kStagedTiles];   // tile base: skeleton slot (far field) or point position (near field)
+  int tn[kStagedTiles];       // points in the tile; negative for the near field
+  int nt, nfar;
+};
+
+// The skeleton position of point p of a far-field tile t of k_evaluate_staged,
+// as loaded (from a clamped slot; anything for other tiles). The caller does
+// not touch it until it loads the tile's points, a tile later: any arithmetic
+// on it here would wait for the load.
+__device__ __attribute__((always_inline)) inline int32_t staged_index(int t, int nt, const int* tn, const int64_t* tb,
+                                                                      const int32_t* __restrict__ skel, int p) {
+  int32_t raw = 0;
+  if (t < nt) {
+    const int n = tn[t];
+    if (n > 0) raw = skel[tb[t] + min(p, n - 1)];
+  }
+  return raw;
+}
+
+// The operands of tile t for point p and group part into registers: groups 0
+// and (NC = 2) 1 of the part's 8 NC values of each split, the point's norm and
+// charge, and whether the point exists. Every load reads a valid address (row
+// or slot 0 stands in for a missing point); the values are masked only when
+// they are stored, a tile later. (Plain functions and named registers: a
+// lambda's captured pointers and an array carried around the loop both ended
+// up in scratch memory.)
+template <int NC>
+__device__ __attribute__((always_inline)) inline void staged_load_tile(
+    int t, int32_t raw, int nt, const int* tn, const int64_t* tb, int p, int part, const __bf16* __restrict__ Hh,
+    const __bf16* __restrict__ Hl, const float* __restrict__ nrm, const double* __restrict__ qt,
+    const double* __restrict__ q_tree, u32x4& xh0, u32x4& xh1, u32x4& xl0, u32x4& xl1, float& xn, double& xq,
+    bool& xv) {
+  constexpr int DP = NC * KCH, PW = NC * 8;
+  int64_t pt = 0, qi = 0;
+  bool far = false, valid = false;
+  if (t < nt) {
+    const int n = tn[t];
+    const int64_t base = tb[t];
+    far = n > 0;
+    const int cnt = far ? n : -n;
+    valid = p < cnt;
+    qi = base + min(p, cnt - 1);
+    pt = far ? (int64_t)raw : qi;
+  }
+  const __bf16* hp = Hh + pt * DP + part * PW;
+  const __bf16* lp = Hl + pt * DP + part * PW;
+  xh0 = *reinterpret_cast<const u32x4*>(hp);
+  xl0 = *reinterpret_cast<const u32x4*>(lp);
+  if constexpr (NC == 2) {
+    xh1 = *reinterpret_cast<const u32x4*>(hp + 8);
+    xl1 = *reinterpret_cast<const u32x4*>(lp + 8);
+  }
+  xn = nrm ? nrm[pt] : 0.f;
+  const double* qb = far ? qt : q_tree;
+  xq = qb[qi];
+  xv = valid;
+}
+
+template <bool DOT, int NC>
+__global__ void __launch_bounds__(NTH, 3)
+k_evaluate_staged(const __bf16* __restrict__ Hh, const __bf16* __restrict__ Hl, const float* __restrict__ nrm,
+                  KParams kp, int depth, const int32_t* __restrict__ tile_leaf, const int32_t* __restrict__ tile_start,
+                  const int32_t* __restrict__ nb, const int32_t* __restrict__ ne, const double* __restrict__ q_tree,
+                  const int32_t* __restrict__ rank, const int32_t* __restrict__ skel, int r_cap,
+                  const double* __restrict__ qt, const int32_t* __restrict__ perm, double* __restrict__ u,
+                  double* __restrict__ u_far, unsigned int* flag) {
+  constexpr int DP = NC * KCH;   // row length of the split operands
+  constexpr int PW = NC * 8;     // values a thread stages per row
+  __shared__ StagedSmem<NC> sm;
+  __shared__ double red[8 * 64];
+  __shared__ double far_sum[TM], near_sum[TM];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int leaf = tile_leaf[blockIdx.x];
+  const int start = tile_start[blockIdx.x];
+  const int nrows = min(TM, ne[leaf] - start);
+  const int lb = nb[leaf];
+  // Tile list: lane l < depth takes the sibling of the leaf's ancestor l
+  // levels up, lane depth the leaf itself; an exclusive scan of the tile counts
+  // places them in the order of k_evaluate_mixed.
+  if (w == 0) {
+    int a = leaf;
+    for (int i = 0; i < lane && i < depth; ++i) a = (a - 1) >> 1;
+    int cnt = 0, r = 0;
+    int64_t base = 0;
+    if (lane < depth) {
+      const int sib = (a & 1) ? a + 1 : a - 1;
+      r = rank[sib];
+      base = (int64_t)sib * r_cap;
+    } else if (lane == depth) {
+      r = ne[leaf] - lb;
+      base = lb;
+    }
+    if (lane <= depth && r > 0) cnt = (r + TN - 1) / TN;
+    int incl = cnt;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += y;
+    }
+    const int off0 = incl - cnt;
+    for (int j = 0; j < cnt; ++j) {
+      const int np = min(TN, r - j * TN);
+      sm.tb[off0 + j] = base + j * TN;
+      sm.tn[off0 + j] = lane < depth ? np : -np;
+    }
+    if (lane == depth) {
+      sm.nt = incl;
+      sm.nfar = off0;
+    }
+  }
+  const int p = tid >> 2, part = tid & 3;
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  {
+    const bool yv = p < nrows;
+    const int64_t yrow = (int64_t)start + (yv ? p : 0);
+    const __bf16* hp = Hh + yrow * DP + part * PW;
+    const __bf16* lp = Hl + yrow * DP + part * PW;
+    const u32x4 h0 = *reinterpret_cast<const u32x4*>(hp);
+    const u32x4 l0 = *reinterpret_cast<const u32x4*>(lp);
+    u32x4 h1 = zero, l1 = zero;
+    if constexpr (NC == 2) {
+      h1 = *reinterpret_cast<const u32x4*>(hp + 8);
+      l1 = *reinterpret_cast<const u32x4*>(lp + 8);
+    }
+    const float yn = nrm ? nrm[yrow] : 0.f;
+    *reinterpret_cast<u32x4*>(&sm.yh[p][part * PW]) = yv ? h0 : zero;
+    *reinterpret_cast<u32x4*>(&sm.yl[p][part * PW]) = yv ? l0 : zero;
+    if constexpr (NC == 2) {
+      *reinterpret_cast<u32x4*>(&sm.yh[p][part * PW + 8]) = yv ? h1 : zero;
+      *reinterpret_cast<u32x4*>(&sm.yl[p][part * PW + 8]) = yv ? l1 : zero;
+    }
+    if (part == 0) sm.yn[p] = yv ? yn : 0.f;
+  }
+  __syncthreads();   // tile list and target rows
+  const int nt = sm.nt, nfar = sm.nfar;
+  // The staged tile's operands in registers (see staged_load_tile).
+  u32x4 xh0 = zero, xh1 = zero, xl0 = zero, xl1 = zero;
+  float xn_r = 0.f;
+  double xq_r = 0.0;
+  bool xv = false;
+  staged_load_tile<NC>(0, staged_index(0, nt, sm.tn, sm.tb, skel, p), nt, sm.tn, sm.tb, p, part, Hh, Hl, nrm, qt,
+                       q_tree, xh0, xh1, xl0, xl1, xn_r, xq_r, xv);
+  int32_t raw_next = staged_index(1, nt, sm.tn, sm.tb, skel, p);
+  double part_f[2] = {0.0, 0.0}, part_n[2] = {0.0, 0.0};
+  bool bad = false;
+  for (int t = 0; t < nt; ++t) {
+    *reinterpret_cast<u32x4*>(&sm.xh[p][part * PW]) = xv ? xh0 : zero;
+    *reinterpret_cast<u32x4*>(&sm.xl[p][part * PW]) = xv ? xl0 : zero;
+    if constexpr (NC == 2) {
+      *reinterpret_cast<u32x4*>(&sm.xh[p][part * PW + 8]) = xv ? xh1 : zero;
+      *reinterpret_cast<u32x4*>(&sm.xl[p][part * PW + 8]) = xv ? xl1 : zero;
+    }
+    if (part == 0) {
+      sm.xn[p] = xv ? xn_r : 0.f;
+      sm.xq[p] = xv ? xq_r : 0.0;
+    }
+    const int n_t = sm.tn[t];
+    __syncthreads();
+    // The next tile's points (their positions were loaded one tile ago),
+    // then the positions of the tile after it.
+    staged_load_tile<NC>(t + 1, raw_next, nt, sm.tn, sm.tb, p, part, Hh, Hl, nrm, qt, q_tree, xh0, xh1, xl0, xl1,
+                         xn_r, xq_r, xv);
+    raw_next = staged_index(t + 2, nt, sm.tn, sm.tb, skel, p);
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < NC; ++kc) {
+      const int kofs = kc * KCH + (lane >> 4) * 8;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int xr = (w >> 1) * 32 + bi * 16 + (lane & 15);
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sm.xh[xr][kofs]);
+        const bf16x8 al = *reinterpret_cast<const bf16x8*>(&sm.xl[xr][kofs]);
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&sm.yh[yr][kofs]);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&sm.yl[yr][kofs]);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[bi][bj], 0, 0, 0);
+        }
+      }
+    }
+    const int ncols = n_t > 0 ? n_t : -n_t;
+    const bool far = t < nfar;
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+      const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+      double s = 0.0;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int xc = (w >> 1) * 32 + bi * 16 + (lane >> 4) * 4 + e;
+          if (xc < ncols) {
+            const float v = kfun_mixed<DOT>(acc[bi][bj][e], DOT ? 0.f : sm.yn[yr], DOT ? 0.f : sm.xn[xc], kp);
+            bad |= !isfinite(v);
+            s = fma((double)v, sm.xq[xc], s);
+          }
+        }
+      if (far) part_f[bj] += s;
+      else part_n[bj] += s;
+    }
+    __syncthreads();   // the tile's operands are rewritten by the next one
+  }
+  mixed_reduce(part_f, red, far_sum);
+  mixed_reduce(part_n, red, near_sum);
+  if (threadIdx.x < nrows) {
+    const int ci = perm[start + threadIdx.x];
+    const double f = far_sum[threadIdx.x];
+    u[ci] = f + near_sum[threadIdx.x];
+    if (u_far) u_far[ci] = f;
+  }
+  if (bad) atomicOr(flag, 1u);
+}
+
+// Column tiles a workgroup of k_evaluate_staged may list: every level's
+// sibling skeleton plus the largest leaf.
+int staged_tile_bound(const ffc_tree* t, const ffc_skel* sk) {
+  int max_leaf = 0;
+  const int first = (1 << t->depth) - 1;
+  for (int a = first; a < t->num_nodes; ++a) max_leaf = std::max(max_leaf, t->end_h[a] - t->begin_h[a]);
+  return t->depth * ((sk->r_cap + TN - 1) / TN) + (max_leaf + TN - 1) / TN;
+}
+
 // Far + near field of the Laplace kernel for one 64-target tile of a leaf
 // (the layout of k_evaluate_mixed), every tile centred on the target leaf.
 __global__ void __launch_bounds__(NTH) k_evaluate_laplace(int d, int depth, const int32_t* __restrict__ tile_leaf,
@@ -951,6 +1196,17 @@ ffc_status launch_evaluate_mixed(const ffc_tree* t, const ffc_skel* sk, const KP
                        sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->perm.ptr, sp.x, sp.cc, sp.dp, u, u_far,
                        device_flag());
     FFC_LAUNCH_CHECK("k_evaluate_laplace");
+    return FFC_OK;
+  }
+  if (sp.hi && (sp.dp == KCH || sp.dp == 2 * KCH) && t->depth < 63 && (int64_t)t->num_nodes == (2LL << t->depth) - 1 &&
+      staged_tile_bound(t, sk) <= kStagedTiles) {
+    const bool dot = kp.kind == FFC_POLYNOMIAL;
+    auto kern = dot ? (sp.dp == KCH ? &k_evaluate_staged<true, 1> : &k_evaluate_staged<true, 2>)
+                    : (sp.dp == KCH ? &k_evaluate_staged<false, 1> : &k_evaluate_staged<false, 2>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)t->num_tiles), dim3(NTH), 0, st, sp.hi, sp.lo, sp.nrm, kp, t->depth,
+                       t->tile_leaf.ptr, t->tile_start.ptr, t->begin.ptr, t->end.ptr, t->q_tree.ptr, sk->rank.ptr,
+                       sk->skel.ptr, sk->r_cap, sk->qt.ptr, t->perm.ptr, u, u_far, device_flag());
+    FFC_LAUNCH_CHECK("k_evaluate_staged");
     return FFC_OK;
   }
   if (kp.kind == FFC_POLYNOMIAL)

@@ -112,6 +112,29 @@ def test_every_qr_variant_gives_the_same_bits(ffc, monkeypatch, s, n, tol, max_r
             np.testing.assert_array_equal(P, ref[2], err_msg=f"variant {v}")
 
 
+@pytest.mark.parametrize("s,n", [(512, 701), (100, 90)])
+def test_solve_kernels_agree_below_and_above_rank_256(ffc, s, n):
+    """The interpolation solve keeps the right-hand sides in registers when the
+    rank bound min(max_rank, s, n) is at most 256 and in LDS above it. With the
+    rank set by the tolerance (below 256 either way) both run the same products
+    in the same order: max_rank 256 and 300 give the same rank, pivots and
+    bits of P, and those match the oracle."""
+    decays = (14.0, 20.0, 40.0)
+    mats = np.stack([decaying(s, n, seed, decay) for seed, decay in zip((21, 22, 23), decays)])
+    tol = 1e-6
+    outs = [tuple(x.cpu().numpy() for x in ffc.interp_decomp(mats, tol, mr)) for mr in (256, 300)]
+    (r0, p0, P0), (r1, p1, P1) = outs
+    assert int(r0.max()) < min(256, s, n), r0
+    assert len(set(r0.tolist())) == len(decays)   # ranks of different 16-row block counts
+    np.testing.assert_array_equal(r0, r1)
+    np.testing.assert_array_equal(p0, p1)
+    for b in range(len(mats)):   # P has max_rank rows; rows below the rank hold the solve
+        r = int(r0[b])
+        np.testing.assert_array_equal(P0[b, :r], P1[b, :r])
+    for b, A in enumerate(mats):
+        check_against_oracle(A, int(r0[b]), p0[b], P0[b], tol, 256)
+
+
 def test_autotune_cache_persists_choices(ffc, tmp_path, monkeypatch):
     """With FFC_TUNE_CACHE the QR autotuner's choice is written to the file; once the process forgets its
     choices (ffc_autotune_reset, as a new process starts) it reads them back, times nothing (the report marks
