@@ -969,6 +969,153 @@ k_evaluate_staged(const __bf16* __restrict__ Hh, const __bf16* __restrict__ Hl, 
   if (bad) atomicOr(flag, 1u);
 }
 
+// k_level_kblock_mixed on the pre-split operands for rows of at most 64
+// dimensions, staged per workgroup: one workgroup computes tpw consecutive
+// 64-column tiles of one 64-row tile of a node's block. The rows and their
+// norms go to LDS once; the column points of the next tile and the column
+// positions of the one after are loaded while a tile is multiplied. Same
+// products and kernel values as k_level_kblock_mixed, so the same bits.
+template <int NC>
+struct __attribute__((aligned(16))) KbSmem {
+  __bf16 yh[TM][NC * KCH + 8], yl[TM][NC * KCH + 8];
+  __bf16 xh[TN][NC * KCH + 8], xl[TN][NC * KCH + 8];
+  float yn[TM], xn[TN];
+};
+
+template <bool DOT, int NC>
+__global__ void __launch_bounds__(NTH, 3)
+k_kblock_staged(const __bf16* __restrict__ Hh, const __bf16* __restrict__ Hl, const float* __restrict__ nrm, KParams kp,
+                int first, int tiles_m, int groups_n, int tpw, const int32_t* __restrict__ rows,
+                const int32_t* __restrict__ nrows_a, int s_cap, const int32_t* __restrict__ cols,
+                const int32_t* __restrict__ ncols_a, int n_cap, const unsigned char* __restrict__ mask,
+                double* __restrict__ A, unsigned int* flag) {
+  constexpr int DP = NC * KCH, PW = NC * 8;
+  __shared__ KbSmem<NC> sm;
+  const int per = tiles_m * groups_n;
+  const int ln = blockIdx.x / per, rem = blockIdx.x % per;
+  const int node = first + ln;
+  if (mask && !mask[node]) return;
+  const int s = nrows_a[node], n = ncols_a[node];
+  const int r0 = (rem % tiles_m) * TM, cb = (rem / tiles_m) * tpw * TN;   // first row, first column
+  if (r0 >= s || cb >= n) return;
+  const int nt = min(tpw, (n - cb + TN - 1) / TN);   // column tiles of this workgroup
+  const int ncol = n - cb;                           // columns from cb to the node's last
+  const int32_t* rix = rows + (int64_t)node * s_cap + r0;
+  const int32_t* cix = cols + (int64_t)node * n_cap + cb;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int p = tid >> 2, part = tid & 3;
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  {
+    const bool yv = r0 + p < s;
+    const int64_t yrow = rix[yv ? p : 0];
+    const __bf16* hp = Hh + yrow * DP + part * PW;
+    const __bf16* lp = Hl + yrow * DP + part * PW;
+    const u32x4 h0 = *reinterpret_cast<const u32x4*>(hp);
+    const u32x4 l0 = *reinterpret_cast<const u32x4*>(lp);
+    u32x4 h1 = zero, l1 = zero;
+    if constexpr (NC == 2) {
+      h1 = *reinterpret_cast<const u32x4*>(hp + 8);
+      l1 = *reinterpret_cast<const u32x4*>(lp + 8);
+    }
+    const float yn = nrm ? nrm[yrow] : 0.f;
+    *reinterpret_cast<u32x4*>(&sm.yh[p][part * PW]) = yv ? h0 : zero;
+    *reinterpret_cast<u32x4*>(&sm.yl[p][part * PW]) = yv ? l0 : zero;
+    if constexpr (NC == 2) {
+      *reinterpret_cast<u32x4*>(&sm.yh[p][part * PW + 8]) = yv ? h1 : zero;
+      *reinterpret_cast<u32x4*>(&sm.yl[p][part * PW + 8]) = yv ? l1 : zero;
+    }
+    if (part == 0) sm.yn[p] = yv ? yn : 0.f;
+  }
+  // Column position of this thread's point in tile t, from a clamped slot (the
+  // node's last column stands in past it); masked when the tile is stored.
+  int32_t raw_cur = cix[min(p, ncol - 1)];
+  int32_t raw_next = nt > 1 ? cix[min(TN + p, ncol - 1)] : 0;
+  u32x4 xh0, xh1 = zero, xl0, xl1 = zero;
+  float xn_r;
+  {
+    const int64_t pt = raw_cur;
+    const __bf16* hp = Hh + pt * DP + part * PW;
+    const __bf16* lp = Hl + pt * DP + part * PW;
+    xh0 = *reinterpret_cast<const u32x4*>(hp);
+    xl0 = *reinterpret_cast<const u32x4*>(lp);
+    if constexpr (NC == 2) {
+      xh1 = *reinterpret_cast<const u32x4*>(hp + 8);
+      xl1 = *reinterpret_cast<const u32x4*>(lp + 8);
+    }
+    xn_r = nrm ? nrm[pt] : 0.f;
+  }
+  double* out = A + (int64_t)ln * s_cap * n_cap;
+  bool bad = false;
+  for (int t = 0; t < nt; ++t) {
+    const int c0 = cb + t * TN;
+    const bool xv = c0 + p < n;
+    *reinterpret_cast<u32x4*>(&sm.xh[p][part * PW]) = xv ? xh0 : zero;
+    *reinterpret_cast<u32x4*>(&sm.xl[p][part * PW]) = xv ? xl0 : zero;
+    if constexpr (NC == 2) {
+      *reinterpret_cast<u32x4*>(&sm.xh[p][part * PW + 8]) = xv ? xh1 : zero;
+      *reinterpret_cast<u32x4*>(&sm.xl[p][part * PW + 8]) = xv ? xl1 : zero;
+    }
+    if (part == 0) sm.xn[p] = xv ? xn_r : 0.f;
+    __syncthreads();
+    if (t + 1 < nt) {
+      // The next tile's points (positions loaded one tile ago), then the
+      // positions of the tile after it.
+      const int64_t pt = raw_next;
+      const __bf16* hp = Hh + pt * DP + part * PW;
+      const __bf16* lp = Hl + pt * DP + part * PW;
+      xh0 = *reinterpret_cast<const u32x4*>(hp);
+      xl0 = *reinterpret_cast<const u32x4*>(lp);
+      if constexpr (NC == 2) {
+        xh1 = *reinterpret_cast<const u32x4*>(hp + 8);
+        xl1 = *reinterpret_cast<const u32x4*>(lp + 8);
+      }
+      xn_r = nrm ? nrm[pt] : 0.f;
+      if (t + 2 < nt) raw_next = cix[min((t + 2) * TN + p, ncol - 1)];
+    }
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < NC; ++kc) {
+      const int kofs = kc * KCH + (lane >> 4) * 8;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int xr = (w >> 1) * 32 + bi * 16 + (lane & 15);
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sm.xh[xr][kofs]);
+        const bf16x8 al = *reinterpret_cast<const bf16x8*>(&sm.xl[xr][kofs]);
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+          const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&sm.yh[yr][kofs]);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&sm.yl[yr][kofs]);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[bi][bj], 0, 0, 0);
+          acc[bi][bj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[bi][bj], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) {
+        const int yr = (w & 1) * 32 + bj * 16 + (lane & 15);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int xc = (w >> 1) * 32 + bi * 16 + (lane >> 4) * 4 + e;
+          if (r0 + yr < s && c0 + xc < n) {
+            const float v = kfun_mixed<DOT>(acc[bi][bj][e], DOT ? 0.f : sm.yn[yr], DOT ? 0.f : sm.xn[xc], kp);
+            bad |= !isfinite(v);
+            out[(int64_t)(c0 + xc) * s_cap + (r0 + yr)] = (double)v;
+          }
+        }
+      }
+    __syncthreads();   // the tile's operands are rewritten by the next one
+  }
+  if (bad) atomicOr(flag, 1u);
+}
+
 // Column tiles a workgroup of k_evaluate_staged may list: every level's
 // sibling skeleton plus the largest leaf.
 int staged_tile_bound(const ffc_tree* t, const ffc_skel* sk) {
@@ -1172,6 +1319,20 @@ ffc_status launch_kblock_batch_mixed(const ffc_tree* t, const KParams& kp, const
     hipLaunchKernelGGL(k_level_kblock_laplace, dim3((unsigned)blocks), dim3(NTH), 0, st, t->d, first, tiles_m, tiles_n,
                        rows, nrows, s_cap, cols, ncols, n_cap, mask, sp.x, sp.cc, sp.dp, A, device_flag());
     FFC_LAUNCH_CHECK("k_level_kblock_laplace");
+    return FFC_OK;
+  }
+  if (sp.hi && (sp.dp == KCH || sp.dp == 2 * KCH)) {
+    // Column tiles per workgroup: enough workgroups (about 4096) to fill the
+    // chip, the rest of the tiles in sequence behind each.
+    const int tpw = (int)std::max<int64_t>(1, std::min<int64_t>(tiles_n, blocks / 4096));
+    const int groups_n = (tiles_n + tpw - 1) / tpw;
+    const int64_t wgs = (int64_t)count * tiles_m * groups_n;
+    const bool dot = kp.kind == FFC_POLYNOMIAL;
+    auto kern = dot ? (sp.dp == KCH ? &k_kblock_staged<true, 1> : &k_kblock_staged<true, 2>)
+                    : (sp.dp == KCH ? &k_kblock_staged<false, 1> : &k_kblock_staged<false, 2>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)wgs), dim3(NTH), 0, st, sp.hi, sp.lo, sp.nrm, kp, first, tiles_m,
+                       groups_n, tpw, rows, nrows, s_cap, cols, ncols, n_cap, mask, A, device_flag());
+    FFC_LAUNCH_CHECK("k_kblock_staged");
     return FFC_OK;
   }
   if (kp.kind == FFC_POLYNOMIAL)
