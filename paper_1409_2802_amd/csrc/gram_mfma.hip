@@ -174,24 +174,24 @@ __device__ void mixed_tile_split(const __bf16* __restrict__ Hh, const __bf16* __
   const int p = tid >> 2, part = (tid & 3) * 8;
   const int64_t yrow = p < nrows ? rows(p) : -1;
   const int64_t xrow = p < ncols ? cols(p) : -1;
-  const uint4 zero{0u, 0u, 0u, 0u};
+  const u32x4 zero = {0u, 0u, 0u, 0u};
   if (nrm && (tid & 3) == 0) {
     sm.yn[p] = yrow >= 0 ? nrm[yrow] : 0.f;
     sm.xn[p] = xrow >= 0 ? nrm[xrow] : 0.f;
   }
-  uint4 yh, yl, xh, xl;
+  u32x4 yh, yl, xh, xl;   // native vectors: a choice between two structs would go through memory
   auto fetch = [&](int k0) {
-    yh = yrow >= 0 ? *reinterpret_cast<const uint4*>(Hh + yrow * dp + k0 + part) : zero;
-    yl = yrow >= 0 ? *reinterpret_cast<const uint4*>(Hl + yrow * dp + k0 + part) : zero;
-    xh = xrow >= 0 ? *reinterpret_cast<const uint4*>(Hh + xrow * dp + k0 + part) : zero;
-    xl = xrow >= 0 ? *reinterpret_cast<const uint4*>(Hl + xrow * dp + k0 + part) : zero;
+    yh = yrow >= 0 ? *reinterpret_cast<const u32x4*>(Hh + yrow * dp + k0 + part) : zero;
+    yl = yrow >= 0 ? *reinterpret_cast<const u32x4*>(Hl + yrow * dp + k0 + part) : zero;
+    xh = xrow >= 0 ? *reinterpret_cast<const u32x4*>(Hh + xrow * dp + k0 + part) : zero;
+    xl = xrow >= 0 ? *reinterpret_cast<const u32x4*>(Hl + xrow * dp + k0 + part) : zero;
   };
   fetch(0);
   for (int k0 = 0; k0 < dp; k0 += KCH) {
-    *reinterpret_cast<uint4*>(&sm.yh[p][part]) = yh;
-    *reinterpret_cast<uint4*>(&sm.yl[p][part]) = yl;
-    *reinterpret_cast<uint4*>(&sm.xh[p][part]) = xh;
-    *reinterpret_cast<uint4*>(&sm.xl[p][part]) = xl;
+    *reinterpret_cast<u32x4*>(&sm.yh[p][part]) = yh;
+    *reinterpret_cast<u32x4*>(&sm.yl[p][part]) = yl;
+    *reinterpret_cast<u32x4*>(&sm.xh[p][part]) = xh;
+    *reinterpret_cast<u32x4*>(&sm.xl[p][part]) = xl;
     __syncthreads();
     if (k0 + KCH < dp) fetch(k0 + KCH);
     const int kofs = (lane >> 4) * 8;
@@ -238,8 +238,8 @@ __global__ void k_offset_centres(const double* __restrict__ centroid, int nodes,
 
 // Splits eight centred values into bf16 hi and lo (16 bytes each) and adds
 // their squares to nsum.
-__device__ inline void split8(const float4& a, const float4& b, const float4& ca, const float4& cb, uint4& hi,
-                              uint4& lo, float& nsum) {
+__device__ inline void split8(const f32x4& a, const f32x4& b, const f32x4& ca, const f32x4& cb, u32x4& hi,
+                              u32x4& lo, float& nsum) {
   const float z[8] = {a.x - ca.x, a.y - ca.y, a.z - ca.z, a.w - ca.w, b.x - cb.x, b.y - cb.y, b.z - cb.z, b.w - cb.w};
   __bf16 h[8], l[8];
 #pragma unroll
@@ -248,8 +248,8 @@ __device__ inline void split8(const float4& a, const float4& b, const float4& ca
     l[i] = (__bf16)(z[i] - (float)h[i]);
     nsum = fmaf(z[i], z[i], nsum);
   }
-  hi = *reinterpret_cast<const uint4*>(h);
-  lo = *reinterpret_cast<const uint4*>(l);
+  hi = *reinterpret_cast<const u32x4*>(h);
+  lo = *reinterpret_cast<const u32x4*>(l);
 }
 
 // The Gram tile of mixed_tile from the float32 points: both sets are centred
@@ -269,12 +269,12 @@ __device__ void mixed_tile_cached(const float* __restrict__ P, const float* __re
   const int p = tid >> 2, part = (tid & 3) * 8;
   const int64_t yrow = p < nrows ? rows(p) : -1;
   const int64_t xrow = p < ncols ? cols(p) : -1;
-  const float4 zero{0.f, 0.f, 0.f, 0.f};
-  float4 y0, y1, x0, x1, c0, c1;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 y0, y1, x0, x1, c0, c1;   // native vectors: a choice between two structs would go through memory
   auto fetch = [&](int k0) {
-    const float4* yp = reinterpret_cast<const float4*>(P + yrow * dp + k0 + part);
-    const float4* xp = reinterpret_cast<const float4*>(P + xrow * dp + k0 + part);
-    const float4* cp = reinterpret_cast<const float4*>(cen + k0 + part);
+    const f32x4* yp = reinterpret_cast<const f32x4*>(P + yrow * dp + k0 + part);
+    const f32x4* xp = reinterpret_cast<const f32x4*>(P + xrow * dp + k0 + part);
+    const f32x4* cp = reinterpret_cast<const f32x4*>(cen + k0 + part);
     y0 = yrow >= 0 ? yp[0] : zero;
     y1 = yrow >= 0 ? yp[1] : zero;
     x0 = xrow >= 0 ? xp[0] : zero;
@@ -285,14 +285,14 @@ __device__ void mixed_tile_cached(const float* __restrict__ P, const float* __re
   float yn = 0.f, xn = 0.f;
   fetch(0);
   for (int k0 = 0; k0 < dp; k0 += KCH) {
-    uint4 h, l;
+    u32x4 h, l;
     // Padded rows stage zeros (not minus the centre) so they add nothing.
     split8(y0, y1, yrow >= 0 ? c0 : zero, yrow >= 0 ? c1 : zero, h, l, yn);
-    *reinterpret_cast<uint4*>(&sm.yh[p][part]) = h;
-    *reinterpret_cast<uint4*>(&sm.yl[p][part]) = l;
+    *reinterpret_cast<u32x4*>(&sm.yh[p][part]) = h;
+    *reinterpret_cast<u32x4*>(&sm.yl[p][part]) = l;
     split8(x0, x1, xrow >= 0 ? c0 : zero, xrow >= 0 ? c1 : zero, h, l, xn);
-    *reinterpret_cast<uint4*>(&sm.xh[p][part]) = h;
-    *reinterpret_cast<uint4*>(&sm.xl[p][part]) = l;
+    *reinterpret_cast<u32x4*>(&sm.xh[p][part]) = h;
+    *reinterpret_cast<u32x4*>(&sm.xl[p][part]) = l;
     __syncthreads();
     if (k0 + KCH < dp) fetch(k0 + KCH);
     const int kofs = (lane >> 4) * 8;
