@@ -120,3 +120,25 @@ def test_mixed_laplace_on_matrix_cores_matches_the_direct_sum(ffc, d, leaf):
     ratio = np.abs(u - ref) / bound
     print(f"d={d}: max error / bound {ratio.max():.3e}, rel 2-norm {rel(u, ref):.3e}")
     assert np.all(np.abs(u - ref) <= bound)
+
+
+@pytest.mark.parametrize("kind,d,kw", [(POLYNOMIAL, 20, dict(h=1.0, p=3)), (POLYNOMIAL, 64, dict(h=1.0, p=2)),
+                                       (GAUSSIAN, 64, dict(h=2.0)), (GAUSSIAN, 100, dict(h=3.0))])
+def test_mixed_evaluation_of_fixed_skeletons_matches_fp64(ffc, kind, d, kw):
+    """The same skeletons (built in FP64) evaluated in mixed precision and in
+    FP64 (whose evaluation is checked against the oracle's): the sums differ
+    only by the bf16x3 kernel values. Points near the origin take the split
+    operands: one and two 32-dimension chunks (the workgroup-staged kernels)
+    and 100 dimensions (the generic tiles)."""
+    N = 8192
+    X = W.normal(N, d, seed=11) / np.sqrt(d)
+    q = W.charges(N, seed=12)
+    gk = gkernel(kind, **kw)
+    t = ffc.build_tree(X, 512)
+    sk = ffc.skeletonize(t, gk, tol=0.0, max_rank=64, seed=0)
+    u64, f64 = (x.cpu().numpy() for x in ffc.evaluate_sum(t, sk, gk, q, precision=ffc.FP64))
+    um, fm = (x.cpu().numpy() for x in ffc.evaluate_sum(t, sk, gk, q, precision=ffc.MIXED_BF16X3))
+    ffc.check_device()
+    print(kind, d, "far", rel(fm, f64), "total", rel(um, u64))
+    assert rel(fm, f64) < 1e-4
+    assert rel(um, u64) < 1e-4
