@@ -424,6 +424,7 @@ struct FeatSmem {
   double xs[2][FR][FKP];
   double cu[2][1 + NANCH][FK + 1];   // centroid and anchor directions, first round
   double ny[FT];
+  double subn[SUB];                  // and their squared norms
   int sub[SUB];                      // the subsample's tree positions
 };
 
@@ -491,8 +492,11 @@ __global__ void __launch_bounds__(256, 3) k_features(const double* __restrict__ 
   const int drow = tid >> 2, da = 2 * (tid & 3);
   // The subsample's positions go to LDS first: a coordinate load then waits
   // on an LDS read, not on an earlier global load (which would serialize the
-  // stage's loads).
-  for (int q = tid; q < SUB; q += 256) sm.sub[q] = q < ns ? S[q] : 0;
+  // stage's loads). Their norms too, which each round's distances read.
+  for (int q = tid; q < SUB; q += 256) {
+    sm.sub[q] = q < ns ? S[q] : 0;
+    sm.subn[q] = q < ns ? nxg[q] : 0.0;
+  }
   __syncthreads();
   load(0);
   store(0, 0);
@@ -535,7 +539,7 @@ __global__ void __launch_bounds__(256, 3) k_features(const double* __restrict__ 
       for (int c = 0; c < FCT; ++c) {
         const int p = r * FR + 16 * c + li;
         if (p < ns) {
-          const double nx = nxg[p];
+          const double nx = sm.subn[p];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int row = 16 * w + 4 * v + lg;
