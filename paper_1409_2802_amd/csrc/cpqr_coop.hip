@@ -772,9 +772,14 @@ k_id_solve_mfma(const double* __restrict__ A, int64_t a_stride, int lda, const i
 // version's 37 KB of T allowed one). The 16 blocks and their chunks are
 // unrolled so that every register index is fixed; the products run in the
 // same order as in k_id_solve_mfma, so the results are the same bits.
+// BATCH chunks' R operands are loaded at a time: two for launches with many
+// wavefronts (two per SIMD, which hide each other's loads; larger batches
+// spilled), all fifteen for small launches (one wavefront per SIMD with 512
+// registers: one load round trip per block instead of one per two chunks).
 constexpr int kRegSolveRank = 256;
 
-__global__ void __launch_bounds__(64, 2)
+template <int BATCH>
+__global__ void __launch_bounds__(64, BATCH > 2 ? 1 : 2)
 k_id_solve_regs(const double* __restrict__ A, int64_t a_stride, int lda, const int32_t* __restrict__ n_arr,
                 int n_uniform, int n_max, const int32_t* __restrict__ rank, int32_t* __restrict__ piv,
                 int64_t piv_stride, const double* __restrict__ Dinv, int nblk, double* __restrict__ P,
@@ -819,13 +824,13 @@ k_id_solve_regs(const double* __restrict__ A, int64_t a_stride, int lda, const i
       const char* Abc = reinterpret_cast<const char*>(Ab);
       const unsigned ko = (unsigned)(kb + i16);
       // Trailing products over the chunks cb > bi that start below the rank,
-      // two chunks' R operands loaded at a time.
+      // BATCH chunks' R operands loaded at a time.
 #pragma unroll
-      for (int c0 = bi + 1; c0 < kRegSolveRank / MB; c0 += 2) {
+      for (int c0 = bi + 1; c0 < kRegSolveRank / MB; c0 += BATCH) {
         if (MB * c0 >= r) break;
-        double a[2][4];
+        double a[BATCH][4];
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < BATCH; ++c)
           if (c0 + c < kRegSolveRank / MB && MB * (c0 + c) < r)
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -834,7 +839,7 @@ k_id_solve_regs(const double* __restrict__ A, int64_t a_stride, int lda, const i
               a[c][m] = *reinterpret_cast<const double*>(Abc + off);
             }
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < BATCH; ++c) {
           const int cb = c0 + c;
           if (cb < kRegSolveRank / MB && MB * cb < r) {
             double bq[4];
@@ -1007,9 +1012,13 @@ ffc_status launch_solve(const IdBatch& bt, int batch, QrScratch scratch, hipStre
                      bt.piv_stride, Dinv, nblk, bt.mask);
   FFC_LAUNCH_CHECK("k_diag_inv");
   if (regs) {
-    hipLaunchKernelGGL(k_id_solve_regs, dim3(batch, (bt.n_max + MB - 1) / MB), dim3(64), lds, st, bt.A,
-                       bt.a_stride, bt.lda, bt.n_arr, bt.n_uniform, bt.n_max, bt.rank, bt.piv, bt.piv_stride, Dinv,
-                       nblk, bt.P, bt.p_stride, bt.p_ld, r_max, bt.mask);
+    // Up to 2048 wavefronts (two per SIMD) the launch cannot hide its load
+    // latency with other wavefronts: load whole blocks' operands at once.
+    const bool small = (int64_t)batch * ((bt.n_max + MB - 1) / MB) <= 2048;
+    hipLaunchKernelGGL(small ? k_id_solve_regs<kRegSolveRank / MB - 1> : k_id_solve_regs<2>,
+                       dim3(batch, (bt.n_max + MB - 1) / MB), dim3(64), lds, st, bt.A, bt.a_stride, bt.lda, bt.n_arr,
+                       bt.n_uniform, bt.n_max, bt.rank, bt.piv, bt.piv_stride, Dinv, nblk, bt.P, bt.p_stride, bt.p_ld,
+                       r_max, bt.mask);
     FFC_LAUNCH_CHECK("k_id_solve_regs");
   } else {
     hipLaunchKernelGGL(k_id_solve_mfma, dim3(batch, (bt.n_max + MB - 1) / MB), dim3(64), lds, st, bt.A,
