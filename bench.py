@@ -548,6 +548,9 @@ def main():
         ms_step, timing = g0.elapsed_time(g1) / args.steps, "HIP graph replays"
         torch.cuda.current_stream().wait_stream(gstream)
         print(f"[bench] graph: {args.steps} steps, {ms_step:.3f} ms/step", file=sys.stderr, flush=True)
+        # The graph holds the tree's and the skeletons' buffers; the runs below (another precision's operands,
+        # the FP64 uniform path) may need to make or resize them.
+        graph.free()
 
     # Work counts of one step.
     st = sk.stats()

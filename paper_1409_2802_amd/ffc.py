@@ -407,6 +407,11 @@ class StepGraph:
             _lib.ffc_graph_free(self._h)
         self._h = None
 
+    def free(self) -> None:
+        """Release the graph now (ffc_graph_free): while it lives, calls that would resize or replace the buffers
+        it holds on its tree and skeletons are refused."""
+        self._release()
+
     def __del__(self):
         self._release()
 
