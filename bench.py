@@ -534,7 +534,8 @@ def main():
         gstream.wait_stream(torch.cuda.current_stream())
         graph = ffc.StepGraph(tree, sk, k, qd, u, uf, gstream, tol=w["tol"], max_rank=w["max_rank"],
                               num_samples=w["num_samples"], precision=prec, seed=0, proposal=proposal,
-                              pool_factor=w.get("pool_factor", 0), separation=w.get("separation", 0.0))
+                              pool_factor=w.get("pool_factor", 0), separation=w.get("separation", 0.0),
+                              fmm=w.get("evaluation") == "fmm")
         for _ in range(max(1, args.warmup)):
             graph.launch(gstream)
         gstream.synchronize()
